@@ -1,0 +1,310 @@
+"""ctypes wrapper of the FP64 CPU oracle (``hlbm_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product path.  It shares no
+code with the HIP library; the two only share the seeded inputs built by
+``paper_2006_10487_amd.workloads``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "hlbm_oracle.c")
+LIB = os.path.join(HERE, "libhlbm_oracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                               "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Cfg(C.Structure):
+    _fields_ = [
+        ("nx_cells", C.c_int32), ("ny_cells", C.c_int32), ("n_refine", C.c_int32),
+        ("patch_i0", C.c_int32 * 3), ("patch_j0", C.c_int32 * 3),
+        ("patch_nx", C.c_int32 * 3), ("patch_ny", C.c_int32 * 3),
+        ("periodic", C.c_int32), ("wall_bc", C.c_int32), ("n_sub", C.c_int32), ("interp", C.c_int32),
+        ("u_inf", C.c_double), ("aoa", C.c_double), ("rho0", C.c_double), ("tau_s", C.c_double),
+        ("chord", C.c_double), ("ein", C.c_double * 4), ("mesh_period", C.c_double * 2),
+        ("n_nodes", C.c_int32), ("n_tris", C.c_int32),
+        ("xy", C.POINTER(C.c_double)), ("tri", C.POINTER(C.c_int32)), ("kind", C.POINTER(C.c_uint8)),
+        ("channel", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        L.or_create.restype = C.c_void_p
+        L.or_create.argtypes = [C.POINTER(_Cfg), C.c_char_p, C.c_int32]
+        L.or_destroy.argtypes = [C.c_void_p]
+        L.or_step.argtypes = [C.c_void_p, C.c_int64]
+        L.or_step.restype = C.c_int
+        for name in ("or_get_level", "or_set_level", "or_level_class"):
+            getattr(L, name).argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
+        for name in ("or_get_mesh", "or_set_mesh"):
+            getattr(L, name).argtypes = [C.c_void_p, C.c_void_p]
+        L.or_history.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
+        L.or_history.restype = C.c_int64
+        L.or_info.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_sint.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_wall_force.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_equilibrium.argtypes = [C.c_double, C.c_double, C.c_double, C.c_void_p]
+        L.or_bgk.argtypes = [C.c_void_p, C.c_double, C.c_void_p]
+        L.or_lattice.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_fv_geometry.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_int32]
+        L.or_stencil6.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
+                                  C.c_double, C.c_int32, C.c_void_p, C.c_void_p]
+        L.or_plant.argtypes = [C.c_int32, C.c_double]
+        L.or_stencil9.argtypes = [C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# point functions
+# ---------------------------------------------------------------------------
+
+class planted:
+    """Context manager that plants a deliberate mistake in the oracle.
+
+    which: 0 scales the eq. (4) non-equilibrium factor, 1 the eq. (5)-(6)
+    factor, 2 the coarse -> fine rescaling, 3 the fine -> coarse rescaling.
+    Used only by mutation tests that show a pin fails on a wrong oracle.
+    """
+
+    def __init__(self, which: int, value: float):
+        self.which, self.value = which, value
+
+    def __enter__(self):
+        lib().or_plant(self.which, self.value)
+        return self
+
+    def __exit__(self, *exc):
+        lib().or_plant(self.which, 1.0)
+        return False
+
+
+def lattice():
+    cx = np.zeros(9, np.int32)
+    cy = np.zeros(9, np.int32)
+    w = np.zeros(9)
+    lib().or_lattice(_p(cx), _p(cy), _p(w))
+    return cx, cy, w
+
+
+def equilibrium(rho: float, ux: float, uy: float) -> np.ndarray:
+    out = np.zeros(9)
+    lib().or_equilibrium(rho, ux, uy, _p(out))
+    return out
+
+
+def bgk(f: np.ndarray, tau: float) -> np.ndarray:
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros(9)
+    lib().or_bgk(_p(f), tau, _p(out))
+    return out
+
+
+def fv_geometry(xy, tri, kind=None, period=(0.0, 0.0)):
+    """CSR rows of (G_Pk, C_Pk), node areas and wall edges."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+    nn, nt = xy.shape[0], tri.shape[0]
+    kind = np.zeros(nn, np.uint8) if kind is None else np.ascontiguousarray(kind, dtype=np.uint8)
+    nnz_max = 40 * nn
+    rowptr = np.zeros(nn + 1, np.int32)
+    col = np.zeros(nnz_max, np.int32)
+    gx = np.zeros(nnz_max)
+    gy = np.zeros(nnz_max)
+    cc = np.zeros(nnz_max)
+    area = np.zeros(nn)
+    nw = np.zeros(1, np.int32)
+    wedge = np.zeros(2 * nn + 2, np.int32)
+    rc = lib().or_fv_geometry(nn, nt, _p(xy), _p(tri), _p(kind), float(period[0]), float(period[1]),
+                              nnz_max, _p(rowptr), _p(col), _p(gx), _p(gy), _p(cc), _p(area),
+                              _p(nw), _p(wedge), nn + 1)
+    if rc:
+        raise RuntimeError(f"or_fv_geometry failed: {rc}")
+    nnz = rowptr[-1]
+    return dict(rowptr=rowptr, col=col[:nnz], gx=gx[:nnz], gy=gy[:nnz], c=cc[:nnz], area=area,
+                wall_edges=wedge[:2 * nw[0]].reshape(-1, 2))
+
+
+def stencil6(xy, tri, x, y, linear=False):
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+    don = np.zeros(8, np.int32)
+    w = np.zeros(8)
+    n = lib().or_stencil6(xy.shape[0], tri.shape[0], _p(xy), _p(tri), float(x), float(y),
+                          int(linear), _p(don), _p(w))
+    if n < 0:
+        raise ValueError("point outside the mesh")
+    return don[:n], w[:n]
+
+
+def stencil9(x, y, linear=False):
+    di = np.zeros(9, np.int32)
+    dj = np.zeros(9, np.int32)
+    w = np.zeros(9)
+    n = lib().or_stencil9(float(x), float(y), int(linear), _p(di), _p(dj), _p(w))
+    return di[:n], dj[:n], w[:n]
+
+
+# ---------------------------------------------------------------------------
+# whole-solver oracle
+# ---------------------------------------------------------------------------
+
+class Oracle:
+    """FP64 reference run of the hybrid scheme.
+
+    All coordinates are finest-level lattice units.  ``tau_s`` is the
+    finest-level relaxation time; ``aoa`` is in radians.
+    """
+
+    def __init__(self, *, nx_cells=0, ny_cells=0, patches=(), periodic=False, wall_bc=True,
+                 n_sub=0, interp="quadratic", u_inf=0.05, aoa=0.0, rho0=1.0, tau_s=0.6,
+                 chord=1.0, inner_ellipse=None, mesh_xy=None, mesh_tri=None, mesh_kind=None,
+                 mesh_period=(0.0, 0.0), channel=False):
+        cfg = _Cfg()
+        cfg.channel = int(channel)
+        cfg.nx_cells, cfg.ny_cells = nx_cells, ny_cells
+        cfg.n_refine = len(patches)
+        for k, (i0, j0, px, py) in enumerate(patches):
+            cfg.patch_i0[k], cfg.patch_j0[k], cfg.patch_nx[k], cfg.patch_ny[k] = i0, j0, px, py
+        cfg.periodic = int(periodic)
+        cfg.wall_bc = int(wall_bc)
+        cfg.n_sub = int(n_sub)
+        cfg.interp = 0 if interp == "quadratic" else 1
+        cfg.u_inf, cfg.aoa, cfg.rho0, cfg.tau_s, cfg.chord = u_inf, aoa, rho0, tau_s, chord
+        ein = inner_ellipse if inner_ellipse is not None else (0.0, 0.0, 0.0, 0.0)
+        for k in range(4):
+            cfg.ein[k] = float(ein[k])
+        cfg.mesh_period[0], cfg.mesh_period[1] = float(mesh_period[0]), float(mesh_period[1])
+        self._keep = []
+        if mesh_xy is not None:
+            xy = np.ascontiguousarray(mesh_xy, dtype=np.float64).reshape(-1, 2)
+            tri = np.ascontiguousarray(mesh_tri, dtype=np.int32).reshape(-1, 3)
+            kind = np.ascontiguousarray(mesh_kind, dtype=np.uint8)
+            self._keep += [xy, tri, kind]
+            cfg.n_nodes, cfg.n_tris = xy.shape[0], tri.shape[0]
+            cfg.xy = xy.ctypes.data_as(C.POINTER(C.c_double))
+            cfg.tri = tri.ctypes.data_as(C.POINTER(C.c_int32))
+            cfg.kind = kind.ctypes.data_as(C.POINTER(C.c_uint8))
+            self.n_nodes = xy.shape[0]
+        else:
+            self.n_nodes = 0
+        err = C.create_string_buffer(256)
+        h = lib().or_create(C.byref(cfg), err, 256)
+        if not h:
+            raise ValueError("oracle create failed: " + err.value.decode())
+        self._h = h
+        ints = np.zeros(16, np.int32)
+        dbls = np.zeros(8)
+        lib().or_info(self._h, _p(ints), _p(dbls))
+        self.n_levels = int(ints[0])
+        self.n_sub = int(ints[1])
+        self.n_sint = int(ints[2])
+        self.n_uint = int(ints[3])
+        self.n_fallback = int(ints[4])
+        self.n_wall_edges = int(ints[5])
+        self.level_shape = [(int(ints[10 + l]), int(ints[6 + l])) for l in range(self.n_levels)]
+        self.tau_u = float(dbls[0])
+        self.tau = [float(dbls[1 + l]) for l in range(self.n_levels)]
+
+    @classmethod
+    def from_workload(cls, w, *, interp="quadratic", n_sub=0, wall_bc=True, aoa_rad=None,
+                      tau_s=None):
+        return cls(nx_cells=w.nx_cells, ny_cells=w.ny_cells, patches=w.patches,
+                   periodic=w.periodic, wall_bc=wall_bc, n_sub=n_sub or w.n_sub, interp=interp,
+                   u_inf=w.u_inf, aoa=w.aoa_rad if aoa_rad is None else aoa_rad, rho0=w.rho0,
+                   tau_s=w.tau_s if tau_s is None else tau_s, chord=w.chord,
+                   inner_ellipse=w.inner_ellipse, mesh_xy=w.mesh_xy, mesh_tri=w.mesh_tri,
+                   mesh_kind=w.mesh_kind)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().or_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int):
+        rc = lib().or_step(self._h, int(n))
+        if rc:
+            raise ValueError("step count must be a multiple of 2^levels")
+
+    def get_level(self, l: int) -> np.ndarray:
+        ny, nx = self.level_shape[l]
+        out = np.zeros((9, ny, nx))
+        lib().or_get_level(self._h, l, _p(out))
+        return out
+
+    def set_level(self, l: int, f: np.ndarray):
+        ny, nx = self.level_shape[l]
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(9, ny, nx)
+        lib().or_set_level(self._h, l, _p(f))
+
+    def level_class(self, l: int) -> np.ndarray:
+        ny, nx = self.level_shape[l]
+        out = np.zeros((ny, nx), np.uint8)
+        lib().or_level_class(self._h, l, _p(out))
+        return out
+
+    def get_mesh(self) -> np.ndarray:
+        out = np.zeros((9, self.n_nodes))
+        lib().or_get_mesh(self._h, _p(out))
+        return out
+
+    def set_mesh(self, f: np.ndarray):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(9, self.n_nodes)
+        lib().or_set_mesh(self._h, _p(f))
+
+    def history(self):
+        n = lib().or_history(self._h, None, None, 0)
+        cd = np.zeros(max(n, 1))
+        cl = np.zeros(max(n, 1))
+        lib().or_history(self._h, _p(cd), _p(cl), n)
+        return cd[:n], cl[:n]
+
+    def sint(self):
+        n = self.n_sint
+        ij = np.zeros((max(n, 1), 2), np.int32)
+        don = np.zeros((max(n, 1), 8), np.int32)
+        w = np.zeros((max(n, 1), 8))
+        lib().or_sint(self._h, _p(ij), _p(don), _p(w))
+        return ij[:n], don[:n], w[:n]
+
+    def wall_force(self):
+        fx = np.zeros(1)
+        fy = np.zeros(1)
+        lib().or_wall_force(self._h, _p(fx), _p(fy))
+        return float(fx[0]), float(fy[0])

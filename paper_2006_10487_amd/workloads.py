@@ -1,0 +1,416 @@
+"""Seeded, synthetic inputs for the hybrid lattice Boltzmann (HLBM) solver.
+
+This module builds the *inputs* of the method: the NACA 0012 profile, the
+body-fitted triangular O-mesh around it, the structured grid with its nested
+refinement boxes, and small test geometries (periodic triangulated squares,
+rectangular mesh patches).  It holds none of the method's arithmetic: no
+equilibrium, no collision, no finite-volume coefficients, no interpolation
+weights.  Both the HIP library and the CPU oracle consume what it returns.
+
+Geometry, in the paper's terms:
+  * NACA 0012, symmetric, 12 % thickness (Sec. 4, problem setup).
+  * Body-fitted unstructured triangular mesh confined around the body whose
+    outer boundary is an ellipse; a second, inner fictitious ellipse closes the
+    overlap band in which the interpolation nodes sit (Sec. 4).
+  * Uniform Cartesian grid with nested factor-two refinement boxes; the
+    innermost box has unit spacing and overlaps the mesh (Sec. 4).
+Coordinates are in lattice units of the finest structured level.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+KIND_INTERIOR = 0
+KIND_WALL = 1
+KIND_INTERP = 2
+
+
+# ---------------------------------------------------------------------------
+# NACA 0012 profile and O-mesh
+# ---------------------------------------------------------------------------
+
+def naca0012_half_thickness(xi: np.ndarray) -> np.ndarray:
+    """Half thickness over chord of the NACA 0012 section (closed trailing edge)."""
+    xi = np.clip(xi, 0.0, 1.0)
+    return 0.6 * (0.2969 * np.sqrt(xi) - 0.1260 * xi - 0.3516 * xi**2
+                  + 0.2843 * xi**3 - 0.1036 * xi**4)
+
+
+def hicks_henne(xi: np.ndarray, peaks, amps, exponent: float = 3.0) -> np.ndarray:
+    """Sum of Hicks-Henne bumps a_m sin^e(pi xi^(ln 0.5 / ln x_m)) (chord units)."""
+    xi = np.clip(np.asarray(xi, dtype=np.float64), 0.0, 1.0)
+    out = np.zeros_like(xi)
+    for xm, am in zip(peaks, amps):
+        p = math.log(0.5) / math.log(xm)
+        out += am * np.sin(np.pi * xi**p) ** exponent
+    return out
+
+
+def _growth_for_first_height(h1: float, dist: float, nl: int) -> float:
+    """Geometric growth r with (r-1)/(r^nl-1)*dist == h1 (bisection)."""
+    if h1 * nl >= dist:
+        raise ValueError("first height too large for uniform-or-growing layers")
+    lo, hi = 1.0 + 1e-12, 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        h = (mid - 1.0) / (mid**nl - 1.0) * dist
+        if h > h1:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+@dataclasses.dataclass
+class OMesh:
+    xy: np.ndarray          # [n_nodes, 2] float64
+    tri: np.ndarray         # [n_tris, 3] int32, counter-clockwise
+    kind: np.ndarray        # [n_nodes] uint8: 0 interior, 1 wall, 2 interpolation
+    ns: int
+    nl: int
+    growth: float
+    centre: Tuple[float, float]
+    outer_axes: Tuple[float, float]
+    outer_layer_thickness: float
+    surface_index: np.ndarray   # [ns] node index of the wall node j
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.xy.shape[0])
+
+    @property
+    def n_tris(self) -> int:
+        return int(self.tri.shape[0])
+
+
+def _surface_parameter(ns: int, spacing: str, bump=None) -> np.ndarray:
+    """Curve parameter theta_j of the ns surface points (j = 0 at the trailing edge).
+
+    The profile is x = x_LE + c (1 + cos theta) / 2, upper surface for theta <= pi.
+    "cosine": theta_j = 2 pi j / ns.  "arclength": theta_j chosen so that the
+    surface points are equally spaced along the profile, which bounds the
+    smallest wall element (cosine spacing shrinks the trailing-edge element to
+    ~c pi^2/ns^2 and with it the stable explicit finite-volume time step).
+    """
+    if spacing == "cosine":
+        return 2.0 * np.pi * np.arange(ns) / ns
+    if spacing != "arclength":
+        raise ValueError(spacing)
+    m = 200001
+    tt = np.linspace(0.0, np.pi, m)
+    xi = 0.5 * (1.0 + np.cos(tt))
+    yy = naca0012_half_thickness(xi)
+    if bump is not None:
+        yy = yy + bump(xi)
+    seg = np.hypot(np.diff(xi), np.diff(yy))
+    s = np.concatenate([[0.0], np.cumsum(seg)])
+    half = ns // 2
+    target = s[-1] * np.arange(half + 1) / half
+    th_up = np.interp(target, s, tt)
+    th_up[0], th_up[-1] = 0.0, np.pi
+    th = np.empty(ns)
+    th[:half + 1] = th_up
+    th[half + 1:] = 2.0 * np.pi - th_up[1:half][::-1]
+    return th
+
+
+def naca0012_omesh(chord: float, le: Tuple[float, float], ns: int, nl: int,
+                   d_out: float, growth: Optional[float] = None,
+                   h1: Optional[float] = None,
+                   bump_amps=None, bump_peaks=None, spacing: str = "arclength") -> OMesh:
+    """O-mesh of ns surface points times nl layers around the NACA 0012.
+
+    Surface point j (j = 0 at the trailing edge, counter-clockwise) sits at
+    curve parameter theta_j, x = x_LE + c (1 + cos theta) / 2, upper surface
+    for theta <= pi (see _surface_parameter for the spacing).  The outer
+    boundary is the ellipse centred at mid-chord with semi-axes
+    (c/2 + d_out, d_out); layer l interpolates between the surface point and
+    the ellipse point of the same theta with geometric spacing.  Quads are
+    split along alternating diagonals so that the mesh is mirror symmetric
+    about the chord line.
+    """
+    if ns % 2:
+        raise ValueError("ns must be even")
+    x_le, y_le = le
+    th = _surface_parameter(ns, spacing)
+    xi = 0.5 * (1.0 + np.cos(th))
+    yt = naca0012_half_thickness(xi)
+    upper = th <= np.pi + 1e-12
+    ys = np.where(upper, yt, -yt)
+    if bump_amps is not None:
+        bump = hicks_henne(xi, bump_peaks, bump_amps)
+        ys = ys + np.where(upper, bump, 0.0)
+    sx = x_le + chord * xi
+    sy = y_le + chord * ys
+    # exact zero thickness at the leading and trailing edge points
+    sy[0] = y_le
+    sy[ns // 2] = y_le
+    xc, yc = x_le + 0.5 * chord, y_le
+    a_out, b_out = 0.5 * chord + d_out, d_out
+    ox = xc + a_out * np.cos(th)
+    oy = yc + b_out * np.sin(th)
+    if growth is None:
+        if h1 is None:
+            raise ValueError("need growth or h1")
+        growth = _growth_for_first_height(h1, d_out, nl)
+    r = growth
+    if abs(r - 1.0) < 1e-14:
+        eta = np.arange(nl + 1) / nl
+    else:
+        eta = (r ** np.arange(nl + 1) - 1.0) / (r**nl - 1.0)
+    # node (j, l) -> l * ns + j
+    X = sx[None, :] + eta[:, None] * (ox - sx)[None, :]
+    Y = sy[None, :] + eta[:, None] * (oy - sy)[None, :]
+    if bump_amps is None:
+        # exact mirror images about the chord line: node ns - j mirrors node j
+        half = ns // 2
+        X[:, half + 1:] = X[:, 1:half][:, ::-1]
+        Y[:, half + 1:] = 2.0 * y_le - Y[:, 1:half][:, ::-1]
+        Y[:, 0] = y_le
+        Y[:, half] = y_le
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+    kind = np.zeros((nl + 1) * ns, dtype=np.uint8)
+    kind[:ns] = KIND_WALL
+    kind[nl * ns:] = KIND_INTERP
+    tris = []
+    for l in range(nl):
+        for j in range(ns):
+            jp = (j + 1) % ns
+            a, b = l * ns + j, l * ns + jp
+            c, d = (l + 1) * ns + jp, (l + 1) * ns + j
+            if j < ns // 2:     # diagonal (j,l)-(j+1,l+1) = a-c
+                t1, t2 = (a, c, b), (a, d, c)
+            else:               # diagonal (j+1,l)-(j,l+1) = b-d
+                t1, t2 = (a, d, b), (b, d, c)
+            tris.append(t1)
+            tris.append(t2)
+    tri = np.asarray(tris, dtype=np.int32)
+    tri = _orient_ccw(xy, tri)
+    t_outer = float(np.max(np.hypot(X[nl] - X[nl - 1], Y[nl] - Y[nl - 1])))
+    return OMesh(xy=xy, tri=tri, kind=kind, ns=ns, nl=nl, growth=float(r),
+                 centre=(xc, yc), outer_axes=(a_out, b_out),
+                 outer_layer_thickness=t_outer,
+                 surface_index=np.arange(ns, dtype=np.int64))
+
+
+def _orient_ccw(xy: np.ndarray, tri: np.ndarray) -> np.ndarray:
+    p, q, r = xy[tri[:, 0]], xy[tri[:, 1]], xy[tri[:, 2]]
+    cross = (q[:, 0] - p[:, 0]) * (r[:, 1] - p[:, 1]) - (q[:, 1] - p[:, 1]) * (r[:, 0] - p[:, 0])
+    out = tri.copy()
+    flip = cross < 0
+    out[flip, 1], out[flip, 2] = tri[flip, 2], tri[flip, 1]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Test geometries
+# ---------------------------------------------------------------------------
+
+def periodic_square_mesh(n: int, length: float, diagonal: str = "alternate"):
+    """Regular triangulation of a periodic square of side `length`, n x n nodes.
+
+    Node (i, j) -> j * n + i at ((i + 0.5) h, (j + 0.5) h).  Each grid square is
+    split into two triangles; connectivity wraps around both directions.
+    Returns (xy, tri, kind) with every node interior.
+    """
+    h = length / n
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+    xy = np.stack([(ii.ravel() + 0.5) * h, (jj.ravel() + 0.5) * h], axis=1)
+    tris = []
+    for j in range(n):
+        for i in range(n):
+            a = j * n + i
+            b = j * n + (i + 1) % n
+            c = ((j + 1) % n) * n + (i + 1) % n
+            d = ((j + 1) % n) * n + i
+            alt = (diagonal == "alternate" and (i + j) % 2 == 1)
+            if alt:
+                tris += [(a, b, d), (b, c, d)]
+            else:
+                tris += [(a, b, c), (a, c, d)]
+    tri = np.asarray(tris, dtype=np.int32)
+    kind = np.zeros(n * n, dtype=np.uint8)
+    return xy, tri, kind
+
+
+def rect_patch_mesh(x0: float, y0: float, nx: int, ny: int, h: float,
+                    jitter: float = 0.0, seed: int = 0):
+    """Triangulated rectangle [x0, x0+nx h] x [y0, y0+ny h] of (nx+1)(ny+1) nodes.
+
+    Interior nodes are displaced by a seeded uniform jitter of at most
+    `jitter * h` per coordinate; boundary nodes are the interpolation ring.
+    Returns (xy, tri, kind) (no wall nodes).
+    """
+    rng = np.random.default_rng(seed)
+    ii, jj = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), indexing="xy")
+    x = x0 + ii.astype(np.float64) * h
+    y = y0 + jj.astype(np.float64) * h
+    kind = np.zeros((ny + 1, nx + 1), dtype=np.uint8)
+    kind[0, :] = kind[-1, :] = KIND_INTERP
+    kind[:, 0] = kind[:, -1] = KIND_INTERP
+    inner = kind == KIND_INTERIOR
+    if jitter > 0:
+        x = x + np.where(inner, rng.uniform(-jitter, jitter, x.shape) * h, 0.0)
+        y = y + np.where(inner, rng.uniform(-jitter, jitter, y.shape) * h, 0.0)
+    xy = np.stack([x.ravel(), y.ravel()], axis=1)
+    tris = []
+    for j in range(ny):
+        for i in range(nx):
+            a = j * (nx + 1) + i
+            b = a + 1
+            d = a + (nx + 1)
+            c = d + 1
+            if (i + j) % 2 == 0:
+                tris += [(a, b, c), (a, c, d)]
+            else:
+                tris += [(a, b, d), (b, c, d)]
+    tri = _orient_ccw(xy, np.asarray(tris, dtype=np.int32))
+    return xy, tri, kind.ravel()
+
+
+# ---------------------------------------------------------------------------
+# Workload presets
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Workload:
+    """One HLBM problem: structured grid, refinement boxes, mesh and flow."""
+    name: str
+    nx_cells: int            # base-level cells along x
+    ny_cells: int            # base-level cells along y
+    patches: List[Tuple[int, int, int, int]]  # (i0, j0, nx, ny): origin in parent nodes, size in own cells
+    u_inf: float
+    aoa_deg: float
+    re: float
+    chord: float
+    mesh_xy: Optional[np.ndarray]
+    mesh_tri: Optional[np.ndarray]
+    mesh_kind: Optional[np.ndarray]
+    inner_ellipse: Tuple[float, float, float, float]   # (xc, yc, a, b), finest lu
+    steps: int
+    rho0: float = 1.0
+    periodic: bool = False
+    n_sub: int = 0
+    omesh: Optional[OMesh] = None
+    notes: str = ""
+
+    @property
+    def n_refine(self) -> int:
+        return len(self.patches)
+
+    @property
+    def base_spacing(self) -> int:
+        return 2 ** self.n_refine
+
+    @property
+    def tau_s(self) -> float:
+        """Finest-level relaxation time from Re on chord and free-stream speed."""
+        nu = self.u_inf * self.chord / self.re
+        return 0.5 + 3.0 * nu
+
+    @property
+    def aoa_rad(self) -> float:
+        return math.radians(self.aoa_deg)
+
+    def level_nodes(self) -> List[Tuple[int, int]]:
+        """(nx_nodes, ny_nodes) for every level, coarse to fine."""
+        out = [(self.nx_cells + (0 if self.periodic else 1),
+                self.ny_cells + (0 if self.periodic else 1))]
+        for (_, _, px, py) in self.patches:
+            out.append((px + 1, py + 1))
+        return out
+
+    def structured_node_count(self) -> int:
+        return int(sum(a * b for a, b in self.level_nodes()))
+
+
+def _place_patches(x_mid: float, y_mid: float, sizes, n_levels: int, base_spacing: int):
+    """Centre nested boxes on (x_mid, y_mid), origins aligned to parent nodes."""
+    patches = []
+    parent_origin = (0.0, 0.0)
+    parent_sp = base_spacing
+    for (pnx, pny) in sizes:
+        own_sp = parent_sp // 2
+        wx, wy = pnx * own_sp, pny * own_sp
+        i0 = int(math.floor((x_mid - 0.5 * wx - parent_origin[0]) / parent_sp + 0.5))
+        j0 = int(math.floor((y_mid - 0.5 * wy - parent_origin[1]) / parent_sp + 0.5))
+        patches.append((i0, j0, pnx, pny))
+        parent_origin = (parent_origin[0] + i0 * parent_sp, parent_origin[1] + j0 * parent_sp)
+        parent_sp = own_sp
+    return patches
+
+
+def _inner_ellipse(om: OMesh) -> Tuple[float, float, float, float]:
+    """Inner fictitious ellipse: outer ellipse shrunk by w = max(4, 2 t_outer + 2)."""
+    w = max(4.0, 2.0 * om.outer_layer_thickness + 2.0)
+    a, b = om.outer_axes
+    return (om.centre[0], om.centre[1], a - w, b - w)
+
+
+def _naca_workload(name, nx, ny, patch_sizes, chord, re, u, aoa, ns, nl, d_out,
+                   growth=None, h1=None, steps=1000, bumps=None, notes=""):
+    n_ref = len(patch_sizes)
+    sp = 2 ** n_ref
+    W, H = nx * sp, ny * sp
+    le = (float(round(W / 3.0)), 0.5 * H)
+    peaks = [0.1 * (m + 1) for m in range(8)]
+    om = naca0012_omesh(chord, le, ns, nl, d_out, growth=growth, h1=h1,
+                        bump_amps=bumps, bump_peaks=peaks if bumps is not None else None)
+    patches = _place_patches(le[0] + 0.5 * chord, le[1], patch_sizes, n_ref, sp)
+    return Workload(name=name, nx_cells=nx, ny_cells=ny, patches=patches, u_inf=u,
+                    aoa_deg=aoa, re=re, chord=chord, mesh_xy=om.xy, mesh_tri=om.tri,
+                    mesh_kind=om.kind, inner_ellipse=_inner_ellipse(om), steps=steps,
+                    omesh=om, notes=notes)
+
+
+HH_PEAKS = [0.1 * (m + 1) for m in range(8)]
+
+
+def hh_amplitudes(seed: int = 0) -> np.ndarray:
+    """Seeded Hicks-Henne amplitudes, uniform in [-0.002, 0.002] (chord units)."""
+    return np.random.default_rng(seed).uniform(-0.002, 0.002, 8)
+
+
+def naca_re100_c40(aoa_deg: float = 0.0) -> Workload:
+    """Small FP64 case: 240x120 grid, c = 40, Re = 100, 128x16 O-mesh."""
+    return _naca_workload("naca0012_re100_c40_240x120", 240, 120, [], 40.0, 100.0, 0.05,
+                          aoa_deg, 128, 16, 52.0, growth=1.15, steps=2000)
+
+
+def naca_re1000_c128(aoa_deg: float = 0.0) -> Workload:
+    """Re = 1000, c = 128: 1024x512 base cells (spacing 2), one 384x192 box, 512x64 mesh."""
+    return _naca_workload("naca0012_re1000_c128_1024x512_r1", 1024, 512, [(384, 192)], 128.0,
+                          1000.0, 0.05, aoa_deg, 512, 64, 92.0, h1=0.5, steps=40000)
+
+
+def naca_re1e4_c256() -> Workload:
+    """Re = 1e4, c = 256: 2048x1024 base cells (spacing 4), two nested boxes, 1024x128 mesh."""
+    return _naca_workload("naca0012_re1e4_c256_2048x1024_r2", 2048, 1024,
+                          [(768, 384), (768, 384)], 256.0, 1.0e4, 0.04, 0.0, 1024, 128,
+                          188.0, h1=0.512, steps=100000)
+
+
+def naca_re1000_c128_bumps() -> Workload:
+    """Shape-gradient case: the Re = 1000, c = 128 geometry at 5 deg with seeded Hicks-Henne bumps."""
+    return _naca_workload("naca0012_re1000_c128_aoa5_bumps", 1024, 512, [(384, 192)], 128.0,
+                          1000.0, 0.05, 5.0, 512, 64, 92.0, h1=0.5, steps=25000,
+                          bumps=hh_amplitudes(0))
+
+
+def naca_re5000_c512() -> Workload:
+    """Throughput case: 8192x4096 base cells (spacing 2), 2048x1024 box, 2048x128 mesh."""
+    return _naca_workload("naca0012_re5000_c512_8192x4096_r1", 8192, 4096, [(2048, 1024)],
+                          512.0, 5000.0, 0.05, 8.0, 2048, 128, 508.0, h1=0.5, steps=10000)
+
+
+PRESETS = {
+    "naca_re100_c40": naca_re100_c40,
+    "naca_re1000_c128": naca_re1000_c128,
+    "naca_re1e4_c256": naca_re1e4_c256,
+    "naca_re1000_c128_bumps": naca_re1000_c128_bumps,
+    "naca_re5000_c512": naca_re5000_c512,
+}
