@@ -1,0 +1,175 @@
+/*
+ * hlbm.h -- C ABI of the hybrid lattice Boltzmann (HLBM) step on one MI355X.
+ *
+ * Method: G. Di Ilio et al., "Fluid flow around NACA 0012 airfoil at low
+ * Reynolds numbers with hybrid lattice Boltzmann method" (arXiv 2006.10487).
+ * One call of hlbm_step advances, per finest time step:
+ *   - the D2Q9 BGK collide-stream of eq. (1)-(2) on a uniform Cartesian grid
+ *     with nested factor-two refinement boxes and time subcycling (Sec. 4);
+ *   - the cell-vertex finite-volume update of eq. (3) on a body-fitted
+ *     triangular mesh, n sub-steps per structured step (Sec. 6.3);
+ *   - the two-way coupling of eqs. (4)-(7) at interpolation nodes, with the
+ *     quadratic interpolations of eqs. (8)-(9) (Sec. 3);
+ *   - the drag and lift of eqs. (10)-(11) from the wall momentum flux.
+ *
+ * Conventions.
+ *   - Coordinates and times are lattice units of the finest structured level
+ *     (spacing 1, time step 1).  Level 0 is the coarsest (base) grid; level
+ *     n_refine is the finest.  Level l has spacing 2^(n_refine - l).
+ *   - D2Q9 population order: (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1)
+ *     (-1,-1) (1,-1).
+ *   - Host arrays passed in are borrowed for the duration of the call.  The
+ *     device workspace is owned by the caller, must stay allocated until
+ *     hlbm_destroy, and is carved by the library; the library never allocates
+ *     device memory and enqueues all work on the caller's HIP stream.
+ *   - Every function returns HLBM_OK (0) or a negative error code; the text
+ *     of the last error of a context is given by hlbm_last_error.
+ *   - One host thread per context.  hlbm_step is asynchronous; calls that
+ *     return host data synchronise the stream.
+ */
+#ifndef HLBM_H
+#define HLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    HLBM_OK = 0,
+    HLBM_E_ARG = -1,        /* null pointer, out-of-range argument, bad part or count     */
+    HLBM_E_GEOMETRY = -2,   /* mesh not counter-clockwise, degenerate control volume,
+                               box outside its parent, stencil donor not active, ...      */
+    HLBM_E_PARAM = -3,      /* tau <= 1/2 on some level, Re and tau inconsistent          */
+    HLBM_E_DEVICE = -4,     /* a HIP call failed                                          */
+    HLBM_E_NONFINITE = -5,  /* non-finite force detected; context poisoned                */
+    HLBM_E_STATE = -6,      /* call not allowed in this state (e.g. poisoned context)     */
+    HLBM_E_WORKSPACE = -7   /* workspace too small or misaligned                          */
+};
+
+enum { HLBM_FP64 = 0, HLBM_FP32_SHIFTED = 1 };
+enum { HLBM_INTERP_QUADRATIC = 0, HLBM_INTERP_LINEAR = 1 };
+enum { HLBM_BC_FARFIELD = 0, HLBM_BC_PERIODIC = 1 };
+enum { HLBM_PART_MESH = 100 };   /* hlbm_get_state / hlbm_set_state: mesh populations */
+
+typedef struct hlbm_ctx hlbm_ctx;
+
+/* Structured grid and run options. */
+typedef struct {
+    int32_t nx_cells, ny_cells;   /* base-level cells (nodes = cells + 1; periodic: nodes = cells) */
+    int32_t n_refine;             /* nested refinement boxes, 0..3                                  */
+    int32_t patch_i0[3], patch_j0[3]; /* box origin, in nodes of its parent level                  */
+    int32_t patch_nx[3], patch_ny[3]; /* box size in its own cells (even)                          */
+    double u_inf;                 /* free-stream speed (finest lattice units)                       */
+    double aoa_rad;               /* angle of attack: the free stream is U (cos a, sin a)           */
+    double rho0;                  /* reference density (1)                                          */
+    int32_t precision;            /* HLBM_FP64 or HLBM_FP32_SHIFTED                                 */
+    int32_t interp;               /* HLBM_INTERP_QUADRATIC (eqs 8-9) or HLBM_INTERP_LINEAR          */
+    int32_t n_sub;                /* FV sub-steps per finest step; 0 = max(10, ceil(1 / tau_u))      */
+    int32_t bc;                   /* HLBM_BC_FARFIELD or HLBM_BC_PERIODIC (base level)              */
+    int32_t wall_bc;              /* 1 = no-slip at mesh wall nodes, 0 = off (free-stream checks)    */
+    int32_t check_every;          /* non-finite check interval in finest steps, 0 = off             */
+    int32_t history_len;          /* force history ring length, 0 = 65536                            */
+} hlbm_grid;
+
+/* Body-fitted triangular mesh (Sec. 2 and 4). */
+typedef struct {
+    int32_t n_nodes, n_tris;      /* 0 nodes = no mesh (structured grid only)                       */
+    const double *xy;             /* [2 * n_nodes] node coordinates                                 */
+    const int32_t *tri;           /* [3 * n_tris] counter-clockwise vertex triples                  */
+    const uint8_t *kind;          /* [n_nodes] 0 interior, 1 wall (no-slip), 2 interpolation node   */
+    double chord;                 /* reference length of eqs. (10)-(11)                             */
+    double inner_ellipse[4];      /* xc, yc, a, b of the inner fictitious ellipse; structured nodes
+                                     strictly inside are inactive (a <= 0: none)                     */
+} hlbm_mesh;
+
+typedef struct {
+    int32_t n_levels;             /* n_refine + 1 (0 without a grid)                                */
+    int32_t n_sub;                /* FV sub-steps per finest step                                   */
+    int32_t nx[4], ny[4], pitch[4];   /* nodes and row pitch (elements) per level                  */
+    double tau[4];                /* relaxation time per level (level units)                        */
+    double tau_u;                 /* FV relaxation time = tau_finest - 1/2 (finest units)           */
+    int64_t active_nodes[4];      /* collide-stream nodes per level                                 */
+    int32_t n_mesh_nodes, n_wall_nodes, n_interp_mesh, n_interp_struct, n_fallback;
+    int32_t n_wall_edges, nnz;
+    int64_t bytes_per_finest_step;    /* algorithmic bytes, all kernels                             */
+    int64_t k1_bytes[4];          /* algorithmic bytes of one collide-stream launch per level       */
+    int64_t fv_bytes;             /* algorithmic bytes of one FV sub-step launch                    */
+    int64_t t;                    /* finest steps done                                              */
+    size_t workspace_bytes;
+} hlbm_info_t;
+
+/* Checks the problem on the host only (no GPU).  Re > 0 gives
+ * tau = 1/2 + 3 U chord / Re (nu = c_s^2 (tau - 1/2), Sec. 2); tau > 1/2 is used
+ * as is, and then Re must be <= 0 or consistent to 1e-12.  Returns HLBM_OK or
+ * HLBM_E_ARG / HLBM_E_GEOMETRY / HLBM_E_PARAM. */
+int hlbm_validate(const hlbm_grid *grid, const hlbm_mesh *mesh, double Re, double tau);
+
+/* Device workspace bytes needed by hlbm_create (host only, no GPU). */
+int hlbm_workspace_size(const hlbm_grid *grid, const hlbm_mesh *mesh, double Re, double tau,
+                        size_t *ws_bytes);
+
+/* Builds the context: host preprocessing (control volumes, stencils, node
+ * order), copies the tables into d_workspace (device pointer, 256-byte
+ * aligned, ws_bytes >= hlbm_workspace_size) and sets the initial state
+ * f^eq(rho0, u_inf) (f^eq(rho0, 0) at wall nodes).  hip_stream is a
+ * hipStream_t (NULL = default stream).  On failure *out is NULL. */
+int hlbm_create(const hlbm_grid *grid, const hlbm_mesh *mesh, double Re, double tau,
+                void *d_workspace, size_t ws_bytes, void *hip_stream, hlbm_ctx **out);
+
+/* Advances n_finest_steps finest steps (a multiple of 2^n_refine).  Async. */
+int hlbm_step(hlbm_ctx *ctx, int64_t n_finest_steps);
+
+/* Drag and lift coefficients of the last finest step (eqs. (10)-(11)).  Syncs. */
+int hlbm_forces(hlbm_ctx *ctx, double *cd, double *cl);
+
+/* Coefficients of finest steps [t0, t1) (within the last history_len steps).  Syncs. */
+int hlbm_force_history(hlbm_ctx *ctx, int64_t t0, int64_t t1, double *cd, double *cl);
+
+/* Canonical state in FP64.  part = level l: pre-collision populations
+ * [9][ny][nx] of level l, zero at nodes that are not collide-stream nodes;
+ * part = HLBM_PART_MESH: mesh populations [9][n_nodes] in the caller's node
+ * order.  count = number of doubles.  Syncs. */
+int hlbm_get_state(hlbm_ctx *ctx, int32_t part, double *host, size_t count);
+
+/* Replaces a part of the state (same layout as hlbm_get_state; on a level,
+ * values at non-collide-stream nodes are ignored).  Set every level and the
+ * mesh before stepping on.  Syncs. */
+int hlbm_set_state(hlbm_ctx *ctx, int32_t part, const double *host, size_t count);
+
+int hlbm_info(hlbm_ctx *ctx, hlbm_info_t *out);
+
+/* Kernel classes timed by hlbm_profile_read. */
+enum {
+    HLBM_K_COLLIDE_L0 = 0,      /* collide-stream of level 0 (+1, +2, +3 for finer levels) */
+    HLBM_K_COARSE_TO_FINE = 4,
+    HLBM_K_FINE_TO_COARSE = 5,
+    HLBM_K_MESH_TO_STRUCT = 6,  /* eq. (4) */
+    HLBM_K_STRUCT_TO_MESH = 7,  /* eq. (9) */
+    HLBM_K_FV = 8,              /* one finite-volume sub-step, eqs. (3), (5) */
+    HLBM_K_FORCE = 9,           /* eqs. (10)-(11) */
+    HLBM_K_COUNT = 10
+};
+
+/* Instrumentation: with enable != 0, every kernel launched by hlbm_step is
+ * bracketed by a pair of HIP events recorded on the context's stream.  Events
+ * are created by the library on first use (no device memory is allocated). */
+int hlbm_profile(hlbm_ctx *ctx, int enable);
+
+/* Synchronises the stream and returns, per kernel class, the summed
+ * event-measured time in ms and the launch count since the last read
+ * (arrays of HLBM_K_COUNT entries); then resets the counters. */
+int hlbm_profile_read(hlbm_ctx *ctx, double *ms, int64_t *launches);
+
+/* Text of the last error of ctx (or of the last failed create when ctx is NULL). */
+const char *hlbm_last_error(const hlbm_ctx *ctx);
+
+/* Releases the host side of the context (the workspace stays the caller's). */
+void hlbm_destroy(hlbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HLBM_H */

@@ -833,10 +833,13 @@ void *or_create(const or_cfg *cfg, char *err_out, int32_t err_len)
     equilibrium(cfg->rho0, 0.0, 0.0, feq0);
     for (int l = 0; cfg->nx_cells > 0 && l <= o->L; ++l) {
         olevel *lv = &o->lev[l];
-        for (int j = 0; j < lv->ny; ++j)
-            for (int i = 0; i < lv->nx; ++i) put_node(lv, lv->f, i, j, feq);
-        memcpy(lv->post, lv->f, sizeof(double) * Q * lv->nx * lv->ny);
-        memcpy(lv->save, lv->f, sizeof(double) * Q * lv->nx * lv->ny);
+        size_t plane = (size_t)lv->nx * lv->ny;
+        for (int q = 0; q < Q; ++q)       /* one population plane at a time */
+            for (size_t a = 0; a < plane; ++a) {
+                lv->f[q * plane + a] = feq[q];
+                lv->post[q * plane + a] = feq[q];
+                lv->save[q * plane + a] = feq[q];
+            }
     }
     for (int p = 0; p < o->nn; ++p)
         for (int q = 0; q < Q; ++q)

@@ -1,0 +1,557 @@
+// capi.cpp -- C ABI of the HLBM library: context, workspace carving, the
+// per-step orchestration of the hybrid scheme, state import/export, forces.
+//
+// One finest step t -> t+1, inside the level recursion (Sec. 4 time
+// subcycling: level l advances once per 2^(L-l) finest steps, and each of
+// its steps is followed by two steps of the finer box):
+//   level_step(l):
+//     l == L: structured interpolation nodes <- mesh at t      (eq. (4))
+//     collide-stream of level l                                (eq. (1))
+//     l <  L: coarse -> fine perimeter at theta = 0; level_step(l+1);
+//             coarse -> fine perimeter at theta = 1/2; level_step(l+1);
+//             fine -> coarse ring                               (Sec. 4)
+//     l == L: mesh interpolation nodes <- finest level at t+1  (eq. (9))
+//             n finite-volume sub-steps, theta = m / n         (eqs. (3), (5))
+//             drag and lift                                     (eqs. (10)-(11))
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hlbm_internal.h"
+
+using namespace hlbm;
+
+struct hlbm_ctx {
+    Plan p;
+    hipStream_t s = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    int cur[4] = {0, 0, 0, 0};   // buffer holding the current post-collision state
+    int side_t[4] = {0, 0, 0, 0};  // side slot holding the parent's (rho, u, f^neq) at the parent's time
+    int mesh_cur = 0;
+    int prep_t = 0;               // prep slot holding the mesh interpolation values at time t
+    int64_t t = 0;
+    int64_t last_check = 0;
+    bool poisoned = false;
+    bool dirty = false;           // an import must be finished before stepping
+    std::string err;
+    KLevel kl[4];
+    KMesh km;
+    std::vector<double> tmp;
+    // instrumentation
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+
+    void* lev(int l, int b) { return ws + p.off.lev[l][b]; }
+    void* side(int l, int b) { return ws + p.off.side[l][b]; }
+    void* mesh(int b) { return ws + p.off.mesh[b]; }
+    void* prep(int b) { return ws + p.off.prep[b]; }
+    double* hist() { return reinterpret_cast<double*>(ws + p.off.hist); }
+    double* stage() { return reinterpret_cast<double*>(ws + p.off.stage); }
+};
+
+namespace {
+
+std::string g_create_err;
+
+hipEvent_t take_event(hlbm_ctx* c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one kernel launch with events when profiling is on.
+struct Timed {
+    hlbm_ctx* c;
+    int cls;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(hlbm_ctx* c_, int cls_) : c(c_), cls(cls_) {
+        if (!c->prof) return;
+        a = take_event(c);
+        b = take_event(c);
+        if (a && b) (void)hipEventRecord(a, c->s);
+    }
+    ~Timed() {
+        if (!c->prof || !a || !b) return;
+        (void)hipEventRecord(b, c->s);
+        c->ev_pending.push_back({cls, {a, b}});
+    }
+};
+
+int set_err(hlbm_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_create_err = msg;
+    return code;
+}
+
+int hip_check(hlbm_ctx* c, hipError_t e, const char* what) {
+    if (e == hipSuccess) return HLBM_OK;
+    return set_err(c, HLBM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+std::vector<char> pack_real(const std::vector<double>& v) {
+    std::vector<char> out(v.size() * sizeof(T));
+    T* d = reinterpret_cast<T*>(out.data());
+    for (size_t a = 0; a < v.size(); ++a) d[a] = T(v[a]);
+    return out;
+}
+
+int upload(hlbm_ctx* c, size_t off, const void* src, size_t bytes) {
+    if (!bytes) return HLBM_OK;
+    return hip_check(c, hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->s), "hipMemcpyAsync");
+}
+
+void setup_views(hlbm_ctx* c) {
+    const Plan& p = c->p;
+    for (int l = 0; l <= p.L; ++l) {
+        const LevelPlan& v = p.lev[l];
+        KLevel& k = c->kl[l];
+        k.nx = v.nx;
+        k.ny = v.ny;
+        k.pitch = v.pitch;
+        k.stride = (long long)v.ny * v.pitch;
+        k.omega = 1.0 / v.tau;
+        k.perim_inactive = v.perim_inactive;
+        k.ci0 = v.has_child ? v.ci0 : -4;
+        k.cj0 = v.has_child ? v.cj0 : -4;
+        k.ci1 = v.has_child ? v.ci1 : -4;
+        k.cj1 = v.has_child ? v.cj1 : -4;
+        k.farfield = v.farfield;
+        k.periodic = v.periodic;
+        const bool spans = l == p.L && !p.spans.empty();
+        k.spans = spans ? reinterpret_cast<const int32_t*>(c->ws + p.off.spans) : nullptr;
+        k.sj0 = v.sj0;
+        k.sj1 = v.sj1;
+        k.u_in_x = p.u_inf * std::cos(p.aoa);
+        k.u_in_y = p.u_inf * std::sin(p.aoa);
+        k.rho0 = p.rho0;
+    }
+    KMesh& m = c->km;
+    m.nn = p.nn;
+    m.n_wall = p.n_wall;
+    m.n_core = p.n_core;
+    m.rowptr = reinterpret_cast<const int32_t*>(c->ws + p.off.rowptr);
+    m.edges = c->ws + p.off.edges;
+    m.dt = p.dt_u;
+    m.dt_over_tau = p.dt_u / p.tau_u;
+    m.star_neq = 1.0 - 1.0 / (2.0 * p.tau_s);
+    m.wall_bc = p.wall_bc;
+    m.rho0 = p.rho0;
+}
+
+int upload_tables(hlbm_ctx* c) {
+    const Plan& p = c->p;
+    const bool f64 = p.precision == HLBM_FP64;
+    int rc = HLBM_OK;
+    auto real = [&](const std::vector<double>& v) { return f64 ? pack_real<double>(v) : pack_real<float>(v); };
+    std::vector<std::vector<char>> keep;   // host copies alive until the stream syncs
+    rc |= upload(c, p.off.spans, p.spans.data(), p.spans.size() * 4);
+    rc |= upload(c, p.off.sint_node, p.sint_node.data(), p.sint_node.size() * 4);
+    rc |= upload(c, p.off.sint_don, p.sint_don.data(), p.sint_don.size() * 4);
+    keep.push_back(real(p.sint_w));
+    rc |= upload(c, p.off.sint_w, keep.back().data(), keep.back().size());
+    if (p.has_mesh) {
+        rc |= upload(c, p.off.rowptr, p.rowptr.data(), p.rowptr.size() * 4);
+        const size_t nnz = p.col.size();
+        std::vector<char> rec(nnz * (f64 ? 32 : 16), 0);
+        for (size_t z = 0; z < nnz; ++z) {
+            char* r = rec.data() + z * (f64 ? 32 : 16);
+            std::memcpy(r, &p.col[z], 4);
+            if (f64) {
+                const double v[3] = {p.gx[z], p.gy[z], p.cc[z]};
+                std::memcpy(r + 8, v, 24);
+            } else {
+                const float v[3] = {float(p.gx[z]), float(p.gy[z]), float(p.cc[z])};
+                std::memcpy(r + 4, v, 12);
+            }
+        }
+        keep.push_back(std::move(rec));
+        rc |= upload(c, p.off.edges, keep.back().data(), keep.back().size());
+        rc |= upload(c, p.off.wedge, p.wedge.data(), p.wedge.size() * 4);
+        rc |= upload(c, p.off.wnorm, p.wnorm.data(), p.wnorm.size() * 8);
+        rc |= upload(c, p.off.uint_don, p.uint_don.data(), p.uint_don.size() * 4);
+        keep.push_back(real(p.uint_w));
+        rc |= upload(c, p.off.uint_w, keep.back().data(), keep.back().size());
+    }
+    if (rc) return HLBM_E_DEVICE;
+    return hip_check(c, hipStreamSynchronize(c->s), "hipStreamSynchronize");
+}
+
+// Derived state after the streamed populations of every level were written
+// into its previous buffer (by a scatter) and the mesh into its current one:
+// post-collision state, restricted rings, box-boundary values, mesh
+// interpolation values at time t.
+void finish_import(hlbm_ctx* c) {
+    const Plan& p = c->p;
+    const int pr = p.precision;
+    for (int l = 0; l <= p.L; ++l)
+        launch_stream_collide(pr, c->kl[l], c->lev(l, 1 - c->cur[l]), c->lev(l, c->cur[l]), c->s);
+    for (int l = 0; l < p.L; ++l) {
+        const LevelPlan& v = p.lev[l];
+        launch_side_init(pr, c->kl[l], v.ci0, v.cj0, v.ci1 - v.ci0, v.cj1 - v.cj0, c->lev(l, 1 - c->cur[l]),
+                         c->side(l, c->side_t[l]), c->s);
+        launch_fine_to_coarse(pr, c->kl[l], c->kl[l + 1], v.ci0, v.cj0, v.ci1 - v.ci0, v.cj1 - v.cj0,
+                              c->lev(l + 1, 1 - c->cur[l + 1]), c->lev(l, c->cur[l]), v.tau, p.lev[l + 1].tau, c->s);
+    }
+    if (p.has_mesh && p.n_int > 0)
+        launch_struct_to_mesh(pr, c->kl[p.L], c->lev(p.L, 1 - c->cur[p.L]), p.n_int,
+                              reinterpret_cast<const int32_t*>(c->ws + p.off.uint_don), c->ws + p.off.uint_w,
+                              c->prep(c->prep_t), c->s);
+    c->dirty = false;
+}
+
+void finest_step(hlbm_ctx* c) {
+    const Plan& p = c->p;
+    const int pr = p.precision, L = p.L;
+    void* A = c->lev(L, c->cur[L]);
+    void* B = c->lev(L, 1 - c->cur[L]);
+    if (p.has_mesh && !p.sint_node.empty()) {
+        const double ts = p.lev[L].tau;
+        Timed tm(c, HLBM_K_MESH_TO_STRUCT);
+        launch_mesh_to_struct(pr, c->kl[L], A, int(p.sint_node.size()),
+                              reinterpret_cast<const int32_t*>(c->ws + p.off.sint_node),
+                              reinterpret_cast<const int32_t*>(c->ws + p.off.sint_don), c->ws + p.off.sint_w,
+                              c->mesh(c->mesh_cur), p.nn, 2.0 * (ts - 1.0) / (2.0 * ts - 1.0), c->s);
+    }
+    {
+        Timed tm(c, HLBM_K_COLLIDE_L0 + L);
+        launch_stream_collide(pr, c->kl[L], A, B, c->s);
+    }
+    double* slot = c->hist() + 2 * (c->t % p.hist_len);
+    if (p.has_mesh) {
+        if (p.n_int > 0) {
+            Timed tm(c, HLBM_K_STRUCT_TO_MESH);
+            launch_struct_to_mesh(pr, c->kl[L], A, p.n_int, reinterpret_cast<const int32_t*>(c->ws + p.off.uint_don),
+                                  c->ws + p.off.uint_w, c->prep(1 - c->prep_t), c->s);
+        }
+        for (int m = 0; m < p.n_sub; ++m) {
+            Timed tm(c, HLBM_K_FV);
+            launch_fv_substep(pr, c->km, c->mesh(c->mesh_cur), c->mesh(1 - c->mesh_cur), c->prep(c->prep_t),
+                              c->prep(1 - c->prep_t), double(m) / p.n_sub, c->s);
+            c->mesh_cur ^= 1;
+        }
+        const double qn = 0.5 * p.rho0 * p.u_inf * p.u_inf * p.chord;
+        Timed tm(c, HLBM_K_FORCE);
+        launch_wall_force(pr, c->km, c->mesh(c->mesh_cur), int(p.wedge.size() / 2),
+                          reinterpret_cast<const int32_t*>(c->ws + p.off.wedge),
+                          reinterpret_cast<const double*>(c->ws + p.off.wnorm), slot, std::cos(p.aoa),
+                          std::sin(p.aoa), qn > 0 ? qn : 1.0, c->s);
+        c->prep_t ^= 1;
+    } else {
+        // no wall: zero force (the kernel writes 0 for an empty edge list)
+        launch_wall_force(pr, c->km, c->mesh(0), 0, nullptr, nullptr, slot, 1.0, 0.0, 1.0, c->s);
+    }
+    c->cur[L] ^= 1;
+    c->t++;
+}
+
+void level_step(hlbm_ctx* c, int l) {
+    const Plan& p = c->p;
+    if (l == p.L) {
+        finest_step(c);
+        return;
+    }
+    const int pr = p.precision;
+    const LevelPlan& v = p.lev[l];
+    void* A = c->lev(l, c->cur[l]);
+    void* B = c->lev(l, 1 - c->cur[l]);
+    {
+        Timed tm(c, HLBM_K_COLLIDE_L0 + l);
+        launch_stream_collide(pr, c->kl[l], A, B, c->s);
+    }
+    for (int half = 0; half < 2; ++half) {
+        {
+            Timed tm(c, HLBM_K_COARSE_TO_FINE);
+            launch_coarse_to_fine(pr, c->kl[l], c->kl[l + 1], v.ci0, v.cj0, A, c->lev(l + 1, c->cur[l + 1]),
+                              c->side(l, 1 - c->side_t[l]), c->side(l, c->side_t[l]), 0.5 * half, half == 0,
+                              v.tau, p.lev[l + 1].tau, c->s);
+        }
+        level_step(c, l + 1);
+    }
+    Timed tm(c, HLBM_K_FINE_TO_COARSE);
+    launch_fine_to_coarse(pr, c->kl[l], c->kl[l + 1], v.ci0, v.cj0, v.ci1 - v.ci0, v.cj1 - v.cj0,
+                          c->lev(l + 1, 1 - c->cur[l + 1]), B, v.tau, p.lev[l + 1].tau, c->s);
+    c->side_t[l] ^= 1;
+    c->cur[l] ^= 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hlbm_validate(const hlbm_grid* grid, const hlbm_mesh* mesh, double Re, double tau) {
+    Plan p;
+    std::string err;
+    const int rc = build_plan(grid, mesh, Re, tau, p, err);
+    if (rc) g_create_err = err;
+    return rc;
+}
+
+int hlbm_workspace_size(const hlbm_grid* grid, const hlbm_mesh* mesh, double Re, double tau, size_t* ws_bytes) {
+    if (!ws_bytes) return set_err(nullptr, HLBM_E_ARG, "ws_bytes is null");
+    Plan p;
+    std::string err;
+    const int rc = build_plan(grid, mesh, Re, tau, p, err);
+    if (rc) return set_err(nullptr, rc, err);
+    *ws_bytes = p.off.total;
+    return HLBM_OK;
+}
+
+int hlbm_create(const hlbm_grid* grid, const hlbm_mesh* mesh, double Re, double tau, void* d_workspace,
+                size_t ws_bytes, void* hip_stream, hlbm_ctx** out) {
+    if (!out) return set_err(nullptr, HLBM_E_ARG, "out is null");
+    *out = nullptr;
+    hlbm_ctx* c = new (std::nothrow) hlbm_ctx();
+    if (!c) return set_err(nullptr, HLBM_E_ARG, "out of host memory");
+    std::string err;
+    int rc = build_plan(grid, mesh, Re, tau, c->p, err);
+    if (rc) {
+        delete c;
+        return set_err(nullptr, rc, err);
+    }
+    if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255) || ws_bytes < c->p.off.total) {
+        const size_t need = c->p.off.total;
+        delete c;
+        return set_err(nullptr, HLBM_E_WORKSPACE,
+                       "workspace must be 256-byte aligned and hold " + std::to_string(need) + " bytes");
+    }
+    c->ws = static_cast<char*>(d_workspace);
+    c->ws_bytes = ws_bytes;
+    c->s = static_cast<hipStream_t>(hip_stream);
+    setup_views(c);
+    rc = upload_tables(c);
+    if (rc) {
+        g_create_err = c->err;
+        delete c;
+        return rc;
+    }
+    // initial state: f^eq(rho0, u_inf) on every level and mesh node, f^eq(rho0, 0) at walls
+    const Plan& p = c->p;
+    const double ux = p.u_inf * std::cos(p.aoa), uy = p.u_inf * std::sin(p.aoa);
+    for (int l = 0; l <= p.L; ++l) launch_fill_uniform(p.precision, c->lev(l, 1), c->kl[l], p.rho0, ux, uy, c->s);
+    if (p.has_mesh) {
+        std::vector<double> f0(size_t(kQ) * p.nn);
+        const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+        const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+        for (int P = 0; P < p.nn; ++P) {
+            const bool wall = P < p.n_wall && p.wall_bc;
+            const double u = wall ? 0.0 : ux, v = wall ? 0.0 : uy;
+            for (int q = 0; q < 9; ++q) {
+                const double cu = cx[q] * u + cy[q] * v;
+                f0[size_t(q) * p.nn + P] = w[q] * p.rho0 * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (u * u + v * v));
+            }
+        }
+        rc = upload(c, p.off.stage, f0.data(), f0.size() * 8);
+        launch_mesh_convert(p.precision, p.nn, c->stage(), c->mesh(0), 1, p.rho0, c->s);
+        rc |= hip_check(c, hipStreamSynchronize(c->s), "init");
+        if (rc) {
+            g_create_err = c->err;
+            delete c;
+            return HLBM_E_DEVICE;
+        }
+    }
+    finish_import(c);
+    rc = hip_check(c, hipGetLastError(), "kernel launch");
+    if (rc) {
+        g_create_err = c->err;
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return HLBM_OK;
+}
+
+int hlbm_step(hlbm_ctx* c, int64_t n) {
+    if (!c) return HLBM_E_ARG;
+    if (c->poisoned) return set_err(c, HLBM_E_STATE, "context poisoned by a non-finite state");
+    const int64_t per = int64_t(1) << c->p.L;
+    if (n < 0 || n % per) return set_err(c, HLBM_E_ARG, "step count must be a non-negative multiple of 2^n_refine");
+    if (c->dirty) finish_import(c);
+    for (int64_t b = 0; b < n / per; ++b) {
+        level_step(c, 0);
+        if (c->p.check_every > 0 && c->t - c->last_check >= c->p.check_every) {
+            c->last_check = c->t;
+            double v[2];
+            int rc = hip_check(c, hipMemcpyAsync(v, c->hist() + 2 * ((c->t - 1) % c->p.hist_len), 16,
+                                                 hipMemcpyDeviceToHost, c->s), "check");
+            rc |= hip_check(c, hipStreamSynchronize(c->s), "check");
+            if (rc) return HLBM_E_DEVICE;
+            if (!std::isfinite(v[0]) || !std::isfinite(v[1])) {
+                c->poisoned = true;
+                return set_err(c, HLBM_E_NONFINITE, "non-finite force at step " + std::to_string(c->t));
+            }
+        }
+    }
+    return hip_check(c, hipGetLastError(), "kernel launch");
+}
+
+int hlbm_forces(hlbm_ctx* c, double* cd, double* cl) {
+    if (!c || !cd || !cl) return HLBM_E_ARG;
+    if (c->t == 0) {
+        *cd = *cl = 0.0;
+        return HLBM_OK;
+    }
+    return hlbm_force_history(c, c->t - 1, c->t, cd, cl);
+}
+
+int hlbm_force_history(hlbm_ctx* c, int64_t t0, int64_t t1, double* cd, double* cl) {
+    if (!c || !cd || !cl) return HLBM_E_ARG;
+    if (t0 < 0 || t1 > c->t || t0 > t1 || t1 - t0 > c->p.hist_len || t0 < c->t - c->p.hist_len)
+        return set_err(c, HLBM_E_ARG, "history range outside the recorded window");
+    std::vector<double> buf(size_t(c->p.hist_len) * 2);
+    int rc = hip_check(c, hipMemcpyAsync(buf.data(), c->hist(), buf.size() * 8, hipMemcpyDeviceToHost, c->s), "history");
+    rc |= hip_check(c, hipStreamSynchronize(c->s), "history");
+    if (rc) return HLBM_E_DEVICE;
+    for (int64_t t = t0; t < t1; ++t) {
+        cd[t - t0] = buf[2 * (t % c->p.hist_len)];
+        cl[t - t0] = buf[2 * (t % c->p.hist_len) + 1];
+    }
+    return HLBM_OK;
+}
+
+int hlbm_get_state(hlbm_ctx* c, int32_t part, double* host, size_t count) {
+    if (!c || !host) return HLBM_E_ARG;
+    const Plan& p = c->p;
+    if (part == HLBM_PART_MESH) {
+        if (!p.has_mesh || count != size_t(kQ) * p.nn) return set_err(c, HLBM_E_ARG, "bad mesh count");
+        launch_mesh_convert(p.precision, p.nn, c->stage(), c->mesh(c->mesh_cur), 0, p.rho0, c->s);
+        c->tmp.resize(count);
+        int rc = hip_check(c, hipMemcpyAsync(c->tmp.data(), c->stage(), count * 8, hipMemcpyDeviceToHost, c->s), "get");
+        rc |= hip_check(c, hipStreamSynchronize(c->s), "get");
+        if (rc) return HLBM_E_DEVICE;
+        for (int q = 0; q < kQ; ++q)
+            for (int P = 0; P < p.nn; ++P) host[size_t(q) * p.nn + p.perm[P]] = c->tmp[size_t(q) * p.nn + P];
+        return HLBM_OK;
+    }
+    if (part < 0 || part > p.L) return set_err(c, HLBM_E_ARG, "bad part");
+    const LevelPlan& v = p.lev[part];
+    if (count != size_t(kQ) * v.nx * v.ny) return set_err(c, HLBM_E_ARG, "bad level count");
+    const int rows = int(std::max<size_t>(1, p.stage_bytes / (size_t(kQ) * v.nx * 8)));
+    for (int j0 = 0; j0 < v.ny; j0 += rows) {
+        const int j1 = std::min(v.ny, j0 + rows);
+        launch_export_level(p.precision, c->kl[part], c->lev(part, 1 - c->cur[part]), c->stage(), j0, j1, c->s);
+        const size_t n = size_t(kQ) * (j1 - j0) * v.nx;
+        c->tmp.resize(n);
+        int rc = hip_check(c, hipMemcpyAsync(c->tmp.data(), c->stage(), n * 8, hipMemcpyDeviceToHost, c->s), "get");
+        rc |= hip_check(c, hipStreamSynchronize(c->s), "get");
+        if (rc) return HLBM_E_DEVICE;
+        for (int q = 0; q < kQ; ++q)
+            std::memcpy(host + (size_t(q) * v.ny + j0) * v.nx, c->tmp.data() + size_t(q) * (j1 - j0) * v.nx,
+                        size_t(j1 - j0) * v.nx * 8);
+    }
+    return HLBM_OK;
+}
+
+int hlbm_set_state(hlbm_ctx* c, int32_t part, const double* host, size_t count) {
+    if (!c || !host) return HLBM_E_ARG;
+    if (c->poisoned) return set_err(c, HLBM_E_STATE, "context poisoned by a non-finite state");
+    const Plan& p = c->p;
+    if (part == HLBM_PART_MESH) {
+        if (!p.has_mesh || count != size_t(kQ) * p.nn) return set_err(c, HLBM_E_ARG, "bad mesh count");
+        c->tmp.resize(count);
+        for (int q = 0; q < kQ; ++q)
+            for (int P = 0; P < p.nn; ++P) c->tmp[size_t(q) * p.nn + P] = host[size_t(q) * p.nn + p.perm[P]];
+        int rc = hip_check(c, hipMemcpyAsync(c->stage(), c->tmp.data(), count * 8, hipMemcpyHostToDevice, c->s), "set");
+        launch_mesh_convert(p.precision, p.nn, c->stage(), c->mesh(c->mesh_cur), 1, p.rho0, c->s);
+        rc |= hip_check(c, hipStreamSynchronize(c->s), "set");
+        if (rc) return HLBM_E_DEVICE;
+        c->dirty = true;
+        return HLBM_OK;
+    }
+    if (part < 0 || part > p.L) return set_err(c, HLBM_E_ARG, "bad part");
+    const LevelPlan& v = p.lev[part];
+    if (count != size_t(kQ) * v.nx * v.ny) return set_err(c, HLBM_E_ARG, "bad level count");
+    const int rows = int(std::max<size_t>(1, p.stage_bytes / (size_t(kQ) * v.nx * 8)));
+    for (int j0 = 0; j0 < v.ny; j0 += rows) {
+        const int j1 = std::min(v.ny, j0 + rows);
+        const size_t n = size_t(kQ) * (j1 - j0) * v.nx;
+        c->tmp.resize(n);
+        for (int q = 0; q < kQ; ++q)
+            std::memcpy(c->tmp.data() + size_t(q) * (j1 - j0) * v.nx, host + (size_t(q) * v.ny + j0) * v.nx,
+                        size_t(j1 - j0) * v.nx * 8);
+        int rc = hip_check(c, hipMemcpyAsync(c->stage(), c->tmp.data(), n * 8, hipMemcpyHostToDevice, c->s), "set");
+        launch_import_level(p.precision, c->kl[part], c->lev(part, 1 - c->cur[part]), c->stage(), j0, j1, c->s);
+        rc |= hip_check(c, hipStreamSynchronize(c->s), "set");
+        if (rc) return HLBM_E_DEVICE;
+    }
+    c->dirty = true;
+    return HLBM_OK;
+}
+
+int hlbm_info(hlbm_ctx* c, hlbm_info_t* o) {
+    if (!c || !o) return HLBM_E_ARG;
+    const Plan& p = c->p;
+    std::memset(o, 0, sizeof(*o));
+    o->n_levels = p.nlev;
+    o->n_sub = p.n_sub;
+    const int64_t E = int64_t(p.elem);
+    int64_t bytes = 0;
+    for (int l = 0; l <= p.L; ++l) {
+        o->nx[l] = p.lev[l].nx;
+        o->ny[l] = p.lev[l].ny;
+        o->pitch[l] = p.lev[l].pitch;
+        o->tau[l] = p.lev[l].tau;
+        o->active_nodes[l] = p.lev[l].active;
+        o->k1_bytes[l] = p.lev[l].active * 2 * kQ * E;
+        bytes += o->k1_bytes[l] << l;   // level l runs 2^l times per base step
+    }
+    o->tau_u = p.tau_u;
+    o->n_mesh_nodes = p.nn;
+    o->n_wall_nodes = p.n_wall;
+    o->n_interp_mesh = p.n_int;
+    o->n_interp_struct = int(p.sint_node.size());
+    o->n_fallback = p.n_fallback;
+    o->n_wall_edges = int(p.wedge.size() / 2);
+    o->nnz = int(p.col.size());
+    // FV sub-step: populations in and out, CSR records, row pointers
+    o->fv_bytes = int64_t(p.nn) * 2 * kQ * E + int64_t(p.col.size()) * (E == 8 ? 32 : 16) + int64_t(p.nn + 1) * 4;
+    o->bytes_per_finest_step = bytes / (int64_t(1) << p.L) + int64_t(p.n_sub) * o->fv_bytes;
+    o->t = c->t;
+    o->workspace_bytes = p.off.total;
+    return HLBM_OK;
+}
+
+int hlbm_profile(hlbm_ctx* c, int enable) {
+    if (!c) return HLBM_E_ARG;
+    c->prof = enable != 0;
+    return HLBM_OK;
+}
+
+int hlbm_profile_read(hlbm_ctx* c, double* ms, int64_t* launches) {
+    if (!c || !ms || !launches) return HLBM_E_ARG;
+    for (int k = 0; k < HLBM_K_COUNT; ++k) ms[k] = 0.0, launches[k] = 0;
+    int rc = hip_check(c, hipStreamSynchronize(c->s), "profile");
+    for (auto& e : c->ev_pending) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, e.second.first, e.second.second) == hipSuccess) {
+            ms[e.first] += t;
+            launches[e.first] += 1;
+        }
+        c->ev_pool.push_back(e.second.first);
+        c->ev_pool.push_back(e.second.second);
+    }
+    c->ev_pending.clear();
+    return rc;
+}
+
+const char* hlbm_last_error(const hlbm_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+void hlbm_destroy(hlbm_ctx* c) {
+    if (!c) return;
+    if (!c->ev_pending.empty()) (void)hipStreamSynchronize(c->s);
+    for (auto& e : c->ev_pending) c->ev_pool.push_back(e.second.first), c->ev_pool.push_back(e.second.second);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+}  // extern "C"

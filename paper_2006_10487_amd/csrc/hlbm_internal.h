@@ -1,0 +1,133 @@
+// hlbm_internal.h -- host plan and device views of the HLBM library.
+//
+// The plan is built on the host (prep.cpp) from the caller's grid and mesh:
+// level sizes and relaxation times, the median-dual finite-volume
+// coefficients in reverse Cuthill-McKee node order, interpolation stencils,
+// and the byte layout of the caller's workspace.  Kernels (kernels.hip)
+// receive small views by value.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hlbm.h"
+
+namespace hlbm {
+
+constexpr int kQ = 9;
+constexpr int kSDon = 8;     // donors of a structured interpolation node (two 6-node stencils on an edge)
+constexpr int kUDon = 9;     // donors of a mesh interpolation node (3 x 3 block)
+constexpr int kMacro = 12;   // (rho or rho - rho0, ux, uy, f^neq[9])
+
+struct LevelPlan {
+    int nx = 0, ny = 0, pitch = 0;  // nodes, row pitch in elements
+    int sp = 1;                     // spacing in finest units
+    double ox = 0, oy = 0;          // origin in finest units
+    double tau = 1;
+    int i0 = 0, j0 = 0;             // origin in parent nodes
+    bool has_child = false;
+    int ci0 = -4, cj0 = -4, ci1 = -4, cj1 = -4;  // child rectangle in this level's nodes
+    bool perim_inactive = false;    // refined level: perimeter nodes come from the parent
+    bool farfield = false, periodic = false;
+    int64_t active = 0;             // collide-stream nodes
+    int sj0 = 0, sj1 = 0;           // rows with inactive spans (finest level, inner ellipse)
+};
+
+struct Plan {
+    // run parameters
+    int L = 0, nlev = 0;
+    double tau_s = 0, tau_u = 0, dt_u = 0;
+    int n_sub = 0, precision = 0, interp = 0;
+    bool periodic = false, wall_bc = true, has_grid = false, has_mesh = false;
+    double u_inf = 0, aoa = 0, rho0 = 1, chord = 1;
+    int check_every = 0, hist_len = 65536;
+    LevelPlan lev[4];
+    // finest level, inner ellipse: inactive nodes of row sj0 + r are [span[2r], span[2r+1])
+    std::vector<int32_t> spans;
+    // structured interpolation nodes (finest level), eq. (4)
+    std::vector<int32_t> sint_node;      // i + nx * j
+    std::vector<int32_t> sint_don;       // kSDon per node, mesh node in plan order, -1 = unused
+    std::vector<double> sint_w;
+    int n_fallback = 0;
+    // mesh in plan order [wall | interior | interpolation]
+    int nn = 0, n_wall = 0, n_core = 0, n_int = 0, nt = 0;
+    std::vector<int32_t> perm;           // perm[new] = caller index
+    std::vector<int32_t> rowptr, col;    // CSR, self entry included
+    std::vector<double> gx, gy, cc;      // G_Pk (x, y) and C_Pk
+    std::vector<int32_t> wedge;          // wall edges (P, Q) in plan order, fluid on the left
+    std::vector<double> wnorm;           // outward normal times length of each wall edge
+    // mesh interpolation nodes <- finest level, eq. (9)
+    std::vector<int32_t> uint_don;       // kUDon per slot, finest node i + nx * j, -1 = unused
+    std::vector<double> uint_w;
+    // workspace layout (byte offsets)
+    struct {
+        size_t lev[4][2];
+        size_t side[4][2];
+        size_t spans, sint_node, sint_don, sint_w;
+        size_t mesh[2], rowptr, edges, wedge, wnorm, prep[2], uint_don, uint_w, hist, stage;
+        size_t total;
+    } off{};
+    size_t stage_bytes = 0;
+    size_t elem = 8;                     // bytes per stored population
+};
+
+// Builds the plan; returns HLBM_OK or an error code with a message.
+int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Plan& p, std::string& err);
+
+// ---------------------------------------------------------------------------
+// device views
+// ---------------------------------------------------------------------------
+
+struct KLevel {
+    int nx, ny, pitch;
+    long long stride;                // ny * pitch
+    double omega;                    // 1 / tau
+    int perim_inactive;
+    int ci0, cj0, ci1, cj1;          // strictly inside -> not a collide-stream node
+    int farfield, periodic;
+    const int32_t* spans;            // inner-ellipse spans (finest level), or null
+    int sj0, sj1;
+    double u_in_x, u_in_y, rho0;     // far-field data
+};
+
+struct KMesh {
+    int nn, n_wall, n_core;
+    const int32_t* rowptr;
+    const void* edges;               // packed (col, gx, gy, c) records
+    double dt, dt_over_tau;          // Delta t_u, Delta t_u / tau_u
+    double star_neq;                 // 1 - 1 / (2 tau_s), eq. (5)-(6)
+    int wall_bc;
+    double rho0;
+};
+
+// launchers (kernels.hip); `prec` is HLBM_FP64 or HLBM_FP32_SHIFTED
+void launch_fill_uniform(int prec, void* buf, const KLevel& L, double rho, double ux, double uy, hipStream_t s);
+void launch_stream_collide(int prec, const KLevel& L, const void* A, void* B, hipStream_t s);
+void launch_export_level(int prec, const KLevel& L, const void* A, double* out, int j0, int j1, hipStream_t s);
+void launch_import_level(int prec, const KLevel& L, void* A, const double* in, int j0, int j1, hipStream_t s);
+void launch_coarse_to_fine(int prec, const KLevel& parent, const KLevel& child, int ci0, int cj0,
+                           const void* parentA, void* childA, void* side_cur, const void* side_prev,
+                           double theta, int compute_side, double tau_c, double tau_f, hipStream_t s);
+void launch_side_init(int prec, const KLevel& parent, int ci0, int cj0, int nxc, int nyc,
+                      const void* parentA, void* side, hipStream_t s);
+void launch_fine_to_coarse(int prec, const KLevel& parent, const KLevel& child, int ci0, int cj0,
+                           int nxc, int nyc, const void* child_prev, void* parent_dst, double tau_c,
+                           double tau_f, hipStream_t s);
+void launch_mesh_to_struct(int prec, const KLevel& fine, void* fineA, int n, const int32_t* node,
+                           const int32_t* don, const void* w, const void* mesh_f, int nn, double factor,
+                           hipStream_t s);
+void launch_struct_to_mesh(int prec, const KLevel& fine, const void* fineA, int n, const int32_t* don,
+                           const void* w, void* prep, hipStream_t s);
+void launch_fv_substep(int prec, const KMesh& M, const void* fin, void* fout, const void* prep0,
+                       const void* prep1, double theta, hipStream_t s);
+void launch_wall_force(int prec, const KMesh& M, const void* f, int n_edges, const int32_t* wedge,
+                       const double* wnorm, double* hist_slot, double cos_a, double sin_a, double qnorm,
+                       hipStream_t s);
+void launch_mesh_convert(int prec, int nn, const double* in, void* out, int to_storage, double rho0,
+                         hipStream_t s);
+
+}  // namespace hlbm

@@ -1,0 +1,621 @@
+// kernels.hip -- HIP kernels of the HLBM step for gfx950 (MI355X).
+//
+// Storage: structure-of-arrays populations [9][ny][pitch] per level with
+// 256-byte rows, double-buffered; the buffer holds post-collision values and
+// the collide-stream kernel pulls f_i(x - c_i) from it (eq. (1)), collides and
+// writes the next post-collision state.  Two instantiations:
+//   <double, false>  FP64 populations f_i;
+//   <float,  true>   FP32 populations stored as the shift f_i - w_i rho0
+//                    (forces are still accumulated in FP64).
+// Everything on this path is bandwidth bound (a few flops per byte), so there
+// is no matrix-core (MFMA) work: the kernels are plain coalesced streams.
+#include <hip/hip_runtime.h>
+
+#include "hlbm_internal.h"
+
+namespace hlbm {
+namespace {
+
+constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+template <typename T>
+__device__ __forceinline__ T wgt(int q) {
+    return q == 0 ? T(4.0 / 9.0) : (q < 5 ? T(1.0 / 9.0) : T(1.0 / 36.0));
+}
+
+// Macroscopic state of stored populations: rho (full), drho = rho - rho0
+// (shifted storage only), velocity.
+template <typename T, bool SHIFT>
+__device__ __forceinline__ void macro(const T (&f)[9], T rho0, T& rho, T& drho, T& ux, T& uy) {
+    T s = 0, mx = 0, my = 0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        s += f[q];
+        mx += T(CX[q]) * f[q];
+        my += T(CY[q]) * f[q];
+    }
+    if (SHIFT) {
+        drho = s;
+        rho = rho0 + s;
+    } else {
+        rho = s;
+        drho = s - rho0;
+    }
+    ux = mx / rho;
+    uy = my / rho;
+}
+
+// Second-order equilibrium of eq. (2) in stored form:
+//   FP64:    w_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2)
+//   shifted: w_i (rho - rho0) + w_i rho (3 c.u + 9/2 (c.u)^2 - 3/2 u^2)
+template <typename T, bool SHIFT>
+__device__ __forceinline__ void equilibrium(T rho, T drho, T ux, T uy, T (&feq)[9]) {
+    const T uu = ux * ux + uy * uy;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const T cu = T(CX[q]) * ux + T(CY[q]) * uy;
+        const T poly = T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu;
+        if (SHIFT) feq[q] = wgt<T>(q) * (drho + rho * poly);
+        else feq[q] = wgt<T>(q) * rho * (T(1) + poly);
+    }
+}
+
+template <typename T, bool SHIFT>
+__device__ __forceinline__ void macro_neq(const T (&f)[9], T rho0, T& r, T& dr, T& ux, T& uy, T (&neq)[9]) {
+    T feq[9];
+    macro<T, SHIFT>(f, rho0, r, dr, ux, uy);
+    equilibrium<T, SHIFT>(r, dr, ux, uy, feq);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) neq[q] = f[q] - feq[q];
+}
+
+// stored <-> physical population
+template <typename T, bool SHIFT>
+__device__ __forceinline__ double to_phys(T v, int q, double rho0) {
+    return SHIFT ? double(v) + wgt<double>(q) * rho0 : double(v);
+}
+template <typename T, bool SHIFT>
+__device__ __forceinline__ T to_store(double v, int q, double rho0) {
+    return SHIFT ? T(v - wgt<double>(q) * rho0) : T(v);
+}
+
+__device__ __forceinline__ size_t lidx(const KLevel& L, int q, int i, int j) {
+    return size_t(q) * size_t(L.stride) + size_t(j) * L.pitch + i;
+}
+
+// Is (i, j) a collide-stream node: not on a refined level's perimeter, not
+// strictly inside the child box, not inside the inner ellipse.
+__device__ __forceinline__ bool is_active(const KLevel& L, int i, int j) {
+    if (L.perim_inactive && (i == 0 || j == 0 || i == L.nx - 1 || j == L.ny - 1)) return false;
+    if (i > L.ci0 && i < L.ci1 && j > L.cj0 && j < L.cj1) return false;
+    if (L.spans && j >= L.sj0 && j < L.sj1) {
+        const int lo = L.spans[2 * (j - L.sj0)], hi = L.spans[2 * (j - L.sj0) + 1];
+        if (i >= lo && i < hi) return false;
+    }
+    return true;
+}
+
+// f_i(x, t+1) = f~_i(x - c_i, t): pull of the nine populations of node (i, j)
+template <typename T>
+__device__ __forceinline__ void pull(const KLevel& L, const T* __restrict__ A, int i, int j, T (&f)[9]) {
+    if (L.periodic) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            int a = i - CX[q], b = j - CY[q];
+            a = a < 0 ? a + L.nx : (a >= L.nx ? a - L.nx : a);
+            b = b < 0 ? b + L.ny : (b >= L.ny ? b - L.ny : b);
+            f[q] = A[lidx(L, q, a, b)];
+        }
+    } else {
+        const size_t base = size_t(j) * L.pitch + i;
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            f[q] = A[size_t(q) * size_t(L.stride) + base - ptrdiff_t(CY[q]) * L.pitch - CX[q]];
+    }
+}
+
+// Streamed (pre-collision) populations of node (i, j), with the far-field
+// conditions of the base level (Sec. 4): top and bottom copy the inner
+// neighbour; inlet and outlet use non-equilibrium extrapolation with u, resp.
+// rho, prescribed; corners belong to the inlet and outlet columns.
+template <typename T, bool SHIFT>
+__device__ __forceinline__ void streamed(const KLevel& L, const T* __restrict__ A, int i, int j, T (&f)[9]) {
+    const bool edge = L.farfield && (i == 0 || j == 0 || i == L.nx - 1 || j == L.ny - 1);
+    if (!edge) {
+        pull(L, A, i, j, f);
+        return;
+    }
+    const int jc = j < 1 ? 1 : (j > L.ny - 2 ? L.ny - 2 : j);
+    if (i != 0 && i != L.nx - 1) {
+        pull(L, A, i, jc, f);
+        return;
+    }
+    T g[9];
+    pull(L, A, i == 0 ? 1 : L.nx - 2, jc, g);
+    const T rho0 = T(L.rho0);
+    T r, dr, ux, uy, feq_nb[9], feq_b[9];
+    macro<T, SHIFT>(g, rho0, r, dr, ux, uy);
+    equilibrium<T, SHIFT>(r, dr, ux, uy, feq_nb);
+    if (i == 0) equilibrium<T, SHIFT>(r, dr, T(L.u_in_x), T(L.u_in_y), feq_b);
+    else equilibrium<T, SHIFT>(rho0, T(0), ux, uy, feq_b);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) f[q] = feq_b[q] + (g[q] - feq_nb[q]);
+}
+
+constexpr int kRows = 4;   // rows per block of the collide-stream kernel
+
+// One fused pull-stream + BGK collision (eq. (1)) of every collide-stream
+// node of a level: B = collide(stream(A)).
+template <typename T, bool SHIFT>
+__global__ __launch_bounds__(256) void k_stream_collide(const KLevel L, const T* __restrict__ A, T* __restrict__ B) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.nx) return;
+    const T omega = T(L.omega), rho0 = T(L.rho0);
+    const int j0 = blockIdx.y * kRows;
+    for (int r = 0; r < kRows; ++r) {
+        const int j = j0 + r;
+        if (j >= L.ny) break;
+        if (!is_active(L, i, j)) continue;
+        T f[9], feq[9], rho, dr, ux, uy;
+        streamed<T, SHIFT>(L, A, i, j, f);
+        macro<T, SHIFT>(f, rho0, rho, dr, ux, uy);
+        equilibrium<T, SHIFT>(rho, dr, ux, uy, feq);
+        const size_t base = size_t(j) * L.pitch + i;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) B[size_t(q) * size_t(L.stride) + base] = f[q] - (f[q] - feq[q]) * omega;
+    }
+}
+
+// Uniform f^eq(rho, u) in every node of a buffer (stored form).
+template <typename T, bool SHIFT>
+__global__ void k_fill_uniform(const KLevel L, T* __restrict__ A, double rho, double ux, double uy) {
+    const size_t n = size_t(L.stride);
+    const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= n * 9) return;
+    const int q = int(e / n);
+    const double cu = CX[q] * ux + CY[q] * uy, uu = ux * ux + uy * uy;
+    const double fe = wgt<double>(q) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    A[e] = to_store<T, SHIFT>(fe, q, L.rho0);
+}
+
+// Canonical export: streamed populations of rows [j0, j1) in FP64, zero at
+// nodes that are not collide-stream nodes.  out = [9][j1 - j0][nx].
+template <typename T, bool SHIFT>
+__global__ void k_export_level(const KLevel L, const T* __restrict__ A, double* __restrict__ out, int j0, int j1) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = j0 + blockIdx.y;
+    if (i >= L.nx || j >= j1) return;
+    const size_t rows = size_t(j1 - j0), o = size_t(j - j0) * L.nx + i;
+    if (!is_active(L, i, j)) {
+        for (int q = 0; q < 9; ++q) out[q * rows * L.nx + o] = 0.0;
+        return;
+    }
+    T f[9];
+    streamed<T, SHIFT>(L, A, i, j, f);
+    for (int q = 0; q < 9; ++q) out[q * rows * L.nx + o] = to_phys<T, SHIFT>(f[q], q, L.rho0);
+}
+
+// Canonical import of rows [j0, j1): scatter f_i(x) to A(x - c_i) so that the
+// next pull of A returns the imported pre-collision populations.  Far-field
+// edge nodes are skipped: their values follow from the boundary conditions.
+template <typename T, bool SHIFT>
+__global__ void k_import_level(const KLevel L, T* __restrict__ A, const double* __restrict__ in, int j0, int j1) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = j0 + blockIdx.y;
+    if (i >= L.nx || j >= j1) return;
+    if (!is_active(L, i, j)) return;
+    if (L.farfield && (i == 0 || j == 0 || i == L.nx - 1 || j == L.ny - 1)) return;
+    const size_t rows = size_t(j1 - j0), o = size_t(j - j0) * L.nx + i;
+    for (int q = 0; q < 9; ++q) {
+        int a = i - CX[q], b = j - CY[q];
+        if (L.periodic) {
+            a = (a + L.nx) % L.nx;
+            b = (b + L.ny) % L.ny;
+        }
+        A[lidx(L, q, a, b)] = to_store<T, SHIFT>(in[q * rows * L.nx + o], q, L.rho0);
+    }
+}
+
+// Position k along the boundary of the child box (in parent nodes):
+// bottom row, top row, left column, right column.
+__device__ __forceinline__ void box_node(int k, int nxc, int nyc, int& a, int& b) {
+    if (k <= nxc) { a = k; b = 0; return; }
+    k -= nxc + 1;
+    if (k <= nxc) { a = k; b = nyc; return; }
+    k -= nxc + 1;
+    if (k < nyc - 1) { a = 0; b = k + 1; return; }
+    k -= nyc - 1;
+    a = nxc;
+    b = k + 1;
+}
+__device__ __forceinline__ int box_index(int a, int b, int nxc, int nyc) {
+    if (b == 0) return a;
+    if (b == nyc) return nxc + 1 + a;
+    if (a == 0) return 2 * (nxc + 1) + b - 1;
+    return 2 * (nxc + 1) + (nyc - 1) + b - 1;
+}
+
+template <typename T, bool SHIFT>
+__device__ __forceinline__ void store_macro(T* dst, const T (&f)[9], T rho0) {
+    T r, dr, ux, uy, neq[9];
+    macro_neq<T, SHIFT>(f, rho0, r, dr, ux, uy, neq);
+    dst[0] = SHIFT ? dr : r;
+    dst[1] = ux;
+    dst[2] = uy;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) dst[3 + q] = neq[q];
+}
+
+// (rho, u, f^neq) of the parent's streamed populations on the box boundary.
+template <typename T, bool SHIFT>
+__global__ void k_side_init(const KLevel P, int ci0, int cj0, int nxc, int nyc, const T* __restrict__ A, T* __restrict__ side) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 2 * (nxc + nyc)) return;
+    int a, b;
+    box_node(k, nxc, nyc, a, b);
+    T f[9];
+    pull(P, A, ci0 + a, cj0 + b, f);
+    store_macro<T, SHIFT>(side + size_t(k) * kMacro, f, T(P.rho0));
+}
+
+// Coarse -> fine transfer (Sec. 4, Filippova-Haenel) onto the child perimeter:
+// (rho, u, f^neq) of the parent, linear in time at theta and linear in space
+// at odd fine nodes; f^neq rescaled by tau_f / (2 tau_c) to a fine
+// pre-collision value, collided at tau_f.  With compute_side (theta = 0) the
+// threads on even nodes also record the parent's (rho, u, f^neq) at t + 1.
+template <typename T, bool SHIFT>
+__global__ void k_coarse_to_fine(const KLevel P, const KLevel C, int ci0, int cj0, const T* __restrict__ pA,
+                                 T* __restrict__ cA, T* __restrict__ side_cur, const T* __restrict__ side_prev,
+                                 T theta, int compute_side, T scale, T omega_f) {
+    const int cnx = C.nx - 1, cny = C.ny - 1, nxc = cnx / 2, nyc = cny / 2;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 2 * (cnx + cny)) return;
+    int ic, jc;
+    box_node(k, cnx, cny, ic, jc);
+    const T rho0 = T(P.rho0);
+    if (compute_side && !(ic & 1) && !(jc & 1)) {
+        T f[9];
+        pull(P, pA, ci0 + ic / 2, cj0 + jc / 2, f);
+        store_macro<T, SHIFT>(side_cur + size_t(box_index(ic / 2, jc / 2, nxc, nyc)) * kMacro, f, rho0);
+    }
+    int ka, kb = -1;
+    if (!(ic & 1) && !(jc & 1)) ka = box_index(ic / 2, jc / 2, nxc, nyc);
+    else if (ic & 1) ka = box_index((ic - 1) / 2, jc / 2, nxc, nyc), kb = box_index((ic + 1) / 2, jc / 2, nxc, nyc);
+    else ka = box_index(ic / 2, (jc - 1) / 2, nxc, nyc), kb = box_index(ic / 2, (jc + 1) / 2, nxc, nyc);
+    T v[kMacro];
+    const T wa = kb < 0 ? T(1) : T(0.5);
+#pragma unroll
+    for (int m = 0; m < kMacro; ++m) {
+        T x = (T(1) - theta) * side_prev[size_t(ka) * kMacro + m];
+        if (theta != T(0)) x += theta * side_cur[size_t(ka) * kMacro + m];
+        x *= wa;
+        if (kb >= 0) {
+            T y = (T(1) - theta) * side_prev[size_t(kb) * kMacro + m];
+            if (theta != T(0)) y += theta * side_cur[size_t(kb) * kMacro + m];
+            x += wa * y;
+        }
+        v[m] = x;
+    }
+    const T rho = SHIFT ? rho0 + v[0] : v[0], dr = SHIFT ? v[0] : v[0] - rho0;
+    T feq[9];
+    equilibrium<T, SHIFT>(rho, dr, v[1], v[2], feq);
+    const size_t base = size_t(jc) * C.pitch + ic;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const T pre = feq[q] + scale * v[3 + q];
+        cA[size_t(q) * size_t(C.stride) + base] = pre - (pre - feq[q]) * omega_f;
+    }
+}
+
+// Fine -> coarse transfer (Sec. 4): parent nodes on the first ring inside the
+// box get the fine (rho, u) and f^neq rescaled by 2 tau_c / tau_f, collided at
+// tau_c.  The fine streamed state is pulled from the child buffer.
+template <typename T, bool SHIFT>
+__global__ void k_fine_to_coarse(const KLevel P, const KLevel C, int ci0, int cj0, int nxc, int nyc,
+                                 const T* __restrict__ cprev, T* __restrict__ pdst, T scale, T omega_c) {
+    const int rx = nxc - 2, ry = nyc - 2;          // ring box (ci0+1 .. ci0+nxc-1) has rx cells
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 2 * (rx + ry)) return;
+    int a, b;
+    box_node(k, rx, ry, a, b);
+    const int pi = ci0 + 1 + a, pj = cj0 + 1 + b;
+    T f[9], r, dr, ux, uy, neq[9], feq[9];
+    pull(C, cprev, 2 * (pi - ci0), 2 * (pj - cj0), f);
+    macro_neq<T, SHIFT>(f, T(P.rho0), r, dr, ux, uy, neq);
+    equilibrium<T, SHIFT>(r, dr, ux, uy, feq);
+    const size_t base = size_t(pj) * P.pitch + pi;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const T pre = feq[q] + scale * neq[q];
+        pdst[size_t(q) * size_t(P.stride) + base] = pre - (pre - feq[q]) * omega_c;
+    }
+}
+
+// Structured interpolation nodes, eq. (4): f~ = f^eq(rho, u) +
+// 2 (tau_s - 1) / (2 tau_s - 1) f^neq with rho, u, f^neq interpolated from the
+// mesh donors (eq. (8)).
+template <typename T, bool SHIFT>
+__global__ void k_mesh_to_struct(const KLevel F, T* __restrict__ A, int n, const int32_t* __restrict__ node,
+                                 const int32_t* __restrict__ don, const T* __restrict__ w,
+                                 const T* __restrict__ mf, int nn, T factor) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const T rho0 = T(F.rho0);
+    T acc[kMacro];
+#pragma unroll
+    for (int m = 0; m < kMacro; ++m) acc[m] = 0;
+    for (int d = 0; d < kSDon; ++d) {
+        const int k = don[size_t(s) * kSDon + d];
+        if (k < 0) break;
+        T f[9], r, dr, ux, uy, neq[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f[q] = mf[size_t(q) * nn + k];
+        macro_neq<T, SHIFT>(f, rho0, r, dr, ux, uy, neq);
+        const T ww = w[size_t(s) * kSDon + d];
+        acc[0] += ww * (SHIFT ? dr : r);
+        acc[1] += ww * ux;
+        acc[2] += ww * uy;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc[3 + q] += ww * neq[q];
+    }
+    const T rho = SHIFT ? rho0 + acc[0] : acc[0], dr = SHIFT ? acc[0] : acc[0] - rho0;
+    T feq[9];
+    equilibrium<T, SHIFT>(rho, dr, acc[1], acc[2], feq);
+    const int id = node[s];
+    const int i = id % F.nx, j = id / F.nx;
+    const size_t base = size_t(j) * F.pitch + i;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) A[size_t(q) * size_t(F.stride) + base] = feq[q] + factor * acc[3 + q];
+}
+
+// Mesh interpolation nodes <- finest level, eq. (9): (rho, u, f^neq) of the
+// streamed populations of the 3 x 3 (or 2 x 2) donor block.
+template <typename T, bool SHIFT>
+__global__ void k_struct_to_mesh(const KLevel F, const T* __restrict__ A, int n, const int32_t* __restrict__ don,
+                                 const T* __restrict__ w, T* __restrict__ prep) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const T rho0 = T(F.rho0);
+    T acc[kMacro];
+#pragma unroll
+    for (int m = 0; m < kMacro; ++m) acc[m] = 0;
+    for (int d = 0; d < kUDon; ++d) {
+        const int id = don[size_t(s) * kUDon + d];
+        if (id < 0) break;
+        T f[9], r, dr, ux, uy, neq[9];
+        pull(F, A, id % F.nx, id / F.nx, f);
+        macro_neq<T, SHIFT>(f, rho0, r, dr, ux, uy, neq);
+        const T ww = w[size_t(s) * kUDon + d];
+        acc[0] += ww * (SHIFT ? dr : r);
+        acc[1] += ww * ux;
+        acc[2] += ww * uy;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc[3 + q] += ww * neq[q];
+    }
+#pragma unroll
+    for (int m = 0; m < kMacro; ++m) prep[size_t(s) * kMacro + m] = acc[m];
+}
+
+template <typename T> struct EdgeRec;
+template <> struct alignas(32) EdgeRec<double> { int32_t col, pad; double gx, gy, c; };
+template <> struct alignas(16) EdgeRec<float> { int32_t col; float gx, gy, c; };
+
+// f* at a mesh interpolation node (eqs. (5)-(6)): the structured (rho, u,
+// f^neq) blended linearly in time, f* = f^eq(rho, u) + (1 - 1/(2 tau_s)) f^neq;
+// nstar = its non-equilibrium part.
+template <typename T, bool SHIFT>
+__device__ __forceinline__ void star_values(const T* __restrict__ p0, const T* __restrict__ p1, T theta, T cst,
+                                            T rho0, T (&fs)[9], T (&ns)[9]) {
+    T v[kMacro];
+#pragma unroll
+    for (int m = 0; m < kMacro; ++m) v[m] = (T(1) - theta) * p0[m] + theta * p1[m];
+    const T rho = SHIFT ? rho0 + v[0] : v[0], dr = SHIFT ? v[0] : v[0] - rho0;
+    T feq[9];
+    equilibrium<T, SHIFT>(rho, dr, v[1], v[2], feq);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        ns[q] = cst * v[3 + q];
+        fs[q] = feq[q] + ns[q];
+    }
+}
+
+// One finite-volume sub-step of eq. (3) on every mesh node (eq. (5) at the
+// interpolation nodes), Jacobi style:
+//   f_P <- f_P + dt sum_k (c_i . G_Pk) f_k - dt/tau_u sum_k C_Pk (f_k - f^eq_k)
+// Interpolation pivots use f* for themselves and for interpolation
+// neighbours; wall nodes get u -> 0 keeping rho and f^neq afterwards.
+template <typename T, bool SHIFT>
+__global__ __launch_bounds__(256) void k_fv_substep(const KMesh M, const T* __restrict__ fin, T* __restrict__ fout,
+                                                    const T* __restrict__ prep0, const T* __restrict__ prep1, T theta) {
+    const int P = blockIdx.x * blockDim.x + threadIdx.x;
+    if (P >= M.nn) return;
+    const int nn = M.nn;
+    const bool pivot_interp = P >= M.n_core;
+    const T rho0 = T(M.rho0), cst = T(M.star_neq);
+    const EdgeRec<T>* __restrict__ E = reinterpret_cast<const EdgeRec<T>*>(M.edges);
+    T ss[9], sc[9], base[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) ss[q] = sc[q] = base[q] = 0;
+    const int z0 = M.rowptr[P], z1 = M.rowptr[P + 1];
+    for (int z = z0; z < z1; ++z) {
+        const EdgeRec<T> e = E[z];
+        const int k = e.col;
+        T f[9], nq[9];
+        if (pivot_interp && k >= M.n_core) {
+            const size_t sl = size_t(k - M.n_core) * kMacro;
+            star_values<T, SHIFT>(prep0 + sl, prep1 + sl, theta, cst, rho0, f, nq);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) f[q] = fin[size_t(q) * nn + k];
+            T r, dr, ux, uy;
+            macro_neq<T, SHIFT>(f, rho0, r, dr, ux, uy, nq);
+        }
+        if (k == P) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) base[q] = f[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const T s_ik = T(CX[q]) * e.gx + T(CY[q]) * e.gy;
+            ss[q] += s_ik * f[q];
+            sc[q] += e.c * nq[q];
+        }
+    }
+    const T dt = T(M.dt), dtt = T(M.dt_over_tau);
+    T fn[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fn[q] = base[q] + dt * ss[q] - dtt * sc[q];
+    if (M.wall_bc && P < M.n_wall) {
+        T r, dr, ux, uy, feq[9], feq0[9];
+        macro<T, SHIFT>(fn, rho0, r, dr, ux, uy);
+        equilibrium<T, SHIFT>(r, dr, ux, uy, feq);
+        equilibrium<T, SHIFT>(r, dr, T(0), T(0), feq0);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) fn[q] = feq0[q] + (fn[q] - feq[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fout[size_t(q) * nn + P] = fn[q];
+}
+
+// Drag and lift, eqs. (10)-(11), in FP64: momentum flux out of the fluid
+// through the wall edges, sum_i c_i (c_i . N_e) (f_i(a) + f_i(b)) / 2, reduced
+// by one block in a fixed order (deterministic).  Shifted storage drops the
+// rest-state part rho0 c_s^2 N_e, which sums to zero over the closed wall.
+template <typename T, bool SHIFT>
+__global__ __launch_bounds__(256) void k_wall_force(const T* __restrict__ f, int nn, int ne, const int32_t* __restrict__ wedge,
+                                                    const double* __restrict__ wn, double* __restrict__ out,
+                                                    double ca, double sa, double qn) {
+    __shared__ double sx[256], sy[256];
+    double ax = 0, ay = 0;
+    for (int e = threadIdx.x; e < ne; e += 256) {
+        const int a = wedge[2 * e], b = wedge[2 * e + 1];
+        const double nx = wn[2 * e], ny = wn[2 * e + 1];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const double m = 0.5 * (double(f[size_t(q) * nn + a]) + double(f[size_t(q) * nn + b]));
+            const double cn = CX[q] * nx + CY[q] * ny;
+            ax += CX[q] * cn * m;
+            ay += CY[q] * cn * m;
+        }
+    }
+    sx[threadIdx.x] = ax;
+    sy[threadIdx.x] = ay;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sx[threadIdx.x] += sx[threadIdx.x + h];
+            sy[threadIdx.x] += sy[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = (sx[0] * ca + sy[0] * sa) / qn;
+        out[1] = (-sx[0] * sa + sy[0] * ca) / qn;
+    }
+}
+
+template <typename T, bool SHIFT>
+__global__ void k_mesh_convert(int nn, const double* __restrict__ in, T* __restrict__ out, double rho0) {
+    const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= size_t(9) * nn) return;
+    out[e] = to_store<T, SHIFT>(in[e], int(e / nn), rho0);
+}
+template <typename T, bool SHIFT>
+__global__ void k_mesh_export(int nn, const T* __restrict__ in, double* __restrict__ out, double rho0) {
+    const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= size_t(9) * nn) return;
+    out[e] = to_phys<T, SHIFT>(in[e], int(e / nn), rho0);
+}
+
+unsigned blocks(size_t n, unsigned b = 256) { return unsigned((n + b - 1) / b); }
+
+}  // namespace
+
+#define HLBM_DISPATCH(prec, CALL)        \
+    do {                                 \
+        if ((prec) == HLBM_FP64) {       \
+            using T = double;            \
+            constexpr bool S = false;    \
+            CALL;                        \
+        } else {                         \
+            using T = float;             \
+            constexpr bool S = true;     \
+            CALL;                        \
+        }                                \
+    } while (0)
+
+void launch_fill_uniform(int prec, void* buf, const KLevel& L, double rho, double ux, double uy, hipStream_t s) {
+    HLBM_DISPATCH(prec, (k_fill_uniform<T, S><<<blocks(size_t(L.stride) * 9), 256, 0, s>>>(L, (T*)buf, rho, ux, uy)));
+}
+
+void launch_stream_collide(int prec, const KLevel& L, const void* A, void* B, hipStream_t s) {
+    dim3 grid(blocks(L.nx), (L.ny + kRows - 1) / kRows);
+    HLBM_DISPATCH(prec, (k_stream_collide<T, S><<<grid, 256, 0, s>>>(L, (const T*)A, (T*)B)));
+}
+
+void launch_export_level(int prec, const KLevel& L, const void* A, double* out, int j0, int j1, hipStream_t s) {
+    dim3 grid(blocks(L.nx), j1 - j0);
+    HLBM_DISPATCH(prec, (k_export_level<T, S><<<grid, 256, 0, s>>>(L, (const T*)A, out, j0, j1)));
+}
+
+void launch_import_level(int prec, const KLevel& L, void* A, const double* in, int j0, int j1, hipStream_t s) {
+    dim3 grid(blocks(L.nx), j1 - j0);
+    HLBM_DISPATCH(prec, (k_import_level<T, S><<<grid, 256, 0, s>>>(L, (T*)A, in, j0, j1)));
+}
+
+void launch_side_init(int prec, const KLevel& P, int ci0, int cj0, int nxc, int nyc, const void* A, void* side, hipStream_t s) {
+    HLBM_DISPATCH(prec, (k_side_init<T, S><<<blocks(2 * size_t(nxc + nyc)), 256, 0, s>>>(P, ci0, cj0, nxc, nyc, (const T*)A, (T*)side)));
+}
+
+void launch_coarse_to_fine(int prec, const KLevel& P, const KLevel& C, int ci0, int cj0, const void* pA, void* cA,
+                           void* side_cur, const void* side_prev, double theta, int compute_side, double tau_c,
+                           double tau_f, hipStream_t s) {
+    const size_t n = 2 * size_t(C.nx - 1 + C.ny - 1);
+    const double scale = tau_f / (2.0 * tau_c);
+    HLBM_DISPATCH(prec, (k_coarse_to_fine<T, S><<<blocks(n), 256, 0, s>>>(P, C, ci0, cj0, (const T*)pA, (T*)cA, (T*)side_cur,
+                                                                          (const T*)side_prev, T(theta), compute_side,
+                                                                          T(scale), T(1.0 / tau_f))));
+}
+
+void launch_fine_to_coarse(int prec, const KLevel& P, const KLevel& C, int ci0, int cj0, int nxc, int nyc,
+                           const void* cprev, void* pdst, double tau_c, double tau_f, hipStream_t s) {
+    const size_t n = 2 * size_t(nxc - 2 + nyc - 2);
+    const double scale = 2.0 * tau_c / tau_f;
+    HLBM_DISPATCH(prec, (k_fine_to_coarse<T, S><<<blocks(n), 256, 0, s>>>(P, C, ci0, cj0, nxc, nyc, (const T*)cprev,
+                                                                          (T*)pdst, T(scale), T(1.0 / tau_c))));
+}
+
+void launch_mesh_to_struct(int prec, const KLevel& F, void* A, int n, const int32_t* node, const int32_t* don,
+                           const void* w, const void* mf, int nn, double factor, hipStream_t s) {
+    if (n <= 0) return;
+    HLBM_DISPATCH(prec, (k_mesh_to_struct<T, S><<<blocks(n, 64), 64, 0, s>>>(F, (T*)A, n, node, don, (const T*)w,
+                                                                             (const T*)mf, nn, T(factor))));
+}
+
+void launch_struct_to_mesh(int prec, const KLevel& F, const void* A, int n, const int32_t* don, const void* w,
+                           void* prep, hipStream_t s) {
+    if (n <= 0) return;
+    HLBM_DISPATCH(prec, (k_struct_to_mesh<T, S><<<blocks(n, 64), 64, 0, s>>>(F, (const T*)A, n, don, (const T*)w, (T*)prep)));
+}
+
+void launch_fv_substep(int prec, const KMesh& M, const void* fin, void* fout, const void* prep0, const void* prep1,
+                       double theta, hipStream_t s) {
+    HLBM_DISPATCH(prec, (k_fv_substep<T, S><<<blocks(M.nn), 256, 0, s>>>(M, (const T*)fin, (T*)fout, (const T*)prep0,
+                                                                         (const T*)prep1, T(theta))));
+}
+
+void launch_wall_force(int prec, const KMesh& M, const void* f, int ne, const int32_t* wedge, const double* wn,
+                       double* out, double ca, double sa, double qn, hipStream_t s) {
+    HLBM_DISPATCH(prec, (k_wall_force<T, S><<<1, 256, 0, s>>>((const T*)f, M.nn, ne, wedge, wn, out, ca, sa, qn)));
+}
+
+void launch_mesh_convert(int prec, int nn, const double* in, void* out, int to_storage, double rho0, hipStream_t s) {
+    if (to_storage) {
+        HLBM_DISPATCH(prec, (k_mesh_convert<T, S><<<blocks(size_t(9) * nn), 256, 0, s>>>(nn, in, (T*)out, rho0)));
+    } else {
+        HLBM_DISPATCH(prec, (k_mesh_export<T, S><<<blocks(size_t(9) * nn), 256, 0, s>>>(nn, (const T*)out, (double*)in, rho0)));
+    }
+}
+
+}  // namespace hlbm

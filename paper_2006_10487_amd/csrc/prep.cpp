@@ -1,0 +1,704 @@
+// prep.cpp -- host preprocessing of the HLBM library.
+//
+// Builds, from the caller's grid and mesh:
+//   * the levels of the structured grid (Sec. 4: nested factor-two boxes,
+//     the finest one with unit spacing), their relaxation times under
+//     acoustic scaling and the inactive region inside the inner ellipse;
+//   * the finite-volume coefficients of eq. (3) on median-dual control
+//     volumes, S_ik = c_i . G_Pk and C_Pk, with boundary control volumes
+//     closed by half boundary edges;
+//   * a reverse Cuthill-McKee order of the mesh nodes, stably partitioned
+//     into [wall | interior | interpolation] so that the finite-volume kernel
+//     reads neighbours close in memory and tells node kinds by index;
+//   * the interpolation stencils of eq. (8) (structured <- mesh) and eq. (9)
+//     (mesh <- structured), or their linear variants;
+//   * the byte layout of the device workspace.
+#include <algorithm>
+#include <cstdarg>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <queue>
+#include <tuple>
+
+#include "hlbm_internal.h"
+
+namespace hlbm {
+namespace {
+
+constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+struct V2 {
+    double x, y;
+};
+inline V2 operator-(V2 a, V2 b) { return {a.x - b.x, a.y - b.y}; }
+inline V2 operator+(V2 a, V2 b) { return {a.x + b.x, a.y + b.y}; }
+inline V2 operator*(double s, V2 a) { return {s * a.x, s * a.y}; }
+inline double cross(V2 a, V2 b) { return a.x * b.y - a.y * b.x; }
+inline V2 rot_cw(V2 a) { return {a.y, -a.x}; }   // outward normal of a counter-clockwise boundary piece
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int fail(std::string& err, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(std::string& err, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+}
+
+// ---------------------------------------------------------------------------
+// finite-volume coefficients on the median dual
+// ---------------------------------------------------------------------------
+
+struct Entry {
+    int p, k;
+    double gx, gy, c;
+};
+
+// Coefficients of eq. (3) for every node P (caller order), sorted by (P, k):
+// G_Pk = -(1/A_P) sum over control-volume segments of N_seg psi_k(mid_seg),
+// C_Pk = (1/A_P) integral of psi_k over the control volume, psi = linear hat.
+int median_dual(int nn, int nt, const double* xy, const int32_t* tri, std::vector<Entry>& out,
+                std::vector<double>& area, std::vector<std::array<int, 2>>& bnd_edges,
+                std::string& err) {
+    std::vector<Entry> acc;
+    acc.reserve(size_t(nt) * 9 + 64);
+    area.assign(nn, 0.0);
+    auto P_of = [&](int v) { return V2{xy[2 * v], xy[2 * v + 1]}; };
+    for (int t = 0; t < nt; ++t) {
+        const int v[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
+        for (int a = 0; a < 3; ++a)
+            if (v[a] < 0 || v[a] >= nn) return fail(err, HLBM_E_GEOMETRY, "triangle %d: vertex index out of range", t);
+        const double at2 = cross(P_of(v[1]) - P_of(v[0]), P_of(v[2]) - P_of(v[0]));
+        if (!(at2 > 0.0)) return fail(err, HLBM_E_GEOMETRY, "triangle %d is not counter-clockwise or is degenerate", t);
+        const double at = 0.5 * at2;
+        for (int r = 0; r < 3; ++r) {
+            const int P = v[r], A = v[(r + 1) % 3], B = v[(r + 2) % 3];
+            const V2 e = P_of(A) - P_of(P), f = P_of(B) - P_of(P);
+            // segments M_PA -> centroid and centroid -> M_PB of P's piece
+            const V2 n1 = (1.0 / 6.0) * rot_cw((2.0 * f) - e);
+            const V2 n2 = (1.0 / 6.0) * rot_cw(f - (2.0 * e));
+            // hat functions at the two segment midpoints: P 5/12, 5/12; A 5/12, 1/6; B 1/6, 5/12
+            const V2 gP = (5.0 / 12.0) * (n1 + n2);
+            const V2 gA = (5.0 / 12.0) * n1 + (1.0 / 6.0) * n2;
+            const V2 gB = (1.0 / 6.0) * n1 + (5.0 / 12.0) * n2;
+            acc.push_back({P, P, -gP.x, -gP.y, at * (11.0 / 54.0)});
+            acc.push_back({P, A, -gA.x, -gA.y, at * (7.0 / 108.0)});
+            acc.push_back({P, B, -gB.x, -gB.y, at * (7.0 / 108.0)});
+            area[P] += at / 3.0;
+        }
+    }
+    // boundary edges: undirected edges used by a single triangle, kept with
+    // the direction they have in that (counter-clockwise) triangle
+    std::vector<std::tuple<int, int, int, int>> edges;  // (min, max, from, to)
+    edges.reserve(size_t(nt) * 3);
+    for (int t = 0; t < nt; ++t)
+        for (int r = 0; r < 3; ++r) {
+            const int a = tri[3 * t + r], b = tri[3 * t + (r + 1) % 3];
+            edges.emplace_back(std::min(a, b), std::max(a, b), a, b);
+        }
+    std::sort(edges.begin(), edges.end());
+    bnd_edges.clear();
+    for (size_t s = 0; s < edges.size();) {
+        size_t e = s + 1;
+        while (e < edges.size() && std::get<0>(edges[e]) == std::get<0>(edges[s]) &&
+               std::get<1>(edges[e]) == std::get<1>(edges[s]))
+            ++e;
+        if (e - s == 1) bnd_edges.push_back({std::get<2>(edges[s]), std::get<3>(edges[s])});
+        else if (e - s > 2) return fail(err, HLBM_E_GEOMETRY, "edge (%d,%d) shared by more than two triangles",
+                                        std::get<0>(edges[s]), std::get<1>(edges[s]));
+        s = e;
+    }
+    // half boundary edges close the control volumes of boundary nodes:
+    // P -> midpoint with hat values (3/4, 1/4), midpoint -> Q with (1/4, 3/4)
+    for (const auto& be : bnd_edges) {
+        const int P = be[0], Qn = be[1];
+        const V2 nh = 0.5 * rot_cw(P_of(Qn) - P_of(P));
+        acc.push_back({P, P, -0.75 * nh.x, -0.75 * nh.y, 0.0});
+        acc.push_back({P, Qn, -0.25 * nh.x, -0.25 * nh.y, 0.0});
+        acc.push_back({Qn, Qn, -0.75 * nh.x, -0.75 * nh.y, 0.0});
+        acc.push_back({Qn, P, -0.25 * nh.x, -0.25 * nh.y, 0.0});
+    }
+    std::sort(acc.begin(), acc.end(), [](const Entry& a, const Entry& b) {
+        return a.p != b.p ? a.p < b.p : a.k < b.k;
+    });
+    out.clear();
+    for (const Entry& e : acc) {
+        if (!out.empty() && out.back().p == e.p && out.back().k == e.k) {
+            out.back().gx += e.gx;
+            out.back().gy += e.gy;
+            out.back().c += e.c;
+        } else {
+            out.push_back(e);
+        }
+    }
+    for (int p = 0; p < nn; ++p)
+        if (!(area[p] > 0.0)) return fail(err, HLBM_E_GEOMETRY, "mesh node %d belongs to no triangle", p);
+    for (Entry& e : out) {
+        e.gx /= area[e.p];
+        e.gy /= area[e.p];
+        e.c /= area[e.p];
+    }
+    return HLBM_OK;
+}
+
+// Reverse Cuthill-McKee order of the mesh graph, started from a minimum-degree
+// node of the lowest-numbered component seed (wall nodes first when present).
+std::vector<int> rcm_order(int nn, const std::vector<int>& rp, const std::vector<int>& cl,
+                           const uint8_t* kind) {
+    std::vector<int> deg(nn), order;
+    order.reserve(nn);
+    for (int p = 0; p < nn; ++p) deg[p] = rp[p + 1] - rp[p];
+    std::vector<char> seen(nn, 0);
+    std::vector<int> nb;
+    while ((int)order.size() < nn) {
+        int seed = -1;
+        for (int pass = 0; pass < 2 && seed < 0; ++pass)
+            for (int p = 0; p < nn; ++p) {
+                if (seen[p]) continue;
+                if (pass == 0 && !(kind && kind[p] == 1)) continue;
+                if (seed < 0 || deg[p] < deg[seed]) seed = p;
+            }
+        std::queue<int> q;
+        q.push(seed);
+        seen[seed] = 1;
+        while (!q.empty()) {
+            const int p = q.front();
+            q.pop();
+            order.push_back(p);
+            nb.clear();
+            for (int z = rp[p]; z < rp[p + 1]; ++z)
+                if (!seen[cl[z]]) nb.push_back(cl[z]);
+            std::sort(nb.begin(), nb.end(), [&](int a, int b) { return deg[a] != deg[b] ? deg[a] < deg[b] : a < b; });
+            for (int k : nb) {
+                seen[k] = 1;
+                q.push(k);
+            }
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    return order;
+}
+
+// ---------------------------------------------------------------------------
+// interpolation stencils
+// ---------------------------------------------------------------------------
+
+struct TriIndex {
+    double x0, y0, h;
+    int nbx, nby;
+    std::vector<int> head, list;          // bucket -> triangles (increasing index)
+    std::vector<int> n2t_head, n2t;       // node -> incident triangles
+};
+
+void build_tri_index(int nn, int nt, const double* xy, const int32_t* tri, TriIndex& T) {
+    double xmin = 1e300, ymin = 1e300, xmax = -1e300, ymax = -1e300;
+    for (int p = 0; p < nn; ++p) {
+        xmin = std::min(xmin, xy[2 * p]);
+        xmax = std::max(xmax, xy[2 * p]);
+        ymin = std::min(ymin, xy[2 * p + 1]);
+        ymax = std::max(ymax, xy[2 * p + 1]);
+    }
+    T.h = std::max(1e-9, 1.5 * std::sqrt((xmax - xmin) * (ymax - ymin) / std::max(1, nt)));
+    T.x0 = xmin - 0.5 * T.h;
+    T.y0 = ymin - 0.5 * T.h;
+    T.nbx = int((xmax - T.x0) / T.h) + 2;
+    T.nby = int((ymax - T.y0) / T.h) + 2;
+    std::vector<std::pair<int, int>> pairs;   // (bucket, triangle)
+    for (int t = 0; t < nt; ++t) {
+        double bx0 = 1e300, by0 = 1e300, bx1 = -1e300, by1 = -1e300;
+        for (int r = 0; r < 3; ++r) {
+            const int v = tri[3 * t + r];
+            bx0 = std::min(bx0, xy[2 * v]);
+            bx1 = std::max(bx1, xy[2 * v]);
+            by0 = std::min(by0, xy[2 * v + 1]);
+            by1 = std::max(by1, xy[2 * v + 1]);
+        }
+        const int i0 = std::max(0, int(std::floor((bx0 - 1e-9 - T.x0) / T.h)));
+        const int i1 = std::min(T.nbx - 1, int(std::floor((bx1 + 1e-9 - T.x0) / T.h)));
+        const int j0 = std::max(0, int(std::floor((by0 - 1e-9 - T.y0) / T.h)));
+        const int j1 = std::min(T.nby - 1, int(std::floor((by1 + 1e-9 - T.y0) / T.h)));
+        for (int j = j0; j <= j1; ++j)
+            for (int i = i0; i <= i1; ++i) pairs.emplace_back(j * T.nbx + i, t);
+    }
+    std::sort(pairs.begin(), pairs.end());
+    T.head.assign(size_t(T.nbx) * T.nby + 1, 0);
+    T.list.resize(pairs.size());
+    for (size_t a = 0; a < pairs.size(); ++a) {
+        T.head[pairs[a].first + 1]++;
+        T.list[a] = pairs[a].second;
+    }
+    for (size_t b = 0; b + 1 < T.head.size(); ++b) T.head[b + 1] += T.head[b];
+    T.n2t_head.assign(nn + 1, 0);
+    for (int a = 0; a < 3 * nt; ++a) T.n2t_head[tri[a] + 1]++;
+    for (int p = 0; p < nn; ++p) T.n2t_head[p + 1] += T.n2t_head[p];
+    T.n2t.resize(size_t(3) * nt);
+    std::vector<int> cur(T.n2t_head.begin(), T.n2t_head.end() - 1);
+    for (int t = 0; t < nt; ++t)
+        for (int r = 0; r < 3; ++r) T.n2t[cur[tri[3 * t + r]]++] = t;
+}
+
+// barycentric coordinates of (x, y) in triangle t (vertex order of the triangle)
+void bary(const double* xy, const int32_t* tri, int t, double x, double y, double l[3]) {
+    const V2 a{xy[2 * tri[3 * t]], xy[2 * tri[3 * t] + 1]};
+    const V2 b{xy[2 * tri[3 * t + 1]], xy[2 * tri[3 * t + 1] + 1]};
+    const V2 c{xy[2 * tri[3 * t + 2]], xy[2 * tri[3 * t + 2] + 1]};
+    const V2 p{x, y};
+    const double d = cross(b - a, c - a);
+    l[1] = cross(p - a, c - a) / d;
+    l[2] = cross(b - a, p - a) / d;
+    l[0] = 1.0 - l[1] - l[2];
+}
+
+// Solves M w = e_0 (6 x 6) by Gauss-Jordan elimination with full pivoting.
+bool solve6(double M[6][6], double w[6]) {
+    double rhs[6] = {1, 0, 0, 0, 0, 0};
+    int colperm[6] = {0, 1, 2, 3, 4, 5};
+    double big = 0;
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) big = std::max(big, std::fabs(M[r][c]));
+    for (int k = 0; k < 6; ++k) {
+        int pr = k, pc = k;
+        for (int r = k; r < 6; ++r)
+            for (int c = k; c < 6; ++c)
+                if (std::fabs(M[r][c]) > std::fabs(M[pr][pc])) pr = r, pc = c;
+        if (std::fabs(M[pr][pc]) < 1e-10 * big) return false;
+        if (pr != k) {
+            for (int c = 0; c < 6; ++c) std::swap(M[k][c], M[pr][c]);
+            std::swap(rhs[k], rhs[pr]);
+        }
+        if (pc != k) {
+            for (int r = 0; r < 6; ++r) std::swap(M[r][k], M[r][pc]);
+            std::swap(colperm[k], colperm[pc]);
+        }
+        const double inv = 1.0 / M[k][k];
+        for (int c = k; c < 6; ++c) M[k][c] *= inv;
+        rhs[k] *= inv;
+        for (int r = 0; r < 6; ++r) {
+            if (r == k || M[r][k] == 0.0) continue;
+            const double f = M[r][k];
+            for (int c = k; c < 6; ++c) M[r][c] -= f * M[k][c];
+            rhs[r] -= f * rhs[k];
+        }
+    }
+    for (int k = 0; k < 6; ++k) w[colperm[k]] = rhs[k];
+    return true;
+}
+
+// Donors and weights of one triangle's stencil at (x, y): the quadratic of
+// eq. (8) through the triangle's vertices and the vertices opposite its three
+// edges in the neighbouring triangles (exact for quadratics); barycentric
+// weights when linear is asked for, a neighbour is missing, or singular.
+int tri_stencil(const TriIndex& T, const double* xy, const int32_t* tri, int t, const double lam[3],
+                double x, double y, bool linear, int* don, double* w, bool& fallback) {
+    const int v0 = tri[3 * t], v1 = tri[3 * t + 1], v2 = tri[3 * t + 2];
+    if (!linear) {
+        auto opposite = [&](int a, int b) {
+            for (int z = T.n2t_head[a]; z < T.n2t_head[a + 1]; ++z) {
+                const int u = T.n2t[z];
+                if (u == t) continue;
+                int third = -1;
+                bool hb = false;
+                for (int r = 0; r < 3; ++r) {
+                    const int q = tri[3 * u + r];
+                    if (q == b) hb = true;
+                    else if (q != a) third = q;
+                }
+                if (hb) return third;
+            }
+            return -1;
+        };
+        const int nodes[6] = {v0, v1, v2, opposite(v0, v1), opposite(v1, v2), opposite(v2, v0)};
+        if (nodes[3] >= 0 && nodes[4] >= 0 && nodes[5] >= 0) {
+            const double h = std::sqrt(std::fabs(cross(V2{xy[2 * v1] - xy[2 * v0], xy[2 * v1 + 1] - xy[2 * v0 + 1]},
+                                                       V2{xy[2 * v2] - xy[2 * v0], xy[2 * v2 + 1] - xy[2 * v0 + 1]})));
+            double M[6][6];
+            for (int k = 0; k < 6; ++k) {
+                const double a = (xy[2 * nodes[k]] - x) / h, b = (xy[2 * nodes[k] + 1] - y) / h;
+                const double mono[6] = {1.0, a, b, a * a, a * b, b * b};
+                for (int r = 0; r < 6; ++r) M[r][k] = mono[r];
+            }
+            double ww[6];
+            if (solve6(M, ww)) {
+                for (int k = 0; k < 6; ++k) don[k] = nodes[k], w[k] = ww[k];
+                return 6;
+            }
+        }
+        fallback = true;
+    }
+    don[0] = v0, don[1] = v1, don[2] = v2;
+    w[0] = lam[0], w[1] = lam[1], w[2] = lam[2];
+    return 3;
+}
+
+// Stencil of a structured interpolation node: a node it sits on; the stencil of
+// the triangle containing it; the mean of the two stencils when it lies on the
+// edge shared by two triangles.  Returns donor count or -1 (outside / ambiguous).
+int mesh_stencil(const TriIndex& T, const double* xy, const int32_t* tri, double x, double y, bool linear,
+                 int* don, double* w, bool& fallback) {
+    fallback = false;
+    const int bi = int(std::floor((x - T.x0) / T.h)), bj = int(std::floor((y - T.y0) / T.h));
+    if (bi < 0 || bj < 0 || bi >= T.nbx || bj >= T.nby) return -1;
+    const int b = bj * T.nbx + bi;
+    int hits[8], nh = 0;
+    double lams[8][3];
+    for (int z = T.head[b]; z < T.head[b + 1] && nh < 8; ++z) {
+        double l[3];
+        bary(xy, tri, T.list[z], x, y, l);
+        if (l[0] >= -1e-12 && l[1] >= -1e-12 && l[2] >= -1e-12) {
+            hits[nh] = T.list[z];
+            std::copy(l, l + 3, lams[nh]);
+            ++nh;
+        }
+    }
+    if (nh == 0) return -1;
+    for (int r = 0; r < 3; ++r)
+        if (lams[0][r] >= 1.0 - 1e-12) {
+            don[0] = tri[3 * hits[0] + r];
+            w[0] = 1.0;
+            return 1;
+        }
+    if (nh > 2) return -1;
+    int n = 0;
+    for (int a = 0; a < nh; ++a) {
+        int d[6];
+        double ww[6];
+        const int nd = tri_stencil(T, xy, tri, hits[a], lams[a], x, y, linear, d, ww, fallback);
+        for (int k = 0; k < nd; ++k) {
+            int slot = -1;
+            for (int s = 0; s < n; ++s)
+                if (don[s] == d[k]) slot = s;
+            if (slot < 0) {
+                slot = n++;
+                don[slot] = d[k];
+                w[slot] = 0.0;
+            }
+            w[slot] += ww[k] / nh;
+        }
+    }
+    return n;
+}
+
+}  // namespace
+
+int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Plan& p, std::string& err) {
+    if (!g) return fail(err, HLBM_E_ARG, "grid is null");
+    p = Plan();
+    p.has_grid = g->nx_cells > 0 && g->ny_cells > 0;
+    p.has_mesh = m && m->n_nodes > 0;
+    if (!p.has_grid) return fail(err, HLBM_E_ARG, "a structured grid is required");
+    if (g->n_refine < 0 || g->n_refine > 3) return fail(err, HLBM_E_ARG, "n_refine must be 0..3");
+    if (g->precision != HLBM_FP64 && g->precision != HLBM_FP32_SHIFTED) return fail(err, HLBM_E_ARG, "bad precision");
+    if (g->interp != HLBM_INTERP_QUADRATIC && g->interp != HLBM_INTERP_LINEAR) return fail(err, HLBM_E_ARG, "bad interp");
+    if (g->bc != HLBM_BC_FARFIELD && g->bc != HLBM_BC_PERIODIC) return fail(err, HLBM_E_ARG, "bad bc");
+    if (!(g->rho0 > 0)) return fail(err, HLBM_E_PARAM, "rho0 must be positive");
+    p.L = g->n_refine;
+    p.nlev = p.L + 1;
+    p.precision = g->precision;
+    p.elem = g->precision == HLBM_FP64 ? 8 : 4;
+    p.interp = g->interp;
+    p.periodic = g->bc == HLBM_BC_PERIODIC;
+    p.wall_bc = g->wall_bc != 0;
+    p.u_inf = g->u_inf;
+    p.aoa = g->aoa_rad;
+    p.rho0 = g->rho0;
+    p.chord = p.has_mesh ? m->chord : 1.0;
+    p.check_every = std::max(0, g->check_every);
+    p.hist_len = g->history_len > 0 ? g->history_len : 65536;
+    // relaxation time of the finest level (nu = c_s^2 (tau - 1/2), Sec. 2)
+    if (tau > 0.5) {
+        p.tau_s = tau;
+        if (Re > 0) {
+            const double t2 = 0.5 + 3.0 * g->u_inf * p.chord / Re;
+            if (std::fabs(t2 - tau) > 1e-12 * tau) return fail(err, HLBM_E_PARAM, "Re and tau disagree");
+        }
+    } else if (Re > 0) {
+        p.tau_s = 0.5 + 3.0 * g->u_inf * p.chord / Re;
+    } else {
+        return fail(err, HLBM_E_PARAM, "need tau > 1/2 or Re > 0");
+    }
+    if (!(p.tau_s > 0.5)) return fail(err, HLBM_E_PARAM, "tau must exceed 1/2");
+    p.tau_u = p.tau_s - 0.5;
+    p.n_sub = g->n_sub > 0 ? g->n_sub : std::max(10, int(std::ceil(1.0 / p.tau_u)));
+    p.dt_u = 1.0 / p.n_sub;
+
+    // ---- levels
+    {
+        LevelPlan& b = p.lev[0];
+        b.nx = g->nx_cells + (p.periodic ? 0 : 1);
+        b.ny = g->ny_cells + (p.periodic ? 0 : 1);
+        b.sp = 1 << p.L;
+        b.farfield = !p.periodic;
+        b.periodic = p.periodic;
+        if (b.nx < 4 || b.ny < 4) return fail(err, HLBM_E_ARG, "grid too small");
+    }
+    for (int l = 1; l <= p.L; ++l) {
+        LevelPlan& c = p.lev[l];
+        LevelPlan& a = p.lev[l - 1];
+        const int px = g->patch_nx[l - 1], py = g->patch_ny[l - 1];
+        if (px <= 0 || py <= 0 || px % 2 || py % 2) return fail(err, HLBM_E_GEOMETRY, "box %d: sizes must be positive and even", l);
+        c.nx = px + 1;
+        c.ny = py + 1;
+        c.i0 = g->patch_i0[l - 1];
+        c.j0 = g->patch_j0[l - 1];
+        c.sp = a.sp / 2;
+        c.ox = a.ox + c.i0 * a.sp;
+        c.oy = a.oy + c.j0 * a.sp;
+        c.perim_inactive = true;
+        a.has_child = true;
+        a.ci0 = c.i0;
+        a.cj0 = c.j0;
+        a.ci1 = c.i0 + px / 2;
+        a.cj1 = c.j0 + py / 2;
+        const int lo = (a.perim_inactive ? 2 : 2);
+        if (a.ci0 < lo || a.cj0 < lo || a.ci1 > a.nx - 1 - lo || a.cj1 > a.ny - 1 - lo)
+            return fail(err, HLBM_E_GEOMETRY, "box %d does not fit inside its parent with a two-node margin", l);
+        if (px / 2 < 4 || py / 2 < 4) return fail(err, HLBM_E_GEOMETRY, "box %d too small", l);
+    }
+    for (int l = 0; l <= p.L; ++l) {
+        LevelPlan& v = p.lev[l];
+        v.tau = 0.5 + (p.tau_s - 0.5) / double(1 << (p.L - l));
+        if (!(v.tau > 0.5)) return fail(err, HLBM_E_PARAM, "tau <= 1/2 on level %d", l);
+        const int al = p.elem == 8 ? 32 : 64;   // 256-byte rows
+        v.pitch = (v.nx + al - 1) / al * al;
+    }
+    LevelPlan& fl = p.lev[p.L];
+    // ---- inner ellipse: inactive nodes of the finest level (one span per row)
+    const bool has_ein = p.has_mesh && m->inner_ellipse[2] > 0 && m->inner_ellipse[3] > 0;
+    std::vector<uint8_t> inside;   // finest level, 1 = strictly inside the inner ellipse
+    if (has_ein) {
+        const double xc = m->inner_ellipse[0], yc = m->inner_ellipse[1];
+        const double ea = m->inner_ellipse[2], eb = m->inner_ellipse[3];
+        inside.assign(size_t(fl.nx) * fl.ny, 0);
+        int jmin = fl.ny, jmax = -1;
+        for (int j = 0; j < fl.ny; ++j)
+            for (int i = 0; i < fl.nx; ++i) {
+                const double dx = (fl.ox + i * fl.sp - xc) / ea, dy = (fl.oy + j * fl.sp - yc) / eb;
+                if (dx * dx + dy * dy < 1.0) {
+                    inside[size_t(j) * fl.nx + i] = 1;
+                    jmin = std::min(jmin, j);
+                    jmax = std::max(jmax, j);
+                }
+            }
+        if (jmax >= 0) {
+            fl.sj0 = jmin;
+            fl.sj1 = jmax + 1;
+            for (int j = fl.sj0; j < fl.sj1; ++j) {
+                int lo = -1, hi = -1;
+                for (int i = 0; i < fl.nx; ++i)
+                    if (inside[size_t(j) * fl.nx + i]) {
+                        if (lo < 0) lo = i;
+                        if (hi >= 0 && hi != i) return fail(err, HLBM_E_GEOMETRY, "inactive region not convex in row %d", j);
+                        hi = i + 1;
+                    }
+                if (lo < 0) lo = hi = 0;
+                if (lo < 2 || hi > fl.nx - 2 || j < 2 || j > fl.ny - 3)
+                    return fail(err, HLBM_E_GEOMETRY, "inner ellipse too close to the edge of the finest level");
+                p.spans.push_back(lo);
+                p.spans.push_back(hi);
+            }
+        }
+    }
+    auto collide_node = [&](int l, int i, int j) -> bool {   // is (i, j) a collide-stream node of level l
+        const LevelPlan& v = p.lev[l];
+        if (i < 0 || j < 0 || i >= v.nx || j >= v.ny) return false;
+        if (v.perim_inactive && (i == 0 || j == 0 || i == v.nx - 1 || j == v.ny - 1)) return false;
+        if (v.has_child && i > v.ci0 && i < v.ci1 && j > v.cj0 && j < v.cj1) return false;
+        if (l == p.L && !inside.empty() && inside[size_t(j) * v.nx + i]) return false;
+        return true;
+    };
+    for (int l = 0; l <= p.L; ++l) {
+        const LevelPlan& v = p.lev[l];
+        int64_t n = int64_t(v.nx) * v.ny;
+        if (v.perim_inactive) n -= 2 * int64_t(v.nx + v.ny) - 4;
+        if (v.has_child) n -= int64_t(v.ci1 - v.ci0 - 1) * (v.cj1 - v.cj0 - 1);
+        if (l == p.L)
+            for (size_t a = 0; a < p.spans.size(); a += 2) n -= p.spans[a + 1] - p.spans[a];
+        p.lev[l].active = n;
+    }
+
+    // ---- mesh
+    if (p.has_mesh) {
+        if (!m->xy || !m->tri || !m->kind || m->n_tris <= 0) return fail(err, HLBM_E_ARG, "mesh arrays missing");
+        const int nn = m->n_nodes, nt = m->n_tris;
+        p.nn = nn;
+        p.nt = nt;
+        for (int a = 0; a < nn; ++a)
+            if (m->kind[a] > 2) return fail(err, HLBM_E_ARG, "node kind must be 0, 1 or 2");
+        std::vector<Entry> ent;
+        std::vector<double> area;
+        std::vector<std::array<int, 2>> bnd;
+        int rc = median_dual(nn, nt, m->xy, m->tri, ent, area, bnd, err);
+        if (rc) return rc;
+        std::vector<int> rp(nn + 1, 0), cl(ent.size());
+        for (const Entry& e : ent) rp[e.p + 1]++;
+        for (int a = 0; a < nn; ++a) rp[a + 1] += rp[a];
+        for (size_t z = 0; z < ent.size(); ++z) cl[z] = ent[z].k;
+        // node order: RCM, then stable partition [wall | interior | interpolation]
+        const std::vector<int> rcm = rcm_order(nn, rp, cl, m->kind);
+        p.perm.clear();
+        for (int kindsel : {1, 0, 2})
+            for (int a : rcm)
+                if (m->kind[a] == kindsel) p.perm.push_back(a);
+        std::vector<int> inv(nn);
+        for (int a = 0; a < nn; ++a) inv[p.perm[a]] = a;
+        p.n_wall = 0;
+        p.n_int = 0;
+        for (int a = 0; a < nn; ++a) p.n_wall += m->kind[a] == 1, p.n_int += m->kind[a] == 2;
+        p.n_core = nn - p.n_int;
+        // CSR in plan order: self entry first, then neighbours by plan index
+        p.rowptr.assign(nn + 1, 0);
+        p.col.clear();
+        p.gx.clear();
+        p.gy.clear();
+        p.cc.clear();
+        for (int P = 0; P < nn; ++P) {
+            const int o = p.perm[P];
+            std::vector<std::pair<int, int>> row;   // (new col, entry index)
+            for (int z = rp[o]; z < rp[o + 1]; ++z) row.emplace_back(inv[cl[z]], z);
+            std::sort(row.begin(), row.end(), [&](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+                const bool sa = a.first == P, sb = b.first == P;
+                if (sa != sb) return sa;
+                return a.first < b.first;
+            });
+            for (auto& pr : row) {
+                p.col.push_back(pr.first);
+                p.gx.push_back(ent[pr.second].gx);
+                p.gy.push_back(ent[pr.second].gy);
+                p.cc.push_back(ent[pr.second].c);
+            }
+            p.rowptr[P + 1] = int(p.col.size());
+        }
+        // wall edges: boundary edges with both ends on the wall
+        for (const auto& be : bnd)
+            if (m->kind[be[0]] == 1 && m->kind[be[1]] == 1) {
+                p.wedge.push_back(inv[be[0]]);
+                p.wedge.push_back(inv[be[1]]);
+                const double dx = m->xy[2 * be[1]] - m->xy[2 * be[0]], dy = m->xy[2 * be[1] + 1] - m->xy[2 * be[0] + 1];
+                p.wnorm.push_back(dy);
+                p.wnorm.push_back(-dx);
+            }
+        // ---- coupling stencils
+        const bool linear = p.interp == HLBM_INTERP_LINEAR;
+        if (has_ein) {
+            TriIndex T;
+            build_tri_index(nn, nt, m->xy, m->tri, T);
+            for (int j = fl.sj0; j < fl.sj1; ++j) {
+                const int lo = p.spans[2 * (j - fl.sj0)], hi = p.spans[2 * (j - fl.sj0) + 1];
+                for (int i = lo; i < hi; ++i) {
+                    bool edge = false;
+                    for (int q = 1; q < 9 && !edge; ++q) edge = collide_node(p.L, i + kCx[q], j + kCy[q]);
+                    if (!edge) continue;
+                    const double x = fl.ox + i * fl.sp, y = fl.oy + j * fl.sp;
+                    int don[kSDon];
+                    double w[kSDon];
+                    bool fb = false;
+                    const int nd = mesh_stencil(T, m->xy, m->tri, x, y, linear, don, w, fb);
+                    if (nd < 0) return fail(err, HLBM_E_GEOMETRY, "structured interpolation node (%d,%d) is outside the mesh", i, j);
+                    p.n_fallback += fb;
+                    p.sint_node.push_back(i + fl.nx * j);
+                    for (int d = 0; d < kSDon; ++d) {
+                        p.sint_don.push_back(d < nd ? inv[don[d]] : -1);
+                        p.sint_w.push_back(d < nd ? w[d] : 0.0);
+                    }
+                }
+            }
+        }
+        for (int s = 0; s < p.n_int; ++s) {
+            const int o = p.perm[p.n_core + s];
+            const double x = m->xy[2 * o] - fl.ox, y = m->xy[2 * o + 1] - fl.oy;   // finest spacing is 1
+            int di[9], dj[9], nd;
+            double w[9];
+            if (!linear) {
+                const int ic = int(std::floor(x + 0.5)), jc = int(std::floor(y + 0.5));
+                const double s1 = x - ic, t1 = y - jc;
+                const double lx[3] = {0.5 * s1 * (s1 - 1.0), (1.0 - s1) * (1.0 + s1), 0.5 * s1 * (s1 + 1.0)};
+                const double ly[3] = {0.5 * t1 * (t1 - 1.0), (1.0 - t1) * (1.0 + t1), 0.5 * t1 * (t1 + 1.0)};
+                nd = 0;
+                for (int b = -1; b <= 1; ++b)
+                    for (int a = -1; a <= 1; ++a) {
+                        di[nd] = ic + a;
+                        dj[nd] = jc + b;
+                        w[nd] = lx[a + 1] * ly[b + 1];
+                        ++nd;
+                    }
+            } else {
+                const int ic = int(std::floor(x)), jc = int(std::floor(y));
+                const double s1 = x - ic, t1 = y - jc;
+                di[0] = ic, dj[0] = jc, w[0] = (1 - s1) * (1 - t1);
+                di[1] = ic + 1, dj[1] = jc, w[1] = s1 * (1 - t1);
+                di[2] = ic, dj[2] = jc + 1, w[2] = (1 - s1) * t1;
+                di[3] = ic + 1, dj[3] = jc + 1, w[3] = s1 * t1;
+                nd = 4;
+            }
+            for (int d = 0; d < kUDon; ++d) {
+                if (d < nd) {
+                    const bool interior = di[d] >= 1 && dj[d] >= 1 && di[d] <= fl.nx - 2 && dj[d] <= fl.ny - 2;
+                    if (!interior || !collide_node(p.L, di[d], dj[d]))
+                        return fail(err, HLBM_E_GEOMETRY,
+                                    "mesh interpolation node %d: donor (%d,%d) is not a collide-stream node of the finest level", o, di[d], dj[d]);
+                    p.uint_don.push_back(di[d] + fl.nx * dj[d]);
+                    p.uint_w.push_back(w[d]);
+                } else {
+                    p.uint_don.push_back(-1);
+                    p.uint_w.push_back(0.0);
+                }
+            }
+        }
+    } else if (has_ein) {
+        return fail(err, HLBM_E_GEOMETRY, "an inactive region needs a mesh");
+    }
+
+    // ---- workspace layout
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + std::max<size_t>(bytes, 1));
+        return o;
+    };
+    const size_t E = p.elem;
+    for (int l = 0; l <= p.L; ++l) {
+        const size_t lb = size_t(kQ) * p.lev[l].ny * p.lev[l].pitch * E;
+        p.off.lev[l][0] = take(lb);
+        p.off.lev[l][1] = take(lb);
+    }
+    for (int l = 0; l < p.L; ++l) {
+        const LevelPlan& v = p.lev[l];
+        const size_t nb = 2 * size_t((v.ci1 - v.ci0) + (v.cj1 - v.cj0));
+        p.off.side[l][0] = take(nb * kMacro * E);
+        p.off.side[l][1] = take(nb * kMacro * E);
+    }
+    p.off.spans = take(p.spans.size() * 4);
+    const size_t ns = p.sint_node.size();
+    p.off.sint_node = take(ns * 4);
+    p.off.sint_don = take(ns * kSDon * 4);
+    p.off.sint_w = take(ns * kSDon * E);
+    const size_t nnp = size_t(std::max(p.nn, 1));
+    p.off.mesh[0] = take(kQ * nnp * E);
+    p.off.mesh[1] = take(kQ * nnp * E);
+    p.off.rowptr = take((nnp + 1) * 4);
+    p.off.edges = take(p.col.size() * (E == 8 ? 32 : 16));
+    p.off.wedge = take(p.wedge.size() * 4);
+    p.off.wnorm = take(p.wnorm.size() * 8);
+    p.off.prep[0] = take(size_t(std::max(p.n_int, 1)) * kMacro * E);
+    p.off.prep[1] = take(size_t(std::max(p.n_int, 1)) * kMacro * E);
+    p.off.uint_don = take(p.uint_don.size() * 4);
+    p.off.uint_w = take(p.uint_w.size() * E);
+    p.off.hist = take(size_t(p.hist_len) * 2 * 8);
+    size_t maxrow = 0;
+    for (int l = 0; l <= p.L; ++l) maxrow = std::max(maxrow, size_t(p.lev[l].nx));
+    p.stage_bytes = std::max(size_t(kQ) * maxrow * 8 * 8, std::min(size_t(32) << 20, size_t(kQ) * maxrow * 8 * 4096));
+    p.stage_bytes = std::max(p.stage_bytes, size_t(kQ) * nnp * 8);
+    p.off.stage = take(p.stage_bytes);
+    p.off.total = off;
+    return HLBM_OK;
+}
+
+}  // namespace hlbm

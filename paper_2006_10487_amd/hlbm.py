@@ -1,0 +1,282 @@
+"""Python binding of the HLBM C ABI (``include/hlbm.h``).
+
+Argument marshalling only: every step of the method runs in the HIP library
+``libhlbm.so``.  PyTorch provides the device workspace and the stream.  The
+binding fails loudly when the library is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhlbm.so")
+
+HLBM_OK = 0
+ERRORS = {-1: "HLBM_E_ARG", -2: "HLBM_E_GEOMETRY", -3: "HLBM_E_PARAM", -4: "HLBM_E_DEVICE",
+          -5: "HLBM_E_NONFINITE", -6: "HLBM_E_STATE", -7: "HLBM_E_WORKSPACE"}
+FP64, FP32_SHIFTED = 0, 1
+INTERP_QUADRATIC, INTERP_LINEAR = 0, 1
+BC_FARFIELD, BC_PERIODIC = 0, 1
+PART_MESH = 100
+
+EXPORTED = ["hlbm_validate", "hlbm_workspace_size", "hlbm_create", "hlbm_step", "hlbm_forces",
+            "hlbm_force_history", "hlbm_get_state", "hlbm_set_state", "hlbm_info", "hlbm_last_error",
+            "hlbm_destroy", "hlbm_profile", "hlbm_profile_read"]
+KERNEL_CLASSES = ["collide_l0", "collide_l1", "collide_l2", "collide_l3", "coarse_to_fine",
+                  "fine_to_coarse", "mesh_to_struct", "struct_to_mesh", "fv_substep", "wall_force"]
+
+
+class HLBMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [
+        ("nx_cells", C.c_int32), ("ny_cells", C.c_int32), ("n_refine", C.c_int32),
+        ("patch_i0", C.c_int32 * 3), ("patch_j0", C.c_int32 * 3),
+        ("patch_nx", C.c_int32 * 3), ("patch_ny", C.c_int32 * 3),
+        ("u_inf", C.c_double), ("aoa_rad", C.c_double), ("rho0", C.c_double),
+        ("precision", C.c_int32), ("interp", C.c_int32), ("n_sub", C.c_int32), ("bc", C.c_int32),
+        ("wall_bc", C.c_int32), ("check_every", C.c_int32), ("history_len", C.c_int32),
+    ]
+
+
+class Mesh(C.Structure):
+    _fields_ = [
+        ("n_nodes", C.c_int32), ("n_tris", C.c_int32),
+        ("xy", C.POINTER(C.c_double)), ("tri", C.POINTER(C.c_int32)), ("kind", C.POINTER(C.c_uint8)),
+        ("chord", C.c_double), ("inner_ellipse", C.c_double * 4),
+    ]
+
+
+class Info(C.Structure):
+    _fields_ = [
+        ("n_levels", C.c_int32), ("n_sub", C.c_int32),
+        ("nx", C.c_int32 * 4), ("ny", C.c_int32 * 4), ("pitch", C.c_int32 * 4),
+        ("tau", C.c_double * 4), ("tau_u", C.c_double), ("active_nodes", C.c_int64 * 4),
+        ("n_mesh_nodes", C.c_int32), ("n_wall_nodes", C.c_int32), ("n_interp_mesh", C.c_int32),
+        ("n_interp_struct", C.c_int32), ("n_fallback", C.c_int32), ("n_wall_edges", C.c_int32),
+        ("nnz", C.c_int32), ("bytes_per_finest_step", C.c_int64), ("k1_bytes", C.c_int64 * 4),
+        ("fv_bytes", C.c_int64), ("t", C.c_int64), ("workspace_bytes", C.c_size_t),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhlbm.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.hlbm_validate.argtypes = [C.POINTER(Grid), C.POINTER(Mesh), C.c_double, C.c_double]
+        L.hlbm_workspace_size.argtypes = [C.POINTER(Grid), C.POINTER(Mesh), C.c_double, C.c_double,
+                                          C.POINTER(C.c_size_t)]
+        L.hlbm_create.argtypes = [C.POINTER(Grid), C.POINTER(Mesh), C.c_double, C.c_double, P,
+                                  C.c_size_t, P, C.POINTER(P)]
+        L.hlbm_step.argtypes = [P, C.c_int64]
+        L.hlbm_forces.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.hlbm_force_history.argtypes = [P, C.c_int64, C.c_int64, P, P]
+        L.hlbm_get_state.argtypes = [P, C.c_int32, P, C.c_size_t]
+        L.hlbm_set_state.argtypes = [P, C.c_int32, P, C.c_size_t]
+        L.hlbm_info.argtypes = [P, C.POINTER(Info)]
+        L.hlbm_last_error.argtypes = [P]
+        L.hlbm_last_error.restype = C.c_char_p
+        L.hlbm_destroy.argtypes = [P]
+        L.hlbm_destroy.restype = None
+        L.hlbm_profile.argtypes = [P, C.c_int]
+        L.hlbm_profile_read.argtypes = [P, P, P]
+        _lib = L
+    return _lib
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def make_structs(nx_cells, ny_cells, patches=(), *, u_inf=0.05, aoa_rad=0.0, rho0=1.0,
+                 precision=FP64, interp=INTERP_QUADRATIC, n_sub=0, periodic=False, wall_bc=True,
+                 check_every=0, history_len=0, mesh_xy=None, mesh_tri=None, mesh_kind=None,
+                 chord=1.0, inner_ellipse=None):
+    """ctypes Grid and Mesh (plus the arrays they point into, kept alive)."""
+    g = Grid()
+    g.nx_cells, g.ny_cells, g.n_refine = nx_cells, ny_cells, len(patches)
+    for k, (i0, j0, px, py) in enumerate(patches):
+        g.patch_i0[k], g.patch_j0[k], g.patch_nx[k], g.patch_ny[k] = i0, j0, px, py
+    g.u_inf, g.aoa_rad, g.rho0 = u_inf, aoa_rad, rho0
+    g.precision, g.interp, g.n_sub = precision, interp, n_sub
+    g.bc = BC_PERIODIC if periodic else BC_FARFIELD
+    g.wall_bc, g.check_every, g.history_len = int(wall_bc), check_every, history_len
+    m = Mesh()
+    keep = []
+    if mesh_xy is not None:
+        xy = np.ascontiguousarray(mesh_xy, dtype=np.float64).reshape(-1, 2)
+        tri = np.ascontiguousarray(mesh_tri, dtype=np.int32).reshape(-1, 3)
+        kind = np.ascontiguousarray(mesh_kind, dtype=np.uint8)
+        keep += [xy, tri, kind]
+        m.n_nodes, m.n_tris = xy.shape[0], tri.shape[0]
+        m.xy = xy.ctypes.data_as(C.POINTER(C.c_double))
+        m.tri = tri.ctypes.data_as(C.POINTER(C.c_int32))
+        m.kind = kind.ctypes.data_as(C.POINTER(C.c_uint8))
+    m.chord = chord
+    ein = inner_ellipse if inner_ellipse is not None else (0.0, 0.0, 0.0, 0.0)
+    for k in range(4):
+        m.inner_ellipse[k] = float(ein[k])
+    return g, m, keep
+
+
+def structs_from_workload(w, **over):
+    kw = dict(u_inf=w.u_inf, aoa_rad=w.aoa_rad, rho0=w.rho0, periodic=w.periodic, n_sub=w.n_sub,
+              mesh_xy=w.mesh_xy, mesh_tri=w.mesh_tri, mesh_kind=w.mesh_kind, chord=w.chord,
+              inner_ellipse=w.inner_ellipse)
+    kw.update(over)
+    return make_structs(w.nx_cells, w.ny_cells, w.patches, **kw)
+
+
+def validate(grid: Grid, mesh: Mesh, re: float = 0.0, tau: float = 0.0) -> int:
+    return lib().hlbm_validate(C.byref(grid), C.byref(mesh), re, tau)
+
+
+def last_error(ctx=None) -> str:
+    return (lib().hlbm_last_error(ctx) or b"").decode()
+
+
+def workspace_size(grid: Grid, mesh: Mesh, re: float = 0.0, tau: float = 0.0) -> int:
+    n = C.c_size_t(0)
+    rc = lib().hlbm_workspace_size(C.byref(grid), C.byref(mesh), re, tau, C.byref(n))
+    if rc:
+        raise HLBMError(rc, last_error())
+    return n.value
+
+
+class HLBM:
+    """One HLBM problem on the current CUDA/HIP device.
+
+    ``HLBM(grid, mesh, tau=...)`` with ctypes structs, or ``HLBM.from_workload(w)``.
+    """
+
+    def __init__(self, grid: Grid, mesh: Mesh, *, re: float = 0.0, tau: float = 0.0,
+                 keep=(), stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("HLBM needs a GPU (torch.cuda is not available)")
+        self._keep = list(keep)
+        self.grid, self.mesh = grid, mesh
+        nbytes = workspace_size(grid, mesh, re, tau)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        ctx = C.c_void_p()
+        rc = lib().hlbm_create(C.byref(grid), C.byref(mesh), re, tau,
+                               C.c_void_p(self.workspace.data_ptr()), nbytes,
+                               C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        if rc:
+            raise HLBMError(rc, last_error())
+        self._ctx = ctx
+        self.info = self.get_info()
+
+    @classmethod
+    def from_workload(cls, w, *, precision=FP64, interp=INTERP_QUADRATIC, n_sub=0, wall_bc=True,
+                      aoa_rad=None, tau=None, check_every=0, history_len=0, stream=None):
+        g, m, keep = structs_from_workload(
+            w, precision=precision, interp=interp, n_sub=n_sub or w.n_sub, wall_bc=wall_bc,
+            aoa_rad=w.aoa_rad if aoa_rad is None else aoa_rad, check_every=check_every,
+            history_len=history_len)
+        return cls(g, m, tau=w.tau_s if tau is None else tau, keep=keep, stream=stream)
+
+    def _check(self, rc):
+        if rc:
+            raise HLBMError(rc, last_error(self._ctx))
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().hlbm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_info(self) -> Info:
+        info = Info()
+        self._check(lib().hlbm_info(self._ctx, C.byref(info)))
+        return info
+
+    @property
+    def t(self) -> int:
+        return int(self.get_info().t)
+
+    def step(self, n: int):
+        self._check(lib().hlbm_step(self._ctx, int(n)))
+
+    def forces(self):
+        cd, cl = C.c_double(), C.c_double()
+        self._check(lib().hlbm_forces(self._ctx, C.byref(cd), C.byref(cl)))
+        return cd.value, cl.value
+
+    def history(self, t0: Optional[int] = None, t1: Optional[int] = None):
+        t = self.t
+        t1 = t if t1 is None else t1
+        t0 = max(0, t1 - (self.grid.history_len or 65536)) if t0 is None else t0
+        cd = np.zeros(max(t1 - t0, 1))
+        cl = np.zeros(max(t1 - t0, 1))
+        self._check(lib().hlbm_force_history(self._ctx, t0, t1, _np_ptr(cd), _np_ptr(cl)))
+        return cd[:t1 - t0], cl[:t1 - t0]
+
+    def level_shape(self, l: int):
+        return (int(self.info.ny[l]), int(self.info.nx[l]))
+
+    def get_state(self, part: int) -> np.ndarray:
+        if part == PART_MESH:
+            out = np.zeros((9, int(self.info.n_mesh_nodes)))
+        else:
+            out = np.zeros((9,) + self.level_shape(part))
+        self._check(lib().hlbm_get_state(self._ctx, part, _np_ptr(out), out.size))
+        return out
+
+    def set_state(self, part: int, f: np.ndarray):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        self._check(lib().hlbm_set_state(self._ctx, part, _np_ptr(f), f.size))
+
+    def profile(self, enable: bool = True):
+        self._check(lib().hlbm_profile(self._ctx, int(enable)))
+
+    def profile_read(self):
+        """{kernel class: (total ms, launches)} since the last read."""
+        ms = np.zeros(len(KERNEL_CLASSES))
+        n = np.zeros(len(KERNEL_CLASSES), np.int64)
+        self._check(lib().hlbm_profile_read(self._ctx, _np_ptr(ms), _np_ptr(n)))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+
+def strouhal(cl: np.ndarray, chord: float, u_inf: float, steady_tol: float = 1e-6) -> float:
+    """Strouhal number c / (U T) of a lift history sampled every finest step.
+
+    T is the mean spacing of the upward crossings of C_L - mean(C_L), located
+    by linear interpolation.  Returns NaN for a steady signal (peak-to-peak
+    below steady_tol) or fewer than two crossings.
+    """
+    cl = np.asarray(cl, dtype=np.float64)
+    if cl.size < 3 or np.ptp(cl) < steady_tol:
+        return math.nan
+    x = cl - cl.mean()
+    idx = np.nonzero((x[:-1] < 0) & (x[1:] >= 0))[0]
+    if idx.size < 2:
+        return math.nan
+    tc = idx + (-x[idx]) / (x[idx + 1] - x[idx])
+    period = (tc[-1] - tc[0]) / (idx.size - 1)
+    return chord / (u_inf * period)

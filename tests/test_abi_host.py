@@ -1,0 +1,101 @@
+"""Host-only checks of the C ABI: the library loads without a GPU, exports every
+function declared in include/hlbm.h, and rejects bad problems before any device
+work (hlbm_validate / hlbm_workspace_size)."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2006_10487_amd import hlbm, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(hlbm.LIB_PATH):
+        from paper_2006_10487_amd import build
+        build.build()
+    return hlbm.lib()
+
+
+def test_header_symbols_exported(lib):
+    text = open(os.path.join(ROOT, "include", "hlbm.h")).read()
+    declared = set(re.findall(r"\b(hlbm_[a-z_]+)\s*\(", text))
+    assert declared == set(hlbm.EXPORTED)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_struct_sizes_match_header(lib):
+    # hlbm_grid: 3 ints, 12 ints, 3 doubles, 7 ints (+ padding) -> ctypes follows the C layout
+    assert C.sizeof(hlbm.Grid) % 8 == 0
+    assert C.sizeof(hlbm.Mesh) == 4 + 4 + 3 * 8 + 8 + 32
+
+
+def _small(**kw):
+    w = W.naca_re100_c40()
+    return hlbm.structs_from_workload(w, **kw), w
+
+
+def test_validate_ok_and_workspace(lib):
+    (g, m, keep), w = _small()
+    assert hlbm.validate(g, m, 0.0, w.tau_s) == 0
+    assert hlbm.validate(g, m, w.re, 0.0) == 0
+    n = hlbm.workspace_size(g, m, 0.0, w.tau_s)
+    # two FP64 buffers of the 241 x 121 grid at least
+    assert n > 2 * 9 * 121 * 241 * 8
+    (g32, m32, keep32), _ = _small(precision=hlbm.FP32_SHIFTED)
+    assert hlbm.workspace_size(g32, m32, 0.0, w.tau_s) < n
+
+
+def test_validate_errors(lib):
+    (g, m, keep), w = _small()
+    assert hlbm.validate(g, m, 0.0, 0.5) == -3                 # tau <= 1/2
+    assert hlbm.validate(g, m, 0.0, 0.0) == -3                 # neither Re nor tau
+    assert hlbm.validate(g, m, 123.0, w.tau_s) == -3           # Re and tau disagree
+    # clockwise triangle
+    tri = w.mesh_tri.copy()
+    tri[5, 1], tri[5, 2] = tri[5, 2], tri[5, 1]
+    g2, m2, k2 = hlbm.structs_from_workload(w, mesh_tri=tri)
+    assert hlbm.validate(g2, m2, 0.0, w.tau_s) == -2
+    assert "counter-clockwise" in hlbm.last_error()
+    # inner ellipse reaching past the mesh: structured interpolation node outside the mesh
+    g3, m3, k3 = hlbm.structs_from_workload(w, inner_ellipse=(100.0, 60.0, 80.0, 50.0))
+    assert hlbm.validate(g3, m3, 0.0, w.tau_s) == -2
+    # mesh interpolation node whose 3x3 donors fall inside the inactive region
+    g4, m4, k4 = hlbm.structs_from_workload(w, inner_ellipse=(100.0, 60.0, 71.0, 51.0))
+    assert hlbm.validate(g4, m4, 0.0, w.tau_s) == -2
+    # odd box size / box outside its parent
+    g5, m5, k5 = hlbm.make_structs(64, 32, [(4, 4, 31, 20)], periodic=True)
+    assert hlbm.validate(g5, m5, 0.0, 0.6) == -2
+    g6, m6, k6 = hlbm.make_structs(64, 32, [(40, 4, 60, 20)], periodic=True)
+    assert hlbm.validate(g6, m6, 0.0, 0.6) == -2
+    g7, m7, k7 = hlbm.make_structs(64, 32, [(8, 4, 40, 20)], periodic=True)
+    assert hlbm.validate(g7, m7, 0.0, 0.6) == 0
+
+
+def test_validate_bad_enums(lib):
+    (g, m, keep), w = _small(precision=7)
+    assert hlbm.validate(g, m, 0.0, w.tau_s) == -1
+
+
+def test_workloads_validate(lib):
+    """Every preset passes host validation (stencils, boxes, inner ellipse)."""
+    for name in ("naca_re100_c40", "naca_re1000_c128", "naca_re1e4_c256", "naca_re1000_c128_bumps"):
+        w = W.PRESETS[name]()
+        g, m, keep = hlbm.structs_from_workload(w)
+        assert hlbm.validate(g, m, 0.0, w.tau_s) == 0, (name, hlbm.last_error())
+
+
+def test_strouhal_of_sinusoid():
+    """Strouhal estimator on a synthetic lift signal of known period."""
+    period = 1234.5
+    t = np.arange(40000)
+    cl = 0.3 + 0.2 * np.sin(2 * np.pi * t / period + 0.4)
+    st = hlbm.strouhal(cl, chord=128.0, u_inf=0.05)
+    assert abs(st - 128.0 / (0.05 * period)) < 1e-6 * st
+    assert math.isnan(hlbm.strouhal(np.full(100, 0.1), 128.0, 0.05))

@@ -1,0 +1,208 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 CPU oracle.
+
+FP64 bar: infinity-norm relative difference of the full state <= 1e-11
+(populations of every level and of the mesh) and drag/lift histories within
+1e-10 absolute.  FP32-shifted bar: time-averaged C_D and C_L within 1e-4
+relative of FP64 (absolute on C_L when it vanishes by symmetry).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from flowfields import feq_field, taylor_green
+from oracle import oracle as O
+from paper_2006_10487_amd import hlbm, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def compare(sim, ref, n_levels, mesh=True):
+    out = {}
+    for l in range(n_levels):
+        out[f"level{l}"] = rel(sim.get_state(l), ref.get_level(l))
+    if mesh:
+        out["mesh"] = rel(sim.get_state(hlbm.PART_MESH), ref.get_mesh())
+        cd, cl = sim.history()
+        cdr, clr = ref.history()
+        out["cd"] = float(np.abs(cd - cdr).max())
+        out["cl"] = float(np.abs(cl - clr).max())
+    print("parity:", out, flush=True)
+    return out
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hlbm.lib()
+
+
+def test_small_fp64_short():
+    w = W.naca_re100_c40()
+    sim = hlbm.HLBM.from_workload(w)
+    ref = O.Oracle.from_workload(w)
+    assert sim.info.n_sub == ref.n_sub and sim.info.n_interp_struct == ref.n_sint
+    assert sim.info.n_interp_mesh == ref.n_uint and sim.info.n_fallback == ref.n_fallback
+    for n in (1, 9):
+        sim.step(n)
+        ref.step(n)
+        e = compare(sim, ref, 1)
+        assert max(e["level0"], e["mesh"]) < TOL and max(e["cd"], e["cl"]) < 1e-10
+
+
+def test_small_fp64_1000_steps():
+    """The headline FP64 gate: state after 1000 steps within 1e-11 of the oracle."""
+    w = W.naca_re100_c40()
+    sim = hlbm.HLBM.from_workload(w)
+    ref = O.Oracle.from_workload(w)
+    sim.step(1000)
+    ref.step(1000)
+    e = compare(sim, ref, 1)
+    assert e["level0"] < TOL and e["mesh"] < TOL
+    assert e["cd"] < 1e-10 and e["cl"] < 1e-10
+
+
+@pytest.mark.parametrize("aoa_deg", [5.0, -12.0])
+def test_small_fp64_incidence_linear_interp(aoa_deg):
+    """Rotated free stream and the linear (barycentric / bilinear) coupling stencils."""
+    w = W.naca_re100_c40(aoa_deg)
+    sim = hlbm.HLBM.from_workload(w, interp=hlbm.INTERP_LINEAR)
+    ref = O.Oracle.from_workload(w, interp="linear")
+    sim.step(200)
+    ref.step(200)
+    e = compare(sim, ref, 1)
+    assert max(e["level0"], e["mesh"]) < TOL and max(e["cd"], e["cl"]) < 1e-10
+
+
+def _tg_pair(L, tau, u0, patches=(), mesh=None, ein=None):
+    kw = {}
+    if mesh is not None:
+        kw = dict(mesh_xy=mesh[0], mesh_tri=mesh[1], mesh_kind=mesh[2], inner_ellipse=ein)
+    ref = O.Oracle(nx_cells=L, ny_cells=L, periodic=True, tau_s=tau, u_inf=u0, patches=patches, **kw)
+    g, m, keep = hlbm.make_structs(L, L, patches, periodic=True, u_inf=u0, **kw)
+    sim = hlbm.HLBM(g, m, tau=tau, keep=keep)
+    nlev = ref.n_levels
+    length = L * 2 ** (nlev - 1)
+    nu = (tau - 0.5) / 3
+    ox = oy = 0.0
+    sp = 2 ** (nlev - 1)
+    for l in range(nlev):
+        if l > 0:
+            ox, oy = ox + patches[l - 1][0] * sp, oy + patches[l - 1][1] * sp
+            sp //= 2
+        ny, nx = ref.level_shape[l]
+        XX, YY = np.meshgrid(ox + np.arange(nx) * sp, oy + np.arange(ny) * sp)
+        f = feq_field(O.equilibrium, *taylor_green(XX, YY, length, u0, nu, 0.0))
+        ref.set_level(l, f)
+        sim.set_state(l, f)
+    if mesh is not None:
+        xy = mesh[0]
+        f = feq_field(O.equilibrium, *taylor_green(xy[:, 0], xy[:, 1], length, u0, nu, 0.0))
+        ref.set_mesh(f)
+        sim.set_state(hlbm.PART_MESH, f)
+    return sim, ref
+
+
+def test_periodic_refined_taylor_green():
+    """Coarse <-> fine transfer and state import on a periodic grid with two nested boxes."""
+    sim, ref = _tg_pair(32, 0.7, 0.02, patches=[(6, 6, 40, 40), (6, 6, 24, 24)])
+    for n in (4, 60):
+        sim.step(n)
+        ref.step(n)
+        e = compare(sim, ref, 3, mesh=False)
+        assert max(e.values()) < TOL
+
+
+def test_hybrid_taylor_green_mesh_patch():
+    """Both coupling directions (eqs. (4)-(9)) and the FV update without walls."""
+    mesh = W.rect_patch_mesh(16.2, 16.2, 40, 40, 0.8, jitter=0.2, seed=1)
+    sim, ref = _tg_pair(64, 0.56, 0.01, mesh=mesh, ein=(32.2, 32.2, 11.0, 11.0))
+    sim.step(100)
+    ref.step(100)
+    e = compare(sim, ref, 1)
+    assert max(e["level0"], e["mesh"]) < TOL
+
+
+def test_refined_naca_fp64_short():
+    """Re = 1000, c = 128 geometry: base grid + one box + 512 x 64 mesh, 8 finest steps."""
+    w = W.naca_re1000_c128(10.0)
+    sim = hlbm.HLBM.from_workload(w)
+    ref = O.Oracle.from_workload(w)
+    sim.step(8)
+    ref.step(8)
+    e = compare(sim, ref, 2)
+    assert max(e["level0"], e["level1"], e["mesh"]) < TOL
+    assert max(e["cd"], e["cl"]) < 1e-10
+
+
+def test_two_box_naca_fp64_short():
+    """Re = 1e4, c = 256 geometry: two nested boxes, 1024 x 128 mesh, 326 sub-steps, 4 finest steps."""
+    w = W.naca_re1e4_c256()
+    sim = hlbm.HLBM.from_workload(w)
+    ref = O.Oracle.from_workload(w)
+    sim.step(4)
+    ref.step(4)
+    e = compare(sim, ref, 3)
+    assert max(e["level0"], e["level1"], e["level2"], e["mesh"]) < TOL
+    assert max(e["cd"], e["cl"]) < 1e-10
+
+
+def test_determinism_and_resume():
+    w = W.naca_re100_c40(3.0)
+    a = hlbm.HLBM.from_workload(w)
+    b = hlbm.HLBM.from_workload(w)
+    a.step(100)
+    b.step(60)
+    state = [b.get_state(0), b.get_state(hlbm.PART_MESH)]
+    c = hlbm.HLBM.from_workload(w)
+    c.set_state(0, state[0])
+    c.set_state(hlbm.PART_MESH, state[1])
+    b.step(40)
+    c.step(40)
+    for part in (0, hlbm.PART_MESH):
+        assert np.array_equal(a.get_state(part), b.get_state(part))
+        assert np.array_equal(a.get_state(part), c.get_state(part))
+
+
+def test_fp32_shifted_forces_small():
+    """FP32 shifted populations, FP64 forces: time-averaged C_D, C_L vs the FP64 oracle."""
+    w = W.naca_re100_c40(6.0)
+    steps = 1500
+    sim = hlbm.HLBM.from_workload(w, precision=hlbm.FP32_SHIFTED)
+    ref = O.Oracle.from_workload(w)
+    sim.step(steps)
+    ref.step(steps)
+    cd, cl = sim.history()
+    cdr, clr = ref.history()
+    win = slice(steps // 2, steps)
+    dcd = abs(cd[win].mean() - cdr[win].mean()) / abs(cdr[win].mean())
+    dcl = abs(cl[win].mean() - clr[win].mean()) / max(abs(clr[win].mean()), cdr[win].mean())
+    print(f"fp32: Cd {cd[win].mean():.6f} vs {cdr[win].mean():.6f} ({dcd:.2e}); "
+          f"Cl {cl[win].mean():.6f} vs {clr[win].mean():.6f} ({dcl:.2e})", flush=True)
+    assert dcd < 1e-4 and dcl < 1e-4
+    f32 = sim.get_state(hlbm.PART_MESH)
+    assert rel(f32, ref.get_mesh()) < 1e-5
+
+
+def test_nonfinite_detection():
+    w = W.naca_re100_c40()
+    sim = hlbm.HLBM.from_workload(w, check_every=2)
+    sim.step(2)
+    m = sim.get_state(hlbm.PART_MESH)
+    m[3, 5] = np.nan
+    sim.set_state(0, sim.get_state(0))
+    sim.set_state(hlbm.PART_MESH, m)
+    with pytest.raises(hlbm.HLBMError) as ei:
+        sim.step(4)
+    assert ei.value.code == -5
+    with pytest.raises(hlbm.HLBMError) as ei:
+        sim.step(2)
+    assert ei.value.code == -6
