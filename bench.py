@@ -37,50 +37,63 @@ def run_precision(w, precision, steps, warmup, hlbm, torch):
     info = sim.info
     sim.step(per * warmup)
     torch.cuda.synchronize()
-    sim.profile(True)
-    sim.profile_read()
-    torch.cuda.synchronize()
     progress("timed region")
     t0 = time.perf_counter()
     sim.step(per * steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = sim.profile_read()
     progress(f"timed {steps} steps in {t1 - t0:.3f} s")
-    sim.profile(False)
-    # unprofiled pass of the same length (launch overhead of the event pairs excluded)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    # per-kernel breakdown: the same number of steps with every launch
+    # bracketed by HIP events (the brackets add launch gaps; not used for value)
+    sim.profile(True)
+    sim.profile_read()
     sim.step(per * steps)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
+    prof = sim.profile_read()
+    sim.profile(False)
     cd, cl = sim.history(sim.t - per * (warmup + 2 * steps), sim.t)
+    # back-to-back launches of single kernels (pure kernel time per launch)
+    pure = {"fv_substep": sim.kernel_bench("fv_substep", 400) if info.n_mesh_nodes else None}
+    for l in range(info.n_levels):
+        pure[f"collide_l{l}"] = sim.kernel_bench(f"collide_l{l}", 20)
+    progress("kernel timings done")
     struct_updates = sum(int(info.active_nodes[l]) << l for l in range(info.n_levels))
     fv_updates = per * info.n_sub * int(info.n_mesh_nodes)
-    out = dict(sim=sim, info=info, prof=prof, t_prof=t1 - t0, t_plain=t3 - t2,
-               struct_updates=struct_updates, fv_updates=fv_updates, cd=cd, cl=cl)
-    return out
+    return dict(sim=sim, info=info, prof=prof, pure=pure, t=t1 - t0,
+                struct_updates=struct_updates, fv_updates=fv_updates, cd=cd, cl=cl)
 
 
-def kernel_table(r, steps):
+def kernel_bytes(info, k):
+    if k.startswith("collide_l"):
+        return int(info.k1_bytes[int(k[-1])])
+    if k == "fv_substep":
+        return int(info.fv_bytes)
+    return None
+
+
+def kernel_table(r):
     info = r["info"]
     rows = {}
     for k, (ms, n) in r["prof"].items():
         if n == 0:
             continue
-        if k.startswith("collide_l"):
-            by = int(info.k1_bytes[int(k[-1])])
-        elif k == "fv_substep":
-            by = int(info.fv_bytes)
-        else:
-            by = None
+        by = kernel_bytes(info, k)
         avg_us = 1e3 * ms / n
-        rows[k] = {"launches": n, "avg_us": round(avg_us, 3), "share": None,
-                   "alg_bytes": by, "gbs": round(by / (avg_us * 1e-6) / 1e9, 1) if by else None}
-    tot = sum(v["avg_us"] * v["launches"] for v in rows.values())
+        rows[k] = {"launches": n, "event_avg_us": round(avg_us, 3), "share": None, "alg_bytes": by}
+        if k in r["pure"] and r["pure"][k]:
+            pu = 1e3 * r["pure"][k]
+            rows[k]["avg_us"] = round(pu, 3)
+            rows[k]["gbs"] = round(by / (pu * 1e-6) / 1e9, 1)
+    tot = sum(v["event_avg_us"] * v["launches"] for v in rows.values())
     for v in rows.values():
-        v["share"] = round(v["avg_us"] * v["launches"] / tot, 4)
+        v["share"] = round(v["event_avg_us"] * v["launches"] / tot, 4)
     return rows
+
+
+def roofline(rows, k, note):
+    v = rows[k]
+    return {"bound": "hbm", "kernel": k, "achieved": v["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(v["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "alg_bytes_per_launch": v["alg_bytes"], "avg_launch_us": v["avg_us"], "note": note}
 
 
 def cpu_baseline(w, base_steps):
@@ -105,6 +118,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=1, help="base steps of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB five times (calibrates HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (--gpus {a.gpus} requested); "
@@ -116,8 +131,8 @@ def main():
     w = workloads.PRESETS[a.workload]()
     per = 2 ** w.n_refine
     r32 = run_precision(w, hlbm.FP32_SHIFTED, a.steps, a.warmup, hlbm, torch)
-    k32 = kernel_table(r32, a.steps)
-    t32 = r32["t_prof"]
+    k32 = kernel_table(r32)
+    t32 = r32["t"]
     value = r32["struct_updates"] * a.steps / t32 / 1e6
     res = {
         "metric": METRIC,
@@ -137,25 +152,18 @@ def main():
                    "re": w.re, "aoa_deg": w.aoa_deg, "chord": w.chord,
                    "finest_steps_per_step": per, "precision": "fp32_shifted_fp64_forces"},
     }
-    # dominant kernel and roofline
-    dom = max(k32, key=lambda k: k32[k]["avg_us"] * k32[k]["launches"])
-    k1 = k32["collide_l0"]
-    ach = k1["gbs"]
-    res["roofline"] = {"bound": "hbm", "kernel": "collide_l0 (base-level fused stream-collide)",
-                       "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                       "alg_bytes_per_launch": k1["alg_bytes"], "avg_launch_us": k1["avg_us"]}
-    res["dominant_kernel"] = dom
+    dom = max(k32, key=lambda k: k32[k]["share"])
+    res["roofline"] = roofline(k32, dom, "dominant kernel by time share; algorithmic bytes per launch over "
+                                         "the mean of back-to-back launches timed with HIP events")
+    res["roofline_base_grid"] = roofline(k32, "collide_l0", "base-level fused stream-collide (72 B per node)")
     res["kernels_fp32"] = k32
     res["fv_msubsteps_per_s"] = round(r32["fv_updates"] * a.steps / t32 / 1e6, 1)
-    res["ms_per_step_unprofiled"] = round(1e3 * r32["t_plain"] / a.steps, 4)
     if not a.no_fp64:
         r64 = run_precision(w, hlbm.FP64, a.steps, a.warmup, hlbm, torch)
-        k64 = kernel_table(r64, a.steps)
-        res["fp64"] = {"value": round(r64["struct_updates"] * a.steps / r64["t_prof"] / 1e6, 1),
-                       "ms_per_step": round(1e3 * r64["t_prof"] / a.steps, 4),
-                       "collide_l0_gbs": k64["collide_l0"]["gbs"],
-                       "collide_l0_frac": round(k64["collide_l0"]["gbs"] / HBM_PEAK_GBS, 4),
+        k64 = kernel_table(r64)
+        res["fp64"] = {"value": round(r64["struct_updates"] * a.steps / r64["t"] / 1e6, 1),
+                       "ms_per_step": round(1e3 * r64["t"] / a.steps, 4),
+                       "roofline_base_grid": roofline(k64, "collide_l0", "FP64, 144 B per node"),
                        "kernels": k64}
         n = min(len(r32["cd"]), len(r64["cd"]))
         cd32, cd64 = r32["cd"][:n], r64["cd"][:n]
@@ -167,6 +175,15 @@ def main():
             "cl_rel_err_last": float(abs(cl32[-1] - cl64[-1]) / max(abs(cl64[-1]), abs(cd64[-1]))),
         }
         r64["sim"].close()
+    if a.copy_probe:
+        n = a.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        res["copy_probe_bytes_each_way"] = n * 4
+        del src, dst
     res["adjoint_over_forward"] = None
     if not a.no_cpu:
         o, tc = cpu_baseline(w, a.cpu_steps)

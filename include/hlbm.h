@@ -163,6 +163,14 @@ int hlbm_profile(hlbm_ctx *ctx, int enable);
  * (arrays of HLBM_K_COUNT entries); then resets the counters. */
 int hlbm_profile_read(hlbm_ctx *ctx, double *ms, int64_t *launches);
 
+/* Instrumentation: launches n times back to back the kernel of class kclass
+ * (HLBM_K_COLLIDE_L0 + l or HLBM_K_FV) on the context's buffers and returns
+ * the mean time per launch from one pair of HIP events around the batch.
+ * The launches advance that part of the state on its own, so afterwards the
+ * state is not a solution of the coupled scheme: benchmark use only (restore
+ * with hlbm_set_state or create a new context).  Syncs. */
+int hlbm_kernel_bench(hlbm_ctx *ctx, int kclass, int n, double *avg_ms);
+
 /* Text of the last error of ctx (or of the last failed create when ctx is NULL). */
 const char *hlbm_last_error(const hlbm_ctx *ctx);
 

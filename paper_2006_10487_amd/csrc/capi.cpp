@@ -140,7 +140,7 @@ void setup_views(hlbm_ctx* c) {
     m.nn = p.nn;
     m.n_wall = p.n_wall;
     m.n_core = p.n_core;
-    m.rowptr = reinterpret_cast<const int32_t*>(c->ws + p.off.rowptr);
+    m.ell_width = p.ell_width;
     m.edges = c->ws + p.off.edges;
     m.dt = p.dt_u;
     m.dt_over_tau = p.dt_u / p.tau_u;
@@ -161,20 +161,24 @@ int upload_tables(hlbm_ctx* c) {
     keep.push_back(real(p.sint_w));
     rc |= upload(c, p.off.sint_w, keep.back().data(), keep.back().size());
     if (p.has_mesh) {
-        rc |= upload(c, p.off.rowptr, p.rowptr.data(), p.rowptr.size() * 4);
-        const size_t nnz = p.col.size();
-        std::vector<char> rec(nnz * (f64 ? 32 : 16), 0);
-        for (size_t z = 0; z < nnz; ++z) {
-            char* r = rec.data() + z * (f64 ? 32 : 16);
-            std::memcpy(r, &p.col[z], 4);
-            if (f64) {
-                const double v[3] = {p.gx[z], p.gy[z], p.cc[z]};
-                std::memcpy(r + 8, v, 24);
-            } else {
-                const float v[3] = {float(p.gx[z]), float(p.gy[z]), float(p.cc[z])};
-                std::memcpy(r + 4, v, 12);
+        // ELL neighbour table: slot z of node P at z * nn + P; unused slots col = -1
+        const size_t W = size_t(p.ell_width), rs = f64 ? 32 : 16;
+        std::vector<char> rec(W * p.nn * rs, 0);
+        for (int P = 0; P < p.nn; ++P)
+            for (size_t z = 0; z < W; ++z) {
+                char* r = rec.data() + (z * p.nn + P) * rs;
+                const int zz = p.rowptr[P] + int(z);
+                const int32_t col = zz < p.rowptr[P + 1] ? p.col[zz] : -1;
+                std::memcpy(r, &col, 4);
+                if (col < 0) continue;
+                if (f64) {
+                    const double v[3] = {p.gx[zz], p.gy[zz], p.cc[zz]};
+                    std::memcpy(r + 8, v, 24);
+                } else {
+                    const float v[3] = {float(p.gx[zz]), float(p.gy[zz]), float(p.cc[zz])};
+                    std::memcpy(r + 4, v, 12);
+                }
             }
-        }
         keep.push_back(std::move(rec));
         rc |= upload(c, p.off.edges, keep.back().data(), keep.back().size());
         rc |= upload(c, p.off.wedge, p.wedge.data(), p.wedge.size() * 4);
@@ -513,8 +517,8 @@ int hlbm_info(hlbm_ctx* c, hlbm_info_t* o) {
     o->n_fallback = p.n_fallback;
     o->n_wall_edges = int(p.wedge.size() / 2);
     o->nnz = int(p.col.size());
-    // FV sub-step: populations in and out, CSR records, row pointers
-    o->fv_bytes = int64_t(p.nn) * 2 * kQ * E + int64_t(p.col.size()) * (E == 8 ? 32 : 16) + int64_t(p.nn + 1) * 4;
+    // FV sub-step: node records (populations + moments) in and out, CSR records, row pointers
+    o->fv_bytes = int64_t(p.nn) * 2 * kRec * E + int64_t(p.col.size()) * (E == 8 ? 32 : 16);
     o->bytes_per_finest_step = bytes / (int64_t(1) << p.L) + int64_t(p.n_sub) * o->fv_bytes;
     o->t = c->t;
     o->workspace_bytes = p.off.total;
@@ -542,6 +546,37 @@ int hlbm_profile_read(hlbm_ctx* c, double* ms, int64_t* launches) {
     }
     c->ev_pending.clear();
     return rc;
+}
+
+int hlbm_kernel_bench(hlbm_ctx* c, int kclass, int n, double* avg_ms) {
+    if (!c || !avg_ms || n <= 0) return HLBM_E_ARG;
+    const Plan& p = c->p;
+    const bool fv = kclass == HLBM_K_FV;
+    const int l = kclass - HLBM_K_COLLIDE_L0;
+    if (!fv && (l < 0 || l > p.L)) return set_err(c, HLBM_E_ARG, "unsupported kernel class");
+    if (fv && !p.has_mesh) return set_err(c, HLBM_E_ARG, "no mesh");
+    if (c->dirty) finish_import(c);
+    hipEvent_t a = take_event(c), b = take_event(c);
+    if (!a || !b) return set_err(c, HLBM_E_DEVICE, "hipEventCreate failed");
+    int rc = hip_check(c, hipEventRecord(a, c->s), "event");
+    for (int k = 0; k < n; ++k) {
+        if (fv) {
+            launch_fv_substep(p.precision, c->km, c->mesh(c->mesh_cur), c->mesh(1 - c->mesh_cur), c->prep(c->prep_t),
+                              c->prep(1 - c->prep_t), double(k % p.n_sub) / p.n_sub, c->s);
+            c->mesh_cur ^= 1;
+        } else {
+            launch_stream_collide(p.precision, c->kl[l], c->lev(l, c->cur[l]), c->lev(l, 1 - c->cur[l]), c->s);
+            c->cur[l] ^= 1;
+        }
+    }
+    rc |= hip_check(c, hipEventRecord(b, c->s), "event");
+    rc |= hip_check(c, hipEventSynchronize(b), "event");
+    float ms = 0.0f;
+    rc |= hip_check(c, hipEventElapsedTime(&ms, a, b), "event");
+    c->ev_pool.push_back(a);
+    c->ev_pool.push_back(b);
+    *avg_ms = double(ms) / n;
+    return rc ? HLBM_E_DEVICE : HLBM_OK;
 }
 
 const char* hlbm_last_error(const hlbm_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }

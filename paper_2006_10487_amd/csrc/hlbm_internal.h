@@ -22,6 +22,7 @@ constexpr int kQ = 9;
 constexpr int kSDon = 8;     // donors of a structured interpolation node (two 6-node stencils on an edge)
 constexpr int kUDon = 9;     // donors of a mesh interpolation node (3 x 3 block)
 constexpr int kMacro = 12;   // (rho or rho - rho0, ux, uy, f^neq[9])
+constexpr int kRec = 12;     // mesh node record: f_0..f_8, rho (or rho - rho0), ux, uy
 
 struct LevelPlan {
     int nx = 0, ny = 0, pitch = 0;  // nodes, row pitch in elements
@@ -56,7 +57,8 @@ struct Plan {
     // mesh in plan order [wall | interior | interpolation]
     int nn = 0, n_wall = 0, n_core = 0, n_int = 0, nt = 0;
     std::vector<int32_t> perm;           // perm[new] = caller index
-    std::vector<int32_t> rowptr, col;    // CSR, self entry included
+    std::vector<int32_t> rowptr, col;    // CSR, self entry first
+    int ell_width = 8;                   // slots per node of the device neighbour table
     std::vector<double> gx, gy, cc;      // G_Pk (x, y) and C_Pk
     std::vector<int32_t> wedge;          // wall edges (P, Q) in plan order, fluid on the left
     std::vector<double> wnorm;           // outward normal times length of each wall edge
@@ -96,8 +98,8 @@ struct KLevel {
 
 struct KMesh {
     int nn, n_wall, n_core;
-    const int32_t* rowptr;
-    const void* edges;               // packed (col, gx, gy, c) records
+    int ell_width;                   // neighbour slots per node (8 or 16)
+    const void* edges;               // ELL (col, gx, gy, c) records, slot-major
     double dt, dt_over_tau;          // Delta t_u, Delta t_u / tau_u
     double star_neq;                 // 1 - 1 / (2 tau_s), eq. (5)-(6)
     int wall_bc;

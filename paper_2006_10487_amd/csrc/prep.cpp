@@ -576,6 +576,10 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
             }
             p.rowptr[P + 1] = int(p.col.size());
         }
+        int maxrow = 0;
+        for (int P = 0; P < nn; ++P) maxrow = std::max(maxrow, p.rowptr[P + 1] - p.rowptr[P]);
+        if (maxrow > 16) return fail(err, HLBM_E_GEOMETRY, "a mesh node has %d neighbours (at most 15 supported)", maxrow - 1);
+        p.ell_width = maxrow <= 8 ? 8 : 16;
         // wall edges: boundary edges with both ends on the wall
         for (const auto& be : bnd)
             if (m->kind[be[0]] == 1 && m->kind[be[1]] == 1) {
@@ -681,10 +685,10 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
     p.off.sint_don = take(ns * kSDon * 4);
     p.off.sint_w = take(ns * kSDon * E);
     const size_t nnp = size_t(std::max(p.nn, 1));
-    p.off.mesh[0] = take(kQ * nnp * E);
-    p.off.mesh[1] = take(kQ * nnp * E);
+    p.off.mesh[0] = take(kRec * nnp * E);
+    p.off.mesh[1] = take(kRec * nnp * E);
     p.off.rowptr = take((nnp + 1) * 4);
-    p.off.edges = take(p.col.size() * (E == 8 ? 32 : 16));
+    p.off.edges = take(size_t(p.ell_width) * nnp * (E == 8 ? 32 : 16));
     p.off.wedge = take(p.wedge.size() * 4);
     p.off.wnorm = take(p.wnorm.size() * 8);
     p.off.prep[0] = take(size_t(std::max(p.n_int, 1)) * kMacro * E);

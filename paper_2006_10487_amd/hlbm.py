@@ -26,7 +26,7 @@ PART_MESH = 100
 
 EXPORTED = ["hlbm_validate", "hlbm_workspace_size", "hlbm_create", "hlbm_step", "hlbm_forces",
             "hlbm_force_history", "hlbm_get_state", "hlbm_set_state", "hlbm_info", "hlbm_last_error",
-            "hlbm_destroy", "hlbm_profile", "hlbm_profile_read"]
+            "hlbm_destroy", "hlbm_profile", "hlbm_profile_read", "hlbm_kernel_bench"]
 KERNEL_CLASSES = ["collide_l0", "collide_l1", "collide_l2", "collide_l3", "coarse_to_fine",
                   "fine_to_coarse", "mesh_to_struct", "struct_to_mesh", "fv_substep", "wall_force"]
 
@@ -96,6 +96,7 @@ def lib():
         L.hlbm_destroy.restype = None
         L.hlbm_profile.argtypes = [P, C.c_int]
         L.hlbm_profile_read.argtypes = [P, P, P]
+        L.hlbm_kernel_bench.argtypes = [P, C.c_int, C.c_int, C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -258,6 +259,14 @@ class HLBM:
         n = np.zeros(len(KERNEL_CLASSES), np.int64)
         self._check(lib().hlbm_profile_read(self._ctx, _np_ptr(ms), _np_ptr(n)))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def kernel_bench(self, kclass: str, n: int) -> float:
+        """Mean ms per launch of n back-to-back launches of one kernel class.
+
+        Benchmark only: the state afterwards is not a solution of the scheme."""
+        ms = C.c_double()
+        self._check(lib().hlbm_kernel_bench(self._ctx, KERNEL_CLASSES.index(kclass), int(n), C.byref(ms)))
+        return ms.value
 
     def synchronize(self):
         self.stream.synchronize()
