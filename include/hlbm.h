@@ -141,6 +141,34 @@ int hlbm_set_state(hlbm_ctx *ctx, int32_t part, const double *host, size_t count
 
 int hlbm_info(hlbm_ctx *ctx, hlbm_info_t *out);
 
+/* Objective for the discrete adjoint: a run of t_end finest steps from the
+ * initial state; J = mean over history entries h in [t0, t1) of
+ * w_cd C_D(h) + w_cl C_L(h).  The forward stores the state every ckpt_every
+ * steps in the objective workspace (revolve-style checkpointing); the reverse
+ * sweep recomputes each segment from its checkpoint. */
+typedef struct {
+    int64_t t_end, t0, t1, ckpt_every;
+    double w_cd, w_cl;
+} hlbm_objective;
+
+/* Device bytes of the objective workspace (checkpoints, one recomputed
+ * segment, the adjoint fields and transposed tables).  Supported: FP64
+ * contexts with a single structured level (n_refine = 0) and a walled mesh;
+ * other contexts get HLBM_E_ARG. */
+int hlbm_objective_workspace_size(hlbm_ctx *ctx, const hlbm_objective *obj, size_t *bytes);
+
+/* Restarts the run from the initial state, advances obj->t_end finest steps,
+ * storing checkpoints in d_ckpt (device, 256-byte aligned, caller-owned), and
+ * returns J.  Syncs. */
+int hlbm_run_objective(hlbm_ctx *ctx, const hlbm_objective *obj, void *d_ckpt, size_t ckpt_bytes, double *J);
+
+/* Discrete adjoint of the last hlbm_run_objective: grad[0] = J_bar dJ/d aoa_rad,
+ * grad[1] = J_bar dJ/d tau (finest-level relaxation time; the number of FV
+ * sub-steps is held fixed).  Reverse mode over the forward kernels (eqs. (1)-(11)
+ * as implemented), FP64 accumulation, deterministic.  Leaves the context in a
+ * mid-run state: run the objective again before another adjoint.  Syncs. */
+int hlbm_adjoint(hlbm_ctx *ctx, double J_bar, double *grad);
+
 /* Kernel classes timed by hlbm_profile_read. */
 enum {
     HLBM_K_COLLIDE_L0 = 0,      /* collide-stream of level 0 (+1, +2, +3 for finer levels) */

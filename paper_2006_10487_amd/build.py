@@ -5,7 +5,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["csrc/kernels.hip", "csrc/prep.cpp", "csrc/capi.cpp"]
+SOURCES = ["csrc/kernels.hip", "csrc/prep.cpp", "csrc/capi.cpp", "csrc/adjoint.cpp"]
 OUT = os.path.join(HERE, "libhlbm.so")
 
 HIPCC_FLAGS = [

@@ -24,37 +24,7 @@
 
 using namespace hlbm;
 
-struct hlbm_ctx {
-    Plan p;
-    hipStream_t s = nullptr;
-    char* ws = nullptr;
-    size_t ws_bytes = 0;
-    int cur[4] = {0, 0, 0, 0};   // buffer holding the current post-collision state
-    int side_t[4] = {0, 0, 0, 0};  // side slot holding the parent's (rho, u, f^neq) at the parent's time
-    int mesh_cur = 0;
-    int prep_t = 0;               // prep slot holding the mesh interpolation values at time t
-    int64_t t = 0;
-    int64_t last_check = 0;
-    bool poisoned = false;
-    bool dirty = false;           // an import must be finished before stepping
-    std::string err;
-    KLevel kl[4];
-    KMesh km;
-    std::vector<double> tmp;
-    // instrumentation
-    bool prof = false;
-    std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
-
-    void* lev(int l, int b) { return ws + p.off.lev[l][b]; }
-    void* side(int l, int b) { return ws + p.off.side[l][b]; }
-    void* mesh(int b) { return ws + p.off.mesh[b]; }
-    void* prep(int b) { return ws + p.off.prep[b]; }
-    double* hist() { return reinterpret_cast<double*>(ws + p.off.hist); }
-    double* stage() { return reinterpret_cast<double*>(ws + p.off.stage); }
-};
-
-namespace {
+namespace hlbm {
 
 std::string g_create_err;
 
@@ -214,6 +184,43 @@ void finish_import(hlbm_ctx* c) {
     c->dirty = false;
 }
 
+
+// Initial state: f^eq(rho0, u_inf) on every level and mesh node, f^eq(rho0, 0)
+// at wall nodes; time and history restart at 0.
+int reset_initial_state_checked(hlbm_ctx* c) {
+    const Plan& p = c->p;
+    for (int l = 0; l < 4; ++l) c->cur[l] = 0, c->side_t[l] = 0;
+    c->mesh_cur = 0;
+    c->prep_t = 0;
+    c->t = 0;
+    c->last_check = 0;
+    c->poisoned = false;
+    const double ux = p.u_inf * std::cos(p.aoa), uy = p.u_inf * std::sin(p.aoa);
+    for (int l = 0; l <= p.L; ++l) launch_fill_uniform(p.precision, c->lev(l, 1), c->kl[l], p.rho0, ux, uy, c->s);
+    int rc = HLBM_OK;
+    if (p.has_mesh) {
+        std::vector<double> f0(size_t(kQ) * p.nn);
+        const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+        const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+        for (int P = 0; P < p.nn; ++P) {
+            const bool wall = P < p.n_wall && p.wall_bc;
+            const double u = wall ? 0.0 : ux, v = wall ? 0.0 : uy;
+            for (int q = 0; q < 9; ++q) {
+                const double cu = cx[q] * u + cy[q] * v;
+                f0[size_t(q) * p.nn + P] = w[q] * p.rho0 * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (u * u + v * v));
+            }
+        }
+        rc = upload(c, p.off.stage, f0.data(), f0.size() * 8);
+        launch_mesh_convert(p.precision, p.nn, c->stage(), c->mesh(0), 1, p.rho0, c->s);
+        rc |= hip_check(c, hipStreamSynchronize(c->s), "init");
+        if (rc) return HLBM_E_DEVICE;
+    }
+    finish_import(c);
+    return hip_check(c, hipGetLastError(), "kernel launch");
+}
+
+void reset_initial_state(hlbm_ctx* c) { (void)reset_initial_state_checked(c); }
+
 void finest_step(hlbm_ctx* c) {
     const Plan& p = c->p;
     const int pr = p.precision, L = p.L;
@@ -339,33 +346,7 @@ int hlbm_create(const hlbm_grid* grid, const hlbm_mesh* mesh, double Re, double 
         delete c;
         return rc;
     }
-    // initial state: f^eq(rho0, u_inf) on every level and mesh node, f^eq(rho0, 0) at walls
-    const Plan& p = c->p;
-    const double ux = p.u_inf * std::cos(p.aoa), uy = p.u_inf * std::sin(p.aoa);
-    for (int l = 0; l <= p.L; ++l) launch_fill_uniform(p.precision, c->lev(l, 1), c->kl[l], p.rho0, ux, uy, c->s);
-    if (p.has_mesh) {
-        std::vector<double> f0(size_t(kQ) * p.nn);
-        const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-        const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-        for (int P = 0; P < p.nn; ++P) {
-            const bool wall = P < p.n_wall && p.wall_bc;
-            const double u = wall ? 0.0 : ux, v = wall ? 0.0 : uy;
-            for (int q = 0; q < 9; ++q) {
-                const double cu = cx[q] * u + cy[q] * v;
-                f0[size_t(q) * p.nn + P] = w[q] * p.rho0 * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (u * u + v * v));
-            }
-        }
-        rc = upload(c, p.off.stage, f0.data(), f0.size() * 8);
-        launch_mesh_convert(p.precision, p.nn, c->stage(), c->mesh(0), 1, p.rho0, c->s);
-        rc |= hip_check(c, hipStreamSynchronize(c->s), "init");
-        if (rc) {
-            g_create_err = c->err;
-            delete c;
-            return HLBM_E_DEVICE;
-        }
-    }
-    finish_import(c);
-    rc = hip_check(c, hipGetLastError(), "kernel launch");
+    rc = reset_initial_state_checked(c);
     if (rc) {
         g_create_err = c->err;
         delete c;
@@ -586,6 +567,7 @@ void hlbm_destroy(hlbm_ctx* c) {
     if (!c->ev_pending.empty()) (void)hipStreamSynchronize(c->s);
     for (auto& e : c->ev_pending) c->ev_pool.push_back(e.second.first), c->ev_pool.push_back(e.second.second);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    adj_free(c->adj);
     delete c;
 }
 

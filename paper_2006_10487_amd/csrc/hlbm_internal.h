@@ -132,4 +132,86 @@ void launch_wall_force(int prec, const KMesh& M, const void* f, int n_edges, con
 void launch_mesh_convert(int prec, int nn, const double* in, void* out, int to_storage, double rho0,
                          hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// adjoint (FP64, single structured level)
+// ---------------------------------------------------------------------------
+
+struct KAdj {
+    KLevel L;                        // the structured level
+    KMesh M;                         // the mesh
+    const void* tedges;              // transposed neighbour table: slot z of node k = (P, G_Pk, C_Pk); slot 0 = (k, sum_{j!=k} G_kj, C_kk)
+    double dt, dtt, ddtt_dtau;       // Delta t_u, Delta t_u / tau_u, d(Delta t_u / tau_u)/d tau
+    double cst, dcst_dtau;           // 1 - 1/(2 tau), d/d tau
+    double omega, domega_dtau;       // 1 / tau, d/d tau
+    double phi, dphi_dtau;           // 2 (tau - 1)/(2 tau - 1), d/d tau
+    double uin_x, uin_y, duin_x, duin_y;  // inlet velocity and d/d alpha
+    double* partial;                 // per-block (d alpha, d tau) partial sums
+};
+
+void launch_zero(double* p, size_t n, hipStream_t s);
+void launch_adj_force(const KAdj& K, double* mbar, const double* vwall, double jx, double jy, hipStream_t s);
+void launch_adj_fv_a(const KAdj& K, const double* Mrec, const double* ybar, double* zbar, const double* prep0,
+                     const double* prep1, double theta, int pslot, hipStream_t s);
+void launch_adj_fv_b(const KAdj& K, const double* Mrec, const double* zbar, double* mbar, hipStream_t s);
+void launch_adj_fv_c(const KAdj& K, const double* zbar, const double* prep0, const double* prep1, double theta,
+                     double* p0bar, double* p1bar, int pslot, hipStream_t s);
+void launch_adj_collide(const KAdj& K, const double* A, const double* bbar, double* prebar, int pslot, hipStream_t s);
+void launch_adj_s2m(const KAdj& K, const double* A, int nd, const int32_t* node, const int32_t* ptr,
+                    const int32_t* slot, const double* w, const double* pbar, double* prebar, hipStream_t s);
+void launch_adj_bc(const KAdj& K, const double* A, double* prebar, int pslot, hipStream_t s);
+void launch_adj_push(const KAdj& K, const double* prebar, double* abar, hipStream_t s);
+void launch_adj_m2s_a(const KAdj& K, const double* Mrec, int n, const int32_t* node, const int32_t* don,
+                      const double* w, double* abar, double* m5bar, int pslot, hipStream_t s);
+void launch_adj_m2s_b(const KAdj& K, const double* Mrec, const int32_t* ptr, const int32_t* slot, const double* w,
+                      const double* m5bar, double* mbar, hipStream_t s);
+void launch_adj_alpha_state(const KAdj& K, const double* abar, const double* mbar, const double* dfeq,
+                            int pslot, hipStream_t s);
+void launch_reduce_partials(const double* partial, int n, double* acc, hipStream_t s);
+int adj_blocks_collide(const KLevel& L);
+int adj_blocks_nodes(int n);
+
+}  // namespace hlbm
+
+struct AdjState;
+struct hlbm_ctx {
+    hlbm::Plan p;
+    hipStream_t s = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    int cur[4] = {0, 0, 0, 0};   // buffer holding the current post-collision state
+    int side_t[4] = {0, 0, 0, 0};  // side slot holding the parent's (rho, u, f^neq) at the parent's time
+    int mesh_cur = 0;
+    int prep_t = 0;               // prep slot holding the mesh interpolation values at time t
+    int64_t t = 0;
+    int64_t last_check = 0;
+    bool poisoned = false;
+    bool dirty = false;           // an import must be finished before stepping
+    std::string err;
+    hlbm::KLevel kl[4];
+    hlbm::KMesh km;
+    std::vector<double> tmp;
+    // adjoint (objective run and reverse sweep)
+    AdjState* adj = nullptr;
+    // instrumentation
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+
+    void* lev(int l, int b) { return ws + p.off.lev[l][b]; }
+    void* side(int l, int b) { return ws + p.off.side[l][b]; }
+    void* mesh(int b) { return ws + p.off.mesh[b]; }
+    void* prep(int b) { return ws + p.off.prep[b]; }
+    double* hist() { return reinterpret_cast<double*>(ws + p.off.hist); }
+    double* stage() { return reinterpret_cast<double*>(ws + p.off.stage); }
+};
+
+
+namespace hlbm {
+void finish_import(hlbm_ctx* c);
+void finest_step(hlbm_ctx* c);
+void reset_initial_state(hlbm_ctx* c);
+hipEvent_t take_event(hlbm_ctx* c);
+void adj_free(AdjState* a);
+int hip_check(hlbm_ctx* c, hipError_t e, const char* what);
+int set_err(hlbm_ctx* c, int code, const std::string& msg);
 }  // namespace hlbm

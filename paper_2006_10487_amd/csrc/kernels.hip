@@ -744,3 +744,611 @@ void launch_mesh_convert(int prec, int nn, const double* in, void* out, int to_s
 }
 
 }  // namespace hlbm
+
+// ===========================================================================
+// Discrete adjoint of the single-level hybrid step (FP64).
+//
+// Reverse mode of the forward kernels above, kernel by kernel: every forward
+// scatter becomes a gather over a transposed table, so the adjoint is
+// deterministic and uses no atomics.  Parameter derivatives (angle of attack,
+// tau) are summed per block in a fixed tree order into `partial` slots and
+// reduced by one block at the end of each step.
+// ===========================================================================
+namespace hlbm {
+namespace {
+
+using D9 = double[9];
+
+// sum_q eb_q d feq_q(rho, u) / d(rho, u) for feq_q = w_q rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2)
+__device__ __forceinline__ void feq_adj(double rho, double ux, double uy, const D9& eb, double& rb, double& uxb,
+                                        double& uyb) {
+    const double uu = ux * ux + uy * uy;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const double cu = CX[q] * ux + CY[q] * uy, w = wgt<double>(q);
+        rb += eb[q] * w * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        uxb += eb[q] * w * rho * (3.0 * CX[q] + 9.0 * cu * CX[q] - 3.0 * ux);
+        uyb += eb[q] * w * rho * (3.0 * CY[q] + 9.0 * cu * CY[q] - 3.0 * uy);
+    }
+}
+
+// fb += adjoint of (rho, u) = (sum f, sum c f / sum f) for adjoints (rb, uxb, uyb)
+__device__ __forceinline__ void macro_adj(double rho, double ux, double uy, double rb, double uxb, double uyb, D9& fb) {
+    const double jxb = uxb / rho, jyb = uyb / rho, r2 = rb - (uxb * ux + uyb * uy) / rho;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fb[q] += r2 + jxb * CX[q] + jyb * CY[q];
+}
+
+__device__ __forceinline__ void macro64(const D9& f, double& rho, double& ux, double& uy) {
+    double s = 0, mx = 0, my = 0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        s += f[q];
+        mx += double(CX[q]) * f[q];
+        my += double(CY[q]) * f[q];
+    }
+    rho = s;
+    ux = mx / rho;
+    uy = my / rho;
+}
+
+// fb += adjoint of the map f -> (rho, ux, uy, f - feq(rho, u)) for adjoint a[12]
+__device__ __forceinline__ void macro_neq_adj(const D9& f, const double* a, D9& fb) {
+    double rho, ux, uy;
+    macro64(f, rho, ux, uy);
+    double rb = a[0], uxb = a[1], uyb = a[2];
+    D9 eb;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        fb[q] += a[3 + q];
+        eb[q] = -a[3 + q];
+    }
+    feq_adj(rho, ux, uy, eb, rb, uxb, uyb);
+    macro_adj(rho, ux, uy, rb, uxb, uyb, fb);
+}
+
+// fixed-order block sum of (a, b) written to partial[2 * (slot + blockIdx.x)]
+__device__ __forceinline__ void block_partial(double a, double b, double* partial, int slot) {
+    __shared__ double sa[256], sb[256];
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sa[threadIdx.x] += sa[threadIdx.x + h];
+            sb[threadIdx.x] += sb[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * (slot + blockIdx.x)] = sa[0];
+        partial[2 * (slot + blockIdx.x) + 1] = sb[0];
+    }
+}
+
+__global__ void k_zero(double* p, size_t n) {
+    const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = 0.0;
+}
+
+// Wall force, eqs. (10)-(11): d J / d f_q(P) = (c_q . j)(c_q . V_P), V_P = half the
+// wall normals of the two wall edges at P, j = drag/lift weights / normaliser.
+__global__ void k_adj_force(int n_wall, int nn, double* __restrict__ mbar, const double* __restrict__ V, double jx,
+                            double jy) {
+    const int P = blockIdx.x * blockDim.x + threadIdx.x;
+    if (P >= n_wall) return;
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        mbar[size_t(q) * nn + P] += (CX[q] * jx + CY[q] * jy) * (CX[q] * V[2 * P] + CY[q] * V[2 * P + 1]);
+}
+
+// star values of one interpolation slot at theta (FP64), with their inputs
+__device__ __forceinline__ void star64(const double* p0, const double* p1, double theta, double cst, double (&v)[12],
+                                       D9& fs, D9& ns) {
+#pragma unroll
+    for (int m = 0; m < 12; ++m) v[m] = (1.0 - theta) * p0[m] + theta * p1[m];
+    double feq[9];
+    equilibrium<double, false>(v[0], v[0], v[1], v[2], feq);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        ns[q] = cst * v[3 + q];
+        fs[q] = feq[q] + ns[q];
+    }
+}
+
+// FV sub-step adjoint, phase A (per pivot P): recompute the pre-reset update
+// fn_P from M^m, take the wall reset's transpose: zbar_P = R'(fn_P)^T ybar_P;
+// tau enters through Delta t_u / tau_u.
+__global__ __launch_bounds__(256) void k_adj_fv_a(const KAdj K, const double* __restrict__ fin,
+                                                  const double* __restrict__ ybar, double* __restrict__ zbar,
+                                                  const double* __restrict__ prep0, const double* __restrict__ prep1,
+                                                  double theta, int pslot) {
+    const KMesh& M = K.M;
+    const int P = blockIdx.x * blockDim.x + threadIdx.x;
+    double dtau = 0.0;
+    if (P < M.nn) {
+        const int nn = M.nn, W = M.ell_width;
+        const bool pivot_interp = P >= M.n_core;
+        const EdgeRec<double>* E = reinterpret_cast<const EdgeRec<double>*>(M.edges);
+        double base[9], ss[9], sc[9];
+        for (int z = 0; z < W; ++z) {
+            const EdgeRec<double> e = E[size_t(z) * nn + P];
+            const int k = e.col;
+            if (k < 0) continue;
+            double f[9], nq[9];
+            if (pivot_interp && k >= M.n_core) {
+                double v[12];
+                const size_t sl = size_t(k - M.n_core) * kMacro;
+                star64(prep0 + sl, prep1 + sl, theta, K.cst, v, f, nq);
+            } else {
+                double m0, ux, uy, feq[9];
+                load_rec(fin + size_t(k) * kRec, f, m0, ux, uy);
+                equilibrium<double, false>(m0, m0, ux, uy, feq);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) nq[q] = f[q] - feq[q];
+            }
+            if (z == 0) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) base[q] = f[q], ss[q] = 0.0, sc[q] = e.c * nq[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    ss[q] += (CX[q] * e.gx + CY[q] * e.gy) * (f[q] - base[q]);
+                    sc[q] += e.c * nq[q];
+                }
+            }
+        }
+        double yb[9], zb[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) yb[q] = ybar[size_t(q) * nn + P];
+        if (M.wall_bc && P < M.n_wall) {
+            double fn[9], rho, ux, uy;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) fn[q] = base[q] + K.dt * ss[q] - K.dtt * sc[q];
+            macro64(fn, rho, ux, uy);
+            // out = feq(rho, 0) + fn - feq(rho, u)
+            double rb = 0.0, uxb = 0.0, uyb = 0.0, eb[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                zb[q] = yb[q];
+                rb += yb[q] * wgt<double>(q);
+                eb[q] = -yb[q];
+            }
+            feq_adj(rho, ux, uy, eb, rb, uxb, uyb);
+            macro_adj(rho, ux, uy, rb, uxb, uyb, zb);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) zb[q] = yb[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            zbar[size_t(q) * nn + P] = zb[q];
+            dtau += zb[q] * (-sc[q]) * K.ddtt_dtau;
+        }
+    }
+    block_partial(0.0, dtau, K.partial, pslot);
+}
+
+// FV sub-step adjoint, phase B (per node k): adjoint of the stored mesh value
+// M^m_k, gathered over the pivots P whose rows contain k (transposed table).
+__global__ __launch_bounds__(256) void k_adj_fv_b(const KAdj K, const double* __restrict__ fin,
+                                                  const double* __restrict__ zbar, double* __restrict__ mbar) {
+    const KMesh& M = K.M;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M.nn) return;
+    const int nn = M.nn, W = M.ell_width;
+    const bool k_interp = k >= M.n_core;
+    const EdgeRec<double>* T = reinterpret_cast<const EdgeRec<double>*>(K.tedges);
+    double vb[9], nqb[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) vb[q] = nqb[q] = 0.0;
+    for (int z = 0; z < W; ++z) {
+        const EdgeRec<double> e = T[size_t(z) * nn + k];
+        const int P = e.col;
+        if (P < 0) continue;
+        const bool p_interp = P >= M.n_core;
+        if (p_interp && k_interp) continue;   // that pivot reads f* of k, not M_k
+        double zp[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) zp[q] = zbar[size_t(q) * nn + P];
+        if (z == 0) {   // k is its own pivot: base term and self collision
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                vb[q] += zp[q] * (1.0 - K.dt * (CX[q] * e.gx + CY[q] * e.gy));
+                nqb[q] -= K.dtt * e.c * zp[q];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                vb[q] += K.dt * (CX[q] * e.gx + CY[q] * e.gy) * zp[q];
+                nqb[q] -= K.dtt * e.c * zp[q];
+            }
+        }
+    }
+    // nq = f - feq(f): f_bar += nqb - J_feq^T nqb
+    double f[9], m0, ux, uy, a[12] = {0, 0, 0};
+    load_rec(fin + size_t(k) * kRec, f, m0, ux, uy);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) a[3 + q] = nqb[q];
+    macro_neq_adj(f, a, vb);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) mbar[size_t(q) * nn + k] = vb[q];
+}
+
+// FV sub-step adjoint, phase C (per interpolation slot k): adjoint of the star
+// values f*_k used by interpolation pivots -> (rho, u, f^neq) at t and t+1.
+__global__ __launch_bounds__(256) void k_adj_fv_c(const KAdj K, const double* __restrict__ zbar,
+                                                  const double* __restrict__ prep0, const double* __restrict__ prep1,
+                                                  double theta, double* __restrict__ p0bar, double* __restrict__ p1bar,
+                                                  int pslot) {
+    const KMesh& M = K.M;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n_int = M.nn - M.n_core;
+    double dtau = 0.0;
+    if (s < n_int) {
+        const int nn = M.nn, W = M.ell_width, k = M.n_core + s;
+        const EdgeRec<double>* T = reinterpret_cast<const EdgeRec<double>*>(K.tedges);
+        double fsb[9], nsb[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) fsb[q] = nsb[q] = 0.0;
+        for (int z = 0; z < W; ++z) {
+            const EdgeRec<double> e = T[size_t(z) * nn + k];
+            const int P = e.col;
+            if (P < M.n_core) continue;   // also skips unused slots (col = -1)
+            double zp[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) zp[q] = zbar[size_t(q) * nn + P];
+            const double sfac = z == 0 ? -1.0 : 1.0;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const double sq = CX[q] * e.gx + CY[q] * e.gy;
+                fsb[q] += (z == 0 ? 1.0 : 0.0) * zp[q] + sfac * K.dt * sq * zp[q];
+                nsb[q] -= K.dtt * e.c * zp[q];
+            }
+        }
+        double v[12], fs[9], ns[9];
+        const size_t sl = size_t(s) * kMacro;
+        star64(prep0 + sl, prep1 + sl, theta, K.cst, v, fs, ns);
+        // fs = feq(v0, v1, v2) + cst v[3..], ns = cst v[3..]
+        double rb = 0.0, uxb = 0.0, uyb = 0.0, vb[12];
+        feq_adj(v[0], v[1], v[2], fsb, rb, uxb, uyb);
+        vb[0] = rb, vb[1] = uxb, vb[2] = uyb;
+        double dcst = 0.0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            vb[3 + q] = K.cst * (fsb[q] + nsb[q]);
+            dcst += (fsb[q] + nsb[q]) * v[3 + q];
+        }
+        dtau = dcst * K.dcst_dtau;
+#pragma unroll
+        for (int m = 0; m < 12; ++m) {
+            p0bar[sl + m] += (1.0 - theta) * vb[m];
+            p1bar[sl + m] += theta * vb[m];
+        }
+    }
+    block_partial(0.0, dtau, K.partial, pslot);
+}
+
+// Collision adjoint (per collide-stream node x, edges included): with
+// g = streamed populations, B = g - omega (g - feq(g)):
+// prebar = (1 - omega) Bbar + omega J_feq(g)^T Bbar; tau through omega.
+__global__ __launch_bounds__(256) void k_adj_collide(const KAdj K, const double* __restrict__ A,
+                                                     const double* __restrict__ bbar, double* __restrict__ prebar,
+                                                     int pslot) {
+    const KLevel& L = K.L;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    double dtau = 0.0;
+    if (i < L.nx && j < L.ny) {
+        const size_t base = size_t(j) * L.pitch + i;
+        if (!is_active(L, i, j)) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) prebar[size_t(q) * L.stride + base] = 0.0;
+        } else {
+            double g[9], feq[9], rho, ux, uy, bb[9], fb[9], eb[9];
+            streamed<double, false>(L, A, i, j, g);
+            macro64(g, rho, ux, uy);
+            equilibrium<double, false>(rho, rho, ux, uy, feq);
+            double domega = 0.0;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                bb[q] = bbar[size_t(q) * L.stride + base];
+                fb[q] = (1.0 - K.omega) * bb[q];
+                eb[q] = K.omega * bb[q];
+                domega -= bb[q] * (g[q] - feq[q]);
+            }
+            double rb = 0.0, uxb = 0.0, uyb = 0.0;
+            feq_adj(rho, ux, uy, eb, rb, uxb, uyb);
+            macro_adj(rho, ux, uy, rb, uxb, uyb, fb);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) prebar[size_t(q) * L.stride + base] = fb[q];
+            dtau = domega * K.domega_dtau;
+        }
+    }
+    block_partial(0.0, dtau, K.partial, pslot + blockIdx.y * gridDim.x);
+}
+
+// Adjoint of eq. (9): prebar(d) += J_(rho,u,neq)(g_d)^T sum_s w_sd pbar_s, per donor d.
+__global__ void k_adj_s2m(const KAdj K, const double* __restrict__ A, int nd, const int32_t* __restrict__ node,
+                          const int32_t* __restrict__ ptr, const int32_t* __restrict__ slot,
+                          const double* __restrict__ w, const double* __restrict__ pbar, double* __restrict__ prebar) {
+    const KLevel& L = K.L;
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= nd) return;
+    double a[12];
+#pragma unroll
+    for (int m = 0; m < 12; ++m) a[m] = 0.0;
+    for (int z = ptr[d]; z < ptr[d + 1]; ++z) {
+        const double ww = w[z];
+        const double* pb = pbar + size_t(slot[z]) * kMacro;
+#pragma unroll
+        for (int m = 0; m < 12; ++m) a[m] += ww * pb[m];
+    }
+    const int id = node[d], i = id % L.nx, j = id / L.nx;
+    double g[9], fb[9];
+    pull(L, A, i, j, g);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fb[q] = 0.0;
+    macro_neq_adj(g, a, fb);
+    const size_t base = size_t(j) * L.pitch + i;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) prebar[size_t(q) * L.stride + base] += fb[q];
+}
+
+// Far-field boundary adjoint for one edge node: moves prebar(edge) onto the
+// neighbour whose streamed populations the boundary condition used (Sec. 4);
+// returns the angle-of-attack derivative (inlet velocity).
+__device__ __forceinline__ double bc_adj_node(const KAdj& K, const double* A, double* prebar, int i, int j) {
+    const KLevel& L = K.L;
+    const int jc = j < 1 ? 1 : (j > L.ny - 2 ? L.ny - 2 : j);
+    const int ni = (i == 0) ? 1 : (i == L.nx - 1 ? L.nx - 2 : i);
+    const int nj = (i == 0 || i == L.nx - 1) ? jc : (j == 0 ? 1 : L.ny - 2);
+    const size_t be = size_t(j) * L.pitch + i, bn = size_t(nj) * L.pitch + ni;
+    double fb[9], gb[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        fb[q] = prebar[size_t(q) * L.stride + be];
+        prebar[size_t(q) * L.stride + be] = 0.0;
+        gb[q] = fb[q];
+    }
+    double dalpha = 0.0;
+    if (i == 0 || i == L.nx - 1) {
+        double g[9], rho, ux, uy, eb[9];
+        pull(L, A, ni, nj, g);
+        macro64(g, rho, ux, uy);
+        double rb = 0.0, uxb = 0.0, uyb = 0.0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) eb[q] = -fb[q];
+        feq_adj(rho, ux, uy, eb, rb, uxb, uyb);   // - feq(rho_g, u_g)
+        if (i == 0) {   // + feq(rho_g, u_in)
+            double rb2 = 0.0, ub_x = 0.0, ub_y = 0.0;
+            feq_adj(rho, L.u_in_x, L.u_in_y, fb, rb2, ub_x, ub_y);
+            rb += rb2;
+            dalpha = ub_x * K.duin_x + ub_y * K.duin_y;
+        } else {        // + feq(rho0, u_g)
+            double rb2 = 0.0;
+            feq_adj(L.rho0, ux, uy, fb, rb2, uxb, uyb);
+        }
+        macro_adj(rho, ux, uy, rb, uxb, uyb, gb);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) prebar[size_t(q) * L.stride + bn] += gb[q];
+    return dalpha;
+}
+
+// part 0: bottom and top rows (copies); part 1: inlet and outlet columns
+// without corners; part 2: the four corners, one thread, in order.
+__global__ __launch_bounds__(256) void k_adj_bc(const KAdj K, const double* __restrict__ A, double* __restrict__ prebar,
+                                                int part, int pslot) {
+    const KLevel& L = K.L;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    double dalpha = 0.0;
+    if (part == 0) {
+        if (t < 2 * (L.nx - 2)) {
+            const int i = 1 + (t % (L.nx - 2)), j = t < L.nx - 2 ? 0 : L.ny - 1;
+            dalpha = bc_adj_node(K, A, prebar, i, j);
+        }
+    } else if (part == 1) {
+        if (t < 2 * (L.ny - 2)) {
+            const int j = 1 + (t % (L.ny - 2)), i = t < L.ny - 2 ? 0 : L.nx - 1;
+            dalpha = bc_adj_node(K, A, prebar, i, j);
+        }
+    } else if (t == 0) {
+        dalpha += bc_adj_node(K, A, prebar, 0, 0);
+        dalpha += bc_adj_node(K, A, prebar, 0, L.ny - 1);
+        dalpha += bc_adj_node(K, A, prebar, L.nx - 1, 0);
+        dalpha += bc_adj_node(K, A, prebar, L.nx - 1, L.ny - 1);
+    }
+    block_partial(dalpha, 0.0, K.partial, pslot);
+}
+
+// Transpose of the pull: Abar(y)_q = prebar(y + c_q)_q when y + c_q pulls
+// (a collide-stream node that is not a far-field edge), else 0.
+__global__ __launch_bounds__(256) void k_adj_push(const KAdj K, const double* __restrict__ prebar,
+                                                  double* __restrict__ abar) {
+    const KLevel& L = K.L;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= L.nx || j >= L.ny) return;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        int a = i + CX[q], b = j + CY[q];
+        if (L.periodic) {
+            a = (a + L.nx) % L.nx;
+            b = (b + L.ny) % L.ny;
+        }
+        double v = 0.0;
+        const bool inb = a >= 0 && b >= 0 && a < L.nx && b < L.ny;
+        const bool edge = L.farfield && (a == 0 || b == 0 || a == L.nx - 1 || b == L.ny - 1);
+        if (inb && !edge && is_active(L, a, b)) v = prebar[size_t(q) * L.stride + size_t(b) * L.pitch + a];
+        abar[size_t(q) * L.stride + size_t(j) * L.pitch + i] = v;
+    }
+}
+
+// Adjoint of eq. (4), phase 1 (per structured interpolation node s): reads and
+// clears Abar at the node, records the adjoint of (rho, u, f^neq) of the
+// interpolant in m5bar; tau through 2 (tau - 1)/(2 tau - 1).
+__global__ __launch_bounds__(256) void k_adj_m2s_a(const KAdj K, const double* __restrict__ mf, int n,
+                                                   const int32_t* __restrict__ node, const int32_t* __restrict__ don,
+                                                   const double* __restrict__ w, double* __restrict__ abar,
+                                                   double* __restrict__ m5bar, int pslot) {
+    const KLevel& L = K.L;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    double dtau = 0.0;
+    if (s < n) {
+        double acc[12];
+#pragma unroll
+        for (int m = 0; m < 12; ++m) acc[m] = 0.0;
+        for (int d = 0; d < kSDon; ++d) {
+            const int k = don[size_t(s) * kSDon + d];
+            if (k < 0) break;
+            double f[9], m0, ux, uy, feq[9];
+            load_rec(mf + size_t(k) * kRec, f, m0, ux, uy);
+            equilibrium<double, false>(m0, m0, ux, uy, feq);
+            const double ww = w[size_t(s) * kSDon + d];
+            acc[0] += ww * m0;
+            acc[1] += ww * ux;
+            acc[2] += ww * uy;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) acc[3 + q] += ww * (f[q] - feq[q]);
+        }
+        const int id = node[s], i = id % L.nx, j = id / L.nx;
+        const size_t base = size_t(j) * L.pitch + i;
+        double vb[9];
+        double dphi = 0.0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            vb[q] = abar[size_t(q) * L.stride + base];
+            abar[size_t(q) * L.stride + base] = 0.0;
+            dphi += vb[q] * acc[3 + q];
+        }
+        double rb = 0.0, uxb = 0.0, uyb = 0.0;
+        feq_adj(acc[0], acc[1], acc[2], vb, rb, uxb, uyb);
+        double* o = m5bar + size_t(s) * kMacro;
+        o[0] = rb, o[1] = uxb, o[2] = uyb;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) o[3 + q] = K.phi * vb[q];
+        dtau = dphi * K.dphi_dtau;
+    }
+    block_partial(0.0, dtau, K.partial, pslot);
+}
+
+// Adjoint of eq. (4), phase 2 (per mesh donor d): mbar(d) += J_(rho,u,neq)(M_d)^T
+// sum_s w_sd m5bar_s.
+__global__ void k_adj_m2s_b(const KAdj K, const double* __restrict__ mf, const int32_t* __restrict__ ptr,
+                            const int32_t* __restrict__ slot, const double* __restrict__ w,
+                            const double* __restrict__ m5bar, double* __restrict__ mbar) {
+    const int nn = K.M.nn;
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= nn || ptr[d] == ptr[d + 1]) return;
+    double a[12];
+#pragma unroll
+    for (int m = 0; m < 12; ++m) a[m] = 0.0;
+    for (int z = ptr[d]; z < ptr[d + 1]; ++z) {
+        const double ww = w[z];
+        const double* mb = m5bar + size_t(slot[z]) * kMacro;
+#pragma unroll
+        for (int m = 0; m < 12; ++m) a[m] += ww * mb[m];
+    }
+    double f[9], m0, ux, uy, fb[9];
+    load_rec(mf + size_t(d) * kRec, f, m0, ux, uy);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fb[q] = 0.0;
+    macro_neq_adj(f, a, fb);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) mbar[size_t(q) * nn + d] += fb[q];
+}
+
+// Angle-of-attack derivative through the initial state: sum over the uniform
+// structured fill and the non-wall mesh nodes of abar . d feq(rho0, u_inf)/d alpha.
+__global__ __launch_bounds__(256) void k_adj_alpha_state(const KAdj K, const double* __restrict__ abar,
+                                                         const double* __restrict__ mbar, const double* __restrict__ dfeq,
+                                                         int pslot) {
+    const KLevel& L = K.L;
+    const size_t nlev = size_t(L.stride), nmesh = size_t(K.M.nn);
+    const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    double da = 0.0;
+    if (e < nlev) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) da += abar[size_t(q) * nlev + e] * dfeq[q];
+    } else if (e < nlev + nmesh) {
+        const size_t P = e - nlev;
+        if (!(K.M.wall_bc && int(P) < K.M.n_wall)) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) da += mbar[size_t(q) * nmesh + P] * dfeq[q];
+        }
+    }
+    block_partial(da, 0.0, K.partial, pslot);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partial, int n, double* acc) {
+    __shared__ double sa[256], sb[256];
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) a += partial[2 * k], b += partial[2 * k + 1];
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sa[threadIdx.x] += sa[threadIdx.x + h], sb[threadIdx.x] += sb[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) acc[0] += sa[0], acc[1] += sb[0];
+}
+
+}  // namespace
+
+int adj_blocks_collide(const KLevel& L) { return int(blocks(L.nx)) * L.ny; }
+int adj_blocks_nodes(int n) { return int(blocks(size_t(n > 0 ? n : 1))); }
+
+void launch_zero(double* p, size_t n, hipStream_t s) {
+    if (n) k_zero<<<blocks(n), 256, 0, s>>>(p, n);
+}
+void launch_adj_force(const KAdj& K, double* mbar, const double* vwall, double jx, double jy, hipStream_t s) {
+    if (K.M.n_wall > 0) k_adj_force<<<blocks(K.M.n_wall), 256, 0, s>>>(K.M.n_wall, K.M.nn, mbar, vwall, jx, jy);
+}
+void launch_adj_fv_a(const KAdj& K, const double* Mrec, const double* ybar, double* zbar, const double* prep0,
+                     const double* prep1, double theta, int pslot, hipStream_t s) {
+    k_adj_fv_a<<<blocks(K.M.nn), 256, 0, s>>>(K, Mrec, ybar, zbar, prep0, prep1, theta, pslot);
+}
+void launch_adj_fv_b(const KAdj& K, const double* Mrec, const double* zbar, double* mbar, hipStream_t s) {
+    k_adj_fv_b<<<blocks(K.M.nn), 256, 0, s>>>(K, Mrec, zbar, mbar);
+}
+void launch_adj_fv_c(const KAdj& K, const double* zbar, const double* prep0, const double* prep1, double theta,
+                     double* p0bar, double* p1bar, int pslot, hipStream_t s) {
+    const int n = K.M.nn - K.M.n_core;
+    k_adj_fv_c<<<adj_blocks_nodes(n), 256, 0, s>>>(K, zbar, prep0, prep1, theta, p0bar, p1bar, pslot);
+}
+void launch_adj_collide(const KAdj& K, const double* A, const double* bbar, double* prebar, int pslot, hipStream_t s) {
+    dim3 grid(blocks(K.L.nx), K.L.ny);
+    k_adj_collide<<<grid, 256, 0, s>>>(K, A, bbar, prebar, pslot);
+}
+void launch_adj_s2m(const KAdj& K, const double* A, int nd, const int32_t* node, const int32_t* ptr,
+                    const int32_t* slot, const double* w, const double* pbar, double* prebar, hipStream_t s) {
+    if (nd > 0) k_adj_s2m<<<blocks(nd), 256, 0, s>>>(K, A, nd, node, ptr, slot, w, pbar, prebar);
+}
+void launch_adj_bc(const KAdj& K, const double* A, double* prebar, int pslot, hipStream_t s) {
+    if (!K.L.farfield) return;
+    k_adj_bc<<<blocks(2 * size_t(K.L.nx - 2)), 256, 0, s>>>(K, A, prebar, 0, pslot);
+    k_adj_bc<<<blocks(2 * size_t(K.L.ny - 2)), 256, 0, s>>>(K, A, prebar, 1, pslot + int(blocks(2 * size_t(K.L.nx - 2))));
+    k_adj_bc<<<1, 256, 0, s>>>(K, A, prebar, 2, pslot + int(blocks(2 * size_t(K.L.nx - 2))) + int(blocks(2 * size_t(K.L.ny - 2))));
+}
+void launch_adj_push(const KAdj& K, const double* prebar, double* abar, hipStream_t s) {
+    dim3 grid(blocks(K.L.nx), K.L.ny);
+    k_adj_push<<<grid, 256, 0, s>>>(K, prebar, abar);
+}
+void launch_adj_m2s_a(const KAdj& K, const double* Mrec, int n, const int32_t* node, const int32_t* don,
+                      const double* w, double* abar, double* m5bar, int pslot, hipStream_t s) {
+    k_adj_m2s_a<<<adj_blocks_nodes(n), 256, 0, s>>>(K, Mrec, n, node, don, w, abar, m5bar, pslot);
+}
+void launch_adj_m2s_b(const KAdj& K, const double* Mrec, const int32_t* ptr, const int32_t* slot, const double* w,
+                      const double* m5bar, double* mbar, hipStream_t s) {
+    k_adj_m2s_b<<<blocks(K.M.nn), 256, 0, s>>>(K, Mrec, ptr, slot, w, m5bar, mbar);
+}
+void launch_adj_alpha_state(const KAdj& K, const double* abar, const double* mbar, const double* dfeq, int pslot,
+                            hipStream_t s) {
+    const size_t n = size_t(K.L.stride) + size_t(K.M.nn);
+    k_adj_alpha_state<<<blocks(n), 256, 0, s>>>(K, abar, mbar, dfeq, pslot);
+}
+void launch_reduce_partials(const double* partial, int n, double* acc, hipStream_t s) {
+    k_reduce_partials<<<1, 256, 0, s>>>(partial, n, acc);
+}
+
+}  // namespace hlbm

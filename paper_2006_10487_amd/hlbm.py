@@ -26,7 +26,8 @@ PART_MESH = 100
 
 EXPORTED = ["hlbm_validate", "hlbm_workspace_size", "hlbm_create", "hlbm_step", "hlbm_forces",
             "hlbm_force_history", "hlbm_get_state", "hlbm_set_state", "hlbm_info", "hlbm_last_error",
-            "hlbm_destroy", "hlbm_profile", "hlbm_profile_read", "hlbm_kernel_bench"]
+            "hlbm_destroy", "hlbm_profile", "hlbm_profile_read", "hlbm_kernel_bench",
+            "hlbm_objective_workspace_size", "hlbm_run_objective", "hlbm_adjoint"]
 KERNEL_CLASSES = ["collide_l0", "collide_l1", "collide_l2", "collide_l3", "coarse_to_fine",
                   "fine_to_coarse", "mesh_to_struct", "struct_to_mesh", "fv_substep", "wall_force"]
 
@@ -54,6 +55,11 @@ class Mesh(C.Structure):
         ("xy", C.POINTER(C.c_double)), ("tri", C.POINTER(C.c_int32)), ("kind", C.POINTER(C.c_uint8)),
         ("chord", C.c_double), ("inner_ellipse", C.c_double * 4),
     ]
+
+
+class Objective(C.Structure):
+    _fields_ = [("t_end", C.c_int64), ("t0", C.c_int64), ("t1", C.c_int64), ("ckpt_every", C.c_int64),
+                ("w_cd", C.c_double), ("w_cl", C.c_double)]
 
 
 class Info(C.Structure):
@@ -97,6 +103,9 @@ def lib():
         L.hlbm_profile.argtypes = [P, C.c_int]
         L.hlbm_profile_read.argtypes = [P, P, P]
         L.hlbm_kernel_bench.argtypes = [P, C.c_int, C.c_int, C.POINTER(C.c_double)]
+        L.hlbm_objective_workspace_size.argtypes = [P, C.POINTER(Objective), C.POINTER(C.c_size_t)]
+        L.hlbm_run_objective.argtypes = [P, C.POINTER(Objective), P, C.c_size_t, C.POINTER(C.c_double)]
+        L.hlbm_adjoint.argtypes = [P, C.c_double, P]
         _lib = L
     return _lib
 
@@ -268,6 +277,27 @@ class HLBM:
         self._check(lib().hlbm_kernel_bench(self._ctx, KERNEL_CLASSES.index(kclass), int(n), C.byref(ms)))
         return ms.value
 
+    def run_objective(self, t_end: int, t0: int, t1: int, ckpt_every: int = 100, w_cd: float = 1.0,
+                      w_cl: float = 0.0) -> float:
+        """Run from the initial state and return the windowed mean of w_cd C_D + w_cl C_L."""
+        import torch
+        o = Objective(int(t_end), int(t0), int(t1), int(ckpt_every), float(w_cd), float(w_cl))
+        n = C.c_size_t(0)
+        self._check(lib().hlbm_objective_workspace_size(self._ctx, C.byref(o), C.byref(n)))
+        if getattr(self, "obj_ws", None) is None or self.obj_ws.numel() < n.value:
+            self.obj_ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        self._objective = o
+        J = C.c_double()
+        self._check(lib().hlbm_run_objective(self._ctx, C.byref(o), C.c_void_p(self.obj_ws.data_ptr()),
+                                             self.obj_ws.numel(), C.byref(J)))
+        return J.value
+
+    def adjoint(self, j_bar: float = 1.0) -> np.ndarray:
+        """[dJ/d aoa_rad, dJ/d tau] of the last run_objective (discrete adjoint)."""
+        g = np.zeros(2)
+        self._check(lib().hlbm_adjoint(self._ctx, float(j_bar), _np_ptr(g)))
+        return g
+
     def synchronize(self):
         self.stream.synchronize()
 
@@ -289,3 +319,32 @@ def strouhal(cl: np.ndarray, chord: float, u_inf: float, steady_tol: float = 1e-
     tc = idx + (-x[idx]) / (x[idx + 1] - x[idx])
     period = (tc[-1] - tc[0]) / (idx.size - 1)
     return chord / (u_inf * period)
+
+
+def objective_function():
+    """torch.autograd.Function J(aoa_rad, tau) of the HLBM drag/lift objective.
+
+    Usage: ``J = objective_function().apply(aoa, tau, workload, spec)`` with
+    ``aoa`` and ``tau`` 0-d float64 CPU tensors, ``spec`` a dict with t_end, t0,
+    t1, ckpt_every, w_cd, w_cl.  forward runs the GPU objective; backward runs
+    the discrete adjoint of the same run.
+    """
+    import torch
+
+    class HLBMObjective(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, aoa, tau, workload, spec):
+            sim = HLBM.from_workload(workload, aoa_rad=float(aoa), tau=float(tau), precision=FP64,
+                                     history_len=max(65536, int(spec["t_end"])))
+            J = sim.run_objective(**spec)
+            ctx.sim = sim
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, g):
+            grad = ctx.sim.adjoint(float(g))
+            ctx.sim.close()
+            return (torch.tensor(grad[0], dtype=torch.float64), torch.tensor(grad[1], dtype=torch.float64),
+                    None, None)
+
+    return HLBMObjective
