@@ -89,11 +89,61 @@ def kernel_table(r):
     return rows
 
 
-def roofline(rows, k, note):
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hlbm_step_naca_re5000_c512_fp32_hbm_traffic.md")
+
+
+def measured_traffic(kernel):
+    """Calibrated HBM bytes per launch from the committed counter summary, or
+    None when the forward kernels changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        src = open(os.path.join(ROOT, "paper_2006_10487_amd", "csrc", "kernels.hip")).read()
+        fwd = src[:src.index("// Discrete adjoint of the single-level hybrid step (FP64).")]
+        if hashlib.sha256(fwd.encode()).hexdigest() != rec["forward_kernels_sha256"]:
+            return None
+        return round(rec[kernel]["traffic_bytes"])
+    except (OSError, ValueError, KeyError, AttributeError):
+        return None
+
+
+def roofline(rows, k, note, traffic=None):
     v = rows[k]
     return {"bound": "hbm", "kernel": k, "achieved": v["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(v["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(v["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
             "alg_bytes_per_launch": v["alg_bytes"], "avg_launch_us": v["avg_us"], "note": note}
+
+
+def adjoint_cost(hlbm, torch, workloads, t_end=400, ckpt=100):
+    """(objective run + discrete adjoint) time over a plain forward of the same steps.
+
+    The adjoint covers single-level problems, so this is measured on the
+    Re = 100, 240 x 120 grid, 128 x 16 mesh workload in FP64."""
+    w = workloads.naca_re100_c40(3.0)
+    progress("adjoint cost")
+    sim = hlbm.HLBM.from_workload(w, precision=hlbm.FP64)
+    sim.step(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(t_end)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    spec = dict(t_end=t_end, t0=t_end // 2, t1=t_end, ckpt_every=ckpt, w_cd=1.0, w_cl=0.0)
+    sim.run_objective(**spec)
+    sim.adjoint()
+    t0 = time.perf_counter()
+    sim.run_objective(**spec)
+    t1 = time.perf_counter()
+    g = sim.adjoint()
+    t2 = time.perf_counter()
+    sim.close()
+    return {"ratio": round((t2 - t0) / t_fwd, 3), "forward_s": round(t_fwd, 4),
+            "objective_run_s": round(t1 - t0, 4), "adjoint_s": round(t2 - t1, 4),
+            "workload": w.name, "finest_steps": t_end, "ckpt_every": ckpt, "precision": "fp64",
+            "grad_aoa_tau": [float(g[0]), float(g[1])],
+            "note": "gradient of the windowed mean C_D w.r.t. angle of attack and tau"}
 
 
 def cpu_baseline(w, base_steps):
@@ -115,7 +165,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100, help="timed base steps")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="naca_re5000_c512")
-    ap.add_argument("--cpu-steps", type=int, default=1, help="base steps of the oracle sample")
+    ap.add_argument("--cpu-steps", type=int, default=16, help="base steps of the oracle sample (~10 s on 16 cores)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -154,8 +204,11 @@ def main():
     }
     dom = max(k32, key=lambda k: k32[k]["share"])
     res["roofline"] = roofline(k32, dom, "dominant kernel by time share; algorithmic bytes per launch over "
-                                         "the mean of back-to-back launches timed with HIP events")
-    res["roofline_base_grid"] = roofline(k32, "collide_l0", "base-level fused stream-collide (72 B per node)")
+                                         "the mean of back-to-back launches timed with HIP events; traffic = "
+                                         "calibrated FETCH_SIZE + WRITE_SIZE bytes per launch",
+                               measured_traffic(dom) if w.name == "naca0012_re5000_c512_8192x4096_r1" else None)
+    res["roofline_base_grid"] = roofline(k32, "collide_l0", "base-level fused stream-collide (72 B per node)",
+                                         measured_traffic("collide_l0") if w.name == "naca0012_re5000_c512_8192x4096_r1" else None)
     res["kernels_fp32"] = k32
     res["fv_msubsteps_per_s"] = round(r32["fv_updates"] * a.steps / t32 / 1e6, 1)
     if not a.no_fp64:
@@ -184,7 +237,7 @@ def main():
         torch.cuda.synchronize()
         res["copy_probe_bytes_each_way"] = n * 4
         del src, dst
-    res["adjoint_over_forward"] = None
+    res["adjoint_over_forward"] = adjoint_cost(hlbm, torch, workloads)
     if not a.no_cpu:
         o, tc = cpu_baseline(w, a.cpu_steps)
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
