@@ -89,7 +89,7 @@ void layout(hlbm_ctx* c, AdjState& a) {
     const int bn = adj_blocks_nodes(p.nn), bi = adj_blocks_nodes(p.n_int);
     const int bc = adj_blocks_nodes(2 * (v.nx - 2)) + adj_blocks_nodes(2 * (v.ny - 2)) + 1;
     a.n_slots = p.n_sub * (bn + bi) + adj_blocks_collide(c->kl[0]) + bc +
-                adj_blocks_nodes(int(p.sint_node.size())) + adj_blocks_nodes(int(v.ny) * v.pitch + p.nn) + 64;
+                adj_blocks_nodes(int(p.sint_node.size())) + adj_blocks_nodes(int(v.ny) * 9 * v.pitch + p.nn) + 64;
     a.off.partial = take(size_t(a.n_slots) * 2 * 8);
     a.off.acc = take(2 * 8);
     a.off.tedges = take(size_t(p.ell_width) * p.nn * 32);
@@ -435,7 +435,7 @@ int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad) {
         }
         rc |= hip_check(c, hipMemcpyAsync(a.ws + a.off.dfeq, dfeq, sizeof(dfeq), hipMemcpyHostToDevice, s), "dfeq");
         launch_adj_alpha_state(K, Anew, a.at<double>(a.off.mbar[mb]), a.at<double>(a.off.dfeq), slot, s);
-        slot += adj_blocks_nodes(int(c->kl[0].stride) + p.nn);
+        slot += adj_blocks_nodes(int(c->kl[0].ny * c->kl[0].rs) + p.nn);
         launch_reduce_partials(a.at<double>(a.off.partial), slot, a.at<double>(a.off.acc), s);
     }
     double acc[2] = {0, 0};

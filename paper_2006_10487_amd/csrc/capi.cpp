@@ -89,7 +89,7 @@ void setup_views(hlbm_ctx* c) {
         k.nx = v.nx;
         k.ny = v.ny;
         k.pitch = v.pitch;
-        k.stride = (long long)v.ny * v.pitch;
+        k.rs = 9LL * v.pitch;
         k.omega = 1.0 / v.tau;
         k.perim_inactive = v.perim_inactive;
         k.ci0 = v.has_child ? v.ci0 : -4;

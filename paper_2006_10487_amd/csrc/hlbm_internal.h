@@ -86,7 +86,7 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
 
 struct KLevel {
     int nx, ny, pitch;
-    long long stride;                // ny * pitch
+    long long rs;                    // row stride: 9 * pitch (planes of one row are adjacent)
     double omega;                    // 1 / tau
     int perim_inactive;
     int ci0, cj0, ci1, cj1;          // strictly inside -> not a collide-stream node
