@@ -90,6 +90,8 @@ def kernel_table(r):
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hlbm_step_naca_re5000_c512_fp32_hbm_traffic.md")
+# the forward kernels are the text of kernels.hip before this line
+ADJOINT_MARKER = "// ---- Discrete adjoint kernels (reverse mode, FP64) ----"
 
 
 def measured_traffic(kernel):
@@ -101,7 +103,7 @@ def measured_traffic(kernel):
         text = open(TRAFFIC_SUMMARY).read()
         rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
         src = open(os.path.join(ROOT, "paper_2006_10487_amd", "csrc", "kernels.hip")).read()
-        fwd = src[:src.index("// Discrete adjoint of the single-level hybrid step (FP64).")]
+        fwd = src[:src.index(ADJOINT_MARKER)]
         if hashlib.sha256(fwd.encode()).hexdigest() != rec["forward_kernels_sha256"]:
             return None
         return round(rec[kernel]["traffic_bytes"])
@@ -168,6 +170,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=16, help="base steps of the oracle sample (~10 s on 16 cores)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost measurement")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB five times (calibrates HBM byte counters)")
     a = ap.parse_args()
@@ -237,7 +240,8 @@ def main():
         torch.cuda.synchronize()
         res["copy_probe_bytes_each_way"] = n * 4
         del src, dst
-    res["adjoint_over_forward"] = adjoint_cost(hlbm, torch, workloads)
+    if not a.no_adjoint:
+        res["adjoint_over_forward"] = adjoint_cost(hlbm, torch, workloads)
     if not a.no_cpu:
         o, tc = cpu_baseline(w, a.cpu_steps)
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))

@@ -48,6 +48,27 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Arithmetic type.  The plain build computes in FP64 (real == double).  The
+ * complex-step build (-DOR_COMPLEX_STEP) makes every quantity that depends on
+ * the angle of attack, tau, the free stream or the mesh coordinates complex:
+ * with an input perturbed by i h v (h ~ 1e-30), the imaginary part of any
+ * output divided by h is its exact directional derivative along v, free of
+ * the cancellation of finite differences (complex-step differentiation,
+ * Squire and Trapp 1998; Martins, Sturdza and Alonso 2003).  Branches,
+ * pivot choices and point location look at real parts only, so the real part
+ * repeats the FP64 build operation for operation.  ABS_A is the analytic
+ * absolute value the method needs (sign taken from the real part). */
+#ifdef OR_COMPLEX_STEP
+#include <complex.h>
+#include <tgmath.h>
+typedef double complex real;
+#define RE(x) creal(x)
+#else
+typedef double real;
+#define RE(x) (x)
+#endif
+#define ABS_A(x) (RE(x) < 0.0 ? -(x) : (x))
+
 #define Q 9
 
 /* D2Q9 velocities and weights. */
@@ -80,13 +101,13 @@ typedef struct {
     int32_t wall_bc;                  /* 1: no-slip reset at wall nodes              */
     int32_t n_sub;                    /* FV sub-steps per finest step; 0 = default   */
     int32_t interp;                   /* 0 quadratic (eqs 8-9), 1 linear             */
-    double u_inf, aoa, rho0, tau_s;   /* free stream, finest-level tau               */
+    real u_inf, aoa, rho0, tau_s;   /* free stream, finest-level tau               */
     double chord;
     double ein[4];                    /* inner ellipse xc, yc, a, b (a <= 0: none)   */
     double mesh_period[2];            /* periodic mesh (0 = not periodic)            */
     /* mesh */
     int32_t n_nodes, n_tris;
-    const double *xy;                 /* [2*n_nodes]                                 */
+    const real *xy;                 /* [2*n_nodes]                                 */
     const int32_t *tri;               /* [3*n_tris] counter-clockwise                */
     const uint8_t *kind;              /* [n_nodes]                                   */
     /* channel variant of the base-level boundaries (closed-form checks only):
@@ -98,12 +119,12 @@ typedef struct {
     int nx, ny;          /* nodes */
     int sp;              /* spacing in finest units */
     double ox, oy;       /* origin (finest units) */
-    double tau;
+    real tau;
     int i0, j0;          /* origin in parent nodes (levels > 0) */
     uint8_t *cls;
-    double *f;           /* pre-collision [Q][ny][nx] */
-    double *post;        /* post-collision */
-    double *save;        /* pre-collision at the start of the current step */
+    real *f;           /* pre-collision [Q][ny][nx] */
+    real *post;        /* post-collision */
+    real *save;        /* pre-collision at the start of the current step */
 } olevel;
 
 typedef struct {
@@ -112,31 +133,31 @@ typedef struct {
     olevel lev[4];
     /* mesh */
     int nn, nt;
-    double *xy;
+    real *xy;
     int32_t *tri;
     uint8_t *kind;
     int *rowptr, *col;     /* CSR, neighbours sorted, self included */
-    double *gx, *gy, *cc;  /* G_Pk and C_Pk */
-    double *area;          /* A_P */
+    real *gx, *gy, *cc;  /* G_Pk and C_Pk */
+    real *area;          /* A_P */
     int n_wall_edges;
     int *wedge;            /* [2*n] directed P->Q, fluid on the left */
-    double *fu, *fu_new;   /* mesh populations [Q][nn] */
+    real *fu, *fu_new;   /* mesh populations [Q][nn] */
     /* interpolation node lists */
     int n_sint;            /* structured interpolation nodes (finest level) */
     int *sint_ij;          /* [2*n] */
     int *sint_don;         /* [8*n] mesh donors (-1 unused) */
-    double *sint_w;        /* [8*n] */
+    real *sint_w;        /* [8*n] */
     int n_fallback;
     int n_uint;            /* mesh interpolation nodes */
     int *uint_node;        /* [n] mesh node index */
     int *uint_slot;        /* [nn] slot or -1 */
     int *uint_don;         /* [9*n] finest-level node (i + nx*j) */
-    double *uint_w;        /* [9*n] */
+    real *uint_w;        /* [9*n] */
     int n_sub;
-    double tau_u;
+    real tau_u;
     int64_t t;             /* finest steps done */
     int64_t hist_cap;
-    double *cd, *cl;
+    real *cd, *cl;
     char err[256];
 } oracle_t;
 
@@ -144,9 +165,9 @@ typedef struct {
 /* D2Q9 basics: moments and the second-order equilibrium, eq. (2)       */
 /* ------------------------------------------------------------------ */
 
-static void moments(const double *f, double *rho, double *ux, double *uy)
+static void moments(const real *f, real *rho, real *ux, real *uy)
 {
-    double r = 0.0, mx = 0.0, my = 0.0;
+    real r = 0.0, mx = 0.0, my = 0.0;
     for (int i = 0; i < Q; ++i) {
         r += f[i];
         mx += f[i] * CX[i];
@@ -158,38 +179,38 @@ static void moments(const double *f, double *rho, double *ux, double *uy)
 }
 
 /* f_i^eq = w_i rho (1 + c.u / c_s^2 + (c.u)^2 / (2 c_s^4) - u^2 / (2 c_s^2)), c_s^2 = 1/3 */
-static void equilibrium(double rho, double ux, double uy, double *feq)
+static void equilibrium(real rho, real ux, real uy, real *feq)
 {
     const double cs2 = 1.0 / 3.0;
-    double uu = ux * ux + uy * uy;
+    real uu = ux * ux + uy * uy;
     for (int i = 0; i < Q; ++i) {
-        double cu = CX[i] * ux + CY[i] * uy;
+        real cu = CX[i] * ux + CY[i] * uy;
         feq[i] = W[i] * rho * (1.0 + cu / cs2 + (cu * cu) / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
     }
 }
 
-void or_equilibrium(double rho, double ux, double uy, double *feq) { equilibrium(rho, ux, uy, feq); }
+void or_equilibrium(real rho, real ux, real uy, real *feq) { equilibrium(rho, ux, uy, feq); }
 
-void or_lattice(int32_t *cx, int32_t *cy, double *w)
+void or_lattice(int32_t *cx, int32_t *cy, real *w)
 {
     for (int i = 0; i < Q; ++i) { cx[i] = CX[i]; cy[i] = CY[i]; w[i] = W[i]; }
 }
 
 /* BGK collision of eq. (1): f~ = f - (f - f^eq) / tau (Delta t_s = 1 in level units) */
-static void bgk(const double *f, double tau, double *out)
+static void bgk(const real *f, real tau, real *out)
 {
-    double rho, ux, uy, feq[Q];
+    real rho, ux, uy, feq[Q];
     moments(f, &rho, &ux, &uy);
     equilibrium(rho, ux, uy, feq);
     for (int i = 0; i < Q; ++i) out[i] = f[i] - (f[i] - feq[i]) / tau;
 }
 
-void or_bgk(const double *f, double tau, double *out) { bgk(f, tau, out); }
+void or_bgk(const real *f, real tau, real *out) { bgk(f, tau, out); }
 
 /* (rho, u, f^neq) of one population vector */
-static void macro_neq(const double *f, double *rho, double *ux, double *uy, double *neq)
+static void macro_neq(const real *f, real *rho, real *ux, real *uy, real *neq)
 {
-    double feq[Q];
+    real feq[Q];
     moments(f, rho, ux, uy);
     equilibrium(*rho, *ux, *uy, feq);
     for (int i = 0; i < Q; ++i) neq[i] = f[i] - feq[i];
@@ -201,12 +222,12 @@ static void macro_neq(const double *f, double *rho, double *ux, double *uy, doub
 
 #define LIDX(lv, q, i, j) (((size_t)(q) * (size_t)(lv)->ny + (size_t)(j)) * (size_t)(lv)->nx + (size_t)(i))
 
-static void get_node(const olevel *lv, const double *a, int i, int j, double *f)
+static void get_node(const olevel *lv, const real *a, int i, int j, real *f)
 {
     for (int q = 0; q < Q; ++q) f[q] = a[LIDX(lv, q, i, j)];
 }
 
-static void put_node(const olevel *lv, double *a, int i, int j, const double *f)
+static void put_node(const olevel *lv, real *a, int i, int j, const real *f)
 {
     for (int q = 0; q < Q; ++q) a[LIDX(lv, q, i, j)] = f[q];
 }
@@ -263,9 +284,9 @@ static void classify(oracle_t *o)
 /* finite-volume geometry on the median dual (eq. (3), reading above)   */
 /* ------------------------------------------------------------------ */
 
-typedef struct { int k; double gx, gy, c; } nbr_t;
+typedef struct { int k; real gx, gy, c; } nbr_t;
 
-static void nb_add(nbr_t *row, int *len, int k, double gx, double gy, double c)
+static void nb_add(nbr_t *row, int *len, int k, real gx, real gy, real c)
 {
     for (int a = 0; a < *len; ++a)
         if (row[a].k == k) { row[a].gx += gx; row[a].gy += gy; row[a].c += c; return; }
@@ -278,10 +299,10 @@ static int cmp_nbr(const void *a, const void *b)
     return ((const nbr_t *)a)->k - ((const nbr_t *)b)->k;
 }
 
-static double wrap(double d, double period)
+static real wrap(real d, double period)
 {
     if (period <= 0.0) return d;
-    return d - period * floor(d / period + 0.5);
+    return d - period * floor(RE(d) / period + 0.5);
 }
 
 #define MAXNB 32
@@ -305,33 +326,33 @@ static void node_triangles(int nn, int nt, const int32_t *tri, int **ptr_o, int 
  *   C_Pk =  (1/A_P) integral over CV_P of psi_k,
  * with N_seg the outward normal times length of each control-volume segment,
  * and the list of wall edges.  Returns 0 or a negative error. */
-static int fv_geometry(int nn, int nt, const double *xy, const int32_t *tri, const uint8_t *kind,
-                       const double *period, int **rowptr_o, int **col_o, double **gx_o,
-                       double **gy_o, double **cc_o, double **area_o, int *n_wall_o, int **wedge_o,
+static int fv_geometry(int nn, int nt, const real *xy, const int32_t *tri, const uint8_t *kind,
+                       const double *period, int **rowptr_o, int **col_o, real **gx_o,
+                       real **gy_o, real **cc_o, real **area_o, int *n_wall_o, int **wedge_o,
                        char *err)
 {
     nbr_t *rows = (nbr_t *)calloc((size_t)nn * MAXNB, sizeof(nbr_t));
     int *len = (int *)calloc((size_t)nn, sizeof(int));
-    double *area = (double *)calloc((size_t)nn, sizeof(double));
+    real *area = (real *)calloc((size_t)nn, sizeof(real));
     if (!rows || !len || !area) { snprintf(err, 256, "oom"); return -1; }
     for (int t = 0; t < nt; ++t) {
         int v[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
         for (int r = 0; r < 3; ++r) {
             int P = v[r], A = v[(r + 1) % 3], B = v[(r + 2) % 3];
             /* positions relative to P (minimum image on a periodic mesh) */
-            double ax = wrap(xy[2 * A] - xy[2 * P], period[0]), ay = wrap(xy[2 * A + 1] - xy[2 * P + 1], period[1]);
-            double bx = wrap(xy[2 * B] - xy[2 * P], period[0]), by = wrap(xy[2 * B + 1] - xy[2 * P + 1], period[1]);
-            double at = 0.5 * (ax * by - ay * bx);
-            if (!(at > 0.0)) { snprintf(err, 256, "triangle %d not counter-clockwise or degenerate", t); free(rows); free(len); free(area); return -2; }
-            double mpa_x = 0.5 * ax, mpa_y = 0.5 * ay;
-            double mpb_x = 0.5 * bx, mpb_y = 0.5 * by;
-            double g_x = (ax + bx) / 3.0, g_y = (ay + by) / 3.0;
+            real ax = wrap(xy[2 * A] - xy[2 * P], period[0]), ay = wrap(xy[2 * A + 1] - xy[2 * P + 1], period[1]);
+            real bx = wrap(xy[2 * B] - xy[2 * P], period[0]), by = wrap(xy[2 * B + 1] - xy[2 * P + 1], period[1]);
+            real at = 0.5 * (ax * by - ay * bx);
+            if (!(RE(at) > 0.0)) { snprintf(err, 256, "triangle %d not counter-clockwise or degenerate", t); free(rows); free(len); free(area); return -2; }
+            real mpa_x = 0.5 * ax, mpa_y = 0.5 * ay;
+            real mpb_x = 0.5 * bx, mpb_y = 0.5 * by;
+            real g_x = (ax + bx) / 3.0, g_y = (ay + by) / 3.0;
             /* segment M_PA -> G, outward normal = clockwise rotation of the segment */
-            double s1x = g_x - mpa_x, s1y = g_y - mpa_y;
-            double n1x = s1y, n1y = -s1x;
+            real s1x = g_x - mpa_x, s1y = g_y - mpa_y;
+            real n1x = s1y, n1y = -s1x;
             /* segment G -> M_PB */
-            double s2x = mpb_x - g_x, s2y = mpb_y - g_y;
-            double n2x = s2y, n2y = -s2x;
+            real s2x = mpb_x - g_x, s2y = mpb_y - g_y;
+            real n2x = s2y, n2y = -s2x;
             /* hat-function values at the segment midpoints: (P, A, B) */
             const double m1[3] = {5.0 / 12.0, 5.0 / 12.0, 1.0 / 6.0};
             const double m2[3] = {5.0 / 12.0, 1.0 / 6.0, 5.0 / 12.0};
@@ -339,8 +360,8 @@ static int fv_geometry(int nn, int nt, const double *xy, const int32_t *tri, con
             /* exact integrals of the hat functions over the quadrilateral P-M_PA-G-M_PB */
             const double ci[3] = {11.0 / 54.0, 7.0 / 108.0, 7.0 / 108.0};
             for (int s = 0; s < 3; ++s) {
-                double gx = -(n1x * m1[s] + n2x * m2[s]);
-                double gy = -(n1y * m1[s] + n2y * m2[s]);
+                real gx = -(n1x * m1[s] + n2x * m2[s]);
+                real gy = -(n1y * m1[s] + n2y * m2[s]);
                 if (len[P] >= MAXNB) { snprintf(err, 256, "node %d degree too large", P); return -2; }
                 nb_add(rows + (size_t)P * MAXNB, &len[P], ids[s], gx, gy, ci[s] * at);
             }
@@ -376,8 +397,8 @@ static int fv_geometry(int nn, int nt, const double *xy, const int32_t *tri, con
     int *wedge = (int *)malloc(sizeof(int) * 2 * (n_be > 0 ? n_be : 1));
     for (int e = 0; e < n_be; ++e) {
         int P = be[2 * e], Qn = be[2 * e + 1];
-        double dx = xy[2 * Qn] - xy[2 * P], dy = xy[2 * Qn + 1] - xy[2 * P + 1];
-        double nx = 0.5 * dy, ny = -0.5 * dx;   /* each half edge: half length */
+        real dx = xy[2 * Qn] - xy[2 * P], dy = xy[2 * Qn + 1] - xy[2 * P + 1];
+        real nx = 0.5 * dy, ny = -0.5 * dx;   /* each half edge: half length */
         nb_add(rows + (size_t)P * MAXNB, &len[P], P, -0.75 * nx, -0.75 * ny, 0.0);
         nb_add(rows + (size_t)P * MAXNB, &len[P], Qn, -0.25 * nx, -0.25 * ny, 0.0);
         nb_add(rows + (size_t)Qn * MAXNB, &len[Qn], Qn, -0.75 * nx, -0.75 * ny, 0.0);
@@ -392,12 +413,12 @@ static int fv_geometry(int nn, int nt, const double *xy, const int32_t *tri, con
     for (int p = 0; p < nn; ++p) rowptr[p + 1] = rowptr[p] + len[p];
     int nnz = rowptr[nn];
     int *col = (int *)malloc(sizeof(int) * nnz);
-    double *gx = (double *)malloc(sizeof(double) * nnz), *gy = (double *)malloc(sizeof(double) * nnz);
-    double *cc = (double *)malloc(sizeof(double) * nnz);
+    real *gx = (real *)malloc(sizeof(real) * nnz), *gy = (real *)malloc(sizeof(real) * nnz);
+    real *cc = (real *)malloc(sizeof(real) * nnz);
     for (int p = 0; p < nn; ++p) {
         nbr_t *row = rows + (size_t)p * MAXNB;
         qsort(row, len[p], sizeof(nbr_t), cmp_nbr);
-        if (!(area[p] > 0.0)) { snprintf(err, 256, "node %d has no control volume", p); return -2; }
+        if (!(RE(area[p]) > 0.0)) { snprintf(err, 256, "node %d has no control volume", p); return -2; }
         for (int a = 0; a < len[p]; ++a) {
             int z = rowptr[p] + a;
             col[z] = row[a].k;
@@ -413,15 +434,15 @@ static int fv_geometry(int nn, int nt, const double *xy, const int32_t *tri, con
 }
 
 /* Stand-alone geometry export for tests: caller passes arrays of size >= nnz_max. */
-int or_fv_geometry(int32_t nn, int32_t nt, const double *xy, const int32_t *tri, const uint8_t *kind,
+int or_fv_geometry(int32_t nn, int32_t nt, const real *xy, const int32_t *tri, const uint8_t *kind,
                    double period_x, double period_y, int32_t nnz_max, int32_t *rowptr_out,
-                   int32_t *col_out, double *gx_out, double *gy_out, double *c_out, double *area_out,
+                   int32_t *col_out, real *gx_out, real *gy_out, real *c_out, real *area_out,
                    int32_t *n_wall_out, int32_t *wedge_out, int32_t wedge_max)
 {
     char err[256];
     double period[2] = {period_x, period_y};
     int *rowptr, *col, *wedge, n_wall;
-    double *gx, *gy, *cc, *area;
+    real *gx, *gy, *cc, *area;
     int rc = fv_geometry(nn, nt, xy, tri, kind, period, &rowptr, &col, &gx, &gy, &cc, &area, &n_wall, &wedge, err);
     if (rc) return rc;
     int nnz = rowptr[nn];
@@ -442,11 +463,11 @@ int or_fv_geometry(int32_t nn, int32_t nt, const double *xy, const int32_t *tri,
 /* ------------------------------------------------------------------ */
 
 /* barycentric coordinates of (x, y) in triangle t */
-static void barycentric(const double *xy, const int32_t *tri, int t, double x, double y, double *lam)
+static void barycentric(const real *xy, const int32_t *tri, int t, double x, double y, real *lam)
 {
     int a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
-    double x1 = xy[2 * a], y1 = xy[2 * a + 1], x2 = xy[2 * b], y2 = xy[2 * b + 1], x3 = xy[2 * c], y3 = xy[2 * c + 1];
-    double det = (x2 - x1) * (y3 - y1) - (x3 - x1) * (y2 - y1);
+    real x1 = xy[2 * a], y1 = xy[2 * a + 1], x2 = xy[2 * b], y2 = xy[2 * b + 1], x3 = xy[2 * c], y3 = xy[2 * c + 1];
+    real det = (x2 - x1) * (y3 - y1) - (x3 - x1) * (y2 - y1);
     lam[1] = ((x - x1) * (y3 - y1) - (x3 - x1) * (y - y1)) / det;
     lam[2] = ((x2 - x1) * (y - y1) - (x - x1) * (y2 - y1)) / det;
     lam[0] = 1.0 - lam[1] - lam[2];
@@ -461,12 +482,12 @@ typedef struct {
     int *n2t_ptr, *n2t;   /* triangles around each node */
 } search_t;
 
-static void search_build(int nn, int nt, const double *xy, const int32_t *tri, search_t *S)
+static void search_build(int nn, int nt, const real *xy, const int32_t *tri, search_t *S)
 {
     double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
     for (int p = 0; p < nn; ++p) {
-        xmin = fmin(xmin, xy[2 * p]); xmax = fmax(xmax, xy[2 * p]);
-        ymin = fmin(ymin, xy[2 * p + 1]); ymax = fmax(ymax, xy[2 * p + 1]);
+        xmin = fmin(xmin, RE(xy[2 * p])); xmax = fmax(xmax, RE(xy[2 * p]));
+        ymin = fmin(ymin, RE(xy[2 * p + 1])); ymax = fmax(ymax, RE(xy[2 * p + 1]));
     }
     double h = sqrt((xmax - xmin) * (ymax - ymin) / (nt > 0 ? nt : 1)) * 2.0;
     if (!(h > 0)) h = 1.0;
@@ -477,8 +498,8 @@ static void search_build(int nn, int nt, const double *xy, const int32_t *tri, s
     for (int pass = 0; pass < 2; ++pass) {
         for (int t = 0; t < nt; ++t) {
             int a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
-            double bx0 = fmin(xy[2 * a], fmin(xy[2 * b], xy[2 * c])) - 1e-9, bx1 = fmax(xy[2 * a], fmax(xy[2 * b], xy[2 * c])) + 1e-9;
-            double by0 = fmin(xy[2 * a + 1], fmin(xy[2 * b + 1], xy[2 * c + 1])) - 1e-9, by1 = fmax(xy[2 * a + 1], fmax(xy[2 * b + 1], xy[2 * c + 1])) + 1e-9;
+            double bx0 = fmin(RE(xy[2 * a]), fmin(RE(xy[2 * b]), RE(xy[2 * c]))) - 1e-9, bx1 = fmax(RE(xy[2 * a]), fmax(RE(xy[2 * b]), RE(xy[2 * c]))) + 1e-9;
+            double by0 = fmin(RE(xy[2 * a + 1]), fmin(RE(xy[2 * b + 1]), RE(xy[2 * c + 1]))) - 1e-9, by1 = fmax(RE(xy[2 * a + 1]), fmax(RE(xy[2 * b + 1]), RE(xy[2 * c + 1]))) + 1e-9;
             int i0 = (int)floor((bx0 - S->x0) / h), i1 = (int)floor((bx1 - S->x0) / h);
             int j0 = (int)floor((by0 - S->y0) / h), j1 = (int)floor((by1 - S->y0) / h);
             if (i0 < 0) i0 = 0;
@@ -511,17 +532,17 @@ static void search_free(search_t *S)
 /* Point location: every triangle whose barycentric coordinates at (x, y) are
  * all >= -1e-12 (one inside a triangle, two on an edge, more at a vertex), in
  * increasing index.  Returns the count (at most cap). */
-static int locate_all(const search_t *S, const double *xy, const int32_t *tri, double x, double y,
-                      int *ts, double *lams, int cap)
+static int locate_all(const search_t *S, const real *xy, const int32_t *tri, double x, double y,
+                      int *ts, real *lams, int cap)
 {
     int i = (int)floor((x - S->x0) / S->h), j = (int)floor((y - S->y0) / S->h);
     if (i < 0 || j < 0 || i >= S->nbx || j >= S->nby) return 0;
     int bk = j * S->nbx + i, n = 0;
     for (int a = S->ptr[bk]; a < S->ptr[bk + 1] && n < cap; ++a) {
         int t = S->lst[a];
-        double lam[3];
+        real lam[3];
         barycentric(xy, tri, t, x, y, lam);
-        if (lam[0] >= -1e-12 && lam[1] >= -1e-12 && lam[2] >= -1e-12) {
+        if (RE(lam[0]) >= -1e-12 && RE(lam[1]) >= -1e-12 && RE(lam[2]) >= -1e-12) {
             ts[n] = t;
             lams[3 * n] = lam[0]; lams[3 * n + 1] = lam[1]; lams[3 * n + 2] = lam[2];
             n++;
@@ -549,26 +570,26 @@ static int opposite_vertex(const search_t *S, const int32_t *tri, int t, int a, 
 
 /* Solve the n x n system M w = rhs by Gaussian elimination with partial
  * pivoting.  Returns 0, or -1 when a pivot falls below tol * max|M|. */
-static int solve_dense(int n, double *M, double *rhs, double tol)
+static int solve_dense(int n, real *M, real *rhs, double tol)
 {
     double mx = 0.0;
-    for (int a = 0; a < n * n; ++a) mx = fmax(mx, fabs(M[a]));
+    for (int a = 0; a < n * n; ++a) mx = fmax(mx, fabs(RE(M[a])));
     for (int k = 0; k < n; ++k) {
         int p = k;
-        for (int r = k + 1; r < n; ++r) if (fabs(M[r * n + k]) > fabs(M[p * n + k])) p = r;
-        if (fabs(M[p * n + k]) < tol * mx) return -1;
+        for (int r = k + 1; r < n; ++r) if (fabs(RE(M[r * n + k])) > fabs(RE(M[p * n + k]))) p = r;
+        if (fabs(RE(M[p * n + k])) < tol * mx) return -1;
         if (p != k) {
-            for (int c = 0; c < n; ++c) { double tmp = M[k * n + c]; M[k * n + c] = M[p * n + c]; M[p * n + c] = tmp; }
-            double tmp = rhs[k]; rhs[k] = rhs[p]; rhs[p] = tmp;
+            for (int c = 0; c < n; ++c) { real tmp = M[k * n + c]; M[k * n + c] = M[p * n + c]; M[p * n + c] = tmp; }
+            real tmp = rhs[k]; rhs[k] = rhs[p]; rhs[p] = tmp;
         }
         for (int r = k + 1; r < n; ++r) {
-            double fct = M[r * n + k] / M[k * n + k];
+            real fct = M[r * n + k] / M[k * n + k];
             for (int c = k; c < n; ++c) M[r * n + c] -= fct * M[k * n + c];
             rhs[r] -= fct * rhs[k];
         }
     }
     for (int k = n - 1; k >= 0; --k) {
-        double s = rhs[k];
+        real s = rhs[k];
         for (int c = k + 1; c < n; ++c) s -= M[k * n + c] * rhs[c];
         rhs[k] = s / M[k * n + k];
     }
@@ -580,8 +601,8 @@ static int solve_dense(int n, double *M, double *rhs, double tol)
  * weights reproduce 1, x, y, x^2, xy, y^2 exactly at (x, y).  Falls back to the
  * barycentric weights (linear) when a neighbour is missing or the system is
  * singular, or when linear interpolation is asked for.  Returns 6 or 3. */
-static int stencil_tri(const search_t *S, const double *xy, const int32_t *tri, int t, const double *lam,
-                       double x, double y, int linear, int *don, double *w, int *fallback)
+static int stencil_tri(const search_t *S, const real *xy, const int32_t *tri, int t, const real *lam,
+                       double x, double y, int linear, int *don, real *w, int *fallback)
 {
     int v0 = tri[3 * t], v1 = tri[3 * t + 1], v2 = tri[3 * t + 2];
     if (!linear) {
@@ -590,12 +611,12 @@ static int stencil_tri(const search_t *S, const double *xy, const int32_t *tri, 
         int o20 = opposite_vertex(S, tri, t, v2, v0);
         if (o01 >= 0 && o12 >= 0 && o20 >= 0) {
             int nodes[6] = {v0, v1, v2, o01, o12, o20};
-            double ax = xy[2 * v1] - xy[2 * v0], ay = xy[2 * v1 + 1] - xy[2 * v0 + 1];
-            double bx = xy[2 * v2] - xy[2 * v0], by = xy[2 * v2 + 1] - xy[2 * v0 + 1];
-            double h = sqrt(fabs(ax * by - ay * bx));   /* sqrt(2 * area) */
-            double M[36], rhs[6] = {1, 0, 0, 0, 0, 0};
+            real ax = xy[2 * v1] - xy[2 * v0], ay = xy[2 * v1 + 1] - xy[2 * v0 + 1];
+            real bx = xy[2 * v2] - xy[2 * v0], by = xy[2 * v2 + 1] - xy[2 * v0 + 1];
+            real h = sqrt(ABS_A(ax * by - ay * bx));   /* sqrt(2 * area) */
+            real M[36], rhs[6] = {1, 0, 0, 0, 0, 0};
             for (int k = 0; k < 6; ++k) {
-                double xi = (xy[2 * nodes[k]] - x) / h, eta = (xy[2 * nodes[k] + 1] - y) / h;
+                real xi = (xy[2 * nodes[k]] - x) / h, eta = (xy[2 * nodes[k] + 1] - y) / h;
                 M[0 * 6 + k] = 1.0;
                 M[1 * 6 + k] = xi;
                 M[2 * 6 + k] = eta;
@@ -622,21 +643,21 @@ static int stencil_tri(const search_t *S, const double *xy, const int32_t *tri, 
  * shared by two triangles takes the mean of the two stencils (any of them
  * reproduces quadratics, and the mean keeps mirror-symmetric meshes
  * symmetric).  Returns the donor count (<= SDON) or -1 outside the mesh. */
-static int stencil_mesh(const search_t *S, const double *xy, const int32_t *tri, double x, double y,
-                        int linear, int *don, double *w, int *fallback)
+static int stencil_mesh(const search_t *S, const real *xy, const int32_t *tri, double x, double y,
+                        int linear, int *don, real *w, int *fallback)
 {
     int ts[8];
-    double lams[24];
+    real lams[24];
     int nt = locate_all(S, xy, tri, x, y, ts, lams, 8);
     *fallback = 0;
     if (nt == 0) return -1;
     for (int r = 0; r < 3; ++r)
-        if (lams[r] >= 1.0 - 1e-12) { don[0] = tri[3 * ts[0] + r]; w[0] = 1.0; return 1; }
+        if (RE(lams[r]) >= 1.0 - 1e-12) { don[0] = tri[3 * ts[0] + r]; w[0] = 1.0; return 1; }
     if (nt > 2) return -1;
     int n = 0;
     for (int a = 0; a < nt; ++a) {
         int d[6];
-        double wt[6];
+        real wt[6];
         int nd = stencil_tri(S, xy, tri, ts[a], lams + 3 * a, x, y, linear, d, wt, fallback);
         for (int k = 0; k < nd; ++k) {
             int found = -1;
@@ -648,8 +669,8 @@ static int stencil_mesh(const search_t *S, const double *xy, const int32_t *tri,
     return n;
 }
 
-int or_stencil6(int32_t nn, int32_t nt, const double *xy, const int32_t *tri, double x, double y, int32_t linear,
-                int32_t *don, double *w)
+int or_stencil6(int32_t nn, int32_t nt, const real *xy, const int32_t *tri, double x, double y, int32_t linear,
+                int32_t *don, real *w)
 {
     int fb, d[SDON];
     search_t S;
@@ -664,13 +685,13 @@ int or_stencil6(int32_t nn, int32_t nt, const double *xy, const int32_t *tri, do
  * centred on the nearest node: tensor product of the quadratic Lagrange
  * polynomials through offsets -1, 0, 1.  Linear: the four nodes of the cell.
  * (x, y) relative to the grid origin, unit spacing.  Outputs node offsets. */
-static int stencil9(double x, double y, int linear, int *di, int *dj, double *w)
+static int stencil9(real x, real y, int linear, int *di, int *dj, real *w)
 {
     if (!linear) {
-        int i = (int)floor(x + 0.5), j = (int)floor(y + 0.5);
-        double s = x - i, t = y - j;
-        double ls[3] = {0.5 * s * (s - 1.0), 1.0 - s * s, 0.5 * s * (s + 1.0)};
-        double lt[3] = {0.5 * t * (t - 1.0), 1.0 - t * t, 0.5 * t * (t + 1.0)};
+        int i = (int)floor(RE(x) + 0.5), j = (int)floor(RE(y) + 0.5);
+        real s = x - i, t = y - j;
+        real ls[3] = {0.5 * s * (s - 1.0), 1.0 - s * s, 0.5 * s * (s + 1.0)};
+        real lt[3] = {0.5 * t * (t - 1.0), 1.0 - t * t, 0.5 * t * (t + 1.0)};
         int k = 0;
         for (int b = 0; b < 3; ++b)
             for (int a = 0; a < 3; ++a) {
@@ -678,8 +699,8 @@ static int stencil9(double x, double y, int linear, int *di, int *dj, double *w)
             }
         return 9;
     }
-    int i = (int)floor(x), j = (int)floor(y);
-    double s = x - i, t = y - j;
+    int i = (int)floor(RE(x)), j = (int)floor(RE(y));
+    real s = x - i, t = y - j;
     di[0] = i; dj[0] = j; w[0] = (1 - s) * (1 - t);
     di[1] = i + 1; dj[1] = j; w[1] = s * (1 - t);
     di[2] = i; dj[2] = j + 1; w[2] = (1 - s) * t;
@@ -687,7 +708,7 @@ static int stencil9(double x, double y, int linear, int *di, int *dj, double *w)
     return 4;
 }
 
-int or_stencil9(double x, double y, int32_t linear, int32_t *di, int32_t *dj, double *w)
+int or_stencil9(double x, double y, int32_t linear, int32_t *di, int32_t *dj, real *w)
 {
     int a[9], b[9];
     int n = stencil9(x, y, linear, a, b, w);
@@ -701,9 +722,9 @@ int or_stencil9(double x, double y, int32_t linear, int32_t *di, int32_t *dj, do
 
 void or_destroy(void *h);
 
-static int default_nsub(double tau_u)
+static int default_nsub(real tau_u)
 {
-    int n = (int)ceil(1.0 / tau_u);
+    int n = (int)ceil(1.0 / RE(tau_u));
     return n > 10 ? n : 10;
 }
 
@@ -715,7 +736,7 @@ void *or_create(const or_cfg *cfg, char *err_out, int32_t err_len)
     o->tau_u = cfg->tau_s - 0.5;
     o->n_sub = cfg->n_sub > 0 ? cfg->n_sub : default_nsub(o->tau_u);
 #define FAIL(...) do { snprintf(o->err, 256, __VA_ARGS__); if (err_out) snprintf(err_out, err_len, "%s", o->err); or_destroy(o); return NULL; } while (0)
-    if (!(cfg->tau_s > 0.5)) FAIL("tau_s must exceed 1/2");
+    if (!(RE(cfg->tau_s) > 0.5)) FAIL("tau_s must exceed 1/2");
     if (cfg->n_refine < 0 || cfg->n_refine > 3) FAIL("n_refine out of range");
     if (cfg->nx_cells > 0) {
         int L = o->L, base_sp = 1 << L;
@@ -736,13 +757,13 @@ void *or_create(const or_cfg *cfg, char *err_out, int32_t err_len)
         }
         /* acoustic scaling: tau_l - 1/2 = (tau_s - 1/2) / 2^(L - l) */
         for (int l = 0; l <= L; ++l) {
-            o->lev[l].tau = 0.5 + (cfg->tau_s - 0.5) / (double)(1 << (L - l));
-            if (!(o->lev[l].tau > 0.5)) FAIL("tau <= 1/2 on level %d", l);
+            o->lev[l].tau = 0.5 + (cfg->tau_s - 0.5) / (real)(1 << (L - l));
+            if (!(RE(o->lev[l].tau) > 0.5)) FAIL("tau <= 1/2 on level %d", l);
             size_t n = (size_t)o->lev[l].nx * o->lev[l].ny;
             o->lev[l].cls = (uint8_t *)calloc(n, 1);
-            o->lev[l].f = (double *)malloc(sizeof(double) * Q * n);
-            o->lev[l].post = (double *)malloc(sizeof(double) * Q * n);
-            o->lev[l].save = (double *)malloc(sizeof(double) * Q * n);
+            o->lev[l].f = (real *)malloc(sizeof(real) * Q * n);
+            o->lev[l].post = (real *)malloc(sizeof(real) * Q * n);
+            o->lev[l].save = (real *)malloc(sizeof(real) * Q * n);
             if (!o->lev[l].f || !o->lev[l].post || !o->lev[l].save) FAIL("oom");
         }
         classify(o);
@@ -750,10 +771,10 @@ void *or_create(const or_cfg *cfg, char *err_out, int32_t err_len)
     /* mesh */
     o->nn = cfg->n_nodes; o->nt = cfg->n_tris;
     if (o->nn > 0) {
-        o->xy = (double *)malloc(sizeof(double) * 2 * o->nn);
+        o->xy = (real *)malloc(sizeof(real) * 2 * o->nn);
         o->tri = (int32_t *)malloc(sizeof(int32_t) * 3 * o->nt);
         o->kind = (uint8_t *)malloc(o->nn);
-        memcpy(o->xy, cfg->xy, sizeof(double) * 2 * o->nn);
+        memcpy(o->xy, cfg->xy, sizeof(real) * 2 * o->nn);
         memcpy(o->tri, cfg->tri, sizeof(int32_t) * 3 * o->nt);
         memcpy(o->kind, cfg->kind, o->nn);
         for (int t = 0; t < 3 * o->nt; ++t)
@@ -761,8 +782,8 @@ void *or_create(const or_cfg *cfg, char *err_out, int32_t err_len)
         int rc = fv_geometry(o->nn, o->nt, o->xy, o->tri, o->kind, cfg->mesh_period, &o->rowptr, &o->col,
                              &o->gx, &o->gy, &o->cc, &o->area, &o->n_wall_edges, &o->wedge, o->err);
         if (rc) FAIL("%s", o->err);
-        o->fu = (double *)malloc(sizeof(double) * Q * o->nn);
-        o->fu_new = (double *)malloc(sizeof(double) * Q * o->nn);
+        o->fu = (real *)malloc(sizeof(real) * Q * o->nn);
+        o->fu_new = (real *)malloc(sizeof(real) * Q * o->nn);
         o->uint_slot = (int *)malloc(sizeof(int) * o->nn);
         int nu = 0;
         for (int p = 0; p < o->nn; ++p) o->uint_slot[p] = o->kind[p] == KIND_INTERP ? nu++ : -1;
@@ -780,7 +801,7 @@ void *or_create(const or_cfg *cfg, char *err_out, int32_t err_len)
         o->n_sint = ns;
         o->sint_ij = (int *)malloc(sizeof(int) * 2 * (ns > 0 ? ns : 1));
         o->sint_don = (int *)malloc(sizeof(int) * SDON * (ns > 0 ? ns : 1));
-        o->sint_w = (double *)malloc(sizeof(double) * SDON * (ns > 0 ? ns : 1));
+        o->sint_w = (real *)malloc(sizeof(real) * SDON * (ns > 0 ? ns : 1));
         int k = 0;
         search_t S;
         search_build(o->nn, o->nt, o->xy, o->tri, &S);
@@ -789,7 +810,7 @@ void *or_create(const or_cfg *cfg, char *err_out, int32_t err_len)
                 if (fl->cls[(size_t)j * fl->nx + i] != CL_INTERP) continue;
                 double x = fl->ox + i * fl->sp, y = fl->oy + j * fl->sp;
                 int don[SDON];
-                double w[SDON];
+                real w[SDON];
                 int fb = 0;
                 int nd = stencil_mesh(&S, o->xy, o->tri, x, y, linear, don, w, &fb);
                 if (nd < 0) { search_free(&S); FAIL("structured interpolation node (%d,%d) lies outside the mesh", i, j); }
@@ -804,11 +825,11 @@ void *or_create(const or_cfg *cfg, char *err_out, int32_t err_len)
         search_free(&S);
         /* mesh interpolation nodes <- finest level, eq. (9) */
         o->uint_don = (int *)malloc(sizeof(int) * 9 * (o->n_uint > 0 ? o->n_uint : 1));
-        o->uint_w = (double *)malloc(sizeof(double) * 9 * (o->n_uint > 0 ? o->n_uint : 1));
+        o->uint_w = (real *)malloc(sizeof(real) * 9 * (o->n_uint > 0 ? o->n_uint : 1));
         for (int s = 0; s < o->n_uint; ++s) {
             int p = o->uint_node[s];
             int di[9], dj[9];
-            double w[9];
+            real w[9];
             int nd = stencil9(o->xy[2 * p] - fl->ox, o->xy[2 * p + 1] - fl->oy, linear, di, dj, w);
             for (int d = 0; d < 9; ++d) {
                 if (d < nd) {
@@ -827,8 +848,8 @@ void *or_create(const or_cfg *cfg, char *err_out, int32_t err_len)
         FAIL("an inactive region needs a mesh");
     }
     /* initial state: f^eq(rho0, u_inf) everywhere, f^eq(rho0, 0) at wall nodes */
-    double ux = cfg->u_inf * cos(cfg->aoa), uy = cfg->u_inf * sin(cfg->aoa);
-    double feq[Q], feq0[Q];
+    real ux = cfg->u_inf * cos(cfg->aoa), uy = cfg->u_inf * sin(cfg->aoa);
+    real feq[Q], feq0[Q];
     equilibrium(cfg->rho0, ux, uy, feq);
     equilibrium(cfg->rho0, 0.0, 0.0, feq0);
     for (int l = 0; cfg->nx_cells > 0 && l <= o->L; ++l) {
@@ -845,8 +866,8 @@ void *or_create(const or_cfg *cfg, char *err_out, int32_t err_len)
         for (int q = 0; q < Q; ++q)
             o->fu[(size_t)q * o->nn + p] = (o->kind[p] == KIND_WALL && cfg->wall_bc) ? feq0[q] : feq[q];
     o->hist_cap = 1024;
-    o->cd = (double *)malloc(sizeof(double) * o->hist_cap);
-    o->cl = (double *)malloc(sizeof(double) * o->hist_cap);
+    o->cd = (real *)malloc(sizeof(real) * o->hist_cap);
+    o->cl = (real *)malloc(sizeof(real) * o->hist_cap);
     return o;
 #undef FAIL
 }
@@ -877,7 +898,7 @@ static void record_forces(oracle_t *o);
 static void coarse_to_fine(oracle_t *o, int l, double theta)
 {
     olevel *pa = &o->lev[l], *ch = &o->lev[l + 1];
-    double scale = plant[2] * ch->tau / (2.0 * pa->tau);
+    real scale = plant[2] * ch->tau / (2.0 * pa->tau);
     for (int jc = 0; jc < ch->ny; ++jc)
         for (int ic = 0; ic < ch->nx; ++ic) {
             if (ch->cls[(size_t)jc * ch->nx + ic] != CL_PERIM) continue;
@@ -885,20 +906,20 @@ static void coarse_to_fine(oracle_t *o, int l, double theta)
             if (ic % 2 == 0 && jc % 2 == 0) { pi[0] = ch->i0 + ic / 2; pj[0] = ch->j0 + jc / 2; }
             else if (ic % 2 == 1) { pi[0] = ch->i0 + (ic - 1) / 2; pi[1] = pi[0] + 1; pj[0] = pj[1] = ch->j0 + jc / 2; np = 2; }
             else { pj[0] = ch->j0 + (jc - 1) / 2; pj[1] = pj[0] + 1; pi[0] = pi[1] = ch->i0 + ic / 2; np = 2; }
-            double rho = 0, ux = 0, uy = 0, neq[Q] = {0};
+            real rho = 0, ux = 0, uy = 0, neq[Q] = {0};
             for (int a = 0; a < np; ++a) {
-                double f0[Q], f1[Q], r0, x0, y0, n0[Q], r1, x1, y1, n1[Q];
+                real f0[Q], f1[Q], r0, x0, y0, n0[Q], r1, x1, y1, n1[Q];
                 get_node(pa, pa->save, pi[a], pj[a], f0);
                 get_node(pa, pa->f, pi[a], pj[a], f1);
                 macro_neq(f0, &r0, &x0, &y0, n0);
                 macro_neq(f1, &r1, &x1, &y1, n1);
-                double wa = 1.0 / np;
+                real wa = 1.0 / np;
                 rho += wa * ((1.0 - theta) * r0 + theta * r1);
                 ux += wa * ((1.0 - theta) * x0 + theta * x1);
                 uy += wa * ((1.0 - theta) * y0 + theta * y1);
                 for (int q = 0; q < Q; ++q) neq[q] += wa * ((1.0 - theta) * n0[q] + theta * n1[q]);
             }
-            double feq[Q], pre[Q], post[Q];
+            real feq[Q], pre[Q], post[Q];
             equilibrium(rho, ux, uy, feq);
             for (int q = 0; q < Q; ++q) pre[q] = feq[q] + scale * neq[q];
             for (int q = 0; q < Q; ++q) post[q] = pre[q] - (pre[q] - feq[q]) / ch->tau;
@@ -912,11 +933,11 @@ static void coarse_to_fine(oracle_t *o, int l, double theta)
 static void fine_to_coarse(oracle_t *o, int l)
 {
     olevel *pa = &o->lev[l], *ch = &o->lev[l + 1];
-    double scale = plant[3] * 2.0 * pa->tau / ch->tau;
+    real scale = plant[3] * 2.0 * pa->tau / ch->tau;
     for (int j = 0; j < pa->ny; ++j)
         for (int i = 0; i < pa->nx; ++i) {
             if (pa->cls[(size_t)j * pa->nx + i] != CL_RING) continue;
-            double f[Q], rho, ux, uy, neq[Q], feq[Q], pre[Q], post[Q];
+            real f[Q], rho, ux, uy, neq[Q], feq[Q], pre[Q], post[Q];
             get_node(ch, ch->f, 2 * (i - ch->i0), 2 * (j - ch->j0), f);
             macro_neq(f, &rho, &ux, &uy, neq);
             equilibrium(rho, ux, uy, feq);
@@ -932,21 +953,21 @@ static void fine_to_coarse(oracle_t *o, int l)
 static void mesh_to_structured(oracle_t *o)
 {
     olevel *fl = &o->lev[o->L];
-    double ts = fl->tau;
-    double factor = plant[0] * 2.0 * (ts - 1.0) / (2.0 * ts - 1.0);
+    real ts = fl->tau;
+    real factor = plant[0] * 2.0 * (ts - 1.0) / (2.0 * ts - 1.0);
     for (int s = 0; s < o->n_sint; ++s) {
-        double rho = 0, ux = 0, uy = 0, neq[Q] = {0};
+        real rho = 0, ux = 0, uy = 0, neq[Q] = {0};
         for (int d = 0; d < SDON; ++d) {
             int k = o->sint_don[SDON * s + d];
             if (k < 0) continue;
-            double f[Q], r, x, y, n[Q];
+            real f[Q], r, x, y, n[Q];
             for (int q = 0; q < Q; ++q) f[q] = o->fu[(size_t)q * o->nn + k];
             macro_neq(f, &r, &x, &y, n);
-            double w = o->sint_w[SDON * s + d];
+            real w = o->sint_w[SDON * s + d];
             rho += w * r; ux += w * x; uy += w * y;
             for (int q = 0; q < Q; ++q) neq[q] += w * n[q];
         }
-        double feq[Q], post[Q];
+        real feq[Q], post[Q];
         equilibrium(rho, ux, uy, feq);
         for (int q = 0; q < Q; ++q) post[q] = feq[q] + factor * neq[q];
         put_node(fl, fl->post, o->sint_ij[2 * s], o->sint_ij[2 * s + 1], post);
@@ -960,7 +981,7 @@ static void farfield(oracle_t *o)
 {
     olevel *b = &o->lev[0];
     int nx = b->nx, ny = b->ny;
-    double f[Q];
+    real f[Q];
     if (!o->cfg.channel) {
         for (int i = 1; i < nx - 1; ++i) {
             get_node(b, b->f, i, 1, f); put_node(b, b->f, i, 0, f);
@@ -971,7 +992,7 @@ static void farfield(oracle_t *o)
         for (int i = 1; i < nx - 1; ++i) {
             for (int side = 0; side < 2; ++side) {
                 int jb = side ? ny - 1 : 0, jn = side ? ny - 2 : 1;
-                double rho, ux, uy, neq[Q], feq[Q], out[Q];
+                real rho, ux, uy, neq[Q], feq[Q], out[Q];
                 get_node(b, b->f, i, jn, f);
                 macro_neq(f, &rho, &ux, &uy, neq);
                 equilibrium(rho, 0.0, 0.0, feq);
@@ -980,15 +1001,15 @@ static void farfield(oracle_t *o)
             }
         }
     }
-    double uinx = o->cfg.u_inf * cos(o->cfg.aoa), uiny = o->cfg.u_inf * sin(o->cfg.aoa);
+    real uinx = o->cfg.u_inf * cos(o->cfg.aoa), uiny = o->cfg.u_inf * sin(o->cfg.aoa);
     for (int j = 0; j < ny; ++j) {
-        double fn[Q], rho, ux, uy, neq[Q], feq[Q], out[Q];
+        real fn[Q], rho, ux, uy, neq[Q], feq[Q], out[Q];
         /* inlet: u given, rho from the neighbour */
         get_node(b, b->f, 1, j, fn);
         macro_neq(fn, &rho, &ux, &uy, neq);
-        double ui = uinx, vi = uiny;
+        real ui = uinx, vi = uiny;
         if (o->cfg.channel) {
-            double H = ny - 1.0, y = j;
+            real H = ny - 1.0, y = j;
             ui = 4.0 * o->cfg.u_inf * y * (H - y) / (H * H);
             vi = 0.0;
         }
@@ -1010,13 +1031,13 @@ static void level_step(oracle_t *o, int l)
     olevel *lv = &o->lev[l];
     int nx = lv->nx, ny = lv->ny;
     int periodic = (l == 0 && o->cfg.periodic);
-    memcpy(lv->save, lv->f, sizeof(double) * Q * nx * ny);
+    memcpy(lv->save, lv->f, sizeof(real) * Q * nx * ny);
     /* 1. BGK collision of the active nodes, eq. (1) */
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             if (lv->cls[(size_t)j * nx + i] != CL_ACTIVE) continue;
-            double f[Q], out[Q];
+            real f[Q], out[Q];
             get_node(lv, lv->f, i, j, f);
             bgk(f, lv->tau, out);
             put_node(lv, lv->post, i, j, out);
@@ -1060,19 +1081,19 @@ static void level_step(oracle_t *o, int l)
 /* ------------------------------------------------------------------ */
 
 /* (rho, u, f^neq) at the mesh interpolation nodes from a finest-level array, eq. (9) */
-static void structured_to_mesh(oracle_t *o, const double *src, double *out /* [12 * n_uint] */)
+static void structured_to_mesh(oracle_t *o, const real *src, real *out /* [12 * n_uint] */)
 {
     olevel *fl = &o->lev[o->L];
     for (int s = 0; s < o->n_uint; ++s) {
-        double rho = 0, ux = 0, uy = 0, neq[Q] = {0};
+        real rho = 0, ux = 0, uy = 0, neq[Q] = {0};
         for (int d = 0; d < 9; ++d) {
             int node = o->uint_don[9 * s + d];
             if (node < 0) continue;
             int i = node % fl->nx, j = node / fl->nx;
-            double f[Q], r, x, y, n[Q];
+            real f[Q], r, x, y, n[Q];
             get_node(fl, src, i, j, f);
             macro_neq(f, &r, &x, &y, n);
-            double w = o->uint_w[9 * s + d];
+            real w = o->uint_w[9 * s + d];
             rho += w * r; ux += w * x; uy += w * y;
             for (int q = 0; q < Q; ++q) neq[q] += w * n[q];
         }
@@ -1085,15 +1106,16 @@ static void structured_to_mesh(oracle_t *o, const double *src, double *out /* [1
  * nodes.  star[] holds, for interpolation nodes, f* = f^eq,s + (1 - 1/(2 tau_s))
  * f^neq,s and nstar[] its non-equilibrium part (eq. (6)); every other node
  * contributes its stored value (eq. (7)). */
-static void fv_substep(oracle_t *o, const double *star, const double *nstar)
+static void fv_substep(oracle_t *o, const real *star, const real *nstar)
 {
     int nn = o->nn;
-    double dt = 1.0 / o->n_sub, tau_u = o->tau_u;
-    double *neq_u = (double *)malloc(sizeof(double) * Q * nn);
+    double dt = 1.0 / o->n_sub;
+    real tau_u = o->tau_u;
+    real *neq_u = (real *)malloc(sizeof(real) * Q * nn);
     /* non-equilibrium part of every stored mesh value */
 #pragma omp parallel for schedule(static)
     for (int p = 0; p < nn; ++p) {
-        double f[Q], r, x, y, n[Q];
+        real f[Q], r, x, y, n[Q];
         for (int q = 0; q < Q; ++q) f[q] = o->fu[(size_t)q * nn + p];
         macro_neq(f, &r, &x, &y, n);
         for (int q = 0; q < Q; ++q) neq_u[(size_t)q * nn + p] = n[q];
@@ -1102,17 +1124,17 @@ static void fv_substep(oracle_t *o, const double *star, const double *nstar)
     for (int p = 0; p < nn; ++p) {
         int sp = o->uint_slot[p];
         int use_star = sp >= 0 && star != NULL;
-        double fnew[Q];
+        real fnew[Q];
         for (int q = 0; q < Q; ++q) {
-            double base = use_star ? star[Q * sp + q] : o->fu[(size_t)q * nn + p];
-            double sum_s = 0.0, sum_c = 0.0;
+            real base = use_star ? star[Q * sp + q] : o->fu[(size_t)q * nn + p];
+            real sum_s = 0.0, sum_c = 0.0;
             for (int z = o->rowptr[p]; z < o->rowptr[p + 1]; ++z) {
                 int k = o->col[z];
                 int sk = o->uint_slot[k];
-                double fk, nk;
+                real fk, nk;
                 if (use_star && sk >= 0) { fk = star[Q * sk + q]; nk = nstar[Q * sk + q]; }
                 else { fk = o->fu[(size_t)q * nn + k]; nk = neq_u[(size_t)q * nn + k]; }
-                double s_ik = CX[q] * o->gx[z] + CY[q] * o->gy[z];
+                real s_ik = CX[q] * o->gx[z] + CY[q] * o->gy[z];
                 sum_s += s_ik * fk;
                 sum_c += o->cc[z] * nk;
             }
@@ -1120,7 +1142,7 @@ static void fv_substep(oracle_t *o, const double *star, const double *nstar)
         }
         if (o->kind[p] == KIND_WALL && o->cfg.wall_bc) {
             /* no-slip: u -> 0 keeping rho and f^neq */
-            double r, x, y, feq[Q], feq0[Q];
+            real r, x, y, feq[Q], feq0[Q];
             moments(fnew, &r, &x, &y);
             equilibrium(r, x, y, feq);
             equilibrium(r, 0.0, 0.0, feq0);
@@ -1129,31 +1151,31 @@ static void fv_substep(oracle_t *o, const double *star, const double *nstar)
         for (int q = 0; q < Q; ++q) o->fu_new[(size_t)q * nn + p] = fnew[q];
     }
     free(neq_u);
-    double *tmp = o->fu; o->fu = o->fu_new; o->fu_new = tmp;
+    real *tmp = o->fu; o->fu = o->fu_new; o->fu_new = tmp;
 }
 
 static void mesh_advance(oracle_t *o)
 {
     int nu = o->n_uint;
-    double *s0 = NULL, *s1 = NULL, *star = NULL, *nstar = NULL;
+    real *s0 = NULL, *s1 = NULL, *star = NULL, *nstar = NULL;
     int coupled = o->cfg.nx_cells > 0 && nu > 0;
     if (coupled) {
-        s0 = (double *)malloc(sizeof(double) * 12 * nu);
-        s1 = (double *)malloc(sizeof(double) * 12 * nu);
-        star = (double *)malloc(sizeof(double) * Q * nu);
-        nstar = (double *)malloc(sizeof(double) * Q * nu);
+        s0 = (real *)malloc(sizeof(real) * 12 * nu);
+        s1 = (real *)malloc(sizeof(real) * 12 * nu);
+        star = (real *)malloc(sizeof(real) * Q * nu);
+        nstar = (real *)malloc(sizeof(real) * Q * nu);
         olevel *fl = &o->lev[o->L];
         structured_to_mesh(o, fl->save, s0);   /* time t   */
         structured_to_mesh(o, fl->f, s1);      /* time t+1 */
     }
-    double ts = o->cfg.tau_s;
+    real ts = o->cfg.tau_s;
     for (int m = 0; m < o->n_sub; ++m) {
         if (coupled) {
             double th = (double)m / o->n_sub;
             for (int s = 0; s < nu; ++s) {
-                double v[12];
+                real v[12];
                 for (int a = 0; a < 12; ++a) v[a] = (1.0 - th) * s0[12 * s + a] + th * s1[12 * s + a];
-                double feq[Q];
+                real feq[Q];
                 equilibrium(v[0], v[1], v[2], feq);
                 for (int q = 0; q < Q; ++q) {
                     nstar[Q * s + q] = plant[1] * (1.0 - 1.0 / (2.0 * ts)) * v[3 + q];
@@ -1169,16 +1191,16 @@ static void mesh_advance(oracle_t *o)
 /* Drag and lift, eqs. (10)-(11): momentum flux out of the fluid through the
  * wall edges, sum_i c_i (c_i . N_e) (f_i(a) + f_i(b)) / 2, N_e = outward
  * normal times length; projected on the free-stream direction and its normal. */
-static void wall_force(const oracle_t *o, double *fx, double *fy)
+static void wall_force(const oracle_t *o, real *fx, real *fy)
 {
-    double sx = 0.0, sy = 0.0;
+    real sx = 0.0, sy = 0.0;
     for (int e = 0; e < o->n_wall_edges; ++e) {
         int P = o->wedge[2 * e], Qn = o->wedge[2 * e + 1];
-        double dx = o->xy[2 * Qn] - o->xy[2 * P], dy = o->xy[2 * Qn + 1] - o->xy[2 * P + 1];
-        double nx = dy, ny = -dx;
+        real dx = o->xy[2 * Qn] - o->xy[2 * P], dy = o->xy[2 * Qn + 1] - o->xy[2 * P + 1];
+        real nx = dy, ny = -dx;
         for (int q = 0; q < Q; ++q) {
-            double fa = o->fu[(size_t)q * o->nn + P], fb = o->fu[(size_t)q * o->nn + Qn];
-            double cn = CX[q] * nx + CY[q] * ny;
+            real fa = o->fu[(size_t)q * o->nn + P], fb = o->fu[(size_t)q * o->nn + Qn];
+            real cn = CX[q] * nx + CY[q] * ny;
             sx += CX[q] * cn * 0.5 * (fa + fb);
             sy += CY[q] * cn * 0.5 * (fa + fb);
         }
@@ -1190,14 +1212,14 @@ static void record_forces(oracle_t *o)
 {
     if (o->t >= o->hist_cap) {
         o->hist_cap *= 2;
-        o->cd = (double *)realloc(o->cd, sizeof(double) * o->hist_cap);
-        o->cl = (double *)realloc(o->cl, sizeof(double) * o->hist_cap);
+        o->cd = (real *)realloc(o->cd, sizeof(real) * o->hist_cap);
+        o->cl = (real *)realloc(o->cl, sizeof(real) * o->hist_cap);
     }
-    double fx = 0, fy = 0;
+    real fx = 0, fy = 0;
     if (o->nn > 0) wall_force(o, &fx, &fy);
-    double ca = cos(o->cfg.aoa), sa = sin(o->cfg.aoa);
-    double qd = 0.5 * o->cfg.rho0 * o->cfg.u_inf * o->cfg.u_inf * o->cfg.chord;
-    if (!(qd > 0)) qd = 1.0;
+    real ca = cos(o->cfg.aoa), sa = sin(o->cfg.aoa);
+    real qd = 0.5 * o->cfg.rho0 * o->cfg.u_inf * o->cfg.u_inf * o->cfg.chord;
+    if (!(RE(qd) > 0)) qd = 1.0;
     o->cd[o->t] = (fx * ca + fy * sa) / qd;
     o->cl[o->t] = (-fx * sa + fy * ca) / qd;
     o->t++;
@@ -1221,7 +1243,7 @@ int or_step(void *h, int64_t n_finest)
 }
 
 /* pre-collision populations of level l as [Q][ny][nx]; non-active nodes are zero */
-int or_get_level(void *h, int32_t l, double *out)
+int or_get_level(void *h, int32_t l, real *out)
 {
     oracle_t *o = (oracle_t *)h;
     if (o->cfg.nx_cells <= 0 || l < 0 || l > o->L) return -1;
@@ -1234,26 +1256,26 @@ int or_get_level(void *h, int32_t l, double *out)
 }
 
 /* replaces the pre-collision populations of level l (every node) */
-int or_set_level(void *h, int32_t l, const double *in)
+int or_set_level(void *h, int32_t l, const real *in)
 {
     oracle_t *o = (oracle_t *)h;
     if (o->cfg.nx_cells <= 0 || l < 0 || l > o->L) return -1;
     olevel *lv = &o->lev[l];
-    memcpy(lv->f, in, sizeof(double) * Q * lv->nx * lv->ny);
+    memcpy(lv->f, in, sizeof(real) * Q * lv->nx * lv->ny);
     return 0;
 }
 
-int or_get_mesh(void *h, double *out)
+int or_get_mesh(void *h, real *out)
 {
     oracle_t *o = (oracle_t *)h;
-    memcpy(out, o->fu, sizeof(double) * Q * o->nn);
+    memcpy(out, o->fu, sizeof(real) * Q * o->nn);
     return 0;
 }
 
-int or_set_mesh(void *h, const double *in)
+int or_set_mesh(void *h, const real *in)
 {
     oracle_t *o = (oracle_t *)h;
-    memcpy(o->fu, in, sizeof(double) * Q * o->nn);
+    memcpy(o->fu, in, sizeof(real) * Q * o->nn);
     return 0;
 }
 
@@ -1265,7 +1287,7 @@ int or_level_class(void *h, int32_t l, uint8_t *out)
     return 0;
 }
 
-int64_t or_history(void *h, double *cd, double *cl, int64_t cap)
+int64_t or_history(void *h, real *cd, real *cl, int64_t cap)
 {
     oracle_t *o = (oracle_t *)h;
     int64_t n = o->t < cap ? o->t : cap;
@@ -1285,14 +1307,14 @@ int or_info(void *h, int32_t *ints, double *dbls)
     for (int l = 0; l < 4; ++l) {
         ints[6 + l] = l <= o->L ? o->lev[l].nx : 0;
         ints[10 + l] = l <= o->L ? o->lev[l].ny : 0;
-        dbls[1 + l] = l <= o->L ? o->lev[l].tau : 0.0;
+        dbls[1 + l] = l <= o->L ? RE(o->lev[l].tau) : 0.0;
     }
-    dbls[0] = o->tau_u;
+    dbls[0] = RE(o->tau_u);
     return 0;
 }
 
 /* structured interpolation node stencils: ij[2n], don[8n], w[8n] */
-int or_sint(void *h, int32_t *ij, int32_t *don, double *w)
+int or_sint(void *h, int32_t *ij, int32_t *don, real *w)
 {
     oracle_t *o = (oracle_t *)h;
     for (int s = 0; s < o->n_sint; ++s) {
@@ -1303,7 +1325,7 @@ int or_sint(void *h, int32_t *ij, int32_t *don, double *w)
 }
 
 /* wall force of the current mesh state (not normalised) */
-int or_wall_force(void *h, double *fx, double *fy)
+int or_wall_force(void *h, real *fx, real *fy)
 {
     oracle_t *o = (oracle_t *)h;
     wall_force(o, fx, fy);

@@ -17,15 +17,18 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hlbm_oracle.c")
 LIB = os.path.join(HERE, "libhlbm_oracle.so")
+LIB_CS = os.path.join(HERE, "libhlbm_oracle_cs.so")
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no FMA contraction, OpenMP)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-                               "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
+    """Compile the oracle with gcc (-O2, no FMA contraction, OpenMP): the FP64
+    build and the complex-step build of the same source."""
+    common = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-Wall"]
+    for out, extra in ((LIB, []), (LIB_CS, ["-DOR_COMPLEX_STEP", "-fcx-fortran-rules"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+            tmp = out + ".tmp"
+            subprocess.check_call(common + extra + ["-o", tmp, SRC, "-lm"])
+            os.replace(tmp, out)
     return LIB
 
 
@@ -308,3 +311,151 @@ class Oracle:
         fy = np.zeros(1)
         lib().or_wall_force(self._h, _p(fx), _p(fy))
         return float(fx[0]), float(fy[0])
+
+
+# ---------------------------------------------------------------------------
+# complex-step derivatives (the oracle's reference gradient)
+# ---------------------------------------------------------------------------
+
+class _CfgCS(C.Structure):
+    """or_cfg of the complex-step build: u_inf, aoa, rho0, tau_s and the mesh
+    coordinates are complex (two doubles, real then imaginary)."""
+    _fields_ = [
+        ("nx_cells", C.c_int32), ("ny_cells", C.c_int32), ("n_refine", C.c_int32),
+        ("patch_i0", C.c_int32 * 3), ("patch_j0", C.c_int32 * 3),
+        ("patch_nx", C.c_int32 * 3), ("patch_ny", C.c_int32 * 3),
+        ("periodic", C.c_int32), ("wall_bc", C.c_int32), ("n_sub", C.c_int32), ("interp", C.c_int32),
+        ("u_inf", C.c_double * 2), ("aoa", C.c_double * 2), ("rho0", C.c_double * 2),
+        ("tau_s", C.c_double * 2),
+        ("chord", C.c_double), ("ein", C.c_double * 4), ("mesh_period", C.c_double * 2),
+        ("n_nodes", C.c_int32), ("n_tris", C.c_int32),
+        ("xy", C.c_void_p), ("tri", C.POINTER(C.c_int32)), ("kind", C.POINTER(C.c_uint8)),
+        ("channel", C.c_int32),
+    ]
+
+
+_lib_cs = None
+
+
+def lib_cs():
+    global _lib_cs
+    if _lib_cs is None:
+        if not os.path.exists(LIB_CS):
+            build()
+        L = C.CDLL(LIB_CS)
+        L.or_create.restype = C.c_void_p
+        L.or_create.argtypes = [C.POINTER(_CfgCS), C.c_char_p, C.c_int32]
+        L.or_destroy.argtypes = [C.c_void_p]
+        L.or_step.argtypes = [C.c_void_p, C.c_int64]
+        L.or_step.restype = C.c_int
+        L.or_history.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
+        L.or_history.restype = C.c_int64
+        L.or_get_mesh.argtypes = [C.c_void_p, C.c_void_p]
+        L.or_get_level.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
+        L.or_info.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib_cs = L
+    return _lib_cs
+
+
+def _cplx(v):
+    return (C.c_double * 2)(float(np.real(v)), float(np.imag(v)))
+
+
+class ComplexStepOracle:
+    """The oracle run in complex arithmetic: inputs perturbed by i h v give
+    outputs whose imaginary parts over h are exact directional derivatives.
+
+    aoa, tau_s and the entries of mesh_xy may be complex; everything else is
+    as in ``Oracle``.
+    """
+
+    def __init__(self, *, nx_cells, ny_cells, patches=(), wall_bc=True, n_sub=0, interp="quadratic",
+                 u_inf=0.05, aoa=0.0, rho0=1.0, tau_s=0.6, chord=1.0, inner_ellipse=None,
+                 mesh_xy=None, mesh_tri=None, mesh_kind=None):
+        cfg = _CfgCS()
+        cfg.nx_cells, cfg.ny_cells = nx_cells, ny_cells
+        cfg.n_refine = len(patches)
+        for k, (i0, j0, px, py) in enumerate(patches):
+            cfg.patch_i0[k], cfg.patch_j0[k], cfg.patch_nx[k], cfg.patch_ny[k] = i0, j0, px, py
+        cfg.wall_bc = int(wall_bc)
+        cfg.n_sub = int(n_sub)
+        cfg.interp = 0 if interp == "quadratic" else 1
+        cfg.u_inf, cfg.aoa, cfg.rho0, cfg.tau_s = _cplx(u_inf), _cplx(aoa), _cplx(rho0), _cplx(tau_s)
+        cfg.chord = chord
+        ein = inner_ellipse if inner_ellipse is not None else (0.0, 0.0, 0.0, 0.0)
+        for k in range(4):
+            cfg.ein[k] = float(ein[k])
+        xy = np.ascontiguousarray(mesh_xy, dtype=np.complex128).reshape(-1, 2)
+        tri = np.ascontiguousarray(mesh_tri, dtype=np.int32).reshape(-1, 3)
+        kind = np.ascontiguousarray(mesh_kind, dtype=np.uint8)
+        self._keep = [xy, tri, kind]
+        cfg.n_nodes, cfg.n_tris = xy.shape[0], tri.shape[0]
+        cfg.xy = xy.ctypes.data
+        cfg.tri = tri.ctypes.data_as(C.POINTER(C.c_int32))
+        cfg.kind = kind.ctypes.data_as(C.POINTER(C.c_uint8))
+        self.n_nodes = xy.shape[0]
+        err = C.create_string_buffer(256)
+        h = lib_cs().or_create(C.byref(cfg), err, 256)
+        if not h:
+            raise ValueError("oracle create failed: " + err.value.decode())
+        self._h = h
+        ints = np.zeros(16, np.int32)
+        dbls = np.zeros(8)
+        lib_cs().or_info(self._h, _p(ints), _p(dbls))
+        self.n_levels = int(ints[0])
+        self.n_sub = int(ints[1])
+        self.level_shape = [(int(ints[10 + l]), int(ints[6 + l])) for l in range(self.n_levels)]
+
+    @classmethod
+    def from_workload(cls, w, *, aoa, tau_s, mesh_xy=None, n_sub=0, interp="quadratic"):
+        return cls(nx_cells=w.nx_cells, ny_cells=w.ny_cells, patches=w.patches, n_sub=n_sub or w.n_sub,
+                   interp=interp, u_inf=w.u_inf, aoa=aoa, rho0=w.rho0, tau_s=tau_s, chord=w.chord,
+                   inner_ellipse=w.inner_ellipse, mesh_xy=w.mesh_xy if mesh_xy is None else mesh_xy,
+                   mesh_tri=w.mesh_tri, mesh_kind=w.mesh_kind)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib_cs().or_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int):
+        if lib_cs().or_step(self._h, int(n)):
+            raise ValueError("step count must be a multiple of 2^levels")
+
+    def history(self):
+        n = lib_cs().or_history(self._h, None, None, 0)
+        cd = np.zeros(max(n, 1), np.complex128)
+        cl = np.zeros(max(n, 1), np.complex128)
+        lib_cs().or_history(self._h, _p(cd), _p(cl), n)
+        return cd[:n], cl[:n]
+
+    def get_mesh(self) -> np.ndarray:
+        out = np.zeros((9, self.n_nodes), np.complex128)
+        lib_cs().or_get_mesh(self._h, _p(out))
+        return out
+
+
+def objective_derivative(w, spec, *, aoa=None, tau_s=None, d_aoa=0.0, d_tau=0.0, d_xy=None, n_sub=0,
+                         interp="quadratic", h=1e-30):
+    """(J, dJ) of J = mean_{t0 <= t < t1} (w_cd C_D + w_cl C_L) after spec['t_end']
+    finest steps, with dJ its derivative along (d_aoa, d_tau, d_xy) by the complex
+    step (exact to rounding)."""
+    aoa = w.aoa_rad if aoa is None else aoa
+    tau_s = w.tau_s if tau_s is None else tau_s
+    xy = np.asarray(w.mesh_xy, dtype=np.complex128)
+    if d_xy is not None:
+        xy = xy + 1j * h * np.asarray(d_xy, dtype=np.float64).reshape(xy.shape)
+    o = ComplexStepOracle.from_workload(w, aoa=aoa + 1j * h * d_aoa, tau_s=tau_s + 1j * h * d_tau,
+                                        mesh_xy=xy, n_sub=n_sub, interp=interp)
+    o.step(spec["t_end"])
+    cd, cl = o.history()
+    s = slice(spec["t0"], spec["t1"])
+    J = np.mean(spec["w_cd"] * cd[s] + spec["w_cl"] * cl[s])
+    o.close()
+    return float(J.real), float(J.imag / h)

@@ -820,7 +820,7 @@ void launch_mesh_convert(int prec, int nn, const double* in, void* out, int to_s
 }  // namespace hlbm
 
 // ===========================================================================
-// Discrete adjoint of the single-level hybrid step (FP64).
+// ---- Discrete adjoint kernels (reverse mode, FP64) ----
 //
 // Reverse mode of the forward kernels above, kernel by kernel: every forward
 // scatter becomes a gather over a transposed table, so the adjoint is

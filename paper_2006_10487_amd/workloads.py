@@ -77,6 +77,28 @@ class OMesh:
     outer_axes: Tuple[float, float]
     outer_layer_thickness: float
     surface_index: np.ndarray   # [ns] node index of the wall node j
+    chord: float = 0.0
+    surface_xi: Optional[np.ndarray] = None   # [ns] x/c of surface point j
+    surface_upper: Optional[np.ndarray] = None  # [ns] bool: point j carries the bumps
+    eta: Optional[np.ndarray] = None          # [nl + 1] layer fractions, 0 at the wall, 1 outside
+
+    def bump_tangent(self, peaks) -> np.ndarray:
+        """d(node coordinates)/d(bump amplitudes), shape [len(peaks), n_nodes, 2].
+
+        The bumps displace the upper-surface points in y by c * sum_m a_m b_m(x/c)
+        (leading and trailing edge points excluded) and layer l carries the
+        displacement of its surface point scaled by 1 - eta_l, so the mesh is
+        linear in the amplitudes and this is exact."""
+        ns, nl = self.ns, self.nl
+        out = np.zeros((len(peaks), (nl + 1) * ns, 2))
+        for m, xm in enumerate(peaks):
+            amps = np.zeros(len(peaks))
+            amps[m] = 1.0
+            dy = self.chord * np.where(self.surface_upper, hicks_henne(self.surface_xi, peaks, amps), 0.0)
+            dy[0] = 0.0
+            dy[ns // 2] = 0.0
+            out[m, :, 1] = ((1.0 - self.eta)[:, None] * dy[None, :]).ravel()
+        return out
 
     @property
     def n_nodes(self) -> int:
@@ -194,7 +216,8 @@ def naca0012_omesh(chord: float, le: Tuple[float, float], ns: int, nl: int,
     return OMesh(xy=xy, tri=tri, kind=kind, ns=ns, nl=nl, growth=float(r),
                  centre=(xc, yc), outer_axes=(a_out, b_out),
                  outer_layer_thickness=t_outer,
-                 surface_index=np.arange(ns, dtype=np.int64))
+                 surface_index=np.arange(ns, dtype=np.int64), chord=float(chord),
+                 surface_xi=xi, surface_upper=upper, eta=eta)
 
 
 def _orient_ccw(xy: np.ndarray, tri: np.ndarray) -> np.ndarray:
@@ -375,10 +398,21 @@ def hh_amplitudes(seed: int = 0) -> np.ndarray:
     return np.random.default_rng(seed).uniform(-0.002, 0.002, 8)
 
 
-def naca_re100_c40(aoa_deg: float = 0.0) -> Workload:
-    """Small FP64 case: 240x120 grid, c = 40, Re = 100, 128x16 O-mesh."""
-    return _naca_workload("naca0012_re100_c40_240x120", 240, 120, [], 40.0, 100.0, 0.05,
-                          aoa_deg, 128, 16, 52.0, growth=1.15, steps=2000)
+def naca_re100_c40(aoa_deg: float = 0.0, bumps=None) -> Workload:
+    """Small FP64 case: 240x120 grid, c = 40, Re = 100, 128x16 O-mesh
+    (optionally with Hicks-Henne bumps of the given amplitudes at HH_PEAKS)."""
+    return _naca_workload("naca0012_re100_c40_240x120" + ("_bumps" if bumps is not None else ""), 240, 120,
+                          [], 40.0, 100.0, 0.05, aoa_deg, 128, 16, 52.0, growth=1.15, steps=2000,
+                          bumps=None if bumps is None else np.asarray(bumps, dtype=np.float64))
+
+
+def naca_re100_c40_refined(aoa_deg: float = 0.0, bumps=None) -> Workload:
+    """Small refined case: the c = 40 airfoil on a 120x60 base grid (spacing 2)
+    with one 128x64 box (unit spacing) around a 128x16 O-mesh reaching 20 lu
+    out from the profile."""
+    return _naca_workload("naca0012_re100_c40_120x60_r1" + ("_bumps" if bumps is not None else ""), 120, 60,
+                          [(128, 64)], 40.0, 100.0, 0.05, aoa_deg, 128, 16, 20.0, growth=1.15, steps=2000,
+                          bumps=None if bumps is None else np.asarray(bumps, dtype=np.float64))
 
 
 def naca_re1000_c128(aoa_deg: float = 0.0) -> Workload:
@@ -409,6 +443,7 @@ def naca_re5000_c512() -> Workload:
 
 PRESETS = {
     "naca_re100_c40": naca_re100_c40,
+    "naca_re100_c40_refined": naca_re100_c40_refined,
     "naca_re1000_c128": naca_re1000_c128,
     "naca_re1e4_c256": naca_re1e4_c256,
     "naca_re1000_c128_bumps": naca_re1000_c128_bumps,
