@@ -143,12 +143,15 @@ int hlbm_info(hlbm_ctx *ctx, hlbm_info_t *out);
 
 /* Objective for the discrete adjoint: a run of t_end finest steps from the
  * initial state; J = mean over history entries h in [t0, t1) of
- * w_cd C_D(h) + w_cl C_L(h).  The forward stores the state every ckpt_every
- * steps in the objective workspace (revolve-style checkpointing); the reverse
- * sweep recomputes each segment from its checkpoint. */
+ * w_cd C_D(h) + w_cl C_L(h) (eqs. (10)-(11)).  The forward stores the state
+ * every ckpt_every steps in the objective workspace (revolve-style
+ * checkpointing); the reverse sweep recomputes each segment from its
+ * checkpoint.  mesh_grad != 0 asks the adjoint for d J / d(mesh node
+ * coordinates) as well (shape gradient; needs more workspace). */
 typedef struct {
     int64_t t_end, t0, t1, ckpt_every;
     double w_cd, w_cl;
+    int32_t mesh_grad;
 } hlbm_objective;
 
 /* Device bytes of the objective workspace (checkpoints, one recomputed
@@ -164,10 +167,16 @@ int hlbm_run_objective(hlbm_ctx *ctx, const hlbm_objective *obj, void *d_ckpt, s
 
 /* Discrete adjoint of the last hlbm_run_objective: grad[0] = J_bar dJ/d aoa_rad,
  * grad[1] = J_bar dJ/d tau (finest-level relaxation time; the number of FV
- * sub-steps is held fixed).  Reverse mode over the forward kernels (eqs. (1)-(11)
- * as implemented), FP64 accumulation, deterministic.  Leaves the context in a
+ * sub-steps is held fixed).  With the objective's mesh_grad set, grad_xy
+ * (host, 2 * n_nodes doubles, caller's node order, (x, y) pairs) receives
+ * J_bar dJ/d(mesh coordinates) through the finite-volume coefficients of
+ * eq. (3), the wall normals of eqs. (10)-(11) and the interpolation weights of
+ * eqs. (8)-(9), with node kinds, connectivity, stencil donors and the
+ * inactive structured region held fixed; grad_xy must be NULL otherwise
+ * (HLBM_E_ARG).  Reverse mode over the forward kernels (eqs. (1)-(11) as
+ * implemented), FP64 accumulation, deterministic.  Leaves the context in a
  * mid-run state: run the objective again before another adjoint.  Syncs. */
-int hlbm_adjoint(hlbm_ctx *ctx, double J_bar, double *grad);
+int hlbm_adjoint(hlbm_ctx *ctx, double J_bar, double *grad, double *grad_xy);
 
 /* Kernel classes timed by hlbm_profile_read. */
 enum {

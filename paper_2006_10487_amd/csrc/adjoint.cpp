@@ -31,9 +31,11 @@ struct AdjState {
     int n_ckpt = 0, seg_len = 0, n_slots = 0, nd6 = 0;
     struct {
         size_t ckpt, seg_lev, seg_mesh, seg_prep, sub, awork, abar[2], prebar, mbar[2], zbar, pbar[2], m5bar;
-        size_t partial, acc, tedges, vwall, t5ptr, t5s, t5w, t6node, t6ptr, t6s, t6w, dfeq, total;
+        size_t partial, acc, tedges, vwall, t5ptr, t5s, t5w, t6node, t6ptr, t6s, t6w, dfeq;
+        size_t gbar, vbar, w5bar, w6bar, total;
     } off{};
     bool tables = false, ran = false;
+    std::vector<int32_t> t5map, t6map;   // transposed entry -> index into sint_w / uint_w
     double J = 0.0;
     std::vector<double> cd, cl;
     template <typename T> T* at(size_t o) { return reinterpret_cast<T*>(ws + o); }
@@ -102,6 +104,12 @@ void layout(hlbm_ctx* c, AdjState& a) {
     a.off.t6s = take(std::max<size_t>(p.uint_don.size(), 1) * 4);
     a.off.t6w = take(std::max<size_t>(p.uint_don.size(), 1) * 8);
     a.off.dfeq = take(9 * 8);
+    if (a.obj.mesh_grad) {
+        a.off.gbar = take(size_t(3) * p.ell_width * p.nn * 8);
+        a.off.vbar = take(size_t(2) * std::max(p.n_wall, 1) * 8);
+        a.off.w5bar = take(std::max<size_t>(p.sint_don.size(), 1) * 8);
+        a.off.w6bar = take(std::max<size_t>(p.uint_don.size(), 1) * 8);
+    }
     a.off.total = off;
 }
 
@@ -156,31 +164,41 @@ int upload_tables(hlbm_ctx* c, AdjState& a) {
     // eq. (4) transpose: mesh donor -> (structured interpolation node, weight)
     std::vector<int32_t> t5ptr(nn + 1, 0), t5s;
     std::vector<double> t5w;
+    a.t5map.clear();
     {
-        std::vector<std::vector<std::pair<int, double>>> lst(nn);
+        std::vector<std::vector<std::pair<int, int>>> lst(nn);   // (s, d)
         for (size_t s = 0; s < p.sint_node.size(); ++s)
             for (int d = 0; d < kSDon; ++d) {
                 const int k = p.sint_don[s * kSDon + d];
-                if (k >= 0) lst[k].push_back({int(s), p.sint_w[s * kSDon + d]});
+                if (k >= 0) lst[k].push_back({int(s), d});
             }
         for (int k = 0; k < nn; ++k) {
-            for (auto& pr : lst[k]) t5s.push_back(pr.first), t5w.push_back(pr.second);
+            for (auto& pr : lst[k]) {
+                t5s.push_back(pr.first);
+                t5w.push_back(p.sint_w[size_t(pr.first) * kSDon + pr.second]);
+                a.t5map.push_back(pr.first * kSDon + pr.second);
+            }
             t5ptr[k + 1] = int(t5s.size());
         }
     }
     // eq. (9) transpose: structured donor -> (mesh interpolation slot, weight)
     std::vector<int32_t> t6node, t6ptr{0}, t6s;
     std::vector<double> t6w;
+    a.t6map.clear();
     {
-        std::map<int, std::vector<std::pair<int, double>>> lst;
+        std::map<int, std::vector<std::pair<int, int>>> lst;   // (slot, d)
         for (int s = 0; s < p.n_int; ++s)
             for (int d = 0; d < kUDon; ++d) {
                 const int id = p.uint_don[size_t(s) * kUDon + d];
-                if (id >= 0) lst[id].push_back({s, p.uint_w[size_t(s) * kUDon + d]});
+                if (id >= 0) lst[id].push_back({s, d});
             }
         for (auto& kv : lst) {
             t6node.push_back(kv.first);
-            for (auto& pr : kv.second) t6s.push_back(pr.first), t6w.push_back(pr.second);
+            for (auto& pr : kv.second) {
+                t6s.push_back(pr.first);
+                t6w.push_back(p.uint_w[size_t(pr.first) * kUDon + pr.second]);
+                a.t6map.push_back(pr.first * kUDon + pr.second);
+            }
             t6ptr.push_back(int(t6s.size()));
         }
         a.nd6 = int(t6node.size());
@@ -224,6 +242,11 @@ KAdj make_kadj(hlbm_ctx* c, AdjState& a) {
     K.duin_x = -p.u_inf * std::sin(p.aoa);
     K.duin_y = p.u_inf * std::cos(p.aoa);
     K.partial = a.at<double>(a.off.partial);
+    const bool g = a.obj.mesh_grad != 0;
+    K.gbar = g ? a.at<double>(a.off.gbar) : nullptr;
+    K.vbar = g ? a.at<double>(a.off.vbar) : nullptr;
+    K.w5bar = g ? a.at<double>(a.off.w5bar) : nullptr;
+    K.w6bar = g ? a.at<double>(a.off.w6bar) : nullptr;
     return K;
 }
 
@@ -252,23 +275,23 @@ void reverse_step(hlbm_ctx* c, AdjState& a, const KAdj& K, int64_t t, int k, int
                               reinterpret_cast<const int32_t*>(c->ws + p.off.sint_don), c->ws + p.off.sint_w, Mt,
                               p.nn, 2.0 * (ts - 1.0) / (2.0 * ts - 1.0), s);
     }
-    // force^T (history entry t belongs to the state after step t)
-    if (t >= o.t0 && t < o.t1) {
-        const double span = double(o.t1 - o.t0);
-        const double jcd = o.w_cd / span, jcl = o.w_cl / span;   // times J_bar, applied below via scaling
-        const double qn = 0.5 * p.rho0 * p.u_inf * p.u_inf * p.chord;
-        const double ca = std::cos(p.aoa), sa = std::sin(p.aoa);
-        launch_adj_force(K, a.at<double>(a.off.mbar[mb]), a.at<double>(a.off.vwall), (jcd * ca - jcl * sa) / qn,
-                         (jcd * sa + jcl * ca) / qn, s);
-        // projection directions depend on alpha: dC_D/dalpha = C_L, dC_L/dalpha = -C_D
-        alpha_host += jcd * a.cl[t] - jcl * a.cd[t];
-    }
     // sub-step states M^0..M^n of this step
     const size_t ms = a256(a.mesh_bytes);
     (void)d2d(c, a.ws + a.off.sub, Mt, a.mesh_bytes);
     for (int m = 0; m < p.n_sub; ++m)
         launch_fv_substep(HLBM_FP64, c->km, a.ws + a.off.sub + ms * m, a.ws + a.off.sub + ms * (m + 1), prep0, prep1,
                           double(m) / p.n_sub, s);
+    // force^T (history entry t belongs to the state after step t, M^n)
+    if (t >= o.t0 && t < o.t1) {
+        const double span = double(o.t1 - o.t0);
+        const double jcd = o.w_cd / span, jcl = o.w_cl / span;   // times J_bar, applied below via scaling
+        const double qn = 0.5 * p.rho0 * p.u_inf * p.u_inf * p.chord;
+        const double ca = std::cos(p.aoa), sa = std::sin(p.aoa);
+        launch_adj_force(K, a.at<double>(a.off.mbar[mb]), a.at<double>(a.off.vwall), (jcd * ca - jcl * sa) / qn,
+                         (jcd * sa + jcl * ca) / qn, a.at<double>(a.off.sub + ms * p.n_sub), s);
+        // projection directions depend on alpha: dC_D/dalpha = C_L, dC_L/dalpha = -C_D
+        alpha_host += jcd * a.cl[t] - jcl * a.cd[t];
+    }
     // FV^T, last sub-step first
     const int bn = adj_blocks_nodes(p.nn), bi = adj_blocks_nodes(p.n_int);
     for (int m = p.n_sub - 1; m >= 0; --m) {
@@ -369,10 +392,12 @@ int hlbm_run_objective(hlbm_ctx* c, const hlbm_objective* o, void* d_ckpt, size_
     return hip_check(c, hipGetLastError(), "objective");
 }
 
-int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad) {
+int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad, double* grad_xy) {
     if (!c || !grad) return HLBM_E_ARG;
     if (!c->adj || !c->adj->ran) return set_err(c, HLBM_E_STATE, "hlbm_run_objective must run first");
     AdjState& a = *c->adj;
+    if ((grad_xy != nullptr) != (a.obj.mesh_grad != 0))
+        return set_err(c, HLBM_E_ARG, "grad_xy must be given exactly when the objective asked for mesh_grad");
     const Plan& p = c->p;
     const hlbm_objective& o = a.obj;
     hipStream_t s = c->s;
@@ -384,6 +409,12 @@ int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad) {
     launch_zero(a.at<double>(a.off.pbar[0]), a.prep_bytes / 8, s);
     launch_zero(a.at<double>(a.off.pbar[1]), a.prep_bytes / 8, s);
     launch_zero(a.at<double>(a.off.acc), 2, s);
+    if (a.obj.mesh_grad) {
+        launch_zero(a.at<double>(a.off.gbar), size_t(3) * p.ell_width * p.nn, s);
+        launch_zero(a.at<double>(a.off.vbar), size_t(2) * std::max(p.n_wall, 1), s);
+        launch_zero(a.at<double>(a.off.w5bar), std::max<size_t>(p.sint_don.size(), 1), s);
+        launch_zero(a.at<double>(a.off.w6bar), std::max<size_t>(p.uint_don.size(), 1), s);
+    }
     int ab = 0, mb = 0, pb = 0;
     double alpha_host = 0.0;
     int rc = 0;
@@ -445,6 +476,27 @@ int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad) {
     if (rc) return HLBM_E_DEVICE;
     grad[0] = J_bar * (acc[0] + alpha_host);
     grad[1] = J_bar * acc[1];
+    if (a.obj.mesh_grad) {
+        // coefficient adjoints -> mesh coordinates (host, forward mode per local coordinate)
+        std::vector<double> gb(size_t(3) * p.ell_width * p.nn), vb(size_t(2) * std::max(p.n_wall, 1));
+        std::vector<double> t5(a.t5map.size()), t6(a.t6map.size());
+        std::vector<double> w5(p.sint_w.size(), 0.0), w6(p.uint_w.size(), 0.0);
+        rc |= hip_check(c, hipMemcpyAsync(gb.data(), a.ws + a.off.gbar, gb.size() * 8, hipMemcpyDeviceToHost, s), "gbar");
+        rc |= hip_check(c, hipMemcpyAsync(vb.data(), a.ws + a.off.vbar, vb.size() * 8, hipMemcpyDeviceToHost, s), "vbar");
+        if (!t5.empty())
+            rc |= hip_check(c, hipMemcpyAsync(t5.data(), a.ws + a.off.w5bar, t5.size() * 8, hipMemcpyDeviceToHost, s), "w5bar");
+        if (!t6.empty())
+            rc |= hip_check(c, hipMemcpyAsync(t6.data(), a.ws + a.off.w6bar, t6.size() * 8, hipMemcpyDeviceToHost, s), "w6bar");
+        rc |= hip_check(c, hipStreamSynchronize(s), "mesh grad");
+        if (rc) return HLBM_E_DEVICE;
+        for (size_t z = 0; z < t5.size(); ++z) w5[a.t5map[z]] = t5[z];
+        for (size_t z = 0; z < t6.size(); ++z) w6[a.t6map[z]] = t6[z];
+        std::vector<double> gx(2 * size_t(p.nn), 0.0);
+        std::string err;
+        const int grc = mesh_geometry_adjoint(p, gb.data(), vb.data(), w5.data(), w6.data(), gx.data(), err);
+        if (grc) return set_err(c, grc, err);
+        for (size_t z = 0; z < gx.size(); ++z) grad_xy[z] = J_bar * gx[z];
+    }
     // the context now holds the state at the end of the first segment; restart from t_end
     // requires a new objective run
     a.ran = false;

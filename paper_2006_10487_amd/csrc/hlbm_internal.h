@@ -11,6 +11,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <array>
 #include <string>
 #include <vector>
 
@@ -65,6 +66,10 @@ struct Plan {
     // mesh interpolation nodes <- finest level, eq. (9)
     std::vector<int32_t> uint_don;       // kUDon per slot, finest node i + nx * j, -1 = unused
     std::vector<double> uint_w;
+    // the caller's mesh (caller order), kept for the shape adjoint
+    std::vector<double> mxy;
+    std::vector<int32_t> mtri;
+    std::vector<std::array<int, 2>> mbnd;   // boundary edges, fluid on the left
     // workspace layout (byte offsets)
     struct {
         size_t lev[4][2];
@@ -79,6 +84,15 @@ struct Plan {
 
 // Builds the plan; returns HLBM_OK or an error code with a message.
 int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Plan& p, std::string& err);
+
+// Reverse of the mesh-geometry preprocessing: given the adjoints of the
+// finite-volume coefficients (gbar[(z * nn + P) * 3 + {0,1,2}] for (G_x, G_y, C)
+// of ELL slot z of plan row P), of the half wall normals summed at each wall
+// node (vbar[2 * P + {0,1}]) and of the interpolation weights (w5bar in the
+// layout of sint_w, w6bar in the layout of uint_w), adds d J / d(mesh
+// coordinates) to grad[2 * caller node + {0,1}].  Returns HLBM_OK or an error.
+int mesh_geometry_adjoint(const Plan& p, const double* gbar, const double* vbar, const double* w5bar,
+                          const double* w6bar, double* grad, std::string& err);
 
 // ---------------------------------------------------------------------------
 // device views
@@ -146,10 +160,16 @@ struct KAdj {
     double phi, dphi_dtau;           // 2 (tau - 1)/(2 tau - 1), d/d tau
     double uin_x, uin_y, duin_x, duin_y;  // inlet velocity and d/d alpha
     double* partial;                 // per-block (d alpha, d tau) partial sums
+    // adjoints of the mesh-geometry coefficients, accumulated over the run (null: not wanted)
+    double* gbar;                    // [ell_width][nn][3]: (G_x, G_y, C) of forward ELL slot z of pivot P
+    double* vbar;                    // [n_wall][2]: half wall normals summed at each wall node
+    double* w5bar;                   // eq. (4) weights, per entry of the transposed (donor-major) list
+    double* w6bar;                   // eq. (9) weights, per entry of the transposed (donor-major) list
 };
 
 void launch_zero(double* p, size_t n, hipStream_t s);
-void launch_adj_force(const KAdj& K, double* mbar, const double* vwall, double jx, double jy, hipStream_t s);
+void launch_adj_force(const KAdj& K, double* mbar, const double* vwall, double jx, double jy, const double* fst,
+                      hipStream_t s);
 void launch_adj_fv_a(const KAdj& K, const double* Mrec, const double* ybar, double* zbar, const double* prep0,
                      const double* prep1, double theta, int pslot, hipStream_t s);
 void launch_adj_fv_b(const KAdj& K, const double* Mrec, const double* zbar, double* mbar, hipStream_t s);

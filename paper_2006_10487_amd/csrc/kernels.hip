@@ -907,13 +907,27 @@ __global__ void k_zero(double* p, size_t n) {
 
 // Wall force, eqs. (10)-(11): d J / d f_q(P) = (c_q . j)(c_q . V_P), V_P = half the
 // wall normals of the two wall edges at P, j = drag/lift weights / normaliser.
+// With vbar set, also accumulates d J / d V_P = sum_q (c_q . j) c_q f_q(P) from the
+// mesh state fst the force was taken on.
 __global__ void k_adj_force(int n_wall, int nn, double* __restrict__ mbar, const double* __restrict__ V, double jx,
-                            double jy) {
+                            double jy, const double* __restrict__ fst, double* __restrict__ vbar) {
     const int P = blockIdx.x * blockDim.x + threadIdx.x;
     if (P >= n_wall) return;
 #pragma unroll
     for (int q = 0; q < 9; ++q)
         mbar[size_t(q) * nn + P] += (CX[q] * jx + CY[q] * jy) * (CX[q] * V[2 * P] + CY[q] * V[2 * P + 1]);
+    if (vbar) {
+        double f[9], m0, ux, uy, ax = 0.0, ay = 0.0;
+        load_rec(fst + size_t(P) * kRec, f, m0, ux, uy);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const double a = (CX[q] * jx + CY[q] * jy) * f[q];
+            ax += CX[q] * a;
+            ay += CY[q] * a;
+        }
+        vbar[2 * P] += ax;
+        vbar[2 * P + 1] += ay;
+    }
 }
 
 // star values of one interpolation slot at theta (FP64), with their inputs
@@ -930,9 +944,28 @@ __device__ __forceinline__ void star64(const double* p0, const double* p1, doubl
     }
 }
 
+// value f and non-equilibrium part nq of neighbour k as pivot P's update reads
+// them: the star values of eqs. (5)-(7) between interpolation nodes, else the
+// stored mesh value
+__device__ __forceinline__ void fv_value(const KAdj& K, const double* fin, const double* prep0, const double* prep1,
+                                         double theta, bool pivot_interp, int k, D9& f, D9& nq) {
+    if (pivot_interp && k >= K.M.n_core) {
+        double v[12];
+        const size_t sl = size_t(k - K.M.n_core) * kMacro;
+        star64(prep0 + sl, prep1 + sl, theta, K.cst, v, f, nq);
+    } else {
+        double m0, ux, uy, feq[9];
+        load_rec(fin + size_t(k) * kRec, f, m0, ux, uy);
+        equilibrium<double, false>(m0, m0, ux, uy, feq);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) nq[q] = f[q] - feq[q];
+    }
+}
+
 // FV sub-step adjoint, phase A (per pivot P): recompute the pre-reset update
 // fn_P from M^m, take the wall reset's transpose: zbar_P = R'(fn_P)^T ybar_P;
-// tau enters through Delta t_u / tau_u.
+// tau enters through Delta t_u / tau_u.  With K.gbar set, also accumulates the
+// adjoints of the pivot's coefficients (G_Pk, C_Pk) of this sub-step.
 __global__ __launch_bounds__(256) void k_adj_fv_a(const KAdj K, const double* __restrict__ fin,
                                                   const double* __restrict__ ybar, double* __restrict__ zbar,
                                                   const double* __restrict__ prep0, const double* __restrict__ prep1,
@@ -950,17 +983,7 @@ __global__ __launch_bounds__(256) void k_adj_fv_a(const KAdj K, const double* __
             const int k = e.col;
             if (k < 0) continue;
             double f[9], nq[9];
-            if (pivot_interp && k >= M.n_core) {
-                double v[12];
-                const size_t sl = size_t(k - M.n_core) * kMacro;
-                star64(prep0 + sl, prep1 + sl, theta, K.cst, v, f, nq);
-            } else {
-                double m0, ux, uy, feq[9];
-                load_rec(fin + size_t(k) * kRec, f, m0, ux, uy);
-                equilibrium<double, false>(m0, m0, ux, uy, feq);
-#pragma unroll
-                for (int q = 0; q < 9; ++q) nq[q] = f[q] - feq[q];
-            }
+            fv_value(K, fin, prep0, prep1, theta, pivot_interp, k, f, nq);
             if (z == 0) {
 #pragma unroll
                 for (int q = 0; q < 9; ++q) base[q] = f[q], ss[q] = 0.0, sc[q] = e.c * nq[q];
@@ -998,6 +1021,27 @@ __global__ __launch_bounds__(256) void k_adj_fv_a(const KAdj K, const double* __
         for (int q = 0; q < 9; ++q) {
             zbar[size_t(q) * nn + P] = zb[q];
             dtau += zb[q] * (-sc[q]) * K.ddtt_dtau;
+        }
+        if (K.gbar) {
+            // d fn_q / d G_Pk = Delta t_u c_q (f_kq - f_Pq) (k != P), d fn_q / d C_Pk = -(Delta t_u / tau_u) nq_kq
+            for (int z = 0; z < W; ++z) {
+                const int k = E[size_t(z) * nn + P].col;
+                if (k < 0) continue;
+                double f[9], nq[9];
+                fv_value(K, fin, prep0, prep1, theta, pivot_interp, k, f, nq);
+                double ax = 0.0, ay = 0.0, ac = 0.0;
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    const double d = z == 0 ? 0.0 : zb[q] * (f[q] - base[q]);
+                    ax += CX[q] * d;
+                    ay += CY[q] * d;
+                    ac += zb[q] * nq[q];
+                }
+                double* g = K.gbar + (size_t(z) * nn + P) * 3;
+                g[0] += K.dt * ax;
+                g[1] += K.dt * ay;
+                g[2] -= K.dtt * ac;
+            }
         }
     }
     block_partial(0.0, dtau, K.partial, pslot);
@@ -1166,6 +1210,20 @@ __global__ void k_adj_s2m(const KAdj K, const double* __restrict__ A, int nd, co
     const size_t base = size_t(j) * size_t(L.rs) + i;
 #pragma unroll
     for (int q = 0; q < 9; ++q) prebar[size_t(q) * L.pitch + base] += fb[q];
+    if (K.w6bar) {   // d J / d w_sd = pbar_s . (rho, u, f^neq)(g_d)
+        double mac[12], feq[9];
+        macro64(g, mac[0], mac[1], mac[2]);
+        equilibrium<double, false>(mac[0], mac[0], mac[1], mac[2], feq);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) mac[3 + q] = g[q] - feq[q];
+        for (int z = ptr[d]; z < ptr[d + 1]; ++z) {
+            const double* pb = pbar + size_t(slot[z]) * kMacro;
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < 12; ++m) acc += pb[m] * mac[m];
+            K.w6bar[z] += acc;
+        }
+    }
 }
 
 // Far-field boundary adjoint for one edge node: moves prebar(edge) onto the
@@ -1329,6 +1387,20 @@ __global__ void k_adj_m2s_b(const KAdj K, const double* __restrict__ mf, const i
     macro_neq_adj(f, a, fb);
 #pragma unroll
     for (int q = 0; q < 9; ++q) mbar[size_t(q) * nn + d] += fb[q];
+    if (K.w5bar) {   // d J / d w_sd = m5bar_s . (rho, u, f^neq)(M_d)
+        double mac[12], feq[9];
+        mac[0] = m0, mac[1] = ux, mac[2] = uy;
+        equilibrium<double, false>(m0, m0, ux, uy, feq);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) mac[3 + q] = f[q] - feq[q];
+        for (int z = ptr[d]; z < ptr[d + 1]; ++z) {
+            const double* mb = m5bar + size_t(slot[z]) * kMacro;
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m < 12; ++m) acc += mb[m] * mac[m];
+            K.w5bar[z] += acc;
+        }
+    }
 }
 
 // Angle-of-attack derivative through the initial state: sum over the uniform
@@ -1374,8 +1446,10 @@ int adj_blocks_nodes(int n) { return int(blocks(size_t(n > 0 ? n : 1))); }
 void launch_zero(double* p, size_t n, hipStream_t s) {
     if (n) k_zero<<<blocks(n), 256, 0, s>>>(p, n);
 }
-void launch_adj_force(const KAdj& K, double* mbar, const double* vwall, double jx, double jy, hipStream_t s) {
-    if (K.M.n_wall > 0) k_adj_force<<<blocks(K.M.n_wall), 256, 0, s>>>(K.M.n_wall, K.M.nn, mbar, vwall, jx, jy);
+void launch_adj_force(const KAdj& K, double* mbar, const double* vwall, double jx, double jy, const double* fst,
+                      hipStream_t s) {
+    if (K.M.n_wall > 0)
+        k_adj_force<<<blocks(K.M.n_wall), 256, 0, s>>>(K.M.n_wall, K.M.nn, mbar, vwall, jx, jy, fst, K.vbar);
 }
 void launch_adj_fv_a(const KAdj& K, const double* Mrec, const double* ybar, double* zbar, const double* prep0,
                      const double* prep1, double theta, int pslot, hipStream_t s) {

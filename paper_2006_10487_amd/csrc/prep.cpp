@@ -22,6 +22,7 @@
 #include <numeric>
 #include <queue>
 #include <tuple>
+#include <type_traits>
 
 #include "hlbm_internal.h"
 
@@ -31,14 +32,49 @@ namespace {
 constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
-struct V2 {
-    double x, y;
+// Forward-mode dual number: value and derivative along one seeded input.  The
+// geometry and stencil code below is written once for a scalar type S and
+// evaluated with S = double (the plan) and S = Dual (derivatives of the
+// coefficients with respect to one mesh coordinate, for the shape adjoint).
+struct Dual {
+    double v, d;
 };
-inline V2 operator-(V2 a, V2 b) { return {a.x - b.x, a.y - b.y}; }
-inline V2 operator+(V2 a, V2 b) { return {a.x + b.x, a.y + b.y}; }
-inline V2 operator*(double s, V2 a) { return {s * a.x, s * a.y}; }
-inline double cross(V2 a, V2 b) { return a.x * b.y - a.y * b.x; }
-inline V2 rot_cw(V2 a) { return {a.y, -a.x}; }   // outward normal of a counter-clockwise boundary piece
+inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+inline Dual operator-(Dual a) { return {-a.v, -a.d}; }
+inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+inline Dual operator/(Dual a, Dual b) { return {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)}; }
+inline Dual operator*(double s, Dual a) { return {s * a.v, s * a.d}; }
+inline Dual operator*(Dual a, double s) { return {a.v * s, a.d * s}; }
+inline Dual operator+(Dual a, double b) { return {a.v + b, a.d}; }
+inline Dual operator-(double a, Dual b) { return {a - b.v, -b.d}; }
+inline Dual operator-(Dual a, double b) { return {a.v - b, a.d}; }
+inline Dual& operator+=(Dual& a, Dual b) { return a = a + b; }
+inline Dual& operator-=(Dual& a, Dual b) { return a = a - b; }
+inline Dual& operator*=(Dual& a, Dual b) { return a = a * b; }
+inline Dual operator/(Dual a, double b) { return {a.v / b, a.d / b}; }
+inline double val(double a) { return a; }
+inline double val(Dual a) { return a.v; }
+inline double sqrt_(double a) { return std::sqrt(a); }
+inline Dual sqrt_(Dual a) {
+    const double r = std::sqrt(a.v);
+    return {r, a.d / (2.0 * r)};
+}
+template <class S> inline S abs_(S a) { return val(a) < 0.0 ? -a : a; }
+template <class S> inline S lift(double v);
+template <> inline double lift<double>(double v) { return v; }
+template <> inline Dual lift<Dual>(double v) { return {v, 0.0}; }
+
+template <class S> struct V2T {
+    S x, y;
+};
+template <class S> inline V2T<S> operator-(V2T<S> a, V2T<S> b) { return {a.x - b.x, a.y - b.y}; }
+template <class S> inline V2T<S> operator+(V2T<S> a, V2T<S> b) { return {a.x + b.x, a.y + b.y}; }
+template <class S> inline V2T<S> operator*(double s, V2T<S> a) { return {s * a.x, s * a.y}; }
+template <class S> inline S cross(V2T<S> a, V2T<S> b) { return a.x * b.y - a.y * b.x; }
+// outward normal of a counter-clockwise boundary piece
+template <class S> inline V2T<S> rot_cw(V2T<S> a) { return {a.y, -a.x}; }
+using V2 = V2T<double>;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -62,6 +98,24 @@ struct Entry {
     double gx, gy, c;
 };
 
+// Contributions of corner P (neighbours A, B counter-clockwise) of a triangle of
+// area at to the rows of P: out[0..5] = G parts of (P,P), (P,A), (P,B) (x, y),
+// out[6..8] = C parts of the same entries (before division by A_P).
+template <class S> void corner_terms(V2T<S> p, V2T<S> a, V2T<S> b, S at, S out[9]) {
+    const V2T<S> e = a - p, f = b - p;
+    // segments M_PA -> centroid and centroid -> M_PB of P's piece
+    const V2T<S> n1 = (1.0 / 6.0) * rot_cw((2.0 * f) - e);
+    const V2T<S> n2 = (1.0 / 6.0) * rot_cw(f - (2.0 * e));
+    // hat functions at the two segment midpoints: P 5/12, 5/12; A 5/12, 1/6; B 1/6, 5/12
+    const V2T<S> gP = (5.0 / 12.0) * (n1 + n2);
+    const V2T<S> gA = (5.0 / 12.0) * n1 + (1.0 / 6.0) * n2;
+    const V2T<S> gB = (1.0 / 6.0) * n1 + (5.0 / 12.0) * n2;
+    out[0] = -gP.x, out[1] = -gP.y, out[2] = -gA.x, out[3] = -gA.y, out[4] = -gB.x, out[5] = -gB.y;
+    out[6] = at * (11.0 / 54.0);
+    out[7] = at * (7.0 / 108.0);
+    out[8] = at * (7.0 / 108.0);
+}
+
 // Coefficients of eq. (3) for every node P (caller order), sorted by (P, k):
 // G_Pk = -(1/A_P) sum over control-volume segments of N_seg psi_k(mid_seg),
 // C_Pk = (1/A_P) integral of psi_k over the control volume, psi = linear hat.
@@ -81,17 +135,11 @@ int median_dual(int nn, int nt, const double* xy, const int32_t* tri, std::vecto
         const double at = 0.5 * at2;
         for (int r = 0; r < 3; ++r) {
             const int P = v[r], A = v[(r + 1) % 3], B = v[(r + 2) % 3];
-            const V2 e = P_of(A) - P_of(P), f = P_of(B) - P_of(P);
-            // segments M_PA -> centroid and centroid -> M_PB of P's piece
-            const V2 n1 = (1.0 / 6.0) * rot_cw((2.0 * f) - e);
-            const V2 n2 = (1.0 / 6.0) * rot_cw(f - (2.0 * e));
-            // hat functions at the two segment midpoints: P 5/12, 5/12; A 5/12, 1/6; B 1/6, 5/12
-            const V2 gP = (5.0 / 12.0) * (n1 + n2);
-            const V2 gA = (5.0 / 12.0) * n1 + (1.0 / 6.0) * n2;
-            const V2 gB = (1.0 / 6.0) * n1 + (5.0 / 12.0) * n2;
-            acc.push_back({P, P, -gP.x, -gP.y, at * (11.0 / 54.0)});
-            acc.push_back({P, A, -gA.x, -gA.y, at * (7.0 / 108.0)});
-            acc.push_back({P, B, -gB.x, -gB.y, at * (7.0 / 108.0)});
+            double o[9];
+            corner_terms<double>(P_of(P), P_of(A), P_of(B), at, o);
+            acc.push_back({P, P, o[0], o[1], o[6]});
+            acc.push_back({P, A, o[2], o[3], o[7]});
+            acc.push_back({P, B, o[4], o[5], o[8]});
             area[P] += at / 3.0;
         }
     }
@@ -246,30 +294,32 @@ void build_tri_index(int nn, int nt, const double* xy, const int32_t* tri, TriIn
 }
 
 // barycentric coordinates of (x, y) in triangle t (vertex order of the triangle)
-void bary(const double* xy, const int32_t* tri, int t, double x, double y, double l[3]) {
-    const V2 a{xy[2 * tri[3 * t]], xy[2 * tri[3 * t] + 1]};
-    const V2 b{xy[2 * tri[3 * t + 1]], xy[2 * tri[3 * t + 1] + 1]};
-    const V2 c{xy[2 * tri[3 * t + 2]], xy[2 * tri[3 * t + 2] + 1]};
-    const V2 p{x, y};
-    const double d = cross(b - a, c - a);
+template <class S> void bary(const S* xy, const int32_t* tri, int t, double x, double y, S l[3]) {
+    const V2T<S> a{xy[2 * tri[3 * t]], xy[2 * tri[3 * t] + 1]};
+    const V2T<S> b{xy[2 * tri[3 * t + 1]], xy[2 * tri[3 * t + 1] + 1]};
+    const V2T<S> c{xy[2 * tri[3 * t + 2]], xy[2 * tri[3 * t + 2] + 1]};
+    const V2T<S> p{lift<S>(x), lift<S>(y)};
+    const S d = cross(b - a, c - a);
     l[1] = cross(p - a, c - a) / d;
     l[2] = cross(b - a, p - a) / d;
     l[0] = 1.0 - l[1] - l[2];
 }
 
-// Solves M w = e_0 (6 x 6) by Gauss-Jordan elimination with full pivoting.
-bool solve6(double M[6][6], double w[6]) {
-    double rhs[6] = {1, 0, 0, 0, 0, 0};
+// Solves M w = e_0 (6 x 6) by Gauss-Jordan elimination with full pivoting
+// (pivots chosen on values).
+template <class S> bool solve6(S M[6][6], S w[6]) {
+    S rhs[6];
+    for (int k = 0; k < 6; ++k) rhs[k] = lift<S>(k == 0 ? 1.0 : 0.0);
     int colperm[6] = {0, 1, 2, 3, 4, 5};
     double big = 0;
     for (int r = 0; r < 6; ++r)
-        for (int c = 0; c < 6; ++c) big = std::max(big, std::fabs(M[r][c]));
+        for (int c = 0; c < 6; ++c) big = std::max(big, std::fabs(val(M[r][c])));
     for (int k = 0; k < 6; ++k) {
         int pr = k, pc = k;
         for (int r = k; r < 6; ++r)
             for (int c = k; c < 6; ++c)
-                if (std::fabs(M[r][c]) > std::fabs(M[pr][pc])) pr = r, pc = c;
-        if (std::fabs(M[pr][pc]) < 1e-10 * big) return false;
+                if (std::fabs(val(M[r][c])) > std::fabs(val(M[pr][pc]))) pr = r, pc = c;
+        if (std::fabs(val(M[pr][pc])) < 1e-10 * big) return false;
         if (pr != k) {
             for (int c = 0; c < 6; ++c) std::swap(M[k][c], M[pr][c]);
             std::swap(rhs[k], rhs[pr]);
@@ -278,12 +328,13 @@ bool solve6(double M[6][6], double w[6]) {
             for (int r = 0; r < 6; ++r) std::swap(M[r][k], M[r][pc]);
             std::swap(colperm[k], colperm[pc]);
         }
-        const double inv = 1.0 / M[k][k];
+        const S inv = lift<S>(1.0) / M[k][k];
         for (int c = k; c < 6; ++c) M[k][c] *= inv;
         rhs[k] *= inv;
         for (int r = 0; r < 6; ++r) {
-            if (r == k || M[r][k] == 0.0) continue;
-            const double f = M[r][k];
+            // (a zero factor changes nothing in values; derivatives still flow through it)
+            if (r == k || (val(M[r][k]) == 0.0 && std::is_same<S, double>::value)) continue;
+            const S f = M[r][k];
             for (int c = k; c < 6; ++c) M[r][c] -= f * M[k][c];
             rhs[r] -= f * rhs[k];
         }
@@ -296,8 +347,10 @@ bool solve6(double M[6][6], double w[6]) {
 // eq. (8) through the triangle's vertices and the vertices opposite its three
 // edges in the neighbouring triangles (exact for quadratics); barycentric
 // weights when linear is asked for, a neighbour is missing, or singular.
-int tri_stencil(const TriIndex& T, const double* xy, const int32_t* tri, int t, const double lam[3],
-                double x, double y, bool linear, int* don, double* w, bool& fallback) {
+// Topology and pivoting come from the values; xy may carry derivatives.
+template <class S>
+int tri_stencil(const TriIndex& T, const S* xy, const int32_t* tri, int t, const S lam[3],
+                double x, double y, bool linear, int* don, S* w, bool& fallback) {
     const int v0 = tri[3 * t], v1 = tri[3 * t + 1], v2 = tri[3 * t + 2];
     if (!linear) {
         auto opposite = [&](int a, int b) {
@@ -317,15 +370,15 @@ int tri_stencil(const TriIndex& T, const double* xy, const int32_t* tri, int t, 
         };
         const int nodes[6] = {v0, v1, v2, opposite(v0, v1), opposite(v1, v2), opposite(v2, v0)};
         if (nodes[3] >= 0 && nodes[4] >= 0 && nodes[5] >= 0) {
-            const double h = std::sqrt(std::fabs(cross(V2{xy[2 * v1] - xy[2 * v0], xy[2 * v1 + 1] - xy[2 * v0 + 1]},
-                                                       V2{xy[2 * v2] - xy[2 * v0], xy[2 * v2 + 1] - xy[2 * v0 + 1]})));
-            double M[6][6];
+            const S h = sqrt_(abs_(cross(V2T<S>{xy[2 * v1] - xy[2 * v0], xy[2 * v1 + 1] - xy[2 * v0 + 1]},
+                                         V2T<S>{xy[2 * v2] - xy[2 * v0], xy[2 * v2 + 1] - xy[2 * v0 + 1]})));
+            S M[6][6];
             for (int k = 0; k < 6; ++k) {
-                const double a = (xy[2 * nodes[k]] - x) / h, b = (xy[2 * nodes[k] + 1] - y) / h;
-                const double mono[6] = {1.0, a, b, a * a, a * b, b * b};
+                const S a = (xy[2 * nodes[k]] - x) / h, b = (xy[2 * nodes[k] + 1] - y) / h;
+                const S mono[6] = {lift<S>(1.0), a, b, a * a, a * b, b * b};
                 for (int r = 0; r < 6; ++r) M[r][k] = mono[r];
             }
-            double ww[6];
+            S ww[6];
             if (solve6(M, ww)) {
                 for (int k = 0; k < 6; ++k) don[k] = nodes[k], w[k] = ww[k];
                 return 6;
@@ -341,18 +394,19 @@ int tri_stencil(const TriIndex& T, const double* xy, const int32_t* tri, int t, 
 // Stencil of a structured interpolation node: a node it sits on; the stencil of
 // the triangle containing it; the mean of the two stencils when it lies on the
 // edge shared by two triangles.  Returns donor count or -1 (outside / ambiguous).
-int mesh_stencil(const TriIndex& T, const double* xy, const int32_t* tri, double x, double y, bool linear,
-                 int* don, double* w, bool& fallback) {
+template <class S>
+int mesh_stencil(const TriIndex& T, const S* xy, const int32_t* tri, double x, double y, bool linear,
+                 int* don, S* w, bool& fallback) {
     fallback = false;
     const int bi = int(std::floor((x - T.x0) / T.h)), bj = int(std::floor((y - T.y0) / T.h));
     if (bi < 0 || bj < 0 || bi >= T.nbx || bj >= T.nby) return -1;
     const int b = bj * T.nbx + bi;
     int hits[8], nh = 0;
-    double lams[8][3];
+    S lams[8][3];
     for (int z = T.head[b]; z < T.head[b + 1] && nh < 8; ++z) {
-        double l[3];
+        S l[3];
         bary(xy, tri, T.list[z], x, y, l);
-        if (l[0] >= -1e-12 && l[1] >= -1e-12 && l[2] >= -1e-12) {
+        if (val(l[0]) >= -1e-12 && val(l[1]) >= -1e-12 && val(l[2]) >= -1e-12) {
             hits[nh] = T.list[z];
             std::copy(l, l + 3, lams[nh]);
             ++nh;
@@ -360,16 +414,16 @@ int mesh_stencil(const TriIndex& T, const double* xy, const int32_t* tri, double
     }
     if (nh == 0) return -1;
     for (int r = 0; r < 3; ++r)
-        if (lams[0][r] >= 1.0 - 1e-12) {
+        if (val(lams[0][r]) >= 1.0 - 1e-12) {
             don[0] = tri[3 * hits[0] + r];
-            w[0] = 1.0;
+            w[0] = lift<S>(1.0);
             return 1;
         }
     if (nh > 2) return -1;
     int n = 0;
     for (int a = 0; a < nh; ++a) {
         int d[6];
-        double ww[6];
+        S ww[6];
         const int nd = tri_stencil(T, xy, tri, hits[a], lams[a], x, y, linear, d, ww, fallback);
         for (int k = 0; k < nd; ++k) {
             int slot = -1;
@@ -378,12 +432,40 @@ int mesh_stencil(const TriIndex& T, const double* xy, const int32_t* tri, double
             if (slot < 0) {
                 slot = n++;
                 don[slot] = d[k];
-                w[slot] = 0.0;
+                w[slot] = lift<S>(0.0);
             }
-            w[slot] += ww[k] / nh;
+            w[slot] += ww[k] / double(nh);
         }
     }
     return n;
+}
+
+// Tensor-product weights of eq. (9) at (x, y) relative to the finest origin
+// (unit spacing): quadratic Lagrange on the 3 x 3 block around the nearest
+// node, or bilinear on the cell.  Returns the donor count.
+template <class S> int lagrange9(S x, S y, bool linear, int* di, int* dj, S* w) {
+    if (!linear) {
+        const int ic = int(std::floor(val(x) + 0.5)), jc = int(std::floor(val(y) + 0.5));
+        const S s1 = x - double(ic), t1 = y - double(jc);
+        const S lx[3] = {0.5 * s1 * (s1 - 1.0), (1.0 - s1) * (s1 + 1.0), 0.5 * s1 * (s1 + 1.0)};
+        const S ly[3] = {0.5 * t1 * (t1 - 1.0), (1.0 - t1) * (t1 + 1.0), 0.5 * t1 * (t1 + 1.0)};
+        int nd = 0;
+        for (int b = -1; b <= 1; ++b)
+            for (int a = -1; a <= 1; ++a) {
+                di[nd] = ic + a;
+                dj[nd] = jc + b;
+                w[nd] = lx[a + 1] * ly[b + 1];
+                ++nd;
+            }
+        return nd;
+    }
+    const int ic = int(std::floor(val(x))), jc = int(std::floor(val(y)));
+    const S s1 = x - double(ic), t1 = y - double(jc);
+    di[0] = ic, dj[0] = jc, w[0] = (1.0 - s1) * (1.0 - t1);
+    di[1] = ic + 1, dj[1] = jc, w[1] = s1 * (1.0 - t1);
+    di[2] = ic, dj[2] = jc + 1, w[2] = (1.0 - s1) * t1;
+    di[3] = ic + 1, dj[3] = jc + 1, w[3] = s1 * t1;
+    return 4;
 }
 
 }  // namespace
@@ -537,6 +619,9 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
         std::vector<std::array<int, 2>> bnd;
         int rc = median_dual(nn, nt, m->xy, m->tri, ent, area, bnd, err);
         if (rc) return rc;
+        p.mxy.assign(m->xy, m->xy + 2 * size_t(nn));
+        p.mtri.assign(m->tri, m->tri + 3 * size_t(nt));
+        p.mbnd = bnd;
         std::vector<int> rp(nn + 1, 0), cl(ent.size());
         for (const Entry& e : ent) rp[e.p + 1]++;
         for (int a = 0; a < nn; ++a) rp[a + 1] += rp[a];
@@ -618,30 +703,9 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
         for (int s = 0; s < p.n_int; ++s) {
             const int o = p.perm[p.n_core + s];
             const double x = m->xy[2 * o] - fl.ox, y = m->xy[2 * o + 1] - fl.oy;   // finest spacing is 1
-            int di[9], dj[9], nd;
+            int di[9], dj[9];
             double w[9];
-            if (!linear) {
-                const int ic = int(std::floor(x + 0.5)), jc = int(std::floor(y + 0.5));
-                const double s1 = x - ic, t1 = y - jc;
-                const double lx[3] = {0.5 * s1 * (s1 - 1.0), (1.0 - s1) * (1.0 + s1), 0.5 * s1 * (s1 + 1.0)};
-                const double ly[3] = {0.5 * t1 * (t1 - 1.0), (1.0 - t1) * (1.0 + t1), 0.5 * t1 * (t1 + 1.0)};
-                nd = 0;
-                for (int b = -1; b <= 1; ++b)
-                    for (int a = -1; a <= 1; ++a) {
-                        di[nd] = ic + a;
-                        dj[nd] = jc + b;
-                        w[nd] = lx[a + 1] * ly[b + 1];
-                        ++nd;
-                    }
-            } else {
-                const int ic = int(std::floor(x)), jc = int(std::floor(y));
-                const double s1 = x - ic, t1 = y - jc;
-                di[0] = ic, dj[0] = jc, w[0] = (1 - s1) * (1 - t1);
-                di[1] = ic + 1, dj[1] = jc, w[1] = s1 * (1 - t1);
-                di[2] = ic, dj[2] = jc + 1, w[2] = (1 - s1) * t1;
-                di[3] = ic + 1, dj[3] = jc + 1, w[3] = s1 * t1;
-                nd = 4;
-            }
+            const int nd = lagrange9<double>(x, y, linear, di, dj, w);
             for (int d = 0; d < kUDon; ++d) {
                 if (d < nd) {
                     const bool interior = di[d] >= 1 && dj[d] >= 1 && di[d] <= fl.nx - 2 && dj[d] <= fl.ny - 2;
@@ -702,6 +766,133 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
     p.stage_bytes = std::max(p.stage_bytes, size_t(kQ) * nnp * 8);
     p.off.stage = take(p.stage_bytes);
     p.off.total = off;
+    return HLBM_OK;
+}
+
+int mesh_geometry_adjoint(const Plan& p, const double* gbar, const double* vbar, const double* w5bar,
+                          const double* w6bar, double* grad, std::string& err) {
+    const int nn = p.nn, nt = p.nt;
+    const double* xy = p.mxy.data();
+    const int32_t* tri = p.mtri.data();
+    auto P_of = [&](int v) { return V2{xy[2 * v], xy[2 * v + 1]}; };
+    // control-volume areas, as in the forward
+    std::vector<double> area(nn, 0.0);
+    for (int t = 0; t < nt; ++t) {
+        const int v[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
+        const double at = 0.5 * cross(P_of(v[1]) - P_of(v[0]), P_of(v[2]) - P_of(v[0]));
+        for (int r = 0; r < 3; ++r) area[v[r]] += at / 3.0;
+    }
+    // adjoints of the raw (undivided) row entries and of the areas, keyed by caller ids
+    std::vector<std::vector<std::pair<int, std::array<double, 3>>>> rowbar(nn);
+    std::vector<double> abar(nn, 0.0);
+    for (int P = 0; P < nn; ++P) {
+        const int o = p.perm[P];
+        for (int zz = p.rowptr[P]; zz < p.rowptr[P + 1]; ++zz) {
+            const int z = zz - p.rowptr[P];
+            const double* g = gbar + (size_t(z) * nn + P) * 3;
+            rowbar[o].push_back({p.perm[p.col[zz]], {g[0] / area[o], g[1] / area[o], g[2] / area[o]}});
+            abar[o] -= (g[0] * p.gx[zz] + g[1] * p.gy[zz] + g[2] * p.cc[zz]) / area[o];
+        }
+    }
+    auto rb = [&](int o, int k) -> const std::array<double, 3>& {
+        for (const auto& e : rowbar[o])
+            if (e.first == k) return e.second;
+        static const std::array<double, 3> zero{0.0, 0.0, 0.0};
+        return zero;
+    };
+    // triangle corners: local forward mode over the six vertex coordinates
+    for (int t = 0; t < nt; ++t) {
+        const int v[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
+        for (int c = 0; c < 6; ++c) {
+            V2T<Dual> X[3];
+            for (int a = 0; a < 3; ++a)
+                X[a] = {Dual{xy[2 * v[a]], c == 2 * a ? 1.0 : 0.0}, Dual{xy[2 * v[a] + 1], c == 2 * a + 1 ? 1.0 : 0.0}};
+            const Dual at = 0.5 * cross(X[1] - X[0], X[2] - X[0]);
+            double d = 0.0;
+            for (int r = 0; r < 3; ++r) {
+                const int P = v[r], A = v[(r + 1) % 3], B = v[(r + 2) % 3];
+                Dual o[9];
+                corner_terms<Dual>(X[r], X[(r + 1) % 3], X[(r + 2) % 3], at, o);
+                const auto &bP = rb(P, P), &bA = rb(P, A), &bB = rb(P, B);
+                d += o[0].d * bP[0] + o[1].d * bP[1] + o[6].d * bP[2];
+                d += o[2].d * bA[0] + o[3].d * bA[1] + o[7].d * bA[2];
+                d += o[4].d * bB[0] + o[5].d * bB[1] + o[8].d * bB[2];
+                d += (at.d / 3.0) * abar[P];
+            }
+            grad[2 * v[c / 2] + c % 2] += d;
+        }
+    }
+    // half boundary edges: (P,P) and (Q,Q) get -3/4 nh, (P,Q) and (Q,P) -1/4 nh,
+    // nh = (y_Q - y_P, -(x_Q - x_P)) / 2
+    for (const auto& be : p.mbnd) {
+        const int P = be[0], Q = be[1];
+        double nb[2];
+        for (int a = 0; a < 2; ++a)
+            nb[a] = -0.75 * rb(P, P)[a] - 0.25 * rb(P, Q)[a] - 0.75 * rb(Q, Q)[a] - 0.25 * rb(Q, P)[a];
+        grad[2 * Q + 1] += 0.5 * nb[0];
+        grad[2 * P + 1] -= 0.5 * nb[0];
+        grad[2 * Q] -= 0.5 * nb[1];
+        grad[2 * P] += 0.5 * nb[1];
+    }
+    // wall normals N_e = (y_b - y_a, -(x_b - x_a)); V_P = sum of N_e / 2 over P's wall edges
+    for (size_t e = 0; e < p.wedge.size() / 2; ++e) {
+        const int a = p.wedge[2 * e], b = p.wedge[2 * e + 1];
+        const double nx = 0.5 * (vbar[2 * a] + vbar[2 * b]), ny = 0.5 * (vbar[2 * a + 1] + vbar[2 * b + 1]);
+        const int ao = p.perm[a], bo = p.perm[b];
+        grad[2 * bo + 1] += nx;
+        grad[2 * ao + 1] -= nx;
+        grad[2 * bo] -= ny;
+        grad[2 * ao] += ny;
+    }
+    const bool linear = p.interp == HLBM_INTERP_LINEAR;
+    const LevelPlan& fl = p.lev[p.L];
+    // eq. (4) weights: forward mode per donor coordinate through the same stencil code
+    if (!p.sint_node.empty()) {
+        TriIndex T;
+        build_tri_index(nn, nt, xy, tri, T);
+        std::vector<Dual> xyd(2 * size_t(nn));
+        for (size_t a = 0; a < xyd.size(); ++a) xyd[a] = {xy[a], 0.0};
+        for (size_t s = 0; s < p.sint_node.size(); ++s) {
+            const int id = p.sint_node[s], i = id % fl.nx, j = id / fl.nx;
+            const double x = fl.ox + i * fl.sp, y = fl.oy + j * fl.sp;
+            int don0[kSDon], nd0 = 0;
+            for (int d = 0; d < kSDon; ++d) {
+                const int k = p.sint_don[s * kSDon + d];
+                if (k < 0) break;
+                don0[nd0++] = p.perm[k];
+            }
+            for (int a = 0; a < nd0; ++a)
+                for (int c = 0; c < 2; ++c) {
+                    Dual& seed = xyd[2 * size_t(don0[a]) + c];
+                    seed.d = 1.0;
+                    int don[kSDon];
+                    Dual w[kSDon];
+                    bool fb = false;
+                    const int nd = mesh_stencil<Dual>(T, xyd.data(), tri, x, y, linear, don, w, fb);
+                    seed.d = 0.0;
+                    if (nd != nd0) return fail(err, HLBM_E_STATE, "eq. (4) stencil %zu changed in the shape adjoint", s);
+                    double g = 0.0;
+                    for (int d = 0; d < nd; ++d) {
+                        if (don[d] != don0[d]) return fail(err, HLBM_E_STATE, "eq. (4) stencil %zu changed in the shape adjoint", s);
+                        g += w5bar[s * kSDon + d] * w[d].d;
+                    }
+                    grad[2 * size_t(don0[a]) + c] += g;
+                }
+        }
+    }
+    // eq. (9) weights: each depends on its own mesh node's coordinates only
+    for (int s = 0; s < p.n_int; ++s) {
+        const int o = p.perm[p.n_core + s];
+        for (int c = 0; c < 2; ++c) {
+            const Dual x{xy[2 * o] - fl.ox, c == 0 ? 1.0 : 0.0}, y{xy[2 * o + 1] - fl.oy, c == 1 ? 1.0 : 0.0};
+            int di[9], dj[9];
+            Dual w[9];
+            const int nd = lagrange9<Dual>(x, y, linear, di, dj, w);
+            double g = 0.0;
+            for (int d = 0; d < nd; ++d) g += w6bar[size_t(s) * kUDon + d] * w[d].d;
+            grad[2 * o + c] += g;
+        }
+    }
     return HLBM_OK;
 }
 

@@ -59,7 +59,7 @@ class Mesh(C.Structure):
 
 class Objective(C.Structure):
     _fields_ = [("t_end", C.c_int64), ("t0", C.c_int64), ("t1", C.c_int64), ("ckpt_every", C.c_int64),
-                ("w_cd", C.c_double), ("w_cl", C.c_double)]
+                ("w_cd", C.c_double), ("w_cl", C.c_double), ("mesh_grad", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -105,7 +105,7 @@ def lib():
         L.hlbm_kernel_bench.argtypes = [P, C.c_int, C.c_int, C.POINTER(C.c_double)]
         L.hlbm_objective_workspace_size.argtypes = [P, C.POINTER(Objective), C.POINTER(C.c_size_t)]
         L.hlbm_run_objective.argtypes = [P, C.POINTER(Objective), P, C.c_size_t, C.POINTER(C.c_double)]
-        L.hlbm_adjoint.argtypes = [P, C.c_double, P]
+        L.hlbm_adjoint.argtypes = [P, C.c_double, P, P]
         _lib = L
     return _lib
 
@@ -193,6 +193,7 @@ class HLBM:
             raise HLBMError(rc, last_error())
         self._ctx = ctx
         self.info = self.get_info()
+        self.n_nodes = int(mesh.n_nodes)
 
     @classmethod
     def from_workload(cls, w, *, precision=FP64, interp=INTERP_QUADRATIC, n_sub=0, wall_bc=True,
@@ -278,10 +279,12 @@ class HLBM:
         return ms.value
 
     def run_objective(self, t_end: int, t0: int, t1: int, ckpt_every: int = 100, w_cd: float = 1.0,
-                      w_cl: float = 0.0) -> float:
-        """Run from the initial state and return the windowed mean of w_cd C_D + w_cl C_L."""
+                      w_cl: float = 0.0, mesh_grad: bool = False) -> float:
+        """Run from the initial state and return the windowed mean of w_cd C_D + w_cl C_L.
+
+        mesh_grad: the following adjoint also returns d J / d(mesh coordinates)."""
         import torch
-        o = Objective(int(t_end), int(t0), int(t1), int(ckpt_every), float(w_cd), float(w_cl))
+        o = Objective(int(t_end), int(t0), int(t1), int(ckpt_every), float(w_cd), float(w_cl), int(bool(mesh_grad)))
         n = C.c_size_t(0)
         self._check(lib().hlbm_objective_workspace_size(self._ctx, C.byref(o), C.byref(n)))
         if getattr(self, "obj_ws", None) is None or self.obj_ws.numel() < n.value:
@@ -293,9 +296,18 @@ class HLBM:
         return J.value
 
     def adjoint(self, j_bar: float = 1.0) -> np.ndarray:
-        """[dJ/d aoa_rad, dJ/d tau] of the last run_objective (discrete adjoint)."""
+        """[dJ/d aoa_rad, dJ/d tau] of the last run_objective (discrete adjoint).
+
+        When that objective asked for mesh_grad, d J / d(mesh coordinates) of
+        the caller's nodes is left in ``self.grad_xy`` ([n_nodes, 2])."""
         g = np.zeros(2)
-        self._check(lib().hlbm_adjoint(self._ctx, float(j_bar), _np_ptr(g)))
+        self.grad_xy = None
+        if self._objective.mesh_grad:
+            gxy = np.zeros((self.n_nodes, 2))
+            self._check(lib().hlbm_adjoint(self._ctx, float(j_bar), _np_ptr(g), _np_ptr(gxy)))
+            self.grad_xy = gxy
+        else:
+            self._check(lib().hlbm_adjoint(self._ctx, float(j_bar), _np_ptr(g), None))
         return g
 
     def synchronize(self):
@@ -322,29 +334,43 @@ def strouhal(cl: np.ndarray, chord: float, u_inf: float, steady_tol: float = 1e-
 
 
 def objective_function():
-    """torch.autograd.Function J(aoa_rad, tau) of the HLBM drag/lift objective.
+    """torch.autograd.Function J(aoa_rad, tau, bumps) of the HLBM drag/lift objective.
 
-    Usage: ``J = objective_function().apply(aoa, tau, workload, spec)`` with
-    ``aoa`` and ``tau`` 0-d float64 CPU tensors, ``spec`` a dict with t_end, t0,
-    t1, ckpt_every, w_cd, w_cl.  forward runs the GPU objective; backward runs
-    the discrete adjoint of the same run.
+    Usage: ``J = objective_function().apply(aoa, tau, bumps, build, spec)`` with
+    ``aoa`` and ``tau`` 0-d float64 CPU tensors, ``bumps`` a float64 CPU tensor of
+    Hicks-Henne amplitudes (or None for a fixed shape), ``build`` a callable
+    mapping the amplitudes (numpy array or None) to a workload whose ``omesh``
+    provides ``bump_tangent``, and ``spec`` a dict with t_end, t0, t1,
+    ckpt_every, w_cd, w_cl.  forward runs the GPU objective; backward runs the
+    discrete adjoint of the same run and, for the amplitudes, contracts the
+    mesh-coordinate gradient with the generator's bump tangent.
     """
     import torch
 
     class HLBMObjective(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, aoa, tau, workload, spec):
-            sim = HLBM.from_workload(workload, aoa_rad=float(aoa), tau=float(tau), precision=FP64,
+        def forward(ctx, aoa, tau, bumps, build, spec):
+            amps = None if bumps is None else bumps.detach().cpu().numpy().astype(np.float64)
+            w = build(amps)
+            sim = HLBM.from_workload(w, aoa_rad=float(aoa), tau=float(tau), precision=FP64,
                                      history_len=max(65536, int(spec["t_end"])))
-            J = sim.run_objective(**spec)
-            ctx.sim = sim
+            want_shape = bumps is not None and ctx.needs_input_grad[2]
+            J = sim.run_objective(**spec, mesh_grad=want_shape)
+            ctx.sim, ctx.w, ctx.want_shape = sim, w, want_shape
+            ctx.peaks = getattr(build, "peaks", None)
             return torch.tensor(J, dtype=torch.float64)
 
         @staticmethod
         def backward(ctx, g):
             grad = ctx.sim.adjoint(float(g))
+            gb = None
+            if ctx.want_shape:
+                from . import workloads
+                peaks = ctx.peaks if ctx.peaks is not None else workloads.HH_PEAKS
+                tan = ctx.w.omesh.bump_tangent(peaks)           # [m, n_nodes, 2]
+                gb = torch.tensor(np.einsum("mnk,nk->m", tan, ctx.sim.grad_xy), dtype=torch.float64)
             ctx.sim.close()
             return (torch.tensor(grad[0], dtype=torch.float64), torch.tensor(grad[1], dtype=torch.float64),
-                    None, None)
+                    gb, None, None)
 
     return HLBMObjective
