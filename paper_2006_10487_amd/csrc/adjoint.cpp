@@ -2,16 +2,23 @@
 //
 // Objective: J = mean over finest steps h in [t0, t1) of w_cd C_D(h) + w_cl C_L(h)
 // (eqs. (10)-(11)), for a run of t_end finest steps from the initial state.
-// Gradient: dJ/d(angle of attack) and dJ/d(tau) with the number of FV
-// sub-steps held fixed.  Reverse mode over the exact sequence of GPU kernels
-// of the forward step (single structured level, FP64):
-//   forward   K5 (eq. 4) -> collide-stream -> K6 (eq. 9) -> n FV sub-steps -> force
-//   reverse   force^T -> FV^T (n sub-steps, states recomputed) -> K6^T + collide^T
-//             + boundary^T + pull^T -> K5^T
+// Gradient: dJ/d(angle of attack), dJ/d(tau) with the number of FV sub-steps
+// held fixed, and optionally dJ/d(mesh coordinates).  Reverse mode over the
+// exact sequence of GPU kernels of the forward step (FP64), level by level:
+//   forward level l < L: collide-stream, [coarse -> fine, child step] x 2, fine -> coarse
+//   forward finest:      eq. (4) -> collide-stream -> eq. (9) -> n FV sub-steps -> force
+//   reverse level l < L: [child step^T, (fine -> coarse^T after the second), coarse -> fine^T]
+//                        x 2 (second half first), collide-stream^T with the recorded side values^T
+//   reverse finest:      force^T -> FV^T (n sub-steps, states recomputed) -> eq. (9)^T +
+//                        collide^T + boundary^T + pull^T -> eq. (4)^T
+// The restriction at the end of a level-l step pulls from the child's buffer
+// between its two steps (the input of the second), so its transpose is added
+// to the adjoint of that buffer.
 // Memory: revolve-style two-level checkpointing: the forward stores the state
-// every K steps; the reverse sweep recomputes each K-step segment forward from
-// its checkpoint (storing every step of the segment) and, inside every step,
-// the n sub-step states from the step's mesh state.
+// every K finest steps; the reverse sweep recomputes each K-step segment
+// forward from its checkpoint (recording the input of every step of every
+// level) and, inside every finest step, the n sub-step states from the step's
+// mesh state.
 #include <array>
 #include <cmath>
 #include <cstring>
@@ -24,13 +31,19 @@
 using namespace hlbm;
 
 struct AdjState {
+    static size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
     hlbm_objective obj{};
     char* ws = nullptr;
     size_t bytes = 0;
-    size_t lev_bytes = 0, mesh_bytes = 0, prep_bytes = 0, adjlev_bytes = 0, adjmesh_bytes = 0;
-    int n_ckpt = 0, seg_len = 0, n_slots = 0, nd6 = 0;
+    int L = 0, per = 1;                       // levels - 1; finest steps per base step
+    int n_ckpt = 0, seg_len = 0, seg_base = 0;
+    size_t lev_bytes[4] = {}, side_bytes[4] = {}, mesh_bytes = 0, prep_bytes = 0, adjmesh_bytes = 0;
+    int n_slots = 0, nd6 = 0;
     struct {
-        size_t ckpt, seg_lev, seg_mesh, seg_prep, sub, awork, abar[2], prebar, mbar[2], zbar, pbar[2], m5bar;
+        size_t ckpt, ckpt_stride, ck_lev[4], ck_side[4], ck_mesh, ck_prep;
+        size_t seg_lev[4], seg_side[4], seg_mesh, seg_prep, sub, awork;
+        size_t abar[4][2], prebar[4], sbar[4][2], vperim[4];
+        size_t mbar[2], zbar, pbar[2], m5bar;
         size_t partial, acc, tedges, vwall, t5ptr, t5s, t5w, t6node, t6ptr, t6s, t6w, dfeq;
         size_t gbar, vbar, w5bar, w6bar, total;
     } off{};
@@ -38,60 +51,117 @@ struct AdjState {
     std::vector<int32_t> t5map, t6map;   // transposed entry -> index into sint_w / uint_w
     double J = 0.0;
     std::vector<double> cd, cl;
+    // reverse-sweep state: current slot of each ping-pong pair
+    int ab[4] = {}, sb[4] = {}, mb = 0, pb = 0;
+    int ridx[4] = {};                    // recorder: next snapshot slot per level
+    int rec_rc = 0;
     template <typename T> T* at(size_t o) { return reinterpret_cast<T*>(ws + o); }
+    size_t seg_lev_at(int l, int k) const { return off.seg_lev[l] + a256(lev_bytes[l]) * size_t(k); }
+    size_t seg_side_at(int l, int k, int w) const { return off.seg_side[l] + a256(side_bytes[l]) * size_t(2 * k + w); }
+    size_t seg_mesh_at(int k) const { return off.seg_mesh + a256(mesh_bytes) * size_t(k); }
+    size_t seg_prep_at(int k) const { return off.seg_prep + a256(prep_bytes) * size_t(k); }
 };
 
 namespace {
 
-size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+size_t a256(size_t x) { return AdjState::a256(x); }
 
 int check_supported(hlbm_ctx* c, const hlbm_objective* o) {
     const Plan& p = c->p;
     if (!o) return set_err(c, HLBM_E_ARG, "objective is null");
     if (p.precision != HLBM_FP64) return set_err(c, HLBM_E_ARG, "the adjoint runs in FP64 contexts");
-    if (p.L != 0) return set_err(c, HLBM_E_ARG, "the adjoint covers a single structured level (n_refine = 0)");
+    if (p.periodic) return set_err(c, HLBM_E_ARG, "the adjoint needs the far-field base level");
     if (!p.has_mesh || p.wedge.empty()) return set_err(c, HLBM_E_ARG, "the adjoint needs a mesh with a wall");
+    const int64_t per = int64_t(1) << p.L;
     if (o->t_end <= 0 || o->t0 < 0 || o->t1 <= o->t0 || o->t1 > o->t_end || o->ckpt_every <= 0)
         return set_err(c, HLBM_E_ARG, "objective window must satisfy 0 <= t0 < t1 <= t_end, ckpt_every > 0");
+    if (o->t_end % per || o->ckpt_every % per)
+        return set_err(c, HLBM_E_ARG, "t_end and ckpt_every must be multiples of 2^n_refine");
     if (o->t_end > p.hist_len) return set_err(c, HLBM_E_ARG, "t_end exceeds the force history length");
     return HLBM_OK;
+}
+
+int box_nodes(const LevelPlan& v) { return 2 * ((v.ci1 - v.ci0) + (v.cj1 - v.cj0)); }
+int perim_nodes(const KLevel& C) { return 2 * ((C.nx - 1) + (C.ny - 1)); }
+int ring_nodes(const LevelPlan& v) { return 2 * ((v.ci1 - v.ci0 - 2) + (v.cj1 - v.cj0 - 2)); }
+int bc_blocks(const KLevel& L) {
+    return L.farfield ? adj_blocks_nodes(2 * (L.nx - 2)) + adj_blocks_nodes(2 * (L.ny - 2)) + 1 : 0;
 }
 
 // Workspace layout of the objective run and the reverse sweep.
 void layout(hlbm_ctx* c, AdjState& a) {
     const Plan& p = c->p;
-    const LevelPlan& v = p.lev[0];
     const int K = int(a.obj.ckpt_every);
+    a.L = p.L;
+    a.per = 1 << p.L;
     a.seg_len = K;
+    a.seg_base = K / a.per;
     a.n_ckpt = int((a.obj.t_end + K - 1) / K);
-    a.lev_bytes = size_t(kQ) * v.ny * v.pitch * 8;
+    size_t maxlev = 0;
+    for (int l = 0; l <= p.L; ++l) {
+        a.lev_bytes[l] = size_t(kQ) * p.lev[l].ny * p.lev[l].pitch * 8;
+        a.side_bytes[l] = l < p.L ? size_t(box_nodes(p.lev[l])) * kMacro * 8 : 0;
+        maxlev = std::max(maxlev, a.lev_bytes[l]);
+    }
     a.mesh_bytes = size_t(kRec) * p.nn * 8;
     a.prep_bytes = size_t(std::max(p.n_int, 1)) * kMacro * 8;
-    a.adjlev_bytes = a.lev_bytes;
     a.adjmesh_bytes = size_t(kQ) * p.nn * 8;
-    const size_t ck = a256(a.lev_bytes) + a256(a.mesh_bytes) + a256(a.prep_bytes);
     size_t off = 0;
     auto take = [&](size_t b) { const size_t o = off; off = a256(off + std::max<size_t>(b, 8)); return o; };
+    // one checkpoint: every level's post buffer and side values, the mesh, prep(t)
+    size_t ck = 0;
+    for (int l = 0; l <= p.L; ++l) {
+        a.off.ck_lev[l] = ck;
+        ck += a256(a.lev_bytes[l]);
+        a.off.ck_side[l] = ck;
+        ck += a256(a.side_bytes[l]);
+    }
+    a.off.ck_mesh = ck;
+    ck += a256(a.mesh_bytes);
+    a.off.ck_prep = ck;
+    ck += a256(a.prep_bytes);
+    a.off.ckpt_stride = ck;
     a.off.ckpt = take(ck * a.n_ckpt);
-    a.off.seg_lev = take(a256(a.lev_bytes) * K);
+    // one segment: level l takes seg_base 2^l steps; one more slot for its state after the segment
+    for (int l = 0; l <= p.L; ++l) {
+        const int n = a.seg_base << l;
+        a.off.seg_lev[l] = take(a256(a.lev_bytes[l]) * (n + 1));
+        a.off.seg_side[l] = l < p.L ? take(a256(a.side_bytes[l]) * 2 * n) : 0;
+    }
     a.off.seg_mesh = take(a256(a.mesh_bytes) * K);
     a.off.seg_prep = take(a256(a.prep_bytes) * (K + 1));
     a.off.sub = take(a256(a.mesh_bytes) * (p.n_sub + 1));
-    a.off.awork = take(a.lev_bytes);
-    a.off.abar[0] = take(a.adjlev_bytes);
-    a.off.abar[1] = take(a.adjlev_bytes);
-    a.off.prebar = take(a.adjlev_bytes);
+    a.off.awork = take(maxlev);
+    for (int l = 0; l <= p.L; ++l) {
+        a.off.abar[l][0] = take(a.lev_bytes[l]);
+        a.off.abar[l][1] = take(a.lev_bytes[l]);
+        a.off.prebar[l] = take(a.lev_bytes[l]);
+        if (l < p.L) {
+            a.off.sbar[l][0] = take(a.side_bytes[l]);
+            a.off.sbar[l][1] = take(a.side_bytes[l]);
+            a.off.vperim[l] = take(size_t(perim_nodes(c->kl[l + 1])) * kMacro * 8);
+        }
+    }
     a.off.mbar[0] = take(a.adjmesh_bytes);
     a.off.mbar[1] = take(a.adjmesh_bytes);
     a.off.zbar = take(a.adjmesh_bytes);
     a.off.pbar[0] = take(a.prep_bytes);
     a.off.pbar[1] = take(a.prep_bytes);
     a.off.m5bar = take(std::max<size_t>(p.sint_node.size(), 1) * kMacro * 8);
-    // partial-sum slots of one reverse step (the largest user)
+    // partial-sum slots between two reductions (the largest user)
+    const KLevel& F = c->kl[p.L];
     const int bn = adj_blocks_nodes(p.nn), bi = adj_blocks_nodes(p.n_int);
-    const int bc = adj_blocks_nodes(2 * (v.nx - 2)) + adj_blocks_nodes(2 * (v.ny - 2)) + 1;
-    a.n_slots = p.n_sub * (bn + bi) + adj_blocks_collide(c->kl[0]) + bc +
-                adj_blocks_nodes(int(p.sint_node.size())) + adj_blocks_nodes(int(v.ny) * 9 * v.pitch + p.nn) + 64;
+    const int fine = p.n_sub * (bn + bi) + adj_blocks_collide(F) + bc_blocks(F) +
+                     adj_blocks_nodes(int(p.sint_node.size()));
+    int coarse = 0, init = 0;
+    for (int l = 0; l <= p.L; ++l) {
+        const int cs = adj_blocks_collide(c->kl[l]) + bc_blocks(c->kl[l]);
+        const int tr = l < p.L ? std::max(adj_blocks_nodes(ring_nodes(p.lev[l])), adj_blocks_nodes(perim_nodes(c->kl[l + 1])))
+                               : 0;
+        coarse = std::max(coarse, std::max(cs, tr));
+        init += cs + tr + adj_blocks_nodes(int(c->kl[l].ny * c->kl[l].rs) + p.nn);
+    }
+    a.n_slots = std::max(fine, std::max(coarse, init)) + 64;
     a.off.partial = take(size_t(a.n_slots) * 2 * 8);
     a.off.acc = take(2 * 8);
     a.off.tedges = take(size_t(p.ell_width) * p.nn * 32);
@@ -113,13 +183,8 @@ void layout(hlbm_ctx* c, AdjState& a) {
     a.off.total = off;
 }
 
-size_t ckpt_lev(const AdjState& a, int k) {
-    return a.off.ckpt + size_t(k) * (a256(a.lev_bytes) + a256(a.mesh_bytes) + a256(a.prep_bytes));
-}
-size_t ckpt_mesh(const AdjState& a, int k) { return ckpt_lev(a, k) + a256(a.lev_bytes); }
-size_t ckpt_prep(const AdjState& a, int k) { return ckpt_mesh(a, k) + a256(a.mesh_bytes); }
-
 int d2d(hlbm_ctx* c, void* dst, const void* src, size_t bytes) {
+    if (!bytes) return HLBM_OK;
     return hip_check(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->s), "hipMemcpyAsync");
 }
 
@@ -221,20 +286,24 @@ int upload_tables(hlbm_ctx* c, AdjState& a) {
     return HLBM_OK;
 }
 
-KAdj make_kadj(hlbm_ctx* c, AdjState& a) {
+// d tau_l / d tau_s under acoustic scaling tau_l - 1/2 = (tau_s - 1/2) / 2^(L - l)
+double dtau_level(const Plan& p, int l) { return 1.0 / double(1 << (p.L - l)); }
+
+// Reverse-mode view of level l (the mesh fields are those of the finest level).
+KAdj make_kadj(hlbm_ctx* c, AdjState& a, int l) {
     const Plan& p = c->p;
     KAdj K;
-    K.L = c->kl[0];
+    K.L = c->kl[l];
     K.M = c->km;
     K.tedges = a.ws + a.off.tedges;
-    const double tau = p.tau_s, tu = p.tau_u;
+    const double tau = p.tau_s, tu = p.tau_u, tl = p.lev[l].tau;
     K.dt = p.dt_u;
     K.dtt = p.dt_u / tu;
     K.ddtt_dtau = -p.dt_u / (tu * tu);
     K.cst = 1.0 - 1.0 / (2.0 * tau);
     K.dcst_dtau = 1.0 / (2.0 * tau * tau);
-    K.omega = 1.0 / tau;
-    K.domega_dtau = -1.0 / (tau * tau);
+    K.omega = 1.0 / tl;
+    K.domega_dtau = -dtau_level(p, l) / (tl * tl);
     K.phi = 2.0 * (tau - 1.0) / (2.0 * tau - 1.0);
     K.dphi_dtau = 2.0 / ((2.0 * tau - 1.0) * (2.0 * tau - 1.0));
     K.uin_x = p.u_inf * std::cos(p.aoa);
@@ -250,27 +319,75 @@ KAdj make_kadj(hlbm_ctx* c, AdjState& a) {
     return K;
 }
 
-// One reverse step: adjoint of finest step t, whose stored inputs are segment slot k.
-void reverse_step(hlbm_ctx* c, AdjState& a, const KAdj& K, int64_t t, int k, int& ab, int& mb, int& pb,
-                  double& alpha_host) {
+// Coefficients of the refinement transfers between levels l and l + 1 (the
+// f^neq factors after collision) and their tau derivatives.
+struct Transfer {
+    double c2f, dc2f, f2c, df2c;
+};
+Transfer transfer(const Plan& p, int l) {
+    const double tc = p.lev[l].tau, tf = p.lev[l + 1].tau;
+    const double dc = dtau_level(p, l), df = dtau_level(p, l + 1);
+    Transfer t;
+    t.c2f = (tf - 1.0) / (2.0 * tc);   // (1 - 1/tau_f) tau_f / (2 tau_c)
+    t.dc2f = (df * 2.0 * tc - (tf - 1.0) * 2.0 * dc) / (4.0 * tc * tc);
+    t.f2c = 2.0 * (tc - 1.0) / tf;     // (1 - 1/tau_c) 2 tau_c / tau_f
+    t.df2c = 2.0 * (dc * tf - (tc - 1.0) * df) / (tf * tf);
+    return t;
+}
+
+// Step recorder of the segment recompute (see hlbm_ctx::rec).
+void recorder(hlbm_ctx* c, int ev, int l) {
+    AdjState& a = *c->adj;
+    int& k = a.ridx[l];
+    if (ev == 0) {
+        a.rec_rc |= d2d(c, a.ws + a.seg_lev_at(l, k), c->lev(l, c->cur[l]), a.lev_bytes[l]);
+        a.rec_rc |= d2d(c, a.ws + a.seg_side_at(l, k, 0), c->side(l, c->side_t[l]), a.side_bytes[l]);
+    } else if (ev == 1) {
+        a.rec_rc |= d2d(c, a.ws + a.seg_side_at(l, k, 1), c->side(l, 1 - c->side_t[l]), a.side_bytes[l]);
+        ++k;
+    } else {
+        a.rec_rc |= d2d(c, a.ws + a.seg_lev_at(l, k), c->lev(l, c->cur[l]), a.lev_bytes[l]);
+        a.rec_rc |= d2d(c, a.ws + a.seg_mesh_at(k), c->mesh(c->mesh_cur), a.mesh_bytes);
+        a.rec_rc |= d2d(c, a.ws + a.seg_prep_at(k), c->prep(c->prep_t), a.prep_bytes);
+        ++k;
+    }
+}
+
+// Collide-stream^T of level l (recorded input X, output adjoint Bbar) with the far
+// field^T on the base level: fills prebar (adjoint of the pulled values).
+// Returns the partial slots used from slot on.
+int collide_adj(hlbm_ctx* c, const KAdj& K, const double* X, const double* Bbar, double* prebar, int slot) {
+    launch_adj_collide(K, X, Bbar, prebar, slot, c->s);
+    return adj_blocks_collide(K.L);
+}
+int bc_adj(hlbm_ctx* c, const KAdj& K, const double* X, double* prebar, int slot) {
+    if (!K.L.farfield) return 0;
+    launch_adj_bc(K, X, prebar, slot, c->s);
+    return bc_blocks(K.L);
+}
+
+// One reverse finest step: adjoint of finest step t, whose recorded inputs are segment slot k.
+void reverse_finest(hlbm_ctx* c, AdjState& a, int64_t t, int k, double& alpha_host) {
     const Plan& p = c->p;
     const hlbm_objective& o = a.obj;
+    const int L = p.L;
+    const KAdj K = make_kadj(c, a, L);
     hipStream_t s = c->s;
-    const double* Mt = a.at<double>(a.off.seg_mesh + a256(a.mesh_bytes) * k);
-    const double* prep0 = a.at<double>(a.off.seg_prep + a256(a.prep_bytes) * k);
-    const double* prep1 = a.at<double>(a.off.seg_prep + a256(a.prep_bytes) * (k + 1));
+    const double* Mt = a.at<double>(a.seg_mesh_at(k));
+    const double* prep0 = a.at<double>(a.seg_prep_at(k));
+    const double* prep1 = a.at<double>(a.seg_prep_at(k + 1));
     double* Aw = a.at<double>(a.off.awork);
-    double* Bbar = a.at<double>(a.off.abar[ab]);
-    double* Anew = a.at<double>(a.off.abar[1 - ab]);
-    double* prebar = a.at<double>(a.off.prebar);
-    double* Pcur = a.at<double>(a.off.pbar[pb]);       // adjoint of prep(t+1)
-    double* Pnext = a.at<double>(a.off.pbar[1 - pb]);  // adjoint of prep(t)
+    double* Bbar = a.at<double>(a.off.abar[L][a.ab[L]]);
+    double* Anew = a.at<double>(a.off.abar[L][1 - a.ab[L]]);
+    double* prebar = a.at<double>(a.off.prebar[L]);
+    double* Pcur = a.at<double>(a.off.pbar[a.pb]);       // adjoint of prep(t+1)
+    double* Pnext = a.at<double>(a.off.pbar[1 - a.pb]);  // adjoint of prep(t)
     int slot = 0;
-    // A as read by the collide-stream kernel: stored post(t) with eq. (4) applied
-    (void)d2d(c, Aw, a.ws + a.off.seg_lev + a256(a.lev_bytes) * k, a.lev_bytes);
+    // A as read by the collide-stream kernel: the recorded input with eq. (4) applied
+    (void)d2d(c, Aw, a.ws + a.seg_lev_at(L, k), a.lev_bytes[L]);
     if (!p.sint_node.empty()) {
         const double ts = p.tau_s;
-        launch_mesh_to_struct(HLBM_FP64, c->kl[0], Aw, int(p.sint_node.size()),
+        launch_mesh_to_struct(HLBM_FP64, c->kl[L], Aw, int(p.sint_node.size()),
                               reinterpret_cast<const int32_t*>(c->ws + p.off.sint_node),
                               reinterpret_cast<const int32_t*>(c->ws + p.off.sint_don), c->ws + p.off.sint_w, Mt,
                               p.nn, 2.0 * (ts - 1.0) / (2.0 * ts - 1.0), s);
@@ -284,10 +401,10 @@ void reverse_step(hlbm_ctx* c, AdjState& a, const KAdj& K, int64_t t, int k, int
     // force^T (history entry t belongs to the state after step t, M^n)
     if (t >= o.t0 && t < o.t1) {
         const double span = double(o.t1 - o.t0);
-        const double jcd = o.w_cd / span, jcl = o.w_cl / span;   // times J_bar, applied below via scaling
+        const double jcd = o.w_cd / span, jcl = o.w_cl / span;   // times J_bar, applied at the end
         const double qn = 0.5 * p.rho0 * p.u_inf * p.u_inf * p.chord;
         const double ca = std::cos(p.aoa), sa = std::sin(p.aoa);
-        launch_adj_force(K, a.at<double>(a.off.mbar[mb]), a.at<double>(a.off.vwall), (jcd * ca - jcl * sa) / qn,
+        launch_adj_force(K, a.at<double>(a.off.mbar[a.mb]), a.at<double>(a.off.vwall), (jcd * ca - jcl * sa) / qn,
                          (jcd * sa + jcl * ca) / qn, a.at<double>(a.off.sub + ms * p.n_sub), s);
         // projection directions depend on alpha: dC_D/dalpha = C_L, dC_L/dalpha = -C_D
         alpha_host += jcd * a.cl[t] - jcl * a.cd[t];
@@ -297,22 +414,20 @@ void reverse_step(hlbm_ctx* c, AdjState& a, const KAdj& K, int64_t t, int k, int
     for (int m = p.n_sub - 1; m >= 0; --m) {
         const double th = double(m) / p.n_sub;
         const double* Mm = a.at<double>(a.off.sub + ms * m);
-        launch_adj_fv_a(K, Mm, a.at<double>(a.off.mbar[mb]), a.at<double>(a.off.zbar), prep0, prep1, th, slot, s);
+        launch_adj_fv_a(K, Mm, a.at<double>(a.off.mbar[a.mb]), a.at<double>(a.off.zbar), prep0, prep1, th, slot, s);
         slot += bn;
-        launch_adj_fv_b(K, Mm, a.at<double>(a.off.zbar), a.at<double>(a.off.mbar[1 - mb]), s);
+        launch_adj_fv_b(K, Mm, a.at<double>(a.off.zbar), a.at<double>(a.off.mbar[1 - a.mb]), s);
         if (p.n_int > 0) {
             launch_adj_fv_c(K, a.at<double>(a.off.zbar), prep0, prep1, th, Pnext, Pcur, slot, s);
             slot += bi;
         }
-        mb ^= 1;
+        a.mb ^= 1;
     }
     // collide-stream^T with eq. (9)^T and the boundary conditions^T, then pull^T
-    launch_adj_collide(K, Aw, Bbar, prebar, slot, s);
-    slot += adj_blocks_collide(c->kl[0]);
+    slot += collide_adj(c, K, Aw, Bbar, prebar, slot);
     launch_adj_s2m(K, Aw, a.nd6, a.at<int32_t>(a.off.t6node), a.at<int32_t>(a.off.t6ptr), a.at<int32_t>(a.off.t6s),
                    a.at<double>(a.off.t6w), Pcur, prebar, s);
-    launch_adj_bc(K, Aw, prebar, slot, s);
-    slot += adj_blocks_nodes(2 * (c->kl[0].nx - 2)) + adj_blocks_nodes(2 * (c->kl[0].ny - 2)) + 1;
+    slot += bc_adj(c, K, Aw, prebar, slot);
     launch_adj_push(K, prebar, Anew, s);
     // eq. (4)^T
     if (!p.sint_node.empty()) {
@@ -321,13 +436,125 @@ void reverse_step(hlbm_ctx* c, AdjState& a, const KAdj& K, int64_t t, int k, int
                          reinterpret_cast<const double*>(c->ws + p.off.sint_w), Anew, a.at<double>(a.off.m5bar), slot, s);
         slot += adj_blocks_nodes(int(p.sint_node.size()));
         launch_adj_m2s_b(K, Mt, a.at<int32_t>(a.off.t5ptr), a.at<int32_t>(a.off.t5s), a.at<double>(a.off.t5w),
-                         a.at<double>(a.off.m5bar), a.at<double>(a.off.mbar[mb]), s);
+                         a.at<double>(a.off.m5bar), a.at<double>(a.off.mbar[a.mb]), s);
     }
     launch_reduce_partials(a.at<double>(a.off.partial), slot, a.at<double>(a.off.acc), s);
-    // carried adjoints: post(t), M_t, prep(t)
-    ab ^= 1;
+    // carried adjoints: finest input buffer, M_t, prep(t)
+    a.ab[L] ^= 1;
     launch_zero(Pcur, a.prep_bytes / 8, s);
-    pb ^= 1;
+    a.pb ^= 1;
+}
+
+// Adjoint of step idx (within the segment that starts at finest time ta) of level l.
+void reverse_level(hlbm_ctx* c, AdjState& a, int l, int idx, int64_t ta, double& alpha_host) {
+    const Plan& p = c->p;
+    if (l == p.L) {
+        reverse_finest(c, a, ta + idx, idx, alpha_host);
+        return;
+    }
+    hipStream_t s = c->s;
+    const LevelPlan& v = p.lev[l];
+    const int nxc = v.ci1 - v.ci0, nyc = v.cj1 - v.cj0;
+    const Transfer tr = transfer(p, l);
+    const KAdj K = make_kadj(c, a, l);
+    double* partial = a.at<double>(a.off.partial);
+    double* acc = a.at<double>(a.off.acc);
+    const double* sp = a.at<double>(a.seg_side_at(l, idx, 0));
+    const double* sc = a.at<double>(a.seg_side_at(l, idx, 1));
+    for (int half = 1; half >= 0; --half) {
+        reverse_level(c, a, l + 1, 2 * idx + half, ta, alpha_host);
+        if (half == 1) {
+            // fine -> coarse^T: the restriction pulls from the child's buffer that is the
+            // input of its second step (interior nodes, untouched by the transfers)
+            launch_adj_f2c(c->kl[l], c->kl[l + 1], v.ci0, v.cj0, nxc, nyc,
+                           a.at<double>(a.seg_lev_at(l + 1, 2 * idx + 1)), a.at<double>(a.off.abar[l][a.ab[l]]),
+                           a.at<double>(a.off.abar[l + 1][a.ab[l + 1]]), tr.f2c, tr.df2c, partial, 0, s);
+            launch_reduce_partials(partial, adj_blocks_nodes(ring_nodes(v)), acc, s);
+        }
+        // coarse -> fine^T onto the side values at the parent's two times
+        launch_adj_c2f_a(c->kl[l + 1], sp, sc, 0.5 * half, a.at<double>(a.off.abar[l + 1][a.ab[l + 1]]),
+                         a.at<double>(a.off.vperim[l]), tr.c2f, tr.dc2f, partial, 0, s);
+        launch_adj_c2f_b(nxc, nyc, a.at<double>(a.off.vperim[l]), 0.5 * half, a.at<double>(a.off.sbar[l][1 - a.sb[l]]),
+                         a.at<double>(a.off.sbar[l][a.sb[l]]), s);
+        launch_reduce_partials(partial, adj_blocks_nodes(perim_nodes(c->kl[l + 1])), acc, s);
+    }
+    // collide-stream^T of level l, with the side values it recorded^T and the far field^T
+    const double* X = a.at<double>(a.seg_lev_at(l, idx));
+    double* prebar = a.at<double>(a.off.prebar[l]);
+    int slot = collide_adj(c, K, X, a.at<double>(a.off.abar[l][a.ab[l]]), prebar, 0);
+    launch_adj_side(c->kl[l], v.ci0, v.cj0, nxc, nyc, X, a.at<double>(a.off.sbar[l][a.sb[l]]), prebar, s);
+    slot += bc_adj(c, K, X, prebar, slot);
+    launch_adj_push(K, prebar, a.at<double>(a.off.abar[l][1 - a.ab[l]]), s);
+    launch_reduce_partials(partial, slot, acc, s);
+    a.ab[l] ^= 1;
+    // the side values recorded by this step are consumed; the other slot holds the
+    // adjoint of the values recorded by the previous step
+    launch_zero(a.at<double>(a.off.sbar[l][a.sb[l]]), a.side_bytes[l] / 8, s);
+    a.sb[l] ^= 1;
+}
+
+// Adjoint of the initial state with respect to the angle of attack and tau:
+// the uniform f^eq(rho0, u_inf) fill of every level's previous buffer, its
+// collide-stream, side values and restriction, eq. (9) at t = 0, and the mesh
+// initial values.
+int reverse_initial(hlbm_ctx* c, AdjState& a) {
+    const Plan& p = c->p;
+    hipStream_t s = c->s;
+    const int L = p.L;
+    double* Aw = a.at<double>(a.off.awork);
+    double* partial = a.at<double>(a.off.partial);
+    const double ux = p.u_inf * std::cos(p.aoa), uy = p.u_inf * std::sin(p.aoa);
+    int slot = 0;
+    // finest level: collide-stream^T + eq. (9)^T at prep(0) + far field^T (single level) + pull^T
+    {
+        const KAdj K = make_kadj(c, a, L);
+        double* prebar = a.at<double>(a.off.prebar[L]);
+        launch_fill_uniform(HLBM_FP64, Aw, c->kl[L], p.rho0, ux, uy, s);
+        slot += collide_adj(c, K, Aw, a.at<double>(a.off.abar[L][a.ab[L]]), prebar, slot);
+        launch_adj_s2m(K, Aw, a.nd6, a.at<int32_t>(a.off.t6node), a.at<int32_t>(a.off.t6ptr),
+                       a.at<int32_t>(a.off.t6s), a.at<double>(a.off.t6w), a.at<double>(a.off.pbar[a.pb]), prebar, s);
+        slot += bc_adj(c, K, Aw, prebar, slot);
+        launch_adj_push(K, prebar, a.at<double>(a.off.abar[L][1 - a.ab[L]]), s);
+    }
+    // coarser levels, finest first: restriction^T into the child's fill, side values^T, collide-stream^T
+    for (int l = L - 1; l >= 0; --l) {
+        const LevelPlan& v = p.lev[l];
+        const int nxc = v.ci1 - v.ci0, nyc = v.cj1 - v.cj0;
+        const Transfer tr = transfer(p, l);
+        const KAdj K = make_kadj(c, a, l);
+        double* prebar = a.at<double>(a.off.prebar[l]);
+        launch_fill_uniform(HLBM_FP64, Aw, c->kl[l + 1], p.rho0, ux, uy, s);
+        launch_adj_f2c(c->kl[l], c->kl[l + 1], v.ci0, v.cj0, nxc, nyc, Aw, a.at<double>(a.off.abar[l][a.ab[l]]),
+                       a.at<double>(a.off.abar[l + 1][1 - a.ab[l + 1]]), tr.f2c, tr.df2c, partial, slot, s);
+        slot += adj_blocks_nodes(ring_nodes(v));
+        launch_fill_uniform(HLBM_FP64, Aw, c->kl[l], p.rho0, ux, uy, s);
+        slot += collide_adj(c, K, Aw, a.at<double>(a.off.abar[l][a.ab[l]]), prebar, slot);
+        launch_adj_side(c->kl[l], v.ci0, v.cj0, nxc, nyc, Aw, a.at<double>(a.off.sbar[l][a.sb[l]]), prebar, s);
+        slot += bc_adj(c, K, Aw, prebar, slot);
+        launch_adj_push(K, prebar, a.at<double>(a.off.abar[l][1 - a.ab[l]]), s);
+    }
+    // angle of attack through the fills and the mesh initial values
+    double dfeq[9];
+    const KAdj K0 = make_kadj(c, a, 0);
+    const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    for (int q = 0; q < 9; ++q) {
+        const double cu = cx[q] * ux + cy[q] * uy;
+        dfeq[q] = w[q] * p.rho0 *
+                  ((3.0 * cx[q] + 9.0 * cu * cx[q] - 3.0 * ux) * K0.duin_x +
+                   (3.0 * cy[q] + 9.0 * cu * cy[q] - 3.0 * uy) * K0.duin_y);
+    }
+    int rc = hip_check(c, hipMemcpyAsync(a.ws + a.off.dfeq, dfeq, sizeof(dfeq), hipMemcpyHostToDevice, s), "dfeq");
+    for (int l = 0; l <= L; ++l) {
+        const KAdj K = make_kadj(c, a, l);
+        launch_adj_alpha_state(K, a.at<double>(a.off.abar[l][1 - a.ab[l]]), a.at<double>(a.off.mbar[a.mb]),
+                               a.at<double>(a.off.dfeq), l == L, slot, s);
+        slot += adj_blocks_nodes(int(c->kl[l].ny * c->kl[l].rs) + (l == L ? p.nn : 0));
+    }
+    launch_reduce_partials(partial, slot, a.at<double>(a.off.acc), s);
+    // dfeq is a stack array: wait for its upload before returning
+    rc |= hip_check(c, hipStreamSynchronize(s), "initial state");
+    return rc;
 }
 
 }  // namespace
@@ -369,14 +596,17 @@ int hlbm_run_objective(hlbm_ctx* c, const hlbm_objective* o, void* d_ckpt, size_
     reset_initial_state(c);
     const Plan& p = c->p;
     const int K = int(o->ckpt_every);
-    for (int64_t t = 0; t < o->t_end; ++t) {
+    for (int64_t t = 0; t < o->t_end; t += a.per) {
         if (t % K == 0) {
-            const int k = int(t / K);
-            rc |= d2d(c, a.ws + ckpt_lev(a, k), c->lev(0, c->cur[0]), a.lev_bytes);
-            rc |= d2d(c, a.ws + ckpt_mesh(a, k), c->mesh(c->mesh_cur), a.mesh_bytes);
-            rc |= d2d(c, a.ws + ckpt_prep(a, k), c->prep(c->prep_t), a.prep_bytes);
+            const size_t ck = a.off.ckpt + a.off.ckpt_stride * size_t(t / K);
+            for (int l = 0; l <= p.L; ++l) {
+                rc |= d2d(c, a.ws + ck + a.off.ck_lev[l], c->lev(l, c->cur[l]), a.lev_bytes[l]);
+                if (l < p.L) rc |= d2d(c, a.ws + ck + a.off.ck_side[l], c->side(l, c->side_t[l]), a.side_bytes[l]);
+            }
+            rc |= d2d(c, a.ws + ck + a.off.ck_mesh, c->mesh(c->mesh_cur), a.mesh_bytes);
+            rc |= d2d(c, a.ws + ck + a.off.ck_prep, c->prep(c->prep_t), a.prep_bytes);
         }
-        finest_step(c);
+        level_step(c, 0);
     }
     if (rc) return HLBM_E_DEVICE;
     a.cd.assign(size_t(o->t_end), 0.0);
@@ -388,7 +618,6 @@ int hlbm_run_objective(hlbm_ctx* c, const hlbm_objective* o, void* d_ckpt, size_
     a.J = s / double(o->t1 - o->t0);
     *J = a.J;
     a.ran = true;
-    (void)p;
     return hip_check(c, hipGetLastError(), "objective");
 }
 
@@ -401,9 +630,17 @@ int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad, double* grad_xy) {
     const Plan& p = c->p;
     const hlbm_objective& o = a.obj;
     hipStream_t s = c->s;
-    const KAdj K = make_kadj(c, a);
-    for (double* z : {a.at<double>(a.off.abar[0]), a.at<double>(a.off.abar[1]), a.at<double>(a.off.prebar)})
-        launch_zero(z, a.adjlev_bytes / 8, s);
+    for (int l = 0; l <= p.L; ++l) {
+        launch_zero(a.at<double>(a.off.abar[l][0]), a.lev_bytes[l] / 8, s);
+        launch_zero(a.at<double>(a.off.abar[l][1]), a.lev_bytes[l] / 8, s);
+        launch_zero(a.at<double>(a.off.prebar[l]), a.lev_bytes[l] / 8, s);
+        if (l < p.L) {
+            launch_zero(a.at<double>(a.off.sbar[l][0]), a.side_bytes[l] / 8, s);
+            launch_zero(a.at<double>(a.off.sbar[l][1]), a.side_bytes[l] / 8, s);
+        }
+        a.ab[l] = 0;
+        a.sb[l] = 0;
+    }
     for (double* z : {a.at<double>(a.off.mbar[0]), a.at<double>(a.off.mbar[1]), a.at<double>(a.off.zbar)})
         launch_zero(z, a.adjmesh_bytes / 8, s);
     launch_zero(a.at<double>(a.off.pbar[0]), a.prep_bytes / 8, s);
@@ -415,60 +652,40 @@ int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad, double* grad_xy) {
         launch_zero(a.at<double>(a.off.w5bar), std::max<size_t>(p.sint_don.size(), 1), s);
         launch_zero(a.at<double>(a.off.w6bar), std::max<size_t>(p.uint_don.size(), 1), s);
     }
-    int ab = 0, mb = 0, pb = 0;
+    a.mb = 0;
+    a.pb = 0;
     double alpha_host = 0.0;
     int rc = 0;
     const int Kc = int(o.ckpt_every);
     for (int seg = a.n_ckpt - 1; seg >= 0; --seg) {
         const int64_t ta = int64_t(seg) * Kc, tb = std::min<int64_t>(o.t_end, ta + Kc);
-        // restore the checkpoint into the context and recompute the segment, storing every step
-        c->cur[0] = 0;
+        // restore the checkpoint into the context and recompute the segment, recording every step
+        const size_t ck = a.off.ckpt + a.off.ckpt_stride * size_t(seg);
+        for (int l = 0; l <= p.L; ++l) {
+            c->cur[l] = 0;
+            c->side_t[l] = 0;
+            rc |= d2d(c, c->lev(l, 0), a.ws + ck + a.off.ck_lev[l], a.lev_bytes[l]);
+            if (l < p.L) rc |= d2d(c, c->side(l, 0), a.ws + ck + a.off.ck_side[l], a.side_bytes[l]);
+            a.ridx[l] = 0;
+        }
         c->mesh_cur = 0;
         c->prep_t = 0;
         c->t = ta;
-        rc |= d2d(c, c->lev(0, 0), a.ws + ckpt_lev(a, seg), a.lev_bytes);
-        rc |= d2d(c, c->mesh(0), a.ws + ckpt_mesh(a, seg), a.mesh_bytes);
-        rc |= d2d(c, c->prep(0), a.ws + ckpt_prep(a, seg), a.prep_bytes);
-        for (int64_t t = ta; t < tb; ++t) {
-            const int k = int(t - ta);
-            rc |= d2d(c, a.ws + a.off.seg_lev + a256(a.lev_bytes) * k, c->lev(0, c->cur[0]), a.lev_bytes);
-            rc |= d2d(c, a.ws + a.off.seg_mesh + a256(a.mesh_bytes) * k, c->mesh(c->mesh_cur), a.mesh_bytes);
-            rc |= d2d(c, a.ws + a.off.seg_prep + a256(a.prep_bytes) * k, c->prep(c->prep_t), a.prep_bytes);
-            finest_step(c);
-        }
-        rc |= d2d(c, a.ws + a.off.seg_prep + a256(a.prep_bytes) * int(tb - ta), c->prep(c->prep_t), a.prep_bytes);
-        for (int64_t t = tb - 1; t >= ta; --t) reverse_step(c, a, K, t, int(t - ta), ab, mb, pb, alpha_host);
+        rc |= d2d(c, c->mesh(0), a.ws + ck + a.off.ck_mesh, a.mesh_bytes);
+        rc |= d2d(c, c->prep(0), a.ws + ck + a.off.ck_prep, a.prep_bytes);
+        a.rec_rc = 0;
+        c->rec = recorder;
+        for (int64_t t = ta; t < tb; t += a.per) level_step(c, 0);
+        c->rec = nullptr;
+        rc |= a.rec_rc;
+        // states after the segment: the post buffer of every refined level, prep at tb
+        for (int l = 1; l <= p.L; ++l)
+            rc |= d2d(c, a.ws + a.seg_lev_at(l, a.ridx[l]), c->lev(l, c->cur[l]), a.lev_bytes[l]);
+        rc |= d2d(c, a.ws + a.seg_prep_at(int(tb - ta)), c->prep(c->prep_t), a.prep_bytes);
+        const int nb = int((tb - ta) / a.per);
+        for (int b = nb - 1; b >= 0; --b) reverse_level(c, a, 0, b, ta, alpha_host);
     }
-    // the initial state: uniform f^eq(rho0, u_inf) fill, its collide-stream and
-    // eq. (9) (post(0) and prep(0)), and the mesh initial values
-    {
-        double* Aw = a.at<double>(a.off.awork);
-        double* prebar = a.at<double>(a.off.prebar);
-        double* Anew = a.at<double>(a.off.abar[1 - ab]);
-        const double ux = p.u_inf * std::cos(p.aoa), uy = p.u_inf * std::sin(p.aoa);
-        launch_fill_uniform(HLBM_FP64, Aw, c->kl[0], p.rho0, ux, uy, s);
-        int slot = 0;
-        launch_adj_collide(K, Aw, a.at<double>(a.off.abar[ab]), prebar, slot, s);
-        slot += adj_blocks_collide(c->kl[0]);
-        launch_adj_s2m(K, Aw, a.nd6, a.at<int32_t>(a.off.t6node), a.at<int32_t>(a.off.t6ptr),
-                       a.at<int32_t>(a.off.t6s), a.at<double>(a.off.t6w), a.at<double>(a.off.pbar[pb]), prebar, s);
-        launch_adj_bc(K, Aw, prebar, slot, s);
-        slot += adj_blocks_nodes(2 * (c->kl[0].nx - 2)) + adj_blocks_nodes(2 * (c->kl[0].ny - 2)) + 1;
-        launch_adj_push(K, prebar, Anew, s);
-        double dfeq[9];
-        const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-        const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-        for (int q = 0; q < 9; ++q) {
-            const double cu = cx[q] * ux + cy[q] * uy;
-            dfeq[q] = w[q] * p.rho0 *
-                      ((3.0 * cx[q] + 9.0 * cu * cx[q] - 3.0 * ux) * K.duin_x +
-                       (3.0 * cy[q] + 9.0 * cu * cy[q] - 3.0 * uy) * K.duin_y);
-        }
-        rc |= hip_check(c, hipMemcpyAsync(a.ws + a.off.dfeq, dfeq, sizeof(dfeq), hipMemcpyHostToDevice, s), "dfeq");
-        launch_adj_alpha_state(K, Anew, a.at<double>(a.off.mbar[mb]), a.at<double>(a.off.dfeq), slot, s);
-        slot += adj_blocks_nodes(int(c->kl[0].ny * c->kl[0].rs) + p.nn);
-        launch_reduce_partials(a.at<double>(a.off.partial), slot, a.at<double>(a.off.acc), s);
-    }
+    rc |= reverse_initial(c, a);
     double acc[2] = {0, 0};
     rc |= hip_check(c, hipMemcpyAsync(acc, a.ws + a.off.acc, 16, hipMemcpyDeviceToHost, s), "grad");
     rc |= hip_check(c, hipStreamSynchronize(s), "grad");

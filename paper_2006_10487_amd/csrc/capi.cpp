@@ -224,6 +224,7 @@ void reset_initial_state(hlbm_ctx* c) { (void)reset_initial_state_checked(c); }
 void finest_step(hlbm_ctx* c) {
     const Plan& p = c->p;
     const int pr = p.precision, L = p.L;
+    if (c->rec) c->rec(c, 2, L);
     void* A = c->lev(L, c->cur[L]);
     void* B = c->lev(L, 1 - c->cur[L]);
     if (p.has_mesh && !p.sint_node.empty()) {
@@ -276,6 +277,7 @@ void level_step(hlbm_ctx* c, int l) {
     const LevelPlan& v = p.lev[l];
     void* A = c->lev(l, c->cur[l]);
     void* B = c->lev(l, 1 - c->cur[l]);
+    if (c->rec) c->rec(c, 0, l);
     {
         Timed tm(c, HLBM_K_COLLIDE_L0 + l);
         launch_stream_collide(pr, c->kl[l], A, B, c->s);
@@ -287,6 +289,7 @@ void level_step(hlbm_ctx* c, int l) {
                               c->side(l, 1 - c->side_t[l]), c->side(l, c->side_t[l]), 0.5 * half, half == 0,
                               v.tau, p.lev[l + 1].tau, c->s);
         }
+        if (half == 0 && c->rec) c->rec(c, 1, l);
         level_step(c, l + 1);
     }
     Timed tm(c, HLBM_K_FINE_TO_COARSE);

@@ -184,8 +184,16 @@ void launch_adj_m2s_a(const KAdj& K, const double* Mrec, int n, const int32_t* n
                       const double* w, double* abar, double* m5bar, int pslot, hipStream_t s);
 void launch_adj_m2s_b(const KAdj& K, const double* Mrec, const int32_t* ptr, const int32_t* slot, const double* w,
                       const double* m5bar, double* mbar, hipStream_t s);
-void launch_adj_alpha_state(const KAdj& K, const double* abar, const double* mbar, const double* dfeq,
+void launch_adj_alpha_state(const KAdj& K, const double* abar, const double* mbar, const double* dfeq, bool with_mesh,
                             int pslot, hipStream_t s);
+void launch_adj_c2f_a(const KLevel& C, const double* side_prev, const double* side_cur, double theta, double* ybar,
+                      double* vbar, double coef, double dcoef, double* partial, int pslot, hipStream_t s);
+void launch_adj_c2f_b(int nxc, int nyc, const double* vbar, double theta, double* sbar_prev, double* sbar_cur,
+                      hipStream_t s);
+void launch_adj_f2c(const KLevel& P, const KLevel& C, int ci0, int cj0, int nxc, int nyc, const double* cprev,
+                    double* xbar, double* ybar, double coef, double dcoef, double* partial, int pslot, hipStream_t s);
+void launch_adj_side(const KLevel& P, int ci0, int cj0, int nxc, int nyc, const double* A, const double* sbar,
+                     double* prebar, hipStream_t s);
 void launch_reduce_partials(const double* partial, int n, double* acc, hipStream_t s);
 int adj_blocks_collide(const KLevel& L);
 int adj_blocks_nodes(int n);
@@ -212,6 +220,10 @@ struct hlbm_ctx {
     std::vector<double> tmp;
     // adjoint (objective run and reverse sweep)
     AdjState* adj = nullptr;
+    // observer of the step recursion (the adjoint's segment recompute), or null:
+    // event 0 = entry of a level-l step (l < L), 1 = the parent's side values of
+    // that step are recorded, 2 = entry of a finest step (before eq. (4))
+    void (*rec)(hlbm_ctx*, int event, int level) = nullptr;
     // instrumentation
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -229,6 +241,7 @@ struct hlbm_ctx {
 namespace hlbm {
 void finish_import(hlbm_ctx* c);
 void finest_step(hlbm_ctx* c);
+void level_step(hlbm_ctx* c, int l);
 void reset_initial_state(hlbm_ctx* c);
 hipEvent_t take_event(hlbm_ctx* c);
 void adj_free(AdjState* a);

@@ -1407,21 +1407,166 @@ __global__ void k_adj_m2s_b(const KAdj K, const double* __restrict__ mf, const i
 // structured fill and the non-wall mesh nodes of abar . d feq(rho0, u_inf)/d alpha.
 __global__ __launch_bounds__(256) void k_adj_alpha_state(const KAdj K, const double* __restrict__ abar,
                                                          const double* __restrict__ mbar, const double* __restrict__ dfeq,
-                                                         int pslot) {
+                                                         int nmesh, int pslot) {
     const KLevel& L = K.L;
-    const size_t nlev = size_t(L.ny) * size_t(L.rs), nmesh = size_t(K.M.nn);
+    const size_t nlev = size_t(L.ny) * size_t(L.rs);
     const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
     double da = 0.0;
     if (e < nlev) {
         da = abar[e] * dfeq[(e / size_t(L.pitch)) % 9];
-    } else if (e < nlev + nmesh) {
+    } else if (e < nlev + size_t(nmesh)) {
         const size_t P = e - nlev;
         if (!(K.M.wall_bc && int(P) < K.M.n_wall)) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) da += mbar[size_t(q) * nmesh + P] * dfeq[q];
+            for (int q = 0; q < 9; ++q) da += mbar[size_t(q) * size_t(nmesh) + P] * dfeq[q];
         }
     }
     block_partial(da, 0.0, K.partial, pslot);
+}
+
+// ---- refinement transfer (Sec. 4, Filippova-Haenel), reverse mode ----
+
+// Coarse -> fine adjoint, pass 1 (per fine perimeter node k): the perimeter
+// value is post = f^eq(rho, u) + coef v_neq, coef = (1 - 1/tau_f) tau_f/(2 tau_c)
+// = (tau_f - 1)/(2 tau_c), with v = (rho, u, f^neq) the side values blended at
+// theta; reads and clears the adjoint of the fine perimeter node and writes
+// vbar_k = d J / d v.
+__global__ __launch_bounds__(256) void k_adj_c2f_a(const KLevel C, const double* __restrict__ side_prev,
+                                                   const double* __restrict__ side_cur, double theta,
+                                                   double* __restrict__ ybar, double* __restrict__ vbar, double coef,
+                                                   double dcoef, double* partial, int pslot) {
+    const int cnx = C.nx - 1, cny = C.ny - 1, nxc = cnx / 2, nyc = cny / 2;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    double dtau = 0.0;
+    if (k < 2 * (cnx + cny)) {
+        int ic, jc;
+        box_node(k, cnx, cny, ic, jc);
+        int ka, kb = -1;
+        if (!(ic & 1) && !(jc & 1)) ka = box_index(ic / 2, jc / 2, nxc, nyc);
+        else if (ic & 1) ka = box_index((ic - 1) / 2, jc / 2, nxc, nyc), kb = box_index((ic + 1) / 2, jc / 2, nxc, nyc);
+        else ka = box_index(ic / 2, (jc - 1) / 2, nxc, nyc), kb = box_index(ic / 2, (jc + 1) / 2, nxc, nyc);
+        const double wa = kb < 0 ? 1.0 : 0.5;
+        double v[kMacro];
+#pragma unroll
+        for (int m = 0; m < kMacro; ++m) {
+            double x = wa * ((1.0 - theta) * side_prev[size_t(ka) * kMacro + m] + theta * side_cur[size_t(ka) * kMacro + m]);
+            if (kb >= 0)
+                x += wa * ((1.0 - theta) * side_prev[size_t(kb) * kMacro + m] + theta * side_cur[size_t(kb) * kMacro + m]);
+            v[m] = x;
+        }
+        const size_t base = size_t(jc) * size_t(C.rs) + ic;
+        double pb[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            pb[q] = ybar[size_t(q) * C.pitch + base];
+            ybar[size_t(q) * C.pitch + base] = 0.0;
+        }
+        double rb = 0.0, uxb = 0.0, uyb = 0.0;
+        feq_adj(v[0], v[1], v[2], pb, rb, uxb, uyb);
+        double* o = vbar + size_t(k) * kMacro;
+        o[0] = rb, o[1] = uxb, o[2] = uyb;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            o[3 + q] = coef * pb[q];
+            dtau += dcoef * pb[q] * v[3 + q];
+        }
+    }
+    block_partial(0.0, dtau, partial, pslot);
+}
+
+// Coarse -> fine adjoint, pass 2 (per box-boundary node kk of the parent):
+// gathers vbar of the fine perimeter nodes that read side entry kk (the even
+// node on it, weight 1, and its odd neighbours along the perimeter, weight 1/2)
+// into the adjoints of the side values at the parent's two times.
+__global__ void k_adj_c2f_b(int nxc, int nyc, const double* __restrict__ vbar, double theta,
+                            double* __restrict__ sbar_prev, double* __restrict__ sbar_cur) {
+    const int kk = blockIdx.x * blockDim.x + threadIdx.x;
+    if (kk >= 2 * (nxc + nyc)) return;
+    const int cnx = 2 * nxc, cny = 2 * nyc;
+    int a, b;
+    box_node(kk, nxc, nyc, a, b);
+    double acc[kMacro];
+    const double* v0 = vbar + size_t(box_index(2 * a, 2 * b, cnx, cny)) * kMacro;
+#pragma unroll
+    for (int m = 0; m < kMacro; ++m) acc[m] = v0[m];
+    auto add_half = [&](int ic, int jc) {
+        const double* vv = vbar + size_t(box_index(ic, jc, cnx, cny)) * kMacro;
+#pragma unroll
+        for (int m = 0; m < kMacro; ++m) acc[m] += 0.5 * vv[m];
+    };
+    if (b == 0 || b == nyc) {
+        if (2 * a - 1 >= 0) add_half(2 * a - 1, 2 * b);
+        if (2 * a + 1 <= cnx) add_half(2 * a + 1, 2 * b);
+    }
+    if (a == 0 || a == nxc) {
+        if (2 * b - 1 >= 0) add_half(2 * a, 2 * b - 1);
+        if (2 * b + 1 <= cny) add_half(2 * a, 2 * b + 1);
+    }
+#pragma unroll
+    for (int m = 0; m < kMacro; ++m) {
+        sbar_prev[size_t(kk) * kMacro + m] += (1.0 - theta) * acc[m];
+        sbar_cur[size_t(kk) * kMacro + m] += theta * acc[m];
+    }
+}
+
+// Fine -> coarse adjoint (per ring node of the parent): post = f^eq(rho, u) +
+// coef f^neq of the fine pulled populations, coef = 2 (tau_c - 1)/tau_f; reads
+// and clears the parent's adjoint at the ring node and adds the adjoint of the
+// pulled fine values to the child's buffer adjoint at their sources (each
+// source belongs to one ring node, so the scatter has no conflicts).
+__global__ __launch_bounds__(256) void k_adj_f2c(const KLevel P, const KLevel C, int ci0, int cj0, int nxc, int nyc,
+                                                 const double* __restrict__ cprev, double* __restrict__ xbar,
+                                                 double* __restrict__ ybar, double coef, double dcoef,
+                                                 double* partial, int pslot) {
+    const int rx = nxc - 2, ry = nyc - 2;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    double dtau = 0.0;
+    if (k < 2 * (rx + ry)) {
+        int a, b;
+        box_node(k, rx, ry, a, b);
+        const int pi = ci0 + 1 + a, pj = cj0 + 1 + b;
+        const int fi = 2 * (pi - ci0), fj = 2 * (pj - cj0);
+        double f[9], rho, ux, uy, feq[9];
+        pull(C, cprev, fi, fj, f);
+        macro64(f, rho, ux, uy);
+        equilibrium<double, false>(rho, rho, ux, uy, feq);
+        const size_t base = size_t(pj) * size_t(P.rs) + pi;
+        double xb[9], a12[12] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            xb[q] = xbar[size_t(q) * P.pitch + base];
+            xbar[size_t(q) * P.pitch + base] = 0.0;
+            a12[3 + q] = coef * xb[q];
+            dtau += dcoef * xb[q] * (f[q] - feq[q]);
+        }
+        feq_adj(rho, ux, uy, xb, a12[0], a12[1], a12[2]);
+        double fb[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) fb[q] = 0.0;
+        macro_neq_adj(f, a12, fb);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) ybar[lidx(C, q, fi - CX[q], fj - CY[q])] += fb[q];
+    }
+    block_partial(0.0, dtau, partial, pslot);
+}
+
+// Adjoint of the side values (rho, u, f^neq) recorded from the parent's pulled
+// populations at its box-boundary nodes: prebar(node) += J^T sbar (per node).
+__global__ void k_adj_side(const KLevel P, int ci0, int cj0, int nxc, int nyc, const double* __restrict__ A,
+                           const double* __restrict__ sbar, double* __restrict__ prebar) {
+    const int kk = blockIdx.x * blockDim.x + threadIdx.x;
+    if (kk >= 2 * (nxc + nyc)) return;
+    int a, b;
+    box_node(kk, nxc, nyc, a, b);
+    const int i = ci0 + a, j = cj0 + b;
+    double g[9], fb[9];
+    pull(P, A, i, j, g);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fb[q] = 0.0;
+    macro_neq_adj(g, sbar + size_t(kk) * kMacro, fb);
+    const size_t base = size_t(j) * size_t(P.rs) + i;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) prebar[size_t(q) * P.pitch + base] += fb[q];
 }
 
 __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partial, int n, double* acc) {
@@ -1489,10 +1634,29 @@ void launch_adj_m2s_b(const KAdj& K, const double* Mrec, const int32_t* ptr, con
                       const double* m5bar, double* mbar, hipStream_t s) {
     k_adj_m2s_b<<<blocks(K.M.nn), 256, 0, s>>>(K, Mrec, ptr, slot, w, m5bar, mbar);
 }
-void launch_adj_alpha_state(const KAdj& K, const double* abar, const double* mbar, const double* dfeq, int pslot,
-                            hipStream_t s) {
-    const size_t n = size_t(K.L.ny) * size_t(K.L.rs) + size_t(K.M.nn);
-    k_adj_alpha_state<<<blocks(n), 256, 0, s>>>(K, abar, mbar, dfeq, pslot);
+void launch_adj_alpha_state(const KAdj& K, const double* abar, const double* mbar, const double* dfeq, bool with_mesh,
+                            int pslot, hipStream_t s) {
+    const int nmesh = with_mesh ? K.M.nn : 0;
+    const size_t n = size_t(K.L.ny) * size_t(K.L.rs) + size_t(nmesh);
+    k_adj_alpha_state<<<blocks(n), 256, 0, s>>>(K, abar, mbar, dfeq, nmesh, pslot);
+}
+void launch_adj_c2f_a(const KLevel& C, const double* side_prev, const double* side_cur, double theta, double* ybar,
+                      double* vbar, double coef, double dcoef, double* partial, int pslot, hipStream_t s) {
+    const int n = 2 * (C.nx - 1 + C.ny - 1);
+    k_adj_c2f_a<<<adj_blocks_nodes(n), 256, 0, s>>>(C, side_prev, side_cur, theta, ybar, vbar, coef, dcoef, partial, pslot);
+}
+void launch_adj_c2f_b(int nxc, int nyc, const double* vbar, double theta, double* sbar_prev, double* sbar_cur,
+                      hipStream_t s) {
+    k_adj_c2f_b<<<adj_blocks_nodes(2 * (nxc + nyc)), 256, 0, s>>>(nxc, nyc, vbar, theta, sbar_prev, sbar_cur);
+}
+void launch_adj_f2c(const KLevel& P, const KLevel& C, int ci0, int cj0, int nxc, int nyc, const double* cprev,
+                    double* xbar, double* ybar, double coef, double dcoef, double* partial, int pslot, hipStream_t s) {
+    const int n = 2 * (nxc - 2 + nyc - 2);
+    k_adj_f2c<<<adj_blocks_nodes(n), 256, 0, s>>>(P, C, ci0, cj0, nxc, nyc, cprev, xbar, ybar, coef, dcoef, partial, pslot);
+}
+void launch_adj_side(const KLevel& P, int ci0, int cj0, int nxc, int nyc, const double* A, const double* sbar,
+                     double* prebar, hipStream_t s) {
+    k_adj_side<<<adj_blocks_nodes(2 * (nxc + nyc)), 256, 0, s>>>(P, ci0, cj0, nxc, nyc, A, sbar, prebar);
 }
 void launch_reduce_partials(const double* partial, int n, double* acc, hipStream_t s) {
     k_reduce_partials<<<1, 256, 0, s>>>(partial, n, acc);

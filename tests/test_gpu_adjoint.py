@@ -146,3 +146,55 @@ def test_autograd_function():
     _, d3 = O.objective_derivative(w, OSPEC, d_xy=w.omesh.bump_tangent(W.HH_PEAKS)[3], n_sub=N_SUB)
     print("dJ/db", bumps.grad.numpy(), "oracle dJ/db3", d3, flush=True)
     assert rel(bumps.grad.numpy()[3], d3) < GRAD_TOL
+
+
+# ---- refined grid: base level + one box (refinement transfer adjoint) ----
+
+def test_refined_adjoint_matches_oracle_gradient():
+    """Re = 100, c = 40 on a 120x60 base grid with one 128x64 box: alpha and tau."""
+    w = W.naca_re100_c40_refined(3.0)
+    J, sim = gpu_J(w, w.aoa_rad, w.tau_s)
+    g = sim.adjoint(1.0)
+    Jo, da = O.objective_derivative(w, OSPEC, d_aoa=1.0, n_sub=N_SUB)
+    _, dt = O.objective_derivative(w, OSPEC, d_tau=1.0, n_sub=N_SUB)
+    print(f"refined: J gpu {J!r} oracle {Jo!r}; dJ/dalpha gpu {g[0]!r} oracle {da!r} ({rel(g[0], da):.2e}); "
+          f"dJ/dtau gpu {g[1]!r} oracle {dt!r} ({rel(g[1], dt):.2e})", flush=True)
+    assert rel(J, Jo) < 1e-12
+    assert rel(g[0], da) < GRAD_TOL
+    assert rel(g[1], dt) < GRAD_TOL
+
+
+def test_refined_shape_gradient_matches_oracle():
+    amps = W.hh_amplitudes(2)
+    w = W.naca_re100_c40_refined(5.0, bumps=amps)
+    _, sim = gpu_J(w, w.aoa_rad, w.tau_s, spec=dict(SPEC, w_cd=0.5, w_cl=1.0), mesh_grad=True)
+    g = sim.adjoint()
+    rng = np.random.default_rng(4)
+    tan = w.omesh.bump_tangent(W.HH_PEAKS)
+    for name, v in {"bump 4": tan[4], "random": rng.standard_normal(w.mesh_xy.shape)}.items():
+        _, d = O.objective_derivative(w, dict(OSPEC, w_cd=0.5, w_cl=1.0), d_xy=v, n_sub=N_SUB)
+        a = float(np.sum(sim.grad_xy * v))
+        print(f"refined shape {name}: adjoint {a!r} oracle {d!r} ({rel(a, d):.2e})", flush=True)
+        assert rel(a, d) < GRAD_TOL
+    _, da = O.objective_derivative(w, dict(OSPEC, w_cd=0.5, w_cl=1.0), d_aoa=1.0, n_sub=N_SUB)
+    print(f"refined mixed objective dJ/dalpha: adjoint {g[0]!r} oracle {da!r}", flush=True)
+    # this derivative is a near-cancellation of drag and lift parts of size ~0.1:
+    # rounding is relative to those parts, not to the small sum
+    assert abs(g[0] - da) < GRAD_TOL * 0.1
+
+
+def test_refined_checkpoint_interval_independent():
+    w = W.naca_re100_c40_refined(3.0)
+    g = []
+    for k in (20, 80, 160):
+        _, sim = gpu_J(w, w.aoa_rad, w.tau_s, spec=dict(SPEC, ckpt_every=k))
+        g.append(sim.adjoint())
+    assert np.array_equal(g[0], g[1]) and np.array_equal(g[0], g[2])
+
+
+def test_refined_objective_rejects_odd_steps():
+    w = W.naca_re100_c40_refined(3.0)
+    sim = hlbm.HLBM.from_workload(w, n_sub=N_SUB)
+    with pytest.raises(hlbm.HLBMError) as ei:
+        sim.run_objective(t_end=161, t0=80, t1=161, ckpt_every=40)
+    assert ei.value.code == -1

@@ -96,3 +96,13 @@ def test_bump_tangent_matches_generator():
     # wall nodes move, the outer (interpolation) ring does not
     assert np.abs(tan[:, :om.ns, 1]).max() > 1.0
     assert np.abs(tan[:, om.nl * om.ns:, :]).max() == 0.0
+
+
+def test_refined_derivative_matches_finite_differences():
+    """One refinement box: the derivative crosses the coarse <-> fine transfers."""
+    w = W.naca_re100_c40_refined(3.0)
+    _, d = O.objective_derivative(w, SPEC, d_tau=1.0, n_sub=N_SUB)
+    h = 1e-7
+    fd = (plain_J(w, tau=w.tau_s + h) - plain_J(w, tau=w.tau_s - h)) / (2 * h)
+    print("refined tau", d, fd)
+    assert abs(d - fd) < 2e-6 * max(1.0, abs(fd))
