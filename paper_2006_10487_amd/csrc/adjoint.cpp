@@ -9,7 +9,8 @@
 //   forward finest:      eq. (4) -> collide-stream -> eq. (9) -> n FV sub-steps -> force
 //   reverse level l < L: [child step^T, (fine -> coarse^T after the second), coarse -> fine^T]
 //                        x 2 (second half first), collide-stream^T with the recorded side values^T
-//   reverse finest:      force^T -> FV^T (n sub-steps, states recomputed) -> eq. (9)^T +
+//   reverse finest:      force^T -> FV^T (n sub-steps, states recomputed; per sub-step the
+//                        no-slip reset^T at wall pivots, then one gather per node) -> eq. (9)^T +
 //                        collide^T + boundary^T + pull^T -> eq. (4)^T
 // The restriction at the end of a level-l step pulls from the child's buffer
 // between its two steps (the input of the second), so its transpose is added
@@ -43,9 +44,9 @@ struct AdjState {
         size_t ckpt, ckpt_stride, ck_lev[4], ck_side[4], ck_mesh, ck_prep;
         size_t seg_lev[4], seg_side[4], seg_mesh, seg_prep, sub, awork;
         size_t abar[4][2], prebar[4], sbar[4][2], vperim[4];
-        size_t mbar[2], zbar, pbar[2], m5bar;
+        size_t mbar[2], zwall[2], pbar[2], m5bar;
         size_t partial, acc, tedges, vwall, t5ptr, t5s, t5w, t6node, t6ptr, t6s, t6w, dfeq;
-        size_t gbar, vbar, w5bar, w6bar, total;
+        size_t gbar, gpivot, vbar, w5bar, w6bar, total;
     } off{};
     bool tables = false, ran = false;
     std::vector<int32_t> t5map, t6map;   // transposed entry -> index into sint_w / uint_w
@@ -144,14 +145,15 @@ void layout(hlbm_ctx* c, AdjState& a) {
     }
     a.off.mbar[0] = take(a.adjmesh_bytes);
     a.off.mbar[1] = take(a.adjmesh_bytes);
-    a.off.zbar = take(a.adjmesh_bytes);
+    a.off.zwall[0] = take(size_t(kQ) * std::max(p.n_wall, 1) * 8);
+    a.off.zwall[1] = take(size_t(kQ) * std::max(p.n_wall, 1) * 8);
     a.off.pbar[0] = take(a.prep_bytes);
     a.off.pbar[1] = take(a.prep_bytes);
     a.off.m5bar = take(std::max<size_t>(p.sint_node.size(), 1) * kMacro * 8);
     // partial-sum slots between two reductions (the largest user)
     const KLevel& F = c->kl[p.L];
-    const int bn = adj_blocks_nodes(p.nn), bi = adj_blocks_nodes(p.n_int);
-    const int fine = p.n_sub * (bn + bi) + adj_blocks_collide(F) + bc_blocks(F) +
+    const int bn = adj_blocks_nodes(p.nn);
+    const int fine = p.n_sub * bn + adj_blocks_collide(F) + bc_blocks(F) +
                      adj_blocks_nodes(int(p.sint_node.size()));
     int coarse = 0, init = 0;
     for (int l = 0; l <= p.L; ++l) {
@@ -176,6 +178,7 @@ void layout(hlbm_ctx* c, AdjState& a) {
     a.off.dfeq = take(9 * 8);
     if (a.obj.mesh_grad) {
         a.off.gbar = take(size_t(3) * p.ell_width * p.nn * 8);
+        a.off.gpivot = take(size_t(2) * p.nn * 8);
         a.off.vbar = take(size_t(2) * std::max(p.n_wall, 1) * 8);
         a.off.w5bar = take(std::max<size_t>(p.sint_don.size(), 1) * 8);
         a.off.w6bar = take(std::max<size_t>(p.uint_don.size(), 1) * 8);
@@ -192,9 +195,14 @@ int d2d(hlbm_ctx* c, void* dst, const void* src, size_t bytes) {
 int upload_tables(hlbm_ctx* c, AdjState& a) {
     const Plan& p = c->p;
     const int nn = p.nn, W = p.ell_width;
-    // FV transpose: slot z of node k = (P, G_Pk, C_Pk) for the pivots P whose row holds k;
-    // slot 0 = (k, sum_{j != k} G_kj, C_kk) (the pivot's own base and collision terms)
-    std::vector<std::vector<std::array<double, 4>>> rows(nn);
+    // FV transpose: slot z of node k = (P, z_P, G_Pk, C_Pk) for the pivots P whose row holds k
+    // in its slot z_P; slot 0 = (k, 0, sum_{j != k} G_kj, C_kk) (the pivot's own base and
+    // collision terms)
+    struct TEnt {
+        int32_t P, zf;
+        double gx, gy, c;
+    };
+    std::vector<std::vector<TEnt>> rows(nn);
     for (int P = 0; P < nn; ++P) {
         double sx = 0.0, sy = 0.0, ckk = 0.0;
         for (int z = p.rowptr[P]; z < p.rowptr[P + 1]; ++z) {
@@ -204,18 +212,23 @@ int upload_tables(hlbm_ctx* c, AdjState& a) {
             }
             sx += p.gx[z];
             sy += p.gy[z];
-            rows[p.col[z]].push_back({double(P), p.gx[z], p.gy[z], p.cc[z]});
+            rows[p.col[z]].push_back({P, z - p.rowptr[P], p.gx[z], p.gy[z], p.cc[z]});
         }
-        rows[P].insert(rows[P].begin(), {double(P), sx, sy, ckk});
+        rows[P].insert(rows[P].begin(), TEnt{P, 0, sx, sy, ckk});
     }
     std::vector<char> te(size_t(W) * nn * 32, 0);
     for (int k = 0; k < nn; ++k) {
         if (int(rows[k].size()) > W) return set_err(c, HLBM_E_GEOMETRY, "mesh connectivity is not symmetric");
         for (int z = 0; z < W; ++z) {
             char* r = te.data() + (size_t(z) * nn + k) * 32;
-            const int32_t col = z < int(rows[k].size()) ? int32_t(rows[k][z][0]) : -1;
+            const bool used = z < int(rows[k].size());
+            const int32_t col = used ? rows[k][z].P : -1, zf = used ? rows[k][z].zf : 0;
             std::memcpy(r, &col, 4);
-            if (col >= 0) std::memcpy(r + 8, &rows[k][z][1], 24);
+            std::memcpy(r + 4, &zf, 4);
+            if (used) {
+                const double v[3] = {rows[k][z].gx, rows[k][z].gy, rows[k][z].c};
+                std::memcpy(r + 8, v, 24);
+            }
         }
     }
     // wall force weights: half the outward normals of the wall edges at each wall node
@@ -313,6 +326,7 @@ KAdj make_kadj(hlbm_ctx* c, AdjState& a, int l) {
     K.partial = a.at<double>(a.off.partial);
     const bool g = a.obj.mesh_grad != 0;
     K.gbar = g ? a.at<double>(a.off.gbar) : nullptr;
+    K.gpivot = g ? a.at<double>(a.off.gpivot) : nullptr;
     K.vbar = g ? a.at<double>(a.off.vbar) : nullptr;
     K.w5bar = g ? a.at<double>(a.off.w5bar) : nullptr;
     K.w6bar = g ? a.at<double>(a.off.w6bar) : nullptr;
@@ -409,19 +423,22 @@ void reverse_finest(hlbm_ctx* c, AdjState& a, int64_t t, int k, double& alpha_ho
         // projection directions depend on alpha: dC_D/dalpha = C_L, dC_L/dalpha = -C_D
         alpha_host += jcd * a.cl[t] - jcl * a.cd[t];
     }
-    // FV^T, last sub-step first
-    const int bn = adj_blocks_nodes(p.nn), bi = adj_blocks_nodes(p.n_int);
+    // FV^T, last sub-step first: one gather per node and sub-step; the no-slip reset
+    // transpose of a sub-step is taken by the wall threads of the launch after it
+    const int bn = adj_blocks_nodes(p.nn);
+    int zw = 0;
+    launch_adj_fv_wall(K, a.at<double>(a.off.sub + ms * (p.n_sub - 1)), a.at<double>(a.off.mbar[a.mb]),
+                       a.at<double>(a.off.zwall[zw]), prep0, prep1, double(p.n_sub - 1) / p.n_sub, s);
     for (int m = p.n_sub - 1; m >= 0; --m) {
         const double th = double(m) / p.n_sub;
         const double* Mm = a.at<double>(a.off.sub + ms * m);
-        launch_adj_fv_a(K, Mm, a.at<double>(a.off.mbar[a.mb]), a.at<double>(a.off.zbar), prep0, prep1, th, slot, s);
+        const double* Mprev = m > 0 ? a.at<double>(a.off.sub + ms * (m - 1)) : nullptr;
+        launch_adj_fv(K, Mm, a.at<double>(a.off.mbar[a.mb]), a.at<double>(a.off.zwall[zw]),
+                      a.at<double>(a.off.mbar[1 - a.mb]), prep0, prep1, th, Pnext, Pcur, slot, Mprev,
+                      double(m - 1) / p.n_sub, a.at<double>(a.off.zwall[1 - zw]), s);
         slot += bn;
-        launch_adj_fv_b(K, Mm, a.at<double>(a.off.zbar), a.at<double>(a.off.mbar[1 - a.mb]), s);
-        if (p.n_int > 0) {
-            launch_adj_fv_c(K, a.at<double>(a.off.zbar), prep0, prep1, th, Pnext, Pcur, slot, s);
-            slot += bi;
-        }
         a.mb ^= 1;
+        zw ^= 1;
     }
     // collide-stream^T with eq. (9)^T and the boundary conditions^T, then pull^T
     slot += collide_adj(c, K, Aw, Bbar, prebar, slot);
@@ -641,13 +658,15 @@ int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad, double* grad_xy) {
         a.ab[l] = 0;
         a.sb[l] = 0;
     }
-    for (double* z : {a.at<double>(a.off.mbar[0]), a.at<double>(a.off.mbar[1]), a.at<double>(a.off.zbar)})
-        launch_zero(z, a.adjmesh_bytes / 8, s);
+    for (double* z : {a.at<double>(a.off.mbar[0]), a.at<double>(a.off.mbar[1])}) launch_zero(z, a.adjmesh_bytes / 8, s);
+    for (double* z : {a.at<double>(a.off.zwall[0]), a.at<double>(a.off.zwall[1])})
+        launch_zero(z, size_t(kQ) * std::max(p.n_wall, 1), s);
     launch_zero(a.at<double>(a.off.pbar[0]), a.prep_bytes / 8, s);
     launch_zero(a.at<double>(a.off.pbar[1]), a.prep_bytes / 8, s);
     launch_zero(a.at<double>(a.off.acc), 2, s);
     if (a.obj.mesh_grad) {
         launch_zero(a.at<double>(a.off.gbar), size_t(3) * p.ell_width * p.nn, s);
+        launch_zero(a.at<double>(a.off.gpivot), size_t(2) * p.nn, s);
         launch_zero(a.at<double>(a.off.vbar), size_t(2) * std::max(p.n_wall, 1), s);
         launch_zero(a.at<double>(a.off.w5bar), std::max<size_t>(p.sint_don.size(), 1), s);
         launch_zero(a.at<double>(a.off.w6bar), std::max<size_t>(p.uint_don.size(), 1), s);
@@ -696,16 +715,25 @@ int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad, double* grad_xy) {
     if (a.obj.mesh_grad) {
         // coefficient adjoints -> mesh coordinates (host, forward mode per local coordinate)
         std::vector<double> gb(size_t(3) * p.ell_width * p.nn), vb(size_t(2) * std::max(p.n_wall, 1));
+        std::vector<double> gp(size_t(2) * p.nn);
         std::vector<double> t5(a.t5map.size()), t6(a.t6map.size());
         std::vector<double> w5(p.sint_w.size(), 0.0), w6(p.uint_w.size(), 0.0);
         rc |= hip_check(c, hipMemcpyAsync(gb.data(), a.ws + a.off.gbar, gb.size() * 8, hipMemcpyDeviceToHost, s), "gbar");
         rc |= hip_check(c, hipMemcpyAsync(vb.data(), a.ws + a.off.vbar, vb.size() * 8, hipMemcpyDeviceToHost, s), "vbar");
+        rc |= hip_check(c, hipMemcpyAsync(gp.data(), a.ws + a.off.gpivot, gp.size() * 8, hipMemcpyDeviceToHost, s), "gpivot");
         if (!t5.empty())
             rc |= hip_check(c, hipMemcpyAsync(t5.data(), a.ws + a.off.w5bar, t5.size() * 8, hipMemcpyDeviceToHost, s), "w5bar");
         if (!t6.empty())
             rc |= hip_check(c, hipMemcpyAsync(t6.data(), a.ws + a.off.w6bar, t6.size() * 8, hipMemcpyDeviceToHost, s), "w6bar");
         rc |= hip_check(c, hipStreamSynchronize(s), "mesh grad");
         if (rc) return HLBM_E_DEVICE;
+        // G_Pk adjoints of the difference form: neighbour part minus the pivot's base part
+        for (int P = 0; P < p.nn; ++P)
+            for (int z = 1; z < p.rowptr[P + 1] - p.rowptr[P]; ++z) {
+                double* g = gb.data() + (size_t(z) * p.nn + P) * 3;
+                g[0] -= gp[2 * size_t(P)];
+                g[1] -= gp[2 * size_t(P) + 1];
+            }
         for (size_t z = 0; z < t5.size(); ++z) w5[a.t5map[z]] = t5[z];
         for (size_t z = 0; z < t6.size(); ++z) w6[a.t6map[z]] = t6[z];
         std::vector<double> gx(2 * size_t(p.nn), 0.0);

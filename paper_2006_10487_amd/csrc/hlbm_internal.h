@@ -153,7 +153,8 @@ void launch_mesh_convert(int prec, int nn, const double* in, void* out, int to_s
 struct KAdj {
     KLevel L;                        // the structured level
     KMesh M;                         // the mesh
-    const void* tedges;              // transposed neighbour table: slot z of node k = (P, G_Pk, C_Pk); slot 0 = (k, sum_{j!=k} G_kj, C_kk)
+    const void* tedges;              // transposed neighbour table: slot z of node k = (P, z_P, G_Pk, C_Pk) with z_P the
+                                     // slot of k in row P; slot 0 = (k, 0, sum_{j!=k} G_kj, C_kk)
     double dt, dtt, ddtt_dtau;       // Delta t_u, Delta t_u / tau_u, d(Delta t_u / tau_u)/d tau
     double cst, dcst_dtau;           // 1 - 1/(2 tau), d/d tau
     double omega, domega_dtau;       // 1 / tau, d/d tau
@@ -162,6 +163,8 @@ struct KAdj {
     double* partial;                 // per-block (d alpha, d tau) partial sums
     // adjoints of the mesh-geometry coefficients, accumulated over the run (null: not wanted)
     double* gbar;                    // [ell_width][nn][3]: (G_x, G_y, C) of forward ELL slot z of pivot P
+                                     // (G parts without the pivot's base term, which is in gpivot)
+    double* gpivot;                  // [nn][2]: Delta t_u sum_q zbar_Pq c_q base_Pq, per pivot
     double* vbar;                    // [n_wall][2]: half wall normals summed at each wall node
     double* w5bar;                   // eq. (4) weights, per entry of the transposed (donor-major) list
     double* w6bar;                   // eq. (9) weights, per entry of the transposed (donor-major) list
@@ -170,11 +173,11 @@ struct KAdj {
 void launch_zero(double* p, size_t n, hipStream_t s);
 void launch_adj_force(const KAdj& K, double* mbar, const double* vwall, double jx, double jy, const double* fst,
                       hipStream_t s);
-void launch_adj_fv_a(const KAdj& K, const double* Mrec, const double* ybar, double* zbar, const double* prep0,
-                     const double* prep1, double theta, int pslot, hipStream_t s);
-void launch_adj_fv_b(const KAdj& K, const double* Mrec, const double* zbar, double* mbar, hipStream_t s);
-void launch_adj_fv_c(const KAdj& K, const double* zbar, const double* prep0, const double* prep1, double theta,
-                     double* p0bar, double* p1bar, int pslot, hipStream_t s);
+void launch_adj_fv_wall(const KAdj& K, const double* Mrec, const double* ybar, double* zwall, const double* prep0,
+                        const double* prep1, double theta, hipStream_t s);
+void launch_adj_fv(const KAdj& K, const double* Mrec, const double* ybar, const double* zwall, double* mbar,
+                   const double* prep0, const double* prep1, double theta, double* p0bar, double* p1bar, int pslot,
+                   const double* Mprev, double theta_prev, double* zwall_prev, hipStream_t s);
 void launch_adj_collide(const KAdj& K, const double* A, const double* bbar, double* prebar, int pslot, hipStream_t s);
 void launch_adj_s2m(const KAdj& K, const double* A, int nd, const int32_t* node, const int32_t* ptr,
                     const int32_t* slot, const double* w, const double* pbar, double* prebar, hipStream_t s);

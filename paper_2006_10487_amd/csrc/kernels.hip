@@ -962,186 +962,185 @@ __device__ __forceinline__ void fv_value(const KAdj& K, const double* fin, const
     }
 }
 
-// FV sub-step adjoint, phase A (per pivot P): recompute the pre-reset update
-// fn_P from M^m, take the wall reset's transpose: zbar_P = R'(fn_P)^T ybar_P;
-// tau enters through Delta t_u / tau_u.  With K.gbar set, also accumulates the
-// adjoints of the pivot's coefficients (G_Pk, C_Pk) of this sub-step.
-__global__ __launch_bounds__(256) void k_adj_fv_a(const KAdj K, const double* __restrict__ fin,
-                                                  const double* __restrict__ ybar, double* __restrict__ zbar,
-                                                  const double* __restrict__ prep0, const double* __restrict__ prep1,
-                                                  double theta, int pslot) {
+// Adjoint of the no-slip reset at wall pivot P: recompute the pre-reset update
+// fn_P of the sub-step from its input fin and map the adjoint yb of the reset
+// output onto it, zb = R'(fn_P)^T yb.
+__device__ __forceinline__ void wall_reset_adj(const KAdj& K, const double* fin, const double* prep0,
+                                               const double* prep1, double theta, int P, const D9& yb, D9& zb) {
+    const KMesh& M = K.M;
+    const int nn = M.nn, W = M.ell_width;
+    const EdgeRec<double>* E = reinterpret_cast<const EdgeRec<double>*>(M.edges);
+    double base[9], ss[9], sc[9];
+    for (int z = 0; z < W; ++z) {
+        const EdgeRec<double> e = E[size_t(z) * nn + P];
+        const int k = e.col;
+        if (k < 0) continue;
+        double f[9], nq[9];
+        fv_value(K, fin, prep0, prep1, theta, false, k, f, nq);   // wall nodes are never interpolation nodes
+        if (z == 0) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) base[q] = f[q], ss[q] = 0.0, sc[q] = e.c * nq[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                ss[q] += (CX[q] * e.gx + CY[q] * e.gy) * (f[q] - base[q]);
+                sc[q] += e.c * nq[q];
+            }
+        }
+    }
+    double fn[9], rho, ux, uy;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fn[q] = base[q] + K.dt * ss[q] - K.dtt * sc[q];
+    macro64(fn, rho, ux, uy);
+    // out = feq(rho, 0) + fn - feq(rho, u)
+    double rb = 0.0, uxb = 0.0, uyb = 0.0, eb[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        zb[q] = yb[q];
+        rb += yb[q] * wgt<double>(q);
+        eb[q] = -yb[q];
+    }
+    feq_adj(rho, ux, uy, eb, rb, uxb, uyb);
+    macro_adj(rho, ux, uy, rb, uxb, uyb, zb);
+}
+
+// No-slip reset adjoint of the last sub-step of a finest step (per wall pivot P):
+// zwall_P (layout [9][n_wall]) from ybar_P.  Earlier sub-steps get theirs from
+// k_adj_fv of the sub-step after them.
+__global__ __launch_bounds__(256) void k_adj_fv_wall(const KAdj K, const double* __restrict__ fin,
+                                                     const double* __restrict__ ybar, double* __restrict__ zwall,
+                                                     const double* __restrict__ prep0, const double* __restrict__ prep1,
+                                                     double theta) {
     const KMesh& M = K.M;
     const int P = blockIdx.x * blockDim.x + threadIdx.x;
-    double dtau = 0.0;
-    if (P < M.nn) {
-        const int nn = M.nn, W = M.ell_width;
-        const bool pivot_interp = P >= M.n_core;
-        const EdgeRec<double>* E = reinterpret_cast<const EdgeRec<double>*>(M.edges);
-        double base[9], ss[9], sc[9];
-        for (int z = 0; z < W; ++z) {
-            const EdgeRec<double> e = E[size_t(z) * nn + P];
-            const int k = e.col;
-            if (k < 0) continue;
-            double f[9], nq[9];
-            fv_value(K, fin, prep0, prep1, theta, pivot_interp, k, f, nq);
-            if (z == 0) {
+    if (P >= M.n_wall) return;
+    double yb[9], zb[9];
 #pragma unroll
-                for (int q = 0; q < 9; ++q) base[q] = f[q], ss[q] = 0.0, sc[q] = e.c * nq[q];
-            } else {
+    for (int q = 0; q < 9; ++q) yb[q] = ybar[size_t(q) * M.nn + P];
+    wall_reset_adj(K, fin, prep0, prep1, theta, P, yb, zb);
 #pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    ss[q] += (CX[q] * e.gx + CY[q] * e.gy) * (f[q] - base[q]);
-                    sc[q] += e.c * nq[q];
-                }
-            }
-        }
-        double yb[9], zb[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) yb[q] = ybar[size_t(q) * nn + P];
-        if (M.wall_bc && P < M.n_wall) {
-            double fn[9], rho, ux, uy;
-#pragma unroll
-            for (int q = 0; q < 9; ++q) fn[q] = base[q] + K.dt * ss[q] - K.dtt * sc[q];
-            macro64(fn, rho, ux, uy);
-            // out = feq(rho, 0) + fn - feq(rho, u)
-            double rb = 0.0, uxb = 0.0, uyb = 0.0, eb[9];
-#pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                zb[q] = yb[q];
-                rb += yb[q] * wgt<double>(q);
-                eb[q] = -yb[q];
-            }
-            feq_adj(rho, ux, uy, eb, rb, uxb, uyb);
-            macro_adj(rho, ux, uy, rb, uxb, uyb, zb);
-        } else {
-#pragma unroll
-            for (int q = 0; q < 9; ++q) zb[q] = yb[q];
-        }
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            zbar[size_t(q) * nn + P] = zb[q];
-            dtau += zb[q] * (-sc[q]) * K.ddtt_dtau;
-        }
-        if (K.gbar) {
-            // d fn_q / d G_Pk = Delta t_u c_q (f_kq - f_Pq) (k != P), d fn_q / d C_Pk = -(Delta t_u / tau_u) nq_kq
-            for (int z = 0; z < W; ++z) {
-                const int k = E[size_t(z) * nn + P].col;
-                if (k < 0) continue;
-                double f[9], nq[9];
-                fv_value(K, fin, prep0, prep1, theta, pivot_interp, k, f, nq);
-                double ax = 0.0, ay = 0.0, ac = 0.0;
-#pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    const double d = z == 0 ? 0.0 : zb[q] * (f[q] - base[q]);
-                    ax += CX[q] * d;
-                    ay += CY[q] * d;
-                    ac += zb[q] * nq[q];
-                }
-                double* g = K.gbar + (size_t(z) * nn + P) * 3;
-                g[0] += K.dt * ax;
-                g[1] += K.dt * ay;
-                g[2] -= K.dtt * ac;
-            }
-        }
-    }
-    block_partial(0.0, dtau, K.partial, pslot);
+    for (int q = 0; q < 9; ++q) zwall[size_t(q) * M.n_wall + P] = zb[q];
 }
 
-// FV sub-step adjoint, phase B (per node k): adjoint of the stored mesh value
-// M^m_k, gathered over the pivots P whose rows contain k (transposed table).
-__global__ __launch_bounds__(256) void k_adj_fv_b(const KAdj K, const double* __restrict__ fin,
-                                                  const double* __restrict__ zbar, double* __restrict__ mbar) {
+// FV sub-step adjoint (per node k): the adjoint of every value of k that the
+// update of eqs. (3), (5) reads, gathered over the pivots P whose rows hold k
+// (transposed table; slot 0 is k itself with its base and collision terms).
+//   stored value M^m_k (read by pivots that are not both interpolation nodes)
+//     -> mbar_k, through (rho, u, f^neq) of the record;
+//   star value f*_k of an interpolation node (read by interpolation pivots)
+//     -> the adjoints of the structured (rho, u, f^neq) at t and t + 1.
+// The adjoint of each pivot's update is ybar_P, or zwall_P after the no-slip
+// reset transpose at wall pivots.  tau enters through Delta t_u / tau_u and
+// 1 - 1/(2 tau); with K.gbar set, the coefficient adjoints of the entries
+// (P, k) are accumulated too (each entry has one column, so no conflicts): the
+// neighbour part of G_Pk here, the pivot's base part once per pivot in gpivot.
+// With fin_prev set (the input of the previous sub-step), wall nodes also take
+// the no-slip reset transpose of that sub-step from the adjoint just computed,
+// into zwall_prev, so the next launch needs no separate wall pass.
+__global__ __launch_bounds__(256) void k_adj_fv(const KAdj K, const double* __restrict__ fin,
+                                                const double* __restrict__ ybar, const double* __restrict__ zwall,
+                                                double* __restrict__ mbar, const double* __restrict__ prep0,
+                                                const double* __restrict__ prep1, double theta,
+                                                double* __restrict__ p0bar, double* __restrict__ p1bar, int pslot,
+                                                const double* __restrict__ fin_prev, double theta_prev,
+                                                double* __restrict__ zwall_prev) {
     const KMesh& M = K.M;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= M.nn) return;
-    const int nn = M.nn, W = M.ell_width;
-    const bool k_interp = k >= M.n_core;
-    const EdgeRec<double>* T = reinterpret_cast<const EdgeRec<double>*>(K.tedges);
-    double vb[9], nqb[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) vb[q] = nqb[q] = 0.0;
-    for (int z = 0; z < W; ++z) {
-        const EdgeRec<double> e = T[size_t(z) * nn + k];
-        const int P = e.col;
-        if (P < 0) continue;
-        const bool p_interp = P >= M.n_core;
-        if (p_interp && k_interp) continue;   // that pivot reads f* of k, not M_k
-        double zp[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) zp[q] = zbar[size_t(q) * nn + P];
-        if (z == 0) {   // k is its own pivot: base term and self collision
-#pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                vb[q] += zp[q] * (1.0 - K.dt * (CX[q] * e.gx + CY[q] * e.gy));
-                nqb[q] -= K.dtt * e.c * zp[q];
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                vb[q] += K.dt * (CX[q] * e.gx + CY[q] * e.gy) * zp[q];
-                nqb[q] -= K.dtt * e.c * zp[q];
-            }
-        }
-    }
-    // nq = f - feq(f): f_bar += nqb - J_feq^T nqb
-    double f[9], m0, ux, uy, a[12] = {0, 0, 0};
-    load_rec(fin + size_t(k) * kRec, f, m0, ux, uy);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) a[3 + q] = nqb[q];
-    macro_neq_adj(f, a, vb);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) mbar[size_t(q) * nn + k] = vb[q];
-}
-
-// FV sub-step adjoint, phase C (per interpolation slot k): adjoint of the star
-// values f*_k used by interpolation pivots -> (rho, u, f^neq) at t and t+1.
-__global__ __launch_bounds__(256) void k_adj_fv_c(const KAdj K, const double* __restrict__ zbar,
-                                                  const double* __restrict__ prep0, const double* __restrict__ prep1,
-                                                  double theta, double* __restrict__ p0bar, double* __restrict__ p1bar,
-                                                  int pslot) {
-    const KMesh& M = K.M;
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    const int n_int = M.nn - M.n_core;
     double dtau = 0.0;
-    if (s < n_int) {
-        const int nn = M.nn, W = M.ell_width, k = M.n_core + s;
+    if (k < M.nn) {
+        const int nn = M.nn, W = M.ell_width;
+        const int nwall = M.wall_bc ? M.n_wall : 0;
+        const bool k_interp = k >= M.n_core;
         const EdgeRec<double>* T = reinterpret_cast<const EdgeRec<double>*>(K.tedges);
-        double fsb[9], nsb[9];
+        double f[9], m0, ux, uy, feq[9], nq[9];
+        load_rec(fin + size_t(k) * kRec, f, m0, ux, uy);
+        equilibrium<double, false>(m0, m0, ux, uy, feq);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) fsb[q] = nsb[q] = 0.0;
+        for (int q = 0; q < 9; ++q) nq[q] = f[q] - feq[q];
+        double v[12], fs[9], ns[9];
+        if (k_interp) {
+            const size_t sl = size_t(k - M.n_core) * kMacro;
+            star64(prep0 + sl, prep1 + sl, theta, K.cst, v, fs, ns);
+        }
+        double vb[9], nqb[9], fsb[9], nsb[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) vb[q] = nqb[q] = fsb[q] = nsb[q] = 0.0;
         for (int z = 0; z < W; ++z) {
             const EdgeRec<double> e = T[size_t(z) * nn + k];
             const int P = e.col;
-            if (P < M.n_core) continue;   // also skips unused slots (col = -1)
+            if (P < 0) continue;
+            const bool star = k_interp && P >= M.n_core;
             double zp[9];
+            if (P < nwall) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) zp[q] = zbar[size_t(q) * nn + P];
-            const double sfac = z == 0 ? -1.0 : 1.0;
+                for (int q = 0; q < 9; ++q) zp[q] = zwall[size_t(q) * M.n_wall + P];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) zp[q] = ybar[size_t(q) * nn + P];
+            }
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
                 const double sq = CX[q] * e.gx + CY[q] * e.gy;
-                fsb[q] += (z == 0 ? 1.0 : 0.0) * zp[q] + sfac * K.dt * sq * zp[q];
-                nsb[q] -= K.dtt * e.c * zp[q];
+                const double a = z == 0 ? zp[q] * (1.0 - K.dt * sq) : K.dt * sq * zp[q];
+                const double c = -K.dtt * e.c * zp[q];
+                if (star) fsb[q] += a, nsb[q] += c;
+                else vb[q] += a, nqb[q] += c;
+            }
+            if (K.gbar) {
+                double gx = 0.0, gy = 0.0, gc = 0.0;
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    const double val = star ? fs[q] : f[q], nv = star ? ns[q] : nq[q];
+                    gx += zp[q] * CX[q] * val;
+                    gy += zp[q] * CY[q] * val;
+                    gc += zp[q] * nv;
+                }
+                if (z == 0) {
+                    K.gbar[size_t(k) * 3 + 2] -= K.dtt * gc;
+                    K.gpivot[2 * size_t(k)] += K.dt * gx;
+                    K.gpivot[2 * size_t(k) + 1] += K.dt * gy;
+                } else {
+                    double* g = K.gbar + (size_t(e.pad) * nn + P) * 3;
+                    g[0] += K.dt * gx;
+                    g[1] += K.dt * gy;
+                    g[2] -= K.dtt * gc;
+                }
             }
         }
-        double v[12], fs[9], ns[9];
-        const size_t sl = size_t(s) * kMacro;
-        star64(prep0 + sl, prep1 + sl, theta, K.cst, v, fs, ns);
-        // fs = feq(v0, v1, v2) + cst v[3..], ns = cst v[3..]
-        double rb = 0.0, uxb = 0.0, uyb = 0.0, vb[12];
-        feq_adj(v[0], v[1], v[2], fsb, rb, uxb, uyb);
-        vb[0] = rb, vb[1] = uxb, vb[2] = uyb;
-        double dcst = 0.0;
+        const double rdt = K.ddtt_dtau / K.dtt;
+        double a12[12] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            vb[3 + q] = K.cst * (fsb[q] + nsb[q]);
-            dcst += (fsb[q] + nsb[q]) * v[3 + q];
+            dtau += rdt * nq[q] * nqb[q];
+            a12[3 + q] = nqb[q];
         }
-        dtau = dcst * K.dcst_dtau;
+        macro_neq_adj(f, a12, vb);
 #pragma unroll
-        for (int m = 0; m < 12; ++m) {
-            p0bar[sl + m] += (1.0 - theta) * vb[m];
-            p1bar[sl + m] += theta * vb[m];
+        for (int q = 0; q < 9; ++q) mbar[size_t(q) * nn + k] = vb[q];
+        if (fin_prev && k < nwall) {
+            double zb[9];
+            wall_reset_adj(K, fin_prev, prep0, prep1, theta_prev, k, vb, zb);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) zwall_prev[size_t(q) * M.n_wall + k] = zb[q];
+        }
+        if (k_interp) {
+            // fs = feq(v0, v1, v2) + cst v[3..], ns = cst v[3..]
+            double rb = 0.0, uxb = 0.0, uyb = 0.0, w12[12], dcst = 0.0;
+            feq_adj(v[0], v[1], v[2], fsb, rb, uxb, uyb);
+            w12[0] = rb, w12[1] = uxb, w12[2] = uyb;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                w12[3 + q] = K.cst * (fsb[q] + nsb[q]);
+                dcst += (fsb[q] + nsb[q]) * v[3 + q];
+                dtau += rdt * ns[q] * nsb[q];
+            }
+            dtau += dcst * K.dcst_dtau;
+            const size_t sl = size_t(k - M.n_core) * kMacro;
+#pragma unroll
+            for (int m = 0; m < 12; ++m) {
+                p0bar[sl + m] += (1.0 - theta) * w12[m];
+                p1bar[sl + m] += theta * w12[m];
+            }
         }
     }
     block_partial(0.0, dtau, K.partial, pslot);
@@ -1596,17 +1595,16 @@ void launch_adj_force(const KAdj& K, double* mbar, const double* vwall, double j
     if (K.M.n_wall > 0)
         k_adj_force<<<blocks(K.M.n_wall), 256, 0, s>>>(K.M.n_wall, K.M.nn, mbar, vwall, jx, jy, fst, K.vbar);
 }
-void launch_adj_fv_a(const KAdj& K, const double* Mrec, const double* ybar, double* zbar, const double* prep0,
-                     const double* prep1, double theta, int pslot, hipStream_t s) {
-    k_adj_fv_a<<<blocks(K.M.nn), 256, 0, s>>>(K, Mrec, ybar, zbar, prep0, prep1, theta, pslot);
+void launch_adj_fv_wall(const KAdj& K, const double* Mrec, const double* ybar, double* zwall, const double* prep0,
+                        const double* prep1, double theta, hipStream_t s) {
+    if (K.M.wall_bc && K.M.n_wall > 0)
+        k_adj_fv_wall<<<blocks(K.M.n_wall), 256, 0, s>>>(K, Mrec, ybar, zwall, prep0, prep1, theta);
 }
-void launch_adj_fv_b(const KAdj& K, const double* Mrec, const double* zbar, double* mbar, hipStream_t s) {
-    k_adj_fv_b<<<blocks(K.M.nn), 256, 0, s>>>(K, Mrec, zbar, mbar);
-}
-void launch_adj_fv_c(const KAdj& K, const double* zbar, const double* prep0, const double* prep1, double theta,
-                     double* p0bar, double* p1bar, int pslot, hipStream_t s) {
-    const int n = K.M.nn - K.M.n_core;
-    k_adj_fv_c<<<adj_blocks_nodes(n), 256, 0, s>>>(K, zbar, prep0, prep1, theta, p0bar, p1bar, pslot);
+void launch_adj_fv(const KAdj& K, const double* Mrec, const double* ybar, const double* zwall, double* mbar,
+                   const double* prep0, const double* prep1, double theta, double* p0bar, double* p1bar, int pslot,
+                   const double* Mprev, double theta_prev, double* zwall_prev, hipStream_t s) {
+    k_adj_fv<<<adj_blocks_nodes(K.M.nn), 256, 0, s>>>(K, Mrec, ybar, zwall, mbar, prep0, prep1, theta, p0bar, p1bar, pslot,
+                                                     Mprev, theta_prev, zwall_prev);
 }
 void launch_adj_collide(const KAdj& K, const double* A, const double* bbar, double* prebar, int pslot, hipStream_t s) {
     dim3 grid(blocks(K.L.nx), K.L.ny);

@@ -140,10 +140,27 @@ def _surface_parameter(ns: int, spacing: str, bump=None) -> np.ndarray:
     return th
 
 
+def _ellipse_parameter(ns: int, a: float, b: float) -> np.ndarray:
+    """Angles of ns points equally spaced in arc length on the ellipse
+    (a cos t, b sin t), point 0 at t = 0, point ns/2 at t = pi, mirror symmetric."""
+    m = 200001
+    tt = np.linspace(0.0, np.pi, m)
+    seg = np.hypot(np.diff(a * np.cos(tt)), np.diff(b * np.sin(tt)))
+    s = np.concatenate([[0.0], np.cumsum(seg)])
+    half = ns // 2
+    t_up = np.interp(s[-1] * np.arange(half + 1) / half, s, tt)
+    t_up[0], t_up[-1] = 0.0, np.pi
+    t = np.empty(ns)
+    t[:half + 1] = t_up
+    t[half + 1:] = 2.0 * np.pi - t_up[1:half][::-1]
+    return t
+
+
 def naca0012_omesh(chord: float, le: Tuple[float, float], ns: int, nl: int,
                    d_out: float, growth: Optional[float] = None,
                    h1: Optional[float] = None,
-                   bump_amps=None, bump_peaks=None, spacing: str = "arclength") -> OMesh:
+                   bump_amps=None, bump_peaks=None, spacing: str = "arclength",
+                   split: str = "halves", outer: str = "theta") -> OMesh:
     """O-mesh of ns surface points times nl layers around the NACA 0012.
 
     Surface point j (j = 0 at the trailing edge, counter-clockwise) sits at
@@ -152,8 +169,11 @@ def naca0012_omesh(chord: float, le: Tuple[float, float], ns: int, nl: int,
     boundary is the ellipse centred at mid-chord with semi-axes
     (c/2 + d_out, d_out); layer l interpolates between the surface point and
     the ellipse point of the same theta with geometric spacing.  Quads are
-    split along alternating diagonals so that the mesh is mirror symmetric
-    about the chord line.
+    split so that the mesh is mirror symmetric about the chord line: split =
+    "halves" uses one diagonal on the upper half and the mirrored one on the
+    lower half; "checker" alternates the diagonal from quad to quad.  outer =
+    "theta" joins surface point j to the ellipse point of the same theta;
+    "arclength" to the j-th of ns points equally spaced along the ellipse.
     """
     if ns % 2:
         raise ValueError("ns must be even")
@@ -173,8 +193,9 @@ def naca0012_omesh(chord: float, le: Tuple[float, float], ns: int, nl: int,
     sy[ns // 2] = y_le
     xc, yc = x_le + 0.5 * chord, y_le
     a_out, b_out = 0.5 * chord + d_out, d_out
-    ox = xc + a_out * np.cos(th)
-    oy = yc + b_out * np.sin(th)
+    th_out = th if outer == "theta" else _ellipse_parameter(ns, a_out, b_out)
+    ox = xc + a_out * np.cos(th_out)
+    oy = yc + b_out * np.sin(th_out)
     if growth is None:
         if h1 is None:
             raise ValueError("need growth or h1")
@@ -204,7 +225,8 @@ def naca0012_omesh(chord: float, le: Tuple[float, float], ns: int, nl: int,
             jp = (j + 1) % ns
             a, b = l * ns + j, l * ns + jp
             c, d = (l + 1) * ns + jp, (l + 1) * ns + j
-            if j < ns // 2:     # diagonal (j,l)-(j+1,l+1) = a-c
+            use_ac = (j < ns // 2) if split == "halves" else ((j + l) % 2 == 0)
+            if use_ac:          # diagonal (j,l)-(j+1,l+1) = a-c
                 t1, t2 = (a, c, b), (a, d, c)
             else:               # diagonal (j+1,l)-(j,l+1) = b-d
                 t1, t2 = (a, d, b), (b, d, c)
@@ -375,14 +397,15 @@ def _inner_ellipse(om: OMesh) -> Tuple[float, float, float, float]:
 
 
 def _naca_workload(name, nx, ny, patch_sizes, chord, re, u, aoa, ns, nl, d_out,
-                   growth=None, h1=None, steps=1000, bumps=None, notes=""):
+                   growth=None, h1=None, steps=1000, bumps=None, notes="", split="halves", outer="theta"):
     n_ref = len(patch_sizes)
     sp = 2 ** n_ref
     W, H = nx * sp, ny * sp
     le = (float(round(W / 3.0)), 0.5 * H)
     peaks = [0.1 * (m + 1) for m in range(8)]
     om = naca0012_omesh(chord, le, ns, nl, d_out, growth=growth, h1=h1,
-                        bump_amps=bumps, bump_peaks=peaks if bumps is not None else None)
+                        bump_amps=bumps, bump_peaks=peaks if bumps is not None else None, split=split,
+                        outer=outer)
     patches = _place_patches(le[0] + 0.5 * chord, le[1], patch_sizes, n_ref, sp)
     return Workload(name=name, nx_cells=nx, ny_cells=ny, patches=patches, u_inf=u,
                     aoa_deg=aoa, re=re, chord=chord, mesh_xy=om.xy, mesh_tri=om.tri,
@@ -415,10 +438,23 @@ def naca_re100_c40_refined(aoa_deg: float = 0.0, bumps=None) -> Workload:
                           bumps=None if bumps is None else np.asarray(bumps, dtype=np.float64))
 
 
-def naca_re1000_c128(aoa_deg: float = 0.0) -> Workload:
-    """Re = 1000, c = 128: 1024x512 base cells (spacing 2), one 384x192 box, 512x64 mesh."""
-    return _naca_workload("naca0012_re1000_c128_1024x512_r1", 1024, 512, [(384, 192)], 128.0,
-                          1000.0, 0.05, aoa_deg, 512, 64, 92.0, h1=0.5, steps=40000)
+# Thickness of the O-mesh band.  The finite-volume streaming of eq. (3) is a
+# central scheme; where the shed wake crosses the mesh it diverges at these
+# relaxation times (Re = 1000, c = 128, tau_u = 0.0192: a band reaching 92 lu
+# = 0.72 c out diverged after 7,000-31,000 steps for 512-2048 surface points;
+# measured), while a thin band that hands the wake to the Cartesian grid runs
+# 40,000 steps (24 lu = 0.19 c; 512 and 1024 surface points agree on C_D
+# within 0.5%).  The paper's own Re = 1000 meshes are thin bands too (~2.2e4
+# nodes, ~0.8 lu at the wall).
+RE1000_C128_DOUT, RE1000_C128_H1 = 24.0, 0.25
+
+
+def naca_re1000_c128(aoa_deg: float = 0.0, ns: int = 512) -> Workload:
+    """Re = 1000, c = 128: 1024x512 base cells (spacing 2), one 384x192 box, ns x 64 mesh
+    in a band 24 lu thick (first layer 0.25 lu)."""
+    return _naca_workload("naca0012_re1000_c128_1024x512_r1" + ("" if ns == 512 else f"_m{ns}"), 1024, 512,
+                          [(384, 192)], 128.0, 1000.0, 0.05, aoa_deg, ns, 64, RE1000_C128_DOUT,
+                          h1=RE1000_C128_H1, steps=40000)
 
 
 def naca_re1e4_c256() -> Workload:
@@ -428,11 +464,13 @@ def naca_re1e4_c256() -> Workload:
                           188.0, h1=0.512, steps=100000)
 
 
-def naca_re1000_c128_bumps() -> Workload:
-    """Shape-gradient case: the Re = 1000, c = 128 geometry at 5 deg with seeded Hicks-Henne bumps."""
+def naca_re1000_c128_bumps(bumps=None) -> Workload:
+    """Shape-gradient case: the Re = 1000, c = 128 geometry at 5 deg with Hicks-Henne bumps
+    (default: the seeded amplitudes hh_amplitudes(0))."""
+    amps = hh_amplitudes(0) if bumps is None else np.asarray(bumps, dtype=np.float64)
     return _naca_workload("naca0012_re1000_c128_aoa5_bumps", 1024, 512, [(384, 192)], 128.0,
-                          1000.0, 0.05, 5.0, 512, 64, 92.0, h1=0.5, steps=25000,
-                          bumps=hh_amplitudes(0))
+                          1000.0, 0.05, 5.0, 512, 64, RE1000_C128_DOUT, h1=RE1000_C128_H1, steps=25000,
+                          bumps=amps)
 
 
 def naca_re5000_c512() -> Workload:
