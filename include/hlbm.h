@@ -147,11 +147,15 @@ int hlbm_info(hlbm_ctx *ctx, hlbm_info_t *out);
  * every ckpt_every steps in the objective workspace (revolve-style
  * checkpointing); the reverse sweep recomputes each segment from its
  * checkpoint.  mesh_grad != 0 asks the adjoint for d J / d(mesh node
- * coordinates) as well (shape gradient; needs more workspace). */
+ * coordinates) as well (shape gradient; needs more workspace).  Gradients do
+ * not depend on ckpt_every or store_substeps. */
 typedef struct {
     int64_t t_end, t0, t1, ckpt_every;
     double w_cd, w_cl;
     int32_t mesh_grad;
+    int32_t store_substeps;   /* != 0: keep every FV sub-step state of a segment
+                                 (ckpt_every * n_sub mesh states more workspace)
+                                 instead of recomputing them in the reverse sweep */
 } hlbm_objective;
 
 /* Device bytes of the objective workspace (checkpoints, one recomputed

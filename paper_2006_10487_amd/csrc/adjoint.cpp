@@ -42,7 +42,7 @@ struct AdjState {
     int n_slots = 0, nd6 = 0;
     struct {
         size_t ckpt, ckpt_stride, ck_lev[4], ck_side[4], ck_mesh, ck_prep;
-        size_t seg_lev[4], seg_side[4], seg_mesh, seg_prep, sub, awork;
+        size_t seg_lev[4], seg_side[4], seg_mesh, seg_prep, seg_sub, sub, awork;
         size_t abar[4][2], prebar[4], sbar[4][2], vperim[4];
         size_t mbar[2], zwall[2], pbar[2], m5bar;
         size_t partial, acc, tedges, vwall, t5ptr, t5s, t5w, t6node, t6ptr, t6s, t6w, dfeq;
@@ -61,6 +61,9 @@ struct AdjState {
     size_t seg_side_at(int l, int k, int w) const { return off.seg_side[l] + a256(side_bytes[l]) * size_t(2 * k + w); }
     size_t seg_mesh_at(int k) const { return off.seg_mesh + a256(mesh_bytes) * size_t(k); }
     size_t seg_prep_at(int k) const { return off.seg_prep + a256(prep_bytes) * size_t(k); }
+    int n_sub = 0;
+    // state after FV sub-step m + 1 of segment step k (stored sub-steps)
+    size_t seg_sub_at(int k, int m) const { return off.seg_sub + a256(mesh_bytes) * (size_t(k) * n_sub + m); }
 };
 
 namespace {
@@ -106,7 +109,7 @@ void layout(hlbm_ctx* c, AdjState& a) {
     }
     a.mesh_bytes = size_t(kRec) * p.nn * 8;
     a.prep_bytes = size_t(std::max(p.n_int, 1)) * kMacro * 8;
-    a.adjmesh_bytes = size_t(kQ) * p.nn * 8;
+    a.adjmesh_bytes = size_t(kAdjRec) * p.nn * 8;
     size_t off = 0;
     auto take = [&](size_t b) { const size_t o = off; off = a256(off + std::max<size_t>(b, 8)); return o; };
     // one checkpoint: every level's post buffer and side values, the mesh, prep(t)
@@ -131,6 +134,8 @@ void layout(hlbm_ctx* c, AdjState& a) {
     }
     a.off.seg_mesh = take(a256(a.mesh_bytes) * K);
     a.off.seg_prep = take(a256(a.prep_bytes) * (K + 1));
+    a.n_sub = p.n_sub;
+    a.off.seg_sub = a.obj.store_substeps ? take(a256(a.mesh_bytes) * size_t(K) * p.n_sub) : 0;
     a.off.sub = take(a256(a.mesh_bytes) * (p.n_sub + 1));
     a.off.awork = take(maxlev);
     for (int l = 0; l <= p.L; ++l) {
@@ -145,14 +150,14 @@ void layout(hlbm_ctx* c, AdjState& a) {
     }
     a.off.mbar[0] = take(a.adjmesh_bytes);
     a.off.mbar[1] = take(a.adjmesh_bytes);
-    a.off.zwall[0] = take(size_t(kQ) * std::max(p.n_wall, 1) * 8);
-    a.off.zwall[1] = take(size_t(kQ) * std::max(p.n_wall, 1) * 8);
+    a.off.zwall[0] = take(size_t(kAdjRec) * std::max(p.n_wall, 1) * 8);
+    a.off.zwall[1] = take(size_t(kAdjRec) * std::max(p.n_wall, 1) * 8);
     a.off.pbar[0] = take(a.prep_bytes);
     a.off.pbar[1] = take(a.prep_bytes);
     a.off.m5bar = take(std::max<size_t>(p.sint_node.size(), 1) * kMacro * 8);
     // partial-sum slots between two reductions (the largest user)
     const KLevel& F = c->kl[p.L];
-    const int bn = adj_blocks_nodes(p.nn);
+    const int bn = adj_fv_blocks(c->km);
     const int fine = p.n_sub * bn + adj_blocks_collide(F) + bc_blocks(F) +
                      adj_blocks_nodes(int(p.sint_node.size()));
     int coarse = 0, init = 0;
@@ -363,6 +368,10 @@ void recorder(hlbm_ctx* c, int ev, int l) {
         a.rec_rc |= d2d(c, a.ws + a.seg_lev_at(l, k), c->lev(l, c->cur[l]), a.lev_bytes[l]);
         a.rec_rc |= d2d(c, a.ws + a.seg_mesh_at(k), c->mesh(c->mesh_cur), a.mesh_bytes);
         a.rec_rc |= d2d(c, a.ws + a.seg_prep_at(k), c->prep(c->prep_t), a.prep_bytes);
+        if (a.obj.store_substeps) {
+            c->sub_sink = a.ws + a.seg_sub_at(k, 0);
+            c->sub_stride = a256(a.mesh_bytes);
+        }
         ++k;
     }
 }
@@ -406,12 +415,19 @@ void reverse_finest(hlbm_ctx* c, AdjState& a, int64_t t, int k, double& alpha_ho
                               reinterpret_cast<const int32_t*>(c->ws + p.off.sint_don), c->ws + p.off.sint_w, Mt,
                               p.nn, 2.0 * (ts - 1.0) / (2.0 * ts - 1.0), s);
     }
-    // sub-step states M^0..M^n of this step
+    // sub-step states M^0..M^n of this step: recorded by the segment recompute, or recomputed
     const size_t ms = a256(a.mesh_bytes);
-    (void)d2d(c, a.ws + a.off.sub, Mt, a.mesh_bytes);
-    for (int m = 0; m < p.n_sub; ++m)
-        launch_fv_substep(HLBM_FP64, c->km, a.ws + a.off.sub + ms * m, a.ws + a.off.sub + ms * (m + 1), prep0, prep1,
-                          double(m) / p.n_sub, s);
+    const bool stored = a.obj.store_substeps != 0;
+    auto Msub = [&](int m) -> const double* {
+        if (m == 0) return Mt;
+        return stored ? a.at<double>(a.seg_sub_at(k, m - 1)) : a.at<double>(a.off.sub + ms * m);
+    };
+    if (!stored) {
+        (void)d2d(c, a.ws + a.off.sub, Mt, a.mesh_bytes);
+        for (int m = 0; m < p.n_sub; ++m)
+            launch_fv_substep(HLBM_FP64, c->km, a.ws + a.off.sub + ms * m, a.ws + a.off.sub + ms * (m + 1), prep0,
+                              prep1, double(m) / p.n_sub, s);
+    }
     // force^T (history entry t belongs to the state after step t, M^n)
     if (t >= o.t0 && t < o.t1) {
         const double span = double(o.t1 - o.t0);
@@ -419,20 +435,20 @@ void reverse_finest(hlbm_ctx* c, AdjState& a, int64_t t, int k, double& alpha_ho
         const double qn = 0.5 * p.rho0 * p.u_inf * p.u_inf * p.chord;
         const double ca = std::cos(p.aoa), sa = std::sin(p.aoa);
         launch_adj_force(K, a.at<double>(a.off.mbar[a.mb]), a.at<double>(a.off.vwall), (jcd * ca - jcl * sa) / qn,
-                         (jcd * sa + jcl * ca) / qn, a.at<double>(a.off.sub + ms * p.n_sub), s);
+                         (jcd * sa + jcl * ca) / qn, Msub(p.n_sub), s);
         // projection directions depend on alpha: dC_D/dalpha = C_L, dC_L/dalpha = -C_D
         alpha_host += jcd * a.cl[t] - jcl * a.cd[t];
     }
     // FV^T, last sub-step first: one gather per node and sub-step; the no-slip reset
     // transpose of a sub-step is taken by the wall threads of the launch after it
-    const int bn = adj_blocks_nodes(p.nn);
+    const int bn = adj_fv_blocks(c->km);
     int zw = 0;
-    launch_adj_fv_wall(K, a.at<double>(a.off.sub + ms * (p.n_sub - 1)), a.at<double>(a.off.mbar[a.mb]),
-                       a.at<double>(a.off.zwall[zw]), prep0, prep1, double(p.n_sub - 1) / p.n_sub, s);
+    launch_adj_fv_wall(K, Msub(p.n_sub - 1), a.at<double>(a.off.mbar[a.mb]), a.at<double>(a.off.zwall[zw]), prep0,
+                       prep1, double(p.n_sub - 1) / p.n_sub, s);
     for (int m = p.n_sub - 1; m >= 0; --m) {
         const double th = double(m) / p.n_sub;
-        const double* Mm = a.at<double>(a.off.sub + ms * m);
-        const double* Mprev = m > 0 ? a.at<double>(a.off.sub + ms * (m - 1)) : nullptr;
+        const double* Mm = Msub(m);
+        const double* Mprev = m > 0 ? Msub(m - 1) : nullptr;
         launch_adj_fv(K, Mm, a.at<double>(a.off.mbar[a.mb]), a.at<double>(a.off.zwall[zw]),
                       a.at<double>(a.off.mbar[1 - a.mb]), prep0, prep1, th, Pnext, Pcur, slot, Mprev,
                       double(m - 1) / p.n_sub, a.at<double>(a.off.zwall[1 - zw]), s);
@@ -660,7 +676,7 @@ int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad, double* grad_xy) {
     }
     for (double* z : {a.at<double>(a.off.mbar[0]), a.at<double>(a.off.mbar[1])}) launch_zero(z, a.adjmesh_bytes / 8, s);
     for (double* z : {a.at<double>(a.off.zwall[0]), a.at<double>(a.off.zwall[1])})
-        launch_zero(z, size_t(kQ) * std::max(p.n_wall, 1), s);
+        launch_zero(z, size_t(kAdjRec) * std::max(p.n_wall, 1), s);
     launch_zero(a.at<double>(a.off.pbar[0]), a.prep_bytes / 8, s);
     launch_zero(a.at<double>(a.off.pbar[1]), a.prep_bytes / 8, s);
     launch_zero(a.at<double>(a.off.acc), 2, s);
@@ -696,6 +712,7 @@ int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad, double* grad_xy) {
         c->rec = recorder;
         for (int64_t t = ta; t < tb; t += a.per) level_step(c, 0);
         c->rec = nullptr;
+        c->sub_sink = nullptr;
         rc |= a.rec_rc;
         // states after the segment: the post buffer of every refined level, prep at tb
         for (int l = 1; l <= p.L; ++l)

@@ -246,11 +246,23 @@ void finest_step(hlbm_ctx* c) {
             launch_struct_to_mesh(pr, c->kl[L], A, p.n_int, reinterpret_cast<const int32_t*>(c->ws + p.off.uint_don),
                                   c->ws + p.off.uint_w, c->prep(1 - c->prep_t), c->s);
         }
-        for (int m = 0; m < p.n_sub; ++m) {
-            Timed tm(c, HLBM_K_FV);
-            launch_fv_substep(pr, c->km, c->mesh(c->mesh_cur), c->mesh(1 - c->mesh_cur), c->prep(c->prep_t),
-                              c->prep(1 - c->prep_t), double(m) / p.n_sub, c->s);
-            c->mesh_cur ^= 1;
+        if (c->sub_sink) {
+            const void* in = c->mesh(c->mesh_cur);
+            for (int m = 0; m < p.n_sub; ++m) {
+                void* out = c->sub_sink + size_t(m) * c->sub_stride;
+                launch_fv_substep(pr, c->km, in, out, c->prep(c->prep_t), c->prep(1 - c->prep_t), double(m) / p.n_sub,
+                                  c->s);
+                in = out;
+            }
+            (void)hip_check(c, hipMemcpyAsync(c->mesh(c->mesh_cur), in, size_t(kRec) * p.nn * p.elem,
+                                              hipMemcpyDeviceToDevice, c->s), "sub-step states");
+        } else {
+            for (int m = 0; m < p.n_sub; ++m) {
+                Timed tm(c, HLBM_K_FV);
+                launch_fv_substep(pr, c->km, c->mesh(c->mesh_cur), c->mesh(1 - c->mesh_cur), c->prep(c->prep_t),
+                                  c->prep(1 - c->prep_t), double(m) / p.n_sub, c->s);
+                c->mesh_cur ^= 1;
+            }
         }
         const double qn = 0.5 * p.rho0 * p.u_inf * p.u_inf * p.chord;
         Timed tm(c, HLBM_K_FORCE);

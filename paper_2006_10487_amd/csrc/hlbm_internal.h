@@ -23,7 +23,8 @@ constexpr int kQ = 9;
 constexpr int kSDon = 8;     // donors of a structured interpolation node (two 6-node stencils on an edge)
 constexpr int kUDon = 9;     // donors of a mesh interpolation node (3 x 3 block)
 constexpr int kMacro = 12;   // (rho or rho - rho0, ux, uy, f^neq[9])
-constexpr int kRec = 12;     // mesh node record: f_0..f_8, rho (or rho - rho0), ux, uy
+constexpr int kRec = 12;
+constexpr int kAdjRec = 10;   // doubles per mesh node of the adjoint fields (9 used)     // mesh node record: f_0..f_8, rho (or rho - rho0), ux, uy
 
 struct LevelPlan {
     int nx = 0, ny = 0, pitch = 0;  // nodes, row pitch in elements
@@ -199,6 +200,7 @@ void launch_adj_side(const KLevel& P, int ci0, int cj0, int nxc, int nyc, const 
                      double* prebar, hipStream_t s);
 void launch_reduce_partials(const double* partial, int n, double* acc, hipStream_t s);
 int adj_blocks_collide(const KLevel& L);
+int adj_fv_blocks(const KMesh& M);   // partial slots of one launch_adj_fv
 int adj_blocks_nodes(int n);
 
 }  // namespace hlbm
@@ -227,6 +229,11 @@ struct hlbm_ctx {
     // event 0 = entry of a level-l step (l < L), 1 = the parent's side values of
     // that step are recorded, 2 = entry of a finest step (before eq. (4))
     void (*rec)(hlbm_ctx*, int event, int level) = nullptr;
+    // with sub_sink set, the FV sub-steps of the next finest step write their
+    // states to sub_sink + m * sub_stride (m = 0..n-1, the state after sub-step
+    // m + 1); the last one is copied back into the mesh buffer
+    char* sub_sink = nullptr;
+    size_t sub_stride = 0;
     // instrumentation
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;

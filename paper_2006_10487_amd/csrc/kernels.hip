@@ -915,7 +915,7 @@ __global__ void k_adj_force(int n_wall, int nn, double* __restrict__ mbar, const
     if (P >= n_wall) return;
 #pragma unroll
     for (int q = 0; q < 9; ++q)
-        mbar[size_t(q) * nn + P] += (CX[q] * jx + CY[q] * jy) * (CX[q] * V[2 * P] + CY[q] * V[2 * P + 1]);
+        mbar[size_t(P) * kAdjRec + q] += (CX[q] * jx + CY[q] * jy) * (CX[q] * V[2 * P] + CY[q] * V[2 * P + 1]);
     if (vbar) {
         double f[9], m0, ux, uy, ax = 0.0, ay = 0.0;
         load_rec(fst + size_t(P) * kRec, f, m0, ux, uy);
@@ -960,6 +960,22 @@ __device__ __forceinline__ void fv_value(const KAdj& K, const double* fin, const
 #pragma unroll
         for (int q = 0; q < 9; ++q) nq[q] = f[q] - feq[q];
     }
+}
+
+// Mesh adjoints are node records of kAdjRec doubles (9 used, 16-byte aligned),
+// so a gather of a neighbour's nine values is five 16-byte loads.
+__device__ __forceinline__ void load_adj(const double* __restrict__ p, D9& v) {
+    const double2* r = reinterpret_cast<const double2*>(p);
+    const double2 a = r[0], b = r[1], c = r[2], d = r[3], e = r[4];
+    v[0] = a.x, v[1] = a.y, v[2] = b.x, v[3] = b.y, v[4] = c.x, v[5] = c.y, v[6] = d.x, v[7] = d.y, v[8] = e.x;
+}
+__device__ __forceinline__ void store_adj(double* __restrict__ p, const D9& v) {
+    double2* r = reinterpret_cast<double2*>(p);
+    r[0] = double2{v[0], v[1]};
+    r[1] = double2{v[2], v[3]};
+    r[2] = double2{v[4], v[5]};
+    r[3] = double2{v[6], v[7]};
+    r[4] = double2{v[8], 0.0};
 }
 
 // Adjoint of the no-slip reset at wall pivot P: recompute the pre-reset update
@@ -1016,10 +1032,9 @@ __global__ __launch_bounds__(256) void k_adj_fv_wall(const KAdj K, const double*
     if (P >= M.n_wall) return;
     double yb[9], zb[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) yb[q] = ybar[size_t(q) * M.nn + P];
+    for (int q = 0; q < 9; ++q) yb[q] = ybar[size_t(P) * kAdjRec + q];
     wall_reset_adj(K, fin, prep0, prep1, theta, P, yb, zb);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) zwall[size_t(q) * M.n_wall + P] = zb[q];
+    store_adj(zwall + size_t(P) * kAdjRec, zb);
 }
 
 // FV sub-step adjoint (per node k): the adjoint of every value of k that the
@@ -1037,63 +1052,54 @@ __global__ __launch_bounds__(256) void k_adj_fv_wall(const KAdj K, const double*
 // With fin_prev set (the input of the previous sub-step), wall nodes also take
 // the no-slip reset transpose of that sub-step from the adjoint just computed,
 // into zwall_prev, so the next launch needs no separate wall pass.
-__global__ __launch_bounds__(256) void k_adj_fv(const KAdj K, const double* __restrict__ fin,
-                                                const double* __restrict__ ybar, const double* __restrict__ zwall,
-                                                double* __restrict__ mbar, const double* __restrict__ prep0,
-                                                const double* __restrict__ prep1, double theta,
-                                                double* __restrict__ p0bar, double* __restrict__ p1bar, int pslot,
-                                                const double* __restrict__ fin_prev, double theta_prev,
-                                                double* __restrict__ zwall_prev) {
+// Adjoint of the values of node k read through one class of pivots: the stored
+// mesh value (STAR = false: every pivot unless both are interpolation nodes)
+// or the star value of an interpolation node (STAR = true: interpolation
+// pivots).  Accumulates into vb (adjoint of the value), nb (of its f^neq part)
+// and, with K.gbar, the coefficient adjoints of the entries read.
+template <int W, bool STAR>
+__device__ __forceinline__ void adj_fv_gather(const KAdj& K, int k, bool k_interp, const double* __restrict__ ybar,
+                                              const double* __restrict__ zwall, const D9& val, const D9& nval, D9& vb,
+                                              D9& nb) {
     const KMesh& M = K.M;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    double dtau = 0.0;
-    if (k < M.nn) {
-        const int nn = M.nn, W = M.ell_width;
-        const int nwall = M.wall_bc ? M.n_wall : 0;
-        const bool k_interp = k >= M.n_core;
-        const EdgeRec<double>* T = reinterpret_cast<const EdgeRec<double>*>(K.tedges);
-        double f[9], m0, ux, uy, feq[9], nq[9];
-        load_rec(fin + size_t(k) * kRec, f, m0, ux, uy);
-        equilibrium<double, false>(m0, m0, ux, uy, feq);
+    const int nn = M.nn;
+    const int nwall = M.wall_bc ? M.n_wall : 0;
+    const EdgeRec<double>* T = reinterpret_cast<const EdgeRec<double>*>(K.tedges);
+    // slots in pairs: both table entries, then both pivot adjoints are loaded
+    // before the arithmetic
+    constexpr int G = 2;
+#pragma unroll 1
+    for (int g0 = 0; g0 < W; g0 += G) {
+        EdgeRec<double> eg[G];
+        double zg[G][9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) nq[q] = f[q] - feq[q];
-        double v[12], fs[9], ns[9];
-        if (k_interp) {
-            const size_t sl = size_t(k - M.n_core) * kMacro;
-            star64(prep0 + sl, prep1 + sl, theta, K.cst, v, fs, ns);
+        for (int a = 0; a < G; ++a) eg[a] = T[size_t(g0 + a) * nn + k];
+#pragma unroll
+        for (int a = 0; a < G; ++a) {
+            const int P = eg[a].col < 0 ? k : eg[a].col;
+            load_adj((P < nwall ? zwall : ybar) + size_t(P) * kAdjRec, zg[a]);
         }
-        double vb[9], nqb[9], fsb[9], nsb[9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) vb[q] = nqb[q] = fsb[q] = nsb[q] = 0.0;
-        for (int z = 0; z < W; ++z) {
-            const EdgeRec<double> e = T[size_t(z) * nn + k];
+        for (int a = 0; a < G; ++a) {
+            const EdgeRec<double>& e = eg[a];
+            const int z = g0 + a;
             const int P = e.col;
             if (P < 0) continue;
-            const bool star = k_interp && P >= M.n_core;
-            double zp[9];
-            if (P < nwall) {
-#pragma unroll
-                for (int q = 0; q < 9; ++q) zp[q] = zwall[size_t(q) * M.n_wall + P];
-            } else {
-#pragma unroll
-                for (int q = 0; q < 9; ++q) zp[q] = ybar[size_t(q) * nn + P];
-            }
+            if ((k_interp && P >= M.n_core) != STAR) continue;
+            const double(&zp)[9] = zg[a];
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
                 const double sq = CX[q] * e.gx + CY[q] * e.gy;
-                const double a = z == 0 ? zp[q] * (1.0 - K.dt * sq) : K.dt * sq * zp[q];
-                const double c = -K.dtt * e.c * zp[q];
-                if (star) fsb[q] += a, nsb[q] += c;
-                else vb[q] += a, nqb[q] += c;
+                vb[q] += z == 0 ? zp[q] * (1.0 - K.dt * sq) : K.dt * sq * zp[q];
+                nb[q] -= K.dtt * e.c * zp[q];
             }
             if (K.gbar) {
                 double gx = 0.0, gy = 0.0, gc = 0.0;
 #pragma unroll
                 for (int q = 0; q < 9; ++q) {
-                    const double val = star ? fs[q] : f[q], nv = star ? ns[q] : nq[q];
-                    gx += zp[q] * CX[q] * val;
-                    gy += zp[q] * CY[q] * val;
-                    gc += zp[q] * nv;
+                    gx += zp[q] * CX[q] * val[q];
+                    gy += zp[q] * CY[q] * val[q];
+                    gc += zp[q] * nval[q];
                 }
                 if (z == 0) {
                     K.gbar[size_t(k) * 3 + 2] -= K.dtt * gc;
@@ -1107,23 +1113,51 @@ __global__ __launch_bounds__(256) void k_adj_fv(const KAdj K, const double* __re
                 }
             }
         }
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_adj_fv(const KAdj K, const double* __restrict__ fin,
+                                                const double* __restrict__ ybar, const double* __restrict__ zwall,
+                                                double* __restrict__ mbar, const double* __restrict__ prep0,
+                                                const double* __restrict__ prep1, double theta,
+                                                double* __restrict__ p0bar, double* __restrict__ p1bar, int pslot,
+                                                const double* __restrict__ fin_prev, double theta_prev,
+                                                double* __restrict__ zwall_prev) {
+    const KMesh& M = K.M;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    double dtau = 0.0;
+    if (k < M.nn) {
+        const bool k_interp = k >= M.n_core;
         const double rdt = K.ddtt_dtau / K.dtt;
-        double a12[12] = {0.0, 0.0, 0.0};
+        {   // the stored value M^m_k
+            double f[9], m0, ux, uy, feq[9], nq[9], vb[9], nqb[9];
+            load_rec(fin + size_t(k) * kRec, f, m0, ux, uy);
+            equilibrium<double, false>(m0, m0, ux, uy, feq);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            dtau += rdt * nq[q] * nqb[q];
-            a12[3 + q] = nqb[q];
+            for (int q = 0; q < 9; ++q) nq[q] = f[q] - feq[q], vb[q] = nqb[q] = 0.0;
+            adj_fv_gather<W, false>(K, k, k_interp, ybar, zwall, f, nq, vb, nqb);
+            double a12[12] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                dtau += rdt * nq[q] * nqb[q];
+                a12[3 + q] = nqb[q];
+            }
+            macro_neq_adj(f, a12, vb);
+            store_adj(mbar + size_t(k) * kAdjRec, vb);
+            if (fin_prev && k < (M.wall_bc ? M.n_wall : 0)) {
+                double zb[9];
+                wall_reset_adj(K, fin_prev, prep0, prep1, theta_prev, k, vb, zb);
+                store_adj(zwall_prev + size_t(k) * kAdjRec, zb);
+            }
         }
-        macro_neq_adj(f, a12, vb);
+        if (k_interp) {   // the star value f*_k read by interpolation pivots
+            const size_t sl = size_t(k - M.n_core) * kMacro;
+            double v[12], fs[9], ns[9], fsb[9], nsb[9];
+            star64(prep0 + sl, prep1 + sl, theta, K.cst, v, fs, ns);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) mbar[size_t(q) * nn + k] = vb[q];
-        if (fin_prev && k < nwall) {
-            double zb[9];
-            wall_reset_adj(K, fin_prev, prep0, prep1, theta_prev, k, vb, zb);
-#pragma unroll
-            for (int q = 0; q < 9; ++q) zwall_prev[size_t(q) * M.n_wall + k] = zb[q];
-        }
-        if (k_interp) {
+            for (int q = 0; q < 9; ++q) fsb[q] = nsb[q] = 0.0;
+            adj_fv_gather<W, true>(K, k, true, ybar, zwall, fs, ns, fsb, nsb);
             // fs = feq(v0, v1, v2) + cst v[3..], ns = cst v[3..]
             double rb = 0.0, uxb = 0.0, uyb = 0.0, w12[12], dcst = 0.0;
             feq_adj(v[0], v[1], v[2], fsb, rb, uxb, uyb);
@@ -1135,7 +1169,6 @@ __global__ __launch_bounds__(256) void k_adj_fv(const KAdj K, const double* __re
                 dtau += rdt * ns[q] * nsb[q];
             }
             dtau += dcst * K.dcst_dtau;
-            const size_t sl = size_t(k - M.n_core) * kMacro;
 #pragma unroll
             for (int m = 0; m < 12; ++m) {
                 p0bar[sl + m] += (1.0 - theta) * w12[m];
@@ -1385,7 +1418,7 @@ __global__ void k_adj_m2s_b(const KAdj K, const double* __restrict__ mf, const i
     for (int q = 0; q < 9; ++q) fb[q] = 0.0;
     macro_neq_adj(f, a, fb);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) mbar[size_t(q) * nn + d] += fb[q];
+    for (int q = 0; q < 9; ++q) mbar[size_t(d) * kAdjRec + q] += fb[q];
     if (K.w5bar) {   // d J / d w_sd = m5bar_s . (rho, u, f^neq)(M_d)
         double mac[12], feq[9];
         mac[0] = m0, mac[1] = ux, mac[2] = uy;
@@ -1417,7 +1450,7 @@ __global__ __launch_bounds__(256) void k_adj_alpha_state(const KAdj K, const dou
         const size_t P = e - nlev;
         if (!(K.M.wall_bc && int(P) < K.M.n_wall)) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) da += mbar[size_t(q) * size_t(nmesh) + P] * dfeq[q];
+            for (int q = 0; q < 9; ++q) da += mbar[P * kAdjRec + q] * dfeq[q];
         }
     }
     block_partial(da, 0.0, K.partial, pslot);
@@ -1586,6 +1619,7 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
 
 int adj_blocks_collide(const KLevel& L) { return int(blocks(L.nx)) * L.ny; }
 int adj_blocks_nodes(int n) { return int(blocks(size_t(n > 0 ? n : 1))); }
+int adj_fv_blocks(const KMesh& M) { return adj_blocks_nodes(M.nn); }
 
 void launch_zero(double* p, size_t n, hipStream_t s) {
     if (n) k_zero<<<blocks(n), 256, 0, s>>>(p, n);
@@ -1603,8 +1637,12 @@ void launch_adj_fv_wall(const KAdj& K, const double* Mrec, const double* ybar, d
 void launch_adj_fv(const KAdj& K, const double* Mrec, const double* ybar, const double* zwall, double* mbar,
                    const double* prep0, const double* prep1, double theta, double* p0bar, double* p1bar, int pslot,
                    const double* Mprev, double theta_prev, double* zwall_prev, hipStream_t s) {
-    k_adj_fv<<<adj_blocks_nodes(K.M.nn), 256, 0, s>>>(K, Mrec, ybar, zwall, mbar, prep0, prep1, theta, p0bar, p1bar, pslot,
-                                                     Mprev, theta_prev, zwall_prev);
+    if (K.M.ell_width == 8)
+        k_adj_fv<8><<<adj_blocks_nodes(K.M.nn), 256, 0, s>>>(K, Mrec, ybar, zwall, mbar, prep0, prep1, theta, p0bar, p1bar,
+                                                            pslot, Mprev, theta_prev, zwall_prev);
+    else
+        k_adj_fv<16><<<adj_blocks_nodes(K.M.nn), 256, 0, s>>>(K, Mrec, ybar, zwall, mbar, prep0, prep1, theta, p0bar,
+                                                             p1bar, pslot, Mprev, theta_prev, zwall_prev);
 }
 void launch_adj_collide(const KAdj& K, const double* A, const double* bbar, double* prebar, int pslot, hipStream_t s) {
     dim3 grid(blocks(K.L.nx), K.L.ny);

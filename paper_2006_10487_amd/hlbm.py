@@ -59,7 +59,8 @@ class Mesh(C.Structure):
 
 class Objective(C.Structure):
     _fields_ = [("t_end", C.c_int64), ("t0", C.c_int64), ("t1", C.c_int64), ("ckpt_every", C.c_int64),
-                ("w_cd", C.c_double), ("w_cl", C.c_double), ("mesh_grad", C.c_int32)]
+                ("w_cd", C.c_double), ("w_cl", C.c_double), ("mesh_grad", C.c_int32),
+                ("store_substeps", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -279,15 +280,26 @@ class HLBM:
         return ms.value
 
     def run_objective(self, t_end: int, t0: int, t1: int, ckpt_every: int = 100, w_cd: float = 1.0,
-                      w_cl: float = 0.0, mesh_grad: bool = False) -> float:
+                      w_cl: float = 0.0, mesh_grad: bool = False, store_substeps=None) -> float:
         """Run from the initial state and return the windowed mean of w_cd C_D + w_cl C_L.
 
-        mesh_grad: the following adjoint also returns d J / d(mesh coordinates)."""
+        mesh_grad: the following adjoint also returns d J / d(mesh coordinates).
+        store_substeps: keep the FV sub-step states of a segment instead of
+        recomputing them (None: when the workspace stays under half the free
+        device memory)."""
         import torch
-        o = Objective(int(t_end), int(t0), int(t1), int(ckpt_every), float(w_cd), float(w_cl), int(bool(mesh_grad)))
+        o = Objective(int(t_end), int(t0), int(t1), int(ckpt_every), float(w_cd), float(w_cl), int(bool(mesh_grad)), 0)
         n = C.c_size_t(0)
+        if store_substeps is None or store_substeps:
+            o.store_substeps = 1
+            self._check(lib().hlbm_objective_workspace_size(self._ctx, C.byref(o), C.byref(n)))
+            if store_substeps is None:
+                free, _ = torch.cuda.mem_get_info()
+                have = 0 if getattr(self, "obj_ws", None) is None else self.obj_ws.numel()
+                o.store_substeps = int(n.value <= 0.5 * (free + have))
         self._check(lib().hlbm_objective_workspace_size(self._ctx, C.byref(o), C.byref(n)))
         if getattr(self, "obj_ws", None) is None or self.obj_ws.numel() < n.value:
+            self.obj_ws = None   # release the smaller workspace first
             self.obj_ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
         self._objective = o
         J = C.c_double()

@@ -192,6 +192,18 @@ def test_refined_checkpoint_interval_independent():
     assert np.array_equal(g[0], g[1]) and np.array_equal(g[0], g[2])
 
 
+@pytest.mark.parametrize("refined", [False, True])
+def test_stored_and_recomputed_substeps_agree(refined):
+    """Keeping the FV sub-step states of a segment or recomputing them gives the same bits."""
+    w = (W.naca_re100_c40_refined if refined else W.naca_re100_c40)(3.0, bumps=W.hh_amplitudes(1))
+    out = []
+    for store in (False, True):
+        _, sim = gpu_J(w, w.aoa_rad, w.tau_s, spec=dict(SPEC, store_substeps=store), mesh_grad=True)
+        out.append((sim.adjoint(), sim.grad_xy.copy()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
 def test_refined_objective_rejects_odd_steps():
     w = W.naca_re100_c40_refined(3.0)
     sim = hlbm.HLBM.from_workload(w, n_sub=N_SUB)
