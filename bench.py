@@ -47,11 +47,14 @@ def run_precision(w, precision, steps, warmup, hlbm, torch):
     progress(f"timed {steps} steps in {t1 - t0:.3f} s")
     # per-kernel breakdown: the same number of steps with every launch
     # bracketed by HIP events (the brackets add launch gaps; not used for value)
+    # (with the running means of the wall coefficients, eqs. (12)-(13), switched on)
+    sim.wall_stats_begin()
     sim.profile(True)
     sim.profile_read()
     sim.step(per * steps)
     prof = sim.profile_read()
     sim.profile(False)
+    wall = sim.wall_stats()
     cd, cl = sim.history(sim.t - per * (warmup + 2 * steps), sim.t)
     # back-to-back launches of single kernels (pure kernel time per launch)
     pure = {"fv_substep": sim.kernel_bench("fv_substep", 400) if info.n_mesh_nodes else None}
@@ -61,7 +64,7 @@ def run_precision(w, precision, steps, warmup, hlbm, torch):
     struct_updates = sum(int(info.active_nodes[l]) << l for l in range(info.n_levels))
     fv_updates = per * info.n_sub * int(info.n_mesh_nodes)
     return dict(sim=sim, info=info, prof=prof, pure=pure, t=t1 - t0,
-                struct_updates=struct_updates, fv_updates=fv_updates, cd=cd, cl=cl)
+                struct_updates=struct_updates, fv_updates=fv_updates, cd=cd, cl=cl, wall=wall)
 
 
 def kernel_bytes(info, k):
@@ -226,6 +229,16 @@ def main():
     res["roofline_base_grid"] = roofline(k32, "collide_l0", "base-level fused stream-collide (72 B per node)",
                                          measured_traffic("collide_l0") if w.name == "naca0012_re5000_c512_8192x4096_r1" else None)
     res["kernels_fp32"] = k32
+    if "wall_stats" in k32:
+        n_wall = int(r32["wall"][1].size)
+        ws = k32["wall_stats"]
+        res["wall_stats"] = {
+            "kernel": "wall_stats", "bound": "latency", "n_wall": n_wall, "launches": ws["launches"],
+            "event_avg_us": ws["event_avg_us"], "share_of_step": ws["share"],
+            "alg_bytes_per_launch": n_wall * (12 * 4 + 16 + 48),
+            "steps_averaged": r32["wall"][0],
+            "note": "running means of C_p, C_f, C_n at the wall nodes (eqs. (12)-(13)), one launch per finest "
+                    "step while switched on; a few hundred KB per launch, so launch latency bounds it"}
     res["fv_msubsteps_per_s"] = round(r32["fv_updates"] * a.steps / t32 / 1e6, 1)
     if not a.no_fp64:
         r64 = run_precision(w, hlbm.FP64, a.steps, a.warmup, hlbm, torch)

@@ -160,8 +160,8 @@ typedef struct {
 
 /* Device bytes of the objective workspace (checkpoints, one recomputed
  * segment, the adjoint fields and transposed tables).  Supported: FP64
- * contexts with a single structured level (n_refine = 0) and a walled mesh;
- * other contexts get HLBM_E_ARG. */
+ * contexts with a walled mesh and any number of refinement boxes; other
+ * contexts get HLBM_E_ARG. */
 int hlbm_objective_workspace_size(hlbm_ctx *ctx, const hlbm_objective *obj, size_t *bytes);
 
 /* Restarts the run from the initial state, advances obj->t_end finest steps,
@@ -182,6 +182,27 @@ int hlbm_run_objective(hlbm_ctx *ctx, const hlbm_objective *obj, void *d_ckpt, s
  * mid-run state: run the objective again before another adjoint.  Syncs. */
 int hlbm_adjoint(hlbm_ctx *ctx, double J_bar, double *grad, double *grad_xy);
 
+/* Mean wall coefficients, eqs. (12)-(13).  After hlbm_wall_stats_begin, every
+ * finest step taken by hlbm_step adds its post-step values at each wall node
+ * (kind 1) to FP64 running sums on the device:
+ *   C_p = (rho - rho0) c_s^2 / q   (pressure p = rho c_s^2, q = rho0 u_inf^2 / 2),
+ *   C_f = t . sigma . n / q        (wall shear stress),
+ *   C_n = n . sigma . n / q        (normal viscous stress),
+ * with sigma = -(sum_i c_i c_i f_i - rho c_s^2 I - rho u u), the viscous
+ * stress of the continuous BGK equation that the finite-volume scheme
+ * integrates (viscosity c_s^2 tau_u), n the unit normal into the fluid
+ * (opposite to the sum of the node's two half wall-edge normals) and
+ * t = (n_y, -n_x) the wall tangent with the fluid on its left.  Clears the sums
+ * (async).  hlbm_run_objective and hlbm_set_state end the accumulation. */
+int hlbm_wall_stats_begin(hlbm_ctx *ctx);
+
+/* Time means since hlbm_wall_stats_begin: *n_steps = number of finest steps
+ * averaged; cp, cf (and cn unless NULL) receive one value per wall node, in
+ * increasing caller node index (host arrays of n_wall doubles, n_wall = number
+ * of kind-1 nodes).  HLBM_E_STATE when no accumulation is in effect or no step
+ * was taken.  Syncs. */
+int hlbm_wall_stats(hlbm_ctx *ctx, int64_t *n_steps, double *cp, double *cf, double *cn);
+
 /* Kernel classes timed by hlbm_profile_read. */
 enum {
     HLBM_K_COLLIDE_L0 = 0,      /* collide-stream of level 0 (+1, +2, +3 for finer levels) */
@@ -191,7 +212,8 @@ enum {
     HLBM_K_STRUCT_TO_MESH = 7,  /* eq. (9) */
     HLBM_K_FV = 8,              /* one finite-volume sub-step, eqs. (3), (5) */
     HLBM_K_FORCE = 9,           /* eqs. (10)-(11) */
-    HLBM_K_COUNT = 10
+    HLBM_K_WALL_STATS = 10,     /* eqs. (12)-(13), while hlbm_wall_stats_begin is in effect */
+    HLBM_K_COUNT = 11
 };
 
 /* Instrumentation: with enable != 0, every kernel launched by hlbm_step is

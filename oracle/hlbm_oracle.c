@@ -158,6 +158,10 @@ typedef struct {
     int64_t t;             /* finest steps done */
     int64_t hist_cap;
     real *cd, *cl;
+    /* running sums of the wall coefficients, eqs. (12)-(13), per wall node */
+    int ws_on, n_wn;
+    int64_t ws_n;
+    real *ws_sum, *ws_tmp; /* [3][n_wn] each */
     char err[256];
 } oracle_t;
 
@@ -881,6 +885,7 @@ void or_destroy(void *h)
     free(o->cc); free(o->area); free(o->wedge); free(o->fu); free(o->fu_new);
     free(o->sint_ij); free(o->sint_don); free(o->sint_w); free(o->uint_node); free(o->uint_slot);
     free(o->uint_don); free(o->uint_w); free(o->cd); free(o->cl);
+    free(o->ws_sum); free(o->ws_tmp);
     free(o);
 }
 
@@ -1208,6 +1213,54 @@ static void wall_force(const oracle_t *o, real *fx, real *fy)
     *fx = sx; *fy = sy;
 }
 
+/* Pressure and wall stresses at the wall nodes, eqs. (12)-(13).  Pressure is
+ * p = rho c_s^2, so C_p = (rho - rho0) c_s^2 / q with q = rho0 U^2 / 2.  The FV
+ * scheme integrates the continuous BGK equation, whose first-order
+ * non-equilibrium moment gives the viscous stress directly:
+ *   sigma = -Pi^neq,  Pi^neq = sum_i c_i c_i f_i - rho c_s^2 I - rho u u
+ * (viscosity c_s^2 tau_u, no half-step shift).  At wall node P, V_P is half the
+ * sum of the outward (into the body) length-normals of its wall edges; n = -V_P
+ * / |V_P| points into the fluid and t = (n_y, -n_x) runs along the wall with the
+ * fluid on its left.  Per wall node, in node order: C_p, the shear
+ * C_f = t.sigma.n / q and the normal viscous stress C_n = n.sigma.n / q. */
+static void wall_coefficients(const oracle_t *o, real *cp, real *cf, real *cn)
+{
+    real *V = (real *)calloc((size_t)2 * o->nn, sizeof(real));
+    for (int e = 0; e < o->n_wall_edges; ++e) {
+        int P = o->wedge[2 * e], Qn = o->wedge[2 * e + 1];
+        real nx = o->xy[2 * Qn + 1] - o->xy[2 * P + 1], ny = -(o->xy[2 * Qn] - o->xy[2 * P]);
+        V[2 * P] += 0.5 * nx; V[2 * P + 1] += 0.5 * ny;
+        V[2 * Qn] += 0.5 * nx; V[2 * Qn + 1] += 0.5 * ny;
+    }
+    const double CS2 = 1.0 / 3.0;
+    real q = 0.5 * o->cfg.rho0 * o->cfg.u_inf * o->cfg.u_inf;
+    int w = 0;
+    for (int P = 0; P < o->nn; ++P) {
+        if (o->kind[P] != KIND_WALL) continue;
+        real f[Q], rho, ux, uy;
+        for (int i = 0; i < Q; ++i) f[i] = o->fu[(size_t)i * o->nn + P];
+        moments(f, &rho, &ux, &uy);
+        real pxx = 0.0, pxy = 0.0, pyy = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            pxx += CX[i] * CX[i] * f[i];
+            pxy += CX[i] * CY[i] * f[i];
+            pyy += CY[i] * CY[i] * f[i];
+        }
+        real sxx = -(pxx - rho * CS2 - rho * ux * ux);
+        real sxy = -(pxy - rho * ux * uy);
+        real syy = -(pyy - rho * CS2 - rho * uy * uy);
+        real len = sqrt(V[2 * P] * V[2 * P] + V[2 * P + 1] * V[2 * P + 1]);
+        real nx = -V[2 * P] / len, ny = -V[2 * P + 1] / len;
+        real tx = ny, ty = -nx;
+        real snx = sxx * nx + sxy * ny, sny = sxy * nx + syy * ny; /* sigma . n */
+        cp[w] = (rho - o->cfg.rho0) * CS2 / q;
+        cf[w] = (tx * snx + ty * sny) / q;
+        cn[w] = (nx * snx + ny * sny) / q;
+        w++;
+    }
+    free(V);
+}
+
 static void record_forces(oracle_t *o)
 {
     if (o->t >= o->hist_cap) {
@@ -1223,6 +1276,12 @@ static void record_forces(oracle_t *o)
     o->cd[o->t] = (fx * ca + fy * sa) / qd;
     o->cl[o->t] = (-fx * sa + fy * ca) / qd;
     o->t++;
+    if (o->ws_on) {
+        real *c = o->ws_tmp;
+        wall_coefficients(o, c, c + o->n_wn, c + 2 * o->n_wn);
+        for (int k = 0; k < 3 * o->n_wn; ++k) o->ws_sum[k] += c[k];
+        o->ws_n++;
+    }
 }
 
 /* ------------------------------------------------------------------ */
@@ -1322,6 +1381,44 @@ int or_sint(void *h, int32_t *ij, int32_t *don, real *w)
         for (int d = 0; d < SDON; ++d) { don[SDON * s + d] = o->sint_don[SDON * s + d]; w[SDON * s + d] = o->sint_w[SDON * s + d]; }
     }
     return o->n_sint;
+}
+
+/* Starts the time means of the wall coefficients: every finest step from now
+ * on adds its post-step values.  Returns the number of wall nodes. */
+int or_wall_stats_begin(void *h)
+{
+    oracle_t *o = (oracle_t *)h;
+    int n = 0;
+    for (int P = 0; P < o->nn; ++P) n += o->kind[P] == KIND_WALL;
+    free(o->ws_sum); free(o->ws_tmp);
+    o->n_wn = n;
+    o->ws_sum = (real *)calloc((size_t)3 * n + 1, sizeof(real));
+    o->ws_tmp = (real *)calloc((size_t)3 * n + 1, sizeof(real));
+    o->ws_n = 0;
+    o->ws_on = 1;
+    return n;
+}
+
+/* Time means since or_wall_stats_begin, per wall node in node order:
+ * C_p, C_f, C_n (see wall_coefficients).  Returns the number of steps. */
+int64_t or_wall_stats(void *h, real *cp, real *cf, real *cn)
+{
+    oracle_t *o = (oracle_t *)h;
+    if (!o->ws_on) return -1;
+    for (int w = 0; w < o->n_wn; ++w) {
+        cp[w] = o->ws_sum[w] / (real)o->ws_n;
+        cf[w] = o->ws_sum[o->n_wn + w] / (real)o->ws_n;
+        cn[w] = o->ws_sum[2 * o->n_wn + w] / (real)o->ws_n;
+    }
+    return o->ws_n;
+}
+
+/* the same coefficients for the current mesh state */
+int or_wall_coefficients(void *h, real *cp, real *cf, real *cn)
+{
+    oracle_t *o = (oracle_t *)h;
+    wall_coefficients(o, cp, cf, cn);
+    return 0;
 }
 
 /* wall force of the current mesh state (not normalised) */

@@ -69,6 +69,11 @@ def lib():
         L.or_info.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_sint.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_wall_force.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_wall_stats_begin.argtypes = [C.c_void_p]
+        L.or_wall_stats_begin.restype = C.c_int
+        L.or_wall_stats.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_wall_stats.restype = C.c_int64
+        L.or_wall_coefficients.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_equilibrium.argtypes = [C.c_double, C.c_double, C.c_double, C.c_void_p]
         L.or_bgk.argtypes = [C.c_void_p, C.c_double, C.c_void_p]
         L.or_lattice.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -219,8 +224,10 @@ class Oracle:
             cfg.tri = tri.ctypes.data_as(C.POINTER(C.c_int32))
             cfg.kind = kind.ctypes.data_as(C.POINTER(C.c_uint8))
             self.n_nodes = xy.shape[0]
+            self._kind = kind
         else:
             self.n_nodes = 0
+            self._kind = np.zeros(0, np.uint8)
         err = C.create_string_buffer(256)
         h = lib().or_create(C.byref(cfg), err, 256)
         if not h:
@@ -311,6 +318,27 @@ class Oracle:
         fy = np.zeros(1)
         lib().or_wall_force(self._h, _p(fx), _p(fy))
         return float(fx[0]), float(fy[0])
+
+    # wall coefficients, eqs. (12)-(13): one entry per wall node, in node order
+
+    def wall_stats_begin(self) -> int:
+        """Start time means of C_p, C_f, C_n over the finest steps that follow."""
+        self._n_wn = lib().or_wall_stats_begin(self._h)
+        return self._n_wn
+
+    def wall_stats(self):
+        """(steps, C_p, C_f, C_n) time means since wall_stats_begin()."""
+        n = self._n_wn
+        cp, cf, cn = np.zeros(max(n, 1)), np.zeros(max(n, 1)), np.zeros(max(n, 1))
+        steps = lib().or_wall_stats(self._h, _p(cp), _p(cf), _p(cn))
+        return int(steps), cp[:n], cf[:n], cn[:n]
+
+    def wall_coefficients(self):
+        """(C_p, C_f, C_n) of the current mesh state."""
+        n = int(np.count_nonzero(self._kind == 1))
+        cp, cf, cn = np.zeros(max(n, 1)), np.zeros(max(n, 1)), np.zeros(max(n, 1))
+        lib().or_wall_coefficients(self._h, _p(cp), _p(cf), _p(cn))
+        return cp[:n], cf[:n], cn[:n]
 
 
 # ---------------------------------------------------------------------------

@@ -616,6 +616,7 @@ int hlbm_run_objective(hlbm_ctx* c, const hlbm_objective* o, void* d_ckpt, size_
     if (!c->adj) c->adj = new AdjState();
     AdjState& a = *c->adj;
     const bool same_ws = a.ws == static_cast<char*>(d_ckpt);
+    c->wstat = false;
     a.obj = *o;
     a.ran = false;
     layout(c, a);

@@ -153,6 +153,8 @@ int upload_tables(hlbm_ctx* c) {
         rc |= upload(c, p.off.edges, keep.back().data(), keep.back().size());
         rc |= upload(c, p.off.wedge, p.wedge.data(), p.wedge.size() * 4);
         rc |= upload(c, p.off.wnorm, p.wnorm.data(), p.wnorm.size() * 8);
+        rc |= upload(c, p.off.wall_nrm, p.wall_nrm.data(), p.wall_nrm.size() * 8);
+        rc |= upload(c, p.off.wall_slot, p.wall_slot.data(), p.wall_slot.size() * 4);
         rc |= upload(c, p.off.uint_don, p.uint_don.data(), p.uint_don.size() * 4);
         keep.push_back(real(p.uint_w));
         rc |= upload(c, p.off.uint_w, keep.back().data(), keep.back().size());
@@ -265,11 +267,20 @@ void finest_step(hlbm_ctx* c) {
             }
         }
         const double qn = 0.5 * p.rho0 * p.u_inf * p.u_inf * p.chord;
-        Timed tm(c, HLBM_K_FORCE);
-        launch_wall_force(pr, c->km, c->mesh(c->mesh_cur), int(p.wedge.size() / 2),
-                          reinterpret_cast<const int32_t*>(c->ws + p.off.wedge),
-                          reinterpret_cast<const double*>(c->ws + p.off.wnorm), slot, std::cos(p.aoa),
-                          std::sin(p.aoa), qn > 0 ? qn : 1.0, c->s);
+        {
+            Timed tm(c, HLBM_K_FORCE);
+            launch_wall_force(pr, c->km, c->mesh(c->mesh_cur), int(p.wedge.size() / 2),
+                              reinterpret_cast<const int32_t*>(c->ws + p.off.wedge),
+                              reinterpret_cast<const double*>(c->ws + p.off.wnorm), slot, std::cos(p.aoa),
+                              std::sin(p.aoa), qn > 0 ? qn : 1.0, c->s);
+        }
+        if (c->wstat && !c->rec) {
+            const double q = 0.5 * p.rho0 * p.u_inf * p.u_inf;
+            Timed tw(c, HLBM_K_WALL_STATS);
+            launch_wall_stats(pr, c->mesh(c->mesh_cur), p.n_wall, reinterpret_cast<const double*>(c->ws + p.off.wall_nrm),
+                              p.rho0, q > 0 ? 1.0 / q : 1.0, reinterpret_cast<double*>(c->ws + p.off.wsum), c->s);
+            c->wstat_n++;
+        }
         c->prep_t ^= 1;
     } else {
         // no wall: zero force (the kernel writes 0 for an empty edge list)
@@ -456,6 +467,7 @@ int hlbm_set_state(hlbm_ctx* c, int32_t part, const double* host, size_t count) 
     if (!c || !host) return HLBM_E_ARG;
     if (c->poisoned) return set_err(c, HLBM_E_STATE, "context poisoned by a non-finite state");
     const Plan& p = c->p;
+    c->wstat = false;
     if (part == HLBM_PART_MESH) {
         if (!p.has_mesh || count != size_t(kQ) * p.nn) return set_err(c, HLBM_E_ARG, "bad mesh count");
         c->tmp.resize(count);
@@ -518,6 +530,35 @@ int hlbm_info(hlbm_ctx* c, hlbm_info_t* o) {
     o->bytes_per_finest_step = bytes / (int64_t(1) << p.L) + int64_t(p.n_sub) * o->fv_bytes;
     o->t = c->t;
     o->workspace_bytes = p.off.total;
+    return HLBM_OK;
+}
+
+int hlbm_wall_stats_begin(hlbm_ctx* c) {
+    if (!c) return HLBM_E_ARG;
+    if (c->poisoned) return set_err(c, HLBM_E_STATE, "context poisoned by a non-finite state");
+    const Plan& p = c->p;
+    if (!p.has_mesh || p.n_wall == 0) return set_err(c, HLBM_E_ARG, "no wall nodes");
+    launch_zero(reinterpret_cast<double*>(c->ws + p.off.wsum), size_t(3) * p.n_wall, c->s);
+    c->wstat = true;
+    c->wstat_n = 0;
+    return hip_check(c, hipGetLastError(), "wall statistics");
+}
+
+int hlbm_wall_stats(hlbm_ctx* c, int64_t* n_steps, double* cp, double* cf, double* cn) {
+    if (!c || !n_steps || !cp || !cf) return HLBM_E_ARG;
+    const Plan& p = c->p;
+    if (!c->wstat || c->wstat_n == 0) return set_err(c, HLBM_E_STATE, "no wall statistics accumulated");
+    double* out = reinterpret_cast<double*>(c->ws + p.off.wout);
+    launch_wall_stats_final(p.n_wall, reinterpret_cast<const double*>(c->ws + p.off.wsum),
+                            reinterpret_cast<const int32_t*>(c->ws + p.off.wall_slot), double(c->wstat_n), out, c->s);
+    std::vector<double> h(size_t(3) * p.n_wall);
+    int rc = hip_check(c, hipMemcpyAsync(h.data(), out, h.size() * 8, hipMemcpyDeviceToHost, c->s), "wall statistics");
+    rc |= hip_check(c, hipStreamSynchronize(c->s), "wall statistics");
+    if (rc) return HLBM_E_DEVICE;
+    std::memcpy(cp, h.data(), size_t(p.n_wall) * 8);
+    std::memcpy(cf, h.data() + p.n_wall, size_t(p.n_wall) * 8);
+    if (cn) std::memcpy(cn, h.data() + 2 * size_t(p.n_wall), size_t(p.n_wall) * 8);
+    *n_steps = c->wstat_n;
     return HLBM_OK;
 }
 

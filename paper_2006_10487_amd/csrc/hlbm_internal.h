@@ -64,6 +64,8 @@ struct Plan {
     std::vector<double> gx, gy, cc;      // G_Pk (x, y) and C_Pk
     std::vector<int32_t> wedge;          // wall edges (P, Q) in plan order, fluid on the left
     std::vector<double> wnorm;           // outward normal times length of each wall edge
+    std::vector<double> wall_nrm;        // [n_wall][2] unit normal into the fluid at each wall node
+    std::vector<int32_t> wall_slot;      // [n_wall] rank of the wall node by caller index
     // mesh interpolation nodes <- finest level, eq. (9)
     std::vector<int32_t> uint_don;       // kUDon per slot, finest node i + nx * j, -1 = unused
     std::vector<double> uint_w;
@@ -77,6 +79,7 @@ struct Plan {
         size_t side[4][2];
         size_t spans, sint_node, sint_don, sint_w;
         size_t mesh[2], rowptr, edges, wedge, wnorm, prep[2], uint_don, uint_w, hist, stage;
+        size_t wall_nrm, wall_slot, wsum, wout;
         size_t total;
     } off{};
     size_t stage_bytes = 0;
@@ -141,6 +144,9 @@ void launch_struct_to_mesh(int prec, const KLevel& fine, const void* fineA, int 
                            const void* w, void* prep, hipStream_t s);
 void launch_fv_substep(int prec, const KMesh& M, const void* fin, void* fout, const void* prep0,
                        const void* prep1, double theta, hipStream_t s);
+void launch_wall_stats(int prec, const void* f, int n_wall, const double* nrm, double rho0, double inv_q, double* sum,
+                       hipStream_t s);
+void launch_wall_stats_final(int n_wall, const double* sum, const int32_t* slot, double n, double* out, hipStream_t s);
 void launch_wall_force(int prec, const KMesh& M, const void* f, int n_edges, const int32_t* wedge,
                        const double* wnorm, double* hist_slot, double cos_a, double sin_a, double qnorm,
                        hipStream_t s);
@@ -234,6 +240,9 @@ struct hlbm_ctx {
     // m + 1); the last one is copied back into the mesh buffer
     char* sub_sink = nullptr;
     size_t sub_stride = 0;
+    // wall statistics (eqs. (12)-(13)): accumulating, and finest steps summed
+    bool wstat = false;
+    int64_t wstat_n = 0;
     // instrumentation
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;

@@ -1698,4 +1698,75 @@ void launch_reduce_partials(const double* partial, int n, double* acc, hipStream
     k_reduce_partials<<<1, 256, 0, s>>>(partial, n, acc);
 }
 
+// ===========================================================================
+// ---- Wall statistics: running sums of C_p, C_f, C_n, eqs. (12)-(13) ----
+// ===========================================================================
+
+namespace {
+
+// One thread per wall node (plan indices 0 .. n_wall-1, the first mesh records).
+// Pressure is rho c_s^2.  The finite-volume scheme integrates the continuous
+// BGK equation, so its viscous stress is sigma = -Pi^neq with
+// Pi^neq = sum_q c_q c_q f_q - rho c_s^2 I - rho u u.  Shifted storage holds
+// f_q - w_q rho0, whose moments lack (rho0, 0, rho0 c_s^2 I), so there the
+// isotropic part subtracted is (rho - rho0) c_s^2.  nrm: unit normal n into the
+// fluid; t = (n_y, -n_x).  Adds (C_p, t.sigma.n / q, n.sigma.n / q) to
+// sum[0 | 1 | 2][P]; each thread owns its node (no atomics).
+template <typename T, bool SHIFT>
+__global__ __launch_bounds__(256) void k_wall_stats(const T* __restrict__ f, int n_wall,
+                                                    const double* __restrict__ nrm, double rho0, double inv_q,
+                                                    double* __restrict__ sum) {
+    const int P = blockIdx.x * blockDim.x + threadIdx.x;
+    if (P >= n_wall) return;
+    T v[9], m0s, uxs, uys;
+    load_rec<T>(f + size_t(P) * kRec, v, m0s, uxs, uys);
+    double m0 = 0, mx = 0, my = 0, pxx = 0, pxy = 0, pyy = 0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const double x = double(v[q]);
+        m0 += x;
+        mx += CX[q] * x;
+        my += CY[q] * x;
+        pxx += (CX[q] * CX[q]) * x;
+        pxy += (CX[q] * CY[q]) * x;
+        pyy += (CY[q] * CY[q]) * x;
+    }
+    constexpr double cs2 = 1.0 / 3.0;
+    const double rho = SHIFT ? rho0 + m0 : m0;
+    const double drho = SHIFT ? m0 : m0 - rho0;
+    const double ux = mx / rho, uy = my / rho;
+    const double iso = (SHIFT ? drho : rho) * cs2;
+    const double sxx = -(pxx - iso - rho * ux * ux);
+    const double sxy = -(pxy - rho * ux * uy);
+    const double syy = -(pyy - iso - rho * uy * uy);
+    const double nx = nrm[2 * P], ny = nrm[2 * P + 1];
+    const double snx = sxx * nx + sxy * ny, sny = sxy * nx + syy * ny;
+    sum[P] += drho * cs2 * inv_q;
+    sum[n_wall + P] += (ny * snx - nx * sny) * inv_q;
+    sum[2 * size_t(n_wall) + P] += (nx * snx + ny * sny) * inv_q;
+}
+
+// Means in the caller's node order: out[k][slot[P]] = sum[k][P] / n.
+__global__ void k_wall_stats_final(int n_wall, const double* __restrict__ sum, const int32_t* __restrict__ slot,
+                                   double n, double* __restrict__ out) {
+    const int P = blockIdx.x * blockDim.x + threadIdx.x;
+    if (P >= n_wall) return;
+    const int r = slot[P];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out[size_t(k) * n_wall + r] = sum[size_t(k) * n_wall + P] / n;
+}
+
+}  // namespace
+
+void launch_wall_stats(int prec, const void* f, int n_wall, const double* nrm, double rho0, double inv_q, double* sum,
+                       hipStream_t s) {
+    if (n_wall <= 0) return;
+    HLBM_DISPATCH(prec, (k_wall_stats<T, S><<<blocks(n_wall), 256, 0, s>>>((const T*)f, n_wall, nrm, rho0, inv_q, sum)));
+}
+
+void launch_wall_stats_final(int n_wall, const double* sum, const int32_t* slot, double n, double* out, hipStream_t s) {
+    if (n_wall <= 0) return;
+    k_wall_stats_final<<<blocks(n_wall), 256, 0, s>>>(n_wall, sum, slot, n, out);
+}
+
 }  // namespace hlbm

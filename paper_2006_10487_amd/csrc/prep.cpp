@@ -674,6 +674,28 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
                 p.wnorm.push_back(dy);
                 p.wnorm.push_back(-dx);
             }
+        // wall statistics: unit normal into the fluid at each wall node (opposite
+        // to half the sum of its wall-edge normals) and its output slot
+        p.wall_nrm.assign(2 * size_t(p.n_wall), 0.0);
+        for (size_t e = 0; e < p.wedge.size() / 2; ++e)
+            for (int end = 0; end < 2; ++end) {
+                const int P = p.wedge[2 * e + end];
+                p.wall_nrm[2 * P] += 0.5 * p.wnorm[2 * e];
+                p.wall_nrm[2 * P + 1] += 0.5 * p.wnorm[2 * e + 1];
+            }
+        for (int P = 0; P < p.n_wall; ++P) {
+            const double vx = p.wall_nrm[2 * P], vy = p.wall_nrm[2 * P + 1], len = std::sqrt(vx * vx + vy * vy);
+            if (!(len > 0)) return fail(err, HLBM_E_GEOMETRY, "wall node %d has no wall edge", p.perm[P]);
+            p.wall_nrm[2 * P] = -vx / len;
+            p.wall_nrm[2 * P + 1] = -vy / len;
+        }
+        {
+            std::vector<int> order(p.n_wall);
+            for (int P = 0; P < p.n_wall; ++P) order[P] = P;
+            std::sort(order.begin(), order.end(), [&](int a, int b) { return p.perm[a] < p.perm[b]; });
+            p.wall_slot.assign(p.n_wall, 0);
+            for (int r = 0; r < p.n_wall; ++r) p.wall_slot[order[r]] = r;
+        }
         // ---- coupling stencils
         const bool linear = p.interp == HLBM_INTERP_LINEAR;
         if (has_ein) {
@@ -760,6 +782,10 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
     p.off.uint_don = take(p.uint_don.size() * 4);
     p.off.uint_w = take(p.uint_w.size() * E);
     p.off.hist = take(size_t(p.hist_len) * 2 * 8);
+    p.off.wall_nrm = take(size_t(p.n_wall) * 2 * 8);
+    p.off.wall_slot = take(size_t(p.n_wall) * 4);
+    p.off.wsum = take(size_t(p.n_wall) * 3 * 8);
+    p.off.wout = take(size_t(p.n_wall) * 3 * 8);
     size_t maxrow = 0;
     for (int l = 0; l <= p.L; ++l) maxrow = std::max(maxrow, size_t(p.lev[l].nx));
     p.stage_bytes = std::max(size_t(kQ) * maxrow * 8 * 8, std::min(size_t(32) << 20, size_t(kQ) * maxrow * 8 * 4096));

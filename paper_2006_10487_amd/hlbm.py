@@ -27,9 +27,11 @@ PART_MESH = 100
 EXPORTED = ["hlbm_validate", "hlbm_workspace_size", "hlbm_create", "hlbm_step", "hlbm_forces",
             "hlbm_force_history", "hlbm_get_state", "hlbm_set_state", "hlbm_info", "hlbm_last_error",
             "hlbm_destroy", "hlbm_profile", "hlbm_profile_read", "hlbm_kernel_bench",
-            "hlbm_objective_workspace_size", "hlbm_run_objective", "hlbm_adjoint"]
+            "hlbm_objective_workspace_size", "hlbm_run_objective", "hlbm_adjoint",
+            "hlbm_wall_stats_begin", "hlbm_wall_stats"]
 KERNEL_CLASSES = ["collide_l0", "collide_l1", "collide_l2", "collide_l3", "coarse_to_fine",
-                  "fine_to_coarse", "mesh_to_struct", "struct_to_mesh", "fv_substep", "wall_force"]
+                  "fine_to_coarse", "mesh_to_struct", "struct_to_mesh", "fv_substep", "wall_force",
+                  "wall_stats"]
 
 
 class HLBMError(RuntimeError):
@@ -107,6 +109,8 @@ def lib():
         L.hlbm_objective_workspace_size.argtypes = [P, C.POINTER(Objective), C.POINTER(C.c_size_t)]
         L.hlbm_run_objective.argtypes = [P, C.POINTER(Objective), P, C.c_size_t, C.POINTER(C.c_double)]
         L.hlbm_adjoint.argtypes = [P, C.c_double, P, P]
+        L.hlbm_wall_stats_begin.argtypes = [P]
+        L.hlbm_wall_stats.argtypes = [P, C.POINTER(C.c_int64), P, P, P]
         _lib = L
     return _lib
 
@@ -195,6 +199,10 @@ class HLBM:
         self._ctx = ctx
         self.info = self.get_info()
         self.n_nodes = int(mesh.n_nodes)
+        self.n_wall = 0
+        if self.n_nodes > 0:
+            kinds = np.ctypeslib.as_array(mesh.kind, shape=(self.n_nodes,))
+            self.n_wall = int(np.count_nonzero(kinds == 1))
 
     @classmethod
     def from_workload(cls, w, *, precision=FP64, interp=INTERP_QUADRATIC, n_sub=0, wall_bc=True,
@@ -322,8 +330,53 @@ class HLBM:
             self._check(lib().hlbm_adjoint(self._ctx, float(j_bar), _np_ptr(g), None))
         return g
 
+    def wall_stats_begin(self):
+        """Start time means of the wall coefficients C_p, C_f, C_n (eqs. (12)-(13))
+        over the finest steps that follow."""
+        self._check(lib().hlbm_wall_stats_begin(self._ctx))
+
+    def wall_stats(self):
+        """(steps, C_p, C_f, C_n) means since wall_stats_begin(), one entry per
+        wall node in increasing node index.  C_f and C_n are the shear and normal
+        viscous stress on the wall tangent t with the fluid on its left and the
+        normal n into the fluid."""
+        n = max(self.n_wall, 1)
+        cp, cf, cn = np.zeros(n), np.zeros(n), np.zeros(n)
+        steps = C.c_int64(0)
+        self._check(lib().hlbm_wall_stats(self._ctx, C.byref(steps), _np_ptr(cp), _np_ptr(cf), _np_ptr(cn)))
+        k = self.n_wall
+        return int(steps.value), cp[:k], cf[:k], cn[:k]
+
     def synchronize(self):
         self.stream.synchronize()
+
+
+def surface_distributions(omesh, cp: np.ndarray, cf: np.ndarray) -> dict:
+    """Wall coefficients of an O-mesh along the chord, per surface.
+
+    cp, cf: one value per surface point (wall nodes in node order, as
+    HLBM.wall_stats returns them).  Returns {"upper": (x/c, C_p, C_f),
+    "lower": (...)}, each ordered from the leading to the trailing edge, with
+    C_f signed positive for shear towards the trailing edge (attached flow) on
+    both surfaces: the wall tangent with the fluid on its left runs downstream
+    on the upper surface and upstream on the lower one."""
+    ns = omesh.ns
+    le = ns // 2
+    up = np.arange(le, -1, -1)                                # LE -> TE over the upper surface
+    lo = np.concatenate([np.arange(le, ns), [0]])             # LE -> TE over the lower surface
+    xi = omesh.surface_xi
+    return {"upper": (xi[up], cp[up], cf[up]), "lower": (xi[lo], cp[lo], -cf[lo])}
+
+
+def separation_point(xc: np.ndarray, cf: np.ndarray) -> Optional[float]:
+    """First zero of C_f with negative slope along x/c (Sec. 6: separation is where
+    the skin friction vanishes and turns negative), by linear interpolation
+    between the two bracketing points; None if C_f never changes from positive
+    to non-positive."""
+    for k in range(len(xc) - 1):
+        if cf[k] > 0.0 >= cf[k + 1]:
+            return float(xc[k] + cf[k] * (xc[k + 1] - xc[k]) / (cf[k] - cf[k + 1]))
+    return None
 
 
 def strouhal(cl: np.ndarray, chord: float, u_inf: float, steady_tol: float = 1e-6) -> float:

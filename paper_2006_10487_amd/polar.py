@@ -1,0 +1,66 @@
+"""Angle-of-attack sweep of the Re = 1000, c = 128 workload in FP64 and FP32-shifted.
+
+For every angle: time-averaged C_D and C_L over the second half of the run,
+the Strouhal number of the lift signal, and the FP32-shifted deviations from
+FP64 (relative; absolute for C_L where it vanishes by symmetry).
+
+    python -m paper_2006_10487_amd.polar --aoa 0,5 --steps 40000 --ns 512
+
+prints one JSON object per angle.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import hlbm, workloads
+
+
+def run(aoa_deg: float, steps: int, ns: int, precision: int):
+    w = workloads.naca_re1000_c128(aoa_deg, ns=ns)
+    sim = hlbm.HLBM.from_workload(w, precision=precision, history_len=steps + 8, check_every=1000)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    dt = time.perf_counter() - t0
+    cd, cl = sim.history()
+    sim.close()
+    win = slice(steps // 2, steps)
+    return w, dt, float(np.mean(cd[win])), float(np.mean(cl[win])), hlbm.strouhal(cl[win], w.chord, w.u_inf)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--aoa", default="0,5,10,15,20")
+    ap.add_argument("--steps", type=int, default=40000)
+    ap.add_argument("--ns", type=int, default=512, help="surface points of the O-mesh")
+    a = ap.parse_args(argv)
+    for aoa in [float(x) for x in a.aoa.split(",")]:
+        out = {"aoa_deg": aoa, "steps": a.steps, "ns": a.ns}
+        try:
+            w, t64, cd64, cl64, st64 = run(aoa, a.steps, a.ns, hlbm.FP64)
+            _, t32, cd32, cl32, st32 = run(aoa, a.steps, a.ns, hlbm.FP32_SHIFTED)
+        except hlbm.HLBMError as e:
+            out["error"] = str(e)
+            print(json.dumps(out), flush=True)
+            continue
+        scale_l = abs(cl64) if abs(cl64) > 1e-6 else 1.0
+        out.update({
+            "workload": w.name, "mesh_nodes": int(w.mesh_xy.shape[0]),
+            "fp64": {"cd": cd64, "cl": cl64, "st": st64, "seconds": round(t64, 3)},
+            "fp32_shifted": {"cd": cd32, "cl": cl32, "st": st32, "seconds": round(t32, 3)},
+            "cd_rel_err": abs(cd32 - cd64) / abs(cd64),
+            "cl_err": abs(cl32 - cl64) / scale_l, "cl_err_kind": "relative" if scale_l != 1.0 else "absolute",
+            "st_rel_err": (abs(st32 - st64) / st64) if (math.isfinite(st32) and math.isfinite(st64)) else None,
+        })
+        print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
