@@ -70,8 +70,8 @@ def run_precision(w, precision, steps, warmup, hlbm, torch):
 def kernel_bytes(info, k):
     if k.startswith("collide_l"):
         return int(info.k1_bytes[int(k[-1])])
-    if k == "fv_substep":
-        return int(info.fv_bytes)
+    if k == "fv_substep":      # one launch takes fv_fuse sub-steps
+        return int(info.fv_bytes) * max(1, int(info.fv_fuse))
     return None
 
 

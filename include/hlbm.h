@@ -72,6 +72,9 @@ typedef struct {
     int32_t wall_bc;              /* 1 = no-slip at mesh wall nodes, 0 = off (free-stream checks)    */
     int32_t check_every;          /* non-finite check interval in finest steps, 0 = off             */
     int32_t history_len;          /* force history ring length, 0 = 65536                            */
+    int32_t fv_fuse;              /* FV sub-steps per launch, 1..4; 0 = 2 where a tile of mesh nodes
+                                     and its halo fit in 64 KB of LDS (else 1).  Results do not
+                                     depend on it (same arithmetic, same order)                      */
 } hlbm_grid;
 
 /* Body-fitted triangular mesh (Sec. 2 and 4). */
@@ -96,9 +99,11 @@ typedef struct {
     int32_t n_wall_edges, nnz;
     int64_t bytes_per_finest_step;    /* algorithmic bytes, all kernels                             */
     int64_t k1_bytes[4];          /* algorithmic bytes of one collide-stream launch per level       */
-    int64_t fv_bytes;             /* algorithmic bytes of one FV sub-step launch                    */
+    int64_t fv_bytes;             /* algorithmic bytes of one FV sub-step                           */
     int64_t t;                    /* finest steps done                                              */
     size_t workspace_bytes;
+    int32_t fv_fuse;              /* FV sub-steps per launch (the HLBM_K_FV class of hlbm_profile_read
+                                     and hlbm_kernel_bench covers that many)                         */
 } hlbm_info_t;
 
 /* Checks the problem on the host only (no GPU).  Re > 0 gives
@@ -210,7 +215,7 @@ enum {
     HLBM_K_FINE_TO_COARSE = 5,
     HLBM_K_MESH_TO_STRUCT = 6,  /* eq. (4) */
     HLBM_K_STRUCT_TO_MESH = 7,  /* eq. (9) */
-    HLBM_K_FV = 8,              /* one finite-volume sub-step, eqs. (3), (5) */
+    HLBM_K_FV = 8,              /* finite-volume sub-steps, eqs. (3), (5): one launch = fv_fuse of them */
     HLBM_K_FORCE = 9,           /* eqs. (10)-(11) */
     HLBM_K_WALL_STATS = 10,     /* eqs. (12)-(13), while hlbm_wall_stats_begin is in effect */
     HLBM_K_COUNT = 11
@@ -227,7 +232,8 @@ int hlbm_profile(hlbm_ctx *ctx, int enable);
 int hlbm_profile_read(hlbm_ctx *ctx, double *ms, int64_t *launches);
 
 /* Instrumentation: launches n times back to back the kernel of class kclass
- * (HLBM_K_COLLIDE_L0 + l or HLBM_K_FV) on the context's buffers and returns
+ * (HLBM_K_COLLIDE_L0 + l, or HLBM_K_FV: one launch of hlbm_info_t.fv_fuse
+ * sub-steps) on the context's buffers and returns
  * the mean time per launch from one pair of HIP events around the batch.
  * The launches advance that part of the state on its own, so afterwards the
  * state is not a solution of the coupled scheme: benchmark use only (restore

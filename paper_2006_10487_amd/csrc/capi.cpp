@@ -117,6 +117,14 @@ void setup_views(hlbm_ctx* c) {
     m.star_neq = 1.0 - 1.0 / (2.0 * p.tau_s);
     m.wall_bc = p.wall_bc;
     m.rho0 = p.rho0;
+    m.fuse = p.fv_fuse;
+    m.n_sub = p.n_sub;
+    m.n_tiles = p.n_tiles;
+    m.maxl = p.fv_maxl;
+    m.tile = p.fv_tile;
+    m.ft_meta = reinterpret_cast<const int32_t*>(c->ws + p.off.ft_meta);
+    m.ft_node = reinterpret_cast<const int32_t*>(c->ws + p.off.ft_node);
+    m.ft_edges = c->ws + p.off.ft_edges;
 }
 
 int upload_tables(hlbm_ctx* c) {
@@ -153,6 +161,28 @@ int upload_tables(hlbm_ctx* c) {
         rc |= upload(c, p.off.edges, keep.back().data(), keep.back().size());
         rc |= upload(c, p.off.wedge, p.wedge.data(), p.wedge.size() * 4);
         rc |= upload(c, p.off.wnorm, p.wnorm.data(), p.wnorm.size() * 8);
+        if (p.fv_fuse > 1) {
+            rc |= upload(c, p.off.ft_meta, p.ft_meta.data(), p.ft_meta.size() * 4);
+            rc |= upload(c, p.off.ft_node, p.ft_node.data(), p.ft_node.size() * 4);
+            // tile edge tables: the ELL record layout with local columns
+            std::vector<char> te(p.ft_col.size() * rs, 0);
+            for (size_t e = 0; e < p.ft_col.size(); ++e) {
+                char* r = te.data() + e * rs;
+                const int32_t col = p.ft_col[e];
+                std::memcpy(r, &col, 4);
+                const int zz = p.ft_src[e];
+                if (zz < 0) continue;
+                if (f64) {
+                    const double v[3] = {p.gx[zz], p.gy[zz], p.cc[zz]};
+                    std::memcpy(r + 8, v, 24);
+                } else {
+                    const float v[3] = {float(p.gx[zz]), float(p.gy[zz]), float(p.cc[zz])};
+                    std::memcpy(r + 4, v, 12);
+                }
+            }
+            keep.push_back(std::move(te));
+            rc |= upload(c, p.off.ft_edges, keep.back().data(), keep.back().size());
+        }
         rc |= upload(c, p.off.wall_nrm, p.wall_nrm.data(), p.wall_nrm.size() * 8);
         rc |= upload(c, p.off.wall_slot, p.wall_slot.data(), p.wall_slot.size() * 4);
         rc |= upload(c, p.off.uint_don, p.uint_don.data(), p.uint_don.size() * 4);
@@ -258,6 +288,13 @@ void finest_step(hlbm_ctx* c) {
             }
             (void)hip_check(c, hipMemcpyAsync(c->mesh(c->mesh_cur), in, size_t(kRec) * p.nn * p.elem,
                                               hipMemcpyDeviceToDevice, c->s), "sub-step states");
+        } else if (p.fv_fuse > 1) {
+            for (int m = 0; m < p.n_sub; m += p.fv_fuse) {
+                Timed tm(c, HLBM_K_FV);
+                launch_fv_fused(pr, c->km, c->mesh(c->mesh_cur), c->mesh(1 - c->mesh_cur), c->prep(c->prep_t),
+                                c->prep(1 - c->prep_t), m, std::min(p.fv_fuse, p.n_sub - m), c->s);
+                c->mesh_cur ^= 1;
+            }
         } else {
             for (int m = 0; m < p.n_sub; ++m) {
                 Timed tm(c, HLBM_K_FV);
@@ -530,6 +567,7 @@ int hlbm_info(hlbm_ctx* c, hlbm_info_t* o) {
     o->bytes_per_finest_step = bytes / (int64_t(1) << p.L) + int64_t(p.n_sub) * o->fv_bytes;
     o->t = c->t;
     o->workspace_bytes = p.off.total;
+    o->fv_fuse = p.has_mesh ? p.fv_fuse : 0;
     return HLBM_OK;
 }
 
@@ -597,7 +635,11 @@ int hlbm_kernel_bench(hlbm_ctx* c, int kclass, int n, double* avg_ms) {
     if (!a || !b) return set_err(c, HLBM_E_DEVICE, "hipEventCreate failed");
     int rc = hip_check(c, hipEventRecord(a, c->s), "event");
     for (int k = 0; k < n; ++k) {
-        if (fv) {
+        if (fv && p.fv_fuse > 1) {
+            launch_fv_fused(p.precision, c->km, c->mesh(c->mesh_cur), c->mesh(1 - c->mesh_cur), c->prep(c->prep_t),
+                            c->prep(1 - c->prep_t), 0, std::min(p.fv_fuse, p.n_sub), c->s);
+            c->mesh_cur ^= 1;
+        } else if (fv) {
             launch_fv_substep(p.precision, c->km, c->mesh(c->mesh_cur), c->mesh(1 - c->mesh_cur), c->prep(c->prep_t),
                               c->prep(1 - c->prep_t), double(k % p.n_sub) / p.n_sub, c->s);
             c->mesh_cur ^= 1;

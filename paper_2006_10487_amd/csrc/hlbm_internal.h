@@ -24,6 +24,8 @@ constexpr int kSDon = 8;     // donors of a structured interpolation node (two 6
 constexpr int kUDon = 9;     // donors of a mesh interpolation node (3 x 3 block)
 constexpr int kMacro = 12;   // (rho or rho - rho0, ux, uy, f^neq[9])
 constexpr int kRec = 12;
+constexpr int kTileMeta = 8;   // ints per fused-FV tile: node off, edge off, width, n_le[0..4]
+constexpr int kMaxFuse = 4;
 constexpr int kAdjRec = 10;   // doubles per mesh node of the adjoint fields (9 used)     // mesh node record: f_0..f_8, rho (or rho - rho0), ux, uy
 
 struct LevelPlan {
@@ -64,6 +66,14 @@ struct Plan {
     std::vector<double> gx, gy, cc;      // G_Pk (x, y) and C_Pk
     std::vector<int32_t> wedge;          // wall edges (P, Q) in plan order, fluid on the left
     std::vector<double> wnorm;           // outward normal times length of each wall edge
+    // fused FV sub-steps (temporal blocking): tiles of at most fv_tile plan
+    // nodes, each with the rings of neighbours that fv_fuse Jacobi sub-steps
+    // reach; per tile kTileMeta ints {node offset, edge offset, edge-table
+    // width, n_le[0..fv_fuse]} with n_le[r] = local nodes within ring r
+    int fv_fuse = 1, fv_tile = 256, fv_maxl = 0, n_tiles = 0;
+    std::vector<int32_t> ft_meta, ft_node;
+    std::vector<int32_t> ft_col;         // local column per (slot, computed node) of each tile
+    std::vector<int32_t> ft_src;         // index into col / gx / gy / cc of that entry, -1 = unused
     std::vector<double> wall_nrm;        // [n_wall][2] unit normal into the fluid at each wall node
     std::vector<int32_t> wall_slot;      // [n_wall] rank of the wall node by caller index
     // mesh interpolation nodes <- finest level, eq. (9)
@@ -80,6 +90,7 @@ struct Plan {
         size_t spans, sint_node, sint_don, sint_w;
         size_t mesh[2], rowptr, edges, wedge, wnorm, prep[2], uint_don, uint_w, hist, stage;
         size_t wall_nrm, wall_slot, wsum, wout;
+        size_t ft_meta, ft_node, ft_edges;
         size_t total;
     } off{};
     size_t stage_bytes = 0;
@@ -122,6 +133,11 @@ struct KMesh {
     double star_neq;                 // 1 - 1 / (2 tau_s), eq. (5)-(6)
     int wall_bc;
     double rho0;
+    // fused sub-steps (fuse > 1): tile tables and the LDS size they need
+    int fuse, n_sub, n_tiles, maxl, tile;
+    const int32_t* ft_meta;
+    const int32_t* ft_node;
+    const void* ft_edges;
 };
 
 // launchers (kernels.hip); `prec` is HLBM_FP64 or HLBM_FP32_SHIFTED
@@ -144,6 +160,9 @@ void launch_struct_to_mesh(int prec, const KLevel& fine, const void* fineA, int 
                            const void* w, void* prep, hipStream_t s);
 void launch_fv_substep(int prec, const KMesh& M, const void* fin, void* fout, const void* prep0,
                        const void* prep1, double theta, hipStream_t s);
+// k = 1..M.fuse sub-steps m0 .. m0 + k - 1 in one launch (tiles with halos in LDS)
+void launch_fv_fused(int prec, const KMesh& M, const void* fin, void* fout, const void* prep0, const void* prep1,
+                     int m0, int k, hipStream_t s);
 void launch_wall_stats(int prec, const void* f, int n_wall, const double* nrm, double rho0, double inv_q, double* sum,
                        hipStream_t s);
 void launch_wall_stats_final(int n_wall, const double* sum, const int32_t* slot, double n, double* out, hipStream_t s);

@@ -571,19 +571,93 @@ __device__ __forceinline__ void store_rec(T* __restrict__ rec, const T (&f)[9], 
     }
 }
 
-// One finite-volume sub-step of eq. (3) on every mesh node (eq. (5) at the
+// One finite-volume sub-step of eq. (3) at one mesh node (eq. (5) at the
 // interpolation nodes), Jacobi style:
 //   f_P <- f_P + dt sum_k (c_i . G_Pk) f_k - dt/tau_u sum_k C_Pk (f_k - f^eq_k)
 // The streaming sum is evaluated as sum_{k != P} (c_i . G_Pk)(f_k - f_P),
 // equal to the above because sum_k G_Pk = 0 on a closed control volume, and
-// exact for a uniform state in any precision.  Interpolation pivots use f*
-// for themselves and for interpolation neighbours (eqs. (5)-(7)); wall nodes
-// then get u -> 0 keeping rho and f^neq.  Each record carries the node's
-// (rho, u) so neighbours need not recompute them.
-// Neighbours are stored ELL-style: W slots per node, slot z of node P at
-// z * nn + P (coalesced across a wavefront), slot 0 = the node itself,
-// unused slots col = -1.  All W coefficient and record loads are issued
-// before the arithmetic, so a wave waits on memory once, not W times.
+// exact for a uniform state in any precision.  The collision sum is split as
+// sum_k C_Pk f_k - sum_k C_Pk f^eq_k, and because f^eq_i is a quadratic form
+// in (rho, rho u) the second part needs only the weighted moments
+//   a0 = sum C (rho or rho - rho0),  a1 = sum C rho u,  a2 = sum C rho u u^T:
+//   sum_k C_Pk f^eq_i(k) = w_i (a0 + 3 c_i.a1 + 9/2 c_i^T a2 c_i - 3/2 tr a2),
+// the same value in a different rounding order, for 20 instead of ~100
+// arithmetic instructions per neighbour (the kernel is bound by its vector
+// ALU).  Interpolation pivots use f* for themselves and for interpolation
+// neighbours (eqs. (5)-(7)), whose non-equilibrium part enters directly;
+// wall nodes then get u -> 0 keeping rho and f^neq.  Each record carries the
+// node's (rho, u), so neighbours do not recompute them.
+template <typename T>
+struct FvAcc {
+    T base[9], ss[9], sf[9];
+    T a0, a1x, a1y, axx, axy, ayy;
+};
+
+// Adds slot z (z = 0: the node itself) with populations f of neighbour k:
+// regular neighbours give their stored moments (m0, ux, uy); interpolation
+// neighbours of an interpolation pivot (star) give their f^neq in nq.
+template <typename T, bool SHIFT>
+__device__ __forceinline__ void fv_add(FvAcc<T>& A, int z, const T (&f)[9], bool star, const T (&nq)[9], T m0, T ux,
+                                       T uy, T gx, T gy, T c, T rho0) {
+    if (z == 0) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            A.base[q] = f[q];
+            A.ss[q] = 0;
+            A.sf[q] = 0;
+        }
+        A.a0 = A.a1x = A.a1y = A.axx = A.axy = A.ayy = 0;
+    } else {
+        const T gp = gx + gy, gm = gx - gy;
+        const T s[9] = {T(0), gx, gy, -gx, -gy, gp, -gm, -gp, gm};   // c_i . G_Pk
+#pragma unroll
+        for (int q = 1; q < 9; ++q) A.ss[q] += s[q] * (f[q] - A.base[q]);
+    }
+    if (star) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) A.sf[q] += c * nq[q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) A.sf[q] += c * f[q];
+        const T rho = SHIFT ? rho0 + m0 : m0;
+        const T cr = c * rho, crx = cr * ux, cry = cr * uy;
+        A.a0 += c * m0;
+        A.a1x += crx;
+        A.a1y += cry;
+        A.axx += crx * ux;
+        A.axy += crx * uy;
+        A.ayy += cry * uy;
+    }
+}
+
+// New populations and moments of the node from its accumulators.
+template <typename T, bool SHIFT>
+__device__ __forceinline__ void fv_finish(const KMesh& M, int P, const FvAcc<T>& A, T (&fn)[9], T& r, T& dr, T& ux,
+                                          T& uy) {
+    const T rho0 = T(M.rho0), dt = T(M.dt), dtt = T(M.dt_over_tau);
+    const T tr = A.axx + A.ayy;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const T cx = T(CX[q]), cy = T(CY[q]);
+        const T ca = cx * A.a1x + cy * A.a1y;
+        const T caa = cx * cx * A.axx + T(2) * cx * cy * A.axy + cy * cy * A.ayy;
+        const T x = A.a0 + T(3) * ca + T(4.5) * caa - T(1.5) * tr;
+        T eqs;
+        if constexpr (SHIFT && sizeof(T) == 4) eqs = weighted_f32(q, x);
+        else eqs = wgt<T>(q) * x;
+        fn[q] = A.base[q] + dt * A.ss[q] - dtt * (A.sf[q] - eqs);
+    }
+    macro<T, SHIFT>(fn, rho0, r, dr, ux, uy);
+    if (M.wall_bc && P < M.n_wall) {
+        T feq[9], feq0[9];
+        equilibrium<T, SHIFT>(r, dr, ux, uy, feq);
+        equilibrium<T, SHIFT>(r, dr, T(0), T(0), feq0);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) fn[q] = feq0[q] + (fn[q] - feq[q]);
+        macro<T, SHIFT>(fn, rho0, r, dr, ux, uy);
+    }
+}
+
 // Workgroup -> node block such that each of the 8 dies (dealt workgroups
 // round-robin, one L2 each) gets a contiguous range of nodes, whose
 // neighbours then mostly sit in the same L2 (measured: -11% FP32, -13% FP64
@@ -609,7 +683,7 @@ __global__ __launch_bounds__(256) void k_fv_substep(const KMesh M, const T* __re
     const T rho0 = T(M.rho0), cst = T(M.star_neq);
     const EdgeRec<T>* __restrict__ E = reinterpret_cast<const EdgeRec<T>*>(M.edges);
     constexpr int kFvGroup = FvGroup<T>::value;
-    T base[9], ss[9], sc[9];
+    FvAcc<T> A;
 #pragma unroll 1
     for (int g0 = 0; g0 < W; g0 += kFvGroup) {
         EdgeRec<T> e[kFvGroup];
@@ -625,51 +699,87 @@ __global__ __launch_bounds__(256) void k_fv_substep(const KMesh M, const T* __re
         for (int a = 0; a < kFvGroup; ++a) {
             const int k = e[a].col;
             if (k < 0) continue;
-            T f[9], nq[9];
-            if (pivot_interp && k >= M.n_core) {
+            const bool star = pivot_interp && k >= M.n_core;
+            T fs[9], nq[9];
+            if (star) {
                 const size_t sl = size_t(k - M.n_core) * kMacro;
-                star_values<T, SHIFT>(prep0 + sl, prep1 + sl, theta, cst, rho0, f, nq);
-            } else {
-                T feq[9];
-                const T m0 = mr[a][0];
-                equilibrium<T, SHIFT>(SHIFT ? rho0 + m0 : m0, SHIFT ? m0 : m0 - rho0, mr[a][1], mr[a][2], feq);
-#pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    f[q] = fr[a][q];
-                    nq[q] = f[q] - feq[q];
-                }
+                star_values<T, SHIFT>(prep0 + sl, prep1 + sl, theta, cst, rho0, fs, nq);
             }
-            if (g0 + a == 0) {   // the node itself: collision term only
-#pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    base[q] = f[q];
-                    ss[q] = 0;
-                    sc[q] = e[a].c * nq[q];
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    const T s_ik = T(CX[q]) * e[a].gx + T(CY[q]) * e[a].gy;
-                    ss[q] += s_ik * (f[q] - base[q]);
-                    sc[q] += e[a].c * nq[q];
-                }
-            }
+            fv_add<T, SHIFT>(A, g0 + a, star ? fs : fr[a], star, nq, mr[a][0], mr[a][1], mr[a][2], e[a].gx, e[a].gy,
+                             e[a].c, rho0);
         }
     }
-    const T dt = T(M.dt), dtt = T(M.dt_over_tau);
     T fn[9], r, dr, ux, uy;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) fn[q] = base[q] + dt * ss[q] - dtt * sc[q];
-    macro<T, SHIFT>(fn, rho0, r, dr, ux, uy);
-    if (M.wall_bc && P < M.n_wall) {
-        T feq[9], feq0[9];
-        equilibrium<T, SHIFT>(r, dr, ux, uy, feq);
-        equilibrium<T, SHIFT>(r, dr, T(0), T(0), feq0);
-#pragma unroll
-        for (int q = 0; q < 9; ++q) fn[q] = feq0[q] + (fn[q] - feq[q]);
-        macro<T, SHIFT>(fn, rho0, r, dr, ux, uy);
-    }
+    fv_finish<T, SHIFT>(M, P, A, fn, r, dr, ux, uy);
     store_rec(fout + size_t(P) * kRec, fn, SHIFT ? dr : r, ux, uy);
+}
+
+// Several FV sub-steps in one launch (temporal blocking).  One workgroup per
+// tile of mesh nodes: it loads the records of the tile and of the rings of
+// neighbours around it into LDS, takes sub-step j (j = 1..k) on the tile and
+// rings 1..k-j (ping-pong between two LDS buffers), and writes only the
+// tile's records after sub-step k.  The rings are recomputed by every tile
+// that borders them, so each sub-step is exactly the Jacobi update of
+// k_fv_substep, in the same operation order, while HBM sees the records
+// and edge coefficients once per k sub-steps.  Tile tables: see
+// build_fv_tiles.
+template <typename T, bool SHIFT, int W>
+__global__ __launch_bounds__(256) void k_fv_fused(const KMesh M, const T* __restrict__ fin, T* __restrict__ fout,
+                                                  const T* __restrict__ prep0, const T* __restrict__ prep1, int m0,
+                                                  int ksteps) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* const buf0 = reinterpret_cast<T*>(smem);
+    T* const buf1 = buf0 + size_t(M.maxl) * kRec;
+    int32_t* const gid = reinterpret_cast<int32_t*>(buf1 + size_t(M.maxl) * kRec);
+    const int t = die_block(blockIdx.x, gridDim.x);
+    const int32_t* meta = M.ft_meta + size_t(t) * kTileMeta;
+    const int noff = meta[0], eoff = meta[1], width = meta[2];
+    const int nload = meta[3 + ksteps];
+    const EdgeRec<T>* __restrict__ E = reinterpret_cast<const EdgeRec<T>*>(M.ft_edges) + eoff;
+    const T rho0 = T(M.rho0), cst = T(M.star_neq);
+    for (int i = threadIdx.x; i < nload; i += blockDim.x) {
+        const int P = M.ft_node[noff + i];
+        gid[i] = P;
+        T f[9], m0r, ux, uy;
+        load_rec(fin + size_t(P) * kRec, f, m0r, ux, uy);
+        store_rec(buf0 + size_t(i) * kRec, f, m0r, ux, uy);
+    }
+    __syncthreads();
+    const T* src = buf0;
+    T* dst = buf1;
+    for (int j = 1; j <= ksteps; ++j) {
+        const int ncomp = meta[3 + ksteps - j];
+        const T theta = T(double(m0 + j - 1) / double(M.n_sub));
+        const bool last = j == ksteps;
+        for (int i = threadIdx.x; i < ncomp; i += blockDim.x) {
+            EdgeRec<T> e[W];
+#pragma unroll
+            for (int z = 0; z < W; ++z) e[z] = E[size_t(z) * width + i];
+            const int P = gid[i];
+            const bool pivot_interp = P >= M.n_core;
+            FvAcc<T> A;
+#pragma unroll
+            for (int z = 0; z < W; ++z) {
+                if (e[z].col < 0) continue;
+                const int k = gid[e[z].col];
+                const bool star = pivot_interp && k >= M.n_core;
+                T f[9], nq[9], mk, uxk, uyk;
+                if (star) {
+                    const size_t sl = size_t(k - M.n_core) * kMacro;
+                    star_values<T, SHIFT>(prep0 + sl, prep1 + sl, theta, cst, rho0, f, nq);
+                } else {
+                    load_rec(src + size_t(e[z].col) * kRec, f, mk, uxk, uyk);
+                }
+                fv_add<T, SHIFT>(A, z, f, star, nq, mk, uxk, uyk, e[z].gx, e[z].gy, e[z].c, rho0);
+            }
+            T fn[9], r, dr, ux, uy;
+            fv_finish<T, SHIFT>(M, P, A, fn, r, dr, ux, uy);
+            store_rec((last ? fout + size_t(P) * kRec : dst + size_t(i) * kRec), fn, SHIFT ? dr : r, ux, uy);
+        }
+        __syncthreads();
+        src = dst;
+        dst = dst == buf1 ? buf0 : buf1;
+    }
 }
 
 // Drag and lift, eqs. (10)-(11), in FP64: momentum flux out of the fluid
@@ -816,6 +926,21 @@ void launch_fv_substep(int prec, const KMesh& M, const void* fin, void* fout, co
     } else {
         HLBM_DISPATCH(prec, (k_fv_substep<T, S, 16><<<blocks(M.nn), 256, 0, s>>>(M, (const T*)fin, (T*)fout, (const T*)prep0,
                                                                                  (const T*)prep1, T(theta))));
+    }
+}
+
+void launch_fv_fused(int prec, const KMesh& M, const void* fin, void* fout, const void* prep0, const void* prep1,
+                     int m0, int k, hipStream_t s) {
+    if (M.n_tiles <= 0 || k < 1 || k > M.fuse) return;
+    const size_t elem = prec == HLBM_FP64 ? 8 : 4;
+    const size_t lds = size_t(M.maxl) * (2 * kRec * elem + 4);
+    const unsigned threads = unsigned(M.tile);
+    if (M.ell_width <= 8) {
+        HLBM_DISPATCH(prec, (k_fv_fused<T, S, 8><<<M.n_tiles, threads, lds, s>>>(M, (const T*)fin, (T*)fout, (const T*)prep0,
+                                                                                  (const T*)prep1, m0, k)));
+    } else {
+        HLBM_DISPATCH(prec, (k_fv_fused<T, S, 16><<<M.n_tiles, threads, lds, s>>>(M, (const T*)fin, (T*)fout, (const T*)prep0,
+                                                                                   (const T*)prep1, m0, k)));
     }
 }
 

@@ -468,6 +468,98 @@ template <class S> int lagrange9(S x, S y, bool linear, int* di, int* dj, S* w) 
     return 4;
 }
 
+constexpr int kFvFuse = 2;   // FV sub-steps per launch (measured on MI355X)
+
+// Tiles for the fused finite-volume kernel, which takes several Jacobi
+// sub-steps per launch out of LDS.  Plan nodes are grouped into tiles of at
+// most `tile` nodes grown breadth-first over the mesh graph (compact tiles,
+// small halos); each tile then gets the rings 1..fuse of neighbours around
+// it: sub-step j of a launch of k sub-steps updates the tile and rings
+// 1..k-j, reading rings up to k-j+1.  Local order: tile, ring 1, ..., ring
+// fuse, each ascending.  The edge table of a tile covers the nodes that are
+// ever updated (tile .. ring fuse-1), slot-major, with local columns.
+void build_fv_tiles(Plan& p, int tile, int fuse) {
+    const int nn = p.nn, W = p.ell_width;
+    std::vector<int> owner(nn, -1);
+    std::vector<std::vector<int>> tiles;
+    int next = 0;
+    for (;;) {
+        while (next < nn && owner[next] >= 0) ++next;
+        if (next >= nn) break;
+        const int id = int(tiles.size());
+        std::vector<int> t;
+        std::queue<int> q;
+        int seed = next;
+        while (int(t.size()) < tile) {
+            if (q.empty()) {          // region exhausted: continue from the next free node
+                while (seed < nn && owner[seed] >= 0) ++seed;
+                if (seed >= nn) break;
+                owner[seed] = id;
+                t.push_back(seed);
+                q.push(seed);
+                continue;
+            }
+            const int a = q.front();
+            q.pop();
+            for (int z = p.rowptr[a] + 1; z < p.rowptr[a + 1] && int(t.size()) < tile; ++z) {
+                const int b = p.col[z];
+                if (owner[b] < 0) {
+                    owner[b] = id;
+                    t.push_back(b);
+                    q.push(b);
+                }
+            }
+        }
+        tiles.push_back(std::move(t));
+    }
+    p.fv_fuse = fuse;
+    p.fv_tile = tile;
+    p.n_tiles = int(tiles.size());
+    p.fv_maxl = 0;
+    p.ft_meta.assign(size_t(p.n_tiles) * kTileMeta, 0);
+    p.ft_node.clear();
+    p.ft_col.clear();
+    p.ft_src.clear();
+    std::vector<int> stamp(nn, -1), loc(nn, -1);
+    for (int t = 0; t < p.n_tiles; ++t) {
+        std::vector<int> nodes = tiles[t];
+        std::sort(nodes.begin(), nodes.end());
+        for (int a : nodes) stamp[a] = t;
+        int32_t* meta = p.ft_meta.data() + size_t(t) * kTileMeta;
+        meta[3] = int(nodes.size());
+        size_t lo = 0;
+        for (int r = 1; r <= fuse; ++r) {
+            const size_t hi = nodes.size();
+            for (size_t i = lo; i < hi; ++i)
+                for (int z = p.rowptr[nodes[i]] + 1; z < p.rowptr[nodes[i] + 1]; ++z) {
+                    const int b = p.col[z];
+                    if (stamp[b] != t) {
+                        stamp[b] = t;
+                        nodes.push_back(b);
+                    }
+                }
+            std::sort(nodes.begin() + hi, nodes.end());
+            meta[3 + r] = int(nodes.size());
+            lo = hi;
+        }
+        for (int r = fuse + 1; r <= kMaxFuse; ++r) meta[3 + r] = meta[3 + fuse];
+        for (size_t i = 0; i < nodes.size(); ++i) loc[nodes[i]] = int(i);
+        const int width = meta[3 + fuse - 1];
+        meta[0] = int(p.ft_node.size());
+        meta[1] = int(p.ft_col.size());
+        meta[2] = width;
+        p.ft_node.insert(p.ft_node.end(), nodes.begin(), nodes.end());
+        for (int z = 0; z < W; ++z)
+            for (int i = 0; i < width; ++i) {
+                const int P = nodes[i], zz = p.rowptr[P] + z;
+                const bool used = zz < p.rowptr[P + 1];
+                p.ft_col.push_back(used ? loc[p.col[zz]] : -1);
+                p.ft_src.push_back(used ? zz : -1);
+            }
+        p.fv_maxl = std::max(p.fv_maxl, int(nodes.size()));
+    }
+}
+
 }  // namespace
 
 int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Plan& p, std::string& err) {
@@ -674,6 +766,24 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
                 p.wnorm.push_back(dy);
                 p.wnorm.push_back(-dx);
             }
+        // fused FV sub-steps: fv_fuse per launch when a tile and its rings fit
+        // twice (ping-pong) in 64 KB of LDS, else one kernel per sub-step
+        if (g->fv_fuse < 0 || g->fv_fuse > kMaxFuse) return fail(err, HLBM_E_ARG, "fv_fuse must be 0..%d", kMaxFuse);
+        const int fuse = g->fv_fuse > 0 ? g->fv_fuse : kFvFuse;
+        p.fv_fuse = 1;
+        if (fuse > 1) {
+            const int tile = p.elem == 8 ? 128 : 256;
+            build_fv_tiles(p, tile, fuse);
+            const size_t lds = size_t(p.fv_maxl) * (2 * kRec * p.elem + 4);
+            if (lds > 65536) {
+                p.fv_fuse = 1;
+                p.n_tiles = 0;
+                p.ft_meta.clear();
+                p.ft_node.clear();
+                p.ft_col.clear();
+                p.ft_src.clear();
+            }
+        }
         // wall statistics: unit normal into the fluid at each wall node (opposite
         // to half the sum of its wall-edge normals) and its output slot
         p.wall_nrm.assign(2 * size_t(p.n_wall), 0.0);
@@ -786,6 +896,9 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
     p.off.wall_slot = take(size_t(p.n_wall) * 4);
     p.off.wsum = take(size_t(p.n_wall) * 3 * 8);
     p.off.wout = take(size_t(p.n_wall) * 3 * 8);
+    p.off.ft_meta = take(p.ft_meta.size() * 4);
+    p.off.ft_node = take(p.ft_node.size() * 4);
+    p.off.ft_edges = take(p.ft_col.size() * (E == 8 ? 32 : 16));
     size_t maxrow = 0;
     for (int l = 0; l <= p.L; ++l) maxrow = std::max(maxrow, size_t(p.lev[l].nx));
     p.stage_bytes = std::max(size_t(kQ) * maxrow * 8 * 8, std::min(size_t(32) << 20, size_t(kQ) * maxrow * 8 * 4096));

@@ -48,6 +48,7 @@ class Grid(C.Structure):
         ("u_inf", C.c_double), ("aoa_rad", C.c_double), ("rho0", C.c_double),
         ("precision", C.c_int32), ("interp", C.c_int32), ("n_sub", C.c_int32), ("bc", C.c_int32),
         ("wall_bc", C.c_int32), ("check_every", C.c_int32), ("history_len", C.c_int32),
+        ("fv_fuse", C.c_int32),
     ]
 
 
@@ -74,6 +75,7 @@ class Info(C.Structure):
         ("n_interp_struct", C.c_int32), ("n_fallback", C.c_int32), ("n_wall_edges", C.c_int32),
         ("nnz", C.c_int32), ("bytes_per_finest_step", C.c_int64), ("k1_bytes", C.c_int64 * 4),
         ("fv_bytes", C.c_int64), ("t", C.c_int64), ("workspace_bytes", C.c_size_t),
+        ("fv_fuse", C.c_int32),
     ]
 
 
@@ -121,7 +123,7 @@ def _np_ptr(a):
 
 def make_structs(nx_cells, ny_cells, patches=(), *, u_inf=0.05, aoa_rad=0.0, rho0=1.0,
                  precision=FP64, interp=INTERP_QUADRATIC, n_sub=0, periodic=False, wall_bc=True,
-                 check_every=0, history_len=0, mesh_xy=None, mesh_tri=None, mesh_kind=None,
+                 check_every=0, history_len=0, fv_fuse=0, mesh_xy=None, mesh_tri=None, mesh_kind=None,
                  chord=1.0, inner_ellipse=None):
     """ctypes Grid and Mesh (plus the arrays they point into, kept alive)."""
     g = Grid()
@@ -132,6 +134,7 @@ def make_structs(nx_cells, ny_cells, patches=(), *, u_inf=0.05, aoa_rad=0.0, rho
     g.precision, g.interp, g.n_sub = precision, interp, n_sub
     g.bc = BC_PERIODIC if periodic else BC_FARFIELD
     g.wall_bc, g.check_every, g.history_len = int(wall_bc), check_every, history_len
+    g.fv_fuse = int(fv_fuse)
     m = Mesh()
     keep = []
     if mesh_xy is not None:
@@ -206,11 +209,11 @@ class HLBM:
 
     @classmethod
     def from_workload(cls, w, *, precision=FP64, interp=INTERP_QUADRATIC, n_sub=0, wall_bc=True,
-                      aoa_rad=None, tau=None, check_every=0, history_len=0, stream=None):
+                      aoa_rad=None, tau=None, check_every=0, history_len=0, fv_fuse=0, stream=None):
         g, m, keep = structs_from_workload(
             w, precision=precision, interp=interp, n_sub=n_sub or w.n_sub, wall_bc=wall_bc,
             aoa_rad=w.aoa_rad if aoa_rad is None else aoa_rad, check_every=check_every,
-            history_len=history_len)
+            history_len=history_len, fv_fuse=fv_fuse)
         return cls(g, m, tau=w.tau_s if tau is None else tau, keep=keep, stream=stream)
 
     def _check(self, rc):

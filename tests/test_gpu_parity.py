@@ -155,6 +155,46 @@ def test_two_box_naca_fp64_short():
     assert max(e["cd"], e["cl"]) < 1e-10
 
 
+def test_four_level_naca_fp64_short():
+    """Re = 500, c = 48: base grid + three nested boxes (four levels), 192 x 24 mesh,
+    70 sub-steps, one base step = 8 finest steps and 16 more."""
+    w = W.naca_re500_conv(48)
+    sim = hlbm.HLBM.from_workload(w)
+    ref = O.Oracle.from_workload(w)
+    assert sim.info.n_levels == ref.n_levels == 4 and sim.info.n_sub == ref.n_sub == 70
+    for n in (8, 16):
+        sim.step(n)
+        ref.step(n)
+        e = compare(sim, ref, 4)
+        assert max(e["level0"], e["level1"], e["level2"], e["level3"], e["mesh"]) < TOL
+        assert max(e["cd"], e["cl"]) < 1e-10
+
+
+@pytest.mark.parametrize("case", ["re100_c40_fp64", "re1000_c128_fp32", "re1000_c128_fp64"])
+def test_fused_fv_substeps_match_single(case):
+    """Several FV sub-steps per launch (tiles with halos in LDS) give the state of
+    one launch per sub-step: same arithmetic in the same order."""
+    if case == "re100_c40_fp64":
+        w, prec, steps = W.naca_re100_c40(6.0), hlbm.FP64, 40
+    else:
+        w, steps = W.naca_re1000_c128(10.0), 20
+        prec = hlbm.FP32_SHIFTED if case.endswith("fp32") else hlbm.FP64
+    states = {}
+    for fuse in (1, 2, 3):
+        sim = hlbm.HLBM.from_workload(w, precision=prec, fv_fuse=fuse)
+        if sim.info.fv_fuse != fuse:          # tile + rings over the LDS budget: one per launch
+            assert fuse == 3 and sim.info.fv_fuse == 1
+            continue
+        sim.step(steps)
+        states[fuse] = [sim.get_state(l) for l in range(sim.info.n_levels)] + [sim.get_state(hlbm.PART_MESH)]
+        states[fuse].append(np.stack(sim.history()))
+    assert 2 in states
+    for fuse in sorted(set(states) - {1}):
+        d = max(rel(a, b) for a, b in zip(states[fuse], states[1]))
+        print(f"{case}: fuse {fuse} vs 1: max rel diff {d:.3e}", flush=True)
+        assert d <= (1e-14 if prec == hlbm.FP64 else 1e-6)
+
+
 def test_determinism_and_resume():
     w = W.naca_re100_c40(3.0)
     a = hlbm.HLBM.from_workload(w)
