@@ -1,0 +1,113 @@
+"""Measured cost of the hybrid scheme against an equivalent uniform-grid LBM (eq. (14)).
+
+eq. (14) models G = T_h / T_eq = (1 + chi s' n) / g, with T_h the time of a
+hybrid iteration and T_eq that of a standard LBM resolving the body as finely
+as the unstructured mesh does.  Here both times are measured on the GPU:
+
+* T_h: one base-level step of the workload (every level, the coupling and the
+  n FV sub-steps of each finest step), from a timed run of hlbm_step;
+* T_eq: one base-level step (the same physical time) of the equivalent LBM:
+  the same structured levels plus one more nested box of half the finest
+  spacing over the finest box (inset by a margin), no mesh.  Its finest
+  spacing is half a lattice unit, the wall spacing of the workloads' meshes.
+  The body itself is not represented: in a pull-streaming kernel a
+  bounce-back mask adds no traffic, so this is a lower bound of T_eq.
+
+The model's inputs are measured on the same runs: chi = FV node updates over
+structured node updates per base step (without n), g = structured node
+updates of the equivalent LBM over those of the hybrid grid, s' = time per FV
+node sub-step over time per structured node update (back-to-back kernel
+timings of the finest collide-stream and the FV sub-step).
+
+    python -m paper_2006_10487_amd.speedup --workload naca_re5000_c512 --steps 20
+
+prints one JSON object.
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import sys
+import time
+
+from . import hlbm, workloads
+
+
+def equivalent_lbm(w: workloads.Workload, margin: int = 8) -> workloads.Workload:
+    """w's structured grid with one more box of half the finest spacing over w's finest
+    box (inset by `margin` cells of that box on every side) and no mesh.  Lengths are
+    in the new finest units, so the chord doubles and Re, U (hence tau from Re) hold."""
+    if w.patches:
+        px, py = w.patches[-1][2], w.patches[-1][3]
+    else:
+        px, py = w.nx_cells, w.ny_cells
+    box = (margin, margin, 2 * (px - 2 * margin), 2 * (py - 2 * margin))
+    return dataclasses.replace(
+        w, name=w.name + "_equivalent_lbm", patches=list(w.patches) + [box], chord=2.0 * w.chord,
+        mesh_xy=None, mesh_tri=None, mesh_kind=None, inner_ellipse=(0.0, 0.0, 0.0, 0.0), omesh=None, n_sub=0)
+
+
+def updates_per_base_step(info) -> int:
+    """Structured node updates of one base step (level l steps 2^l times)."""
+    return sum(int(info.active_nodes[l]) << l for l in range(info.n_levels))
+
+
+def time_base_steps(sim, per: int, steps: int, warmup: int) -> float:
+    import torch
+    sim.step(per * warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(per * steps)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--workload", default="naca_re5000_c512")
+    ap.add_argument("--steps", type=int, default=20, help="timed base steps")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--fp64", action="store_true", help="FP64 populations (default FP32-shifted)")
+    a = ap.parse_args(argv)
+    prec = hlbm.FP64 if a.fp64 else hlbm.FP32_SHIFTED
+    w = workloads.PRESETS[a.workload]()
+    sim = hlbm.HLBM.from_workload(w, precision=prec)
+    info = sim.info
+    L = info.n_levels - 1
+    t_h = time_base_steps(sim, 2 ** L, a.steps, a.warmup)
+    t_collide = sim.kernel_bench(f"collide_l{L}", 50) * 1e-3
+    t_fv = sim.kernel_bench("fv_substep", 200) * 1e-3 / max(1, int(info.fv_fuse))   # per sub-step
+    n_fin = int(info.active_nodes[L])
+    n_mesh = int(info.n_mesh_nodes)
+    n_sub = int(info.n_sub)
+    ups_h = updates_per_base_step(info)
+    sim.close()
+
+    e = equivalent_lbm(w)
+    sim = hlbm.HLBM.from_workload(e, precision=prec)
+    einfo = sim.info
+    t_eq = time_base_steps(sim, 2 ** (einfo.n_levels - 1), a.steps, a.warmup)
+    ups_eq = updates_per_base_step(einfo)
+    sim.close()
+
+    fv_ups = n_mesh * (2 ** L)                       # FV node updates per base step, without n
+    chi = fv_ups / ups_h
+    g = ups_eq / ups_h
+    s_prime = (t_fv / n_mesh) / (t_collide / n_fin)
+    out = {
+        "workload": w.name, "equivalent": e.name, "precision": "fp64" if a.fp64 else "fp32_shifted",
+        "t_h_ms_per_base_step": round(1e3 * t_h, 4), "t_eq_ms_per_base_step": round(1e3 * t_eq, 4),
+        "G_measured": round(t_h / t_eq, 4),
+        "model": {"chi": chi, "n": n_sub, "s_prime": round(s_prime, 3), "g": round(g, 4),
+                  "G": round((1.0 + chi * s_prime * n_sub) / g, 4)},
+        "structured_updates_per_base_step": {"hybrid": ups_h, "equivalent": ups_eq},
+        "mesh_nodes": n_mesh, "finest_collide_us": round(1e6 * t_collide, 3), "fv_substep_us": round(1e6 * t_fv, 3),
+        "paper": {"chi": 1.5e-4, "g": 1.6, "n": 10, "s_prime": "3-5", "G": 0.63},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -479,6 +479,37 @@ def naca_re5000_c512() -> Workload:
                           512.0, 5000.0, 0.05, 8.0, 2048, 128, 508.0, h1=0.5, steps=10000)
 
 
+CONV_CHORDS = (48, 64, 96, 128, 144)
+CONV_N_SUB = 70     # ceil(1 / tau_u) of the smallest chord: one FV time step for every chord
+
+
+def naca_re500_conv(chord: int = 48) -> Workload:
+    """Self-convergence family (Sec. 5): Re = 500, alpha = 0, four structured
+    levels: a base grid of spacing 8 spanning 30c x 15c and three nested boxes
+    centred on mid-chord (finest, unit spacing: 2.5c x 1.25c; each parent box
+    twice as large), so every chord gives the same geometry in chord units.
+    The O-mesh has the same wall element size for every chord (4c surface
+    points, ~0.5 lu apart; first layer 0.25 lu; a band c/4 thick in c/2
+    layers), and the finite-volume time step is the same for all (n = 70)."""
+    c = int(chord)
+    if c % 16:
+        raise ValueError("chord must be a multiple of 16")
+    box = (5 * c // 2, 5 * c // 4)
+    w = _naca_workload(f"naca0012_re500_c{c}_conv", 15 * c // 4, 15 * c // 8, [box, box, box], float(c),
+                       500.0, 0.05, 0.0, 4 * c, c // 2, c / 4.0, h1=0.25, steps=600 * c)
+    return dataclasses.replace(w, n_sub=CONV_N_SUB)
+
+
+def naca_re_sweep(re: float = 2000.0) -> Workload:
+    """Reynolds sweep at zero incidence (Sec. 6.2): c = 512, U = 0.05, a base grid of
+    spacing 4 spanning 16c x 8c with two nested boxes (4c x 2c at spacing 2, 2c x c at
+    unit spacing) and a thin O-mesh band (0.19 c, 1280 surface points ~0.8 lu apart,
+    first layer 0.8 lu, 64 layers)."""
+    c = 512
+    return _naca_workload(f"naca0012_re{int(re)}_c512_sweep", 2048, 1024, [(1024, 512), (1024, 512)], float(c),
+                          float(re), 0.05, 0.0, 1280, 64, 0.19 * c, h1=0.8, steps=200 * c)
+
+
 PRESETS = {
     "naca_re100_c40": naca_re100_c40,
     "naca_re100_c40_refined": naca_re100_c40_refined,
@@ -486,4 +517,6 @@ PRESETS = {
     "naca_re1e4_c256": naca_re1e4_c256,
     "naca_re1000_c128_bumps": naca_re1000_c128_bumps,
     "naca_re5000_c512": naca_re5000_c512,
+    "naca_re500_conv": naca_re500_conv,
+    "naca_re_sweep": naca_re_sweep,
 }

@@ -89,6 +89,22 @@ def test_workloads_validate(lib):
         w = W.PRESETS[name]()
         g, m, keep = hlbm.structs_from_workload(w)
         assert hlbm.validate(g, m, 0.0, w.tau_s) == 0, (name, hlbm.last_error())
+    # the four-level convergence family: every chord, one FV time step
+    for c in W.CONV_CHORDS:
+        w = W.naca_re500_conv(c)
+        assert w.n_refine == 3 and w.n_sub == W.CONV_N_SUB
+        g, m, keep = hlbm.structs_from_workload(w)
+        assert hlbm.validate(g, m, 0.0, w.tau_s) == 0, (c, hlbm.last_error())
+        assert abs(w.tau_s - (0.5 + 3 * 0.05 * c / 500.0)) < 1e-12
+        assert W.CONV_N_SUB >= 1.0 / (w.tau_s - 0.5)
+
+
+def test_richardson_fit_recovers_order():
+    from paper_2006_10487_amd.convergence import richardson
+    c = np.array([48, 64, 96, 128, 144], dtype=float)
+    for p0, cinf0, k0 in ((2.0, 0.18, 40.0), (1.3, 0.05, -3.0)):
+        p, cinf, K, rms = richardson(c, cinf0 + k0 * c ** -p0)
+        assert abs(p - p0) < 1e-5 and abs(cinf - cinf0) < 1e-8 and rms < 1e-10
 
 
 def test_strouhal_of_sinusoid():
