@@ -219,12 +219,14 @@ def main():
         "config": {"workload": w.name, "base_cells": [w.nx_cells, w.ny_cells], "boxes": w.patches,
                    "mesh_nodes": int(r32["info"].n_mesh_nodes), "n_sub": int(r32["info"].n_sub),
                    "re": w.re, "aoa_deg": w.aoa_deg, "chord": w.chord,
-                   "finest_steps_per_step": per, "precision": "fp32_shifted_fp64_forces"},
+                   "finest_steps_per_step": per, "fv_fuse": int(r32["info"].fv_fuse),
+                   "precision": "fp32_shifted_fp64_forces"},
     }
     dom = max(k32, key=lambda k: k32[k]["share"])
-    res["roofline"] = roofline(k32, dom, "dominant kernel by time share; algorithmic bytes per launch over "
-                                         "the mean of back-to-back launches timed with HIP events; traffic = "
-                                         "calibrated FETCH_SIZE + WRITE_SIZE bytes per launch",
+    res["roofline"] = roofline(k32, dom, "dominant kernel by time share; algorithmic bytes per launch (for the "
+                                         "FV kernel: fv_fuse sub-steps) over the mean of back-to-back launches "
+                                         "timed with HIP events; traffic = calibrated FETCH_SIZE + WRITE_SIZE "
+                                         "bytes per launch",
                                measured_traffic(dom) if w.name == "naca0012_re5000_c512_8192x4096_r1" else None)
     res["roofline_base_grid"] = roofline(k32, "collide_l0", "base-level fused stream-collide (72 B per node)",
                                          measured_traffic("collide_l0") if w.name == "naca0012_re5000_c512_8192x4096_r1" else None)

@@ -72,9 +72,10 @@ typedef struct {
     int32_t wall_bc;              /* 1 = no-slip at mesh wall nodes, 0 = off (free-stream checks)    */
     int32_t check_every;          /* non-finite check interval in finest steps, 0 = off             */
     int32_t history_len;          /* force history ring length, 0 = 65536                            */
-    int32_t fv_fuse;              /* FV sub-steps per launch, 1..4; 0 = 2 where a tile of mesh nodes
-                                     and its halo fit in 64 KB of LDS (else 1).  Results do not
-                                     depend on it (same arithmetic, same order)                      */
+    int32_t fv_fuse;              /* FV sub-steps per launch, 1..4 (falls back to 1 when a tile of
+                                     mesh nodes and its halo do not fit in 64 KB of LDS); 0 = 2 for
+                                     FP32 meshes of >= 100k nodes, else 1.  Results do not depend on
+                                     it (same arithmetic, same order)                                */
 } hlbm_grid;
 
 /* Body-fitted triangular mesh (Sec. 2 and 4). */

@@ -31,8 +31,7 @@ def run(chord: int, passes: float, precision: int):
     steps = int(round(passes * chord / w.u_inf / per)) * per
     sim = hlbm.HLBM.from_workload(w, precision=precision, history_len=steps + 8, check_every=4000)
     t0 = time.perf_counter()
-    sim.step(steps)
-    sim.synchronize()
+    sim.step_logged(steps, w.name)
     dt = time.perf_counter() - t0
     cd, cl = sim.history()
     sim.close()

@@ -291,8 +291,13 @@ void finest_step(hlbm_ctx* c) {
         } else if (p.fv_fuse > 1) {
             for (int m = 0; m < p.n_sub; m += p.fv_fuse) {
                 Timed tm(c, HLBM_K_FV);
-                launch_fv_fused(pr, c->km, c->mesh(c->mesh_cur), c->mesh(1 - c->mesh_cur), c->prep(c->prep_t),
-                                c->prep(1 - c->prep_t), m, std::min(p.fv_fuse, p.n_sub - m), c->s);
+                const int k = std::min(p.fv_fuse, p.n_sub - m);
+                if (k > 1)
+                    launch_fv_fused(pr, c->km, c->mesh(c->mesh_cur), c->mesh(1 - c->mesh_cur), c->prep(c->prep_t),
+                                    c->prep(1 - c->prep_t), m, k, c->s);
+                else   // a single remaining sub-step: no halo to stage
+                    launch_fv_substep(pr, c->km, c->mesh(c->mesh_cur), c->mesh(1 - c->mesh_cur), c->prep(c->prep_t),
+                                      c->prep(1 - c->prep_t), double(m) / p.n_sub, c->s);
                 c->mesh_cur ^= 1;
             }
         } else {

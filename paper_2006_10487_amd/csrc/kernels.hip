@@ -667,10 +667,11 @@ __device__ __forceinline__ int die_block(int b, int nb) {
     return x < r ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
 }
 
-// Neighbour slots whose loads are issued together: all eight in FP32 (151
-// VGPRs, 3 waves/SIMD), four in FP64 (240 VGPRs, 2 waves/SIMD); measured
-// fastest on MI355X among 2, 4 and 8.
-template <typename T> struct FvGroup { static constexpr int value = sizeof(T) == 4 ? 8 : 4; };
+// Neighbour slots whose loads are issued together: all eight in FP32 (168
+// VGPRs, 3 waves/SIMD), two in FP64 (188 VGPRs); measured fastest on MI355X
+// among 2, 4 and 8 (FP64: 30.3 against 32.0 us per sub-step with four, on
+// the 264k-node mesh).
+template <typename T> struct FvGroup { static constexpr int value = sizeof(T) == 4 ? 8 : 2; };
 
 template <typename T, bool SHIFT, int W>
 __global__ __launch_bounds__(256) void k_fv_substep(const KMesh M, const T* __restrict__ fin, T* __restrict__ fout,

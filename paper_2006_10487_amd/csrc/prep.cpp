@@ -468,7 +468,12 @@ template <class S> int lagrange9(S x, S y, bool linear, int* di, int* dj, S* w) 
     return 4;
 }
 
-constexpr int kFvFuse = 2;   // FV sub-steps per launch (measured on MI355X)
+// Default FV sub-steps per launch: two for FP32 meshes of at least 100k nodes
+// (measured on MI355X: -4% per base step at 264k nodes), else one (at 33k
+// nodes the tiles' ring recomputation costs more than it saves, and FP64
+// tiles are LDS-bound).
+constexpr int kFvFuse = 2;
+constexpr int kFvFuseMinNodes = 100000;
 
 // Tiles for the fused finite-volume kernel, which takes several Jacobi
 // sub-steps per launch out of LDS.  Plan nodes are grouped into tiles of at
@@ -769,7 +774,7 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
         // fused FV sub-steps: fv_fuse per launch when a tile and its rings fit
         // twice (ping-pong) in 64 KB of LDS, else one kernel per sub-step
         if (g->fv_fuse < 0 || g->fv_fuse > kMaxFuse) return fail(err, HLBM_E_ARG, "fv_fuse must be 0..%d", kMaxFuse);
-        const int fuse = g->fv_fuse > 0 ? g->fv_fuse : kFvFuse;
+        const int fuse = g->fv_fuse > 0 ? g->fv_fuse : (p.elem == 4 && nn >= kFvFuseMinNodes ? kFvFuse : 1);
         p.fv_fuse = 1;
         if (fuse > 1) {
             const int tile = p.elem == 8 ? 128 : 256;

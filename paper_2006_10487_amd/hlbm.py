@@ -243,6 +243,20 @@ class HLBM:
     def step(self, n: int):
         self._check(lib().hlbm_step(self._ctx, int(n)))
 
+    def step_logged(self, n: int, label: str = "", chunk: int = 20000):
+        """step(n) in chunks of about `chunk` finest steps, each followed by a
+        synchronisation and a progress line on stderr (for long runs)."""
+        import sys
+        per = 2 ** max(0, int(self.info.n_levels) - 1)
+        chunk = max(per, chunk - chunk % per)
+        done = 0
+        while done < n:
+            k = min(chunk, n - done)
+            self.step(k)
+            self.synchronize()
+            done += k
+            print(f"[{label}] {done}/{n} steps", file=sys.stderr, flush=True)
+
     def forces(self):
         cd, cl = C.c_double(), C.c_double()
         self._check(lib().hlbm_forces(self._ctx, C.byref(cd), C.byref(cl)))

@@ -25,8 +25,7 @@ def run(aoa_deg: float, steps: int, ns: int, precision: int):
     w = workloads.naca_re1000_c128(aoa_deg, ns=ns)
     sim = hlbm.HLBM.from_workload(w, precision=precision, history_len=steps + 8, check_every=1000)
     t0 = time.perf_counter()
-    sim.step(steps)
-    sim.synchronize()
+    sim.step_logged(steps, w.name)
     dt = time.perf_counter() - t0
     cd, cl = sim.history()
     sim.close()

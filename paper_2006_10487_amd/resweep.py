@@ -32,8 +32,7 @@ def run(re: float, passes: float, precision: int):
     sim = hlbm.HLBM.from_workload(w, precision=precision, history_len=steps + 8, check_every=2000)
     n_sub = int(sim.info.n_sub)
     t0 = time.perf_counter()
-    sim.step(steps)
-    sim.synchronize()
+    sim.step_logged(steps, w.name)
     dt = time.perf_counter() - t0
     cd, cl = sim.history()
     sim.close()
