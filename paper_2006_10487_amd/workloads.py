@@ -482,31 +482,50 @@ def naca_re5000_c512() -> Workload:
 CONV_CHORDS = (48, 64, 96, 128, 144)
 CONV_N_SUB = 70     # ceil(1 / tau_u) of the smallest chord: one FV time step for every chord
 
+# Levels of the Re 500 and Re-sweep families.  With acoustic scaling level l
+# has tau_l - 1/2 = (tau_s - 1/2) / 2^(L-l), so its cell Reynolds number is
+# U dx_l / nu_l = 2^(L-l) Re / c (in chords).  At 83 (Re 500, c = 48, four
+# levels) the upstream coarse-to-fine interface diverged after 4,000-8,000
+# steps (measured); two levels keep it at or below 21 in the convergence
+# family and at 4-39 in the Reynolds sweep.
+FAMILY_BOXES = 1
+
+
+def naca_re500_four_levels(chord: int = 48) -> Workload:
+    """Four structured levels (base spacing 8 over 30c x 15c, three nested boxes
+    of 2.5c x 1.25c cells each) around a 4c x c/2 O-mesh, Re = 500: the paper's
+    level layout, for short parity runs (its coarse levels are too close to
+    tau = 1/2 for long runs at this chord)."""
+    c = int(chord)
+    box = (5 * c // 2, 5 * c // 4)
+    w = _naca_workload(f"naca0012_re500_c{c}_four_levels", 15 * c // 4, 15 * c // 8, [box, box, box], float(c),
+                       500.0, 0.05, 0.0, 4 * c, c // 2, c / 4.0, h1=0.25, steps=1000)
+    return dataclasses.replace(w, n_sub=CONV_N_SUB)
+
 
 def naca_re500_conv(chord: int = 48) -> Workload:
-    """Self-convergence family (Sec. 5): Re = 500, alpha = 0, four structured
-    levels: a base grid of spacing 8 spanning 30c x 15c and three nested boxes
-    centred on mid-chord (finest, unit spacing: 2.5c x 1.25c; each parent box
-    twice as large), so every chord gives the same geometry in chord units.
-    The O-mesh has the same wall element size for every chord (4c surface
-    points, ~0.5 lu apart; first layer 0.25 lu; a band c/4 thick in c/2
+    """Self-convergence family (Sec. 5): Re = 500, alpha = 0, a base grid of
+    spacing 2 spanning 30c x 15c and one box of unit spacing (2.5c x 1.25c)
+    centred on mid-chord, so every chord gives the same geometry in chord
+    units.  The O-mesh has the same wall element size for every chord (4c
+    surface points, ~0.5 lu apart; first layer 0.25 lu; a band c/4 thick in c/2
     layers), and the finite-volume time step is the same for all (n = 70)."""
     c = int(chord)
     if c % 16:
         raise ValueError("chord must be a multiple of 16")
-    box = (5 * c // 2, 5 * c // 4)
-    w = _naca_workload(f"naca0012_re500_c{c}_conv", 15 * c // 4, 15 * c // 8, [box, box, box], float(c),
-                       500.0, 0.05, 0.0, 4 * c, c // 2, c / 4.0, h1=0.25, steps=600 * c)
+    sp = 2 ** FAMILY_BOXES
+    w = _naca_workload(f"naca0012_re500_c{c}_conv", 30 * c // sp, 15 * c // sp, [(5 * c // 2, 5 * c // 4)],
+                       float(c), 500.0, 0.05, 0.0, 4 * c, c // 2, c / 4.0, h1=0.25, steps=600 * c)
     return dataclasses.replace(w, n_sub=CONV_N_SUB)
 
 
 def naca_re_sweep(re: float = 2000.0) -> Workload:
-    """Reynolds sweep at zero incidence (Sec. 6.2): c = 512, U = 0.05, a base grid of
-    spacing 4 spanning 16c x 8c with two nested boxes (4c x 2c at spacing 2, 2c x c at
-    unit spacing) and a thin O-mesh band (0.19 c, 1280 surface points ~0.8 lu apart,
-    first layer 0.8 lu, 64 layers)."""
+    """Reynolds sweep at zero incidence (Sec. 6.2): c = 512, U = 0.05, a base grid
+    of spacing 2 spanning 16c x 8c with one box of unit spacing (2c x c) and a thin
+    O-mesh band (0.19 c, 1280 surface points ~0.8 lu apart, first layer 0.8 lu,
+    64 layers)."""
     c = 512
-    return _naca_workload(f"naca0012_re{int(re)}_c512_sweep", 2048, 1024, [(1024, 512), (1024, 512)], float(c),
+    return _naca_workload(f"naca0012_re{int(re)}_c512_sweep", 8 * c, 4 * c, [(2 * c, c)], float(c),
                           float(re), 0.05, 0.0, 1280, 64, 0.19 * c, h1=0.8, steps=200 * c)
 
 

@@ -92,11 +92,15 @@ def test_workloads_validate(lib):
     # the four-level convergence family: every chord, one FV time step
     for c in W.CONV_CHORDS:
         w = W.naca_re500_conv(c)
-        assert w.n_refine == 3 and w.n_sub == W.CONV_N_SUB
+        assert w.n_refine == W.FAMILY_BOXES and w.n_sub == W.CONV_N_SUB
+        assert 2 ** w.n_refine * w.re / w.chord <= 21.0      # coarse-level cell Reynolds number
         g, m, keep = hlbm.structs_from_workload(w)
         assert hlbm.validate(g, m, 0.0, w.tau_s) == 0, (c, hlbm.last_error())
         assert abs(w.tau_s - (0.5 + 3 * 0.05 * c / 500.0)) < 1e-12
         assert W.CONV_N_SUB >= 1.0 / (w.tau_s - 0.5)
+    w = W.naca_re500_four_levels(48)
+    g, m, keep = hlbm.structs_from_workload(w)
+    assert w.n_refine == 3 and hlbm.validate(g, m, 0.0, w.tau_s) == 0
 
 
 def test_richardson_fit_recovers_order():

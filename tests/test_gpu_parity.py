@@ -158,7 +158,7 @@ def test_two_box_naca_fp64_short():
 def test_four_level_naca_fp64_short():
     """Re = 500, c = 48: base grid + three nested boxes (four levels), 192 x 24 mesh,
     70 sub-steps, one base step = 8 finest steps and 16 more."""
-    w = W.naca_re500_conv(48)
+    w = W.naca_re500_four_levels(48)
     sim = hlbm.HLBM.from_workload(w)
     ref = O.Oracle.from_workload(w)
     assert sim.info.n_levels == ref.n_levels == 4 and sim.info.n_sub == ref.n_sub == 70
