@@ -21,8 +21,8 @@ import numpy as np
 from . import hlbm, workloads
 
 
-def run(aoa_deg: float, steps: int, ns: int, precision: int):
-    w = workloads.naca_re1000_c128(aoa_deg, ns=ns)
+def run(aoa_deg: float, steps: int, ns: int, precision: int, band: float, nl: int):
+    w = workloads.naca_re1000_c128(aoa_deg, ns=ns, band=band, nl=nl)
     sim = hlbm.HLBM.from_workload(w, precision=precision, history_len=steps + 8, check_every=1000)
     t0 = time.perf_counter()
     sim.step_logged(steps, w.name)
@@ -38,12 +38,20 @@ def main(argv=None):
     ap.add_argument("--aoa", default="0,5,10,15,20")
     ap.add_argument("--steps", type=int, default=40000)
     ap.add_argument("--ns", type=int, default=512, help="surface points of the O-mesh")
+    ap.add_argument("--band", type=float, default=workloads.RE1000_C128_DOUT, help="O-mesh band thickness (lu)")
+    ap.add_argument("--nl", type=int, default=64, help="O-mesh layers")
+    ap.add_argument("--fp64-only", action="store_true", help="skip the FP32-shifted run")
     a = ap.parse_args(argv)
     for aoa in [float(x) for x in a.aoa.split(",")]:
         out = {"aoa_deg": aoa, "steps": a.steps, "ns": a.ns}
         try:
-            w, t64, cd64, cl64, st64 = run(aoa, a.steps, a.ns, hlbm.FP64)
-            _, t32, cd32, cl32, st32 = run(aoa, a.steps, a.ns, hlbm.FP32_SHIFTED)
+            w, t64, cd64, cl64, st64 = run(aoa, a.steps, a.ns, hlbm.FP64, a.band, a.nl)
+            if a.fp64_only:
+                out.update({"workload": w.name, "mesh_nodes": int(w.mesh_xy.shape[0]),
+                            "fp64": {"cd": cd64, "cl": cl64, "st": st64, "seconds": round(t64, 3)}})
+                print(json.dumps(out), flush=True)
+                continue
+            _, t32, cd32, cl32, st32 = run(aoa, a.steps, a.ns, hlbm.FP32_SHIFTED, a.band, a.nl)
         except hlbm.HLBMError as e:
             out["error"] = str(e)
             print(json.dumps(out), flush=True)

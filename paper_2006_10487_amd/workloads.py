@@ -449,11 +449,13 @@ def naca_re100_c40_refined(aoa_deg: float = 0.0, bumps=None) -> Workload:
 RE1000_C128_DOUT, RE1000_C128_H1 = 24.0, 0.25
 
 
-def naca_re1000_c128(aoa_deg: float = 0.0, ns: int = 512) -> Workload:
-    """Re = 1000, c = 128: 1024x512 base cells (spacing 2), one 384x192 box, ns x 64 mesh
-    in a band 24 lu thick (first layer 0.25 lu)."""
-    return _naca_workload("naca0012_re1000_c128_1024x512_r1" + ("" if ns == 512 else f"_m{ns}"), 1024, 512,
-                          [(384, 192)], 128.0, 1000.0, 0.05, aoa_deg, ns, 64, RE1000_C128_DOUT,
+def naca_re1000_c128(aoa_deg: float = 0.0, ns: int = 512, band: float = RE1000_C128_DOUT,
+                     nl: int = 64) -> Workload:
+    """Re = 1000, c = 128: 1024x512 base cells (spacing 2), one 384x192 box, ns x nl mesh
+    in a band `band` lu thick (default 24, 64 layers; first layer 0.25 lu)."""
+    tag = ("" if ns == 512 else f"_m{ns}") + ("" if (band, nl) == (RE1000_C128_DOUT, 64) else f"_b{band:g}x{nl}")
+    return _naca_workload("naca0012_re1000_c128_1024x512_r1" + tag, 1024, 512,
+                          [(384, 192)], 128.0, 1000.0, 0.05, aoa_deg, ns, nl, band,
                           h1=RE1000_C128_H1, steps=40000)
 
 
