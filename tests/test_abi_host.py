@@ -103,6 +103,21 @@ def test_workloads_validate(lib):
     assert w.n_refine == 3 and hlbm.validate(g, m, 0.0, w.tau_s) == 0
 
 
+def test_equivalent_lbm_workload(lib):
+    """The eq. (14) comparison grid: one more box of half spacing over the finest box, no mesh,
+    the same Reynolds number (chord doubled in the new finest units)."""
+    from paper_2006_10487_amd.speedup import equivalent_lbm
+    for name in ("naca_re1000_c128", "naca_re5000_c512"):
+        w = W.PRESETS[name]()
+        e = equivalent_lbm(w)
+        assert e.n_refine == w.n_refine + 1 and e.mesh_xy is None and e.chord == 2 * w.chord
+        px, py = w.patches[-1][2], w.patches[-1][3]
+        assert e.patches[-1] == (8, 8, 2 * (px - 16), 2 * (py - 16))
+        assert abs((e.tau_s - 0.5) - 2 * (w.tau_s - 0.5)) < 1e-12
+        g, m, keep = hlbm.structs_from_workload(e)
+        assert hlbm.validate(g, m, 0.0, e.tau_s) == 0, hlbm.last_error()
+
+
 def test_richardson_fit_recovers_order():
     from paper_2006_10487_amd.convergence import richardson
     c = np.array([48, 64, 96, 128, 144], dtype=float)
