@@ -25,8 +25,8 @@ from . import hlbm, workloads
 PAPER_CD = {1000: 0.119, 2000: 0.084, 5000: 0.052, 10000: 0.037}
 
 
-def run(re: float, passes: float, precision: int):
-    w = workloads.naca_re_sweep(re)
+def run(re: float, passes: float, precision: int, mesh: dict):
+    w = workloads.naca_re_sweep(re, **mesh)
     per = 2 ** w.n_refine
     steps = int(round(passes * w.chord / w.u_inf / per)) * per
     sim = hlbm.HLBM.from_workload(w, precision=precision, history_len=steps + 8, check_every=2000)
@@ -46,16 +46,21 @@ def main(argv=None):
     ap.add_argument("--re", default="1000,2000,5000,10000")
     ap.add_argument("--passes", type=float, default=20.0, help="chord-transit times per run")
     ap.add_argument("--no-fp64", action="store_true", help="FP32-shifted runs only")
+    ap.add_argument("--ns", type=int, default=1280, help="surface points of the O-mesh")
+    ap.add_argument("--d-out", type=float, default=0.19, help="outer ellipse beyond the chord, in chords")
+    ap.add_argument("--nl", type=int, default=64, help="O-mesh layers")
+    ap.add_argument("--h1", type=float, default=0.8, help="first layer height (lu)")
     a = ap.parse_args(argv)
+    mesh = dict(ns=a.ns, d_out=a.d_out, nl=a.nl, h1=a.h1)
     for re in [float(x) for x in a.re.split(",")]:
         out = {"re": re, "passes": a.passes}
         try:
-            w, steps, n_sub, t32, cd32, cl32, st32 = run(re, a.passes, hlbm.FP32_SHIFTED)
+            w, steps, n_sub, t32, cd32, cl32, st32 = run(re, a.passes, hlbm.FP32_SHIFTED, mesh)
             out.update({"workload": w.name, "finest_steps": steps, "n_sub": n_sub, "mesh_nodes": int(w.mesh_xy.shape[0]),
                         "fp32_shifted": {"cd": cd32, "cl": cl32, "st": st32, "seconds": round(t32, 2)},
                         "paper_cd_c1024": PAPER_CD.get(int(re))})
             if not a.no_fp64:
-                _, _, _, t64, cd64, cl64, st64 = run(re, a.passes, hlbm.FP64)
+                _, _, _, t64, cd64, cl64, st64 = run(re, a.passes, hlbm.FP64, mesh)
                 out["fp64"] = {"cd": cd64, "cl": cl64, "st": st64, "seconds": round(t64, 2)}
                 out["cd_rel_err"] = abs(cd32 - cd64) / abs(cd64)
                 out["cl_abs_err"] = abs(cl32 - cl64)

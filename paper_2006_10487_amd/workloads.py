@@ -521,14 +521,17 @@ def naca_re500_conv(chord: int = 48) -> Workload:
     return dataclasses.replace(w, n_sub=CONV_N_SUB)
 
 
-def naca_re_sweep(re: float = 2000.0) -> Workload:
+def naca_re_sweep(re: float = 2000.0, ns: int = 1280, d_out: float = 0.19, nl: int = 64,
+                  h1: float = 0.8) -> Workload:
     """Reynolds sweep at zero incidence (Sec. 6.2): c = 512, U = 0.05, a base grid
     of spacing 2 spanning 16c x 8c with one box of unit spacing (2c x c) and a thin
-    O-mesh band (0.19 c, 1280 surface points ~0.8 lu apart, first layer 0.8 lu,
-    64 layers)."""
+    O-mesh band (outer ellipse d_out c beyond the chord line and the edges; by
+    default 1280 surface points ~0.8 lu apart, first layer 0.8 lu, 64 layers)."""
     c = 512
-    return _naca_workload(f"naca0012_re{int(re)}_c512_sweep", 8 * c, 4 * c, [(2 * c, c)], float(c),
-                          float(re), 0.05, 0.0, 1280, 64, 0.19 * c, h1=0.8, steps=200 * c)
+    default = (ns, d_out, nl, h1) == (1280, 0.19, 64, 0.8)
+    tag = "" if default else f"_m{ns}_d{d_out:g}_l{nl}_h{h1:g}"
+    return _naca_workload(f"naca0012_re{int(re)}_c512_sweep{tag}", 8 * c, 4 * c, [(2 * c, c)], float(c),
+                          float(re), 0.05, 0.0, ns, nl, d_out * c, h1=h1, steps=200 * c)
 
 
 PRESETS = {
