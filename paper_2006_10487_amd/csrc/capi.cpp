@@ -121,6 +121,7 @@ void setup_views(hlbm_ctx* c) {
     m.n_sub = p.n_sub;
     m.n_tiles = p.n_tiles;
     m.maxl = p.fv_maxl;
+    m.maxw = p.fv_maxw;
     m.tile = p.fv_tile;
     m.ft_meta = reinterpret_cast<const int32_t*>(c->ws + p.off.ft_meta);
     m.ft_node = reinterpret_cast<const int32_t*>(c->ws + p.off.ft_node);

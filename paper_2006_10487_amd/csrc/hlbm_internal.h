@@ -70,7 +70,7 @@ struct Plan {
     // nodes, each with the rings of neighbours that fv_fuse Jacobi sub-steps
     // reach; per tile kTileMeta ints {node offset, edge offset, edge-table
     // width, n_le[0..fv_fuse]} with n_le[r] = local nodes within ring r
-    int fv_fuse = 1, fv_tile = 256, fv_maxl = 0, n_tiles = 0;
+    int fv_fuse = 1, fv_tile = 256, fv_maxl = 0, fv_maxw = 0, n_tiles = 0;
     std::vector<int32_t> ft_meta, ft_node;
     std::vector<int32_t> ft_col;         // local column per (slot, computed node) of each tile
     std::vector<int32_t> ft_src;         // index into col / gx / gy / cc of that entry, -1 = unused
@@ -134,7 +134,7 @@ struct KMesh {
     int wall_bc;
     double rho0;
     // fused sub-steps (fuse > 1): tile tables and the LDS size they need
-    int fuse, n_sub, n_tiles, maxl, tile;
+    int fuse, n_sub, n_tiles, maxl, maxw, tile;   // maxw: largest edge-table width (second LDS buffer)
     const int32_t* ft_meta;
     const int32_t* ft_node;
     const void* ft_edges;

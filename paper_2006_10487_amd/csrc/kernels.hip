@@ -730,8 +730,8 @@ __global__ __launch_bounds__(256) void k_fv_fused(const KMesh M, const T* __rest
                                                   int ksteps) {
     extern __shared__ __align__(16) unsigned char smem[];
     T* const buf0 = reinterpret_cast<T*>(smem);
-    T* const buf1 = buf0 + size_t(M.maxl) * kRec;
-    int32_t* const gid = reinterpret_cast<int32_t*>(buf1 + size_t(M.maxl) * kRec);
+    T* const buf1 = buf0 + size_t(M.maxl) * kRec;       // holds at most the updated nodes (maxw)
+    int32_t* const gid = reinterpret_cast<int32_t*>(buf1 + size_t(M.maxw) * kRec);
     const int t = die_block(blockIdx.x, gridDim.x);
     const int32_t* meta = M.ft_meta + size_t(t) * kTileMeta;
     const int noff = meta[0], eoff = meta[1], width = meta[2];
@@ -934,7 +934,7 @@ void launch_fv_fused(int prec, const KMesh& M, const void* fin, void* fout, cons
                      int m0, int k, hipStream_t s) {
     if (M.n_tiles <= 0 || k < 1 || k > M.fuse) return;
     const size_t elem = prec == HLBM_FP64 ? 8 : 4;
-    const size_t lds = size_t(M.maxl) * (2 * kRec * elem + 4);
+    const size_t lds = size_t(M.maxl + M.maxw) * kRec * elem + size_t(M.maxl) * 4;
     const unsigned threads = unsigned(M.tile);
     if (M.ell_width <= 8) {
         HLBM_DISPATCH(prec, (k_fv_fused<T, S, 8><<<M.n_tiles, threads, lds, s>>>(M, (const T*)fin, (T*)fout, (const T*)prep0,

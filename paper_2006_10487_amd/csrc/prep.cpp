@@ -521,6 +521,7 @@ void build_fv_tiles(Plan& p, int tile, int fuse) {
     p.fv_tile = tile;
     p.n_tiles = int(tiles.size());
     p.fv_maxl = 0;
+    p.fv_maxw = 0;
     p.ft_meta.assign(size_t(p.n_tiles) * kTileMeta, 0);
     p.ft_node.clear();
     p.ft_col.clear();
@@ -562,6 +563,7 @@ void build_fv_tiles(Plan& p, int tile, int fuse) {
                 p.ft_src.push_back(used ? zz : -1);
             }
         p.fv_maxl = std::max(p.fv_maxl, int(nodes.size()));
+        p.fv_maxw = std::max(p.fv_maxw, width);
     }
 }
 
@@ -771,15 +773,18 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
                 p.wnorm.push_back(dy);
                 p.wnorm.push_back(-dx);
             }
-        // fused FV sub-steps: fv_fuse per launch when a tile and its rings fit
-        // twice (ping-pong) in 64 KB of LDS, else one kernel per sub-step
+        // fused FV sub-steps: fv_fuse per launch when a tile with its rings,
+        // plus the nodes it updates (ping-pong), fit in 64 KB of LDS, else one
+        // kernel per sub-step
         if (g->fv_fuse < 0 || g->fv_fuse > kMaxFuse) return fail(err, HLBM_E_ARG, "fv_fuse must be 0..%d", kMaxFuse);
         const int fuse = g->fv_fuse > 0 ? g->fv_fuse : (p.elem == 4 && nn >= kFvFuseMinNodes ? kFvFuse : 1);
         p.fv_fuse = 1;
         if (fuse > 1) {
-            const int tile = p.elem == 8 ? 128 : 256;
+            // tile sizes measured on MI355X (FP32: 192 nodes, 32.6 KB of LDS on the
+            // 264k-node mesh, 1-2% faster than 224 or 256; FP64 tiles of 128)
+            const int tile = p.elem == 8 ? 128 : 192;
             build_fv_tiles(p, tile, fuse);
-            const size_t lds = size_t(p.fv_maxl) * (2 * kRec * p.elem + 4);
+            const size_t lds = size_t(p.fv_maxl + p.fv_maxw) * kRec * p.elem + size_t(p.fv_maxl) * 4;
             if (lds > 65536) {
                 p.fv_fuse = 1;
                 p.n_tiles = 0;
