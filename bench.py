@@ -13,7 +13,6 @@ events on the library's stream during the timed region.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time

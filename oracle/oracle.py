@@ -10,7 +10,6 @@ from __future__ import annotations
 import ctypes as C
 import os
 import subprocess
-from typing import Optional
 
 import numpy as np
 

@@ -5,7 +5,6 @@ FP64 bar: infinity-norm relative difference of the full state <= 1e-11
 1e-10 absolute.  FP32-shifted bar: time-averaged C_D and C_L within 1e-4
 relative of FP64 (absolute on C_L when it vanishes by symmetry).
 """
-import math
 
 import numpy as np
 import pytest
