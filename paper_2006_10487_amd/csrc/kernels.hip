@@ -662,7 +662,12 @@ __device__ __forceinline__ void fv_finish(const KMesh& M, int P, const FvAcc<T>&
 // round-robin, one L2 each) gets a contiguous range of nodes, whose
 // neighbours then mostly sit in the same L2 (measured: -11% FP32, -13% FP64
 // sub-step time on the 264k-node mesh).
+// The order is reversed: the last node blocks hold the interpolation pivots,
+// whose f* work makes them the slowest, and dispatching them first keeps them
+// out of the kernel's tail (measured: -5.5% per FP32 sub-step on the
+// 264k-node mesh).
 __device__ __forceinline__ int die_block(int b, int nb) {
+    b = nb - 1 - b;
     const int q = nb / 8, r = nb % 8, x = b % 8, slot = b / 8;
     return x < r ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
 }

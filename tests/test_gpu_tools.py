@@ -57,4 +57,5 @@ def test_speedup_tool(capsys):
     assert x["t_h_ms_per_base_step"] > 0 and x["t_eq_ms_per_base_step"] > 0
     m = x["model"]
     assert m["n"] == 53 and m["g"] > 1 and 0 < m["chi"] < 1
-    assert abs(x["G_measured"] - x["t_h_ms_per_base_step"] / x["t_eq_ms_per_base_step"]) < 1e-3
+    ratio = x["t_h_ms_per_base_step"] / x["t_eq_ms_per_base_step"]   # both rounded to 1e-4 ms
+    assert abs(x["G_measured"] - ratio) < 2e-3 * ratio
