@@ -194,6 +194,27 @@ def test_fused_fv_substeps_match_single(case):
         assert d <= (1e-14 if prec == hlbm.FP64 else 1e-6)
 
 
+def test_bench_workload_full_size():
+    """The throughput workload at its full size (8192 x 4096 base cells, 2048 x 1024 box,
+    264k-node mesh, 66 sub-steps) for one base step: FP64 against the oracle to the
+    FP64 bar; FP32-shifted (two fused sub-steps per launch, as bench.py times it)
+    against the oracle within the FP32 rounding of two finest steps."""
+    w = W.naca_re5000_c512()
+    ref = O.Oracle.from_workload(w)
+    ref.step(2)
+    sim = hlbm.HLBM.from_workload(w)
+    assert sim.info.n_sub == ref.n_sub == 66
+    sim.step(2)
+    e = compare(sim, ref, 2)
+    assert max(e["level0"], e["level1"], e["mesh"]) < TOL and max(e["cd"], e["cl"]) < 1e-10
+    sim.close()
+    sim = hlbm.HLBM.from_workload(w, precision=hlbm.FP32_SHIFTED)
+    assert sim.info.fv_fuse == 2
+    sim.step(2)
+    e = compare(sim, ref, 2)
+    assert max(e["level0"], e["level1"], e["mesh"]) < 1e-6 and max(e["cd"], e["cl"]) < 1e-5
+
+
 def test_determinism_and_resume():
     w = W.naca_re100_c40(3.0)
     a = hlbm.HLBM.from_workload(w)
