@@ -312,7 +312,7 @@ void finest_step(hlbm_ctx* c) {
         const double qn = 0.5 * p.rho0 * p.u_inf * p.u_inf * p.chord;
         {
             Timed tm(c, HLBM_K_FORCE);
-            launch_wall_force(pr, c->km, c->mesh(c->mesh_cur), int(p.wedge.size() / 2),
+            launch_wall_force(pr, c->mesh(c->mesh_cur), int(p.wedge.size() / 2),
                               reinterpret_cast<const int32_t*>(c->ws + p.off.wedge),
                               reinterpret_cast<const double*>(c->ws + p.off.wnorm), slot, std::cos(p.aoa),
                               std::sin(p.aoa), qn > 0 ? qn : 1.0, c->s);
@@ -327,7 +327,7 @@ void finest_step(hlbm_ctx* c) {
         c->prep_t ^= 1;
     } else {
         // no wall: zero force (the kernel writes 0 for an empty edge list)
-        launch_wall_force(pr, c->km, c->mesh(0), 0, nullptr, nullptr, slot, 1.0, 0.0, 1.0, c->s);
+        launch_wall_force(pr, c->mesh(0), 0, nullptr, nullptr, slot, 1.0, 0.0, 1.0, c->s);
     }
     c->cur[L] ^= 1;
     c->t++;

@@ -166,7 +166,7 @@ void launch_fv_fused(int prec, const KMesh& M, const void* fin, void* fout, cons
 void launch_wall_stats(int prec, const void* f, int n_wall, const double* nrm, double rho0, double inv_q, double* sum,
                        hipStream_t s);
 void launch_wall_stats_final(int n_wall, const double* sum, const int32_t* slot, double n, double* out, hipStream_t s);
-void launch_wall_force(int prec, const KMesh& M, const void* f, int n_edges, const int32_t* wedge,
+void launch_wall_force(int prec, const void* f, int n_edges, const int32_t* wedge,
                        const double* wnorm, double* hist_slot, double cos_a, double sin_a, double qnorm,
                        hipStream_t s);
 void launch_mesh_convert(int prec, int nn, const double* in, void* out, int to_storage, double rho0,

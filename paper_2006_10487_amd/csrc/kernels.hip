@@ -769,7 +769,7 @@ __global__ __launch_bounds__(256) void k_fv_fused(const KMesh M, const T* __rest
                 if (e[z].col < 0) continue;
                 const int k = gid[e[z].col];
                 const bool star = pivot_interp && k >= M.n_core;
-                T f[9], nq[9], mk, uxk, uyk;
+                T f[9], nq[9], mk = 0, uxk = 0, uyk = 0;
                 if (star) {
                     const size_t sl = size_t(k - M.n_core) * kMacro;
                     star_values<T, SHIFT>(prep0 + sl, prep1 + sl, theta, cst, rho0, f, nq);
@@ -793,7 +793,7 @@ __global__ __launch_bounds__(256) void k_fv_fused(const KMesh M, const T* __rest
 // by one block in a fixed order (deterministic).  Shifted storage drops the
 // rest-state part rho0 c_s^2 N_e, which sums to zero over the closed wall.
 template <typename T, bool SHIFT>
-__global__ __launch_bounds__(256) void k_wall_force(const T* __restrict__ f, int nn, int ne, const int32_t* __restrict__ wedge,
+__global__ __launch_bounds__(256) void k_wall_force(const T* __restrict__ f, int ne, const int32_t* __restrict__ wedge,
                                                     const double* __restrict__ wn, double* __restrict__ out,
                                                     double ca, double sa, double qn) {
     __shared__ double sx[256], sy[256];
@@ -813,7 +813,7 @@ __global__ __launch_bounds__(256) void k_wall_force(const T* __restrict__ f, int
     sy[threadIdx.x] = ay;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) {
+        if (int(threadIdx.x) < h) {
             sx[threadIdx.x] += sx[threadIdx.x + h];
             sy[threadIdx.x] += sy[threadIdx.x + h];
         }
@@ -950,9 +950,9 @@ void launch_fv_fused(int prec, const KMesh& M, const void* fin, void* fout, cons
     }
 }
 
-void launch_wall_force(int prec, const KMesh& M, const void* f, int ne, const int32_t* wedge, const double* wn,
+void launch_wall_force(int prec, const void* f, int ne, const int32_t* wedge, const double* wn,
                        double* out, double ca, double sa, double qn, hipStream_t s) {
-    HLBM_DISPATCH(prec, (k_wall_force<T, S><<<1, 256, 0, s>>>((const T*)f, M.nn, ne, wedge, wn, out, ca, sa, qn)));
+    HLBM_DISPATCH(prec, (k_wall_force<T, S><<<1, 256, 0, s>>>((const T*)f, ne, wedge, wn, out, ca, sa, qn)));
 }
 
 void launch_mesh_convert(int prec, int nn, const double* in, void* out, int to_storage, double rho0, hipStream_t s) {
@@ -1034,7 +1034,7 @@ __device__ __forceinline__ void block_partial(double a, double b, double* partia
     sb[threadIdx.x] = b;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) {
+        if (int(threadIdx.x) < h) {
             sa[threadIdx.x] += sa[threadIdx.x + h];
             sb[threadIdx.x] += sb[threadIdx.x + h];
         }
@@ -1055,7 +1055,7 @@ __global__ void k_zero(double* p, size_t n) {
 // wall normals of the two wall edges at P, j = drag/lift weights / normaliser.
 // With vbar set, also accumulates d J / d V_P = sum_q (c_q . j) c_q f_q(P) from the
 // mesh state fst the force was taken on.
-__global__ void k_adj_force(int n_wall, int nn, double* __restrict__ mbar, const double* __restrict__ V, double jx,
+__global__ void k_adj_force(int n_wall, double* __restrict__ mbar, const double* __restrict__ V, double jx,
                             double jy, const double* __restrict__ fst, double* __restrict__ vbar) {
     const int P = blockIdx.x * blockDim.x + threadIdx.x;
     if (P >= n_wall) return;
@@ -1755,7 +1755,7 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
     sb[threadIdx.x] = b;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) sa[threadIdx.x] += sa[threadIdx.x + h], sb[threadIdx.x] += sb[threadIdx.x + h];
+        if (int(threadIdx.x) < h) sa[threadIdx.x] += sa[threadIdx.x + h], sb[threadIdx.x] += sb[threadIdx.x + h];
         __syncthreads();
     }
     if (threadIdx.x == 0) acc[0] += sa[0], acc[1] += sb[0];
@@ -1773,7 +1773,7 @@ void launch_zero(double* p, size_t n, hipStream_t s) {
 void launch_adj_force(const KAdj& K, double* mbar, const double* vwall, double jx, double jy, const double* fst,
                       hipStream_t s) {
     if (K.M.n_wall > 0)
-        k_adj_force<<<blocks(K.M.n_wall), 256, 0, s>>>(K.M.n_wall, K.M.nn, mbar, vwall, jx, jy, fst, K.vbar);
+        k_adj_force<<<blocks(K.M.n_wall), 256, 0, s>>>(K.M.n_wall, mbar, vwall, jx, jy, fst, K.vbar);
 }
 void launch_adj_fv_wall(const KAdj& K, const double* Mrec, const double* ybar, double* zwall, const double* prep0,
                         const double* prep1, double theta, hipStream_t s) {
