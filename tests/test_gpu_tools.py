@@ -59,3 +59,17 @@ def test_speedup_tool(capsys):
     assert m["n"] == 53 and m["g"] > 1 and 0 < m["chi"] < 1
     ratio = x["t_h_ms_per_base_step"] / x["t_eq_ms_per_base_step"]   # both rounded to 1e-4 ms
     assert abs(x["G_measured"] - ratio) < 2e-3 * ratio
+
+
+def test_wallprofile_tool(capsys):
+    from paper_2006_10487_amd import wallprofile
+    assert wallprofile.main(["--aoa", "8", "--steps", "200", "--ns", "512"]) == 0
+    (x,) = records(capsys)
+    assert x["steps_averaged"] == 100
+    for side in ("upper", "lower"):
+        s = x[side]
+        assert len(s["cp"]) == len(s["cf"]) == len(s["x_stations"]) == 21
+        assert s["x_stations"][0] == 0.0 and s["x_stations"][-1] == 1.0
+    # stagnation on the lower side of the leading edge at positive incidence: the
+    # suction peak is on the upper surface
+    assert x["upper"]["cp_min"] < x["lower"]["cp_min"]
