@@ -249,9 +249,11 @@ def _fp32_vs_oracle(aoa_deg=6.0, steps=1500):
 
 
 def test_fp32_shifted_drag_and_state():
-    """FP32 shifted populations, FP64 forces: time-averaged C_D within 1e-4 of the FP64 oracle."""
+    """FP32 shifted populations, FP64 forces: time-averaged C_D within 1e-4 of the FP64 oracle
+    (measured 1e-8; the bar of 1e-6 catches a systematic FP32 bias such as rounded weights
+    or unrepaired collision residuals, which gave 6e-6 to 6e-5 here)."""
     dcd, dcl, sim, ref = _fp32_vs_oracle()
-    assert dcd < 1e-4
+    assert dcd < 1e-6
     # the populations themselves: ~1e-5 of the FP64 state after 1500 steps (FP32
     # rounding of the shifted populations, accumulated over 1500 x 17 sub-steps)
     assert rel(sim.get_state(hlbm.PART_MESH), ref.get_mesh()) < 5e-5
@@ -259,9 +261,10 @@ def test_fp32_shifted_drag_and_state():
 
 
 def test_fp32_shifted_lift():
-    """Time-averaged C_L within 1e-4 (relative to max(|C_L|, C_D)) of the FP64 oracle."""
+    """Time-averaged C_L within 1e-4 (relative to max(|C_L|, C_D)) of the FP64 oracle
+    (measured 4.4e-6; asserted at 2e-5)."""
     dcd, dcl, sim, ref = _fp32_vs_oracle()
-    assert dcl < 1e-4
+    assert dcl < 2e-5
 
 
 def test_nonfinite_detection():
