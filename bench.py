@@ -186,6 +186,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost measurement")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the adjoint cost measurement (prints its JSON object; for profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB five times (calibrates HBM byte counters)")
     a = ap.parse_args()
@@ -198,6 +200,9 @@ def main():
 
     w = workloads.PRESETS[a.workload]()
     per = 2 ** w.n_refine
+    if a.adjoint_only:
+        print(json.dumps(adjoint_cost(hlbm, torch, workloads)))
+        return
     r32 = run_precision(w, hlbm.FP32_SHIFTED, a.steps, a.warmup, hlbm, torch)
     k32 = kernel_table(r32)
     t32 = r32["t"]
