@@ -123,6 +123,7 @@ void setup_views(hlbm_ctx* c) {
     m.maxl = p.fv_maxl;
     m.maxw = p.fv_maxw;
     m.tile = p.fv_tile;
+    m.threads = p.fv_threads;
     m.ft_meta = reinterpret_cast<const int32_t*>(c->ws + p.off.ft_meta);
     m.ft_node = reinterpret_cast<const int32_t*>(c->ws + p.off.ft_node);
     m.ft_edges = c->ws + p.off.ft_edges;

@@ -25,6 +25,7 @@ constexpr int kUDon = 9;     // donors of a mesh interpolation node (3 x 3 block
 constexpr int kMacro = 12;   // (rho or rho - rho0, ux, uy, f^neq[9])
 constexpr int kRec = 12;
 constexpr int kTileMeta = 8;   // ints per fused-FV tile: node off, edge off, width, n_le[0..4]
+constexpr int kFvStage = 2;    // nodes per thread of a fused FV sub-step (results held in registers)
 constexpr int kMaxFuse = 4;
 constexpr int kAdjRec = 10;   // doubles per mesh node of the adjoint fields (9 used)     // mesh node record: f_0..f_8, rho (or rho - rho0), ux, uy
 
@@ -70,7 +71,8 @@ struct Plan {
     // nodes, each with the rings of neighbours that fv_fuse Jacobi sub-steps
     // reach; per tile kTileMeta ints {node offset, edge offset, edge-table
     // width, n_le[0..fv_fuse]} with n_le[r] = local nodes within ring r
-    int fv_fuse = 1, fv_tile = 256, fv_maxl = 0, fv_maxw = 0, n_tiles = 0;
+    // fv_threads: workgroup size of the fused kernel, at least fv_maxw / kFvStage
+    int fv_fuse = 1, fv_tile = 256, fv_threads = 256, fv_maxl = 0, fv_maxw = 0, n_tiles = 0;
     std::vector<int32_t> ft_meta, ft_node;
     std::vector<int32_t> ft_col;         // local column per (slot, computed node) of each tile
     std::vector<int32_t> ft_src;         // index into col / gx / gy / cc of that entry, -1 = unused
@@ -134,7 +136,8 @@ struct KMesh {
     int wall_bc;
     double rho0;
     // fused sub-steps (fuse > 1): tile tables and the LDS size they need
-    int fuse, n_sub, n_tiles, maxl, maxw, tile;   // maxw: largest edge-table width (second LDS buffer)
+    int fuse, n_sub, n_tiles, maxl, maxw, tile;   // maxw: largest edge-table width (nodes of sub-step 1)
+    int threads;                                  // workgroup size, kFvStage * threads >= maxw
     const int32_t* ft_meta;
     const int32_t* ft_node;
     const void* ft_edges;

@@ -772,41 +772,64 @@ __global__ __launch_bounds__(256) void k_fv_substep(const KMesh M, const T* __re
 // Several FV sub-steps in one launch (temporal blocking).  One workgroup per
 // tile of mesh nodes: it loads the records of the tile and of the rings of
 // neighbours around it into LDS, takes sub-step j (j = 1..k) on the tile and
-// rings 1..k-j (ping-pong between two LDS buffers), and writes only the
-// tile's records after sub-step k.  The rings are recomputed by every tile
+// rings 1..k-j, and writes only the tile's records after sub-step k.  Each
+// thread updates nodes tid and tid + blockDim (the host sizes the workgroup
+// so that these cover every updated node) and holds their new records in
+// registers until all reads of the sub-step are done, then writes them back
+// in place: one LDS buffer per tile, so that a 264k-node mesh fits the chip
+// in a single wave of workgroups.  The rings are recomputed by every tile
 // that borders them, so each sub-step is exactly the Jacobi update of
 // k_fv_substep, in the same operation order, while HBM sees the records
 // and edge coefficients once per k sub-steps.  Tile tables: see
 // build_fv_tiles.
+// Waves per SIMD the fused kernel is compiled for: three in FP32 with 8 slots
+// (at most 168 VGPRs), so that three workgroups of 256 threads share a CU.
+template <typename T, int W> struct FvFusedWaves { static constexpr int value = sizeof(T) == 4 && W == 8 ? 3 : 1; };
+
 template <typename T, bool SHIFT, int W>
-__global__ __launch_bounds__(256) void k_fv_fused(const KMesh M, const T* __restrict__ fin, T* __restrict__ fout,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWaves<T, W>::value))) void k_fv_fused(const KMesh M, const T* __restrict__ fin, T* __restrict__ fout,
                                                   const T* __restrict__ prep0, const T* __restrict__ prep1, int m0,
                                                   int ksteps) {
     extern __shared__ __align__(16) unsigned char smem[];
-    T* const buf0 = reinterpret_cast<T*>(smem);
-    T* const buf1 = buf0 + size_t(M.maxl) * kRec;       // holds at most the updated nodes (maxw)
-    int32_t* const gid = reinterpret_cast<int32_t*>(buf1 + size_t(M.maxw) * kRec);
+    T* const buf = reinterpret_cast<T*>(smem);
+    int32_t* const gid = reinterpret_cast<int32_t*>(buf + size_t(M.maxl) * kRec);
     const int t = die_block(blockIdx.x, gridDim.x);
     const int32_t* meta = M.ft_meta + size_t(t) * kTileMeta;
     const int noff = meta[0], eoff = meta[1], width = meta[2];
     const int nload = meta[3 + ksteps];
     const EdgeRec<T>* __restrict__ E = reinterpret_cast<const EdgeRec<T>*>(M.ft_edges) + eoff;
     const T rho0 = T(M.rho0), cst = T(M.star_neq);
-    for (int i = threadIdx.x; i < nload; i += blockDim.x) {
-        const int P = M.ft_node[noff + i];
-        gid[i] = P;
-        T f[9], m0r, ux, uy;
-        load_rec(fin + size_t(P) * kRec, f, m0r, ux, uy);
-        store_rec(buf0 + size_t(i) * kRec, f, m0r, ux, uy);
+    // records of the tile and its rings: all loads of a batch in flight together
+    constexpr int kBatch = 3;
+    for (int i0 = 0; i0 < nload; i0 += kBatch * int(blockDim.x)) {
+        int P[kBatch];
+        T f[kBatch][9], mm[kBatch][3];
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r) {
+            const int i = i0 + r * int(blockDim.x) + int(threadIdx.x);
+            P[r] = i < nload ? M.ft_node[noff + i] : -1;
+        }
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r)
+            if (P[r] >= 0) load_rec(fin + size_t(P[r]) * kRec, f[r], mm[r][0], mm[r][1], mm[r][2]);
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r) {
+            const int i = i0 + r * int(blockDim.x) + int(threadIdx.x);
+            if (P[r] < 0) continue;
+            gid[i] = P[r];
+            store_rec(buf + size_t(i) * kRec, f[r], mm[r][0], mm[r][1], mm[r][2]);
+        }
     }
     __syncthreads();
-    const T* src = buf0;
-    T* dst = buf1;
     for (int j = 1; j <= ksteps; ++j) {
         const int ncomp = meta[3 + ksteps - j];
         const T theta = T(double(m0 + j - 1) / double(M.n_sub));
         const bool last = j == ksteps;
-        for (int i = threadIdx.x; i < ncomp; i += blockDim.x) {
+        T res[kFvStage][9], rm[kFvStage][3];
+#pragma unroll
+        for (int s2 = 0; s2 < kFvStage; ++s2) {
+            const int i = int(threadIdx.x) + s2 * int(blockDim.x);
+            if (i >= ncomp) break;
             EdgeRec<T> e[W];
 #pragma unroll
             for (int z = 0; z < W; ++z) e[z] = E[size_t(z) * width + i];
@@ -823,17 +846,25 @@ __global__ __launch_bounds__(256) void k_fv_fused(const KMesh M, const T* __rest
                     const size_t sl = size_t(k - M.n_core) * kMacro;
                     star_values<T, SHIFT>(prep0 + sl, prep1 + sl, theta, cst, rho0, f, nq);
                 } else {
-                    load_rec(src + size_t(e[z].col) * kRec, f, mk, uxk, uyk);
+                    load_rec(buf + size_t(e[z].col) * kRec, f, mk, uxk, uyk);
                 }
                 fv_add<T, SHIFT>(A, z, f, star, nq, mk, uxk, uyk, e[z].gx, e[z].gy, e[z].c, rho0);
             }
-            T fn[9], r, dr, ux, uy;
-            fv_finish<T, SHIFT>(M, P, A, fn, r, dr, ux, uy);
-            store_rec((last ? fout + size_t(P) * kRec : dst + size_t(i) * kRec), fn, SHIFT ? dr : r, ux, uy);
+            T r, dr;
+            fv_finish<T, SHIFT>(M, P, A, res[s2], r, dr, rm[s2][1], rm[s2][2]);
+            rm[s2][0] = SHIFT ? dr : r;
+            if (last) store_rec(fout + size_t(P) * kRec, res[s2], rm[s2][0], rm[s2][1], rm[s2][2]);
+            __builtin_amdgcn_sched_barrier(0);   // one node at a time: registers for occupancy
         }
-        __syncthreads();
-        src = dst;
-        dst = dst == buf1 ? buf0 : buf1;
+        if (!last) {
+            __syncthreads();   // every read of this sub-step is done
+#pragma unroll
+            for (int s2 = 0; s2 < kFvStage; ++s2) {
+                const int i = int(threadIdx.x) + s2 * int(blockDim.x);
+                if (i < ncomp) store_rec(buf + size_t(i) * kRec, res[s2], rm[s2][0], rm[s2][1], rm[s2][2]);
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -988,8 +1019,9 @@ void launch_fv_fused(int prec, const KMesh& M, const void* fin, void* fout, cons
                      int m0, int k, hipStream_t s) {
     if (M.n_tiles <= 0 || k < 1 || k > M.fuse) return;
     const size_t elem = prec == HLBM_FP64 ? 8 : 4;
-    const size_t lds = size_t(M.maxl + M.maxw) * kRec * elem + size_t(M.maxl) * 4;
-    const unsigned threads = unsigned(M.tile);
+    const size_t lds = size_t(M.maxl) * (kRec * elem + 4);
+    const unsigned threads = unsigned(M.threads);
+    if (size_t(M.maxw) > size_t(kFvStage) * threads || threads > 256) return;   // rejected by the plan
     if (M.ell_width <= 8) {
         HLBM_DISPATCH(prec, (k_fv_fused<T, S, 8><<<M.n_tiles, threads, lds, s>>>(M, (const T*)fin, (T*)fout, (const T*)prep0,
                                                                                   (const T*)prep1, m0, k)));

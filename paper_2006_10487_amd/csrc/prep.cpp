@@ -475,6 +475,17 @@ template <class S> int lagrange9(S x, S y, bool linear, int* di, int* dj, S* w) 
 constexpr int kFvFuse = 2;
 constexpr int kFvFuseMinNodes = 100000;
 
+// Fused-kernel tiles (plan nodes) and workgroup sizes.  A launch is fastest
+// when all of its workgroups are resident at once: the kernel then takes about
+// one workgroup lifetime, and a partial second wave of workgroups doubles it
+// (measured on MI355X, 264k-node mesh, two FP32 sub-steps per launch: 787
+// tiles of 336 nodes 30.8 us, 768 tiles of 344-368 nodes 22.8 us; 3 blocks of
+// 256 threads per CU x 256 CUs = 768 resident).  FP32 tiles are therefore sized
+// so that the tiles fill a whole number of such waves.
+constexpr int kFvCUs = 256;                          // compute units of an MI355X
+constexpr int kFvThreadsF32 = 256, kFvTileMinF32 = 192, kFvTileMaxF32 = 368;
+constexpr int kFvTileF64 = 128, kFvThreadsF64 = 128;
+
 // Tiles for the fused finite-volume kernel, which takes several Jacobi
 // sub-steps per launch out of LDS.  Plan nodes are grouped into tiles of at
 // most `tile` nodes grown breadth-first over the mesh graph (compact tiles,
@@ -564,6 +575,27 @@ void build_fv_tiles(Plan& p, int tile, int fuse) {
             }
         p.fv_maxl = std::max(p.fv_maxl, int(nodes.size()));
         p.fv_maxw = std::max(p.fv_maxw, width);
+    }
+}
+
+// Resident fused-FV workgroups per CU in FP32: three at 8 slots (168 VGPRs),
+// two at 16.
+int fv_blocks_per_cu_f32(int ell_width) { return ell_width <= 8 ? 3 : 2; }
+
+void choose_fv_tiles(Plan& p, int fuse) {
+    if (p.elem == 8) {
+        build_fv_tiles(p, kFvTileF64, fuse);
+        return;
+    }
+    const int64_t slots = int64_t(kFvCUs) * fv_blocks_per_cu_f32(p.ell_width);
+    const int64_t waves = std::max<int64_t>(1, (p.nn + kFvTileMaxF32 * slots - 1) / (kFvTileMaxF32 * slots));
+    int tile = int((p.nn + waves * slots - 1) / (waves * slots));
+    tile = std::min(kFvTileMaxF32, std::max(kFvTileMinF32, (tile + 7) / 8 * 8));
+    build_fv_tiles(p, tile, fuse);
+    // breadth-first tiles come out partly smaller than `tile`: grow until they fit
+    while (p.n_tiles > waves * slots && tile + 8 <= kFvTileMaxF32) {
+        tile += 8;
+        build_fv_tiles(p, tile, fuse);
     }
 }
 
@@ -773,19 +805,19 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
                 p.wnorm.push_back(dy);
                 p.wnorm.push_back(-dx);
             }
-        // fused FV sub-steps: fv_fuse per launch when a tile with its rings,
-        // plus the nodes it updates (ping-pong), fit in 64 KB of LDS, else one
-        // kernel per sub-step
+        // fused FV sub-steps: fv_fuse per launch when a tile with its rings fits
+        // in 64 KB of LDS and a workgroup of at most 256 threads covers the
+        // nodes of sub-step 1 with kFvStage nodes per thread, else one kernel
+        // per sub-step
         if (g->fv_fuse < 0 || g->fv_fuse > kMaxFuse) return fail(err, HLBM_E_ARG, "fv_fuse must be 0..%d", kMaxFuse);
         const int fuse = g->fv_fuse > 0 ? g->fv_fuse : (p.elem == 4 && nn >= kFvFuseMinNodes ? kFvFuse : 1);
         p.fv_fuse = 1;
         if (fuse > 1) {
-            // tile sizes measured on MI355X (FP32: 192 nodes, 32.6 KB of LDS on the
-            // 264k-node mesh, 1-2% faster than 224 or 256; FP64 tiles of 128)
-            const int tile = p.elem == 8 ? 128 : 192;
-            build_fv_tiles(p, tile, fuse);
-            const size_t lds = size_t(p.fv_maxl + p.fv_maxw) * kRec * p.elem + size_t(p.fv_maxl) * 4;
-            if (lds > 65536) {
+            choose_fv_tiles(p, fuse);
+            const int need = (p.fv_maxw + kFvStage - 1) / kFvStage;
+            p.fv_threads = std::max(p.elem == 8 ? kFvThreadsF64 : kFvThreadsF32, (need + 63) / 64 * 64);
+            const size_t lds = size_t(p.fv_maxl) * (kRec * p.elem + 4);
+            if (lds > 65536 || p.fv_threads > 256) {
                 p.fv_fuse = 1;
                 p.n_tiles = 0;
                 p.ft_meta.clear();
