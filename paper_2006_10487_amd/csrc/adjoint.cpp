@@ -50,6 +50,7 @@ struct AdjState {
     } off{};
     bool tables = false, ran = false;
     std::vector<int32_t> t5map, t6map;   // transposed entry -> index into sint_w / uint_w
+    std::vector<int64_t> gmap;           // transposed FV slot z * nn + k -> forward slot z_P * nn + P, -1 = unused
     double J = 0.0;
     std::vector<double> cd, cl;
     // reverse-sweep state: current slot of each ping-pong pair
@@ -222,12 +223,14 @@ int upload_tables(hlbm_ctx* c, AdjState& a) {
         rows[P].insert(rows[P].begin(), TEnt{P, 0, sx, sy, ckk});
     }
     std::vector<char> te(size_t(W) * nn * 32, 0);
+    a.gmap.assign(size_t(W) * nn, -1);
     for (int k = 0; k < nn; ++k) {
         if (int(rows[k].size()) > W) return set_err(c, HLBM_E_GEOMETRY, "mesh connectivity is not symmetric");
         for (int z = 0; z < W; ++z) {
             char* r = te.data() + (size_t(z) * nn + k) * 32;
             const bool used = z < int(rows[k].size());
             const int32_t col = used ? rows[k][z].P : -1, zf = used ? rows[k][z].zf : 0;
+            if (used) a.gmap[size_t(z) * nn + k] = int64_t(zf) * nn + col;
             std::memcpy(r, &col, 4);
             std::memcpy(r + 4, &zf, 4);
             if (used) {
@@ -732,11 +735,12 @@ int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad, double* grad_xy) {
     grad[1] = J_bar * acc[1];
     if (a.obj.mesh_grad) {
         // coefficient adjoints -> mesh coordinates (host, forward mode per local coordinate)
-        std::vector<double> gb(size_t(3) * p.ell_width * p.nn), vb(size_t(2) * std::max(p.n_wall, 1));
+        std::vector<double> gt(size_t(3) * p.ell_width * p.nn), gb(gt.size(), 0.0);
+        std::vector<double> vb(size_t(2) * std::max(p.n_wall, 1));
         std::vector<double> gp(size_t(2) * p.nn);
         std::vector<double> t5(a.t5map.size()), t6(a.t6map.size());
         std::vector<double> w5(p.sint_w.size(), 0.0), w6(p.uint_w.size(), 0.0);
-        rc |= hip_check(c, hipMemcpyAsync(gb.data(), a.ws + a.off.gbar, gb.size() * 8, hipMemcpyDeviceToHost, s), "gbar");
+        rc |= hip_check(c, hipMemcpyAsync(gt.data(), a.ws + a.off.gbar, gt.size() * 8, hipMemcpyDeviceToHost, s), "gbar");
         rc |= hip_check(c, hipMemcpyAsync(vb.data(), a.ws + a.off.vbar, vb.size() * 8, hipMemcpyDeviceToHost, s), "vbar");
         rc |= hip_check(c, hipMemcpyAsync(gp.data(), a.ws + a.off.gpivot, gp.size() * 8, hipMemcpyDeviceToHost, s), "gpivot");
         if (!t5.empty())
@@ -745,6 +749,10 @@ int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad, double* grad_xy) {
             rc |= hip_check(c, hipMemcpyAsync(t6.data(), a.ws + a.off.w6bar, t6.size() * 8, hipMemcpyDeviceToHost, s), "w6bar");
         rc |= hip_check(c, hipStreamSynchronize(s), "mesh grad");
         if (rc) return HLBM_E_DEVICE;
+        // transposed slots -> forward ELL slots
+        for (size_t e = 0; e < a.gmap.size(); ++e)
+            if (a.gmap[e] >= 0)
+                for (int j = 0; j < 3; ++j) gb[size_t(a.gmap[e]) * 3 + j] = gt[e * 3 + j];
         // G_Pk adjoints of the difference form: neighbour part minus the pivot's base part
         for (int P = 0; P < p.nn; ++P)
             for (int z = 1; z < p.rowptr[P + 1] - p.rowptr[P]; ++z) {

@@ -281,12 +281,20 @@ void finest_step(hlbm_ctx* c) {
                                   c->ws + p.off.uint_w, c->prep(1 - c->prep_t), c->s);
         }
         if (c->sub_sink) {
+            // every sub-step's state to the sink (fused launches write their
+            // intermediate states there too)
             const void* in = c->mesh(c->mesh_cur);
-            for (int m = 0; m < p.n_sub; ++m) {
-                void* out = c->sub_sink + size_t(m) * c->sub_stride;
-                launch_fv_substep(pr, c->km, in, out, c->prep(c->prep_t), c->prep(1 - c->prep_t), double(m) / p.n_sub,
-                                  c->s);
+            for (int m = 0; m < p.n_sub;) {
+                const int k = std::min(p.fv_fuse, p.n_sub - m);
+                void* out = c->sub_sink + size_t(m + k - 1) * c->sub_stride;
+                if (k > 1)
+                    launch_fv_fused(pr, c->km, in, out, c->prep(c->prep_t), c->prep(1 - c->prep_t), m, k, c->s,
+                                    c->sub_sink + size_t(m) * c->sub_stride, c->sub_stride);
+                else
+                    launch_fv_substep(pr, c->km, in, out, c->prep(c->prep_t), c->prep(1 - c->prep_t),
+                                      double(m) / p.n_sub, c->s);
                 in = out;
+                m += k;
             }
             (void)hip_check(c, hipMemcpyAsync(c->mesh(c->mesh_cur), in, size_t(kRec) * p.nn * p.elem,
                                               hipMemcpyDeviceToDevice, c->s), "sub-step states");

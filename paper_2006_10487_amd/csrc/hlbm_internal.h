@@ -163,9 +163,11 @@ void launch_struct_to_mesh(int prec, const KLevel& fine, const void* fineA, int 
                            const void* w, void* prep, hipStream_t s);
 void launch_fv_substep(int prec, const KMesh& M, const void* fin, void* fout, const void* prep0,
                        const void* prep1, double theta, hipStream_t s);
-// k = 1..M.fuse sub-steps m0 .. m0 + k - 1 in one launch (tiles with halos in LDS)
+// k = 1..M.fuse sub-steps m0 .. m0 + k - 1 in one launch (tiles with halos in LDS);
+// with mid set, also the states after sub-steps m0 .. m0 + k - 2 at
+// mid + j * mid_stride_bytes (j = 0..k-2)
 void launch_fv_fused(int prec, const KMesh& M, const void* fin, void* fout, const void* prep0, const void* prep1,
-                     int m0, int k, hipStream_t s);
+                     int m0, int k, hipStream_t s, void* mid = nullptr, size_t mid_stride_bytes = 0);
 void launch_wall_stats(int prec, const void* f, int n_wall, const double* nrm, double rho0, double inv_q, double* sum,
                        hipStream_t s);
 void launch_wall_stats_final(int n_wall, const double* sum, const int32_t* slot, double n, double* out, hipStream_t s);
@@ -191,8 +193,9 @@ struct KAdj {
     double uin_x, uin_y, duin_x, duin_y;  // inlet velocity and d/d alpha
     double* partial;                 // per-block (d alpha, d tau) partial sums
     // adjoints of the mesh-geometry coefficients, accumulated over the run (null: not wanted)
-    double* gbar;                    // [ell_width][nn][3]: (G_x, G_y, C) of forward ELL slot z of pivot P
-                                     // (G parts without the pivot's base term, which is in gpivot)
+    double* gbar;                    // [ell_width][nn][3]: (G_x, G_y, C) of the entry in transposed slot z of
+                                     // node k (G parts without the pivot's base term, which is in gpivot);
+                                     // slot 0 = the pivot k itself, C only
     double* gpivot;                  // [nn][2]: Delta t_u sum_q zbar_Pq c_q base_Pq, per pivot
     double* vbar;                    // [n_wall][2]: half wall normals summed at each wall node
     double* w5bar;                   // eq. (4) weights, per entry of the transposed (donor-major) list
@@ -229,6 +232,9 @@ void launch_adj_side(const KLevel& P, int ci0, int cj0, int nxc, int nyc, const 
 void launch_reduce_partials(const double* partial, int n, double* acc, hipStream_t s);
 int adj_blocks_collide(const KLevel& L);
 int adj_fv_blocks(const KMesh& M);   // partial slots of one launch_adj_fv
+// workgroup size of the FV sub-step adjoint: small meshes are latency-bound,
+// and small workgroups spread them over more CUs
+constexpr int kAdjFvBlock = 64;
 int adj_blocks_nodes(int n);
 
 }  // namespace hlbm

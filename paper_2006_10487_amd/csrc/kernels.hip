@@ -781,7 +781,9 @@ __global__ __launch_bounds__(256) void k_fv_substep(const KMesh M, const T* __re
 // that borders them, so each sub-step is exactly the Jacobi update of
 // k_fv_substep, in the same operation order, while HBM sees the records
 // and edge coefficients once per k sub-steps.  Tile tables: see
-// build_fv_tiles.
+// build_fv_tiles.  With mid set, the state after each sub-step j < k is
+// written too, each tile its own nodes, to mid + (j - 1) * mid_stride (the
+// intermediate states that the discrete adjoint reads).
 // Waves per SIMD the fused kernel is compiled for: three in FP32 with 8 slots
 // (at most 168 VGPRs), so that three workgroups of 256 threads share a CU.
 template <typename T, int W> struct FvFusedWaves { static constexpr int value = sizeof(T) == 4 && W == 8 ? 3 : 1; };
@@ -789,14 +791,14 @@ template <typename T, int W> struct FvFusedWaves { static constexpr int value = 
 template <typename T, bool SHIFT, int W>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWaves<T, W>::value))) void k_fv_fused(const KMesh M, const T* __restrict__ fin, T* __restrict__ fout,
                                                   const T* __restrict__ prep0, const T* __restrict__ prep1, int m0,
-                                                  int ksteps) {
+                                                  int ksteps, T* __restrict__ mid, size_t mid_stride) {
     extern __shared__ __align__(16) unsigned char smem[];
     T* const buf = reinterpret_cast<T*>(smem);
     int32_t* const gid = reinterpret_cast<int32_t*>(buf + size_t(M.maxl) * kRec);
     const int t = die_block(blockIdx.x, gridDim.x);
     const int32_t* meta = M.ft_meta + size_t(t) * kTileMeta;
     const int noff = meta[0], eoff = meta[1], width = meta[2];
-    const int nload = meta[3 + ksteps];
+    const int nload = meta[3 + ksteps], ntile = meta[3];
     const EdgeRec<T>* __restrict__ E = reinterpret_cast<const EdgeRec<T>*>(M.ft_edges) + eoff;
     const T rho0 = T(M.rho0), cst = T(M.star_neq);
     // records of the tile and its rings: all loads of a batch in flight together
@@ -854,6 +856,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
             fv_finish<T, SHIFT>(M, P, A, res[s2], r, dr, rm[s2][1], rm[s2][2]);
             rm[s2][0] = SHIFT ? dr : r;
             if (last) store_rec(fout + size_t(P) * kRec, res[s2], rm[s2][0], rm[s2][1], rm[s2][2]);
+            else if (mid && i < ntile)
+                store_rec(mid + size_t(j - 1) * mid_stride + size_t(P) * kRec, res[s2], rm[s2][0], rm[s2][1], rm[s2][2]);
             __builtin_amdgcn_sched_barrier(0);   // one node at a time: registers for occupancy
         }
         if (!last) {
@@ -926,6 +930,11 @@ __global__ void k_mesh_export(int nn, const T* __restrict__ in, double* __restri
 }
 
 unsigned blocks(size_t n, unsigned b = 256) { return unsigned((n + b - 1) / b); }
+
+// Workgroup size of the one-sub-step FV kernel: 256 threads, or 64 when that
+// leaves fewer than two workgroups per CU (small meshes are latency-bound, and
+// more, smaller workgroups spread them over the chip).
+unsigned fv_substep_block(int nn) { return nn < 2 * 256 * 256 ? 64u : 256u; }
 
 }  // namespace
 
@@ -1006,17 +1015,18 @@ void launch_struct_to_mesh(int prec, const KLevel& F, const void* A, int n, cons
 
 void launch_fv_substep(int prec, const KMesh& M, const void* fin, void* fout, const void* prep0, const void* prep1,
                        double theta, hipStream_t s) {
+    const unsigned b = fv_substep_block(M.nn);
     if (M.ell_width <= 8) {
-        HLBM_DISPATCH(prec, (k_fv_substep<T, S, 8><<<blocks(M.nn), 256, 0, s>>>(M, (const T*)fin, (T*)fout, (const T*)prep0,
+        HLBM_DISPATCH(prec, (k_fv_substep<T, S, 8><<<blocks(M.nn, b), b, 0, s>>>(M, (const T*)fin, (T*)fout, (const T*)prep0,
                                                                                 (const T*)prep1, T(theta))));
     } else {
-        HLBM_DISPATCH(prec, (k_fv_substep<T, S, 16><<<blocks(M.nn), 256, 0, s>>>(M, (const T*)fin, (T*)fout, (const T*)prep0,
+        HLBM_DISPATCH(prec, (k_fv_substep<T, S, 16><<<blocks(M.nn, b), b, 0, s>>>(M, (const T*)fin, (T*)fout, (const T*)prep0,
                                                                                  (const T*)prep1, T(theta))));
     }
 }
 
 void launch_fv_fused(int prec, const KMesh& M, const void* fin, void* fout, const void* prep0, const void* prep1,
-                     int m0, int k, hipStream_t s) {
+                     int m0, int k, hipStream_t s, void* mid, size_t mid_stride_bytes) {
     if (M.n_tiles <= 0 || k < 1 || k > M.fuse) return;
     const size_t elem = prec == HLBM_FP64 ? 8 : 4;
     const size_t lds = size_t(M.maxl) * (kRec * elem + 4);
@@ -1024,10 +1034,12 @@ void launch_fv_fused(int prec, const KMesh& M, const void* fin, void* fout, cons
     if (size_t(M.maxw) > size_t(kFvStage) * threads || threads > 256) return;   // rejected by the plan
     if (M.ell_width <= 8) {
         HLBM_DISPATCH(prec, (k_fv_fused<T, S, 8><<<M.n_tiles, threads, lds, s>>>(M, (const T*)fin, (T*)fout, (const T*)prep0,
-                                                                                  (const T*)prep1, m0, k)));
+                                                                                  (const T*)prep1, m0, k, (T*)mid,
+                                                                 mid_stride_bytes / sizeof(T))));
     } else {
         HLBM_DISPATCH(prec, (k_fv_fused<T, S, 16><<<M.n_tiles, threads, lds, s>>>(M, (const T*)fin, (T*)fout, (const T*)prep0,
-                                                                                   (const T*)prep1, m0, k)));
+                                                                                   (const T*)prep1, m0, k, (T*)mid,
+                                                                 mid_stride_bytes / sizeof(T))));
     }
 }
 
@@ -1108,13 +1120,15 @@ __device__ __forceinline__ void macro_neq_adj(const D9& f, const double* a, D9& 
     macro_adj(rho, ux, uy, rb, uxb, uyb, fb);
 }
 
-// fixed-order block sum of (a, b) written to partial[2 * (slot + blockIdx.x)]
+// fixed-order block sum of (a, b) written to partial[2 * (slot + blockIdx.x)],
+// for blocks of B threads
+template <int B = 256>
 __device__ __forceinline__ void block_partial(double a, double b, double* partial, int slot) {
-    __shared__ double sa[256], sb[256];
+    __shared__ double sa[B], sb[B];
     sa[threadIdx.x] = a;
     sb[threadIdx.x] = b;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = B / 2; h > 0; h >>= 1) {
         if (int(threadIdx.x) < h) {
             sa[threadIdx.x] += sa[threadIdx.x + h];
             sb[threadIdx.x] += sb[threadIdx.x + h];
@@ -1274,7 +1288,8 @@ __global__ __launch_bounds__(256) void k_adj_fv_wall(const KAdj K, const double*
 // The adjoint of each pivot's update is ybar_P, or zwall_P after the no-slip
 // reset transpose at wall pivots.  tau enters through Delta t_u / tau_u and
 // 1 - 1/(2 tau); with K.gbar set, the coefficient adjoints of the entries
-// (P, k) are accumulated too (each entry has one column, so no conflicts): the
+// (P, k) are accumulated too, in the transposed slot of k (one writer per
+// slot, so no conflicts; consecutive k are consecutive in memory): the
 // neighbour part of G_Pk here, the pivot's base part once per pivot in gpivot.
 // With fin_prev set (the input of the previous sub-step), wall nodes also take
 // the no-slip reset transpose of that sub-step from the adjoint just computed,
@@ -1332,8 +1347,8 @@ __device__ __forceinline__ void adj_fv_gather(const KAdj& K, int k, bool k_inter
                     K.gbar[size_t(k) * 3 + 2] -= K.dtt * gc;
                     K.gpivot[2 * size_t(k)] += K.dt * gx;
                     K.gpivot[2 * size_t(k) + 1] += K.dt * gy;
-                } else {
-                    double* g = K.gbar + (size_t(e.pad) * nn + P) * 3;
+                } else {   // transposed slot z of k (coalesced); mapped to the forward slot on download
+                    double* g = K.gbar + (size_t(z) * nn + k) * 3;
                     g[0] += K.dt * gx;
                     g[1] += K.dt * gy;
                     g[2] -= K.dtt * gc;
@@ -1343,8 +1358,8 @@ __device__ __forceinline__ void adj_fv_gather(const KAdj& K, int k, bool k_inter
     }
 }
 
-template <int W>
-__global__ __launch_bounds__(256) void k_adj_fv(const KAdj K, const double* __restrict__ fin,
+template <int W, int B>
+__global__ __launch_bounds__(B) void k_adj_fv(const KAdj K, const double* __restrict__ fin,
                                                 const double* __restrict__ ybar, const double* __restrict__ zwall,
                                                 double* __restrict__ mbar, const double* __restrict__ prep0,
                                                 const double* __restrict__ prep1, double theta,
@@ -1403,7 +1418,7 @@ __global__ __launch_bounds__(256) void k_adj_fv(const KAdj K, const double* __re
             }
         }
     }
-    block_partial(0.0, dtau, K.partial, pslot);
+    block_partial<B>(0.0, dtau, K.partial, pslot);
 }
 
 // Collision adjoint (per collide-stream node x, edges included): with
@@ -1846,7 +1861,7 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
 
 int adj_blocks_collide(const KLevel& L) { return int(blocks(L.nx)) * L.ny; }
 int adj_blocks_nodes(int n) { return int(blocks(size_t(n > 0 ? n : 1))); }
-int adj_fv_blocks(const KMesh& M) { return adj_blocks_nodes(M.nn); }
+int adj_fv_blocks(const KMesh& M) { return int(blocks(size_t(M.nn > 0 ? M.nn : 1), kAdjFvBlock)); }
 
 void launch_zero(double* p, size_t n, hipStream_t s) {
     if (n) k_zero<<<blocks(n), 256, 0, s>>>(p, n);
@@ -1864,12 +1879,13 @@ void launch_adj_fv_wall(const KAdj& K, const double* Mrec, const double* ybar, d
 void launch_adj_fv(const KAdj& K, const double* Mrec, const double* ybar, const double* zwall, double* mbar,
                    const double* prep0, const double* prep1, double theta, double* p0bar, double* p1bar, int pslot,
                    const double* Mprev, double theta_prev, double* zwall_prev, hipStream_t s) {
+    const unsigned nb = unsigned(adj_fv_blocks(K.M));
     if (K.M.ell_width == 8)
-        k_adj_fv<8><<<adj_blocks_nodes(K.M.nn), 256, 0, s>>>(K, Mrec, ybar, zwall, mbar, prep0, prep1, theta, p0bar, p1bar,
-                                                            pslot, Mprev, theta_prev, zwall_prev);
+        k_adj_fv<8, kAdjFvBlock><<<nb, kAdjFvBlock, 0, s>>>(K, Mrec, ybar, zwall, mbar, prep0, prep1, theta, p0bar,
+                                                           p1bar, pslot, Mprev, theta_prev, zwall_prev);
     else
-        k_adj_fv<16><<<adj_blocks_nodes(K.M.nn), 256, 0, s>>>(K, Mrec, ybar, zwall, mbar, prep0, prep1, theta, p0bar,
-                                                             p1bar, pslot, Mprev, theta_prev, zwall_prev);
+        k_adj_fv<16, kAdjFvBlock><<<nb, kAdjFvBlock, 0, s>>>(K, Mrec, ybar, zwall, mbar, prep0, prep1, theta, p0bar,
+                                                            p1bar, pslot, Mprev, theta_prev, zwall_prev);
 }
 void launch_adj_collide(const KAdj& K, const double* A, const double* bbar, double* prebar, int pslot, hipStream_t s) {
     dim3 grid(blocks(K.L.nx), K.L.ny);

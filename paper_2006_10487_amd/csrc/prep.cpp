@@ -468,12 +468,12 @@ template <class S> int lagrange9(S x, S y, bool linear, int* di, int* dj, S* w) 
     return 4;
 }
 
-// Default FV sub-steps per launch: two for FP32 meshes of at least 100k nodes
-// (measured on MI355X: -4% per base step at 264k nodes), else one (at 33k
-// nodes the tiles' ring recomputation costs more than it saves, and FP64
-// tiles are LDS-bound).
+// Default FV sub-steps per launch: two on meshes with at most 8 neighbour
+// slots per node, else one.  Measured on MI355X, per sub-step, fused against
+// one launch per sub-step: FP32 11.2 against 13.9-14.8 us (264k nodes) and
+// 4.8 against 5.7 us (33k nodes); FP64 22.5 against 29.8 us and 6.2 against
+// 8.1 us.
 constexpr int kFvFuse = 2;
-constexpr int kFvFuseMinNodes = 100000;
 
 // Fused-kernel tiles (plan nodes) and workgroup sizes.  A launch is fastest
 // when all of its workgroups are resident at once: the kernel then takes about
@@ -484,7 +484,10 @@ constexpr int kFvFuseMinNodes = 100000;
 // so that the tiles fill a whole number of such waves.
 constexpr int kFvCUs = 256;                          // compute units of an MI355X
 constexpr int kFvThreadsF32 = 256, kFvTileMinF32 = 192, kFvTileMaxF32 = 368;
-constexpr int kFvTileF64 = 128, kFvThreadsF64 = 128;
+// FP64 (240 VGPRs, 2 waves per SIMD): tiles of 128 nodes on large meshes, down
+// to 64 so that a small mesh still gives about two tiles per CU (measured at
+// 33k nodes: 6.2 us per sub-step with 64, 7.6 with 128).
+constexpr int kFvThreadsF64 = 128, kFvTileMinF64 = 64, kFvTileMaxF64 = 128;
 
 // Tiles for the fused finite-volume kernel, which takes several Jacobi
 // sub-steps per launch out of LDS.  Plan nodes are grouped into tiles of at
@@ -584,7 +587,8 @@ int fv_blocks_per_cu_f32(int ell_width) { return ell_width <= 8 ? 3 : 2; }
 
 void choose_fv_tiles(Plan& p, int fuse) {
     if (p.elem == 8) {
-        build_fv_tiles(p, kFvTileF64, fuse);
+        const int tile = std::max(kFvTileMinF64, std::min(kFvTileMaxF64, p.nn / (2 * kFvCUs) / 8 * 8));
+        build_fv_tiles(p, tile, fuse);
         return;
     }
     const int64_t slots = int64_t(kFvCUs) * fv_blocks_per_cu_f32(p.ell_width);
@@ -810,7 +814,7 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
         // nodes of sub-step 1 with kFvStage nodes per thread, else one kernel
         // per sub-step
         if (g->fv_fuse < 0 || g->fv_fuse > kMaxFuse) return fail(err, HLBM_E_ARG, "fv_fuse must be 0..%d", kMaxFuse);
-        const int fuse = g->fv_fuse > 0 ? g->fv_fuse : (p.elem == 4 && nn >= kFvFuseMinNodes ? kFvFuse : 1);
+        const int fuse = g->fv_fuse > 0 ? g->fv_fuse : (p.ell_width <= 8 ? kFvFuse : 1);
         p.fv_fuse = 1;
         if (fuse > 1) {
             choose_fv_tiles(p, fuse);
