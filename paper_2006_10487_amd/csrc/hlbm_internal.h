@@ -235,6 +235,7 @@ int adj_fv_blocks(const KMesh& M);   // partial slots of one launch_adj_fv
 // workgroup size of the FV sub-step adjoint: small meshes are latency-bound,
 // and small workgroups spread them over more CUs
 constexpr int kAdjFvBlock = 64;
+constexpr int kAdjFvSimds = 1024;   // SIMDs of an MI355X (256 CUs x 4)
 int adj_blocks_nodes(int n);
 
 }  // namespace hlbm

@@ -1299,19 +1299,18 @@ __global__ __launch_bounds__(256) void k_adj_fv_wall(const KAdj K, const double*
 // or the star value of an interpolation node (STAR = true: interpolation
 // pivots).  Accumulates into vb (adjoint of the value), nb (of its f^neq part)
 // and, with K.gbar, the coefficient adjoints of the entries read.
-template <int W, bool STAR>
+template <int W, bool STAR, int G>
 __device__ __forceinline__ void adj_fv_gather(const KAdj& K, int k, bool k_interp, const double* __restrict__ ybar,
                                               const double* __restrict__ zwall, const D9& val, const D9& nval, D9& vb,
-                                              D9& nb) {
+                                              D9& nb, int z_begin = 0) {
     const KMesh& M = K.M;
     const int nn = M.nn;
     const int nwall = M.wall_bc ? M.n_wall : 0;
     const EdgeRec<double>* T = reinterpret_cast<const EdgeRec<double>*>(K.tedges);
-    // slots in pairs: both table entries, then both pivot adjoints are loaded
-    // before the arithmetic
-    constexpr int G = 2;
+    // slots in groups of G: the G table entries, then the G pivot adjoints are
+    // loaded before the arithmetic
 #pragma unroll 1
-    for (int g0 = 0; g0 < W; g0 += G) {
+    for (int g0 = z_begin; g0 < z_begin + W; g0 += G) {
         EdgeRec<double> eg[G];
         double zg[G][9];
 #pragma unroll
@@ -1358,7 +1357,7 @@ __device__ __forceinline__ void adj_fv_gather(const KAdj& K, int k, bool k_inter
     }
 }
 
-template <int W, int B>
+template <int W, int B, int G>
 __global__ __launch_bounds__(B) void k_adj_fv(const KAdj K, const double* __restrict__ fin,
                                                 const double* __restrict__ ybar, const double* __restrict__ zwall,
                                                 double* __restrict__ mbar, const double* __restrict__ prep0,
@@ -1378,7 +1377,7 @@ __global__ __launch_bounds__(B) void k_adj_fv(const KAdj K, const double* __rest
             equilibrium<double, false>(m0, m0, ux, uy, feq);
 #pragma unroll
             for (int q = 0; q < 9; ++q) nq[q] = f[q] - feq[q], vb[q] = nqb[q] = 0.0;
-            adj_fv_gather<W, false>(K, k, k_interp, ybar, zwall, f, nq, vb, nqb);
+            adj_fv_gather<W, false, G>(K, k, k_interp, ybar, zwall, f, nq, vb, nqb);
             double a12[12] = {0.0, 0.0, 0.0};
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
@@ -1399,7 +1398,7 @@ __global__ __launch_bounds__(B) void k_adj_fv(const KAdj K, const double* __rest
             star64(prep0 + sl, prep1 + sl, theta, K.cst, v, fs, ns);
 #pragma unroll
             for (int q = 0; q < 9; ++q) fsb[q] = nsb[q] = 0.0;
-            adj_fv_gather<W, true>(K, k, true, ybar, zwall, fs, ns, fsb, nsb);
+            adj_fv_gather<W, true, G>(K, k, true, ybar, zwall, fs, ns, fsb, nsb);
             // fs = feq(v0, v1, v2) + cst v[3..], ns = cst v[3..]
             double rb = 0.0, uxb = 0.0, uyb = 0.0, w12[12], dcst = 0.0;
             feq_adj(v[0], v[1], v[2], fsb, rb, uxb, uyb);
@@ -1415,6 +1414,92 @@ __global__ __launch_bounds__(B) void k_adj_fv(const KAdj K, const double* __rest
             for (int m = 0; m < 12; ++m) {
                 p0bar[sl + m] += (1.0 - theta) * w12[m];
                 p1bar[sl + m] += theta * w12[m];
+            }
+        }
+    }
+    block_partial<B>(0.0, dtau, K.partial, pslot);
+}
+
+// Sum of a double over the two lanes of a pair (DPP quad_perm 1,0,3,2): both
+// lanes get the same bits, the addition being commutative.  Both lanes of the
+// pair must be active.
+__device__ __forceinline__ double pair_sum(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int lo2 = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);
+    const int hi2 = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
+    return v + __hiloint2double(hi2, lo2);
+}
+
+// k_adj_fv on small 8-slot meshes, two lanes per node: lane h of node k
+// gathers slots 4h..4h+3 (one round of four table entries, then four pivot
+// adjoints), the two partial sums are added with pair_sum, and lane 0 finishes
+// the node.  The same terms as k_adj_fv, with the slot sum split in two halves.
+template <int B>
+__global__ __launch_bounds__(B) void k_adj_fv2(const KAdj K, const double* __restrict__ fin,
+                                                const double* __restrict__ ybar, const double* __restrict__ zwall,
+                                                double* __restrict__ mbar, const double* __restrict__ prep0,
+                                                const double* __restrict__ prep1, double theta,
+                                                double* __restrict__ p0bar, double* __restrict__ p1bar, int pslot,
+                                                const double* __restrict__ fin_prev, double theta_prev,
+                                                double* __restrict__ zwall_prev) {
+    const KMesh& M = K.M;
+    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = gt >> 1, h = gt & 1;   // lanes 2k, 2k + 1: slots 0-3, 4-7 of node k
+    double dtau = 0.0;
+    if (k < M.nn) {
+        const bool k_interp = k >= M.n_core;
+        const double rdt = K.ddtt_dtau / K.dtt;
+        {   // the stored value M^m_k
+            double f[9], m0, ux, uy, feq[9], nq[9], vb[9], nqb[9];
+            load_rec(fin + size_t(k) * kRec, f, m0, ux, uy);
+            equilibrium<double, false>(m0, m0, ux, uy, feq);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) nq[q] = f[q] - feq[q], vb[q] = nqb[q] = 0.0;
+            adj_fv_gather<4, false, 4>(K, k, k_interp, ybar, zwall, f, nq, vb, nqb, 4 * h);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) vb[q] = pair_sum(vb[q]), nqb[q] = pair_sum(nqb[q]);
+            if (h == 0) {
+            double a12[12] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                dtau += rdt * nq[q] * nqb[q];
+                a12[3 + q] = nqb[q];
+            }
+            macro_neq_adj(f, a12, vb);
+            store_adj(mbar + size_t(k) * kAdjRec, vb);
+            if (fin_prev && k < (M.wall_bc ? M.n_wall : 0)) {
+                double zb[9];
+                wall_reset_adj(K, fin_prev, prep0, prep1, theta_prev, k, vb, zb);
+                store_adj(zwall_prev + size_t(k) * kAdjRec, zb);
+            }
+            }
+        }
+        if (k_interp) {   // the star value f*_k read by interpolation pivots
+            const size_t sl = size_t(k - M.n_core) * kMacro;
+            double v[12], fs[9], ns[9], fsb[9], nsb[9];
+            star64(prep0 + sl, prep1 + sl, theta, K.cst, v, fs, ns);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) fsb[q] = nsb[q] = 0.0;
+            adj_fv_gather<4, true, 4>(K, k, true, ybar, zwall, fs, ns, fsb, nsb, 4 * h);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) fsb[q] = pair_sum(fsb[q]), nsb[q] = pair_sum(nsb[q]);
+            if (h == 0) {
+            // fs = feq(v0, v1, v2) + cst v[3..], ns = cst v[3..]
+            double rb = 0.0, uxb = 0.0, uyb = 0.0, w12[12], dcst = 0.0;
+            feq_adj(v[0], v[1], v[2], fsb, rb, uxb, uyb);
+            w12[0] = rb, w12[1] = uxb, w12[2] = uyb;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                w12[3 + q] = K.cst * (fsb[q] + nsb[q]);
+                dcst += (fsb[q] + nsb[q]) * v[3 + q];
+                dtau += rdt * ns[q] * nsb[q];
+            }
+            dtau += dcst * K.dcst_dtau;
+#pragma unroll
+            for (int m = 0; m < 12; ++m) {
+                p0bar[sl + m] += (1.0 - theta) * w12[m];
+                p1bar[sl + m] += theta * w12[m];
+            }
             }
         }
     }
@@ -1861,7 +1946,15 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
 
 int adj_blocks_collide(const KLevel& L) { return int(blocks(L.nx)) * L.ny; }
 int adj_blocks_nodes(int n) { return int(blocks(size_t(n > 0 ? n : 1))); }
-int adj_fv_blocks(const KMesh& M) { return int(blocks(size_t(M.nn > 0 ? M.nn : 1), kAdjFvBlock)); }
+// the FV sub-step adjoint takes two lanes per node (k_adj_fv2) on 8-slot
+// meshes that give at most one wave per SIMD at one node per lane
+bool adj_fv_two_lanes(const KMesh& M) {
+    return M.ell_width == 8 && size_t(M.nn) <= size_t(kAdjFvSimds) * kAdjFvBlock;
+}
+int adj_fv_blocks(const KMesh& M) {
+    const size_t n = M.nn > 0 ? size_t(M.nn) : 1;
+    return int(blocks(adj_fv_two_lanes(M) ? 2 * n : n, kAdjFvBlock));
+}
 
 void launch_zero(double* p, size_t n, hipStream_t s) {
     if (n) k_zero<<<blocks(n), 256, 0, s>>>(p, n);
@@ -1879,13 +1972,22 @@ void launch_adj_fv_wall(const KAdj& K, const double* Mrec, const double* ybar, d
 void launch_adj_fv(const KAdj& K, const double* Mrec, const double* ybar, const double* zwall, double* mbar,
                    const double* prep0, const double* prep1, double theta, double* p0bar, double* p1bar, int pslot,
                    const double* Mprev, double theta_prev, double* zwall_prev, hipStream_t s) {
+    // Small 8-slot meshes (at most one wave per SIMD of one node per lane) take
+    // two lanes per node, so each lane waits on one round of dependent loads;
+    // measured on the 33k-node bump workload, (objective + adjoint)/forward:
+    // 4.43, against 4.55 with one lane per node and slot groups of four and
+    // 4.68 with pairs.  Larger meshes: one lane per node, slots in pairs (236
+    // VGPRs, two waves per SIMD).
     const unsigned nb = unsigned(adj_fv_blocks(K.M));
-    if (K.M.ell_width == 8)
-        k_adj_fv<8, kAdjFvBlock><<<nb, kAdjFvBlock, 0, s>>>(K, Mrec, ybar, zwall, mbar, prep0, prep1, theta, p0bar,
-                                                           p1bar, pslot, Mprev, theta_prev, zwall_prev);
+    if (adj_fv_two_lanes(K.M))
+        k_adj_fv2<kAdjFvBlock><<<nb, kAdjFvBlock, 0, s>>>(K, Mrec, ybar, zwall, mbar, prep0, prep1, theta, p0bar,
+                                                              p1bar, pslot, Mprev, theta_prev, zwall_prev);
+    else if (K.M.ell_width == 8)
+        k_adj_fv<8, kAdjFvBlock, 2><<<nb, kAdjFvBlock, 0, s>>>(K, Mrec, ybar, zwall, mbar, prep0, prep1, theta, p0bar,
+                                                              p1bar, pslot, Mprev, theta_prev, zwall_prev);
     else
-        k_adj_fv<16, kAdjFvBlock><<<nb, kAdjFvBlock, 0, s>>>(K, Mrec, ybar, zwall, mbar, prep0, prep1, theta, p0bar,
-                                                            p1bar, pslot, Mprev, theta_prev, zwall_prev);
+        k_adj_fv<16, kAdjFvBlock, 2><<<nb, kAdjFvBlock, 0, s>>>(K, Mrec, ybar, zwall, mbar, prep0, prep1, theta, p0bar,
+                                                               p1bar, pslot, Mprev, theta_prev, zwall_prev);
 }
 void launch_adj_collide(const KAdj& K, const double* A, const double* bbar, double* prebar, int pslot, hipStream_t s) {
     dim3 grid(blocks(K.L.nx), K.L.ny);

@@ -68,6 +68,24 @@ def test_adjoint_matches_finite_differences():
     assert abs(g[1] - fd_t) < 1e-5 * max(1.0, abs(fd_t))
 
 
+def test_adjoint_large_mesh_matches_finite_differences():
+    """Meshes of more than 65,536 nodes take the one-lane-per-node FV adjoint
+    (smaller ones two lanes per node); central differences of the GPU forward
+    on a 133k-node mesh check that path."""
+    w = W.naca_re1000_c128(3.0, ns=2048)
+    assert w.mesh_xy.shape[0] > 65536
+    spec = dict(t_end=40, t0=20, t1=40, ckpt_every=20, w_cd=1.0, w_cl=0.0)
+    a0, t0 = w.aoa_rad, w.tau_s
+    _, sim = gpu_J(w, a0, t0, n_sub=w.n_sub, spec=spec)
+    g = sim.adjoint(1.0)
+    ha, ht = 1e-6, 1e-7
+    fd_a = (gpu_J(w, a0 + ha, t0, w.n_sub, spec)[0] - gpu_J(w, a0 - ha, t0, w.n_sub, spec)[0]) / (2 * ha)
+    fd_t = (gpu_J(w, a0, t0 + ht, w.n_sub, spec)[0] - gpu_J(w, a0, t0 - ht, w.n_sub, spec)[0]) / (2 * ht)
+    print(f"adjoint {g}  gpu FD [{fd_a:.10g}, {fd_t:.10g}]", flush=True)
+    assert abs(g[0] - fd_a) < 1e-6 * max(1.0, abs(fd_a))
+    assert abs(g[1] - fd_t) < 1e-5 * max(1.0, abs(fd_t))
+
+
 def test_adjoint_lift_objective_and_symmetry():
     """alpha = 0: dC_D/dalpha vanishes by mirror symmetry; the lift slope matches the oracle."""
     w = W.naca_re100_c40(0.0)
