@@ -74,8 +74,8 @@ typedef struct {
     int32_t history_len;          /* force history ring length, 0 = 65536                            */
     int32_t fv_fuse;              /* FV sub-steps per launch, 1..4 (falls back to 1 when a tile of
                                      mesh nodes and its halo do not fit in 64 KB of LDS or need more
-                                     than 512 updated nodes per tile); 0 = 2 for
-                                     FP32 meshes of >= 100k nodes, else 1.  Results do not depend on
+                                     than 512 updated nodes per tile); 0 = 2 on meshes with at most
+                                     8 neighbour slots per node, else 1.  Results do not depend on
                                      it (same arithmetic, same order)                                */
 } hlbm_grid;
 

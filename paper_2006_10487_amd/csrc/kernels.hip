@@ -1928,14 +1928,30 @@ __global__ void k_adj_side(const KLevel P, int ci0, int cj0, int nxc, int nyc, c
     for (int q = 0; q < 9; ++q) prebar[size_t(q) * P.pitch + base] += fb[q];
 }
 
-__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partial, int n, double* acc) {
-    __shared__ double sa[256], sb[256];
-    double a = 0.0, b = 0.0;
-    for (int k = threadIdx.x; k < n; k += 256) a += partial[2 * k], b += partial[2 * k + 1];
-    sa[threadIdx.x] = a;
-    sb[threadIdx.x] = b;
+// One block adds the n partial pairs to acc in a fixed order: thread t sums
+// slots t + j * kRedThreads into four accumulators by j mod 4 (four loads in
+// flight), then the accumulators and the threads are added in a fixed tree.
+constexpr int kRedThreads = 1024;
+__global__ __launch_bounds__(kRedThreads) void k_reduce_partials(const double* __restrict__ partial, int n,
+                                                                 double* acc) {
+    __shared__ double sa[kRedThreads], sb[kRedThreads];
+    double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = threadIdx.x;
+    for (; k + 3 * kRedThreads < n; k += 4 * kRedThreads) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            a[j] += partial[2 * size_t(k + j * kRedThreads)];
+            b[j] += partial[2 * size_t(k + j * kRedThreads) + 1];
+        }
+    }
+    for (int j = 0; k < n; k += kRedThreads, ++j) {
+        a[j] += partial[2 * size_t(k)];
+        b[j] += partial[2 * size_t(k) + 1];
+    }
+    sa[threadIdx.x] = (a[0] + a[1]) + (a[2] + a[3]);
+    sb[threadIdx.x] = (b[0] + b[1]) + (b[2] + b[3]);
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = kRedThreads / 2; h > 0; h >>= 1) {
         if (int(threadIdx.x) < h) sa[threadIdx.x] += sa[threadIdx.x + h], sb[threadIdx.x] += sb[threadIdx.x + h];
         __syncthreads();
     }
@@ -2040,7 +2056,7 @@ void launch_adj_side(const KLevel& P, int ci0, int cj0, int nxc, int nyc, const 
     k_adj_side<<<adj_blocks_nodes(2 * (nxc + nyc)), 256, 0, s>>>(P, ci0, cj0, nxc, nyc, A, sbar, prebar);
 }
 void launch_reduce_partials(const double* partial, int n, double* acc, hipStream_t s) {
-    k_reduce_partials<<<1, 256, 0, s>>>(partial, n, acc);
+    k_reduce_partials<<<1, kRedThreads, 0, s>>>(partial, n, acc);
 }
 
 // ===========================================================================
