@@ -127,7 +127,6 @@ void setup_views(hlbm_ctx* c) {
     m.ft_meta = reinterpret_cast<const int32_t*>(c->ws + p.off.ft_meta);
     m.ft_node = reinterpret_cast<const int32_t*>(c->ws + p.off.ft_node);
     m.ft_edges = c->ws + p.off.ft_edges;
-    m.ft_c0 = c->ws + p.off.ft_c0;
 }
 
 int upload_tables(hlbm_ctx* c) {
@@ -167,44 +166,24 @@ int upload_tables(hlbm_ctx* c) {
         if (p.fv_fuse > 1) {
             rc |= upload(c, p.off.ft_meta, p.ft_meta.data(), p.ft_meta.size() * 4);
             rc |= upload(c, p.off.ft_node, p.ft_node.data(), p.ft_node.size() * 4);
-            // tile edge tables: slot 0 (the node itself) as its coefficient C_PP
-            // alone, slots 1..W-1 in the ELL record layout with local columns
-            const int W = p.ell_width;
-            std::vector<char> te(p.ft_col.size() / W * (W - 1) * rs, 0), tc(p.ft_col.size() / W * p.elem, 0);
-            for (int t = 0; t < p.n_tiles; ++t) {
-                const int32_t* meta = p.ft_meta.data() + size_t(t) * kTileMeta;
-                const size_t eoff = size_t(meta[1]), width = size_t(meta[2]);
-                for (size_t z = 0; z < size_t(W); ++z)
-                    for (size_t i = 0; i < width; ++i) {
-                        const size_t e = eoff + z * width + i;
-                        const int32_t col = p.ft_col[e];
-                        const int zz = p.ft_src[e];
-                        if (z == 0) {
-                            if (col != int32_t(i) || zz < 0) return set_err(c, HLBM_E_GEOMETRY, "tile slot 0 is not the node");
-                            char* r = tc.data() + (eoff / W + i) * p.elem;
-                            if (f64) std::memcpy(r, &p.cc[zz], 8);
-                            else {
-                                const float v = float(p.cc[zz]);
-                                std::memcpy(r, &v, 4);
-                            }
-                            continue;
-                        }
-                        char* r = te.data() + (eoff / W * (W - 1) + (z - 1) * width + i) * rs;
-                        std::memcpy(r, &col, 4);
-                        if (zz < 0) continue;
-                        if (f64) {
-                            const double v[3] = {p.gx[zz], p.gy[zz], p.cc[zz]};
-                            std::memcpy(r + 8, v, 24);
-                        } else {
-                            const float v[3] = {float(p.gx[zz]), float(p.gy[zz]), float(p.cc[zz])};
-                            std::memcpy(r + 4, v, 12);
-                        }
-                    }
+            // tile edge tables: the ELL record layout with local columns
+            std::vector<char> te(p.ft_col.size() * rs, 0);
+            for (size_t e = 0; e < p.ft_col.size(); ++e) {
+                char* r = te.data() + e * rs;
+                const int32_t col = p.ft_col[e];
+                std::memcpy(r, &col, 4);
+                const int zz = p.ft_src[e];
+                if (zz < 0) continue;
+                if (f64) {
+                    const double v[3] = {p.gx[zz], p.gy[zz], p.cc[zz]};
+                    std::memcpy(r + 8, v, 24);
+                } else {
+                    const float v[3] = {float(p.gx[zz]), float(p.gy[zz]), float(p.cc[zz])};
+                    std::memcpy(r + 4, v, 12);
+                }
             }
             keep.push_back(std::move(te));
             rc |= upload(c, p.off.ft_edges, keep.back().data(), keep.back().size());
-            keep.push_back(std::move(tc));
-            rc |= upload(c, p.off.ft_c0, keep.back().data(), keep.back().size());
         }
         rc |= upload(c, p.off.wall_nrm, p.wall_nrm.data(), p.wall_nrm.size() * 8);
         rc |= upload(c, p.off.wall_slot, p.wall_slot.data(), p.wall_slot.size() * 4);

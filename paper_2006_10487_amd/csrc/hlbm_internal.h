@@ -92,7 +92,7 @@ struct Plan {
         size_t spans, sint_node, sint_don, sint_w;
         size_t mesh[2], rowptr, edges, wedge, wnorm, prep[2], uint_don, uint_w, hist, stage;
         size_t wall_nrm, wall_slot, wsum, wout;
-        size_t ft_meta, ft_node, ft_edges, ft_c0;
+        size_t ft_meta, ft_node, ft_edges;
         size_t total;
     } off{};
     size_t stage_bytes = 0;
@@ -140,8 +140,7 @@ struct KMesh {
     int threads;                                  // workgroup size, kFvStage * threads >= maxw
     const int32_t* ft_meta;
     const int32_t* ft_node;
-    const void* ft_edges;            // per tile: slots 1..W-1, [W-1][width] ELL records, local columns
-    const void* ft_c0;               // per tile: [width] C_PP of slot 0 (the node itself)
+    const void* ft_edges;
 };
 
 // launchers (kernels.hip); `prec` is HLBM_FP64 or HLBM_FP32_SHIFTED

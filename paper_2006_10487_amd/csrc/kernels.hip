@@ -769,47 +769,29 @@ __global__ __launch_bounds__(256) void k_fv_substep(const KMesh M, const T* __re
     store_rec(fout + size_t(P) * kRec, fn, SHIFT ? dr : r, ux, uy);
 }
 
-// Edge records of local node i in a tile table: slot 0 (the node itself)
-// needs only its coefficient C_PP, slots 1..W-1 the full records.
-template <typename T, int W>
-struct TileEdges {
-    T c0;
-    EdgeRec<T> e[W - 1];
-};
-template <typename T, int W>
-__device__ __forceinline__ void load_tile_edges(const EdgeRec<T>* __restrict__ E, const T* __restrict__ C0, int width,
-                                                int i, TileEdges<T, W>& te) {
-    te.c0 = C0[i];
-#pragma unroll
-    for (int z = 1; z < W; ++z) te.e[z - 1] = E[size_t(z - 1) * width + i];
-}
-
-// One node update of the fused kernel: local node i with its edge records te,
+// One node update of the fused kernel: local node i with its edge records e,
 // reading the tile state in buf; returns the node's plan index.
 template <typename T, bool SHIFT, int W>
 __device__ __forceinline__ int fv_tile_node(const KMesh& M, const T* __restrict__ buf, const int32_t* gid,
                                             const T* __restrict__ prep0, const T* __restrict__ prep1, T theta,
-                                            int i, const TileEdges<T, W>& te, T (&fn)[9], T (&mv)[3]) {
+                                            int i, const EdgeRec<T> (&e)[W], T (&fn)[9], T (&mv)[3]) {
     const T rho0 = T(M.rho0), cst = T(M.star_neq);
     const int P = gid[i];
     const bool pivot_interp = P >= M.n_core;
     FvAcc<T> A;
 #pragma unroll
     for (int z = 0; z < W; ++z) {
-        // slot 0: the node itself (its G coefficients do not enter, see fv_add)
-        const int col = z == 0 ? i : te.e[z - 1].col;
-        if (col < 0) continue;
-        const int k = z == 0 ? P : gid[col];
+        if (e[z].col < 0) continue;
+        const int k = gid[e[z].col];
         const bool star = pivot_interp && k >= M.n_core;
         T f[9], nq[9], mk = 0, uxk = 0, uyk = 0;
         if (star) {
             const size_t sl = size_t(k - M.n_core) * kMacro;
             star_values<T, SHIFT>(prep0 + sl, prep1 + sl, theta, cst, rho0, f, nq);
         } else {
-            load_rec(buf + size_t(col) * kRec, f, mk, uxk, uyk);
+            load_rec(buf + size_t(e[z].col) * kRec, f, mk, uxk, uyk);
         }
-        if (z == 0) fv_add<T, SHIFT>(A, 0, f, star, nq, mk, uxk, uyk, T(0), T(0), te.c0, rho0);
-        else fv_add<T, SHIFT>(A, z, f, star, nq, mk, uxk, uyk, te.e[z - 1].gx, te.e[z - 1].gy, te.e[z - 1].c, rho0);
+        fv_add<T, SHIFT>(A, z, f, star, nq, mk, uxk, uyk, e[z].gx, e[z].gy, e[z].c, rho0);
     }
     T r, dr;
     fv_finish<T, SHIFT>(M, P, A, fn, r, dr, mv[1], mv[2]);
@@ -850,8 +832,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
     const int32_t* meta = M.ft_meta + size_t(t) * kTileMeta;
     const int noff = meta[0], eoff = meta[1], width = meta[2];
     const int nload = meta[3 + ksteps], ntile = meta[3];
-    const EdgeRec<T>* __restrict__ E = reinterpret_cast<const EdgeRec<T>*>(M.ft_edges) + size_t(eoff) / W * (W - 1);
-    const T* __restrict__ C0 = reinterpret_cast<const T*>(M.ft_c0) + eoff / W;
+    const EdgeRec<T>* __restrict__ E = reinterpret_cast<const EdgeRec<T>*>(M.ft_edges) + eoff;
     // records of the tile and its rings: all loads of a batch in flight together
     constexpr int kBatch = 3;
     for (int i0 = 0; i0 < nload; i0 += kBatch * int(blockDim.x)) {
@@ -881,17 +862,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
         // registers for sub-step 2, which takes node tx first.
         const int n1 = meta[4];
         const T th1 = T(double(m0) / double(M.n_sub)), th2 = T(double(m0 + 1) / double(M.n_sub));
-        TileEdges<T, W> e, e0;
+        EdgeRec<T> e[W], e0[W];
         T r1[9], m1[3], r0[9], m0v[3];
         const bool has1 = tx + B < n1, has0 = tx < n1;
         if (has1) {
-            load_tile_edges<T, W>(E, C0, width, tx + B, e);
+#pragma unroll
+            for (int z = 0; z < W; ++z) e[z] = E[size_t(z) * width + tx + B];
             const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, prep0, prep1, th1, tx + B, e, r1, m1);
             if (mid && tx + B < ntile) store_rec(mid + size_t(P) * kRec, r1, m1[0], m1[1], m1[2]);
         }
         __builtin_amdgcn_sched_barrier(0);
         if (has0) {
-            load_tile_edges<T, W>(E, C0, width, tx, e0);
+#pragma unroll
+            for (int z = 0; z < W; ++z) e0[z] = E[size_t(z) * width + tx];
             const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, prep0, prep1, th1, tx, e0, r0, m0v);
             if (mid && tx < ntile) store_rec(mid + size_t(P) * kRec, r0, m0v[0], m0v[1], m0v[2]);
         }
@@ -905,7 +888,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
         }
         __builtin_amdgcn_sched_barrier(0);
         if (tx + B < ntile) {
-            load_tile_edges<T, W>(E, C0, width, tx + B, e);
+#pragma unroll
+            for (int z = 0; z < W; ++z) e[z] = E[size_t(z) * width + tx + B];
             const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, prep0, prep1, th2, tx + B, e, r1, m1);
             store_rec(fout + size_t(P) * kRec, r1, m1[0], m1[1], m1[2]);
         }
@@ -920,8 +904,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
         for (int s2 = 0; s2 < kFvStage; ++s2) {
             const int i = tx + s2 * B;
             if (i >= ncomp) break;
-            TileEdges<T, W> e;
-            load_tile_edges<T, W>(E, C0, width, i, e);
+            EdgeRec<T> e[W];
+#pragma unroll
+            for (int z = 0; z < W; ++z) e[z] = E[size_t(z) * width + i];
             const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, prep0, prep1, theta, i, e, res[s2], rm[s2]);
             if (last) store_rec(fout + size_t(P) * kRec, res[s2], rm[s2][0], rm[s2][1], rm[s2][2]);
             else if (mid && i < ntile)

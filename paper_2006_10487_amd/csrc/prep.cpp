@@ -944,8 +944,7 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
     p.off.wout = take(size_t(p.n_wall) * 3 * 8);
     p.off.ft_meta = take(p.ft_meta.size() * 4);
     p.off.ft_node = take(p.ft_node.size() * 4);
-    p.off.ft_edges = take(p.ft_col.size() / p.ell_width * (p.ell_width - 1) * (E == 8 ? 32 : 16));
-    p.off.ft_c0 = take(p.ft_col.size() / p.ell_width * E);
+    p.off.ft_edges = take(p.ft_col.size() * (E == 8 ? 32 : 16));
     size_t maxrow = 0;
     for (int l = 0; l <= p.L; ++l) maxrow = std::max(maxrow, size_t(p.lev[l].nx));
     p.stage_bytes = std::max(size_t(kQ) * maxrow * 8 * 8, std::min(size_t(32) << 20, size_t(kQ) * maxrow * 8 * 4096));
