@@ -169,12 +169,15 @@ def test_four_level_naca_fp64_short():
         assert max(e["cd"], e["cl"]) < 1e-10
 
 
-@pytest.mark.parametrize("case", ["re100_c40_fp64", "re1000_c128_fp32", "re1000_c128_fp64"])
+@pytest.mark.parametrize("case", ["re100_c40_fp64", "re100_c40_refined_fp64", "re1000_c128_fp32",
+                                  "re1000_c128_fp64"])
 def test_fused_fv_substeps_match_single(case):
     """Several FV sub-steps per launch (tiles with halos in LDS) give the state of
     one launch per sub-step: same arithmetic in the same order."""
     if case == "re100_c40_fp64":
         w, prec, steps = W.naca_re100_c40(6.0), hlbm.FP64, 40
+    elif case == "re100_c40_refined_fp64":
+        w, prec, steps = W.naca_re100_c40_refined(6.0, bumps=W.hh_amplitudes(1)), hlbm.FP64, 40
     else:
         w, steps = W.naca_re1000_c128(10.0), 20
         prec = hlbm.FP32_SHIFTED if case.endswith("fp32") else hlbm.FP64
@@ -191,7 +194,8 @@ def test_fused_fv_substeps_match_single(case):
     for fuse in sorted(set(states) - {1}):
         d = max(rel(a, b) for a, b in zip(states[fuse], states[1]))
         print(f"{case}: fuse {fuse} vs 1: max rel diff {d:.3e}", flush=True)
-        assert d <= (1e-14 if prec == hlbm.FP64 else 1e-6)
+        # the same arithmetic in the same order: equal bits
+        assert d == 0.0
 
 
 def test_bench_workload_full_size():
