@@ -106,6 +106,9 @@ typedef struct {
     size_t workspace_bytes;
     int32_t fv_fuse;              /* FV sub-steps per launch (the HLBM_K_FV class of hlbm_profile_read
                                      and hlbm_kernel_bench covers that many)                         */
+    int32_t fv_tiles;             /* workgroups of one fused FV launch (tiles), 0 when fv_fuse = 1  */
+    int32_t fv_tile_nodes;        /* nominal mesh nodes per tile                                    */
+    int32_t fv_threads;           /* threads per fused-launch workgroup                             */
 } hlbm_info_t;
 
 /* Checks the problem on the host only (no GPU).  Re > 0 gives

@@ -583,6 +583,10 @@ int hlbm_info(hlbm_ctx* c, hlbm_info_t* o) {
     o->t = c->t;
     o->workspace_bytes = p.off.total;
     o->fv_fuse = p.has_mesh ? p.fv_fuse : 0;
+    const bool fused = p.has_mesh && p.fv_fuse > 1;
+    o->fv_tiles = fused ? p.n_tiles : 0;
+    o->fv_tile_nodes = fused ? p.fv_tile : 0;
+    o->fv_threads = fused ? p.fv_threads : 0;
     return HLBM_OK;
 }
 

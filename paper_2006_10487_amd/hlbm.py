@@ -48,7 +48,8 @@ class Grid(C.Structure):
         ("u_inf", C.c_double), ("aoa_rad", C.c_double), ("rho0", C.c_double),
         ("precision", C.c_int32), ("interp", C.c_int32), ("n_sub", C.c_int32), ("bc", C.c_int32),
         ("wall_bc", C.c_int32), ("check_every", C.c_int32), ("history_len", C.c_int32),
-        ("fv_fuse", C.c_int32),
+        ("fv_fuse", C.c_int32), ("fv_tiles", C.c_int32), ("fv_tile_nodes", C.c_int32),
+        ("fv_threads", C.c_int32),
     ]
 
 
@@ -75,7 +76,8 @@ class Info(C.Structure):
         ("n_interp_struct", C.c_int32), ("n_fallback", C.c_int32), ("n_wall_edges", C.c_int32),
         ("nnz", C.c_int32), ("bytes_per_finest_step", C.c_int64), ("k1_bytes", C.c_int64 * 4),
         ("fv_bytes", C.c_int64), ("t", C.c_int64), ("workspace_bytes", C.c_size_t),
-        ("fv_fuse", C.c_int32),
+        ("fv_fuse", C.c_int32), ("fv_tiles", C.c_int32), ("fv_tile_nodes", C.c_int32),
+        ("fv_threads", C.c_int32),
     ]
 
 

@@ -214,6 +214,8 @@ def test_bench_workload_full_size():
     sim.close()
     sim = hlbm.HLBM.from_workload(w, precision=hlbm.FP32_SHIFTED)
     assert sim.info.fv_fuse == 2
+    # every tile of a fused launch resident at once: 3 workgroups of 256 threads on each of 256 CUs
+    assert sim.info.fv_threads == 256 and 0 < sim.info.fv_tiles <= 3 * 256
     sim.step(2)
     e = compare(sim, ref, 2)
     assert max(e["level0"], e["level1"], e["mesh"]) < 1e-6 and max(e["cd"], e["cl"]) < 1e-5
