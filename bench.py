@@ -224,6 +224,7 @@ def main():
                    "mesh_nodes": int(r32["info"].n_mesh_nodes), "n_sub": int(r32["info"].n_sub),
                    "re": w.re, "aoa_deg": w.aoa_deg, "chord": w.chord,
                    "finest_steps_per_step": per, "fv_fuse": int(r32["info"].fv_fuse),
+                   "fv_tiles": int(r32["info"].fv_tiles), "fv_tile_nodes": int(r32["info"].fv_tile_nodes),
                    "precision": "fp32_shifted_fp64_forces"},
     }
     dom = max(k32, key=lambda k: k32[k]["share"])
