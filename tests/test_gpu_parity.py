@@ -219,6 +219,12 @@ def test_bench_workload_full_size():
     sim.step(2)
     e = compare(sim, ref, 2)
     assert max(e["level0"], e["level1"], e["mesh"]) < 1e-6 and max(e["cd"], e["cl"]) < 1e-5
+    # the launch shape bench.py times gives the bits of one launch per sub-step
+    fused = sim.get_state(hlbm.PART_MESH)
+    sim.close()
+    one = hlbm.HLBM.from_workload(w, precision=hlbm.FP32_SHIFTED, fv_fuse=1)
+    one.step(2)
+    assert np.array_equal(fused, one.get_state(hlbm.PART_MESH))
 
 
 def test_determinism_and_resume():
