@@ -229,6 +229,15 @@ __global__ __launch_bounds__(256) void k_stream_collide_f32x2(const KLevel L, co
     const int i0 = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
     const int j = blockIdx.y;
     if (j == 0 || j == L.ny - 1) return;   // far-field edge rows or box perimeter rows: no pulling node
+    bool act[2];
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+        const int i = i0 + v;
+        act[v] = i < L.nx && !(L.farfield && (i == 0 || i == L.nx - 1)) && is_active(L, i, j);
+    }
+    // a wave with no active node (inside a child box or the inner ellipse)
+    // loads nothing; the others keep every lane for the neighbour shuffles
+    if (__ballot(act[0] || act[1]) == 0) return;
     const bool in_row = i0 < L.pitch;
     float f[2][9];
 #pragma unroll
@@ -254,12 +263,6 @@ __global__ __launch_bounds__(256) void k_stream_collide_f32x2(const KLevel L, co
             f[0][q] = a1;
             f[1][q] = right;
         }
-    }
-    bool act[2];
-#pragma unroll
-    for (int v = 0; v < 2; ++v) {
-        const int i = i0 + v;
-        act[v] = i < L.nx && !(L.farfield && (i == 0 || i == L.nx - 1)) && is_active(L, i, j);
     }
     if (!act[0] && !act[1]) return;
     const float omega = float(L.omega), rho0 = float(L.rho0);
