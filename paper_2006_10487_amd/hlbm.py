@@ -48,8 +48,7 @@ class Grid(C.Structure):
         ("u_inf", C.c_double), ("aoa_rad", C.c_double), ("rho0", C.c_double),
         ("precision", C.c_int32), ("interp", C.c_int32), ("n_sub", C.c_int32), ("bc", C.c_int32),
         ("wall_bc", C.c_int32), ("check_every", C.c_int32), ("history_len", C.c_int32),
-        ("fv_fuse", C.c_int32), ("fv_tiles", C.c_int32), ("fv_tile_nodes", C.c_int32),
-        ("fv_threads", C.c_int32),
+        ("fv_fuse", C.c_int32),
     ]
 
 

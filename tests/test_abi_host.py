@@ -33,6 +33,8 @@ def test_header_symbols_exported(lib):
 def test_struct_sizes_match_header(lib):
     # hlbm_grid: 3 ints, 12 ints, 3 doubles, 7 ints (+ padding) -> ctypes follows the C layout
     assert C.sizeof(hlbm.Grid) % 8 == 0
+    # hlbm_grid: 15 int32 (60 B, padded to 64), 3 doubles, 8 int32
+    assert C.sizeof(hlbm.Grid) == 64 + 3 * 8 + 8 * 4
     assert C.sizeof(hlbm.Mesh) == 4 + 4 + 3 * 8 + 8 + 32
 
 
