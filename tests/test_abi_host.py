@@ -31,11 +31,36 @@ def test_header_symbols_exported(lib):
 
 
 def test_struct_sizes_match_header(lib):
-    # hlbm_grid: 3 ints, 12 ints, 3 doubles, 7 ints (+ padding) -> ctypes follows the C layout
-    assert C.sizeof(hlbm.Grid) % 8 == 0
     # hlbm_grid: 15 int32 (60 B, padded to 64), 3 doubles, 8 int32
     assert C.sizeof(hlbm.Grid) == 64 + 3 * 8 + 8 * 4
     assert C.sizeof(hlbm.Mesh) == 4 + 4 + 3 * 8 + 8 + 32
+
+
+def test_struct_layouts_match_compiled_header(tmp_path):
+    """Size and every field offset of the binding's structs against the C compiler's
+    reading of include/hlbm.h."""
+    structs = {"hlbm_grid": hlbm.Grid, "hlbm_mesh": hlbm.Mesh, "hlbm_info_t": hlbm.Info,
+               "hlbm_objective": hlbm.Objective}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hlbm.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    import subprocess
+    subprocess.check_call(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        cname, field, value = line.split()
+        got[(cname, field)] = int(value)
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == C.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
 
 
 def _small(**kw):
