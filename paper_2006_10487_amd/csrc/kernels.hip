@@ -496,7 +496,7 @@ __global__ void k_fine_to_coarse(const KLevel P, const KLevel C, int ci0, int cj
 // mesh donors (eq. (8)).  Mesh nodes are records [f_0..f_8, rho (or
 // rho - rho0), ux, uy].
 template <typename T, bool SHIFT>
-__global__ void k_mesh_to_struct(const KLevel F, T* __restrict__ A, int n, const int32_t* __restrict__ node,
+__global__ __launch_bounds__(64) void k_mesh_to_struct(const KLevel F, T* __restrict__ A, int n, const int32_t* __restrict__ node,
                                  const int32_t* __restrict__ don, const T* __restrict__ w,
                                  const T* __restrict__ mf, T factor) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -505,10 +505,22 @@ __global__ void k_mesh_to_struct(const KLevel F, T* __restrict__ A, int n, const
     T acc[kMacro];
 #pragma unroll
     for (int m = 0; m < kMacro; ++m) acc[m] = 0;
+    // every donor index, then every donor record, in flight together (the list
+    // is packed: the first unused slot ends it); then the sums in donor order
+    int kd[kSDon];
+#pragma unroll
+    for (int d = 0; d < kSDon; ++d) kd[d] = don[size_t(s) * kSDon + d];
+    T rd[kSDon][kRec];
+#pragma unroll
+    for (int d = 0; d < kSDon; ++d)
+        if (kd[d] >= 0) {
+#pragma unroll
+            for (int q = 0; q < kRec; ++q) rd[d][q] = mf[size_t(kd[d]) * kRec + q];
+        }
+#pragma unroll
     for (int d = 0; d < kSDon; ++d) {
-        const int k = don[size_t(s) * kSDon + d];
-        if (k < 0) break;
-        const T* rec = mf + size_t(k) * kRec;
+        if (kd[d] < 0) break;
+        const T* rec = rd[d];
         T f[9], feq[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) f[q] = rec[q];
@@ -535,7 +547,7 @@ __global__ void k_mesh_to_struct(const KLevel F, T* __restrict__ A, int n, const
 // Mesh interpolation nodes <- finest level, eq. (9): (rho, u, f^neq) of the
 // streamed populations of the 3 x 3 (or 2 x 2) donor block.
 template <typename T, bool SHIFT>
-__global__ void k_struct_to_mesh(const KLevel F, const T* __restrict__ A, int n, const int32_t* __restrict__ don,
+__global__ __launch_bounds__(64) void k_struct_to_mesh(const KLevel F, const T* __restrict__ A, int n, const int32_t* __restrict__ don,
                                  const T* __restrict__ w, T* __restrict__ prep) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -543,11 +555,22 @@ __global__ void k_struct_to_mesh(const KLevel F, const T* __restrict__ A, int n,
     T acc[kMacro];
 #pragma unroll
     for (int m = 0; m < kMacro; ++m) acc[m] = 0;
+    // every donor index, then every donor's pulled populations, in flight
+    // together (the list is packed: the first unused slot ends it); then the
+    // sums in donor order
+    int idd[kUDon];
+#pragma unroll
+    for (int d = 0; d < kUDon; ++d) idd[d] = don[size_t(s) * kUDon + d];
+    T fd[kUDon][9];
+#pragma unroll
+    for (int d = 0; d < kUDon; ++d)
+        if (idd[d] >= 0) pull(F, A, idd[d] % F.nx, idd[d] / F.nx, fd[d]);
+#pragma unroll
     for (int d = 0; d < kUDon; ++d) {
-        const int id = don[size_t(s) * kUDon + d];
+        const int id = idd[d];
         if (id < 0) break;
-        T f[9], r, dr, ux, uy, neq[9];
-        pull(F, A, id % F.nx, id / F.nx, f);
+        T r, dr, ux, uy, neq[9];
+        const T(&f)[9] = fd[d];
         macro_neq<T, SHIFT>(f, rho0, r, dr, ux, uy, neq);
         const T ww = w[size_t(s) * kUDon + d];
         acc[0] += ww * (SHIFT ? dr : r);
