@@ -951,17 +951,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
     }
 }
 
+// Threads of the single wall-force block: with 1024, each thread takes about
+// two of the 2048 wall edges of the 264k-node mesh, so its chain of dependent
+// loads (edge, then the two records) is short.
+constexpr int kWallForceThreads = 1024;
+
 // Drag and lift, eqs. (10)-(11), in FP64: momentum flux out of the fluid
 // through the wall edges, sum_i c_i (c_i . N_e) (f_i(a) + f_i(b)) / 2, reduced
 // by one block in a fixed order (deterministic).  Shifted storage drops the
 // rest-state part rho0 c_s^2 N_e, which sums to zero over the closed wall.
 template <typename T, bool SHIFT>
-__global__ __launch_bounds__(256) void k_wall_force(const T* __restrict__ f, int ne, const int32_t* __restrict__ wedge,
-                                                    const double* __restrict__ wn, double* __restrict__ out,
-                                                    double ca, double sa, double qn) {
-    __shared__ double sx[256], sy[256];
+__global__ __launch_bounds__(kWallForceThreads) void k_wall_force(const T* __restrict__ f, int ne,
+                                                                  const int32_t* __restrict__ wedge,
+                                                                  const double* __restrict__ wn,
+                                                                  double* __restrict__ out, double ca, double sa,
+                                                                  double qn) {
+    __shared__ double sx[kWallForceThreads], sy[kWallForceThreads];
     double ax = 0, ay = 0;
-    for (int e = threadIdx.x; e < ne; e += 256) {
+    for (int e = threadIdx.x; e < ne; e += kWallForceThreads) {
         const int a = wedge[2 * e], b = wedge[2 * e + 1];
         const double nx = wn[2 * e], ny = wn[2 * e + 1];
 #pragma unroll
@@ -975,7 +982,7 @@ __global__ __launch_bounds__(256) void k_wall_force(const T* __restrict__ f, int
     sx[threadIdx.x] = ax;
     sy[threadIdx.x] = ay;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = kWallForceThreads / 2; h > 0; h >>= 1) {
         if (int(threadIdx.x) < h) {
             sx[threadIdx.x] += sx[threadIdx.x + h];
             sy[threadIdx.x] += sy[threadIdx.x + h];
@@ -1124,7 +1131,7 @@ void launch_fv_fused(int prec, const KMesh& M, const void* fin, void* fout, cons
 
 void launch_wall_force(int prec, const void* f, int ne, const int32_t* wedge, const double* wn,
                        double* out, double ca, double sa, double qn, hipStream_t s) {
-    HLBM_DISPATCH(prec, (k_wall_force<T, S><<<1, 256, 0, s>>>((const T*)f, ne, wedge, wn, out, ca, sa, qn)));
+    HLBM_DISPATCH(prec, (k_wall_force<T, S><<<1, kWallForceThreads, 0, s>>>((const T*)f, ne, wedge, wn, out, ca, sa, qn)));
 }
 
 void launch_mesh_convert(int prec, int nn, const double* in, void* out, int to_storage, double rho0, hipStream_t s) {
