@@ -227,6 +227,19 @@ def test_bench_workload_full_size():
     assert np.array_equal(fused, one.get_state(hlbm.PART_MESH))
 
 
+def test_fused_fallback_when_tiles_too_large():
+    """Four sub-steps per launch on the 264k-node mesh would need more than 512
+    updated nodes per tile: the plan falls back to one sub-step per launch."""
+    w = W.naca_re5000_c512()
+    sim = hlbm.HLBM.from_workload(w, precision=hlbm.FP32_SHIFTED, fv_fuse=4)
+    assert sim.info.fv_fuse == 1 and sim.info.fv_tiles == 0 and sim.info.fv_threads == 0
+    sim.close()
+    sim = hlbm.HLBM.from_workload(w, precision=hlbm.FP32_SHIFTED, fv_fuse=3)
+    assert sim.info.fv_fuse in (1, 3)
+    if sim.info.fv_fuse == 3:
+        assert 2 * sim.info.fv_threads >= sim.info.fv_tile_nodes
+
+
 def test_determinism_and_resume():
     w = W.naca_re100_c40(3.0)
     a = hlbm.HLBM.from_workload(w)
