@@ -72,9 +72,9 @@ typedef struct {
     int32_t wall_bc;              /* 1 = no-slip at mesh wall nodes, 0 = off (free-stream checks)    */
     int32_t check_every;          /* non-finite check interval in finest steps, 0 = off             */
     int32_t history_len;          /* force history ring length, 0 = 65536                            */
-    int32_t fv_fuse;              /* FV sub-steps per launch, 1..4 (falls back to 1 when a tile of
-                                     mesh nodes and its halo do not fit in 64 KB of LDS or need more
-                                     than 512 updated nodes per tile); 0 = 2 on meshes with at most
+    int32_t fv_fuse;              /* FV sub-steps per launch, 1..4 (falls back to the largest count
+                                     whose tile of mesh nodes and halo fit in 64 KB of LDS with at
+                                     most 512 updated nodes per tile, else 1); 0 = 2 on meshes with at most
                                      8 neighbour slots per node, else 1.  Results do not depend on
                                      it (same arithmetic, same order)                                */
 } hlbm_grid;

@@ -811,24 +811,24 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
             }
         // fused FV sub-steps: fv_fuse per launch when a tile with its rings fits
         // in 64 KB of LDS and a workgroup of at most 256 threads covers the
-        // nodes of sub-step 1 with kFvStage nodes per thread, else one kernel
-        // per sub-step
+        // nodes of sub-step 1 with kFvStage nodes per thread, else fewer (one
+        // kernel per sub-step when not even two fit)
         if (g->fv_fuse < 0 || g->fv_fuse > kMaxFuse) return fail(err, HLBM_E_ARG, "fv_fuse must be 0..%d", kMaxFuse);
         const int fuse = g->fv_fuse > 0 ? g->fv_fuse : (p.ell_width <= 8 ? kFvFuse : 1);
+        // the largest count from the requested one down to two whose tiles fit
         p.fv_fuse = 1;
-        if (fuse > 1) {
-            choose_fv_tiles(p, fuse);
+        for (int k = fuse; k > 1; --k) {
+            choose_fv_tiles(p, k);
             const int need = (p.fv_maxw + kFvStage - 1) / kFvStage;
             p.fv_threads = std::max(p.elem == 8 ? kFvThreadsF64 : kFvThreadsF32, (need + 63) / 64 * 64);
             const size_t lds = size_t(p.fv_maxl) * (kRec * p.elem + 4);
-            if (lds > 65536 || p.fv_threads > 256) {
-                p.fv_fuse = 1;
-                p.n_tiles = 0;
-                p.ft_meta.clear();
-                p.ft_node.clear();
-                p.ft_col.clear();
-                p.ft_src.clear();
-            }
+            if (lds <= 65536 && p.fv_threads <= 256) break;
+            p.fv_fuse = 1;
+            p.n_tiles = 0;
+            p.ft_meta.clear();
+            p.ft_node.clear();
+            p.ft_col.clear();
+            p.ft_src.clear();
         }
         // wall statistics: unit normal into the fluid at each wall node (opposite
         // to half the sum of its wall-edge normals) and its output slot
