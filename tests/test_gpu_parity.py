@@ -81,12 +81,12 @@ def test_small_fp64_incidence_linear_interp(aoa_deg):
     assert max(e["level0"], e["mesh"]) < TOL and max(e["cd"], e["cl"]) < 1e-10
 
 
-def _tg_pair(L, tau, u0, patches=(), mesh=None, ein=None):
+def _tg_pair(L, tau, u0, patches=(), mesh=None, ein=None, fv_fuse=0):
     kw = {}
     if mesh is not None:
         kw = dict(mesh_xy=mesh[0], mesh_tri=mesh[1], mesh_kind=mesh[2], inner_ellipse=ein)
     ref = O.Oracle(nx_cells=L, ny_cells=L, periodic=True, tau_s=tau, u_inf=u0, patches=patches, **kw)
-    g, m, keep = hlbm.make_structs(L, L, patches, periodic=True, u_inf=u0, **kw)
+    g, m, keep = hlbm.make_structs(L, L, patches, periodic=True, u_inf=u0, fv_fuse=fv_fuse, **kw)
     sim = hlbm.HLBM(g, m, tau=tau, keep=keep)
     nlev = ref.n_levels
     length = L * 2 ** (nlev - 1)
@@ -128,6 +128,20 @@ def test_hybrid_taylor_green_mesh_patch():
     ref.step(100)
     e = compare(sim, ref, 1)
     assert max(e["level0"], e["mesh"]) < TOL
+
+
+def test_fused_fv_16_slot_mesh_matches_single():
+    """The fused FV path on a 16-slot mesh (vertex degree 8, one sub-step per launch by
+    default) gives the bits of one launch per sub-step."""
+    mesh = W.rect_patch_mesh(16.2, 16.2, 40, 40, 0.8, jitter=0.2, seed=1)
+    out = []
+    for fuse in (1, 2):
+        sim, _ = _tg_pair(64, 0.56, 0.01, mesh=mesh, ein=(32.2, 32.2, 11.0, 11.0), fv_fuse=fuse)
+        assert sim.info.fv_fuse == fuse
+        sim.step(40)
+        out.append(sim.get_state(hlbm.PART_MESH))
+        sim.close()
+    assert np.array_equal(out[0], out[1])
 
 
 def test_refined_naca_fp64_short():
