@@ -1022,6 +1022,12 @@ unsigned blocks(size_t n, unsigned b = 256) { return unsigned((n + b - 1) / b); 
 // more, smaller workgroups spread them over the chip).
 unsigned fv_substep_block(int nn) { return nn < 2 * 256 * 256 ? 64u : 256u; }
 
+// Workgroup size of the interface kernels (far-field edges, box transfers): a
+// few thousand nodes, each a short chain of dependent loads; one-wave groups
+// spread them over more CUs (measured on the 2048 x 1024 box: coarse -> fine
+// 11.1 -> 9.4 us, fine -> coarse 10.3 -> 6.9 us against 256-thread groups).
+constexpr unsigned kSmallBlock = 64;
+
 }  // namespace
 
 #define HLBM_DISPATCH(prec, CALL)        \
@@ -1050,7 +1056,7 @@ void launch_stream_collide(int prec, const KLevel& L, const void* A, void* B, hi
         HLBM_DISPATCH(prec, (k_stream_collide<T, S><<<grid, 256, 0, s>>>(L, (const T*)A, (T*)B)));
     }
     if (L.farfield)
-        HLBM_DISPATCH(prec, (k_edges<T, S><<<blocks(2 * size_t(L.nx) + 2 * size_t(L.ny - 2)), 256, 0, s>>>(L, (const T*)A, (T*)B)));
+        HLBM_DISPATCH(prec, (k_edges<T, S><<<blocks(2 * size_t(L.nx) + 2 * size_t(L.ny - 2), kSmallBlock), kSmallBlock, 0, s>>>(L, (const T*)A, (T*)B)));
 }
 
 void launch_export_level(int prec, const KLevel& L, const void* A, double* out, int j0, int j1, hipStream_t s) {
@@ -1072,7 +1078,7 @@ void launch_coarse_to_fine(int prec, const KLevel& P, const KLevel& C, int ci0, 
                            double tau_f, hipStream_t s) {
     const size_t n = 2 * size_t(C.nx - 1 + C.ny - 1);
     const double scale = tau_f / (2.0 * tau_c);
-    HLBM_DISPATCH(prec, (k_coarse_to_fine<T, S><<<blocks(n), 256, 0, s>>>(P, C, ci0, cj0, (const T*)pA, (T*)cA, (T*)side_cur,
+    HLBM_DISPATCH(prec, (k_coarse_to_fine<T, S><<<blocks(n, kSmallBlock), kSmallBlock, 0, s>>>(P, C, ci0, cj0, (const T*)pA, (T*)cA, (T*)side_cur,
                                                                           (const T*)side_prev, T(theta), compute_side,
                                                                           T(scale), T(1.0 / tau_f))));
 }
@@ -1081,7 +1087,7 @@ void launch_fine_to_coarse(int prec, const KLevel& P, const KLevel& C, int ci0, 
                            const void* cprev, void* pdst, double tau_c, double tau_f, hipStream_t s) {
     const size_t n = 2 * size_t(nxc - 2 + nyc - 2);
     const double scale = 2.0 * tau_c / tau_f;
-    HLBM_DISPATCH(prec, (k_fine_to_coarse<T, S><<<blocks(n), 256, 0, s>>>(P, C, ci0, cj0, nxc, nyc, (const T*)cprev,
+    HLBM_DISPATCH(prec, (k_fine_to_coarse<T, S><<<blocks(n, kSmallBlock), kSmallBlock, 0, s>>>(P, C, ci0, cj0, nxc, nyc, (const T*)cprev,
                                                                           (T*)pdst, T(scale), T(1.0 / tau_c))));
 }
 
