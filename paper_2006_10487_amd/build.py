@@ -10,7 +10,7 @@ OUT = os.path.join(HERE, "libhlbm.so")
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
-    # no packed FP32 instructions: some of their forms have given wrong results on this platform
+    # no packed FP32 instructions: some of their forms have been seen to give wrong results
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
