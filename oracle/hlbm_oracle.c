@@ -79,12 +79,16 @@ static const double W[Q] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.
 
 /* Deliberate-mistake multipliers for mutation tests of the pins (all 1 in a
  * normal run): [0] eq. (4) non-equilibrium factor, [1] eq. (5)-(6) factor,
- * [2] coarse -> fine rescaling, [3] fine -> coarse rescaling. */
-static double plant[4] = {1.0, 1.0, 1.0, 1.0};
+ * [2] coarse -> fine rescaling, [3] fine -> coarse rescaling, [4] the
+ * non-equilibrium part kept by the no-slip reset of wall nodes, [5] the reset
+ * itself (0 skips it), [6] the time fraction theta = m/n at which the
+ * structured values are blended into the finite-volume sub-steps. */
+#define N_PLANT 7
+static double plant[N_PLANT] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};
 
 void or_plant(int32_t which, double value)
 {
-    if (which >= 0 && which < 4) plant[which] = value;
+    if (which >= 0 && which < N_PLANT) plant[which] = value;
 }
 
 /* node classes of a structured level */
@@ -401,7 +405,7 @@ static int fv_geometry(int nn, int nt, const real *xy, const int32_t *tri, const
     int *wedge = (int *)malloc(sizeof(int) * 2 * (n_be > 0 ? n_be : 1));
     for (int e = 0; e < n_be; ++e) {
         int P = be[2 * e], Qn = be[2 * e + 1];
-        real dx = xy[2 * Qn] - xy[2 * P], dy = xy[2 * Qn + 1] - xy[2 * P + 1];
+        real dx = wrap(xy[2 * Qn] - xy[2 * P], period[0]), dy = wrap(xy[2 * Qn + 1] - xy[2 * P + 1], period[1]);
         real nx = 0.5 * dy, ny = -0.5 * dx;   /* each half edge: half length */
         nb_add(rows + (size_t)P * MAXNB, &len[P], P, -0.75 * nx, -0.75 * ny, 0.0);
         nb_add(rows + (size_t)P * MAXNB, &len[P], Qn, -0.25 * nx, -0.25 * ny, 0.0);
@@ -1145,13 +1149,13 @@ static void fv_substep(oracle_t *o, const real *star, const real *nstar)
             }
             fnew[q] = base + dt * sum_s - (dt / tau_u) * sum_c;
         }
-        if (o->kind[p] == KIND_WALL && o->cfg.wall_bc) {
+        if (o->kind[p] == KIND_WALL && o->cfg.wall_bc && plant[5] != 0.0) {
             /* no-slip: u -> 0 keeping rho and f^neq */
             real r, x, y, feq[Q], feq0[Q];
             moments(fnew, &r, &x, &y);
             equilibrium(r, x, y, feq);
             equilibrium(r, 0.0, 0.0, feq0);
-            for (int q = 0; q < Q; ++q) fnew[q] = feq0[q] + (fnew[q] - feq[q]);
+            for (int q = 0; q < Q; ++q) fnew[q] = feq0[q] + plant[4] * (fnew[q] - feq[q]);
         }
         for (int q = 0; q < Q; ++q) o->fu_new[(size_t)q * nn + p] = fnew[q];
     }
@@ -1176,7 +1180,7 @@ static void mesh_advance(oracle_t *o)
     real ts = o->cfg.tau_s;
     for (int m = 0; m < o->n_sub; ++m) {
         if (coupled) {
-            double th = (double)m / o->n_sub;
+            double th = plant[6] * m / o->n_sub;
             for (int s = 0; s < nu; ++s) {
                 real v[12];
                 for (int a = 0; a < 12; ++a) v[a] = (1.0 - th) * s0[12 * s + a] + th * s1[12 * s + a];
@@ -1201,7 +1205,8 @@ static void wall_force(const oracle_t *o, real *fx, real *fy)
     real sx = 0.0, sy = 0.0;
     for (int e = 0; e < o->n_wall_edges; ++e) {
         int P = o->wedge[2 * e], Qn = o->wedge[2 * e + 1];
-        real dx = o->xy[2 * Qn] - o->xy[2 * P], dy = o->xy[2 * Qn + 1] - o->xy[2 * P + 1];
+        real dx = wrap(o->xy[2 * Qn] - o->xy[2 * P], o->cfg.mesh_period[0]);
+        real dy = wrap(o->xy[2 * Qn + 1] - o->xy[2 * P + 1], o->cfg.mesh_period[1]);
         real nx = dy, ny = -dx;
         for (int q = 0; q < Q; ++q) {
             real fa = o->fu[(size_t)q * o->nn + P], fb = o->fu[(size_t)q * o->nn + Qn];
@@ -1228,7 +1233,8 @@ static void wall_coefficients(const oracle_t *o, real *cp, real *cf, real *cn)
     real *V = (real *)calloc((size_t)2 * o->nn, sizeof(real));
     for (int e = 0; e < o->n_wall_edges; ++e) {
         int P = o->wedge[2 * e], Qn = o->wedge[2 * e + 1];
-        real nx = o->xy[2 * Qn + 1] - o->xy[2 * P + 1], ny = -(o->xy[2 * Qn] - o->xy[2 * P]);
+        real nx = wrap(o->xy[2 * Qn + 1] - o->xy[2 * P + 1], o->cfg.mesh_period[1]);
+        real ny = -wrap(o->xy[2 * Qn] - o->xy[2 * P], o->cfg.mesh_period[0]);
         V[2 * P] += 0.5 * nx; V[2 * P + 1] += 0.5 * ny;
         V[2 * Qn] += 0.5 * nx; V[2 * Qn + 1] += 0.5 * ny;
     }

@@ -100,7 +100,10 @@ class planted:
     """Context manager that plants a deliberate mistake in the oracle.
 
     which: 0 scales the eq. (4) non-equilibrium factor, 1 the eq. (5)-(6)
-    factor, 2 the coarse -> fine rescaling, 3 the fine -> coarse rescaling.
+    factor, 2 the coarse -> fine rescaling, 3 the fine -> coarse rescaling,
+    4 the non-equilibrium part kept by the no-slip reset of wall nodes, 5 the
+    reset itself (0 skips it), 6 the time fraction theta = m/n of the
+    structured values blended into the sub-steps (0 freezes them at t).
     Used only by mutation tests that show a pin fails on a wrong oracle.
     """
 

@@ -282,6 +282,36 @@ def periodic_square_mesh(n: int, length: float, diagonal: str = "alternate"):
     return xy, tri, kind
 
 
+def periodic_channel_mesh(nx: int, ny: int, length: float, height: float,
+                          diagonal: str = "alternate"):
+    """Triangulated strip [0, length) x [0, height], periodic in x, with wall rows.
+
+    nx nodes per row (x = (i + 0.5) length / nx, wrapping around in x) and
+    ny + 1 rows (y = j height / ny).  The rows j = 0 and j = ny are wall nodes;
+    every other node is interior.  Each cell is split into two triangles along
+    alternating diagonals ("alternate") or always along the same one ("same").
+    Returns (xy, tri, kind).
+    """
+    hx, hy = length / nx, height / ny
+    ii, jj = np.meshgrid(np.arange(nx), np.arange(ny + 1), indexing="xy")
+    xy = np.stack([(ii.ravel() + 0.5) * hx, jj.ravel() * hy], axis=1)
+    tris = []
+    for j in range(ny):
+        for i in range(nx):
+            a = j * nx + i
+            b = j * nx + (i + 1) % nx
+            c = (j + 1) * nx + (i + 1) % nx
+            d = (j + 1) * nx + i
+            if diagonal == "alternate" and (i + j) % 2 == 1:
+                tris += [(a, b, d), (b, c, d)]
+            else:
+                tris += [(a, b, c), (a, c, d)]
+    tri = np.asarray(tris, dtype=np.int32)
+    kind = np.zeros((ny + 1, nx), dtype=np.uint8)
+    kind[0, :] = kind[-1, :] = KIND_WALL
+    return xy, tri, kind.ravel()
+
+
 def rect_patch_mesh(x0: float, y0: float, nx: int, ny: int, h: float,
                     jitter: float = 0.0, seed: int = 0):
     """Triangulated rectangle [x0, x0+nx h] x [y0, y0+ny h] of (nx+1)(ny+1) nodes.

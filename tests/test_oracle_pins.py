@@ -348,6 +348,70 @@ def test_fv_taylor_green_and_agreement_with_lbm():
 
 
 # ---------------------------------------------------------------------------
+# No-slip wall of the mesh (half control volumes + reset u -> 0 keeping rho and
+# f^neq) and the wall force of eqs. (10)-(11): decaying shear wave in a channel
+# ---------------------------------------------------------------------------
+
+def _channel_shear_wave(ny, tau, u0=0.01, nx=8, diagonal="alternate"):
+    """u_x = u0 sin(pi y / H) between no-slip walls at y = 0 and y = H (= ny lu),
+    x-periodic triangulated strip.  Closed form (Stokes): the mode keeps its shape
+    and decays as exp(-nu (pi/H)^2 t) with nu = c_s^2 tau_u; the fluid drags each
+    wall along +x with mu du/dy = rho0 nu (pi/H) a(t) per unit length.
+
+    Returns (decay-rate error, force error, max |u| at the wall nodes, |F_y|) as
+    relative errors against the closed form, measured over [T/10, T] with T one
+    half-life (the first tenth lets the non-equilibrium part of the initial
+    equilibrium state settle)."""
+    H = float(ny)
+    length = nx * H / ny
+    xy, tri, kind = W.periodic_channel_mesh(nx, ny, length, H, diagonal)
+    o = O.Oracle(mesh_xy=xy, mesh_tri=tri, mesh_kind=kind, mesh_period=(length, 0.0), tau_s=tau,
+                 u_inf=u0, chord=1.0)
+    k = math.pi / H
+    nu = (tau - 0.5) / 3.0
+    shape = np.sin(k * xy[:, 1])
+    o.set_mesh(feq_field(eq, np.ones(len(xy)), u0 * shape, np.zeros(len(xy))))
+    T = int(round(math.log(2) / (nu * k * k)))
+    T0 = T // 10
+    o.step(T0)
+    _, ux, _ = macro(o.get_mesh())
+    a0 = float((ux * shape).sum() / (shape * shape).sum())
+    o.step(T - T0)
+    _, ux, uy = macro(o.get_mesh())
+    a1 = float((ux * shape).sum() / (shape * shape).sum())
+    fx, fy = o.wall_force()
+    with np.errstate(all="ignore"):
+        rate_err = math.log(a0 / a1) / (T - T0) / (nu * k * k) - 1.0 if a0 / a1 > 0 else math.inf
+    f_exact = 2.0 * length * nu * k * a1          # both walls, rho0 = 1
+    u_wall = float(np.abs(np.stack([ux, uy])[:, kind == W.KIND_WALL]).max())
+    return rate_err, fx / f_exact - 1.0, u_wall, abs(fy)
+
+
+@pytest.mark.parametrize("tau,diagonal", [(0.56, "alternate"), (0.8, "alternate"), (0.56, "same")])
+def test_fv_no_slip_channel_shear_wave(tau, diagonal):
+    """The wall reset makes the wall a no-slip wall: the shear wave decays at the
+    Stokes rate with nu = c_s^2 tau_u and the wall force equals the viscous drag,
+    both converging at second order; the wall velocity is zero to round-off."""
+    res = {ny: _channel_shear_wave(ny, tau, diagonal=diagonal) for ny in (8, 16, 32)}
+    for ny in (8, 16, 32):
+        rate_err, f_err, u_wall, fy = res[ny]
+        assert abs(rate_err) < 2.4 / ny**2 and abs(f_err) < 0.8 / ny**2, (ny, res[ny])
+        assert u_wall < 1e-15 and fy < 1e-12
+    for a, b in ((8, 16), (16, 32)):
+        assert 3.5 < res[a][0] / res[b][0] < 4.5
+        assert 3.5 < res[a][1] / res[b][1] < 4.6
+
+
+@pytest.mark.parametrize("which,value", [(4, 0.0), (4, 0.5), (4, 1.2), (5, 0.0)])
+def test_fv_no_slip_planted_reset_fails(which, value):
+    """Dropping, scaling or skipping the reset's kept non-equilibrium part breaks the pin."""
+    with O.planted(which, value):
+        rate_err, f_err, _, _ = _channel_shear_wave(16, 0.56)
+    good = abs(rate_err) < 2.4 / 16**2 and abs(f_err) < 0.8 / 16**2
+    assert not good, (which, value, rate_err, f_err)
+
+
+# ---------------------------------------------------------------------------
 # Interpolation stencils, eqs. (8)-(9)
 # ---------------------------------------------------------------------------
 
@@ -430,6 +494,57 @@ def test_hybrid_taylor_green_mesh_factor():
         with O.planted(1, val):
             bad, _ = _tg_run(64, tau, 0.01, T, **_PATCH)
         assert bad[1] > 0.03
+
+
+def _acoustic_wave(x, L, amp, nu, t):
+    """Standing sound wave rho = 1 + amp cos(kx) e^(-g t)(cos wt + (g/w) sin wt), u from
+    continuity, of the isothermal Navier-Stokes equations the D2Q9 BGK scheme
+    approximates (viscous stress rho nu (grad u + grad u^T), so the longitudinal
+    damping is g = nu k^2), w^2 = c_s^2 k^2 - g^2; starts at rest."""
+    k = 2 * math.pi / L
+    g = nu * k * k
+    w = math.sqrt(k * k / 3.0 - g * g)
+    d = math.exp(-g * t)
+    rho = 1.0 + amp * np.cos(k * x) * d * (math.cos(w * t) + g / w * math.sin(w * t))
+    drho_dt = -amp * d * (w + g * g / w) * math.sin(w * t)
+    return rho, -drho_dt / k * np.sin(k * x), 0.0 * x
+
+
+def _hybrid_acoustic(L, tau, T, amp=1e-3):
+    """Relative L2 density errors (grid, mesh) of the standing wave on a periodic grid
+    with the jittered mesh patch after T steps."""
+    mesh, ein = _PATCH["mesh"], _PATCH["ein"]
+    o = O.Oracle(nx_cells=L, ny_cells=L, periodic=True, tau_s=tau, u_inf=0.0, mesh_xy=mesh[0],
+                 mesh_tri=mesh[1], mesh_kind=mesh[2], inner_ellipse=ein)
+    nu = (tau - 0.5) / 3.0
+    XX, YY = np.meshgrid(np.arange(L, dtype=float), np.arange(L, dtype=float))
+    o.set_level(0, feq_field(eq, *_acoustic_wave(XX, L, amp, nu, 0.0)))
+    o.set_mesh(feq_field(eq, *_acoustic_wave(mesh[0][:, 0], L, amp, nu, 0.0)))
+    o.step(T)
+    act = o.level_class(0) == 0
+    r, _, _ = macro(o.get_level(0))
+    er, _, _ = _acoustic_wave(XX, L, amp, nu, T)
+    e_grid = math.sqrt(((r - er) ** 2)[act].sum() / ((er - 1.0) ** 2)[act].sum())
+    r, _, _ = macro(o.get_mesh())
+    er, _, _ = _acoustic_wave(mesh[0][:, 0], L, amp, nu, T)
+    e_mesh = math.sqrt(((r - er) ** 2).sum() / ((er - 1.0) ** 2).sum())
+    return e_grid, e_mesh
+
+
+@pytest.mark.parametrize("tau", [0.56, 0.8])
+def test_hybrid_acoustic_wave_time_blend(tau):
+    """A sound wave changes by ~20 % per step at this wavelength, so the mesh must take
+    the structured values blended in time at theta = m/n (eqs. (5)-(7) solved
+    consistently in time): the hybrid run follows the closed form, while freezing the
+    blend at t or doubling or halving theta puts the mesh off by 5-14 %."""
+    L = 64
+    T = int(round(1.3 * L * math.sqrt(3.0)))     # 1.3 periods
+    e_grid, e_mesh = _hybrid_acoustic(L, tau, T)
+    assert e_grid < 0.02 and e_mesh < 0.02, (e_grid, e_mesh)
+    for v in (0.0, 0.5, 2.0):
+        with O.planted(6, v):
+            _, bad = _hybrid_acoustic(L, tau, T)
+        assert bad > 0.05, (v, bad)
 
 
 def test_hybrid_uniform_flow_preserved_wall_off():
