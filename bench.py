@@ -115,65 +115,179 @@ def measured_traffic(kernel):
         return None
 
 
-def roofline(rows, k, note, traffic=None):
+def roofline(rows, k, note, traffic=None, info=None):
     v = rows[k]
-    return {"bound": "hbm", "kernel": k, "achieved": v["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(v["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "alg_bytes_per_launch": v["alg_bytes"], "avg_launch_us": v["avg_us"], "note": note}
+    out = {"bound": "hbm", "kernel": k, "achieved": v["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(v["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "alg_bytes_per_launch": v["alg_bytes"], "avg_launch_us": v["avg_us"], "note": note}
+    if k == "fv_substep" and info is not None:
+        # what this implementation's layout moves if nothing stays on chip between sub-steps
+        # (records with stored moments, padded neighbour table), for comparison with traffic
+        out["layout_bytes_per_launch"] = int(info.fv_layout_bytes) * max(1, int(info.fv_fuse))
+    return out
 
 
-def adjoint_cost(hlbm, torch, workloads, t_end=2000, ckpt=500):
+def adjoint_cost(hlbm, torch, workloads, t_end=25000, ckpt=500, fd=False):
     """(objective run + discrete adjoint) time over a plain forward of the same steps.
 
     Workload: Re = 1000, c = 128, 5 deg, eight seeded Hicks-Henne bumps
     (1024x512 base grid, one 384x192 box, 512x64 mesh), FP64, J = mean C_D over
-    the last fifth of the run, gradient w.r.t. angle of attack, tau and the mesh
-    coordinates (shape).  The run is shortened from 25,000 to t_end steps to keep
-    the benchmark within minutes; the cost per step does not depend on the length."""
+    finest steps [0.8 t_end, t_end), checkpoints every `ckpt` steps; gradient
+    w.r.t. angle of attack, tau and the eight bump amplitudes (the mesh carries
+    the bump tangent as its shape derivatives).  With fd, central differences
+    (h = 1e-6) of the GPU forward check dJ/d alpha and two amplitudes."""
     w = workloads.naca_re1000_c128_bumps()
-    progress("adjoint cost")
-    sim = hlbm.HLBM.from_workload(w, precision=hlbm.FP64, history_len=t_end + 8)
+    tan = w.omesh.bump_tangent(workloads.HH_PEAKS)
+    progress(f"adjoint cost, {t_end} finest steps")
+    sim = hlbm.HLBM.from_workload(w, precision=hlbm.FP64, history_len=t_end + 8, dxy_dshape=tan)
     sim.step(20)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(t_end)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
+    progress(f"forward {t_fwd:.2f} s")
     spec = dict(t_end=t_end, t0=t_end * 4 // 5, t1=t_end, ckpt_every=ckpt, w_cd=1.0, w_cl=0.0)
-    out = {"workload": w.name, "finest_steps": t_end, "ckpt_every": ckpt, "precision": "fp64",
-           "forward_s": round(t_fwd, 4)}
+    out = {"workload": w.name, "finest_steps": t_end, "window": [spec["t0"], spec["t1"]], "ckpt_every": ckpt,
+           "precision": "fp64", "forward_s": round(t_fwd, 4)}
+    # workspace and transposed tables once, outside the timed runs
+    sim.reserve_objective(**spec, mesh_grad=True)
+    warm = dict(spec, t_end=2 * ckpt, t0=ckpt, t1=2 * ckpt)
+    sim.run_objective(**warm, mesh_grad=True)
+    sim.adjoint()
     for mesh_grad in (False, True):
-        sim.run_objective(**spec, mesh_grad=mesh_grad)   # warm-up (workspace, tables)
-        sim.adjoint()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sim.run_objective(**spec, mesh_grad=mesh_grad)
+        J = sim.run_objective(**spec, mesh_grad=mesh_grad)
         t1 = time.perf_counter()
         g = sim.adjoint()
         t2 = time.perf_counter()
         key = "with_shape" if mesh_grad else "aoa_tau"
         out[key] = {"ratio": round((t2 - t0) / t_fwd, 3), "objective_run_s": round(t1 - t0, 4),
-                    "adjoint_s": round(t2 - t1, 4), "grad_aoa_tau": [float(g[0]), float(g[1])]}
+                    "adjoint_s": round(t2 - t1, 4), "J": J, "grad_aoa_tau": [float(g[0]), float(g[1])]}
         if mesh_grad:
-            gb = np.einsum("mnk,nk->m", w.omesh.bump_tangent(workloads.HH_PEAKS), sim.grad_xy)
-            out[key]["grad_bumps"] = [float(v) for v in gb]
+            out[key]["grad_bumps"] = [float(v) for v in g[2:]]
+        progress(f"{key}: ratio {out[key]['ratio']}")
     sim.close()
     out["ratio"] = out["with_shape"]["ratio"]
-    out["note"] = "gradient of the windowed mean C_D w.r.t. angle of attack, tau and the 8 bump amplitudes"
+    if fd:
+        out["central_fd"] = adjoint_fd(hlbm, torch, workloads, w, spec, out["with_shape"])
+    out["note"] = ("gradient of the windowed mean C_D w.r.t. angle of attack, tau and the 8 bump amplitudes; "
+                   "ratio = (objective run + adjoint) / plain forward of the same finest steps")
     return out
 
 
-def cpu_baseline(w, base_steps):
-    from oracle import oracle as O
-    progress("oracle create (CPU baseline)")
-    o = O.Oracle.from_workload(w)
-    per = 2 ** w.n_refine
-    progress("oracle timed sample")
+def adjoint_fd(hlbm, torch, workloads, w, spec, adj, h=1e-6):
+    """Central differences of the GPU forward (FP64) for alpha and bumps 2 and 5."""
+    amps0 = workloads.hh_amplitudes(0)
+
+    def J(aoa=None, amps=None):
+        ww = w if amps is None else workloads.naca_re1000_c128_bumps(amps)
+        sim = hlbm.HLBM.from_workload(ww, precision=hlbm.FP64, history_len=spec["t_end"] + 8,
+                                      aoa_rad=ww.aoa_rad if aoa is None else aoa)
+        sim.step(spec["t_end"])
+        cd, _ = sim.history(spec["t0"], spec["t1"])
+        sim.close()
+        return float(np.mean(cd))
+
+    res = {"h": h}
+    fd_a = (J(aoa=w.aoa_rad + h) - J(aoa=w.aoa_rad - h)) / (2 * h)
+    res["aoa"] = {"fd": fd_a, "adjoint": adj["grad_aoa_tau"][0],
+                  "rel_diff": abs(fd_a - adj["grad_aoa_tau"][0]) / abs(fd_a)}
+    progress(f"fd alpha {res['aoa']}")
+    for m in (2, 5):
+        ap, am = amps0.copy(), amps0.copy()
+        ap[m] += h
+        am[m] -= h
+        fd_m = (J(amps=ap) - J(amps=am)) / (2 * h)
+        res[f"bump{m}"] = {"fd": fd_m, "adjoint": adj["grad_bumps"][m],
+                           "rel_diff": abs(fd_m - adj["grad_bumps"][m]) / abs(fd_m)}
+        progress(f"fd bump {m} {res[f'bump{m}']}")
+    return res
+
+
+def oracle_legs(preset, legs):
+    """Runs the FP64 oracle in a child process on a workload preset: per (threads,
+    finest steps) leg its wall time (create excluded)."""
+    import subprocess
+    cmd = [sys.executable, "-m", "oracle.oracle", preset] + [str(v) for leg in legs for v in leg]
+    out = subprocess.run(cmd, cwd=ROOT, check=True, capture_output=True, text=True).stdout
+    return json.loads(out.strip().splitlines()[-1])
+
+
+def gpu_seconds_per_step(hlbm, torch, w, precision, finest_steps):
+    sim = hlbm.HLBM.from_workload(w, precision=precision)
+    info = sim.info
+    sim.step(2 ** w.n_refine * 4)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    o.step(per * base_steps)
-    t1 = time.perf_counter()
-    progress(f"oracle sample {t1 - t0:.2f} s")
-    return o, t1 - t0
+    sim.step(finest_steps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / finest_steps
+    sim.close()
+    return dt, info
+
+
+def cpu_baseline(hlbm, torch, workloads, preset, w, r32, base_steps, c0_steps):
+    """The oracle as it stands, on the host cores: the bench workload (base_steps
+    base steps with all threads, one base step with one thread) and the Re = 100
+    workload (c0_steps finest steps with all threads and with one)."""
+    per = 2 ** w.n_refine
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    progress(f"oracle legs on the bench workload ({threads} threads, then 1)")
+    big = oracle_legs(preset, [(threads, per * base_steps), (1, per)])
+    su = r32["struct_updates"]                      # structured node updates per base step (all levels)
+    fvu = r32["fv_updates"]                         # FV node-substeps per base step
+    legs = []
+    for leg in big["legs"]:
+        n_base = leg["finest_steps"] / per
+        legs.append({"workload": w.name, "threads": leg["threads"], "finest_steps": leg["finest_steps"],
+                     "seconds": round(leg["seconds"], 3),
+                     "mlups": round(su * n_base / leg["seconds"] / 1e6, 2),
+                     "fv_msubsteps_per_s": round(fvu * n_base / leg["seconds"] / 1e6, 2)})
+    w0 = workloads.naca_re100_c40()
+    progress(f"oracle legs on the Re 100 workload ({c0_steps} steps, {threads} threads, then 1)")
+    small = oracle_legs("naca_re100_c40", [(threads, c0_steps), (1, c0_steps)])
+    g_dt, info0 = gpu_seconds_per_step(hlbm, torch, w0, hlbm.FP64, c0_steps)
+    su0 = int(info0.active_nodes[0])
+    fvu0 = int(info0.n_sub) * int(info0.n_mesh_nodes)
+    for leg in small["legs"]:
+        legs.append({"workload": w0.name, "threads": leg["threads"], "finest_steps": leg["finest_steps"],
+                     "seconds": round(leg["seconds"], 3),
+                     "mlups": round(su0 * leg["finest_steps"] / leg["seconds"] / 1e6, 2),
+                     "fv_msubsteps_per_s": round(fvu0 * leg["finest_steps"] / leg["seconds"] / 1e6, 2)})
+    gpu_c0 = {"workload": w0.name, "precision": "fp64", "finest_steps": c0_steps,
+              "ms_per_finest_step": round(1e3 * g_dt, 4), "mlups": round(su0 / g_dt / 1e6, 2),
+              "fv_msubsteps_per_s": round(fvu0 / g_dt / 1e6, 2)}
+    main_leg = legs[0]
+    return {"value": main_leg["mlups"], "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{base_steps} base steps = {per * base_steps} finest steps of the same workload in FP64 "
+                      f"with {threads} OpenMP threads (structured levels, {int(r32['info'].n_sub)} FV sub-steps "
+                      f"per finest step, coupling, forces), {main_leg['seconds']} s wall",
+            "seconds": main_leg["seconds"], "legs": legs, "gpu_same_legs_re100_fp64": gpu_c0}
+
+
+def drift(hlbm, torch, w, finest_steps):
+    """C_D and C_L of the bench workload over `finest_steps` finest steps in FP32-shifted
+    and FP64 storage: means over the second half and their differences."""
+    out = {"finest_steps": finest_steps, "window": [finest_steps // 2, finest_steps]}
+    hist = {}
+    for name, prec in (("fp64", hlbm.FP64), ("fp32", hlbm.FP32_SHIFTED)):
+        sim = hlbm.HLBM.from_workload(w, precision=prec, history_len=finest_steps + 8, check_every=1000)
+        progress(f"drift run {name}")
+        sim.step_logged(finest_steps, name)
+        hist[name] = sim.history(0, finest_steps)
+        sim.close()
+    h = slice(finest_steps // 2, finest_steps)
+    for name in ("fp64", "fp32"):
+        cd, cl = hist[name]
+        out[name] = {"cd_mean": float(np.mean(cd[h])), "cl_mean": float(np.mean(cl[h])),
+                     "cd_min": float(np.min(cd[h])), "cd_max": float(np.max(cd[h])),
+                     "cl_min": float(np.min(cl[h])), "cl_max": float(np.max(cl[h]))}
+    d, s_ = out["fp64"], out["fp32"]
+    out["cd_mean_rel_err"] = abs(s_["cd_mean"] - d["cd_mean"]) / abs(d["cd_mean"])
+    out["cl_mean_err_over_max_abs_cl_cd"] = abs(s_["cl_mean"] - d["cl_mean"]) / max(abs(d["cl_mean"]), abs(d["cd_mean"]))
+    return out
 
 
 def main():
@@ -183,11 +297,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="naca_re5000_c512")
     ap.add_argument("--cpu-steps", type=int, default=16, help="base steps of the oracle sample (~10 s on 16 cores)")
+    ap.add_argument("--cpu-c0-steps", type=int, default=500,
+                    help="finest steps of the oracle legs on the Re 100 workload (its stated run is 2000)")
+    ap.add_argument("--drift-steps", type=int, default=0,
+                    help="also run the bench workload this many finest steps in both precisions and compare "
+                         "the means of C_D and C_L over the second half")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost measurement")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the adjoint cost measurement (prints its JSON object; for profiling)")
+    ap.add_argument("--adjoint-steps", type=int, default=25000,
+                    help="finest steps of the adjoint cost run (the adjoint workload's length is 25,000)")
+    ap.add_argument("--adjoint-fd", action="store_true",
+                    help="also check the adjoint gradient against central differences of the GPU forward")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB five times (calibrates HBM byte counters)")
     a = ap.parse_args()
@@ -201,7 +324,7 @@ def main():
     w = workloads.PRESETS[a.workload]()
     per = 2 ** w.n_refine
     if a.adjoint_only:
-        print(json.dumps(adjoint_cost(hlbm, torch, workloads)))
+        print(json.dumps(adjoint_cost(hlbm, torch, workloads, a.adjoint_steps, fd=a.adjoint_fd)))
         return
     r32 = run_precision(w, hlbm.FP32_SHIFTED, a.steps, a.warmup, hlbm, torch)
     k32 = kernel_table(r32)
@@ -228,11 +351,14 @@ def main():
                    "precision": "fp32_shifted_fp64_forces"},
     }
     dom = max(k32, key=lambda k: k32[k]["share"])
-    res["roofline"] = roofline(k32, dom, "dominant kernel by time share; algorithmic bytes per launch (for the "
-                                         "FV kernel: fv_fuse sub-steps) over the mean of back-to-back launches "
-                                         "timed with HIP events; traffic = calibrated FETCH_SIZE + WRITE_SIZE "
-                                         "bytes per launch",
-                               measured_traffic(dom) if w.name == "naca0012_re5000_c512_8192x4096_r1" else None)
+    res["roofline"] = roofline(k32, dom, "dominant kernel by time share; algorithmic bytes per launch (FV: per "
+                                         "node-sub-step 9 populations in and out, own coefficients and row "
+                                         "pointer, column and (G_x, G_y, C) per neighbour entry; fv_fuse "
+                                         "sub-steps per launch) over the mean of back-to-back launches timed "
+                                         "with HIP events; traffic = calibrated FETCH_SIZE + WRITE_SIZE bytes "
+                                         "per launch",
+                               measured_traffic(dom) if w.name == "naca0012_re5000_c512_8192x4096_r1" else None,
+                               info=r32["info"])
     res["roofline_base_grid"] = roofline(k32, "collide_l0", "base-level fused stream-collide (72 B per node)",
                                          measured_traffic("collide_l0") if w.name == "naca0012_re5000_c512_8192x4096_r1" else None)
     res["kernels_fp32"] = k32
@@ -259,9 +385,13 @@ def main():
         cl32, cl64 = r32["cl"][:n], r64["cl"][:n]
         res["fp32_vs_fp64"] = {
             "finest_steps": int(n),
-            "cd_fp64_last": float(cd64[-1]), "cl_fp64_last": float(cl64[-1]),
-            "cd_rel_err_last": float(abs(cd32[-1] - cd64[-1]) / abs(cd64[-1])),
-            "cl_rel_err_last": float(abs(cl32[-1] - cl64[-1]) / max(abs(cl64[-1]), abs(cd64[-1]))),
+            "window": "every finest step of the two bench runs from the initial state: the impulsive start, "
+                      "not a settled flow (--drift-steps compares the means of a longer run)",
+            "cd_mean_fp64": float(np.mean(cd64)), "cl_mean_fp64": float(np.mean(cl64)),
+            "cd_mean_rel_err": float(abs(np.mean(cd32) - np.mean(cd64)) / abs(np.mean(cd64))),
+            "cl_mean_err_over_max_abs_cl_cd": float(abs(np.mean(cl32) - np.mean(cl64)) /
+                                                    max(abs(np.mean(cl64)), abs(np.mean(cd64)))),
+            "cd_max_rel_err_per_step": float(np.max(np.abs(cd32 - cd64) / np.abs(cd64))),
         }
         r64["sim"].close()
     if a.copy_probe:
@@ -274,18 +404,11 @@ def main():
         res["copy_probe_bytes_each_way"] = n * 4
         del src, dst
     if not a.no_adjoint:
-        res["adjoint_over_forward"] = adjoint_cost(hlbm, torch, workloads)
+        res["adjoint_over_forward"] = adjoint_cost(hlbm, torch, workloads, a.adjoint_steps, fd=a.adjoint_fd)
+    if a.drift_steps:
+        res["fp32_vs_fp64_drift"] = drift(hlbm, torch, w, a.drift_steps)
     if not a.no_cpu:
-        o, tc = cpu_baseline(w, a.cpu_steps)
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        res["cpu_baseline"] = {
-            "value": round(r32["struct_updates"] * a.cpu_steps / tc / 1e6, 2), "unit": "MLUPS",
-            "cores": cores, "kind": "oracle",
-            "sample": f"{a.cpu_steps} base step(s) = {per * a.cpu_steps} finest steps of the same "
-                      f"workload in FP64 (structured levels, {int(r32['info'].n_sub)} FV sub-steps "
-                      f"per finest step, coupling, forces), {tc:.2f} s wall",
-            "seconds": round(tc, 3)}
-        o.close()
+        res["cpu_baseline"] = cpu_baseline(hlbm, torch, workloads, a.workload, w, r32, a.cpu_steps, a.cpu_c0_steps)
     r32["sim"].close()
     print(json.dumps(res))
 

@@ -88,6 +88,9 @@ typedef struct {
     double chord;                 /* reference length of eqs. (10)-(11)                             */
     double inner_ellipse[4];      /* xc, yc, a, b of the inner fictitious ellipse; structured nodes
                                      strictly inside are inactive (a <= 0: none)                     */
+    int32_t n_shape;              /* shape parameters a_m of the discrete adjoint (0: none)         */
+    const double *dxy_dshape;     /* [n_shape][n_nodes][2] d(node x, y)/d a_m in the caller's node
+                                     order (borrowed, copied at create), or NULL when n_shape = 0   */
 } hlbm_mesh;
 
 typedef struct {
@@ -100,8 +103,12 @@ typedef struct {
     int32_t n_mesh_nodes, n_wall_nodes, n_interp_mesh, n_interp_struct, n_fallback;
     int32_t n_wall_edges, nnz;
     int64_t bytes_per_finest_step;    /* algorithmic bytes, all kernels                             */
-    int64_t k1_bytes[4];          /* algorithmic bytes of one collide-stream launch per level       */
-    int64_t fv_bytes;             /* algorithmic bytes of one FV sub-step                           */
+    int64_t k1_bytes[4];          /* algorithmic bytes of one collide-stream launch per level:
+                                     9 populations read and 9 written per active node               */
+    int64_t fv_bytes;             /* algorithmic bytes of one FV sub-step: per mesh node the 9
+                                     populations read and written, its own C_PP and G_PP, and
+                                     one row pointer; per neighbour entry its column index and
+                                     (G_x, G_y, C) -- what eq. (3) must move, whatever the layout    */
     int64_t t;                    /* finest steps done                                              */
     size_t workspace_bytes;
     int32_t fv_fuse;              /* FV sub-steps per launch (the HLBM_K_FV class of hlbm_profile_read
@@ -109,6 +116,9 @@ typedef struct {
     int32_t fv_tiles;             /* workgroups of one fused FV launch (tiles), 0 when fv_fuse = 1  */
     int32_t fv_tile_nodes;        /* nominal mesh nodes per tile                                    */
     int32_t fv_threads;           /* threads per fused-launch workgroup                             */
+    int64_t fv_layout_bytes;      /* bytes one unfused FV sub-step of this layout reads and writes:
+                                     node records with their stored moments (rho, u) in and out,
+                                     every slot of the padded neighbour table                       */
 } hlbm_info_t;
 
 /* Checks the problem on the host only (no GPU).  Re > 0 gives
@@ -121,15 +131,26 @@ int hlbm_validate(const hlbm_grid *grid, const hlbm_mesh *mesh, double Re, doubl
 int hlbm_workspace_size(const hlbm_grid *grid, const hlbm_mesh *mesh, double Re, double tau,
                         size_t *ws_bytes);
 
-/* Builds the context: host preprocessing (control volumes, stencils, node
- * order), copies the tables into d_workspace (device pointer, 256-byte
- * aligned, ws_bytes >= hlbm_workspace_size) and sets the initial state
- * f^eq(rho0, u_inf) (f^eq(rho0, 0) at wall nodes).  hip_stream is a
- * hipStream_t (NULL = default stream).  On failure *out is NULL. */
+/* Builds the context for the problem of Sec. 4: host preprocessing
+ * (median-dual control volumes and the S, C coefficients of eq. (3), the
+ * stencils of eqs. (8)-(9), node order), copies the tables into d_workspace
+ * (device pointer, 256-byte aligned, ws_bytes >= hlbm_workspace_size; the
+ * caller keeps ownership) and sets the initial state f^eq(rho0, u_inf) of
+ * eq. (2) (f^eq(rho0, 0) at wall nodes).  Re and tau as in hlbm_validate.
+ * hip_stream is a hipStream_t (NULL = default stream); all device work of the
+ * context goes on it.  Errors: those of hlbm_validate, HLBM_E_WORKSPACE,
+ * HLBM_E_DEVICE.  On failure *out is NULL and nothing is left allocated. */
 int hlbm_create(const hlbm_grid *grid, const hlbm_mesh *mesh, double Re, double tau,
                 void *d_workspace, size_t ws_bytes, void *hip_stream, hlbm_ctx **out);
 
-/* Advances n_finest_steps finest steps (a multiple of 2^n_refine).  Async. */
+/* Advances n_finest_steps finest steps (a multiple of 2^n_refine): per finest
+ * step the coupling of eq. (4), the collide-stream of eqs. (1)-(2) on every
+ * level with the subcycling and box transfers of Sec. 4, eq. (9), the n
+ * finite-volume sub-steps of eqs. (3) and (5)-(7), and the force of
+ * eqs. (10)-(11) into the history.  Async (enqueued on the context's stream).
+ * Errors: HLBM_E_ARG (count), HLBM_E_STATE (poisoned context),
+ * HLBM_E_NONFINITE (a non-finite force at a check_every boundary; the context
+ * is poisoned). */
 int hlbm_step(hlbm_ctx *ctx, int64_t n_finest_steps);
 
 /* Drag and lift coefficients of the last finest step (eqs. (10)-(11)).  Syncs. */
@@ -138,15 +159,21 @@ int hlbm_forces(hlbm_ctx *ctx, double *cd, double *cl);
 /* Coefficients of finest steps [t0, t1) (within the last history_len steps).  Syncs. */
 int hlbm_force_history(hlbm_ctx *ctx, int64_t t0, int64_t t1, double *cd, double *cl);
 
-/* Canonical state in FP64.  part = level l: pre-collision populations
- * [9][ny][nx] of level l, zero at nodes that are not collide-stream nodes;
- * part = HLBM_PART_MESH: mesh populations [9][n_nodes] in the caller's node
- * order.  count = number of doubles.  Syncs. */
+/* Canonical state in FP64: the populations f_i of eq. (1) (structured) and of
+ * eq. (3) (mesh) after the last finest step.  part = level l: pre-collision
+ * populations [9][ny][nx] of level l (host array, row-major, x fastest), zero
+ * at nodes that are not collide-stream nodes; part = HLBM_PART_MESH: mesh
+ * populations [9][n_nodes] in the caller's node order.  count = number of
+ * doubles (HLBM_E_ARG if it does not match).  FP32-shifted contexts return
+ * w_i rho0 + the stored value.  Syncs. */
 int hlbm_get_state(hlbm_ctx *ctx, int32_t part, double *host, size_t count);
 
-/* Replaces a part of the state (same layout as hlbm_get_state; on a level,
- * values at non-collide-stream nodes are ignored).  Set every level and the
- * mesh before stepping on.  Syncs. */
+/* Replaces a part of the state of eqs. (1) and (3) (same layout and count
+ * rule as hlbm_get_state; on a level, values at non-collide-stream nodes are
+ * ignored; copied from the borrowed host array).  Set every level and the
+ * mesh before stepping on: the next step rebuilds the derived values (box
+ * transfers of Sec. 4, eq. (9) at t) from them.  Ends wall statistics.
+ * Syncs. */
 int hlbm_set_state(hlbm_ctx *ctx, int32_t part, const double *host, size_t count);
 
 int hlbm_info(hlbm_ctx *ctx, hlbm_info_t *out);
@@ -179,17 +206,25 @@ int hlbm_objective_workspace_size(hlbm_ctx *ctx, const hlbm_objective *obj, size
  * returns J.  Syncs. */
 int hlbm_run_objective(hlbm_ctx *ctx, const hlbm_objective *obj, void *d_ckpt, size_t ckpt_bytes, double *J);
 
-/* Discrete adjoint of the last hlbm_run_objective: grad[0] = J_bar dJ/d aoa_rad,
- * grad[1] = J_bar dJ/d tau (finest-level relaxation time; the number of FV
- * sub-steps is held fixed).  With the objective's mesh_grad set, grad_xy
- * (host, 2 * n_nodes doubles, caller's node order, (x, y) pairs) receives
- * J_bar dJ/d(mesh coordinates) through the finite-volume coefficients of
+/* Discrete adjoint of the last hlbm_run_objective, reverse mode over the
+ * forward kernels (eqs. (1)-(11) as implemented), FP64 accumulation,
+ * deterministic.  grad (host, 2 + n_shape doubles):
+ *   grad[0]      = J_bar dJ/d aoa_rad,
+ *   grad[1]      = J_bar dJ/d tau (finest-level relaxation time; the number of
+ *                  FV sub-steps is held fixed),
+ *   grad[2 + m]  = J_bar dJ/d a_m = J_bar sum over nodes of dJ/d(x, y) .
+ *                  dxy_dshape[m] (the mesh's shape parameters), when the
+ *                  objective's mesh_grad is set; NaN (not computed) otherwise.
+ * The mesh-coordinate gradient runs through the finite-volume coefficients of
  * eq. (3), the wall normals of eqs. (10)-(11) and the interpolation weights of
- * eqs. (8)-(9), with node kinds, connectivity, stencil donors and the
- * inactive structured region held fixed; grad_xy must be NULL otherwise
- * (HLBM_E_ARG).  Reverse mode over the forward kernels (eqs. (1)-(11) as
- * implemented), FP64 accumulation, deterministic.  Leaves the context in a
- * mid-run state: run the objective again before another adjoint.  Syncs. */
+ * eqs. (8)-(9), with node kinds, connectivity, stencil donors and the inactive
+ * structured region held fixed.  grad_xy (host, 2 * n_nodes doubles, caller's
+ * node order, (x, y) pairs) optionally receives J_bar dJ/d(mesh coordinates)
+ * itself when mesh_grad is set (NULL: not wanted); it must be NULL otherwise
+ * (HLBM_E_ARG).  Afterwards the context holds the state at t_end of the
+ * objective run again (as after hlbm_run_objective), so stepping, forces and
+ * state export continue from there; a second adjoint needs a new objective
+ * run (HLBM_E_STATE).  Syncs. */
 int hlbm_adjoint(hlbm_ctx *ctx, double J_bar, double *grad, double *grad_xy);
 
 /* Mean wall coefficients, eqs. (12)-(13).  After hlbm_wall_stats_begin, every

@@ -489,3 +489,37 @@ def objective_derivative(w, spec, *, aoa=None, tau_s=None, d_aoa=0.0, d_tau=0.0,
     J = np.mean(spec["w_cd"] * cd[s] + spec["w_cl"] * cl[s])
     o.close()
     return float(J.real), float(J.imag / h)
+
+
+# ---------------------------------------------------------------------------
+# timing of the oracle as it stands (the benchmark's CPU baseline)
+# ---------------------------------------------------------------------------
+
+def time_workload(preset: str, legs) -> dict:
+    """Wall time of the oracle on a workload preset, from its initial state
+    (create excluded): for each (threads, finest_steps) of `legs`, in order, that
+    many finest steps with that many OpenMP threads (the state carries on from
+    one leg to the next; the cost of a step does not depend on it)."""
+    import ctypes.util
+    import time
+    from paper_2006_10487_amd import workloads as W
+    lib()
+    gomp = C.CDLL(ctypes.util.find_library("gomp") or "libgomp.so.1")
+    w = W.PRESETS[preset]()
+    o = Oracle.from_workload(w)
+    out = {"preset": preset, "workload": w.name, "legs": []}
+    for threads, steps in legs:
+        gomp.omp_set_num_threads(int(threads))
+        t0 = time.perf_counter()
+        o.step(int(steps))
+        out["legs"].append({"threads": int(threads), "finest_steps": int(steps),
+                            "seconds": time.perf_counter() - t0})
+    o.close()
+    return out
+
+
+if __name__ == "__main__":
+    import json
+    import sys
+    args = sys.argv[2:]
+    print(json.dumps(time_workload(sys.argv[1], [(int(args[k]), int(args[k + 1])) for k in range(0, len(args), 2)])))

@@ -42,6 +42,7 @@ struct AdjState {
     int n_slots = 0, nd6 = 0;
     struct {
         size_t ckpt, ckpt_stride, ck_lev[4], ck_side[4], ck_mesh, ck_prep;
+        size_t fin, fin_prev[4];   // state at t_end: a checkpoint plus every level's previous buffer
         size_t seg_lev[4], seg_side[4], seg_mesh, seg_prep, seg_sub, sub, awork;
         size_t abar[4][2], prebar[4], sbar[4][2], vperim[4];
         size_t mbar[2], zwall[2], pbar[2], m5bar;
@@ -49,6 +50,7 @@ struct AdjState {
         size_t gbar, gpivot, vbar, w5bar, w6bar, total;
     } off{};
     bool tables = false, ran = false;
+    size_t tables_at[9] = {};            // offsets of the transposed tables when they were uploaded
     std::vector<int32_t> t5map, t6map;   // transposed entry -> index into sint_w / uint_w
     std::vector<int64_t> gmap;           // transposed FV slot z * nn + k -> forward slot z_P * nn + P, -1 = unused
     double J = 0.0;
@@ -127,6 +129,10 @@ void layout(hlbm_ctx* c, AdjState& a) {
     ck += a256(a.prep_bytes);
     a.off.ckpt_stride = ck;
     a.off.ckpt = take(ck * a.n_ckpt);
+    // the state at t_end, restored after the reverse sweep; state export pulls
+    // from the previous buffer of each level, so that one is kept as well
+    a.off.fin = take(ck);
+    for (int l = 0; l <= p.L; ++l) a.off.fin_prev[l] = take(a.lev_bytes[l]);
     // one segment: level l takes seg_base 2^l steps; one more slot for its state after the segment
     for (int l = 0; l <= p.L; ++l) {
         const int n = a.seg_base << l;
@@ -195,6 +201,39 @@ void layout(hlbm_ctx* c, AdjState& a) {
 int d2d(hlbm_ctx* c, void* dst, const void* src, size_t bytes) {
     if (!bytes) return HLBM_OK;
     return hip_check(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->s), "hipMemcpyAsync");
+}
+
+// Copies the context's current state into the final-state region.
+int save_final(hlbm_ctx* c, AdjState& a) {
+    const Plan& p = c->p;
+    int rc = HLBM_OK;
+    for (int l = 0; l <= p.L; ++l) {
+        rc |= d2d(c, a.ws + a.off.fin + a.off.ck_lev[l], c->lev(l, c->cur[l]), a.lev_bytes[l]);
+        rc |= d2d(c, a.ws + a.off.fin_prev[l], c->lev(l, 1 - c->cur[l]), a.lev_bytes[l]);
+        if (l < p.L) rc |= d2d(c, a.ws + a.off.fin + a.off.ck_side[l], c->side(l, c->side_t[l]), a.side_bytes[l]);
+    }
+    rc |= d2d(c, a.ws + a.off.fin + a.off.ck_mesh, c->mesh(c->mesh_cur), a.mesh_bytes);
+    rc |= d2d(c, a.ws + a.off.fin + a.off.ck_prep, c->prep(c->prep_t), a.prep_bytes);
+    return rc;
+}
+
+// Puts the state saved by save_final back into the context (time t_end).
+int restore_final(hlbm_ctx* c, AdjState& a) {
+    const Plan& p = c->p;
+    int rc = HLBM_OK;
+    for (int l = 0; l <= p.L; ++l) {
+        c->cur[l] = 0;
+        c->side_t[l] = 0;
+        rc |= d2d(c, c->lev(l, 0), a.ws + a.off.fin + a.off.ck_lev[l], a.lev_bytes[l]);
+        rc |= d2d(c, c->lev(l, 1), a.ws + a.off.fin_prev[l], a.lev_bytes[l]);
+        if (l < p.L) rc |= d2d(c, c->side(l, 0), a.ws + a.off.fin + a.off.ck_side[l], a.side_bytes[l]);
+    }
+    c->mesh_cur = 0;
+    c->prep_t = 0;
+    rc |= d2d(c, c->mesh(0), a.ws + a.off.fin + a.off.ck_mesh, a.mesh_bytes);
+    rc |= d2d(c, c->prep(0), a.ws + a.off.fin + a.off.ck_prep, a.prep_bytes);
+    c->t = a.obj.t_end;
+    return rc;
 }
 
 // Transposed tables of the reverse sweep, built from the plan.
@@ -626,7 +665,12 @@ int hlbm_run_objective(hlbm_ctx* c, const hlbm_objective* o, void* d_ckpt, size_
     if (!d_ckpt || (reinterpret_cast<uintptr_t>(d_ckpt) & 255) || ckpt_bytes < a.off.total)
         return set_err(c, HLBM_E_WORKSPACE, "objective workspace must be 256-byte aligned and hold " +
                                                 std::to_string(a.off.total) + " bytes");
-    if (!same_ws) a.tables = false;
+    // the tables sit after the checkpoints and segment buffers, so their offsets move
+    // with t_end, ckpt_every and store_substeps: upload again whenever they do
+    const size_t at[9] = {a.off.tedges, a.off.vwall, a.off.t5ptr, a.off.t5s, a.off.t5w,
+                          a.off.t6node, a.off.t6ptr, a.off.t6s, a.off.t6w};
+    if (!same_ws || std::memcmp(at, a.tables_at, sizeof(at)) != 0) a.tables = false;
+    std::memcpy(a.tables_at, at, sizeof(at));
     a.ws = static_cast<char*>(d_ckpt);
     a.bytes = ckpt_bytes;
     if (!a.tables && (rc = upload_tables(c, a))) return rc;
@@ -645,6 +689,7 @@ int hlbm_run_objective(hlbm_ctx* c, const hlbm_objective* o, void* d_ckpt, size_
         }
         level_step(c, 0);
     }
+    rc |= save_final(c, a);
     if (rc) return HLBM_E_DEVICE;
     a.cd.assign(size_t(o->t_end), 0.0);
     a.cl.assign(size_t(o->t_end), 0.0);
@@ -662,8 +707,8 @@ int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad, double* grad_xy) {
     if (!c || !grad) return HLBM_E_ARG;
     if (!c->adj || !c->adj->ran) return set_err(c, HLBM_E_STATE, "hlbm_run_objective must run first");
     AdjState& a = *c->adj;
-    if ((grad_xy != nullptr) != (a.obj.mesh_grad != 0))
-        return set_err(c, HLBM_E_ARG, "grad_xy must be given exactly when the objective asked for mesh_grad");
+    if (grad_xy && !a.obj.mesh_grad)
+        return set_err(c, HLBM_E_ARG, "grad_xy needs an objective run with mesh_grad set");
     const Plan& p = c->p;
     const hlbm_objective& o = a.obj;
     hipStream_t s = c->s;
@@ -733,6 +778,7 @@ int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad, double* grad_xy) {
     if (rc) return HLBM_E_DEVICE;
     grad[0] = J_bar * (acc[0] + alpha_host);
     grad[1] = J_bar * acc[1];
+    for (int m = 0; m < p.n_shape; ++m) grad[2 + m] = std::nan("");
     if (a.obj.mesh_grad) {
         // coefficient adjoints -> mesh coordinates (host, forward mode per local coordinate)
         std::vector<double> gt(size_t(3) * p.ell_width * p.nn), gb(gt.size(), 0.0);
@@ -766,12 +812,21 @@ int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad, double* grad_xy) {
         std::string err;
         const int grc = mesh_geometry_adjoint(p, gb.data(), vb.data(), w5.data(), w6.data(), gx.data(), err);
         if (grc) return set_err(c, grc, err);
-        for (size_t z = 0; z < gx.size(); ++z) grad_xy[z] = J_bar * gx[z];
+        if (grad_xy)
+            for (size_t z = 0; z < gx.size(); ++z) grad_xy[z] = J_bar * gx[z];
+        // shape parameters: contraction with the caller's d(x, y)/d a_m
+        for (int m = 0; m < p.n_shape; ++m) {
+            const double* d = p.dshape.data() + size_t(m) * gx.size();
+            double sum = 0.0;
+            for (size_t z = 0; z < gx.size(); ++z) sum += gx[z] * d[z];
+            grad[2 + m] = J_bar * sum;
+        }
     }
-    // the context now holds the state at the end of the first segment; restart from t_end
-    // requires a new objective run
+    // back to the state at t_end of the objective run; another adjoint needs a new run
     a.ran = false;
-    return HLBM_OK;
+    rc = restore_final(c, a);
+    rc |= hip_check(c, hipStreamSynchronize(s), "restore");
+    return rc ? HLBM_E_DEVICE : HLBM_OK;
 }
 
 }  // extern "C"

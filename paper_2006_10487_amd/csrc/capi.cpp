@@ -577,8 +577,12 @@ int hlbm_info(hlbm_ctx* c, hlbm_info_t* o) {
     o->n_fallback = p.n_fallback;
     o->n_wall_edges = int(p.wedge.size() / 2);
     o->nnz = int(p.col.size());
-    // FV sub-step: node records (populations + moments) in and out, CSR records, row pointers
-    o->fv_bytes = int64_t(p.nn) * 2 * kRec * E + int64_t(p.col.size()) * (E == 8 ? 32 : 16);
+    // FV sub-step of eq. (3), algorithmic: per node 9 populations in and out, its own
+    // (G_x, G_y, C) and a row pointer; per neighbour entry a column index and (G_x, G_y, C)
+    const int64_t nn = p.nn, nbr = int64_t(p.col.size()) - nn;
+    o->fv_bytes = nn * (2 * kQ * E + 3 * E + 4) + nbr * (4 + 3 * E);
+    // what this layout moves: records with stored moments in and out, every padded table slot
+    o->fv_layout_bytes = nn * 2 * kRec * E + nn * p.ell_width * (E == 8 ? 32 : 16);
     o->bytes_per_finest_step = bytes / (int64_t(1) << p.L) + int64_t(p.n_sub) * o->fv_bytes;
     o->t = c->t;
     o->workspace_bytes = p.off.total;

@@ -81,7 +81,11 @@ struct Plan {
     // mesh interpolation nodes <- finest level, eq. (9)
     std::vector<int32_t> uint_don;       // kUDon per slot, finest node i + nx * j, -1 = unused
     std::vector<double> uint_w;
-    // the caller's mesh (caller order), kept for the shape adjoint
+    // the caller's mesh (caller order), kept for the shape adjoint, and the
+    // derivatives of its coordinates with respect to n_shape shape parameters
+    // ([n_shape][n_nodes][2], caller order)
+    int n_shape = 0;
+    std::vector<double> dshape;
     std::vector<double> mxy;
     std::vector<int32_t> mtri;
     std::vector<std::array<int, 2>> mbnd;   // boundary edges, fluid on the left

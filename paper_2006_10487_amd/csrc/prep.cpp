@@ -756,6 +756,10 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
         if (rc) return rc;
         p.mxy.assign(m->xy, m->xy + 2 * size_t(nn));
         p.mtri.assign(m->tri, m->tri + 3 * size_t(nt));
+        if (m->n_shape < 0 || (m->n_shape > 0 && !m->dxy_dshape))
+            return fail(err, HLBM_E_ARG, "n_shape must be >= 0, with dxy_dshape given when it is positive");
+        p.n_shape = m->n_shape;
+        if (p.n_shape > 0) p.dshape.assign(m->dxy_dshape, m->dxy_dshape + size_t(p.n_shape) * 2 * nn);
         p.mbnd = bnd;
         std::vector<int> rp(nn + 1, 0), cl(ent.size());
         for (const Entry& e : ent) rp[e.p + 1]++;

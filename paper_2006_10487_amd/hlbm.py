@@ -57,6 +57,7 @@ class Mesh(C.Structure):
         ("n_nodes", C.c_int32), ("n_tris", C.c_int32),
         ("xy", C.POINTER(C.c_double)), ("tri", C.POINTER(C.c_int32)), ("kind", C.POINTER(C.c_uint8)),
         ("chord", C.c_double), ("inner_ellipse", C.c_double * 4),
+        ("n_shape", C.c_int32), ("dxy_dshape", C.POINTER(C.c_double)),
     ]
 
 
@@ -76,7 +77,7 @@ class Info(C.Structure):
         ("nnz", C.c_int32), ("bytes_per_finest_step", C.c_int64), ("k1_bytes", C.c_int64 * 4),
         ("fv_bytes", C.c_int64), ("t", C.c_int64), ("workspace_bytes", C.c_size_t),
         ("fv_fuse", C.c_int32), ("fv_tiles", C.c_int32), ("fv_tile_nodes", C.c_int32),
-        ("fv_threads", C.c_int32),
+        ("fv_threads", C.c_int32), ("fv_layout_bytes", C.c_int64),
     ]
 
 
@@ -125,8 +126,12 @@ def _np_ptr(a):
 def make_structs(nx_cells, ny_cells, patches=(), *, u_inf=0.05, aoa_rad=0.0, rho0=1.0,
                  precision=FP64, interp=INTERP_QUADRATIC, n_sub=0, periodic=False, wall_bc=True,
                  check_every=0, history_len=0, fv_fuse=0, mesh_xy=None, mesh_tri=None, mesh_kind=None,
-                 chord=1.0, inner_ellipse=None):
-    """ctypes Grid and Mesh (plus the arrays they point into, kept alive)."""
+                 chord=1.0, inner_ellipse=None, dxy_dshape=None):
+    """ctypes Grid and Mesh (plus the arrays they point into, kept alive).
+
+    dxy_dshape: optional [n_shape, n_nodes, 2] derivatives of the node
+    coordinates with respect to shape parameters; the adjoint then returns
+    dJ/d(parameter) for each of them."""
     g = Grid()
     g.nx_cells, g.ny_cells, g.n_refine = nx_cells, ny_cells, len(patches)
     for k, (i0, j0, px, py) in enumerate(patches):
@@ -147,6 +152,11 @@ def make_structs(nx_cells, ny_cells, patches=(), *, u_inf=0.05, aoa_rad=0.0, rho
         m.xy = xy.ctypes.data_as(C.POINTER(C.c_double))
         m.tri = tri.ctypes.data_as(C.POINTER(C.c_int32))
         m.kind = kind.ctypes.data_as(C.POINTER(C.c_uint8))
+        if dxy_dshape is not None:
+            d = np.ascontiguousarray(dxy_dshape, dtype=np.float64).reshape(-1, xy.shape[0], 2)
+            keep.append(d)
+            m.n_shape = d.shape[0]
+            m.dxy_dshape = d.ctypes.data_as(C.POINTER(C.c_double))
     m.chord = chord
     ein = inner_ellipse if inner_ellipse is not None else (0.0, 0.0, 0.0, 0.0)
     for k in range(4):
@@ -210,11 +220,12 @@ class HLBM:
 
     @classmethod
     def from_workload(cls, w, *, precision=FP64, interp=INTERP_QUADRATIC, n_sub=0, wall_bc=True,
-                      aoa_rad=None, tau=None, check_every=0, history_len=0, fv_fuse=0, stream=None):
+                      aoa_rad=None, tau=None, check_every=0, history_len=0, fv_fuse=0, stream=None,
+                      dxy_dshape=None):
         g, m, keep = structs_from_workload(
             w, precision=precision, interp=interp, n_sub=n_sub or w.n_sub, wall_bc=wall_bc,
             aoa_rad=w.aoa_rad if aoa_rad is None else aoa_rad, check_every=check_every,
-            history_len=history_len, fv_fuse=fv_fuse)
+            history_len=history_len, fv_fuse=fv_fuse, dxy_dshape=dxy_dshape)
         return cls(g, m, tau=w.tau_s if tau is None else tau, keep=keep, stream=stream)
 
     def _check(self, rc):
@@ -305,14 +316,8 @@ class HLBM:
         self._check(lib().hlbm_kernel_bench(self._ctx, KERNEL_CLASSES.index(kclass), int(n), C.byref(ms)))
         return ms.value
 
-    def run_objective(self, t_end: int, t0: int, t1: int, ckpt_every: int = 100, w_cd: float = 1.0,
-                      w_cl: float = 0.0, mesh_grad: bool = False, store_substeps=None) -> float:
-        """Run from the initial state and return the windowed mean of w_cd C_D + w_cl C_L.
-
-        mesh_grad: the following adjoint also returns d J / d(mesh coordinates).
-        store_substeps: keep the FV sub-step states of a segment instead of
-        recomputing them (None: when the workspace stays under half the free
-        device memory)."""
+    def _prepare_objective(self, t_end, t0, t1, ckpt_every, w_cd, w_cl, mesh_grad, store_substeps):
+        """Objective struct and a workspace that holds it (allocated or grown here)."""
         import torch
         o = Objective(int(t_end), int(t0), int(t1), int(ckpt_every), float(w_cd), float(w_cl), int(bool(mesh_grad)), 0)
         n = C.c_size_t(0)
@@ -327,6 +332,23 @@ class HLBM:
         if getattr(self, "obj_ws", None) is None or self.obj_ws.numel() < n.value:
             self.obj_ws = None   # release the smaller workspace first
             self.obj_ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        return o
+
+    def reserve_objective(self, t_end: int, t0: int, t1: int, ckpt_every: int = 100, w_cd: float = 1.0,
+                          w_cl: float = 0.0, mesh_grad: bool = False, store_substeps=None):
+        """Allocate the objective workspace of run_objective(same arguments) without running it."""
+        self._prepare_objective(t_end, t0, t1, ckpt_every, w_cd, w_cl, mesh_grad, store_substeps)
+
+    def run_objective(self, t_end: int, t0: int, t1: int, ckpt_every: int = 100, w_cd: float = 1.0,
+                      w_cl: float = 0.0, mesh_grad: bool = False, store_substeps=None) -> float:
+        """Run from the initial state and return the windowed mean of w_cd C_D + w_cl C_L.
+
+        mesh_grad: the following adjoint also returns d J / d(mesh coordinates)
+        and the shape-parameter gradient.
+        store_substeps: keep the FV sub-step states of a segment instead of
+        recomputing them (None: when the workspace stays under half the free
+        device memory)."""
+        o = self._prepare_objective(t_end, t0, t1, ckpt_every, w_cd, w_cl, mesh_grad, store_substeps)
         self._objective = o
         J = C.c_double()
         self._check(lib().hlbm_run_objective(self._ctx, C.byref(o), C.c_void_p(self.obj_ws.data_ptr()),
@@ -334,18 +356,19 @@ class HLBM:
         return J.value
 
     def adjoint(self, j_bar: float = 1.0) -> np.ndarray:
-        """[dJ/d aoa_rad, dJ/d tau] of the last run_objective (discrete adjoint).
+        """[dJ/d aoa_rad, dJ/d tau, dJ/d a_0, ..] of the last run_objective (discrete
+        adjoint), one entry per shape parameter of the mesh (NaN unless the
+        objective asked for mesh_grad).
 
         When that objective asked for mesh_grad, d J / d(mesh coordinates) of
-        the caller's nodes is left in ``self.grad_xy`` ([n_nodes, 2])."""
-        g = np.zeros(2)
+        the caller's nodes is left in ``self.grad_xy`` ([n_nodes, 2]).  The
+        context is back at the end of the objective run afterwards."""
+        g = np.zeros(2 + int(self.mesh.n_shape))
+        gxy = np.zeros((self.n_nodes, 2)) if self._objective.mesh_grad else None
         self.grad_xy = None
-        if self._objective.mesh_grad:
-            gxy = np.zeros((self.n_nodes, 2))
-            self._check(lib().hlbm_adjoint(self._ctx, float(j_bar), _np_ptr(g), _np_ptr(gxy)))
-            self.grad_xy = gxy
-        else:
-            self._check(lib().hlbm_adjoint(self._ctx, float(j_bar), _np_ptr(g), None))
+        self._check(lib().hlbm_adjoint(self._ctx, float(j_bar), _np_ptr(g),
+                                       None if gxy is None else _np_ptr(gxy)))
+        self.grad_xy = gxy
         return g
 
     def wall_stats_begin(self):
@@ -424,34 +447,34 @@ def objective_function():
     Hicks-Henne amplitudes (or None for a fixed shape), ``build`` a callable
     mapping the amplitudes (numpy array or None) to a workload whose ``omesh``
     provides ``bump_tangent``, and ``spec`` a dict with t_end, t0, t1,
-    ckpt_every, w_cd, w_cl.  forward runs the GPU objective; backward runs the
-    discrete adjoint of the same run and, for the amplitudes, contracts the
-    mesh-coordinate gradient with the generator's bump tangent.
+    ckpt_every, w_cd, w_cl.  forward runs the GPU objective on a mesh that
+    carries the generator's bump tangent as its shape derivatives; backward
+    runs the discrete adjoint of the same run, which returns the gradient with
+    respect to the angle, tau and every amplitude.
     """
     import torch
 
     class HLBMObjective(torch.autograd.Function):
         @staticmethod
         def forward(ctx, aoa, tau, bumps, build, spec):
+            from . import workloads
             amps = None if bumps is None else bumps.detach().cpu().numpy().astype(np.float64)
             w = build(amps)
-            sim = HLBM.from_workload(w, aoa_rad=float(aoa), tau=float(tau), precision=FP64,
-                                     history_len=max(65536, int(spec["t_end"])))
             want_shape = bumps is not None and ctx.needs_input_grad[2]
+            tan = None
+            if want_shape:
+                peaks = getattr(build, "peaks", None)
+                tan = w.omesh.bump_tangent(workloads.HH_PEAKS if peaks is None else peaks)
+            sim = HLBM.from_workload(w, aoa_rad=float(aoa), tau=float(tau), precision=FP64,
+                                     history_len=max(65536, int(spec["t_end"])), dxy_dshape=tan)
             J = sim.run_objective(**spec, mesh_grad=want_shape)
-            ctx.sim, ctx.w, ctx.want_shape = sim, w, want_shape
-            ctx.peaks = getattr(build, "peaks", None)
+            ctx.sim, ctx.want_shape = sim, want_shape
             return torch.tensor(J, dtype=torch.float64)
 
         @staticmethod
         def backward(ctx, g):
             grad = ctx.sim.adjoint(float(g))
-            gb = None
-            if ctx.want_shape:
-                from . import workloads
-                peaks = ctx.peaks if ctx.peaks is not None else workloads.HH_PEAKS
-                tan = ctx.w.omesh.bump_tangent(peaks)           # [m, n_nodes, 2]
-                gb = torch.tensor(np.einsum("mnk,nk->m", tan, ctx.sim.grad_xy), dtype=torch.float64)
+            gb = torch.tensor(grad[2:], dtype=torch.float64) if ctx.want_shape else None
             ctx.sim.close()
             return (torch.tensor(grad[0], dtype=torch.float64), torch.tensor(grad[1], dtype=torch.float64),
                     gb, None, None)

@@ -33,7 +33,8 @@ def test_header_symbols_exported(lib):
 def test_struct_sizes_match_header(lib):
     # hlbm_grid: 15 int32 (60 B, padded to 64), 3 doubles, 8 int32
     assert C.sizeof(hlbm.Grid) == 64 + 3 * 8 + 8 * 4
-    assert C.sizeof(hlbm.Mesh) == 4 + 4 + 3 * 8 + 8 + 32
+    # hlbm_mesh: 2 int32, 3 pointers, 5 doubles, int32 n_shape (padded to 8), 1 pointer
+    assert C.sizeof(hlbm.Mesh) == 4 + 4 + 3 * 8 + 8 + 32 + 8 + 8
 
 
 def test_struct_layouts_match_compiled_header(tmp_path):

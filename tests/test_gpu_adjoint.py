@@ -131,6 +131,72 @@ def test_shape_gradient_matches_oracle():
     assert np.array_equal(sim2.adjoint(), g)
 
 
+def test_shape_parameters_through_the_abi():
+    """With the bump tangent passed as the mesh's shape derivatives, the adjoint
+    returns dJ/d a_m itself: equal to the contraction of the coordinate gradient
+    and, for one amplitude, to the oracle's complex-step derivative."""
+    amps = W.hh_amplitudes(0)
+    w = W.naca_re100_c40(3.0, bumps=amps)
+    tan = w.omesh.bump_tangent(W.HH_PEAKS)
+    sim = hlbm.HLBM.from_workload(w, n_sub=N_SUB, dxy_dshape=tan)
+    sim.run_objective(**SPEC, mesh_grad=True)
+    g = sim.adjoint()
+    assert g.shape == (2 + len(W.HH_PEAKS),)
+    ref = np.einsum("mnk,nk->m", tan, sim.grad_xy)
+    assert np.allclose(g[2:], ref, rtol=1e-12, atol=1e-15 * np.abs(ref).max())
+    _, d5 = O.objective_derivative(w, OSPEC, d_xy=tan[5], n_sub=N_SUB)
+    print(f"dJ/da_5: adjoint {g[7]!r} oracle {d5!r} ({rel(g[7], d5):.2e})", flush=True)
+    assert rel(g[7], d5) < GRAD_TOL
+    # without mesh_grad the shape entries are not computed
+    sim.run_objective(**SPEC)
+    g2 = sim.adjoint()
+    assert np.array_equal(g2[:2], g[:2]) and np.isnan(g2[2:]).all()
+
+
+@pytest.mark.parametrize("refined", [False, True])
+def test_adjoint_leaves_the_state_at_t_end(refined):
+    """After the adjoint the context is back at the end of the objective run:
+    same time, forces and state, and stepping on gives the bits of a plain run."""
+    w = (W.naca_re100_c40_refined if refined else W.naca_re100_c40)(3.0)
+    _, sim = gpu_J(w, w.aoa_rad, w.tau_s)
+    parts = list(range(sim.info.n_levels)) + [hlbm.PART_MESH]
+    before = [sim.get_state(part) for part in parts]
+    t_end = SPEC["t_end"]
+    cd_b, cl_b = sim.forces()
+    sim.adjoint()
+    assert sim.t == t_end
+    assert sim.forces() == (cd_b, cl_b)
+    for part, f in zip(parts, before):
+        assert np.array_equal(sim.get_state(part), f), part
+    sim.step(40)
+    plain = hlbm.HLBM.from_workload(w, n_sub=N_SUB)
+    plain.step(t_end + 40)
+    assert np.array_equal(np.asarray(sim.history(0, t_end + 40)), np.asarray(plain.history(0, t_end + 40)))
+    for part in parts:
+        assert np.array_equal(sim.get_state(part), plain.get_state(part)), part
+    with pytest.raises(hlbm.HLBMError) as ei:
+        sim.adjoint()
+    assert ei.value.code == -6
+
+
+def test_objective_runs_of_other_lengths_on_one_workspace():
+    """A shorter objective run first, then a longer one on the same context and
+    workspace (the adjoint tables then sit at other offsets): the gradient equals
+    that of a fresh context, bit for bit."""
+    w = W.naca_re100_c40(3.0, bumps=W.hh_amplitudes(0))
+    tan = w.omesh.bump_tangent(W.HH_PEAKS)
+    long_spec = dict(SPEC, t_end=240, t0=160, t1=240)
+    sim = hlbm.HLBM.from_workload(w, n_sub=N_SUB, dxy_dshape=tan, history_len=4096)
+    sim.reserve_objective(**long_spec, mesh_grad=True)
+    sim.run_objective(**SPEC, mesh_grad=True)
+    sim.adjoint()
+    sim.run_objective(**long_spec, mesh_grad=True)
+    g = sim.adjoint()
+    fresh = hlbm.HLBM.from_workload(w, n_sub=N_SUB, dxy_dshape=tan, history_len=4096)
+    fresh.run_objective(**long_spec, mesh_grad=True)
+    assert np.array_equal(g, fresh.adjoint())
+
+
 def test_shape_gradient_wrong_call_is_an_error():
     w = W.naca_re100_c40(3.0)
     _, sim = gpu_J(w, w.aoa_rad, w.tau_s)
@@ -159,7 +225,7 @@ def test_autograd_function():
     gb = np.einsum("mnk,nk->m", w.omesh.bump_tangent(W.HH_PEAKS), sim.grad_xy)
     assert abs(aoa.grad.item() - g[0]) < 1e-12 * max(1, abs(g[0]))
     assert abs(tau.grad.item() - g[1]) < 1e-12 * max(1, abs(g[1]))
-    assert np.allclose(bumps.grad.numpy(), gb, rtol=1e-12, atol=0)
+    assert np.allclose(bumps.grad.numpy(), gb, rtol=1e-12, atol=1e-15 * np.abs(gb).max())
     # one amplitude against the oracle's complex-step derivative
     _, d3 = O.objective_derivative(w, OSPEC, d_xy=w.omesh.bump_tangent(W.HH_PEAKS)[3], n_sub=N_SUB)
     print("dJ/db", bumps.grad.numpy(), "oracle dJ/db3", d3, flush=True)
