@@ -25,6 +25,10 @@ constexpr int kUDon = 9;     // donors of a mesh interpolation node (3 x 3 block
 constexpr int kMacro = 12;   // (rho or rho - rho0, ux, uy, f^neq[9])
 constexpr int kRec = 12;
 constexpr int kTileMeta = 8;   // ints per fused-FV tile: node off, edge off, width, n_le[0..4]
+// fused-FV tile edge tables: local column, with kFtStar set where an
+// interpolation pivot reads the interpolated f* of its neighbour (eqs. (5)-(7))
+constexpr int32_t kFtStar = 1 << 30;
+constexpr int32_t kFtLocal = kFtStar - 1;
 constexpr int kFvStage = 2;    // nodes per thread of a fused FV sub-step (results held in registers)
 constexpr int kMaxFuse = 4;
 constexpr int kAdjRec = 10;   // doubles per mesh node of the adjoint fields (9 used)     // mesh node record: f_0..f_8, rho (or rho - rho0), ux, uy

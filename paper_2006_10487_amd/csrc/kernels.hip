@@ -26,15 +26,23 @@ __device__ __forceinline__ T wgt(int q) {
 
 // Macroscopic state of stored populations: rho (full), drho = rho - rho0
 // (shifted storage only), velocity.
+// First moments sum_i c_i g_i with the velocity components written out (c has
+// entries -1, 0, 1), in the order of increasing i.
+template <typename T>
+__device__ __forceinline__ T moment_x(const T (&g)[9]) {
+    return ((((g[1] - g[3]) + g[5]) - g[6]) - g[7]) + g[8];
+}
+template <typename T>
+__device__ __forceinline__ T moment_y(const T (&g)[9]) {
+    return ((((g[2] - g[4]) + g[5]) + g[6]) - g[7]) - g[8];
+}
+
 template <typename T, bool SHIFT>
 __device__ __forceinline__ void macro(const T (&f)[9], T rho0, T& rho, T& drho, T& ux, T& uy) {
-    T s = 0, mx = 0, my = 0;
+    T s = 0;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        s += f[q];
-        mx += T(CX[q]) * f[q];
-        my += T(CY[q]) * f[q];
-    }
+    for (int q = 0; q < 9; ++q) s += f[q];
+    const T mx = moment_x(f), my = moment_y(f);
     if (SHIFT) {
         drho = s;
         rho = rho0 + s;
@@ -42,8 +50,17 @@ __device__ __forceinline__ void macro(const T (&f)[9], T rho0, T& rho, T& drho, 
         rho = s;
         drho = s - rho0;
     }
-    ux = mx / rho;
-    uy = my / rho;
+    if constexpr (sizeof(T) == 4) {
+        // one reciprocal for both components: the hardware estimate refined by
+        // one Newton step (within one unit in the last place of the quotient)
+        float r = __builtin_amdgcn_rcpf(rho);
+        r = __builtin_fmaf(__builtin_fmaf(-rho, r, 1.0f), r, r);
+        ux = mx * r;
+        uy = my * r;
+    } else {
+        ux = mx / rho;
+        uy = my / rho;
+    }
 }
 
 // w_i x in FP32 without a common bias.  Rounded to FP32, 4/9, 1/9 and 1/36
@@ -53,11 +70,12 @@ __device__ __forceinline__ void macro(const T (&f)[9], T rho0, T& rho, T& drho, 
 // streamwise pressure gradient.  Here w_i = W_i / 36 with W_i in {16, 4, 1}
 // (exact) and x / 36 formed with a two-term 1/36, so the only error left is
 // the final rounding, of either sign.
+// The exact factor W_i (a power of two) is folded into both parts of 1/36.
 __device__ __forceinline__ float weighted_f32(int q, float x) {
     constexpr float k_hi = float(1.0 / 36.0);
     constexpr float k_lo = float(1.0 / 36.0 - double(float(1.0 / 36.0)));
     const float w36 = q == 0 ? 16.0f : (q < 5 ? 4.0f : 1.0f);
-    return w36 * __builtin_fmaf(x, k_hi, x * k_lo);
+    return __builtin_fmaf(x, w36 * k_hi, x * (w36 * k_lo));
 }
 
 
@@ -72,14 +90,13 @@ __device__ __forceinline__ float weighted_f32(int q, float x) {
 // Measured: FP32-shifted C_L at Re 1000, 5 deg within 8.3e-5 of FP64 (2.2e-4
 // without), C_D at Re 100 within 1e-8 (6e-6).
 __device__ __forceinline__ void conserve_f32(const float (&g)[9], float (&o)[9]) {
-    float dm = 0.f, dx = 0.f, dy = 0.f;
+    float d[9], dm = 0.f;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        const float d = o[q] - g[q];
-        dm += d;
-        dx += float(CX[q]) * d;
-        dy += float(CY[q]) * d;
+        d[q] = o[q] - g[q];
+        dm += d[q];
     }
+    const float dx = moment_x(d), dy = moment_y(d);
     const float ax = 0.25f * dx, ay = 0.25f * dy;
     o[5] -= ax + ay;
     o[7] += ax + ay;
@@ -91,12 +108,28 @@ __device__ __forceinline__ void conserve_f32(const float (&g)[9], float (&o)[9])
 // Second-order equilibrium of eq. (2) in stored form:
 //   FP64:    w_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2)
 //   shifted: w_i (rho - rho0) + w_i rho (3 c.u + 9/2 (c.u)^2 - 3/2 u^2)
+// c_i . (x, y) with the components of c_i written out.
+template <typename T>
+__device__ __forceinline__ T cdot(int q, T x, T y) {
+    switch (q) {
+    case 1: return x;
+    case 2: return y;
+    case 3: return -x;
+    case 4: return -y;
+    case 5: return x + y;
+    case 6: return y - x;
+    case 7: return -(x + y);
+    case 8: return x - y;
+    default: return T(0);
+    }
+}
+
 template <typename T, bool SHIFT>
 __device__ __forceinline__ void equilibrium(T rho, T drho, T ux, T uy, T (&feq)[9]) {
     const T uu = ux * ux + uy * uy;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        const T cu = T(CX[q]) * ux + T(CY[q]) * uy;
+        const T cu = cdot(q, ux, uy);
         const T poly = T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu;
         if constexpr (SHIFT && sizeof(T) == 4) feq[q] = weighted_f32(q, drho + rho * poly);
         else if constexpr (SHIFT) feq[q] = wgt<T>(q) * (drho + rho * poly);
@@ -583,6 +616,11 @@ __global__ __launch_bounds__(64) void k_struct_to_mesh(const KLevel F, const T* 
     for (int m = 0; m < kMacro; ++m) prep[size_t(s) * kMacro + m] = acc[m];
 }
 
+// Time fractions theta of the sub-steps of one fused launch (computed on the host).
+struct FvTheta {
+    double v[kMaxFuse];
+};
+
 template <typename T> struct EdgeRec;
 template <> struct alignas(32) EdgeRec<double> { int32_t col, pad; double gx, gy, c; };
 template <> struct alignas(16) EdgeRec<float> { int32_t col; float gx, gy, c; };
@@ -701,14 +739,22 @@ template <typename T, bool SHIFT>
 __device__ __forceinline__ void fv_finish(const KMesh& M, int P, const FvAcc<T>& A, T (&fn)[9], T& r, T& dr, T& ux,
                                           T& uy) {
     const T rho0 = T(M.rho0), dt = T(M.dt), dtt = T(M.dt_over_tau);
+    // x_i = a0 + 3 c_i.a1 + 9/2 c_i^T a2 c_i - 3/2 tr a2, with the shared parts
+    // b = a0 - 3/2 tr a2 and c_i^T a2 c_i in {0, a_xx, a_yy, tr a2 +- 2 a_xy}
     const T tr = A.axx + A.ayy;
+    const T b = A.a0 - T(1.5) * tr;
+    const T hxx = T(4.5) * A.axx, hyy = T(4.5) * A.ayy;
+    const T hpp = T(4.5) * (tr + T(2) * A.axy), hpm = T(4.5) * (tr - T(2) * A.axy);
+    const T sp = A.a1x + A.a1y, sm = A.a1y - A.a1x;
+    const T xs[9] = {b,
+                     (b + T(3) * A.a1x) + hxx, (b + T(3) * A.a1y) + hyy,
+                     (b - T(3) * A.a1x) + hxx, (b - T(3) * A.a1y) + hyy,
+                     (b + T(3) * sp) + hpp, (b + T(3) * sm) + hpm,
+                     (b - T(3) * sp) + hpp, (b - T(3) * sm) + hpm};
     T col[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        const T cx = T(CX[q]), cy = T(CY[q]);
-        const T ca = cx * A.a1x + cy * A.a1y;
-        const T caa = cx * cx * A.axx + T(2) * cx * cy * A.axy + cy * cy * A.ayy;
-        const T x = A.a0 + T(3) * ca + T(4.5) * caa - T(1.5) * tr;
+        const T x = xs[q];
         T eqs;
         if constexpr (SHIFT && sizeof(T) == 4) eqs = weighted_f32(q, x);
         else eqs = wgt<T>(q) * x;
@@ -796,26 +842,28 @@ __global__ __launch_bounds__(256) void k_fv_substep(const KMesh M, const T* __re
 }
 
 // One node update of the fused kernel: local node i with its edge records e,
-// reading the tile state in buf; returns the node's plan index.
+// reading the tile state in buf; returns the node's plan index.  Which
+// neighbours enter through f* is in the edge records (kFtStar), so a regular
+// node reads its neighbours' records without looking up their plan indices.
 template <typename T, bool SHIFT, int W>
 __device__ __forceinline__ int fv_tile_node(const KMesh& M, const T* __restrict__ buf, const int32_t* gid,
                                             const T* __restrict__ prep0, const T* __restrict__ prep1, T theta,
                                             int i, const EdgeRec<T> (&e)[W], T (&fn)[9], T (&mv)[3]) {
     const T rho0 = T(M.rho0), cst = T(M.star_neq);
     const int P = gid[i];
-    const bool pivot_interp = P >= M.n_core;
     FvAcc<T> A;
 #pragma unroll
     for (int z = 0; z < W; ++z) {
-        if (e[z].col < 0) continue;
-        const int k = gid[e[z].col];
-        const bool star = pivot_interp && k >= M.n_core;
+        const int32_t cz = e[z].col;
+        if (cz < 0) continue;
+        const bool star = (cz & kFtStar) != 0;
+        const int lc = cz & kFtLocal;
         T f[9], nq[9], mk = 0, uxk = 0, uyk = 0;
         if (star) {
-            const size_t sl = size_t(k - M.n_core) * kMacro;
+            const size_t sl = size_t(gid[lc] - M.n_core) * kMacro;
             star_values<T, SHIFT>(prep0 + sl, prep1 + sl, theta, cst, rho0, f, nq);
         } else {
-            load_rec(buf + size_t(e[z].col) * kRec, f, mk, uxk, uyk);
+            load_rec(buf + size_t(lc) * kRec, f, mk, uxk, uyk);
         }
         fv_add<T, SHIFT>(A, z, f, star, nq, mk, uxk, uyk, e[z].gx, e[z].gy, e[z].c, rho0);
     }
@@ -849,8 +897,8 @@ template <typename T, int W> struct FvFusedWaves { static constexpr int value = 
 
 template <typename T, bool SHIFT, int W>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWaves<T, W>::value))) void k_fv_fused(const KMesh M, const T* __restrict__ fin, T* __restrict__ fout,
-                                                  const T* __restrict__ prep0, const T* __restrict__ prep1, int m0,
-                                                  int ksteps, T* __restrict__ mid, size_t mid_stride) {
+                                                  const T* __restrict__ prep0, const T* __restrict__ prep1,
+                                                  FvTheta th, int ksteps, T* __restrict__ mid, size_t mid_stride) {
     extern __shared__ __align__(16) unsigned char smem[];
     T* const buf = reinterpret_cast<T*>(smem);
     int32_t* const gid = reinterpret_cast<int32_t*>(buf + size_t(M.maxl) * kRec);
@@ -887,7 +935,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
         // records of node tx (the same local node in both sub-steps) stay in
         // registers for sub-step 2, which takes node tx first.
         const int n1 = meta[4];
-        const T th1 = T(double(m0) / double(M.n_sub)), th2 = T(double(m0 + 1) / double(M.n_sub));
+        const T th1 = T(th.v[0]), th2 = T(th.v[1]);
         EdgeRec<T> e[W], e0[W];
         T r1[9], m1[3], r0[9], m0v[3];
         const bool has1 = tx + B < n1, has0 = tx < n1;
@@ -923,7 +971,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
     }
     for (int j = 1; j <= ksteps; ++j) {
         const int ncomp = meta[3 + ksteps - j];
-        const T theta = T(double(m0 + j - 1) / double(M.n_sub));
+        const T theta = T(th.v[j - 1]);
         const bool last = j == ksteps;
         T res[kFvStage][9], rm[kFvStage][3];
 #pragma unroll
@@ -1124,13 +1172,15 @@ void launch_fv_fused(int prec, const KMesh& M, const void* fin, void* fout, cons
     const size_t lds = size_t(M.maxl) * (kRec * elem + 4);
     const unsigned threads = unsigned(M.threads);
     if (size_t(M.maxw) > size_t(kFvStage) * threads || threads > 256) return;   // rejected by the plan
+    FvTheta th;   // theta = m / n of sub-steps m0 .. m0 + k - 1, as the one-sub-step launches take it
+    for (int j = 0; j < kMaxFuse; ++j) th.v[j] = double(m0 + j) / double(M.n_sub);
     if (M.ell_width <= 8) {
         HLBM_DISPATCH(prec, (k_fv_fused<T, S, 8><<<M.n_tiles, threads, lds, s>>>(M, (const T*)fin, (T*)fout, (const T*)prep0,
-                                                                                  (const T*)prep1, m0, k, (T*)mid,
+                                                                                  (const T*)prep1, th, k, (T*)mid,
                                                                  mid_stride_bytes / sizeof(T))));
     } else {
         HLBM_DISPATCH(prec, (k_fv_fused<T, S, 16><<<M.n_tiles, threads, lds, s>>>(M, (const T*)fin, (T*)fout, (const T*)prep0,
-                                                                                   (const T*)prep1, m0, k, (T*)mid,
+                                                                                   (const T*)prep1, th, k, (T*)mid,
                                                                  mid_stride_bytes / sizeof(T))));
     }
 }
@@ -1320,20 +1370,34 @@ __device__ __forceinline__ void wall_reset_adj(const KAdj& K, const double* fin,
     const int nn = M.nn, W = M.ell_width;
     const EdgeRec<double>* E = reinterpret_cast<const EdgeRec<double>*>(M.edges);
     double base[9], ss[9], sc[9];
-    for (int z = 0; z < W; ++z) {
-        const EdgeRec<double> e = E[size_t(z) * nn + P];
-        const int k = e.col;
-        if (k < 0) continue;
-        double f[9], nq[9];
-        fv_value(K, fin, prep0, prep1, theta, false, k, f, nq);   // wall nodes are never interpolation nodes
-        if (z == 0) {
+    // eight slots at a time: their table entries, then their records, are
+    // loaded together (two rounds of dependent loads instead of sixteen)
+    constexpr int G = 8;
+    for (int g0 = 0; g0 < W; g0 += G) {
+        EdgeRec<double> e[G];
+        double fr[G][9], mr[G][3];
 #pragma unroll
-            for (int q = 0; q < 9; ++q) base[q] = f[q], ss[q] = 0.0, sc[q] = e.c * nq[q];
-        } else {
+        for (int a = 0; a < G; ++a) e[a] = E[size_t(g0 + a) * nn + P];
 #pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                ss[q] += (CX[q] * e.gx + CY[q] * e.gy) * (f[q] - base[q]);
-                sc[q] += e.c * nq[q];
+        for (int a = 0; a < G; ++a)
+            load_rec(fin + size_t(e[a].col < 0 ? P : e[a].col) * kRec, fr[a], mr[a][0], mr[a][1], mr[a][2]);
+#pragma unroll
+        for (int a = 0; a < G; ++a) {
+            if (e[a].col < 0) continue;
+            // wall nodes are never interpolation nodes: stored values only (as fv_value)
+            double feq[9], nq[9];
+            equilibrium<double, false>(mr[a][0], mr[a][0], mr[a][1], mr[a][2], feq);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) nq[q] = fr[a][q] - feq[q];
+            if (g0 + a == 0) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) base[q] = fr[a][q], ss[q] = 0.0, sc[q] = e[a].c * nq[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    ss[q] += (CX[q] * e[a].gx + CY[q] * e[a].gy) * (fr[a][q] - base[q]);
+                    sc[q] += e[a].c * nq[q];
+                }
             }
         }
     }
@@ -1405,6 +1469,23 @@ __device__ __forceinline__ void adj_fv_gather(const KAdj& K, int k, bool k_inter
     for (int g0 = z_begin; g0 < z_begin + W; g0 += G) {
         EdgeRec<double> eg[G];
         double zg[G][9];
+        // coefficient adjoints of the group's slots, read before the pivot gathers
+        // (each entry has one writer per launch: the lane of its slot)
+        double gold[G][3];
+        if (K.gbar) {
+#pragma unroll
+            for (int a = 0; a < G; ++a) {
+                const int z = g0 + a;
+                if (z == 0) {
+                    gold[a][0] = K.gpivot[2 * size_t(k)];
+                    gold[a][1] = K.gpivot[2 * size_t(k) + 1];
+                    gold[a][2] = K.gbar[size_t(k) * 3 + 2];
+                } else {
+                    const double* g = K.gbar + (size_t(z) * nn + k) * 3;
+                    gold[a][0] = g[0], gold[a][1] = g[1], gold[a][2] = g[2];
+                }
+            }
+        }
 #pragma unroll
         for (int a = 0; a < G; ++a) eg[a] = T[size_t(g0 + a) * nn + k];
 #pragma unroll
@@ -1435,14 +1516,14 @@ __device__ __forceinline__ void adj_fv_gather(const KAdj& K, int k, bool k_inter
                     gc += zp[q] * nval[q];
                 }
                 if (z == 0) {
-                    K.gbar[size_t(k) * 3 + 2] -= K.dtt * gc;
-                    K.gpivot[2 * size_t(k)] += K.dt * gx;
-                    K.gpivot[2 * size_t(k) + 1] += K.dt * gy;
+                    K.gbar[size_t(k) * 3 + 2] = gold[a][2] - K.dtt * gc;
+                    K.gpivot[2 * size_t(k)] = gold[a][0] + K.dt * gx;
+                    K.gpivot[2 * size_t(k) + 1] = gold[a][1] + K.dt * gy;
                 } else {   // transposed slot z of k (coalesced); mapped to the forward slot on download
                     double* g = K.gbar + (size_t(z) * nn + k) * 3;
-                    g[0] += K.dt * gx;
-                    g[1] += K.dt * gy;
-                    g[2] -= K.dtt * gc;
+                    g[0] = gold[a][0] + K.dt * gx;
+                    g[1] = gold[a][1] + K.dt * gy;
+                    g[2] = gold[a][2] - K.dtt * gc;
                 }
             }
         }

@@ -573,7 +573,9 @@ void build_fv_tiles(Plan& p, int tile, int fuse) {
             for (int i = 0; i < width; ++i) {
                 const int P = nodes[i], zz = p.rowptr[P] + z;
                 const bool used = zz < p.rowptr[P + 1];
-                p.ft_col.push_back(used ? loc[p.col[zz]] : -1);
+                // an interpolation pivot reads f* (eqs. (5)-(7)) for its interpolation neighbours
+                const bool star = used && P >= p.n_core && p.col[zz] >= p.n_core;
+                p.ft_col.push_back(used ? loc[p.col[zz]] | (star ? kFtStar : 0) : -1);
                 p.ft_src.push_back(used ? zz : -1);
             }
         p.fv_maxl = std::max(p.fv_maxl, int(nodes.size()));

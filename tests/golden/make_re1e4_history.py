@@ -5,8 +5,11 @@ base grid with two nested factor-two boxes, and a 1024 x 128 O-mesh
 (`workloads.naca_re1e4_c256`).  The script runs the first STEPS finest steps of
 the plain FP64 CPU oracle from the initial state and stores C_D and C_L of
 every step (eqs. (10)-(11)).  The GPU tests compare the library's FP64 history
-with it and state the FP32-shifted deviation from it.  It calls only the oracle
-and the input generator.  It takes about an hour on 8 cores:
+with it and state the FP32-shifted deviation from it.  With these settings the
+run turns non-finite at finest step 1482 (the central finite-volume streaming is
+unstable on this mesh at this Reynolds number); from there on the stored values
+are nan.  It calls only the oracle and the input generator.  It takes about an
+hour on 8 cores:
 
     python tests/golden/make_re1e4_history.py [steps]
 """

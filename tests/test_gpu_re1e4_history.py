@@ -1,0 +1,91 @@
+"""Re = 1e4 workload (chord 256 lu, 2048 x 1024 base grid with two nested boxes,
+1024 x 128 O-mesh, 326 FV sub-steps per finest step): the GPU drag and lift
+histories of the first 2000 finest steps against the FP64 CPU oracle's, stored
+in tests/golden/ by tests/golden/make_re1e4_history.py (which calls only the
+oracle and the input generator).
+
+The oracle run itself turns non-finite at finest step 1482: with these
+settings the outer cells of the O-mesh are ~3 lu across at a viscosity of
+1e-3 lu^2, a cell Peclet number near 125, where the central finite-volume
+streaming of eq. (3) has no stability margin.  The comparison therefore covers
+the steps before the first non-finite value of either run, minus 100 steps in
+which the blow-up grows, and FP64 must blow up at the same step as the oracle.
+FP32-shifted storage blows up about 80 steps earlier (step 1406).
+
+FP64: every compared step within 1e-10 of the oracle, relative to the largest
+|C_D| of the compared steps (C_L, which vanishes by mirror symmetry at zero
+incidence, is held to the same absolute bar), and the first non-finite force
+within 2 steps of the oracle's.  FP32-shifted storage: the mean C_D over the
+second half of the compared steps within 1e-4 relative (the FP32 target of the
+configuration, stated for time means) and the mean C_L within 1e-4 of the mean
+C_D; single steps within 1e-3 relative to the largest |C_D| (measured 4.3e-4:
+the deviation grows as the run approaches its blow-up).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2006_10487_amd import hlbm, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "naca_re1e4_c256_fp64_history.txt")
+STEPS = 2000
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hlbm.lib()
+
+
+def golden():
+    data = np.loadtxt(GOLDEN, comments="#")
+    assert data.shape == (STEPS, 3) and np.array_equal(data[:, 0], np.arange(STEPS))
+    header = open(GOLDEN).readline()
+    return header, data[:, 1], data[:, 2]
+
+
+def run(precision, steps):
+    w = W.naca_re1e4_c256()
+    sim = hlbm.HLBM.from_workload(w, precision=precision)
+    assert sim.info.n_sub == 326
+    sim.step_logged(steps, "re1e4", chunk=250)
+    cd, cl = sim.history(0, steps)
+    sim.close()
+    return w, cd, cl
+
+
+@pytest.mark.parametrize("precision", [hlbm.FP64, hlbm.FP32_SHIFTED])
+def test_re1e4_history_against_oracle(precision):
+    header, cd_o, cl_o = golden()
+    bad = np.nonzero(~np.isfinite(cd_o))[0]
+    t_bad = int(bad[0]) if bad.size else STEPS
+    assert t_bad == 1482                       # the stored oracle run
+    w, cd, cl = run(precision, 1500)
+    assert w.name in header and "n_sub 326" in header
+    gbad = np.nonzero(~np.isfinite(cd))[0]
+    g_bad = int(gbad[0]) if gbad.size else None
+    # compared: the steps before either run starts to blow up
+    n = min(t_bad, g_bad if g_bad is not None else STEPS) - 100
+    scale = np.abs(cd_o[:n]).max()
+    e_cd = np.abs(cd[:n] - cd_o[:n]) / scale
+    e_cl = np.abs(cl[:n] - cl_o[:n]) / scale
+    h = slice(n // 2, n)
+    mean_cd_err = abs(cd[h].mean() - cd_o[h].mean()) / abs(cd_o[h].mean())
+    print(f"precision {precision}: steps 0-{n - 1}: max |dC_D| / max|C_D| {e_cd.max():.3e} "
+          f"(step {int(e_cd.argmax())}), max |dC_L| / max|C_D| {e_cl.max():.3e}; mean C_D over steps "
+          f"{n // 2}-{n - 1}: oracle {cd_o[h].mean()!r}, GPU {cd[h].mean()!r} (rel. difference "
+          f"{mean_cd_err:.2e}); first non-finite force: oracle step {t_bad}, GPU step {g_bad}", flush=True)
+    if precision == hlbm.FP64:
+        assert e_cd.max() < 1e-10 and e_cl.max() < 1e-10
+        assert g_bad is not None and abs(g_bad - t_bad) <= 2
+    else:
+        # the target is on time means; single steps deviate more as the run nears its blow-up
+        cl_mean_err = abs(cl[h].mean() - cl_o[h].mean()) / abs(cd_o[h].mean())
+        assert mean_cd_err < 1e-4 and cl_mean_err < 1e-4
+        assert e_cd.max() < 1e-3 and e_cl.max() < 1e-3
