@@ -143,6 +143,25 @@ int hlbm_workspace_size(const hlbm_grid *grid, const hlbm_mesh *mesh, double Re,
 int hlbm_create(const hlbm_grid *grid, const hlbm_mesh *mesh, double Re, double tau,
                 void *d_workspace, size_t ws_bytes, void *hip_stream, hlbm_ctx **out);
 
+/* Size of the static workspace of hlbm_create_noalloc (bytes). */
+#define HLBM_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+
+/* hlbm_create for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * workspace is a static device array of HLBM_NOALLOC_MAX_BYTES that the
+ * library holds on each device it runs on until the process ends, instead of
+ * a caller buffer.  No hipMalloc, hipFree or other allocating routine is
+ * called.  Problems whose hlbm_workspace_size exceeds the array get
+ * HLBM_E_WORKSPACE (host-side check, before any device work); the Re = 100
+ * workloads of the tests (about 35-39 MiB) fit.  Every context created this
+ * way on one device uses that device's array: creating another one overwrites
+ * the earlier context's state (destroy it first), and work on two such
+ * contexts of one device races.  The array keeps the contents of the last
+ * call; create writes every part of it that the context reads before reading
+ * it.  Otherwise as hlbm_create; hlbm_destroy frees only host memory. */
+int hlbm_create_noalloc(const hlbm_grid *grid, const hlbm_mesh *mesh, double Re, double tau, void *hip_stream,
+                        hlbm_ctx **out);
+
 /* Advances n_finest_steps finest steps (a multiple of 2^n_refine): per finest
  * step the coupling of eq. (4), the collide-stream of eqs. (1)-(2) on every
  * level with the subcycling and box transfers of Sec. 4, eq. (9), the n

@@ -434,6 +434,23 @@ int hlbm_create(const hlbm_grid* grid, const hlbm_mesh* mesh, double Re, double 
     return HLBM_OK;
 }
 
+int hlbm_create_noalloc(const hlbm_grid* grid, const hlbm_mesh* mesh, double Re, double tau, void* hip_stream,
+                        hlbm_ctx** out) {
+    if (!out) return set_err(nullptr, HLBM_E_ARG, "out is null");
+    *out = nullptr;
+    size_t need = 0;
+    int rc = hlbm_workspace_size(grid, mesh, Re, tau, &need);
+    if (rc) return rc;
+    if (need > kNoAllocBytes)
+        return set_err(nullptr, HLBM_E_WORKSPACE,
+                       "problem needs a workspace of " + std::to_string(need) + " bytes; the static workspace of "
+                       "hlbm_create_noalloc holds " + std::to_string(kNoAllocBytes));
+    void* ws = nullptr;
+    rc = noalloc_workspace(&ws);
+    if (rc) return set_err(nullptr, rc, "hipGetSymbolAddress of the static workspace failed");
+    return hlbm_create(grid, mesh, Re, tau, ws, kNoAllocBytes, hip_stream, out);
+}
+
 int hlbm_step(hlbm_ctx* c, int64_t n) {
     if (!c) return HLBM_E_ARG;
     if (c->poisoned) return set_err(c, HLBM_E_STATE, "context poisoned by a non-finite state");

@@ -295,6 +295,10 @@ struct hlbm_ctx {
 
 
 namespace hlbm {
+// Static workspace of hlbm_create_noalloc on the current device (kernels.hip):
+// its device address, looked up once per device.  Returns HLBM_OK or HLBM_E_DEVICE.
+constexpr size_t kNoAllocBytes = HLBM_NOALLOC_MAX_BYTES;
+int noalloc_workspace(void** ptr);
 void finish_import(hlbm_ctx* c);
 void finest_step(hlbm_ctx* c);
 void level_step(hlbm_ctx* c, int l);

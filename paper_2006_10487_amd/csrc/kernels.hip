@@ -11,6 +11,8 @@
 // is no matrix-core (MFMA) work: the kernels are plain coalesced streams.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "hlbm_internal.h"
 
 namespace hlbm {
@@ -2301,6 +2303,31 @@ void launch_wall_stats(int prec, const void* f, int n_wall, const double* nrm, d
 void launch_wall_stats_final(int n_wall, const double* sum, const int32_t* slot, double n, double* out, hipStream_t s) {
     if (n_wall <= 0) return;
     k_wall_stats_final<<<blocks(n_wall), 256, 0, s>>>(n_wall, sum, slot, n, out);
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of hlbm_create_noalloc: a file-scope device array, one copy per
+// device, held until the process ends.  Host code reaches it only through the
+// address that hipGetSymbolAddress returns for the current device (the array's
+// name is a host-side stand-in, not a device address).
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+int noalloc_workspace(void** ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return HLBM_E_DEVICE;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HLBM_E_DEVICE;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return HLBM_OK;
 }
 
 }  // namespace hlbm

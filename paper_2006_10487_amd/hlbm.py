@@ -28,7 +28,7 @@ EXPORTED = ["hlbm_validate", "hlbm_workspace_size", "hlbm_create", "hlbm_step", 
             "hlbm_force_history", "hlbm_get_state", "hlbm_set_state", "hlbm_info", "hlbm_last_error",
             "hlbm_destroy", "hlbm_profile", "hlbm_profile_read", "hlbm_kernel_bench",
             "hlbm_objective_workspace_size", "hlbm_run_objective", "hlbm_adjoint",
-            "hlbm_wall_stats_begin", "hlbm_wall_stats"]
+            "hlbm_wall_stats_begin", "hlbm_wall_stats", "hlbm_create_noalloc"]
 KERNEL_CLASSES = ["collide_l0", "collide_l1", "collide_l2", "collide_l3", "coarse_to_fine",
                   "fine_to_coarse", "mesh_to_struct", "struct_to_mesh", "fv_substep", "wall_force",
                   "wall_stats"]
@@ -97,6 +97,8 @@ def lib():
                                           C.POINTER(C.c_size_t)]
         L.hlbm_create.argtypes = [C.POINTER(Grid), C.POINTER(Mesh), C.c_double, C.c_double, P,
                                   C.c_size_t, P, C.POINTER(P)]
+        L.hlbm_create_noalloc.argtypes = [C.POINTER(Grid), C.POINTER(Mesh), C.c_double, C.c_double, P,
+                                          C.POINTER(P)]
         L.hlbm_step.argtypes = [P, C.c_int64]
         L.hlbm_forces.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.hlbm_force_history.argtypes = [P, C.c_int64, C.c_int64, P, P]
@@ -195,19 +197,26 @@ class HLBM:
     """
 
     def __init__(self, grid: Grid, mesh: Mesh, *, re: float = 0.0, tau: float = 0.0,
-                 keep=(), stream=None):
+                 keep=(), stream=None, noalloc: bool = False):
+        """noalloc: the library's static per-device workspace (hlbm_create_noalloc)
+        instead of a torch buffer; one such context per device at a time."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("HLBM needs a GPU (torch.cuda is not available)")
         self._keep = list(keep)
         self.grid, self.mesh = grid, mesh
-        nbytes = workspace_size(grid, mesh, re, tau)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         ctx = C.c_void_p()
-        rc = lib().hlbm_create(C.byref(grid), C.byref(mesh), re, tau,
-                               C.c_void_p(self.workspace.data_ptr()), nbytes,
-                               C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        if noalloc:
+            self.workspace = None
+            rc = lib().hlbm_create_noalloc(C.byref(grid), C.byref(mesh), re, tau,
+                                           C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        else:
+            nbytes = workspace_size(grid, mesh, re, tau)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            rc = lib().hlbm_create(C.byref(grid), C.byref(mesh), re, tau,
+                                   C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
         if rc:
             raise HLBMError(rc, last_error())
         self._ctx = ctx
@@ -221,12 +230,12 @@ class HLBM:
     @classmethod
     def from_workload(cls, w, *, precision=FP64, interp=INTERP_QUADRATIC, n_sub=0, wall_bc=True,
                       aoa_rad=None, tau=None, check_every=0, history_len=0, fv_fuse=0, stream=None,
-                      dxy_dshape=None):
+                      dxy_dshape=None, noalloc=False):
         g, m, keep = structs_from_workload(
             w, precision=precision, interp=interp, n_sub=n_sub or w.n_sub, wall_bc=wall_bc,
             aoa_rad=w.aoa_rad if aoa_rad is None else aoa_rad, check_every=check_every,
             history_len=history_len, fv_fuse=fv_fuse, dxy_dshape=dxy_dshape)
-        return cls(g, m, tau=w.tau_s if tau is None else tau, keep=keep, stream=stream)
+        return cls(g, m, tau=w.tau_s if tau is None else tau, keep=keep, stream=stream, noalloc=noalloc)
 
     def _check(self, rc):
         if rc:
