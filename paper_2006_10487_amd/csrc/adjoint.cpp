@@ -44,6 +44,7 @@ struct AdjState {
         size_t ckpt, ckpt_stride, ck_lev[4], ck_side[4], ck_mesh, ck_prep;
         size_t fin, fin_prev[4];   // state at t_end: a checkpoint plus every level's previous buffer
         size_t seg_lev[4], seg_side[4], seg_mesh, seg_prep, seg_sub, sub, awork;
+        size_t seg_wmom, wmom;   // pre-reset (rho, u) of the wall nodes per sub-step
         size_t abar[4][2], prebar[4], sbar[4][2], vperim[4];
         size_t mbar[2], zwall[2], pbar[2], m5bar;
         size_t partial, acc, tedges, vwall, t5ptr, t5s, t5w, t6node, t6ptr, t6s, t6w, dfeq;
@@ -67,6 +68,8 @@ struct AdjState {
     int n_sub = 0;
     // state after FV sub-step m + 1 of segment step k (stored sub-steps)
     size_t seg_sub_at(int k, int m) const { return off.seg_sub + a256(mesh_bytes) * (size_t(k) * n_sub + m); }
+    size_t wmom_bytes = 0;   // one sub-step's wall-node moments
+    size_t seg_wmom_at(int k, int m) const { return off.seg_wmom + a256(wmom_bytes) * (size_t(k) * n_sub + m); }
 };
 
 namespace {
@@ -144,6 +147,9 @@ void layout(hlbm_ctx* c, AdjState& a) {
     a.n_sub = p.n_sub;
     a.off.seg_sub = a.obj.store_substeps ? take(a256(a.mesh_bytes) * size_t(K) * p.n_sub) : 0;
     a.off.sub = take(a256(a.mesh_bytes) * (p.n_sub + 1));
+    a.wmom_bytes = size_t(std::max(p.n_wall, 1)) * 3 * 8;
+    a.off.seg_wmom = a.obj.store_substeps ? take(a256(a.wmom_bytes) * size_t(K) * p.n_sub) : 0;
+    a.off.wmom = take(a256(a.wmom_bytes) * p.n_sub);
     a.off.awork = take(maxlev);
     for (int l = 0; l <= p.L; ++l) {
         a.off.abar[l][0] = take(a.lev_bytes[l]);
@@ -413,6 +419,8 @@ void recorder(hlbm_ctx* c, int ev, int l) {
         if (a.obj.store_substeps) {
             c->sub_sink = a.ws + a.seg_sub_at(k, 0);
             c->sub_stride = a256(a.mesh_bytes);
+            c->wmom_sink = a.at<double>(a.seg_wmom_at(k, 0));
+            c->wmom_stride = a256(a.wmom_bytes) / 8;
         }
         ++k;
     }
@@ -464,11 +472,18 @@ void reverse_finest(hlbm_ctx* c, AdjState& a, int64_t t, int k, double& alpha_ho
         if (m == 0) return Mt;
         return stored ? a.at<double>(a.seg_sub_at(k, m - 1)) : a.at<double>(a.off.sub + ms * m);
     };
+    // pre-reset (rho, u) of the wall nodes in sub-step m, recorded by the forward
+    auto Wmom = [&](int m) -> const double* {
+        return stored ? a.at<double>(a.seg_wmom_at(k, m)) : a.at<double>(a.off.wmom + a256(a.wmom_bytes) * m);
+    };
     if (!stored) {
         (void)d2d(c, a.ws + a.off.sub, Mt, a.mesh_bytes);
-        for (int m = 0; m < p.n_sub; ++m)
-            launch_fv_substep(HLBM_FP64, c->km, a.ws + a.off.sub + ms * m, a.ws + a.off.sub + ms * (m + 1), prep0,
+        KMesh km = c->km;
+        for (int m = 0; m < p.n_sub; ++m) {
+            km.wmom = a.at<double>(a.off.wmom + a256(a.wmom_bytes) * m);
+            launch_fv_substep(HLBM_FP64, km, a.ws + a.off.sub + ms * m, a.ws + a.off.sub + ms * (m + 1), prep0,
                               prep1, double(m) / p.n_sub, s);
+        }
     }
     // force^T (history entry t belongs to the state after step t, M^n)
     if (t >= o.t0 && t < o.t1) {
@@ -485,15 +500,13 @@ void reverse_finest(hlbm_ctx* c, AdjState& a, int64_t t, int k, double& alpha_ho
     // transpose of a sub-step is taken by the wall threads of the launch after it
     const int bn = adj_fv_blocks(c->km);
     int zw = 0;
-    launch_adj_fv_wall(K, Msub(p.n_sub - 1), a.at<double>(a.off.mbar[a.mb]), a.at<double>(a.off.zwall[zw]), prep0,
-                       prep1, double(p.n_sub - 1) / p.n_sub, s);
+    launch_adj_fv_wall(K, Wmom(p.n_sub - 1), a.at<double>(a.off.mbar[a.mb]), a.at<double>(a.off.zwall[zw]), s);
     for (int m = p.n_sub - 1; m >= 0; --m) {
         const double th = double(m) / p.n_sub;
         const double* Mm = Msub(m);
-        const double* Mprev = m > 0 ? Msub(m - 1) : nullptr;
         launch_adj_fv(K, Mm, a.at<double>(a.off.mbar[a.mb]), a.at<double>(a.off.zwall[zw]),
-                      a.at<double>(a.off.mbar[1 - a.mb]), prep0, prep1, th, Pnext, Pcur, slot, Mprev,
-                      double(m - 1) / p.n_sub, a.at<double>(a.off.zwall[1 - zw]), s);
+                      a.at<double>(a.off.mbar[1 - a.mb]), prep0, prep1, th, Pnext, Pcur, slot,
+                      m > 0 ? Wmom(m - 1) : nullptr, a.at<double>(a.off.zwall[1 - zw]), s);
         slot += bn;
         a.mb ^= 1;
         zw ^= 1;
@@ -762,6 +775,7 @@ int hlbm_adjoint(hlbm_ctx* c, double J_bar, double* grad, double* grad_xy) {
         for (int64_t t = ta; t < tb; t += a.per) level_step(c, 0);
         c->rec = nullptr;
         c->sub_sink = nullptr;
+        c->wmom_sink = nullptr;
         rc |= a.rec_rc;
         // states after the segment: the post buffer of every refined level, prep at tb
         for (int l = 1; l <= p.L; ++l)

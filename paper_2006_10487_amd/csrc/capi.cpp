@@ -121,12 +121,16 @@ void setup_views(hlbm_ctx* c) {
     m.n_sub = p.n_sub;
     m.n_tiles = p.n_tiles;
     m.maxl = p.fv_maxl;
+    m.maxs = p.fv_maxs;
     m.maxw = p.fv_maxw;
     m.tile = p.fv_tile;
     m.threads = p.fv_threads;
     m.ft_meta = reinterpret_cast<const int32_t*>(c->ws + p.off.ft_meta);
     m.ft_node = reinterpret_cast<const int32_t*>(c->ws + p.off.ft_node);
     m.ft_edges = c->ws + p.off.ft_edges;
+    m.ft_star = reinterpret_cast<const int32_t*>(c->ws + p.off.ft_star);
+    m.wmom = nullptr;
+    m.wmom_stride = 0;
 }
 
 int upload_tables(hlbm_ctx* c) {
@@ -166,6 +170,7 @@ int upload_tables(hlbm_ctx* c) {
         if (p.fv_fuse > 1) {
             rc |= upload(c, p.off.ft_meta, p.ft_meta.data(), p.ft_meta.size() * 4);
             rc |= upload(c, p.off.ft_node, p.ft_node.data(), p.ft_node.size() * 4);
+            rc |= upload(c, p.off.ft_star, p.ft_star.data(), p.ft_star.size() * 4);
             // tile edge tables: the ELL record layout with local columns
             std::vector<char> te(p.ft_col.size() * rs, 0);
             for (size_t e = 0; e < p.ft_col.size(); ++e) {
@@ -284,14 +289,17 @@ void finest_step(hlbm_ctx* c) {
             // every sub-step's state to the sink (fused launches write their
             // intermediate states there too)
             const void* in = c->mesh(c->mesh_cur);
+            KMesh km = c->km;
+            km.wmom_stride = c->wmom_stride;
             for (int m = 0; m < p.n_sub;) {
                 const int k = std::min(p.fv_fuse, p.n_sub - m);
                 void* out = c->sub_sink + size_t(m + k - 1) * c->sub_stride;
+                km.wmom = c->wmom_sink ? c->wmom_sink + size_t(m) * c->wmom_stride : nullptr;
                 if (k > 1)
-                    launch_fv_fused(pr, c->km, in, out, c->prep(c->prep_t), c->prep(1 - c->prep_t), m, k, c->s,
+                    launch_fv_fused(pr, km, in, out, c->prep(c->prep_t), c->prep(1 - c->prep_t), m, k, c->s,
                                     c->sub_sink + size_t(m) * c->sub_stride, c->sub_stride);
                 else
-                    launch_fv_substep(pr, c->km, in, out, c->prep(c->prep_t), c->prep(1 - c->prep_t),
+                    launch_fv_substep(pr, km, in, out, c->prep(c->prep_t), c->prep(1 - c->prep_t),
                                       double(m) / p.n_sub, c->s);
                 in = out;
                 m += k;

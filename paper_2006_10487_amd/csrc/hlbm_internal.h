@@ -24,14 +24,24 @@ constexpr int kSDon = 8;     // donors of a structured interpolation node (two 6
 constexpr int kUDon = 9;     // donors of a mesh interpolation node (3 x 3 block)
 constexpr int kMacro = 12;   // (rho or rho - rho0, ux, uy, f^neq[9])
 constexpr int kRec = 12;
-constexpr int kTileMeta = 8;   // ints per fused-FV tile: node off, edge off, width, n_le[0..4]
-// fused-FV tile edge tables: local column, with kFtStar set where an
-// interpolation pivot reads the interpolated f* of its neighbour (eqs. (5)-(7))
+constexpr int kTileMeta = 10;  // ints per fused-FV tile: node off, edge off, width, n_le[0..4], star off, star count
+// fused-FV tile edge tables: local column, or, where an interpolation pivot
+// reads the interpolated f* of its neighbour (eqs. (5)-(7)), kFtStar plus the
+// neighbour's slot in the tile's list of such nodes
 constexpr int32_t kFtStar = 1 << 30;
 constexpr int32_t kFtLocal = kFtStar - 1;
+constexpr int kStarRec = 20;   // per staged f* node: f*[9], its f^neq part [9], 2 unused (16-byte rows)
 constexpr int kFvStage = 2;    // nodes per thread of a fused FV sub-step (results held in registers)
 constexpr int kMaxFuse = 4;
 constexpr int kAdjRec = 10;   // doubles per mesh node of the adjoint fields (9 used)     // mesh node record: f_0..f_8, rho (or rho - rho0), ux, uy
+
+// LDS bytes of one fused-FV workgroup: node records and plan indices of the
+// tile with its rings, then f* of the tile's interpolation nodes at each of the
+// launch's sub-steps.
+inline size_t fv_lds_bytes(int maxl, int maxs, int fuse, size_t elem) {
+    const size_t recs = (size_t(maxl) * (kRec * elem + 4) + 15) / 16 * 16;
+    return recs + size_t(fuse) * size_t(maxs) * kStarRec * elem;
+}
 
 struct LevelPlan {
     int nx = 0, ny = 0, pitch = 0;  // nodes, row pitch in elements
@@ -76,8 +86,10 @@ struct Plan {
     // reach; per tile kTileMeta ints {node offset, edge offset, edge-table
     // width, n_le[0..fv_fuse]} with n_le[r] = local nodes within ring r
     // fv_threads: workgroup size of the fused kernel, at least fv_maxw / kFvStage
-    int fv_fuse = 1, fv_tile = 256, fv_threads = 256, fv_maxl = 0, fv_maxw = 0, n_tiles = 0;
+    // fv_maxs: most f* nodes of a tile (their f* is staged in LDS once per sub-step)
+    int fv_fuse = 1, fv_tile = 256, fv_threads = 256, fv_maxl = 0, fv_maxw = 0, fv_maxs = 0, n_tiles = 0;
     std::vector<int32_t> ft_meta, ft_node;
+    std::vector<int32_t> ft_star;        // per tile: interpolation slot (plan index - n_core) of its f* nodes
     std::vector<int32_t> ft_col;         // local column per (slot, computed node) of each tile
     std::vector<int32_t> ft_src;         // index into col / gx / gy / cc of that entry, -1 = unused
     std::vector<double> wall_nrm;        // [n_wall][2] unit normal into the fluid at each wall node
@@ -100,7 +112,7 @@ struct Plan {
         size_t spans, sint_node, sint_don, sint_w;
         size_t mesh[2], rowptr, edges, wedge, wnorm, prep[2], uint_don, uint_w, hist, stage;
         size_t wall_nrm, wall_slot, wsum, wout;
-        size_t ft_meta, ft_node, ft_edges;
+        size_t ft_meta, ft_node, ft_edges, ft_star;
         size_t total;
     } off{};
     size_t stage_bytes = 0;
@@ -145,10 +157,17 @@ struct KMesh {
     double rho0;
     // fused sub-steps (fuse > 1): tile tables and the LDS size they need
     int fuse, n_sub, n_tiles, maxl, maxw, tile;   // maxw: largest edge-table width (nodes of sub-step 1)
+    int maxs;                                     // most staged f* nodes of a tile
     int threads;                                  // workgroup size, kFvStage * threads >= maxw
     const int32_t* ft_meta;
     const int32_t* ft_node;
     const void* ft_edges;
+    const int32_t* ft_star;
+    // optional: the pre-reset (rho, u_x, u_y) of every wall node after each
+    // sub-step of the launch, at wmom + j * wmom_stride + 3 * P (j = sub-step of
+    // the launch); read by the adjoint's no-slip reset transpose
+    double* wmom;
+    size_t wmom_stride;
 };
 
 // launchers (kernels.hip); `prec` is HLBM_FP64 or HLBM_FP32_SHIFTED
@@ -213,11 +232,12 @@ struct KAdj {
 void launch_zero(double* p, size_t n, hipStream_t s);
 void launch_adj_force(const KAdj& K, double* mbar, const double* vwall, double jx, double jy, const double* fst,
                       hipStream_t s);
-void launch_adj_fv_wall(const KAdj& K, const double* Mrec, const double* ybar, double* zwall, const double* prep0,
-                        const double* prep1, double theta, hipStream_t s);
+// wmom: pre-reset (rho, u) of the wall nodes in the sub-step whose reset is
+// transposed (recorded by the forward, KMesh::wmom)
+void launch_adj_fv_wall(const KAdj& K, const double* wmom, const double* ybar, double* zwall, hipStream_t s);
 void launch_adj_fv(const KAdj& K, const double* Mrec, const double* ybar, const double* zwall, double* mbar,
                    const double* prep0, const double* prep1, double theta, double* p0bar, double* p1bar, int pslot,
-                   const double* Mprev, double theta_prev, double* zwall_prev, hipStream_t s);
+                   const double* wmom_prev, double* zwall_prev, hipStream_t s);
 void launch_adj_collide(const KAdj& K, const double* A, const double* bbar, double* prebar, int pslot, hipStream_t s);
 void launch_adj_s2m(const KAdj& K, const double* A, int nd, const int32_t* node, const int32_t* ptr,
                     const int32_t* slot, const double* w, const double* pbar, double* prebar, hipStream_t s);
@@ -277,6 +297,10 @@ struct hlbm_ctx {
     // m + 1); the last one is copied back into the mesh buffer
     char* sub_sink = nullptr;
     size_t sub_stride = 0;
+    // with wmom_sink set as well, the pre-reset (rho, u) of the wall nodes after
+    // sub-step m go to wmom_sink + m * wmom_stride (doubles)
+    double* wmom_sink = nullptr;
+    size_t wmom_stride = 0;
     // wall statistics (eqs. (12)-(13)): accumulating, and finest steps summed
     bool wstat = false;
     int64_t wstat_n = 0;

@@ -677,6 +677,11 @@ __device__ __forceinline__ void store_rec(T* __restrict__ rec, const T (&f)[9], 
     }
 }
 
+template <typename T>
+__device__ __forceinline__ void store_wmom(double* w, const T (&pre)[3]) {
+    w[0] = double(pre[0]), w[1] = double(pre[1]), w[2] = double(pre[2]);
+}
+
 // One finite-volume sub-step of eq. (3) at one mesh node (eq. (5) at the
 // interpolation nodes), Jacobi style:
 //   f_P <- f_P + dt sum_k (c_i . G_Pk) f_k - dt/tau_u sum_k C_Pk (f_k - f^eq_k)
@@ -737,9 +742,10 @@ __device__ __forceinline__ void fv_add(FvAcc<T>& A, int z, const T (&f)[9], bool
 }
 
 // New populations and moments of the node from its accumulators.
+// pre: (rho, u_x, u_y) of the update before the no-slip reset (wall nodes).
 template <typename T, bool SHIFT>
 __device__ __forceinline__ void fv_finish(const KMesh& M, int P, const FvAcc<T>& A, T (&fn)[9], T& r, T& dr, T& ux,
-                                          T& uy) {
+                                          T& uy, T (&pre)[3]) {
     const T rho0 = T(M.rho0), dt = T(M.dt), dtt = T(M.dt_over_tau);
     // x_i = a0 + 3 c_i.a1 + 9/2 c_i^T a2 c_i - 3/2 tr a2, with the shared parts
     // b = a0 - 3/2 tr a2 and c_i^T a2 c_i in {0, a_xx, a_yy, tr a2 +- 2 a_xy}
@@ -771,6 +777,7 @@ __device__ __forceinline__ void fv_finish(const KMesh& M, int P, const FvAcc<T>&
 #pragma unroll
     for (int q = 0; q < 9; ++q) fn[q] = A.base[q] + dt * A.ss[q] - dtt * col[q];
     macro<T, SHIFT>(fn, rho0, r, dr, ux, uy);
+    pre[0] = r, pre[1] = ux, pre[2] = uy;
     if (M.wall_bc && P < M.n_wall) {
         T feq[9], feq0[9];
         equilibrium<T, SHIFT>(r, dr, ux, uy, feq);
@@ -838,20 +845,36 @@ __global__ __launch_bounds__(256) void k_fv_substep(const KMesh M, const T* __re
                              e[a].c, rho0);
         }
     }
-    T fn[9], r, dr, ux, uy;
-    fv_finish<T, SHIFT>(M, P, A, fn, r, dr, ux, uy);
+    T fn[9], r, dr, ux, uy, pre[3];
+    fv_finish<T, SHIFT>(M, P, A, fn, r, dr, ux, uy, pre);
     store_rec(fout + size_t(P) * kRec, fn, SHIFT ? dr : r, ux, uy);
+    if (M.wmom && P < M.n_wall) store_wmom(M.wmom + 3 * size_t(P), pre);
+}
+
+// The rest of a staged f* record [f*_0..f*_8, f^neq_0..f^neq_8, unused x 2]
+// after its first twelve values (read like a node record): f^neq_3..f^neq_8.
+template <typename T>
+__device__ __forceinline__ void load_star_tail(const T* __restrict__ s, T (&nq)[9]) {
+    if constexpr (sizeof(T) == 4) {
+        const float4 a = reinterpret_cast<const float4*>(s)[3];
+        const float2 b = reinterpret_cast<const float2*>(s)[8];
+        nq[3] = a.x; nq[4] = a.y; nq[5] = a.z; nq[6] = a.w; nq[7] = b.x; nq[8] = b.y;
+    } else {
+        const double2* v = reinterpret_cast<const double2*>(s);
+        const double2 a = v[6], b = v[7], c = v[8];
+        nq[3] = a.x; nq[4] = a.y; nq[5] = b.x; nq[6] = b.y; nq[7] = c.x; nq[8] = c.y;
+    }
 }
 
 // One node update of the fused kernel: local node i with its edge records e,
-// reading the tile state in buf; returns the node's plan index.  Which
-// neighbours enter through f* is in the edge records (kFtStar), so a regular
-// node reads its neighbours' records without looking up their plan indices.
+// reading the tile state in buf and, for neighbours that enter through f*
+// (kFtStar in the edge record), the values staged in st for this sub-step;
+// returns the node's plan index.
 template <typename T, bool SHIFT, int W>
 __device__ __forceinline__ int fv_tile_node(const KMesh& M, const T* __restrict__ buf, const int32_t* gid,
-                                            const T* __restrict__ prep0, const T* __restrict__ prep1, T theta,
-                                            int i, const EdgeRec<T> (&e)[W], T (&fn)[9], T (&mv)[3]) {
-    const T rho0 = T(M.rho0), cst = T(M.star_neq);
+                                            const T* __restrict__ st, int i, const EdgeRec<T> (&e)[W], T (&fn)[9],
+                                            T (&mv)[3], double* wmom = nullptr) {
+    const T rho0 = T(M.rho0);
     const int P = gid[i];
     FvAcc<T> A;
 #pragma unroll
@@ -860,18 +883,21 @@ __device__ __forceinline__ int fv_tile_node(const KMesh& M, const T* __restrict_
         if (cz < 0) continue;
         const bool star = (cz & kFtStar) != 0;
         const int lc = cz & kFtLocal;
-        T f[9], nq[9], mk = 0, uxk = 0, uyk = 0;
+        // both record kinds start with the nine populations: one vector read of the
+        // first twelve values, then the rest of f^neq for an f* record
+        const T* src = star ? st + size_t(lc) * kStarRec : buf + size_t(lc) * kRec;
+        T f[9], nq[9], mk, uxk, uyk;
+        load_rec(src, f, mk, uxk, uyk);
         if (star) {
-            const size_t sl = size_t(gid[lc] - M.n_core) * kMacro;
-            star_values<T, SHIFT>(prep0 + sl, prep1 + sl, theta, cst, rho0, f, nq);
-        } else {
-            load_rec(buf + size_t(lc) * kRec, f, mk, uxk, uyk);
+            nq[0] = mk; nq[1] = uxk; nq[2] = uyk;
+            load_star_tail(src, nq);
         }
         fv_add<T, SHIFT>(A, z, f, star, nq, mk, uxk, uyk, e[z].gx, e[z].gy, e[z].c, rho0);
     }
-    T r, dr;
-    fv_finish<T, SHIFT>(M, P, A, fn, r, dr, mv[1], mv[2]);
+    T r, dr, pre[3];
+    fv_finish<T, SHIFT>(M, P, A, fn, r, dr, mv[1], mv[2], pre);
     mv[0] = SHIFT ? dr : r;
+    if (wmom && P < M.n_wall) store_wmom(wmom + 3 * size_t(P), pre);
     return P;
 }
 
@@ -904,6 +930,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
     extern __shared__ __align__(16) unsigned char smem[];
     T* const buf = reinterpret_cast<T*>(smem);
     int32_t* const gid = reinterpret_cast<int32_t*>(buf + size_t(M.maxl) * kRec);
+    // f* of the tile's interpolation nodes, sub-step j of the launch at stg + j * stj
+    T* const stg = reinterpret_cast<T*>(smem + (size_t(M.maxl) * (kRec * sizeof(T) + 4) + 15) / 16 * 16);
+    const size_t stj = size_t(M.maxs) * kStarRec;
     const int t = die_block(blockIdx.x, gridDim.x);
     const int32_t* meta = M.ft_meta + size_t(t) * kTileMeta;
     const int noff = meta[0], eoff = meta[1], width = meta[2];
@@ -930,6 +959,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
             store_rec(buf + size_t(i) * kRec, f[r], mm[r][0], mm[r][1], mm[r][2]);
         }
     }
+    // f* (eqs. (5)-(7)) of each interpolation node that a pivot of the tile reads
+    // through it, once per sub-step, shared by all its readers
+    {
+        const int soff = meta[8], ns = meta[9];
+        const T rho0 = T(M.rho0), cst = T(M.star_neq);
+        for (int s = int(threadIdx.x); s < ns; s += int(blockDim.x)) {
+            const size_t sl = size_t(M.ft_star[soff + s]) * kMacro;
+            for (int j = 0; j < ksteps; ++j) {
+                T fs[9], nq[9];
+                star_values<T, SHIFT>(prep0 + sl, prep1 + sl, T(th.v[j]), cst, rho0, fs, nq);
+                T* d = stg + j * stj + size_t(s) * kStarRec;
+#pragma unroll
+                for (int q = 0; q < 9; ++q) d[q] = fs[q], d[9 + q] = nq[q];
+            }
+        }
+    }
     __syncthreads();
     const int B = int(blockDim.x), tx = int(threadIdx.x);
     if (ksteps == 2) {
@@ -937,21 +982,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
         // records of node tx (the same local node in both sub-steps) stay in
         // registers for sub-step 2, which takes node tx first.
         const int n1 = meta[4];
-        const T th1 = T(th.v[0]), th2 = T(th.v[1]);
+        const T* const st1 = stg;
+        const T* const st2 = stg + stj;
         EdgeRec<T> e[W], e0[W];
         T r1[9], m1[3], r0[9], m0v[3];
         const bool has1 = tx + B < n1, has0 = tx < n1;
         if (has1) {
 #pragma unroll
             for (int z = 0; z < W; ++z) e[z] = E[size_t(z) * width + tx + B];
-            const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, prep0, prep1, th1, tx + B, e, r1, m1);
+            const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, st1, tx + B, e, r1, m1,
+                                                    tx + B < ntile ? M.wmom : nullptr);
             if (mid && tx + B < ntile) store_rec(mid + size_t(P) * kRec, r1, m1[0], m1[1], m1[2]);
         }
         __builtin_amdgcn_sched_barrier(0);
         if (has0) {
 #pragma unroll
             for (int z = 0; z < W; ++z) e0[z] = E[size_t(z) * width + tx];
-            const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, prep0, prep1, th1, tx, e0, r0, m0v);
+            const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, st1, tx, e0, r0, m0v, tx < ntile ? M.wmom : nullptr);
             if (mid && tx < ntile) store_rec(mid + size_t(P) * kRec, r0, m0v[0], m0v[1], m0v[2]);
         }
         __syncthreads();   // every read of sub-step 1 is done
@@ -959,21 +1006,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
         if (has0) store_rec(buf + size_t(tx) * kRec, r0, m0v[0], m0v[1], m0v[2]);
         __syncthreads();
         if (tx < ntile) {
-            const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, prep0, prep1, th2, tx, e0, r0, m0v);
+            const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, st2, tx, e0, r0, m0v,
+                                                    M.wmom ? M.wmom + M.wmom_stride : nullptr);
             store_rec(fout + size_t(P) * kRec, r0, m0v[0], m0v[1], m0v[2]);
         }
         __builtin_amdgcn_sched_barrier(0);
         if (tx + B < ntile) {
 #pragma unroll
             for (int z = 0; z < W; ++z) e[z] = E[size_t(z) * width + tx + B];
-            const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, prep0, prep1, th2, tx + B, e, r1, m1);
+            const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, st2, tx + B, e, r1, m1,
+                                                    M.wmom ? M.wmom + M.wmom_stride : nullptr);
             store_rec(fout + size_t(P) * kRec, r1, m1[0], m1[1], m1[2]);
         }
         return;
     }
     for (int j = 1; j <= ksteps; ++j) {
         const int ncomp = meta[3 + ksteps - j];
-        const T theta = T(th.v[j - 1]);
+        const T* const stj_ = stg + (j - 1) * stj;
         const bool last = j == ksteps;
         T res[kFvStage][9], rm[kFvStage][3];
 #pragma unroll
@@ -983,7 +1032,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
             EdgeRec<T> e[W];
 #pragma unroll
             for (int z = 0; z < W; ++z) e[z] = E[size_t(z) * width + i];
-            const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, prep0, prep1, theta, i, e, res[s2], rm[s2]);
+            const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, stj_, i, e, res[s2], rm[s2],
+                                                    M.wmom && i < ntile ? M.wmom + (j - 1) * M.wmom_stride : nullptr);
             if (last) store_rec(fout + size_t(P) * kRec, res[s2], rm[s2][0], rm[s2][1], rm[s2][2]);
             else if (mid && i < ntile)
                 store_rec(mid + size_t(j - 1) * mid_stride + size_t(P) * kRec, res[s2], rm[s2][0], rm[s2][1], rm[s2][2]);
@@ -1171,7 +1221,7 @@ void launch_fv_fused(int prec, const KMesh& M, const void* fin, void* fout, cons
                      int m0, int k, hipStream_t s, void* mid, size_t mid_stride_bytes) {
     if (M.n_tiles <= 0 || k < 1 || k > M.fuse) return;
     const size_t elem = prec == HLBM_FP64 ? 8 : 4;
-    const size_t lds = size_t(M.maxl) * (kRec * elem + 4);
+    const size_t lds = fv_lds_bytes(M.maxl, M.maxs, k, elem);
     const unsigned threads = unsigned(M.threads);
     if (size_t(M.maxw) > size_t(kFvStage) * threads || threads > 256) return;   // rejected by the plan
     FvTheta th;   // theta = m / n of sub-steps m0 .. m0 + k - 1, as the one-sub-step launches take it
@@ -1363,51 +1413,12 @@ __device__ __forceinline__ void store_adj(double* __restrict__ p, const D9& v) {
     r[4] = double2{v[8], 0.0};
 }
 
-// Adjoint of the no-slip reset at wall pivot P: recompute the pre-reset update
-// fn_P of the sub-step from its input fin and map the adjoint yb of the reset
-// output onto it, zb = R'(fn_P)^T yb.
-__device__ __forceinline__ void wall_reset_adj(const KAdj& K, const double* fin, const double* prep0,
-                                               const double* prep1, double theta, int P, const D9& yb, D9& zb) {
-    const KMesh& M = K.M;
-    const int nn = M.nn, W = M.ell_width;
-    const EdgeRec<double>* E = reinterpret_cast<const EdgeRec<double>*>(M.edges);
-    double base[9], ss[9], sc[9];
-    // eight slots at a time: their table entries, then their records, are
-    // loaded together (two rounds of dependent loads instead of sixteen)
-    constexpr int G = 8;
-    for (int g0 = 0; g0 < W; g0 += G) {
-        EdgeRec<double> e[G];
-        double fr[G][9], mr[G][3];
-#pragma unroll
-        for (int a = 0; a < G; ++a) e[a] = E[size_t(g0 + a) * nn + P];
-#pragma unroll
-        for (int a = 0; a < G; ++a)
-            load_rec(fin + size_t(e[a].col < 0 ? P : e[a].col) * kRec, fr[a], mr[a][0], mr[a][1], mr[a][2]);
-#pragma unroll
-        for (int a = 0; a < G; ++a) {
-            if (e[a].col < 0) continue;
-            // wall nodes are never interpolation nodes: stored values only (as fv_value)
-            double feq[9], nq[9];
-            equilibrium<double, false>(mr[a][0], mr[a][0], mr[a][1], mr[a][2], feq);
-#pragma unroll
-            for (int q = 0; q < 9; ++q) nq[q] = fr[a][q] - feq[q];
-            if (g0 + a == 0) {
-#pragma unroll
-                for (int q = 0; q < 9; ++q) base[q] = fr[a][q], ss[q] = 0.0, sc[q] = e[a].c * nq[q];
-            } else {
-#pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    ss[q] += (CX[q] * e[a].gx + CY[q] * e[a].gy) * (fr[a][q] - base[q]);
-                    sc[q] += e[a].c * nq[q];
-                }
-            }
-        }
-    }
-    double fn[9], rho, ux, uy;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) fn[q] = base[q] + K.dt * ss[q] - K.dtt * sc[q];
-    macro64(fn, rho, ux, uy);
-    // out = feq(rho, 0) + fn - feq(rho, u)
+// Adjoint of the no-slip reset at a wall node, out = f^eq(rho, 0) + fn - f^eq(rho, u):
+// maps the adjoint yb of the reset output onto the pre-reset update fn,
+// zb = R'(fn)^T yb, which depends on fn only through its (rho, u), recorded by
+// the forward sub-step in w = (rho, u_x, u_y).
+__device__ __forceinline__ void wall_reset_apply(const double* __restrict__ w, const D9& yb, D9& zb) {
+    const double rho = w[0], ux = w[1], uy = w[2];
     double rb = 0.0, uxb = 0.0, uyb = 0.0, eb[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
@@ -1422,17 +1433,14 @@ __device__ __forceinline__ void wall_reset_adj(const KAdj& K, const double* fin,
 // No-slip reset adjoint of the last sub-step of a finest step (per wall pivot P):
 // zwall_P (layout [9][n_wall]) from ybar_P.  Earlier sub-steps get theirs from
 // k_adj_fv of the sub-step after them.
-__global__ __launch_bounds__(256) void k_adj_fv_wall(const KAdj K, const double* __restrict__ fin,
-                                                     const double* __restrict__ ybar, double* __restrict__ zwall,
-                                                     const double* __restrict__ prep0, const double* __restrict__ prep1,
-                                                     double theta) {
+__global__ __launch_bounds__(256) void k_adj_fv_wall(const KAdj K, const double* __restrict__ wmom,
+                                                     const double* __restrict__ ybar, double* __restrict__ zwall) {
     const KMesh& M = K.M;
     const int P = blockIdx.x * blockDim.x + threadIdx.x;
     if (P >= M.n_wall) return;
     double yb[9], zb[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) yb[q] = ybar[size_t(P) * kAdjRec + q];
-    wall_reset_adj(K, fin, prep0, prep1, theta, P, yb, zb);
+    load_adj(ybar + size_t(P) * kAdjRec, yb);
+    wall_reset_apply(wmom + 3 * size_t(P), yb, zb);
     store_adj(zwall + size_t(P) * kAdjRec, zb);
 }
 
@@ -1449,9 +1457,10 @@ __global__ __launch_bounds__(256) void k_adj_fv_wall(const KAdj K, const double*
 // (P, k) are accumulated too, in the transposed slot of k (one writer per
 // slot, so no conflicts; consecutive k are consecutive in memory): the
 // neighbour part of G_Pk here, the pivot's base part once per pivot in gpivot.
-// With fin_prev set (the input of the previous sub-step), wall nodes also take
-// the no-slip reset transpose of that sub-step from the adjoint just computed,
-// into zwall_prev, so the next launch needs no separate wall pass.
+// With wmom_prev set (the pre-reset (rho, u) of the wall nodes in the previous
+// sub-step, recorded by the forward), wall nodes also take the no-slip reset
+// transpose of that sub-step from the adjoint just computed, into zwall_prev,
+// so the next launch needs no separate wall pass.
 // Adjoint of the values of node k read through one class of pivots: the stored
 // mesh value (STAR = false: every pivot unless both are interpolation nodes)
 // or the star value of an interpolation node (STAR = true: interpolation
@@ -1538,8 +1547,7 @@ __global__ __launch_bounds__(B) void k_adj_fv(const KAdj K, const double* __rest
                                                 double* __restrict__ mbar, const double* __restrict__ prep0,
                                                 const double* __restrict__ prep1, double theta,
                                                 double* __restrict__ p0bar, double* __restrict__ p1bar, int pslot,
-                                                const double* __restrict__ fin_prev, double theta_prev,
-                                                double* __restrict__ zwall_prev) {
+                                                const double* __restrict__ wmom_prev, double* __restrict__ zwall_prev) {
     const KMesh& M = K.M;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     double dtau = 0.0;
@@ -1561,9 +1569,9 @@ __global__ __launch_bounds__(B) void k_adj_fv(const KAdj K, const double* __rest
             }
             macro_neq_adj(f, a12, vb);
             store_adj(mbar + size_t(k) * kAdjRec, vb);
-            if (fin_prev && k < (M.wall_bc ? M.n_wall : 0)) {
+            if (wmom_prev && k < (M.wall_bc ? M.n_wall : 0)) {
                 double zb[9];
-                wall_reset_adj(K, fin_prev, prep0, prep1, theta_prev, k, vb, zb);
+                wall_reset_apply(wmom_prev + 3 * size_t(k), vb, zb);
                 store_adj(zwall_prev + size_t(k) * kAdjRec, zb);
             }
         }
@@ -1615,8 +1623,7 @@ __global__ __launch_bounds__(B) void k_adj_fv2(const KAdj K, const double* __res
                                                 double* __restrict__ mbar, const double* __restrict__ prep0,
                                                 const double* __restrict__ prep1, double theta,
                                                 double* __restrict__ p0bar, double* __restrict__ p1bar, int pslot,
-                                                const double* __restrict__ fin_prev, double theta_prev,
-                                                double* __restrict__ zwall_prev) {
+                                                const double* __restrict__ wmom_prev, double* __restrict__ zwall_prev) {
     const KMesh& M = K.M;
     const int gt = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = gt >> 1, h = gt & 1;   // lanes 2k, 2k + 1: slots 0-3, 4-7 of node k
@@ -1642,9 +1649,9 @@ __global__ __launch_bounds__(B) void k_adj_fv2(const KAdj K, const double* __res
             }
             macro_neq_adj(f, a12, vb);
             store_adj(mbar + size_t(k) * kAdjRec, vb);
-            if (fin_prev && k < (M.wall_bc ? M.n_wall : 0)) {
+            if (wmom_prev && k < (M.wall_bc ? M.n_wall : 0)) {
                 double zb[9];
-                wall_reset_adj(K, fin_prev, prep0, prep1, theta_prev, k, vb, zb);
+                wall_reset_apply(wmom_prev + 3 * size_t(k), vb, zb);
                 store_adj(zwall_prev + size_t(k) * kAdjRec, zb);
             }
             }
@@ -2155,14 +2162,13 @@ void launch_adj_force(const KAdj& K, double* mbar, const double* vwall, double j
     if (K.M.n_wall > 0)
         k_adj_force<<<blocks(K.M.n_wall), 256, 0, s>>>(K.M.n_wall, mbar, vwall, jx, jy, fst, K.vbar);
 }
-void launch_adj_fv_wall(const KAdj& K, const double* Mrec, const double* ybar, double* zwall, const double* prep0,
-                        const double* prep1, double theta, hipStream_t s) {
+void launch_adj_fv_wall(const KAdj& K, const double* wmom, const double* ybar, double* zwall, hipStream_t s) {
     if (K.M.wall_bc && K.M.n_wall > 0)
-        k_adj_fv_wall<<<blocks(K.M.n_wall), 256, 0, s>>>(K, Mrec, ybar, zwall, prep0, prep1, theta);
+        k_adj_fv_wall<<<blocks(K.M.n_wall), 256, 0, s>>>(K, wmom, ybar, zwall);
 }
 void launch_adj_fv(const KAdj& K, const double* Mrec, const double* ybar, const double* zwall, double* mbar,
                    const double* prep0, const double* prep1, double theta, double* p0bar, double* p1bar, int pslot,
-                   const double* Mprev, double theta_prev, double* zwall_prev, hipStream_t s) {
+                   const double* wmom_prev, double* zwall_prev, hipStream_t s) {
     // Small 8-slot meshes (at most one wave per SIMD of one node per lane) take
     // two lanes per node, so each lane waits on one round of dependent loads;
     // measured on the 33k-node bump workload, (objective + adjoint)/forward:
@@ -2172,13 +2178,13 @@ void launch_adj_fv(const KAdj& K, const double* Mrec, const double* ybar, const 
     const unsigned nb = unsigned(adj_fv_blocks(K.M));
     if (adj_fv_two_lanes(K.M))
         k_adj_fv2<kAdjFvBlock><<<nb, kAdjFvBlock, 0, s>>>(K, Mrec, ybar, zwall, mbar, prep0, prep1, theta, p0bar,
-                                                              p1bar, pslot, Mprev, theta_prev, zwall_prev);
+                                                              p1bar, pslot, wmom_prev, zwall_prev);
     else if (K.M.ell_width == 8)
         k_adj_fv<8, kAdjFvBlock, 2><<<nb, kAdjFvBlock, 0, s>>>(K, Mrec, ybar, zwall, mbar, prep0, prep1, theta, p0bar,
-                                                              p1bar, pslot, Mprev, theta_prev, zwall_prev);
+                                                              p1bar, pslot, wmom_prev, zwall_prev);
     else
         k_adj_fv<16, kAdjFvBlock, 2><<<nb, kAdjFvBlock, 0, s>>>(K, Mrec, ybar, zwall, mbar, prep0, prep1, theta, p0bar,
-                                                               p1bar, pslot, Mprev, theta_prev, zwall_prev);
+                                                               p1bar, pslot, wmom_prev, zwall_prev);
 }
 void launch_adj_collide(const KAdj& K, const double* A, const double* bbar, double* prebar, int pslot, hipStream_t s) {
     dim3 grid(blocks(K.L.nx), K.L.ny);

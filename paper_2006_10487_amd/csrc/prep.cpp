@@ -536,8 +536,11 @@ void build_fv_tiles(Plan& p, int tile, int fuse) {
     p.n_tiles = int(tiles.size());
     p.fv_maxl = 0;
     p.fv_maxw = 0;
+    p.fv_maxs = 0;
     p.ft_meta.assign(size_t(p.n_tiles) * kTileMeta, 0);
     p.ft_node.clear();
+    p.ft_star.clear();
+    std::vector<int> sstamp(nn, -1), sslot(nn, -1);
     p.ft_col.clear();
     p.ft_src.clear();
     std::vector<int> stamp(nn, -1), loc(nn, -1);
@@ -569,15 +572,29 @@ void build_fv_tiles(Plan& p, int tile, int fuse) {
         meta[1] = int(p.ft_col.size());
         meta[2] = width;
         p.ft_node.insert(p.ft_node.end(), nodes.begin(), nodes.end());
+        meta[8] = int(p.ft_star.size());
+        int ns = 0;
         for (int z = 0; z < W; ++z)
             for (int i = 0; i < width; ++i) {
                 const int P = nodes[i], zz = p.rowptr[P] + z;
                 const bool used = zz < p.rowptr[P + 1];
                 // an interpolation pivot reads f* (eqs. (5)-(7)) for its interpolation neighbours
                 const bool star = used && P >= p.n_core && p.col[zz] >= p.n_core;
-                p.ft_col.push_back(used ? loc[p.col[zz]] | (star ? kFtStar : 0) : -1);
+                int32_t c = used ? loc[p.col[zz]] : -1;
+                if (star) {
+                    const int b = p.col[zz];
+                    if (sstamp[b] != t) {
+                        sstamp[b] = t;
+                        sslot[b] = ns++;
+                        p.ft_star.push_back(b - p.n_core);
+                    }
+                    c = sslot[b] | kFtStar;
+                }
+                p.ft_col.push_back(c);
                 p.ft_src.push_back(used ? zz : -1);
             }
+        meta[9] = ns;
+        p.fv_maxs = std::max(p.fv_maxs, ns);
         p.fv_maxl = std::max(p.fv_maxl, int(nodes.size()));
         p.fv_maxw = std::max(p.fv_maxw, width);
     }
@@ -827,7 +844,7 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
             choose_fv_tiles(p, k);
             const int need = (p.fv_maxw + kFvStage - 1) / kFvStage;
             p.fv_threads = std::max(p.elem == 8 ? kFvThreadsF64 : kFvThreadsF32, (need + 63) / 64 * 64);
-            const size_t lds = size_t(p.fv_maxl) * (kRec * p.elem + 4);
+            const size_t lds = fv_lds_bytes(p.fv_maxl, p.fv_maxs, k, p.elem);
             if (lds <= 65536 && p.fv_threads <= 256) break;
             p.fv_fuse = 1;
             p.n_tiles = 0;
@@ -835,6 +852,7 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
             p.ft_node.clear();
             p.ft_col.clear();
             p.ft_src.clear();
+            p.ft_star.clear();
         }
         // wall statistics: unit normal into the fluid at each wall node (opposite
         // to half the sum of its wall-edge normals) and its output slot
@@ -951,6 +969,7 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
     p.off.ft_meta = take(p.ft_meta.size() * 4);
     p.off.ft_node = take(p.ft_node.size() * 4);
     p.off.ft_edges = take(p.ft_col.size() * (E == 8 ? 32 : 16));
+    p.off.ft_star = take(p.ft_star.size() * 4);
     size_t maxrow = 0;
     for (int l = 0; l <= p.L; ++l) maxrow = std::max(maxrow, size_t(p.lev[l].nx));
     p.stage_bytes = std::max(size_t(kQ) * maxrow * 8 * 8, std::min(size_t(32) << 20, size_t(kQ) * maxrow * 8 * 4096));
