@@ -1617,6 +1617,9 @@ __device__ __forceinline__ double pair_sum(double v) {
 // gathers slots 4h..4h+3 (one round of four table entries, then four pivot
 // adjoints), the two partial sums are added with pair_sum, and lane 0 finishes
 // the node.  The same terms as k_adj_fv, with the slot sum split in two halves.
+// Threads 2 nn .. 2 nn + 2 n_int - 1 take the star values of the interpolation
+// nodes on lane pairs of their own, so that those gathers run beside the
+// stored-value gathers instead of after them.
 template <int B>
 __global__ __launch_bounds__(B) void k_adj_fv2(const KAdj K, const double* __restrict__ fin,
                                                 const double* __restrict__ ybar, const double* __restrict__ zwall,
@@ -1626,11 +1629,13 @@ __global__ __launch_bounds__(B) void k_adj_fv2(const KAdj K, const double* __res
                                                 const double* __restrict__ wmom_prev, double* __restrict__ zwall_prev) {
     const KMesh& M = K.M;
     const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = gt >> 1, h = gt & 1;   // lanes 2k, 2k + 1: slots 0-3, 4-7 of node k
+    const bool star_lane = gt >= 2 * M.nn;
+    const int k = star_lane ? M.n_core + ((gt - 2 * M.nn) >> 1) : gt >> 1;
+    const int h = gt & 1;   // lanes 2k, 2k + 1: slots 0-3, 4-7 of node k
     double dtau = 0.0;
-    if (k < M.nn) {
+    const double rdt = K.ddtt_dtau / K.dtt;
+    if (!star_lane && k < M.nn) {
         const bool k_interp = k >= M.n_core;
-        const double rdt = K.ddtt_dtau / K.dtt;
         {   // the stored value M^m_k
             double f[9], m0, ux, uy, feq[9], nq[9], vb[9], nqb[9];
             load_rec(fin + size_t(k) * kRec, f, m0, ux, uy);
@@ -1656,7 +1661,7 @@ __global__ __launch_bounds__(B) void k_adj_fv2(const KAdj K, const double* __res
             }
             }
         }
-        if (k_interp) {   // the star value f*_k read by interpolation pivots
+    } else if (star_lane && k < M.nn) {   // the star value f*_k read by interpolation pivots
             const size_t sl = size_t(k - M.n_core) * kMacro;
             double v[12], fs[9], ns[9], fsb[9], nsb[9];
             star64(prep0 + sl, prep1 + sl, theta, K.cst, v, fs, ns);
@@ -1683,7 +1688,6 @@ __global__ __launch_bounds__(B) void k_adj_fv2(const KAdj K, const double* __res
                 p1bar[sl + m] += theta * w12[m];
             }
             }
-        }
     }
     block_partial<B>(0.0, dtau, K.partial, pslot);
 }
@@ -2150,8 +2154,8 @@ bool adj_fv_two_lanes(const KMesh& M) {
     return M.ell_width == 8 && size_t(M.nn) <= size_t(kAdjFvSimds) * kAdjFvBlock;
 }
 int adj_fv_blocks(const KMesh& M) {
-    const size_t n = M.nn > 0 ? size_t(M.nn) : 1;
-    return int(blocks(adj_fv_two_lanes(M) ? 2 * n : n, kAdjFvBlock));
+    const size_t n = M.nn > 0 ? size_t(M.nn) : 1, n_int = size_t(M.nn - M.n_core);
+    return int(blocks(adj_fv_two_lanes(M) ? 2 * (n + n_int) : n, kAdjFvBlock));
 }
 
 void launch_zero(double* p, size_t n, hipStream_t s) {
