@@ -629,20 +629,31 @@ template <> struct alignas(16) EdgeRec<float> { int32_t col; float gx, gy, c; };
 
 // f* at a mesh interpolation node (eqs. (5)-(6)): the structured (rho, u,
 // f^neq) blended linearly in time, f* = f^eq(rho, u) + (1 - 1/(2 tau_s)) f^neq;
-// nstar = its non-equilibrium part.
+// nstar = its non-equilibrium part.  Evaluated without floating-point
+// contraction (the equilibrium written out here for that), so that every
+// kernel that forms f* rounds it the same way whatever code surrounds the
+// call: the fused and the one-sub-step finite-volume kernels give the same
+// bits, and an adjoint segment that keeps its sub-step states agrees bit for
+// bit with one that recomputes them.
 template <typename T, bool SHIFT>
 __device__ __forceinline__ void star_values(const T* __restrict__ p0, const T* __restrict__ p1, T theta, T cst,
                                             T rho0, T (&fs)[9], T (&ns)[9]) {
+#pragma clang fp contract(off)
     T v[kMacro];
 #pragma unroll
     for (int m = 0; m < kMacro; ++m) v[m] = (T(1) - theta) * p0[m] + theta * p1[m];
     const T rho = SHIFT ? rho0 + v[0] : v[0], dr = SHIFT ? v[0] : v[0] - rho0;
-    T feq[9];
-    equilibrium<T, SHIFT>(rho, dr, v[1], v[2], feq);
+    const T ux = v[1], uy = v[2], uu = ux * ux + uy * uy;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
+        const T cu = cdot(q, ux, uy);
+        const T poly = T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu;
+        T feq;
+        if constexpr (SHIFT && sizeof(T) == 4) feq = weighted_f32(q, dr + rho * poly);
+        else if constexpr (SHIFT) feq = wgt<T>(q) * (dr + rho * poly);
+        else feq = wgt<T>(q) * rho * (T(1) + poly);
         ns[q] = cst * v[3 + q];
-        fs[q] = feq[q] + ns[q];
+        fs[q] = feq + ns[q];
     }
 }
 
@@ -938,6 +949,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
     const int noff = meta[0], eoff = meta[1], width = meta[2];
     const int nload = meta[3 + ksteps], ntile = meta[3];
     const EdgeRec<T>* __restrict__ E = reinterpret_cast<const EdgeRec<T>*>(M.ft_edges) + eoff;
+    // structured values (t, t + 1) of this thread's interpolation node, if the tile
+    // stages one for it (at most one per thread), loaded before the records
+    const int soff = meta[8], ns = meta[9];
+    const bool has_star = int(threadIdx.x) < ns;
+    T sp0[kMacro], sp1[kMacro];
+    if (has_star) {
+        const size_t sl = size_t(M.ft_star[soff + threadIdx.x]) * kMacro;
+#pragma unroll
+        for (int m = 0; m < kMacro; ++m) sp0[m] = prep0[sl + m], sp1[m] = prep1[sl + m];
+    }
     // records of the tile and its rings: all loads of a batch in flight together
     constexpr int kBatch = 3;
     for (int i0 = 0; i0 < nload; i0 += kBatch * int(blockDim.x)) {
@@ -961,18 +982,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
     }
     // f* (eqs. (5)-(7)) of each interpolation node that a pivot of the tile reads
     // through it, once per sub-step, shared by all its readers
-    {
-        const int soff = meta[8], ns = meta[9];
+    if (has_star) {
         const T rho0 = T(M.rho0), cst = T(M.star_neq);
-        for (int s = int(threadIdx.x); s < ns; s += int(blockDim.x)) {
-            const size_t sl = size_t(M.ft_star[soff + s]) * kMacro;
-            for (int j = 0; j < ksteps; ++j) {
-                T fs[9], nq[9];
-                star_values<T, SHIFT>(prep0 + sl, prep1 + sl, T(th.v[j]), cst, rho0, fs, nq);
-                T* d = stg + j * stj + size_t(s) * kStarRec;
+        for (int j = 0; j < ksteps; ++j) {
+            T fs[9], nq[9];
+            star_values<T, SHIFT>(sp0, sp1, T(th.v[j]), cst, rho0, fs, nq);
+            T* d = stg + j * stj + size_t(threadIdx.x) * kStarRec;
 #pragma unroll
-                for (int q = 0; q < 9; ++q) d[q] = fs[q], d[9 + q] = nq[q];
-            }
+            for (int q = 0; q < 9; ++q) d[q] = fs[q], d[9 + q] = nq[q];
         }
     }
     __syncthreads();

@@ -845,7 +845,8 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
             const int need = (p.fv_maxw + kFvStage - 1) / kFvStage;
             p.fv_threads = std::max(p.elem == 8 ? kFvThreadsF64 : kFvThreadsF32, (need + 63) / 64 * 64);
             const size_t lds = fv_lds_bytes(p.fv_maxl, p.fv_maxs, k, p.elem);
-            if (lds <= 65536 && p.fv_threads <= 256) break;
+            // each thread stages at most one f* node
+            if (lds <= 65536 && p.fv_threads <= 256 && p.fv_maxs <= p.fv_threads) break;
             p.fv_fuse = 1;
             p.n_tiles = 0;
             p.ft_meta.clear();
