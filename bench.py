@@ -269,24 +269,32 @@ def cpu_baseline(hlbm, torch, workloads, preset, w, r32, base_steps, c0_steps):
 
 def drift(hlbm, torch, w, finest_steps):
     """C_D and C_L of the bench workload over `finest_steps` finest steps in FP32-shifted
-    and FP64 storage: means over the second half and their differences."""
+    and FP64 storage: means over the second half and their differences.  A third
+    run in FP64 with the angle of attack moved by 1e-9 rad measures how far the
+    flow itself carries a perturbation of that size (its deterministic effect on
+    the means is ~1e-9): FP32 deviations of the same size are flow sensitivity."""
     out = {"finest_steps": finest_steps, "window": [finest_steps // 2, finest_steps]}
     hist = {}
-    for name, prec in (("fp64", hlbm.FP64), ("fp32", hlbm.FP32_SHIFTED)):
-        sim = hlbm.HLBM.from_workload(w, precision=prec, history_len=finest_steps + 8, check_every=1000)
+    for name, prec, da in (("fp64", hlbm.FP64, 0.0), ("fp32", hlbm.FP32_SHIFTED, 0.0),
+                           ("fp64_aoa_plus_1e-9", hlbm.FP64, 1e-9)):
+        sim = hlbm.HLBM.from_workload(w, precision=prec, history_len=finest_steps + 8, check_every=1000,
+                                      aoa_rad=w.aoa_rad + da)
         progress(f"drift run {name}")
         sim.step_logged(finest_steps, name)
         hist[name] = sim.history(0, finest_steps)
         sim.close()
     h = slice(finest_steps // 2, finest_steps)
-    for name in ("fp64", "fp32"):
+    for name in ("fp64", "fp32", "fp64_aoa_plus_1e-9"):
         cd, cl = hist[name]
         out[name] = {"cd_mean": float(np.mean(cd[h])), "cl_mean": float(np.mean(cl[h])),
                      "cd_min": float(np.min(cd[h])), "cd_max": float(np.max(cd[h])),
                      "cl_min": float(np.min(cl[h])), "cl_max": float(np.max(cl[h]))}
-    d, s_ = out["fp64"], out["fp32"]
+    d, s_, pt = out["fp64"], out["fp32"], out["fp64_aoa_plus_1e-9"]
+    norm = max(abs(d["cl_mean"]), abs(d["cd_mean"]))
     out["cd_mean_rel_err"] = abs(s_["cd_mean"] - d["cd_mean"]) / abs(d["cd_mean"])
-    out["cl_mean_err_over_max_abs_cl_cd"] = abs(s_["cl_mean"] - d["cl_mean"]) / max(abs(d["cl_mean"]), abs(d["cd_mean"]))
+    out["cl_mean_err_over_max_abs_cl_cd"] = abs(s_["cl_mean"] - d["cl_mean"]) / norm
+    out["fp64_sensitivity_cd_rel"] = abs(pt["cd_mean"] - d["cd_mean"]) / abs(d["cd_mean"])
+    out["fp64_sensitivity_cl_over_max_abs_cl_cd"] = abs(pt["cl_mean"] - d["cl_mean"]) / norm
     return out
 
 
@@ -297,8 +305,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="naca_re5000_c512")
     ap.add_argument("--cpu-steps", type=int, default=16, help="base steps of the oracle sample (~10 s on 16 cores)")
-    ap.add_argument("--cpu-c0-steps", type=int, default=500,
-                    help="finest steps of the oracle legs on the Re 100 workload (its stated run is 2000)")
+    ap.add_argument("--cpu-c0-steps", type=int, default=2000,
+                    help="finest steps of the oracle legs on the Re 100 workload (its stated run)")
     ap.add_argument("--drift-steps", type=int, default=0,
                     help="also run the bench workload this many finest steps in both precisions and compare "
                          "the means of C_D and C_L over the second half")

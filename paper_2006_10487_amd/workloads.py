@@ -517,9 +517,12 @@ CONV_N_SUB = 70     # ceil(1 / tau_u) of the smallest chord: one FV time step fo
 # Levels of the Re 500 and Re-sweep families.  With acoustic scaling level l
 # has tau_l - 1/2 = (tau_s - 1/2) / 2^(L-l), so its cell Reynolds number is
 # U dx_l / nu_l = 2^(L-l) Re / c (in chords).  At 83 (Re 500, c = 48, four
-# levels) the upstream coarse-to-fine interface diverged after 4,000-8,000
-# steps (measured); two levels keep it at or below 21 in the convergence
-# family and at 4-39 in the Reynolds sweep.
+# levels, coarse tau 0.5018 and 0.5036) the upstream coarse-to-fine interface
+# diverged after 4,000-8,000 steps (measured).  The growth needs both
+# non-equilibrium rescalings of the refinement interface and sets in for a
+# coarse tau below about 0.506 (seeded-noise runs of the oracle, far field
+# only); two levels keep every coarse tau above that, with cell Reynolds
+# numbers at or below 21 in the convergence family and 4-39 in the sweep.
 FAMILY_BOXES = 1
 
 
