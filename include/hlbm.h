@@ -77,6 +77,11 @@ typedef struct {
                                      most 512 updated nodes per tile, else 1); 0 = 2 on meshes with at most
                                      8 neighbour slots per node, else 1.  Results do not depend on
                                      it (same arithmetic, same order)                                */
+    int32_t f2c_filter;           /* fine -> coarse transfer (Sec. 4): 0 = the rescaled f^neq of the
+                                     coincident fine node; 1 = that f^neq full-weighted over the
+                                     3 x 3 fine nodes around it (weights (2-|di|)(2-|dj|)/16), which
+                                     keeps the interface stable with tau close to 1/2 on the coarse
+                                     levels.  The discrete adjoint supports 0 only                   */
 } hlbm_grid;
 
 /* Body-fitted triangular mesh (Sec. 2 and 4). */

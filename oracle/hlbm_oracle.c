@@ -117,6 +117,9 @@ typedef struct {
     /* channel variant of the base-level boundaries (closed-form checks only):
      * no-slip top and bottom by non-equilibrium extrapolation, parabolic inlet */
     int32_t channel;
+    /* fine -> coarse restriction: 0 = f^neq of the coincident fine node,
+     * 1 = f^neq full-weighted over the 3 x 3 fine nodes around it */
+    int32_t f2c_filter;
 } or_cfg;
 
 typedef struct {
@@ -938,7 +941,10 @@ static void coarse_to_fine(oracle_t *o, int l, double theta)
 
 /* Fine -> coarse (Sec. 4): coarse nodes on the first ring inside the box get
  * the fine (rho, u) and the fine f^neq rescaled by 2 tau_c / tau_f, collided
- * at tau_c. */
+ * at tau_c.  With f2c_filter the f^neq is first averaged over the 3 x 3 fine
+ * nodes around the coincident one with full-weighting weights
+ * (2 - |di|)(2 - |dj|) / 16, which sum to one and reproduce fields linear in
+ * space; (rho, u) stay those of the coincident node. */
 static void fine_to_coarse(oracle_t *o, int l)
 {
     olevel *pa = &o->lev[l], *ch = &o->lev[l + 1];
@@ -947,8 +953,20 @@ static void fine_to_coarse(oracle_t *o, int l)
         for (int i = 0; i < pa->nx; ++i) {
             if (pa->cls[(size_t)j * pa->nx + i] != CL_RING) continue;
             real f[Q], rho, ux, uy, neq[Q], feq[Q], pre[Q], post[Q];
-            get_node(ch, ch->f, 2 * (i - ch->i0), 2 * (j - ch->j0), f);
+            const int fi = 2 * (i - ch->i0), fj = 2 * (j - ch->j0);
+            get_node(ch, ch->f, fi, fj, f);
             macro_neq(f, &rho, &ux, &uy, neq);
+            if (o->cfg.f2c_filter) {
+                for (int q = 0; q < Q; ++q) neq[q] = 0.0;
+                for (int dj = -1; dj <= 1; ++dj)
+                    for (int di = -1; di <= 1; ++di) {
+                        real g[Q], r2, x2, y2, n2[Q];
+                        const double w = (2 - abs(di)) * (2 - abs(dj)) / 16.0;
+                        get_node(ch, ch->f, fi + di, fj + dj, g);
+                        macro_neq(g, &r2, &x2, &y2, n2);
+                        for (int q = 0; q < Q; ++q) neq[q] += w * n2[q];
+                    }
+            }
             equilibrium(rho, ux, uy, feq);
             for (int q = 0; q < Q; ++q) pre[q] = feq[q] + scale * neq[q];
             for (int q = 0; q < Q; ++q) post[q] = pre[q] - (pre[q] - feq[q]) / pa->tau;

@@ -41,7 +41,7 @@ class _Cfg(C.Structure):
         ("chord", C.c_double), ("ein", C.c_double * 4), ("mesh_period", C.c_double * 2),
         ("n_nodes", C.c_int32), ("n_tris", C.c_int32),
         ("xy", C.POINTER(C.c_double)), ("tri", C.POINTER(C.c_int32)), ("kind", C.POINTER(C.c_uint8)),
-        ("channel", C.c_int32),
+        ("channel", C.c_int32), ("f2c_filter", C.c_int32),
     ]
 
 
@@ -199,9 +199,10 @@ class Oracle:
     def __init__(self, *, nx_cells=0, ny_cells=0, patches=(), periodic=False, wall_bc=True,
                  n_sub=0, interp="quadratic", u_inf=0.05, aoa=0.0, rho0=1.0, tau_s=0.6,
                  chord=1.0, inner_ellipse=None, mesh_xy=None, mesh_tri=None, mesh_kind=None,
-                 mesh_period=(0.0, 0.0), channel=False):
+                 mesh_period=(0.0, 0.0), channel=False, f2c_filter=False):
         cfg = _Cfg()
         cfg.channel = int(channel)
+        cfg.f2c_filter = int(f2c_filter)
         cfg.nx_cells, cfg.ny_cells = nx_cells, ny_cells
         cfg.n_refine = len(patches)
         for k, (i0, j0, px, py) in enumerate(patches):
@@ -256,7 +257,7 @@ class Oracle:
                    u_inf=w.u_inf, aoa=w.aoa_rad if aoa_rad is None else aoa_rad, rho0=w.rho0,
                    tau_s=w.tau_s if tau_s is None else tau_s, chord=w.chord,
                    inner_ellipse=w.inner_ellipse, mesh_xy=w.mesh_xy, mesh_tri=w.mesh_tri,
-                   mesh_kind=w.mesh_kind)
+                   mesh_kind=w.mesh_kind, f2c_filter=w.f2c_filter)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -360,7 +361,7 @@ class _CfgCS(C.Structure):
         ("chord", C.c_double), ("ein", C.c_double * 4), ("mesh_period", C.c_double * 2),
         ("n_nodes", C.c_int32), ("n_tris", C.c_int32),
         ("xy", C.c_void_p), ("tri", C.POINTER(C.c_int32)), ("kind", C.POINTER(C.c_uint8)),
-        ("channel", C.c_int32),
+        ("channel", C.c_int32), ("f2c_filter", C.c_int32),
     ]
 
 

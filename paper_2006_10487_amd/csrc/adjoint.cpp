@@ -82,6 +82,7 @@ int check_supported(hlbm_ctx* c, const hlbm_objective* o) {
     if (p.precision != HLBM_FP64) return set_err(c, HLBM_E_ARG, "the adjoint runs in FP64 contexts");
     if (p.periodic) return set_err(c, HLBM_E_ARG, "the adjoint needs the far-field base level");
     if (!p.has_mesh || p.wedge.empty()) return set_err(c, HLBM_E_ARG, "the adjoint needs a mesh with a wall");
+    if (p.f2c_filter) return set_err(c, HLBM_E_ARG, "the adjoint covers the pointwise fine -> coarse transfer only");
     const int64_t per = int64_t(1) << p.L;
     if (o->t_end <= 0 || o->t0 < 0 || o->t1 <= o->t0 || o->t1 > o->t_end || o->ckpt_every <= 0)
         return set_err(c, HLBM_E_ARG, "objective window must satisfy 0 <= t0 < t1 <= t_end, ckpt_every > 0");

@@ -214,7 +214,8 @@ void finish_import(hlbm_ctx* c) {
         launch_side_init(pr, c->kl[l], v.ci0, v.cj0, v.ci1 - v.ci0, v.cj1 - v.cj0, c->lev(l, 1 - c->cur[l]),
                          c->side(l, c->side_t[l]), c->s);
         launch_fine_to_coarse(pr, c->kl[l], c->kl[l + 1], v.ci0, v.cj0, v.ci1 - v.ci0, v.cj1 - v.cj0,
-                              c->lev(l + 1, 1 - c->cur[l + 1]), c->lev(l, c->cur[l]), v.tau, p.lev[l + 1].tau, c->s);
+                              c->lev(l + 1, 1 - c->cur[l + 1]), c->lev(l, c->cur[l]), v.tau, p.lev[l + 1].tau,
+                              p.f2c_filter, c->s);
     }
     if (p.has_mesh && p.n_int > 0)
         launch_struct_to_mesh(pr, c->kl[p.L], c->lev(p.L, 1 - c->cur[p.L]), p.n_int,
@@ -377,7 +378,7 @@ void level_step(hlbm_ctx* c, int l) {
     }
     Timed tm(c, HLBM_K_FINE_TO_COARSE);
     launch_fine_to_coarse(pr, c->kl[l], c->kl[l + 1], v.ci0, v.cj0, v.ci1 - v.ci0, v.cj1 - v.cj0,
-                          c->lev(l + 1, 1 - c->cur[l + 1]), B, v.tau, p.lev[l + 1].tau, c->s);
+                          c->lev(l + 1, 1 - c->cur[l + 1]), B, v.tau, p.lev[l + 1].tau, p.f2c_filter, c->s);
     c->side_t[l] ^= 1;
     c->cur[l] ^= 1;
 }

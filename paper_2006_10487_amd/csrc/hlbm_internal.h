@@ -87,6 +87,7 @@ struct Plan {
     // width, n_le[0..fv_fuse]} with n_le[r] = local nodes within ring r
     // fv_threads: workgroup size of the fused kernel, at least fv_maxw / kFvStage
     // fv_maxs: most f* nodes of a tile (their f* is staged in LDS once per sub-step)
+    int f2c_filter = 0;
     int fv_fuse = 1, fv_tile = 256, fv_threads = 256, fv_maxl = 0, fv_maxw = 0, fv_maxs = 0, n_tiles = 0;
     std::vector<int32_t> ft_meta, ft_node;
     std::vector<int32_t> ft_star;        // per tile: interpolation slot (plan index - n_core) of its f* nodes
@@ -182,7 +183,7 @@ void launch_side_init(int prec, const KLevel& parent, int ci0, int cj0, int nxc,
                       const void* parentA, void* side, hipStream_t s);
 void launch_fine_to_coarse(int prec, const KLevel& parent, const KLevel& child, int ci0, int cj0,
                            int nxc, int nyc, const void* child_prev, void* parent_dst, double tau_c,
-                           double tau_f, hipStream_t s);
+                           double tau_f, int filter, hipStream_t s);
 void launch_mesh_to_struct(int prec, const KLevel& fine, void* fineA, int n, const int32_t* node,
                            const int32_t* don, const void* w, const void* mesh_f, int nn, double factor,
                            hipStream_t s);

@@ -504,19 +504,36 @@ __global__ void k_coarse_to_fine(const KLevel P, const KLevel C, int ci0, int cj
 
 // Fine -> coarse transfer (Sec. 4): parent nodes on the first ring inside the
 // box get the fine (rho, u) and f^neq rescaled by 2 tau_c / tau_f, collided at
-// tau_c.  The fine streamed state is pulled from the child buffer.
+// tau_c.  The fine streamed state is pulled from the child buffer.  With
+// `filter` the f^neq is full-weighted over the 3 x 3 fine nodes around the
+// coincident one (weights (2 - |di|)(2 - |dj|) / 16, exact in any precision),
+// all interior nodes of the child, at least one cell inside its perimeter.
 template <typename T, bool SHIFT>
 __global__ void k_fine_to_coarse(const KLevel P, const KLevel C, int ci0, int cj0, int nxc, int nyc,
-                                 const T* __restrict__ cprev, T* __restrict__ pdst, T scale, T omega_c) {
+                                 const T* __restrict__ cprev, T* __restrict__ pdst, T scale, T omega_c, int filter) {
     const int rx = nxc - 2, ry = nyc - 2;          // ring box (ci0+1 .. ci0+nxc-1) has rx cells
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= 2 * (rx + ry)) return;
     int a, b;
     box_node(k, rx, ry, a, b);
     const int pi = ci0 + 1 + a, pj = cj0 + 1 + b;
+    const int fi = 2 * (pi - ci0), fj = 2 * (pj - cj0);
     T f[9], r, dr, ux, uy, neq[9], feq[9];
-    pull(C, cprev, 2 * (pi - ci0), 2 * (pj - cj0), f);
+    pull(C, cprev, fi, fj, f);
     macro_neq<T, SHIFT>(f, T(P.rho0), r, dr, ux, uy, neq);
+    if (filter) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) neq[q] = T(0);
+        for (int dj = -1; dj <= 1; ++dj)
+            for (int di = -1; di <= 1; ++di) {
+                T g[9], r2, dr2, x2, y2, n2[9];
+                const T w = T((2 - abs(di)) * (2 - abs(dj))) * T(0.0625);
+                pull(C, cprev, fi + di, fj + dj, g);
+                macro_neq<T, SHIFT>(g, T(P.rho0), r2, dr2, x2, y2, n2);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) neq[q] += w * n2[q];
+            }
+    }
     equilibrium<T, SHIFT>(r, dr, ux, uy, feq);
     const size_t base = size_t(pj) * size_t(P.rs) + pi;
 #pragma unroll
@@ -1201,11 +1218,11 @@ void launch_coarse_to_fine(int prec, const KLevel& P, const KLevel& C, int ci0, 
 }
 
 void launch_fine_to_coarse(int prec, const KLevel& P, const KLevel& C, int ci0, int cj0, int nxc, int nyc,
-                           const void* cprev, void* pdst, double tau_c, double tau_f, hipStream_t s) {
+                           const void* cprev, void* pdst, double tau_c, double tau_f, int filter, hipStream_t s) {
     const size_t n = 2 * size_t(nxc - 2 + nyc - 2);
     const double scale = 2.0 * tau_c / tau_f;
     HLBM_DISPATCH(prec, (k_fine_to_coarse<T, S><<<blocks(n, kSmallBlock), kSmallBlock, 0, s>>>(P, C, ci0, cj0, nxc, nyc, (const T*)cprev,
-                                                                          (T*)pdst, T(scale), T(1.0 / tau_c))));
+                                                                          (T*)pdst, T(scale), T(1.0 / tau_c), filter)));
 }
 
 void launch_mesh_to_struct(int prec, const KLevel& F, void* A, int n, const int32_t* node, const int32_t* don,

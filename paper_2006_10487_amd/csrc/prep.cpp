@@ -647,6 +647,8 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
     p.rho0 = g->rho0;
     p.chord = p.has_mesh ? m->chord : 1.0;
     p.check_every = std::max(0, g->check_every);
+    if (g->f2c_filter != 0 && g->f2c_filter != 1) return fail(err, HLBM_E_ARG, "f2c_filter must be 0 or 1");
+    p.f2c_filter = g->f2c_filter;
     p.hist_len = g->history_len > 0 ? g->history_len : 65536;
     // relaxation time of the finest level (nu = c_s^2 (tau - 1/2), Sec. 2)
     if (tau > 0.5) {

@@ -48,7 +48,7 @@ class Grid(C.Structure):
         ("u_inf", C.c_double), ("aoa_rad", C.c_double), ("rho0", C.c_double),
         ("precision", C.c_int32), ("interp", C.c_int32), ("n_sub", C.c_int32), ("bc", C.c_int32),
         ("wall_bc", C.c_int32), ("check_every", C.c_int32), ("history_len", C.c_int32),
-        ("fv_fuse", C.c_int32),
+        ("fv_fuse", C.c_int32), ("f2c_filter", C.c_int32),
     ]
 
 
@@ -128,7 +128,7 @@ def _np_ptr(a):
 def make_structs(nx_cells, ny_cells, patches=(), *, u_inf=0.05, aoa_rad=0.0, rho0=1.0,
                  precision=FP64, interp=INTERP_QUADRATIC, n_sub=0, periodic=False, wall_bc=True,
                  check_every=0, history_len=0, fv_fuse=0, mesh_xy=None, mesh_tri=None, mesh_kind=None,
-                 chord=1.0, inner_ellipse=None, dxy_dshape=None):
+                 chord=1.0, inner_ellipse=None, dxy_dshape=None, f2c_filter=False):
     """ctypes Grid and Mesh (plus the arrays they point into, kept alive).
 
     dxy_dshape: optional [n_shape, n_nodes, 2] derivatives of the node
@@ -143,6 +143,7 @@ def make_structs(nx_cells, ny_cells, patches=(), *, u_inf=0.05, aoa_rad=0.0, rho
     g.bc = BC_PERIODIC if periodic else BC_FARFIELD
     g.wall_bc, g.check_every, g.history_len = int(wall_bc), check_every, history_len
     g.fv_fuse = int(fv_fuse)
+    g.f2c_filter = int(f2c_filter)
     m = Mesh()
     keep = []
     if mesh_xy is not None:
@@ -169,7 +170,7 @@ def make_structs(nx_cells, ny_cells, patches=(), *, u_inf=0.05, aoa_rad=0.0, rho
 def structs_from_workload(w, **over):
     kw = dict(u_inf=w.u_inf, aoa_rad=w.aoa_rad, rho0=w.rho0, periodic=w.periodic, n_sub=w.n_sub,
               mesh_xy=w.mesh_xy, mesh_tri=w.mesh_tri, mesh_kind=w.mesh_kind, chord=w.chord,
-              inner_ellipse=w.inner_ellipse)
+              inner_ellipse=w.inner_ellipse, f2c_filter=w.f2c_filter)
     kw.update(over)
     return make_structs(w.nx_cells, w.ny_cells, w.patches, **kw)
 

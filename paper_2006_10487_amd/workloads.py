@@ -372,6 +372,7 @@ class Workload:
     n_sub: int = 0
     omesh: Optional[OMesh] = None
     notes: str = ""
+    f2c_filter: bool = False   # fine -> coarse f^neq full-weighted over 3 x 3 fine nodes
 
     @property
     def n_refine(self) -> int:
@@ -489,11 +490,15 @@ def naca_re1000_c128(aoa_deg: float = 0.0, ns: int = 512, band: float = RE1000_C
                           h1=RE1000_C128_H1, steps=40000)
 
 
-def naca_re1e4_c256() -> Workload:
-    """Re = 1e4, c = 256: 2048x1024 base cells (spacing 4), two nested boxes, 1024x128 mesh."""
-    return _naca_workload("naca0012_re1e4_c256_2048x1024_r2", 2048, 1024,
-                          [(768, 384), (768, 384)], 256.0, 1.0e4, 0.04, 0.0, 1024, 128,
-                          188.0, h1=0.512, steps=100000)
+def naca_re1e4_c256(f2c_filter: bool = False) -> Workload:
+    """Re = 1e4, c = 256: 2048x1024 base cells (spacing 4), two nested boxes, 1024x128 mesh.
+    Its coarse levels run at tau = 0.5008 and 0.5015; with the pointwise fine -> coarse
+    transfer the run blows up at the upstream edge of the finest box after ~1,500 steps,
+    with the filtered one (f2c_filter) it runs on."""
+    w = _naca_workload("naca0012_re1e4_c256_2048x1024_r2" + ("_f2c3x3" if f2c_filter else ""), 2048, 1024,
+                       [(768, 384), (768, 384)], 256.0, 1.0e4, 0.04, 0.0, 1024, 128,
+                       188.0, h1=0.512, steps=100000)
+    return dataclasses.replace(w, f2c_filter=bool(f2c_filter))
 
 
 def naca_re1000_c128_bumps(bumps=None) -> Workload:
@@ -506,9 +511,12 @@ def naca_re1000_c128_bumps(bumps=None) -> Workload:
 
 
 def naca_re5000_c512() -> Workload:
-    """Throughput case: 8192x4096 base cells (spacing 2), 2048x1024 box, 2048x128 mesh."""
+    """Throughput case: 8192x4096 base cells (spacing 2), 2048x1024 box, 2048x128 mesh in
+    a band 0.1c = 51.2 lu thick with a 0.25 lu first layer (outer cells ~0.6 lu).  A band
+    reaching 508 lu out (outer cells 13 lu across) carried a spurious lift oscillation
+    with a period of ~100 steps."""
     return _naca_workload("naca0012_re5000_c512_8192x4096_r1", 8192, 4096, [(2048, 1024)],
-                          512.0, 5000.0, 0.05, 8.0, 2048, 128, 508.0, h1=0.5, steps=10000)
+                          512.0, 5000.0, 0.05, 8.0, 2048, 128, 51.2, h1=0.25, steps=10000)
 
 
 CONV_CHORDS = (48, 64, 96, 128, 144)
@@ -526,16 +534,20 @@ CONV_N_SUB = 70     # ceil(1 / tau_u) of the smallest chord: one FV time step fo
 FAMILY_BOXES = 1
 
 
-def naca_re500_four_levels(chord: int = 48) -> Workload:
+def naca_re500_four_levels(chord: int = 48, f2c_filter: bool = False) -> Workload:
     """Four structured levels (base spacing 8 over 30c x 15c, three nested boxes
     of 2.5c x 1.25c cells each) around a 4c x c/2 O-mesh, Re = 500: the paper's
-    level layout, for short parity runs (its coarse levels are too close to
-    tau = 1/2 for long runs at this chord)."""
+    level layout.  Its coarse levels run close to tau = 1/2 (0.5018 and 0.5036
+    at c = 48): long runs need the filtered fine -> coarse transfer
+    (f2c_filter); with the pointwise one it serves short parity runs."""
     c = int(chord)
+    if c % 8:
+        raise ValueError("chord must be a multiple of 8")
     box = (5 * c // 2, 5 * c // 4)
-    w = _naca_workload(f"naca0012_re500_c{c}_four_levels", 15 * c // 4, 15 * c // 8, [box, box, box], float(c),
-                       500.0, 0.05, 0.0, 4 * c, c // 2, c / 4.0, h1=0.25, steps=1000)
-    return dataclasses.replace(w, n_sub=CONV_N_SUB)
+    w = _naca_workload(f"naca0012_re500_c{c}_four_levels" + ("_f2c3x3" if f2c_filter else ""), 15 * c // 4,
+                       15 * c // 8, [box, box, box], float(c), 500.0, 0.05, 0.0, 4 * c, c // 2, c / 4.0, h1=0.25,
+                       steps=1000)
+    return dataclasses.replace(w, n_sub=CONV_N_SUB, f2c_filter=bool(f2c_filter))
 
 
 def naca_re500_conv(chord: int = 48) -> Workload:

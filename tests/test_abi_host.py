@@ -31,8 +31,8 @@ def test_header_symbols_exported(lib):
 
 
 def test_struct_sizes_match_header(lib):
-    # hlbm_grid: 15 int32 (60 B, padded to 64), 3 doubles, 8 int32
-    assert C.sizeof(hlbm.Grid) == 64 + 3 * 8 + 8 * 4
+    # hlbm_grid: 15 int32 (60 B, padded to 64), 3 doubles, 9 int32 (36 B, padded to 40)
+    assert C.sizeof(hlbm.Grid) == 64 + 3 * 8 + 40
     # hlbm_mesh: 2 int32, 3 pointers, 5 doubles, int32 n_shape (padded to 8), 1 pointer
     assert C.sizeof(hlbm.Mesh) == 4 + 4 + 3 * 8 + 8 + 32 + 8 + 8
 

@@ -7,6 +7,8 @@ independence of the checkpoint interval, the shape gradient (d J / d mesh
 coordinates) along Hicks-Henne and random directions, and the
 torch.autograd.Function wrapper.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -286,6 +288,15 @@ def test_stored_and_recomputed_substeps_agree(refined):
         out.append((sim.adjoint(), sim.grad_xy.copy()))
     assert np.array_equal(out[0][0], out[1][0])
     assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_objective_rejects_filtered_restriction():
+    """The discrete adjoint covers the pointwise fine -> coarse transfer only."""
+    w = dataclasses.replace(W.naca_re100_c40_refined(3.0), f2c_filter=True)
+    sim = hlbm.HLBM.from_workload(w, n_sub=N_SUB)
+    with pytest.raises(hlbm.HLBMError) as ei:
+        sim.run_objective(t_end=160, t0=80, t1=160, ckpt_every=40)
+    assert ei.value.code == -1 and "fine -> coarse" in str(ei.value)
 
 
 def test_refined_objective_rejects_odd_steps():

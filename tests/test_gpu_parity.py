@@ -6,6 +6,8 @@ FP64 bar: infinity-norm relative difference of the full state <= 1e-11
 relative of FP64 (absolute on C_L when it vanishes by symmetry).
 """
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -81,12 +83,14 @@ def test_small_fp64_incidence_linear_interp(aoa_deg):
     assert max(e["level0"], e["mesh"]) < TOL and max(e["cd"], e["cl"]) < 1e-10
 
 
-def _tg_pair(L, tau, u0, patches=(), mesh=None, ein=None, fv_fuse=0):
+def _tg_pair(L, tau, u0, patches=(), mesh=None, ein=None, fv_fuse=0, f2c_filter=False):
     kw = {}
     if mesh is not None:
         kw = dict(mesh_xy=mesh[0], mesh_tri=mesh[1], mesh_kind=mesh[2], inner_ellipse=ein)
-    ref = O.Oracle(nx_cells=L, ny_cells=L, periodic=True, tau_s=tau, u_inf=u0, patches=patches, **kw)
-    g, m, keep = hlbm.make_structs(L, L, patches, periodic=True, u_inf=u0, fv_fuse=fv_fuse, **kw)
+    ref = O.Oracle(nx_cells=L, ny_cells=L, periodic=True, tau_s=tau, u_inf=u0, patches=patches,
+                   f2c_filter=f2c_filter, **kw)
+    g, m, keep = hlbm.make_structs(L, L, patches, periodic=True, u_inf=u0, fv_fuse=fv_fuse,
+                                   f2c_filter=f2c_filter, **kw)
     sim = hlbm.HLBM(g, m, tau=tau, keep=keep)
     nlev = ref.n_levels
     length = L * 2 ** (nlev - 1)
@@ -110,9 +114,11 @@ def _tg_pair(L, tau, u0, patches=(), mesh=None, ein=None, fv_fuse=0):
     return sim, ref
 
 
-def test_periodic_refined_taylor_green():
-    """Coarse <-> fine transfer and state import on a periodic grid with two nested boxes."""
-    sim, ref = _tg_pair(32, 0.7, 0.02, patches=[(6, 6, 40, 40), (6, 6, 24, 24)])
+@pytest.mark.parametrize("f2c_filter", [False, True])
+def test_periodic_refined_taylor_green(f2c_filter):
+    """Coarse <-> fine transfer and state import on a periodic grid with two nested boxes
+    (fine -> coarse pointwise, and with the f^neq full-weighted over 3 x 3 fine nodes)."""
+    sim, ref = _tg_pair(32, 0.7, 0.02, patches=[(6, 6, 40, 40), (6, 6, 24, 24)], f2c_filter=f2c_filter)
     for n in (4, 60):
         sim.step(n)
         ref.step(n)
@@ -168,10 +174,11 @@ def test_two_box_naca_fp64_short():
     assert max(e["cd"], e["cl"]) < 1e-10
 
 
-def test_four_level_naca_fp64_short():
+@pytest.mark.parametrize("f2c_filter", [False, True])
+def test_four_level_naca_fp64_short(f2c_filter):
     """Re = 500, c = 48: base grid + three nested boxes (four levels), 192 x 24 mesh,
     70 sub-steps, one base step = 8 finest steps and 16 more."""
-    w = W.naca_re500_four_levels(48)
+    w = dataclasses.replace(W.naca_re500_four_levels(48), f2c_filter=f2c_filter)
     sim = hlbm.HLBM.from_workload(w)
     ref = O.Oracle.from_workload(w)
     assert sim.info.n_levels == ref.n_levels == 4 and sim.info.n_sub == ref.n_sub == 70

@@ -4,11 +4,12 @@ histories of the first 2000 finest steps against the FP64 CPU oracle's, stored
 in tests/golden/ by tests/golden/make_re1e4_history.py (which calls only the
 oracle and the input generator).
 
-The oracle run itself turns non-finite at finest step 1482: with these
-settings the outer cells of the O-mesh are ~3 lu across at a viscosity of
-1e-3 lu^2, a cell Peclet number near 125, where the central finite-volume
-streaming of eq. (3) has no stability margin.  The comparison therefore covers
-the steps before the first non-finite value of either run, minus 100 steps in
+The oracle run itself turns non-finite at finest step 1482.  The velocity
+first grows at the upstream edge of the finest box (speed 5 U there at step
+1300, while the mesh stays near U): the middle level runs at tau = 0.5015 and
+the coarse level at 0.5008, where the two non-equilibrium rescalings of the
+refinement interface feed each other.  The comparison therefore covers the
+steps before the first non-finite value of either run, minus 100 steps in
 which the blow-up grows, and FP64 must blow up at the same step as the oracle.
 FP32-shifted storage blows up about 80 steps earlier (step 1406).
 

@@ -72,13 +72,13 @@ def test_bgk_conserves_and_fixed_point(seed):
 # Structured LBM: closed forms
 # ---------------------------------------------------------------------------
 
-def _tg_run(L, tau, u0, T, patches=(), mesh=None, ein=None, interp="quadratic"):
+def _tg_run(L, tau, u0, T, patches=(), mesh=None, ein=None, interp="quadratic", f2c_filter=False):
     """Taylor-Green vortex on a periodic L x L base grid (+ boxes, + mesh)."""
     kw = {}
     if mesh is not None:
         kw = dict(mesh_xy=mesh[0], mesh_tri=mesh[1], mesh_kind=mesh[2], inner_ellipse=ein)
     o = O.Oracle(nx_cells=L, ny_cells=L, periodic=True, tau_s=tau, u_inf=u0, patches=patches,
-                 interp=interp, **kw)
+                 interp=interp, f2c_filter=f2c_filter, **kw)
     nlev = o.n_levels
     length = L * 2 ** (nlev - 1)
     nu = (tau - 0.5) / 3.0
@@ -182,16 +182,72 @@ def test_refinement_uniform_flow_preserved():
         assert np.abs(o.get_level(l) - f0[l]).max() < 1e-13
 
 
-def test_refinement_taylor_green():
-    """A centred fine box keeps the Taylor-Green decay; wrong rescalings do not."""
+@pytest.mark.parametrize("f2c_filter", [False, True])
+def test_refinement_taylor_green(f2c_filter):
+    """A centred fine box keeps the Taylor-Green decay; wrong rescalings do not.
+    Also with the fine -> coarse f^neq full-weighted over 3 x 3 fine nodes."""
     T = _half_life(64, 0.8)
     T -= T % 2
-    good, _ = _tg_run(32, 0.8, 0.01, T, patches=[(8, 8, 32, 32)])
+    good, _ = _tg_run(32, 0.8, 0.01, T, patches=[(8, 8, 32, 32)], f2c_filter=f2c_filter)
     assert max(good) < 0.0095
     for which, val in [(2, 0.0), (2, 2.0), (3, 0.5)]:
         with O.planted(which, val):
-            bad, _ = _tg_run(32, 0.8, 0.01, T, patches=[(8, 8, 32, 32)])
+            bad, _ = _tg_run(32, 0.8, 0.01, T, patches=[(8, 8, 32, 32)], f2c_filter=f2c_filter)
         assert max(bad) > 0.04
+
+
+def test_refinement_filtered_restriction_differs_at_second_order():
+    """The full-weighted restriction reproduces linear f^neq fields, so on the
+    smooth Taylor-Green field it moves the run by O(h^2) only: the two
+    restrictions agree far better than either agrees with the closed form's
+    error scale, and halving h shrinks their gap about fourfold."""
+    gaps = []
+    for L in (32, 64):
+        T = _half_life(2 * L, 0.8)
+        T -= T % 2
+        box = [(L // 4, L // 4, L, L)]
+        _, a = _tg_run(L, 0.8, 0.01, T, patches=box)
+        _, b = _tg_run(L, 0.8, 0.01, T, patches=box, f2c_filter=True)
+        fa, fb = a.get_level(0), b.get_level(0)
+        act = a.level_class(0) == 0
+        _, ua, va = macro(fa)
+        _, ub, vb = macro(fb)
+        gaps.append(math.sqrt((((ua - ub) ** 2 + (va - vb) ** 2)[act]).sum() / ((ua ** 2 + va ** 2)[act]).sum()))
+    assert gaps[0] < 2e-3
+    assert 2.5 < gaps[0] / gaps[1] < 6.0
+
+
+def _interface_noise(tau_c, f2c_filter, steps=6000):
+    """Largest deviation from the free stream after `steps` finest steps of a
+    far-field grid with one refinement box (no body), started from the free
+    stream with seeded noise of 1e-4 on rho and u."""
+    u = 0.05
+    o = O.Oracle(nx_cells=180, ny_cells=90, patches=[(33, 30, 120, 60)], tau_s=0.5 + 2 * (tau_c - 0.5),
+                 u_inf=u, wall_bc=False, f2c_filter=f2c_filter)
+    rng = np.random.default_rng(3)
+    for l in range(o.n_levels):
+        ny, nx = o.level_shape[l]
+        rho = 1.0 + 1e-4 * rng.standard_normal((ny, nx))
+        ux = u + 1e-4 * rng.standard_normal((ny, nx))
+        uy = 1e-4 * rng.standard_normal((ny, nx))
+        o.set_level(l, feq_field(eq, rho, ux, uy))
+    o.step(steps)
+    dev = 0.0
+    for l in range(o.n_levels):
+        _, ux, uy = macro(o.get_level(l))
+        act = o.level_class(l) == 0
+        d = np.hypot(ux - u, uy)[act]
+        dev = max(dev, float(d.max()) if np.isfinite(d).all() else math.inf)
+    return dev
+
+
+def test_refinement_interface_noise_growth_and_filter():
+    """With the coarse tau close to 1/2 (0.5035 here) the two f^neq rescalings
+    of the interface feed each other and seeded noise grows by two orders of
+    magnitude; with the fine -> coarse f^neq full-weighted it stays at its
+    initial size."""
+    assert _interface_noise(0.5035, False) > 1e-2
+    assert _interface_noise(0.5035, True) < 2e-4
 
 
 def test_refinement_nested_two_levels_uniform():
