@@ -1,15 +1,19 @@
-"""Self-convergence study of the mean drag (Sec. 5) on four structured levels.
+"""Self-convergence study of the mean drag (Sec. 5).
 
-Re = 500, alpha = 0, chords 48, 64, 96, 128, 144 (``workloads.naca_re500_conv``:
-geometrically similar grids and boxes, the same wall element size and FV time
-step for every chord), FP64.  Each run starts from the uniform state and lasts
+Re = 500, alpha = 0, chords 48, 64, 96, 128, 144, FP64.  Two layouts:
+``--levels 2`` (``workloads.naca_re500_conv``: a base grid of spacing 2 and
+one box) and ``--levels 4`` (``workloads.naca_re500_four_levels``: the paper's
+four structured levels, base spacing 8 and three nested boxes, with the
+filtered fine -> coarse transfer that keeps its coarse levels stable at tau
+close to 1/2).  Both have geometrically similar grids and boxes, the same wall
+element size and FV time step for every chord.  Each run starts from the uniform state and lasts
 ``passes`` chord-transit times (c / U finest steps each); C_D is averaged over
 the last tenth.  The paper measures the drag error against XFOIL; without an
 external reference, the limit C_D(inf) and the order p come from a
 least-squares fit of C_D(c) = C_D(inf) + K c^-p to the five chords
 (Richardson extrapolation), and the errors are stated against that limit.
 
-    python -m paper_2006_10487_amd.convergence --passes 40
+    python -m paper_2006_10487_amd.convergence --passes 40 [--levels 4]
 
 prints one JSON object per chord and one for the fit.
 """
@@ -25,8 +29,8 @@ import numpy as np
 from . import hlbm, workloads
 
 
-def run(chord: int, passes: float, precision: int):
-    w = workloads.naca_re500_conv(chord)
+def run(chord: int, passes: float, precision: int, levels: int = 2):
+    w = workloads.naca_re500_conv(chord) if levels == 2 else workloads.naca_re500_four_levels(chord, f2c_filter=True)
     per = 2 ** w.n_refine
     steps = int(round(passes * chord / w.u_inf / per)) * per
     sim = hlbm.HLBM.from_workload(w, precision=precision, history_len=steps + 8, check_every=4000)
@@ -74,12 +78,13 @@ def main(argv=None):
     ap.add_argument("--chords", default=",".join(str(c) for c in workloads.CONV_CHORDS))
     ap.add_argument("--passes", type=float, default=40.0, help="chord-transit times per run")
     ap.add_argument("--fp32", action="store_true", help="FP32-shifted populations instead of FP64")
+    ap.add_argument("--levels", type=int, default=2, choices=(2, 4), help="structured levels of the layout")
     a = ap.parse_args(argv)
     prec = hlbm.FP32_SHIFTED if a.fp32 else hlbm.FP64
     chords = [int(x) for x in a.chords.split(",")]
     cds = []
     for c in chords:
-        w, steps, dt, cd, drift, clmax = run(c, a.passes, prec)
+        w, steps, dt, cd, drift, clmax = run(c, a.passes, prec, a.levels)
         cds.append(cd)
         print(json.dumps({"chord": c, "workload": w.name, "finest_steps": steps, "n_sub": w.n_sub,
                           "tau_s": w.tau_s, "mesh_nodes": int(w.mesh_xy.shape[0]), "cd": cd,

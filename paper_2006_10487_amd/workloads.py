@@ -587,5 +587,6 @@ PRESETS = {
     "naca_re1000_c128_bumps": naca_re1000_c128_bumps,
     "naca_re5000_c512": naca_re5000_c512,
     "naca_re500_conv": naca_re500_conv,
+    "naca_re500_four_levels": naca_re500_four_levels,
     "naca_re_sweep": naca_re_sweep,
 }

@@ -111,6 +111,18 @@ def test_validate_bad_enums(lib):
     assert hlbm.validate(g, m, 0.0, w.tau_s) == -1
 
 
+def test_f2c_filter_option(lib):
+    """The four-level layout with the filtered fine -> coarse transfer validates for
+    every chord of the convergence family; values other than 0 and 1 are rejected."""
+    for c in W.CONV_CHORDS:
+        w = W.naca_re500_four_levels(c, f2c_filter=True)
+        assert w.n_refine == 3 and w.f2c_filter
+        g, m, keep = hlbm.structs_from_workload(w)
+        assert g.f2c_filter == 1 and hlbm.validate(g, m, 0.0, w.tau_s) == 0, (c, hlbm.last_error())
+    g.f2c_filter = 2
+    assert hlbm.validate(g, m, 0.0, w.tau_s) == -1 and "f2c_filter" in hlbm.last_error()
+
+
 def test_workloads_validate(lib):
     """Every preset passes host validation (stencils, boxes, inner ellipse)."""
     for name in ("naca_re100_c40", "naca_re1000_c128", "naca_re1e4_c256", "naca_re1000_c128_bumps"):
