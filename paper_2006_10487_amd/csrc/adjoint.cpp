@@ -413,8 +413,7 @@ void recorder(hlbm_ctx* c, int ev, int l) {
     } else if (ev == 1) {
         a.rec_rc |= d2d(c, a.ws + a.seg_side_at(l, k, 1), c->side(l, 1 - c->side_t[l]), a.side_bytes[l]);
         ++k;
-    } else {
-        a.rec_rc |= d2d(c, a.ws + a.seg_lev_at(l, k), c->lev(l, c->cur[l]), a.lev_bytes[l]);
+    } else if (ev == 2) {
         a.rec_rc |= d2d(c, a.ws + a.seg_mesh_at(k), c->mesh(c->mesh_cur), a.mesh_bytes);
         a.rec_rc |= d2d(c, a.ws + a.seg_prep_at(k), c->prep(c->prep_t), a.prep_bytes);
         if (a.obj.store_substeps) {
@@ -423,6 +422,10 @@ void recorder(hlbm_ctx* c, int ev, int l) {
             c->wmom_sink = a.at<double>(a.seg_wmom_at(k, 0));
             c->wmom_stride = a256(a.wmom_bytes) / 8;
         }
+    } else {
+        // finest input after eq. (4), as the collide-stream reads it: the reverse
+        // step uses it as is
+        a.rec_rc |= d2d(c, a.ws + a.seg_lev_at(l, k), c->lev(l, c->cur[l]), a.lev_bytes[l]);
         ++k;
     }
 }
@@ -450,22 +453,13 @@ void reverse_finest(hlbm_ctx* c, AdjState& a, int64_t t, int k, double& alpha_ho
     const double* Mt = a.at<double>(a.seg_mesh_at(k));
     const double* prep0 = a.at<double>(a.seg_prep_at(k));
     const double* prep1 = a.at<double>(a.seg_prep_at(k + 1));
-    double* Aw = a.at<double>(a.off.awork);
+    const double* Aw = a.at<double>(a.seg_lev_at(L, k));   // the input the collide-stream read
     double* Bbar = a.at<double>(a.off.abar[L][a.ab[L]]);
     double* Anew = a.at<double>(a.off.abar[L][1 - a.ab[L]]);
     double* prebar = a.at<double>(a.off.prebar[L]);
     double* Pcur = a.at<double>(a.off.pbar[a.pb]);       // adjoint of prep(t+1)
     double* Pnext = a.at<double>(a.off.pbar[1 - a.pb]);  // adjoint of prep(t)
     int slot = 0;
-    // A as read by the collide-stream kernel: the recorded input with eq. (4) applied
-    (void)d2d(c, Aw, a.ws + a.seg_lev_at(L, k), a.lev_bytes[L]);
-    if (!p.sint_node.empty()) {
-        const double ts = p.tau_s;
-        launch_mesh_to_struct(HLBM_FP64, c->kl[L], Aw, int(p.sint_node.size()),
-                              reinterpret_cast<const int32_t*>(c->ws + p.off.sint_node),
-                              reinterpret_cast<const int32_t*>(c->ws + p.off.sint_don), c->ws + p.off.sint_w, Mt,
-                              p.nn, 2.0 * (ts - 1.0) / (2.0 * ts - 1.0), s);
-    }
     // sub-step states M^0..M^n of this step: recorded by the segment recompute, or recomputed
     const size_t ms = a256(a.mesh_bytes);
     const bool stored = a.obj.store_substeps != 0;

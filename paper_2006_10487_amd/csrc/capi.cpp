@@ -111,6 +111,7 @@ void setup_views(hlbm_ctx* c) {
     m.n_wall = p.n_wall;
     m.n_core = p.n_core;
     m.ell_width = p.ell_width;
+    m.ft_width = p.ft_width;
     m.edges = c->ws + p.off.edges;
     m.dt = p.dt_u;
     m.dt_over_tau = p.dt_u / p.tau_u;
@@ -275,6 +276,7 @@ void finest_step(hlbm_ctx* c) {
                               reinterpret_cast<const int32_t*>(c->ws + p.off.sint_don), c->ws + p.off.sint_w,
                               c->mesh(c->mesh_cur), p.nn, 2.0 * (ts - 1.0) / (2.0 * ts - 1.0), c->s);
     }
+    if (c->rec) c->rec(c, 3, L);   // the finest input as the collide-stream reads it
     {
         Timed tm(c, HLBM_K_COLLIDE_L0 + L);
         launch_stream_collide(pr, c->kl[L], A, B, c->s);

@@ -38,9 +38,9 @@ constexpr int kAdjRec = 10;   // doubles per mesh node of the adjoint fields (9 
 // LDS bytes of one fused-FV workgroup: node records and plan indices of the
 // tile with its rings, then f* of the tile's interpolation nodes at each of the
 // launch's sub-steps.
+__host__ __device__ inline size_t fv_stg_offset(int maxl, size_t elem) { return (size_t(maxl) * (kRec * elem + 4) + 15) / 16 * 16; }
 inline size_t fv_lds_bytes(int maxl, int maxs, int fuse, size_t elem) {
-    const size_t recs = (size_t(maxl) * (kRec * elem + 4) + 15) / 16 * 16;
-    return recs + size_t(fuse) * size_t(maxs) * kStarRec * elem;
+    return fv_stg_offset(maxl, elem) + size_t(fuse) * size_t(maxs) * kStarRec * elem;
 }
 
 struct LevelPlan {
@@ -78,6 +78,7 @@ struct Plan {
     std::vector<int32_t> perm;           // perm[new] = caller index
     std::vector<int32_t> rowptr, col;    // CSR, self entry first
     int ell_width = 8;                   // slots per node of the device neighbour table
+    int ft_width = 8;                    // slots per node of the fused-FV tile tables (7 when no row is longer)
     std::vector<double> gx, gy, cc;      // G_Pk (x, y) and C_Pk
     std::vector<int32_t> wedge;          // wall edges (P, Q) in plan order, fluid on the left
     std::vector<double> wnorm;           // outward normal times length of each wall edge
@@ -151,6 +152,7 @@ struct KLevel {
 struct KMesh {
     int nn, n_wall, n_core;
     int ell_width;                   // neighbour slots per node (8 or 16)
+    int ft_width;                    // slots per node of the tile tables (7, 8 or 16)
     const void* edges;               // ELL (col, gx, gy, c) records, slot-major
     double dt, dt_over_tau;          // Delta t_u, Delta t_u / tau_u
     double star_neq;                 // 1 - 1 / (2 tau_s), eq. (5)-(6)
@@ -291,7 +293,8 @@ struct hlbm_ctx {
     AdjState* adj = nullptr;
     // observer of the step recursion (the adjoint's segment recompute), or null:
     // event 0 = entry of a level-l step (l < L), 1 = the parent's side values of
-    // that step are recorded, 2 = entry of a finest step (before eq. (4))
+    // that step are recorded, 2 = entry of a finest step (before eq. (4)), 3 = the
+    // finest input after eq. (4), before its collide-stream
     void (*rec)(hlbm_ctx*, int event, int level) = nullptr;
     // with sub_sink set, the FV sub-steps of the next finest step write their
     // states to sub_sink + m * sub_stride (m = 0..n-1, the state after sub-step

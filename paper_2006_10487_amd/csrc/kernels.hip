@@ -949,7 +949,7 @@ __device__ __forceinline__ int fv_tile_node(const KMesh& M, const T* __restrict_
 // intermediate states that the discrete adjoint reads).
 // Waves per SIMD the fused kernel is compiled for: three in FP32 with 8 slots
 // (at most 168 VGPRs), so that three workgroups of 256 threads share a CU.
-template <typename T, int W> struct FvFusedWaves { static constexpr int value = sizeof(T) == 4 && W == 8 ? 3 : 1; };
+template <typename T, int W> struct FvFusedWaves { static constexpr int value = sizeof(T) == 4 && W <= 8 ? 3 : 1; };
 
 template <typename T, bool SHIFT, int W>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWaves<T, W>::value))) void k_fv_fused(const KMesh M, const T* __restrict__ fin, T* __restrict__ fout,
@@ -959,7 +959,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
     T* const buf = reinterpret_cast<T*>(smem);
     int32_t* const gid = reinterpret_cast<int32_t*>(buf + size_t(M.maxl) * kRec);
     // f* of the tile's interpolation nodes, sub-step j of the launch at stg + j * stj
-    T* const stg = reinterpret_cast<T*>(smem + (size_t(M.maxl) * (kRec * sizeof(T) + 4) + 15) / 16 * 16);
+    T* const stg = reinterpret_cast<T*>(smem + fv_stg_offset(M.maxl, sizeof(T)));
     const size_t stj = size_t(M.maxs) * kStarRec;
     const int t = die_block(blockIdx.x, gridDim.x);
     const int32_t* meta = M.ft_meta + size_t(t) * kTileMeta;
@@ -1260,7 +1260,11 @@ void launch_fv_fused(int prec, const KMesh& M, const void* fin, void* fout, cons
     if (size_t(M.maxw) > size_t(kFvStage) * threads || threads > 256) return;   // rejected by the plan
     FvTheta th;   // theta = m / n of sub-steps m0 .. m0 + k - 1, as the one-sub-step launches take it
     for (int j = 0; j < kMaxFuse; ++j) th.v[j] = double(m0 + j) / double(M.n_sub);
-    if (M.ell_width <= 8) {
+    if (M.ft_width == 7) {
+        HLBM_DISPATCH(prec, (k_fv_fused<T, S, 7><<<M.n_tiles, threads, lds, s>>>(M, (const T*)fin, (T*)fout, (const T*)prep0,
+                                                                                  (const T*)prep1, th, k, (T*)mid,
+                                                                 mid_stride_bytes / sizeof(T))));
+    } else if (M.ft_width == 8) {
         HLBM_DISPATCH(prec, (k_fv_fused<T, S, 8><<<M.n_tiles, threads, lds, s>>>(M, (const T*)fin, (T*)fout, (const T*)prep0,
                                                                                   (const T*)prep1, th, k, (T*)mid,
                                                                  mid_stride_bytes / sizeof(T))));

@@ -498,7 +498,7 @@ constexpr int kFvThreadsF64 = 128, kFvTileMinF64 = 64, kFvTileMaxF64 = 128;
 // fuse, each ascending.  The edge table of a tile covers the nodes that are
 // ever updated (tile .. ring fuse-1), slot-major, with local columns.
 void build_fv_tiles(Plan& p, int tile, int fuse) {
-    const int nn = p.nn, W = p.ell_width;
+    const int nn = p.nn, W = p.ft_width;
     std::vector<int> owner(nn, -1);
     std::vector<std::vector<int>> tiles;
     int next = 0;
@@ -825,6 +825,8 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
         for (int P = 0; P < nn; ++P) maxrow = std::max(maxrow, p.rowptr[P + 1] - p.rowptr[P]);
         if (maxrow > 16) return fail(err, HLBM_E_GEOMETRY, "a mesh node has %d neighbours (at most 15 supported)", maxrow - 1);
         p.ell_width = maxrow <= 8 ? 8 : 16;
+        // tile tables drop the eighth slot when no node has seven neighbours
+        p.ft_width = maxrow <= 7 ? 7 : p.ell_width;
         // wall edges: boundary edges with both ends on the wall
         for (const auto& be : bnd)
             if (m->kind[be[0]] == 1 && m->kind[be[1]] == 1) {

@@ -44,15 +44,15 @@ def _gpu():
     hlbm.lib()
 
 
-def golden():
-    data = np.loadtxt(GOLDEN, comments="#")
+def golden(path=GOLDEN):
+    data = np.loadtxt(path, comments="#")
     assert data.shape == (STEPS, 3) and np.array_equal(data[:, 0], np.arange(STEPS))
-    header = open(GOLDEN).readline()
+    header = open(path).readline()
     return header, data[:, 1], data[:, 2]
 
 
-def run(precision, steps):
-    w = W.naca_re1e4_c256()
+def run(precision, steps, f2c_filter=False):
+    w = W.naca_re1e4_c256(f2c_filter=f2c_filter)
     sim = hlbm.HLBM.from_workload(w, precision=precision)
     assert sim.info.n_sub == 326
     sim.step_logged(steps, "re1e4", chunk=250)
