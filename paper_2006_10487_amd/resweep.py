@@ -1,10 +1,11 @@
 """Reynolds-number sweep at zero incidence (Sec. 6.2) in FP64 and FP32-shifted.
 
-Workload ``workloads.naca_re_sweep(re)`` (c = 512, three structured levels, thin
-O-mesh band).  Each run starts from the uniform state and lasts ``passes``
-chord-transit times; C_D, C_L and the Strouhal number of the lift are taken
-over the last 40 % of it.  The paper's drag at these Reynolds numbers (its
-table of C_D against Re, computed at c = 1024) is printed beside as context.
+Workload ``workloads.naca_re_sweep(re)`` (c = 512, two structured levels, thin
+O-mesh band; ``--f2c-filter`` for the filtered fine -> coarse transfer).  Each
+run starts from the uniform state and lasts ``passes`` chord-transit times;
+C_D, C_L and the Strouhal number of the lift are taken over the last 40 % of
+it.  The paper's drag at these Reynolds numbers (its table of C_D against Re,
+computed at c = 1024) is printed beside as context.
 
     python -m paper_2006_10487_amd.resweep --re 1000,2000,5000,10000 --passes 20
 
@@ -50,8 +51,9 @@ def main(argv=None):
     ap.add_argument("--d-out", type=float, default=0.19, help="outer ellipse beyond the chord, in chords")
     ap.add_argument("--nl", type=int, default=64, help="O-mesh layers")
     ap.add_argument("--h1", type=float, default=0.8, help="first layer height (lu)")
+    ap.add_argument("--f2c-filter", action="store_true", help="filtered fine -> coarse transfer")
     a = ap.parse_args(argv)
-    mesh = dict(ns=a.ns, d_out=a.d_out, nl=a.nl, h1=a.h1)
+    mesh = dict(ns=a.ns, d_out=a.d_out, nl=a.nl, h1=a.h1, f2c_filter=a.f2c_filter)
     for re in [float(x) for x in a.re.split(",")]:
         out = {"re": re, "passes": a.passes}
         try:

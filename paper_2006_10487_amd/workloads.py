@@ -567,16 +567,18 @@ def naca_re500_conv(chord: int = 48) -> Workload:
 
 
 def naca_re_sweep(re: float = 2000.0, ns: int = 1280, d_out: float = 0.19, nl: int = 64,
-                  h1: float = 0.8) -> Workload:
+                  h1: float = 0.8, f2c_filter: bool = False) -> Workload:
     """Reynolds sweep at zero incidence (Sec. 6.2): c = 512, U = 0.05, a base grid
     of spacing 2 spanning 16c x 8c with one box of unit spacing (2c x c) and a thin
     O-mesh band (outer ellipse d_out c beyond the chord line and the edges; by
-    default 1280 surface points ~0.8 lu apart, first layer 0.8 lu, 64 layers)."""
+    default 1280 surface points ~0.8 lu apart, first layer 0.8 lu, 64 layers).
+    The base level runs at tau = 0.5 + 38.4 / Re (0.5038 at Re 1e4)."""
     c = 512
     default = (ns, d_out, nl, h1) == (1280, 0.19, 64, 0.8)
-    tag = "" if default else f"_m{ns}_d{d_out:g}_l{nl}_h{h1:g}"
-    return _naca_workload(f"naca0012_re{int(re)}_c512_sweep{tag}", 8 * c, 4 * c, [(2 * c, c)], float(c),
-                          float(re), 0.05, 0.0, ns, nl, d_out * c, h1=h1, steps=200 * c)
+    tag = ("" if default else f"_m{ns}_d{d_out:g}_l{nl}_h{h1:g}") + ("_f2c3x3" if f2c_filter else "")
+    w = _naca_workload(f"naca0012_re{int(re)}_c512_sweep{tag}", 8 * c, 4 * c, [(2 * c, c)], float(c),
+                       float(re), 0.05, 0.0, ns, nl, d_out * c, h1=h1, steps=200 * c)
+    return dataclasses.replace(w, f2c_filter=bool(f2c_filter))
 
 
 PRESETS = {
