@@ -81,7 +81,7 @@ typedef struct {
                                      coincident fine node; 1 = that f^neq full-weighted over the
                                      3 x 3 fine nodes around it (weights (2-|di|)(2-|dj|)/16), which
                                      keeps the interface stable with tau close to 1/2 on the coarse
-                                     levels.  The discrete adjoint supports 0 only                   */
+                                     levels (boxes of at least 8 x 8 cells)                          */
 } hlbm_grid;
 
 /* Body-fitted triangular mesh (Sec. 2 and 4). */

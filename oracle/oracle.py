@@ -402,8 +402,9 @@ class ComplexStepOracle:
 
     def __init__(self, *, nx_cells, ny_cells, patches=(), wall_bc=True, n_sub=0, interp="quadratic",
                  u_inf=0.05, aoa=0.0, rho0=1.0, tau_s=0.6, chord=1.0, inner_ellipse=None,
-                 mesh_xy=None, mesh_tri=None, mesh_kind=None):
+                 mesh_xy=None, mesh_tri=None, mesh_kind=None, f2c_filter=False):
         cfg = _CfgCS()
+        cfg.f2c_filter = int(f2c_filter)
         cfg.nx_cells, cfg.ny_cells = nx_cells, ny_cells
         cfg.n_refine = len(patches)
         for k, (i0, j0, px, py) in enumerate(patches):
@@ -442,7 +443,7 @@ class ComplexStepOracle:
         return cls(nx_cells=w.nx_cells, ny_cells=w.ny_cells, patches=w.patches, n_sub=n_sub or w.n_sub,
                    interp=interp, u_inf=w.u_inf, aoa=aoa, rho0=w.rho0, tau_s=tau_s, chord=w.chord,
                    inner_ellipse=w.inner_ellipse, mesh_xy=w.mesh_xy if mesh_xy is None else mesh_xy,
-                   mesh_tri=w.mesh_tri, mesh_kind=w.mesh_kind)
+                   mesh_tri=w.mesh_tri, mesh_kind=w.mesh_kind, f2c_filter=w.f2c_filter)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -487,9 +488,12 @@ def objective_derivative(w, spec, *, aoa=None, tau_s=None, d_aoa=0.0, d_tau=0.0,
     o.step(spec["t_end"])
     cd, cl = o.history()
     s = slice(spec["t0"], spec["t1"])
-    J = np.mean(spec["w_cd"] * cd[s] + spec["w_cl"] * cl[s])
+    # real and imaginary parts summed as real arrays: the real part then takes the
+    # summation order of the FP64 objective
+    j = spec["w_cd"] * cd[s] + spec["w_cl"] * cl[s]
+    J_re, J_im = np.mean(np.real(j)), np.mean(np.imag(j))
     o.close()
-    return float(J.real), float(J.imag / h)
+    return float(J_re), float(J_im / h)
 
 
 # ---------------------------------------------------------------------------

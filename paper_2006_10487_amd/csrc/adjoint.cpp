@@ -82,7 +82,6 @@ int check_supported(hlbm_ctx* c, const hlbm_objective* o) {
     if (p.precision != HLBM_FP64) return set_err(c, HLBM_E_ARG, "the adjoint runs in FP64 contexts");
     if (p.periodic) return set_err(c, HLBM_E_ARG, "the adjoint needs the far-field base level");
     if (!p.has_mesh || p.wedge.empty()) return set_err(c, HLBM_E_ARG, "the adjoint needs a mesh with a wall");
-    if (p.f2c_filter) return set_err(c, HLBM_E_ARG, "the adjoint covers the pointwise fine -> coarse transfer only");
     const int64_t per = int64_t(1) << p.L;
     if (o->t_end <= 0 || o->t0 < 0 || o->t1 <= o->t0 || o->t1 > o->t_end || o->ckpt_every <= 0)
         return set_err(c, HLBM_E_ARG, "objective window must satisfy 0 <= t0 < t1 <= t_end, ckpt_every > 0");
@@ -94,7 +93,6 @@ int check_supported(hlbm_ctx* c, const hlbm_objective* o) {
 
 int box_nodes(const LevelPlan& v) { return 2 * ((v.ci1 - v.ci0) + (v.cj1 - v.cj0)); }
 int perim_nodes(const KLevel& C) { return 2 * ((C.nx - 1) + (C.ny - 1)); }
-int ring_nodes(const LevelPlan& v) { return 2 * ((v.ci1 - v.ci0 - 2) + (v.cj1 - v.cj0 - 2)); }
 int bc_blocks(const KLevel& L) {
     return L.farfield ? adj_blocks_nodes(2 * (L.nx - 2)) + adj_blocks_nodes(2 * (L.ny - 2)) + 1 : 0;
 }
@@ -177,7 +175,9 @@ void layout(hlbm_ctx* c, AdjState& a) {
     int coarse = 0, init = 0;
     for (int l = 0; l <= p.L; ++l) {
         const int cs = adj_blocks_collide(c->kl[l]) + bc_blocks(c->kl[l]);
-        const int tr = l < p.L ? std::max(adj_blocks_nodes(ring_nodes(p.lev[l])), adj_blocks_nodes(perim_nodes(c->kl[l + 1])))
+        const int tr = l < p.L ? std::max(adj_blocks_nodes(f2c_adj_threads(p.lev[l].ci1 - p.lev[l].ci0,
+                                                                             p.lev[l].cj1 - p.lev[l].cj0, p.f2c_filter)),
+                                          adj_blocks_nodes(perim_nodes(c->kl[l + 1])))
                                : 0;
         coarse = std::max(coarse, std::max(cs, tr));
         init += cs + tr + adj_blocks_nodes(int(c->kl[l].ny * c->kl[l].rs) + p.nn);
@@ -551,8 +551,8 @@ void reverse_level(hlbm_ctx* c, AdjState& a, int l, int idx, int64_t ta, double&
             // input of its second step (interior nodes, untouched by the transfers)
             launch_adj_f2c(c->kl[l], c->kl[l + 1], v.ci0, v.cj0, nxc, nyc,
                            a.at<double>(a.seg_lev_at(l + 1, 2 * idx + 1)), a.at<double>(a.off.abar[l][a.ab[l]]),
-                           a.at<double>(a.off.abar[l + 1][a.ab[l + 1]]), tr.f2c, tr.df2c, partial, 0, s);
-            launch_reduce_partials(partial, adj_blocks_nodes(ring_nodes(v)), acc, s);
+                           a.at<double>(a.off.abar[l + 1][a.ab[l + 1]]), tr.f2c, tr.df2c, partial, 0, p.f2c_filter, s);
+            launch_reduce_partials(partial, adj_blocks_nodes(f2c_adj_threads(nxc, nyc, p.f2c_filter)), acc, s);
         }
         // coarse -> fine^T onto the side values at the parent's two times
         launch_adj_c2f_a(c->kl[l + 1], sp, sc, 0.5 * half, a.at<double>(a.off.abar[l + 1][a.ab[l + 1]]),
@@ -608,8 +608,9 @@ int reverse_initial(hlbm_ctx* c, AdjState& a) {
         double* prebar = a.at<double>(a.off.prebar[l]);
         launch_fill_uniform(HLBM_FP64, Aw, c->kl[l + 1], p.rho0, ux, uy, s);
         launch_adj_f2c(c->kl[l], c->kl[l + 1], v.ci0, v.cj0, nxc, nyc, Aw, a.at<double>(a.off.abar[l][a.ab[l]]),
-                       a.at<double>(a.off.abar[l + 1][1 - a.ab[l + 1]]), tr.f2c, tr.df2c, partial, slot, s);
-        slot += adj_blocks_nodes(ring_nodes(v));
+                       a.at<double>(a.off.abar[l + 1][1 - a.ab[l + 1]]), tr.f2c, tr.df2c, partial, slot,
+                       p.f2c_filter, s);
+        slot += adj_blocks_nodes(f2c_adj_threads(nxc, nyc, p.f2c_filter));
         launch_fill_uniform(HLBM_FP64, Aw, c->kl[l], p.rho0, ux, uy, s);
         slot += collide_adj(c, K, Aw, a.at<double>(a.off.abar[l][a.ab[l]]), prebar, slot);
         launch_adj_side(c->kl[l], v.ci0, v.cj0, nxc, nyc, Aw, a.at<double>(a.off.sbar[l][a.sb[l]]), prebar, s);

@@ -257,7 +257,11 @@ void launch_adj_c2f_a(const KLevel& C, const double* side_prev, const double* si
 void launch_adj_c2f_b(int nxc, int nyc, const double* vbar, double theta, double* sbar_prev, double* sbar_cur,
                       hipStream_t s);
 void launch_adj_f2c(const KLevel& P, const KLevel& C, int ci0, int cj0, int nxc, int nyc, const double* cprev,
-                    double* xbar, double* ybar, double coef, double dcoef, double* partial, int pslot, hipStream_t s);
+                    double* xbar, double* ybar, double coef, double dcoef, double* partial, int pslot, int filter,
+                    hipStream_t s);
+// threads (and so partial-sum blocks) of launch_adj_f2c: the ring nodes, or with the
+// filtered transfer the fine band their 3 x 3 stencils cover
+int f2c_adj_threads(int nxc, int nyc, int filter);
 void launch_adj_side(const KLevel& P, int ci0, int cj0, int nxc, int nyc, const double* A, const double* sbar,
                      double* prebar, hipStream_t s);
 void launch_reduce_partials(const double* partial, int n, double* acc, hipStream_t s);

@@ -2133,6 +2133,85 @@ __global__ __launch_bounds__(256) void k_adj_f2c(const KLevel P, const KLevel C,
     block_partial(0.0, dtau, partial, pslot);
 }
 
+// Fine -> coarse^T with the filtered transfer (the f^neq of the coincident fine
+// node full-weighted over its 3 x 3 fine nodes).  One thread per fine node of
+// the band those stencils cover: the perimeters of the fine rectangles at
+// offsets 1, 2 (the coincident nodes) and 3 from the child's edge.  Each band
+// node gathers w * coef * xbar of the up to four ring nodes whose stencil holds
+// it, adds the (rho, u) adjoint of its own ring node if it is a coincident one,
+// and scatters the result onto the populations it pulls (a fine node's pull
+// sources are its own, so the scatter has one writer per entry).  xbar of the
+// ring nodes is cleared by k_adj_f2c_clear afterwards.
+__device__ __forceinline__ bool f2c_ring_fine(int x, int y, int nxc, int nyc) {
+    const int x1 = 2 * (nxc - 1), y1 = 2 * (nyc - 1);
+    return x >= 2 && x <= x1 && y >= 2 && y <= y1 && (x == 2 || x == x1 || y == 2 || y == y1);
+}
+__global__ __launch_bounds__(256) void k_adj_f2c_filt(const KLevel P, const KLevel C, int ci0, int cj0, int nxc,
+                                                      int nyc, const double* __restrict__ cprev,
+                                                      const double* __restrict__ xbar, double* __restrict__ ybar,
+                                                      double coef, double dcoef, double* partial, int pslot) {
+    const int rx = nxc - 2, ry = nyc - 2;
+    // band rectangles (cells): offset 1 has 2 rx + 2 by 2 ry + 2, offset 2 has 2 rx by 2 ry,
+    // offset 3 has 2 rx - 2 by 2 ry - 2
+    const int n1 = 2 * ((2 * rx + 2) + (2 * ry + 2)), n2 = 2 * (2 * rx + 2 * ry);
+    const int n3 = rx > 1 && ry > 1 ? 2 * ((2 * rx - 2) + (2 * ry - 2)) : 0;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    double dtau = 0.0;
+    if (t < n1 + n2 + n3) {
+        int off, cx, cy;
+        if (t < n1) { off = 1; cx = 2 * rx + 2; cy = 2 * ry + 2; }
+        else if (t < n1 + n2) { t -= n1; off = 2; cx = 2 * rx; cy = 2 * ry; }
+        else { t -= n1 + n2; off = 3; cx = 2 * rx - 2; cy = 2 * ry - 2; }
+        int a, b;
+        box_node(t, cx, cy, a, b);
+        const int x = off + a, y = off + b;
+        double f[9], rho, ux, uy, feq[9], nb[9];
+        pull(C, cprev, x, y, f);
+        macro64(f, rho, ux, uy);
+        equilibrium<double, false>(rho, rho, ux, uy, feq);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) nb[q] = 0.0;
+        double a12[12] = {0.0, 0.0, 0.0};
+        const int xs0 = (x & 1) ? x - 1 : x, xs1 = (x & 1) ? x + 1 : x;
+        const int ys0 = (y & 1) ? y - 1 : y, ys1 = (y & 1) ? y + 1 : y;
+        for (int ry_ = ys0; ry_ <= ys1; ry_ += 2)
+            for (int rx_ = xs0; rx_ <= xs1; rx_ += 2) {
+                if (!f2c_ring_fine(rx_, ry_, nxc, nyc)) continue;
+                const double w = double((2 - abs(x - rx_)) * (2 - abs(y - ry_))) * 0.0625;
+                const size_t base = size_t(cj0 + ry_ / 2) * size_t(P.rs) + (ci0 + rx_ / 2);
+                double xb[9];
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    xb[q] = xbar[size_t(q) * P.pitch + base];
+                    nb[q] += w * coef * xb[q];
+                    dtau += dcoef * w * xb[q] * (f[q] - feq[q]);
+                }
+                if (rx_ == x && ry_ == y) feq_adj(rho, ux, uy, xb, a12[0], a12[1], a12[2]);
+            }
+#pragma unroll
+        for (int q = 0; q < 9; ++q) a12[3 + q] = nb[q];
+        double fb[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) fb[q] = 0.0;
+        macro_neq_adj(f, a12, fb);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) ybar[lidx(C, q, x - CX[q], y - CY[q])] += fb[q];
+    }
+    block_partial(0.0, dtau, partial, pslot);
+}
+
+// Clears xbar at the ring nodes after k_adj_f2c_filt has read it.
+__global__ void k_adj_f2c_clear(const KLevel P, int ci0, int cj0, int nxc, int nyc, double* __restrict__ xbar) {
+    const int rx = nxc - 2, ry = nyc - 2;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 2 * (rx + ry)) return;
+    int a, b;
+    box_node(k, rx, ry, a, b);
+    const size_t base = size_t(cj0 + 1 + b) * size_t(P.rs) + (ci0 + 1 + a);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) xbar[size_t(q) * P.pitch + base] = 0.0;
+}
+
 // Adjoint of the side values (rho, u, f^neq) recorded from the parent's pulled
 // populations at its box-boundary nodes: prebar(node) += J^T sbar (per node).
 __global__ void k_adj_side(const KLevel P, int ci0, int cj0, int nxc, int nyc, const double* __restrict__ A,
@@ -2269,10 +2348,25 @@ void launch_adj_c2f_b(int nxc, int nyc, const double* vbar, double theta, double
                       hipStream_t s) {
     k_adj_c2f_b<<<adj_blocks_nodes(2 * (nxc + nyc)), 256, 0, s>>>(nxc, nyc, vbar, theta, sbar_prev, sbar_cur);
 }
+int f2c_adj_threads(int nxc, int nyc, int filter) {
+    const int rx = nxc - 2, ry = nyc - 2;
+    if (!filter) return 2 * (rx + ry);
+    return 2 * ((2 * rx + 2) + (2 * ry + 2)) + 2 * (2 * rx + 2 * ry) +
+           (rx > 1 && ry > 1 ? 2 * ((2 * rx - 2) + (2 * ry - 2)) : 0);
+}
 void launch_adj_f2c(const KLevel& P, const KLevel& C, int ci0, int cj0, int nxc, int nyc, const double* cprev,
-                    double* xbar, double* ybar, double coef, double dcoef, double* partial, int pslot, hipStream_t s) {
-    const int n = 2 * (nxc - 2 + nyc - 2);
-    k_adj_f2c<<<adj_blocks_nodes(n), 256, 0, s>>>(P, C, ci0, cj0, nxc, nyc, cprev, xbar, ybar, coef, dcoef, partial, pslot);
+                    double* xbar, double* ybar, double coef, double dcoef, double* partial, int pslot, int filter,
+                    hipStream_t s) {
+    const int n = f2c_adj_threads(nxc, nyc, filter);
+    if (!filter) {
+        k_adj_f2c<<<adj_blocks_nodes(n), 256, 0, s>>>(P, C, ci0, cj0, nxc, nyc, cprev, xbar, ybar, coef, dcoef, partial,
+                                                      pslot);
+        return;
+    }
+    k_adj_f2c_filt<<<adj_blocks_nodes(n), 256, 0, s>>>(P, C, ci0, cj0, nxc, nyc, cprev, xbar, ybar, coef, dcoef,
+                                                       partial, pslot);
+    const int nr = 2 * (nxc - 2 + nyc - 2);
+    k_adj_f2c_clear<<<blocks(nr), 256, 0, s>>>(P, ci0, cj0, nxc, nyc, xbar);
 }
 void launch_adj_side(const KLevel& P, int ci0, int cj0, int nxc, int nyc, const double* A, const double* sbar,
                      double* prebar, hipStream_t s) {

@@ -649,6 +649,10 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
     p.check_every = std::max(0, g->check_every);
     if (g->f2c_filter != 0 && g->f2c_filter != 1) return fail(err, HLBM_E_ARG, "f2c_filter must be 0 or 1");
     p.f2c_filter = g->f2c_filter;
+    if (p.f2c_filter)
+        for (int l = 0; l < g->n_refine && l < 3; ++l)
+            if (g->patch_nx[l] < 8 || g->patch_ny[l] < 8)
+                return fail(err, HLBM_E_ARG, "f2c_filter needs boxes of at least 8 x 8 cells");
     p.hist_len = g->history_len > 0 ? g->history_len : 65536;
     // relaxation time of the finest level (nu = c_s^2 (tau - 1/2), Sec. 2)
     if (tau > 0.5) {

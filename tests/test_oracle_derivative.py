@@ -98,10 +98,15 @@ def test_bump_tangent_matches_generator():
     assert np.abs(tan[:, om.nl * om.ns:, :]).max() == 0.0
 
 
-def test_refined_derivative_matches_finite_differences():
-    """One refinement box: the derivative crosses the coarse <-> fine transfers."""
-    w = W.naca_re100_c40_refined(3.0)
-    _, d = O.objective_derivative(w, SPEC, d_tau=1.0, n_sub=N_SUB)
+@pytest.mark.parametrize("f2c_filter", [False, True])
+def test_refined_derivative_matches_finite_differences(f2c_filter):
+    """One refinement box: the derivative crosses the coarse <-> fine transfers
+    (fine -> coarse pointwise, and with the f^neq full-weighted over 3 x 3 fine
+    nodes, where the real part must still be the FP64 oracle bit for bit)."""
+    import dataclasses
+    w = dataclasses.replace(W.naca_re100_c40_refined(3.0), f2c_filter=f2c_filter)
+    J, d = O.objective_derivative(w, SPEC, d_tau=1.0, n_sub=N_SUB)
+    assert J == plain_J(w)
     h = 1e-7
     fd = (plain_J(w, tau=w.tau_s + h) - plain_J(w, tau=w.tau_s - h)) / (2 * h)
     print("refined tau", d, fd)
