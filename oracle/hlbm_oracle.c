@@ -38,6 +38,15 @@
  *     populations copied from the inner neighbour at top and bottom.
  *   - no-slip on the mesh: half control volume update, then u -> 0 keeping
  *     rho and the non-equilibrium part.
+ *   - the standard LBM that resolves the body, against which eq. (14) prices
+ *     the hybrid scheme (no mesh, the body a polygon on the finest level):
+ *     nodes strictly inside the polygon (crossing-number test, an edge counted
+ *     when exactly one of its end points lies on or below the node's row) are
+ *     solid; a population that would stream out of a solid node is the
+ *     fluid node's own post-collision population of the opposite direction
+ *     (halfway bounce-back, wall midway between the two nodes), and the force
+ *     on the body is the momentum those populations bring back, 2 c f~ per
+ *     link (momentum exchange).
  *   - exchange order inside a finest step: eq. (4) from the mesh at t, the
  *     finest level to t+1, eq. (9) at t+1, then the n sub-steps with the
  *     structured values blended linearly in time.
@@ -76,15 +85,20 @@ static const int CX[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 static const int CY[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 static const double W[Q] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+/* index of -c_i */
+static const int OPPOSITE[Q] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
 /* Deliberate-mistake multipliers for mutation tests of the pins (all 1 in a
  * normal run): [0] eq. (4) non-equilibrium factor, [1] eq. (5)-(6) factor,
  * [2] coarse -> fine rescaling, [3] fine -> coarse rescaling, [4] the
  * non-equilibrium part kept by the no-slip reset of wall nodes, [5] the reset
  * itself (0 skips it), [6] the time fraction theta = m/n at which the
- * structured values are blended into the finite-volume sub-steps. */
-#define N_PLANT 7
-static double plant[N_PLANT] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};
+ * structured values are blended into the finite-volume sub-steps, [7] the
+ * bounce-back at a solid body (0: the population of the same direction comes
+ * back instead of the opposite one), [8] the returning half of the momentum
+ * exchanged per bounce-back link (0: only the outgoing population counts). */
+#define N_PLANT 9
+static double plant[N_PLANT] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};
 
 void or_plant(int32_t which, double value)
 {
@@ -92,7 +106,7 @@ void or_plant(int32_t which, double value)
 }
 
 /* node classes of a structured level */
-enum { CL_ACTIVE = 0, CL_INACTIVE = 1, CL_INTERP = 2, CL_PERIM = 3, CL_RING = 4, CL_COVERED = 5 };
+enum { CL_ACTIVE = 0, CL_INACTIVE = 1, CL_INTERP = 2, CL_PERIM = 3, CL_RING = 4, CL_COVERED = 5, CL_SOLID = 6 };
 enum { KIND_INTERIOR = 0, KIND_WALL = 1, KIND_INTERP = 2 };
 
 typedef struct {
@@ -120,6 +134,10 @@ typedef struct {
     /* fine -> coarse restriction: 0 = f^neq of the coincident fine node,
      * 1 = f^neq full-weighted over the 3 x 3 fine nodes around it */
     int32_t f2c_filter;
+    /* solid body resolved on the finest level by bounce-back (no mesh):
+     * polygon vertices (x, y) in finest-level units, body_n = 0: none */
+    int32_t body_n;
+    const double *body_xy;
 } or_cfg;
 
 typedef struct {
@@ -249,6 +267,21 @@ static int inside_ellipse(const double *e, double x, double y)
     return dx * dx + dy * dy < 1.0;
 }
 
+/* Crossing number of the ray from (x, y) towards +x with the polygon's edges;
+ * an edge counts when exactly one of its end points has y' <= y.  Odd: inside. */
+static int inside_polygon(int n, const double *xy, double x, double y)
+{
+    int crossings = 0;
+    for (int e = 0; e < n; ++e) {
+        const double *a = xy + 2 * e, *b = xy + 2 * ((e + 1) % n);
+        int a_below = a[1] <= y, b_below = b[1] <= y;
+        if (a_below == b_below) continue;
+        double x_cross = a[0] + (y - a[1]) * (b[0] - a[0]) / (b[1] - a[1]);
+        if (x < x_cross) crossings++;
+    }
+    return crossings % 2;
+}
+
 /* Node classes (Sec. 4): boxes covered by a finer box keep their boundary
  * nodes; the first ring inside receives the restricted fine values; the finest
  * level has an inactive region inside the inner ellipse whose nodes with an
@@ -272,6 +305,10 @@ static void classify(oracle_t *o)
                 if (l == o->L && o->cfg.ein[2] > 0.0 && c == CL_ACTIVE) {
                     double x = lv->ox + i * lv->sp, y = lv->oy + j * lv->sp;
                     if (inside_ellipse(o->cfg.ein, x, y)) c = CL_INACTIVE;
+                }
+                if (l == o->L && o->cfg.body_n > 0 && c == CL_ACTIVE) {
+                    double x = lv->ox + i * lv->sp, y = lv->oy + j * lv->sp;
+                    if (inside_polygon(o->cfg.body_n, o->cfg.body_xy, x, y)) c = CL_SOLID;
                 }
                 lv->cls[(size_t)j * lv->nx + i] = c;
             }
@@ -778,6 +815,26 @@ void *or_create(const or_cfg *cfg, char *err_out, int32_t err_len)
             if (!o->lev[l].f || !o->lev[l].post || !o->lev[l].save) FAIL("oom");
         }
         classify(o);
+        if (cfg->body_n > 0) {
+            /* every solid node is surrounded by active or solid nodes of the level */
+            olevel *fl = &o->lev[L];
+            int per = L == 0 && cfg->periodic, nsolid = 0;
+            if (cfg->n_nodes > 0 || cfg->ein[2] > 0.0) FAIL("a body resolved by bounce-back excludes a mesh");
+            for (int j = 0; j < fl->ny; ++j)
+                for (int i = 0; i < fl->nx; ++i) {
+                    if (fl->cls[(size_t)j * fl->nx + i] != CL_SOLID) continue;
+                    nsolid++;
+                    for (int q = 1; q < Q; ++q) {
+                        int a = i + CX[q], b = j + CY[q];
+                        if (per) { a = (a + fl->nx) % fl->nx; b = (b + fl->ny) % fl->ny; }
+                        else if (a < 1 || b < 1 || a > fl->nx - 2 || b > fl->ny - 2)
+                            FAIL("the body touches the edge of the finest level");
+                        uint8_t c = fl->cls[(size_t)b * fl->nx + a];
+                        if (c != CL_ACTIVE && c != CL_SOLID) FAIL("the body touches a box boundary");
+                    }
+                }
+            if (nsolid == 0) FAIL("the body covers no node of the finest level");
+        }
     }
     /* mesh */
     o->nn = cfg->n_nodes; o->nt = cfg->n_tris;
@@ -1082,7 +1139,13 @@ static void level_step(oracle_t *o, int l)
             for (int q = 0; q < Q; ++q) {
                 int a = i - CX[q], b = j - CY[q];
                 if (periodic) { a = (a + nx) % nx; b = (b + ny) % ny; }
-                lv->f[LIDX(lv, q, i, j)] = lv->post[LIDX(lv, q, a, b)];
+                if (lv->cls[(size_t)b * nx + a] == CL_SOLID) {
+                    /* halfway bounce-back: what left (i, j) towards the body returns */
+                    int back = plant[7] != 0.0 ? OPPOSITE[q] : q;
+                    lv->f[LIDX(lv, q, i, j)] = lv->post[LIDX(lv, back, i, j)];
+                } else {
+                    lv->f[LIDX(lv, q, i, j)] = lv->post[LIDX(lv, q, a, b)];
+                }
             }
         }
     /* 5. far field on the base level */
@@ -1285,6 +1348,31 @@ static void wall_coefficients(const oracle_t *o, real *cp, real *cf, real *cn)
     free(V);
 }
 
+/* Force on the body by momentum exchange: every population f~_p that left a
+ * fluid node towards a solid one (x + c_p solid) comes back reversed and gives
+ * the body 2 c_p f~_p. */
+static void body_force(const oracle_t *o, real *fx, real *fy)
+{
+    const olevel *lv = &o->lev[o->L];
+    int nx = lv->nx, ny = lv->ny;
+    int periodic = (o->L == 0 && o->cfg.periodic);
+    real sx = 0.0, sy = 0.0;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            if (lv->cls[(size_t)j * nx + i] != CL_ACTIVE) continue;
+            for (int p = 1; p < Q; ++p) {
+                int a = i + CX[p], b = j + CY[p];
+                if (periodic) { a = (a + nx) % nx; b = (b + ny) % ny; }
+                if (a < 0 || b < 0 || a >= nx || b >= ny || lv->cls[(size_t)b * nx + a] != CL_SOLID) continue;
+                real out = lv->post[LIDX(lv, p, i, j)];
+                sx += (1.0 + plant[8]) * CX[p] * out;
+                sy += (1.0 + plant[8]) * CY[p] * out;
+            }
+        }
+    *fx = sx;
+    *fy = sy;
+}
+
 static void record_forces(oracle_t *o)
 {
     if (o->t >= o->hist_cap) {
@@ -1294,6 +1382,7 @@ static void record_forces(oracle_t *o)
     }
     real fx = 0, fy = 0;
     if (o->nn > 0) wall_force(o, &fx, &fy);
+    else if (o->cfg.body_n > 0) body_force(o, &fx, &fy);
     real ca = cos(o->cfg.aoa), sa = sin(o->cfg.aoa);
     real qd = 0.5 * o->cfg.rho0 * o->cfg.u_inf * o->cfg.u_inf * o->cfg.chord;
     if (!(RE(qd) > 0)) qd = 1.0;

@@ -42,6 +42,7 @@ class _Cfg(C.Structure):
         ("n_nodes", C.c_int32), ("n_tris", C.c_int32),
         ("xy", C.POINTER(C.c_double)), ("tri", C.POINTER(C.c_int32)), ("kind", C.POINTER(C.c_uint8)),
         ("channel", C.c_int32), ("f2c_filter", C.c_int32),
+        ("body_n", C.c_int32), ("body_xy", C.POINTER(C.c_double)),
     ]
 
 
@@ -103,7 +104,10 @@ class planted:
     factor, 2 the coarse -> fine rescaling, 3 the fine -> coarse rescaling,
     4 the non-equilibrium part kept by the no-slip reset of wall nodes, 5 the
     reset itself (0 skips it), 6 the time fraction theta = m/n of the
-    structured values blended into the sub-steps (0 freezes them at t).
+    structured values blended into the sub-steps (0 freezes them at t), 7
+    the bounce-back at a resolved body (0: the population of the same
+    direction comes back), 8 the returning half of the momentum exchanged per
+    bounce-back link (0: only the outgoing population counts).
     Used only by mutation tests that show a pin fails on a wrong oracle.
     """
 
@@ -199,7 +203,7 @@ class Oracle:
     def __init__(self, *, nx_cells=0, ny_cells=0, patches=(), periodic=False, wall_bc=True,
                  n_sub=0, interp="quadratic", u_inf=0.05, aoa=0.0, rho0=1.0, tau_s=0.6,
                  chord=1.0, inner_ellipse=None, mesh_xy=None, mesh_tri=None, mesh_kind=None,
-                 mesh_period=(0.0, 0.0), channel=False, f2c_filter=False):
+                 mesh_period=(0.0, 0.0), channel=False, f2c_filter=False, body_xy=None):
         cfg = _Cfg()
         cfg.channel = int(channel)
         cfg.f2c_filter = int(f2c_filter)
@@ -217,6 +221,11 @@ class Oracle:
             cfg.ein[k] = float(ein[k])
         cfg.mesh_period[0], cfg.mesh_period[1] = float(mesh_period[0]), float(mesh_period[1])
         self._keep = []
+        if body_xy is not None:   # solid polygon on the finest level, resolved by bounce-back
+            bxy = np.ascontiguousarray(body_xy, dtype=np.float64).reshape(-1, 2)
+            self._keep.append(bxy)
+            cfg.body_n = bxy.shape[0]
+            cfg.body_xy = bxy.ctypes.data_as(C.POINTER(C.c_double))
         if mesh_xy is not None:
             xy = np.ascontiguousarray(mesh_xy, dtype=np.float64).reshape(-1, 2)
             tri = np.ascontiguousarray(mesh_tri, dtype=np.int32).reshape(-1, 3)
@@ -257,7 +266,7 @@ class Oracle:
                    u_inf=w.u_inf, aoa=w.aoa_rad if aoa_rad is None else aoa_rad, rho0=w.rho0,
                    tau_s=w.tau_s if tau_s is None else tau_s, chord=w.chord,
                    inner_ellipse=w.inner_ellipse, mesh_xy=w.mesh_xy, mesh_tri=w.mesh_tri,
-                   mesh_kind=w.mesh_kind, f2c_filter=w.f2c_filter)
+                   mesh_kind=w.mesh_kind, f2c_filter=w.f2c_filter, body_xy=w.body_xy)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -362,6 +371,7 @@ class _CfgCS(C.Structure):
         ("n_nodes", C.c_int32), ("n_tris", C.c_int32),
         ("xy", C.c_void_p), ("tri", C.POINTER(C.c_int32)), ("kind", C.POINTER(C.c_uint8)),
         ("channel", C.c_int32), ("f2c_filter", C.c_int32),
+        ("body_n", C.c_int32), ("body_xy", C.POINTER(C.c_double)),
     ]
 
 

@@ -373,6 +373,9 @@ class Workload:
     omesh: Optional[OMesh] = None
     notes: str = ""
     f2c_filter: bool = False   # fine -> coarse f^neq full-weighted over 3 x 3 fine nodes
+    # solid body on the finest level resolved by bounce-back (a standard LBM, no mesh):
+    # polygon vertices (x, y) in finest lu, counter-clockwise
+    body_xy: Optional[np.ndarray] = None
 
     @property
     def n_refine(self) -> int:
@@ -579,6 +582,28 @@ def naca_re_sweep(re: float = 2000.0, ns: int = 1280, d_out: float = 0.19, nl: i
     w = _naca_workload(f"naca0012_re{int(re)}_c512_sweep{tag}", 8 * c, 4 * c, [(2 * c, c)], float(c),
                        float(re), 0.05, 0.0, ns, nl, d_out * c, h1=h1, steps=200 * c)
     return dataclasses.replace(w, f2c_filter=bool(f2c_filter))
+
+
+def equivalent_lbm(w: Workload, margin: int = 8, body: bool = True) -> Workload:
+    """The standard LBM against which eq. (14) prices the hybrid scheme: w's
+    structured grid with one more box of half the finest spacing over w's finest
+    box (inset by `margin` cells of that box on every side) and no mesh, the
+    profile resolved on that box by bounce-back (its wall points as a polygon;
+    body=False leaves it out).  Its finest spacing is half a lattice unit of w,
+    the wall spacing of the workloads' meshes.  Lengths are in the new finest
+    units, so coordinates and the chord double and Re, U (hence tau) hold."""
+    if w.patches:
+        px, py = w.patches[-1][2], w.patches[-1][3]
+    else:
+        px, py = w.nx_cells, w.ny_cells
+    box = (margin, margin, 2 * (px - 2 * margin), 2 * (py - 2 * margin))
+    poly = None
+    if body and w.omesh is not None:
+        poly = 2.0 * w.omesh.xy[w.omesh.surface_index]
+    return dataclasses.replace(
+        w, name=w.name + ("_equivalent_lbm" if body else "_equivalent_lbm_nobody"), patches=list(w.patches) + [box],
+        chord=2.0 * w.chord, mesh_xy=None, mesh_tri=None, mesh_kind=None, inner_ellipse=(0.0, 0.0, 0.0, 0.0),
+        omesh=None, n_sub=0, body_xy=poly)
 
 
 PRESETS = {

@@ -655,3 +655,125 @@ def test_symmetry_zero_incidence_and_mirror():
     assert np.abs(clp + clm).max() < 1e-9
     assert np.abs(cdp - cdm).max() < 1e-9
     assert clp[-1] > 0.05
+
+
+# ---------------------------------------------------------------------------
+# Standard LBM with the body resolved by bounce-back (the comparison scheme of
+# eq. (14)): halfway bounce-back and the momentum-exchange force
+# ---------------------------------------------------------------------------
+
+def _bounce_back_shear_wave(H, tau=0.8, u0=1e-3, nx=4):
+    """Shear wave u_x = u0 sin(pi eta / H) between two halfway bounce-back walls:
+    a periodic nx x (H + 2) lattice whose rows 0 and 1 are a solid slab, so the
+    walls sit at y = 1.5 and (through the period) at y = H + 1.5.  Returns the
+    relative errors of the decay rate against nu (pi / H)^2, nu = (tau - 1/2) / 3,
+    and of the force on the slab against the two walls' shear, 2 rho nu (pi / H)
+    u(t) nx, plus the mass drift."""
+    ny = H + 2
+    slab = [(-1.0, -0.5), (nx + 1.0, -0.5), (nx + 1.0, 1.5), (-1.0, 1.5)]
+    o = O.Oracle(nx_cells=nx, ny_cells=ny, periodic=True, u_inf=0.0, tau_s=tau, chord=1.0, body_xy=slab)
+    y = np.repeat(np.arange(ny, dtype=float)[:, None], nx, 1)
+    eta = y - 1.5
+    fluid = y >= 2
+    ux = np.where(fluid, u0 * np.sin(math.pi * eta / H), 0.0)
+    o.set_level(0, feq_field(eq, np.ones_like(ux), ux, np.zeros_like(ux)))
+    nu = (tau - 0.5) / 3.0
+    lam = nu * (math.pi / H) ** 2
+    t2 = int(round(0.5 / lam))
+    t1 = t2 // 4
+    shape = np.where(fluid, np.sin(math.pi * eta / H), 0.0)
+
+    def amp_mass():
+        g = o.get_level(0)
+        rho, vx, vy = macro(g)
+        return amplitude(np.where(fluid, vx, 0.0), 0.0 * vy, shape, 0.0 * shape), float(rho[fluid].sum())
+
+    a0, m0 = amp_mass()
+    o.step(t1)
+    a1, _ = amp_mass()
+    o.step(t2 - t1)
+    a2, m2 = amp_mass()
+    cd, _ = o.history()
+    rate = math.log(a1 / a2) / (t2 - t1)
+    force = 2.0 * nu * (math.pi / H) * a2 * nx
+    return rate / lam - 1.0, float(cd[t2 - 1]) / force - 1.0, abs(m2 - m0) / m0
+
+
+def test_bounce_back_shear_wave_second_order():
+    """Decay rate and wall force of a shear wave between halfway bounce-back walls
+    converge to the closed form at second order (errors 8e-3 / 2e-2 at H = 8)."""
+    e16, f16, m16 = _bounce_back_shear_wave(16)
+    e32, f32, m32 = _bounce_back_shear_wave(32)
+    print(f"decay rate errors {e16:.3e} {e32:.3e}, force errors {f16:.3e} {f32:.3e}")
+    assert abs(e16) < 3e-3 and abs(e32) < 8e-4
+    assert abs(f16) < 8e-3 and abs(f32) < 2e-3
+    assert 3.5 < e16 / e32 < 4.5 and 3.5 < f16 / f32 < 4.5
+    # halfway bounce-back keeps the mass of the fluid exactly (to round-off)
+    assert m16 < 1e-13 and m32 < 1e-13
+
+
+@pytest.mark.parametrize("which", [7, 8])
+def test_bounce_back_planted_mistakes_fail(which):
+    """The same direction coming back instead of the opposite one ([7]) or only the
+    outgoing half of the exchanged momentum ([8]) fails the shear-wave pin."""
+    with O.planted(which, 0.0):
+        e, f, _ = _bounce_back_shear_wave(16)
+    assert abs(e) > 0.1 or abs(f) > 0.1
+
+
+def _winding_number(poly, x, y):
+    """Winding number of the closed polygon around (x, y) by summed angles."""
+    d = poly - np.array([x, y])
+    ang = np.arctan2(d[:, 1], d[:, 0])
+    turn = np.diff(np.concatenate([ang, ang[:1]]))
+    turn = (turn + np.pi) % (2.0 * np.pi) - np.pi
+    return int(round(turn.sum() / (2.0 * np.pi)))
+
+
+def test_bounce_back_body_nodes_inside_polygon():
+    """The solid nodes are the nodes inside the profile polygon (winding number),
+    apart from nodes within 1e-9 of its boundary, which the crossing rule decides."""
+    e = W.equivalent_lbm(W.naca_re100_c40_refined(0.0))
+    o = O.Oracle.from_workload(e)
+    L = o.n_levels - 1
+    cls = o.level_class(L)
+    ny, nx = o.level_shape[L]
+    ox = e.patches[0][0] * 4 + e.patches[1][0] * 2   # finest-level origin in finest lu
+    oy = e.patches[0][1] * 4 + e.patches[1][1] * 2
+    poly = np.asarray(e.body_xy)
+    seg_a, seg_b = poly, np.roll(poly, -1, axis=0)
+    n_solid = 0
+    for j in range(ny):
+        for i in range(nx):
+            x, y = ox + i, oy + j
+            if not (poly[:, 0].min() - 1 < x < poly[:, 0].max() + 1 and poly[:, 1].min() - 1 < y < poly[:, 1].max() + 1):
+                assert cls[j, i] != 6
+                continue
+            ab = seg_b - seg_a
+            tpar = np.clip(((x - seg_a[:, 0]) * ab[:, 0] + (y - seg_a[:, 1]) * ab[:, 1]) / (ab * ab).sum(1), 0, 1)
+            dist = np.hypot(seg_a[:, 0] + tpar * ab[:, 0] - x, seg_a[:, 1] + tpar * ab[:, 1] - y).min()
+            if dist < 1e-9:
+                continue
+            inside = _winding_number(poly, x, y) != 0
+            assert (cls[j, i] == 6) == inside, (i, j)
+            n_solid += inside
+    assert n_solid > 400
+
+
+def test_bounce_back_airfoil_mirror_symmetry():
+    """Body-resolved LBM of the profile: C_L(0) vanishes to round-off, C_L(-a) = -C_L(a)
+    and C_D(-a) = C_D(a) (the grid and the solid nodes are mirror symmetric)."""
+    w0 = W.equivalent_lbm(W.naca_re100_c40_refined(0.0))
+    o = O.Oracle.from_workload(w0)
+    o.step(120)
+    cd, cl = o.history()
+    assert np.abs(cl).max() < 1e-11 and cd[-1] > 0.5
+    a = math.radians(4.0)
+    op = O.Oracle.from_workload(w0, aoa_rad=a)
+    om = O.Oracle.from_workload(w0, aoa_rad=-a)
+    op.step(120)
+    om.step(120)
+    cdp, clp = op.history()
+    cdm, clm = om.history()
+    assert np.abs(clp + clm).max() < 1e-10 and np.abs(cdp - cdm).max() < 1e-10
+    assert np.abs(clp).max() > 1e-2
