@@ -96,6 +96,19 @@ typedef struct {
     int32_t n_shape;              /* shape parameters a_m of the discrete adjoint (0: none)         */
     const double *dxy_dshape;     /* [n_shape][n_nodes][2] d(node x, y)/d a_m in the caller's node
                                      order (borrowed, copied at create), or NULL when n_shape = 0   */
+    int32_t body_n;               /* without a mesh (n_nodes = 0, no inner ellipse): vertices of a
+                                     solid body resolved on the finest structured level, the standard
+                                     LBM that eq. (14) compares the hybrid scheme with; 0 = none.
+                                     Nodes strictly inside the polygon (crossing number, an edge
+                                     counted when exactly one of its end points has y' <= y) are
+                                     solid, one run of them per row, at least 6 nodes from the edges
+                                     of the finest level.  A population that would stream out of a
+                                     solid node is the fluid node's own post-collision population of
+                                     the opposite direction (halfway bounce-back); C_D and C_L come
+                                     from the momentum those populations exchange with the body,
+                                     2 c_i f~_i per link, over rho0 U^2 chord / 2                    */
+    const double *body_xy;        /* [2 * body_n] polygon vertices (x, y) in finest-level coordinates
+                                     (borrowed, copied at create), or NULL when body_n = 0           */
 } hlbm_mesh;
 
 typedef struct {
@@ -124,6 +137,8 @@ typedef struct {
     int64_t fv_layout_bytes;      /* bytes one unfused FV sub-step of this layout reads and writes:
                                      node records with their stored moments (rho, u) in and out,
                                      every slot of the padded neighbour table                       */
+    int32_t n_solid;              /* solid nodes of a body resolved by bounce-back (0: none)         */
+    int32_t n_bounce;             /* fluid nodes next to it (at least one bounce-back link)          */
 } hlbm_info_t;
 
 /* Checks the problem on the host only (no GPU).  Re > 0 gives

@@ -102,6 +102,10 @@ void setup_views(hlbm_ctx* c) {
         k.spans = spans ? reinterpret_cast<const int32_t*>(c->ws + p.off.spans) : nullptr;
         k.sj0 = v.sj0;
         k.sj1 = v.sj1;
+        const bool bounce = l == p.L && !p.bounce_node.empty();
+        k.n_bounce = bounce ? int(p.bounce_node.size()) : 0;
+        k.bounce_node = bounce ? reinterpret_cast<const int32_t*>(c->ws + p.off.bounce_node) : nullptr;
+        k.bounce_mask = bounce ? reinterpret_cast<const int32_t*>(c->ws + p.off.bounce_mask) : nullptr;
         k.u_in_x = p.u_inf * std::cos(p.aoa);
         k.u_in_y = p.u_inf * std::sin(p.aoa);
         k.rho0 = p.rho0;
@@ -141,6 +145,8 @@ int upload_tables(hlbm_ctx* c) {
     auto real = [&](const std::vector<double>& v) { return f64 ? pack_real<double>(v) : pack_real<float>(v); };
     std::vector<std::vector<char>> keep;   // host copies alive until the stream syncs
     rc |= upload(c, p.off.spans, p.spans.data(), p.spans.size() * 4);
+    rc |= upload(c, p.off.bounce_node, p.bounce_node.data(), p.bounce_node.size() * 4);
+    rc |= upload(c, p.off.bounce_mask, p.bounce_mask.data(), p.bounce_mask.size() * 4);
     rc |= upload(c, p.off.sint_node, p.sint_node.data(), p.sint_node.size() * 4);
     rc |= upload(c, p.off.sint_don, p.sint_don.data(), p.sint_don.size() * 4);
     keep.push_back(real(p.sint_w));
@@ -345,6 +351,11 @@ void finest_step(hlbm_ctx* c) {
             c->wstat_n++;
         }
         c->prep_t ^= 1;
+    } else if (c->kl[L].n_bounce > 0) {
+        // body resolved by bounce-back: momentum exchanged over its links in this step
+        const double qn = 0.5 * p.rho0 * p.u_inf * p.u_inf * p.chord;
+        Timed tm(c, HLBM_K_FORCE);
+        launch_body_force(pr, c->kl[L], A, slot, std::cos(p.aoa), std::sin(p.aoa), qn > 0 ? qn : 1.0, c->s);
     } else {
         // no wall: zero force (the kernel writes 0 for an empty edge list)
         launch_wall_force(pr, c->mesh(0), 0, nullptr, nullptr, slot, 1.0, 0.0, 1.0, c->s);
@@ -611,6 +622,8 @@ int hlbm_info(hlbm_ctx* c, hlbm_info_t* o) {
     o->fv_bytes = nn * (2 * kQ * E + 3 * E + 4) + nbr * (4 + 3 * E);
     // what this layout moves: records with stored moments in and out, every padded table slot
     o->fv_layout_bytes = nn * 2 * kRec * E + nn * p.ell_width * (E == 8 ? 32 : 16);
+    o->n_solid = p.n_solid;
+    o->n_bounce = int32_t(p.bounce_node.size());
     o->bytes_per_finest_step = bytes / (int64_t(1) << p.L) + int64_t(p.n_sub) * o->fv_bytes;
     o->t = c->t;
     o->workspace_bytes = p.off.total;

@@ -62,7 +62,7 @@ struct Plan {
     int L = 0, nlev = 0;
     double tau_s = 0, tau_u = 0, dt_u = 0;
     int n_sub = 0, precision = 0, interp = 0;
-    bool periodic = false, wall_bc = true, has_grid = false, has_mesh = false;
+    bool periodic = false, wall_bc = true, has_grid = false, has_mesh = false, has_body = false;
     double u_inf = 0, aoa = 0, rho0 = 1, chord = 1;
     int check_every = 0, hist_len = 65536;
     LevelPlan lev[4];
@@ -73,6 +73,11 @@ struct Plan {
     std::vector<int32_t> sint_don;       // kSDon per node, mesh node in plan order, -1 = unused
     std::vector<double> sint_w;
     int n_fallback = 0;
+    // body resolved by bounce-back (finest level): solid nodes are the spans; the
+    // collide-stream nodes with a solid neighbour, i + nx * j, and per node the bit
+    // mask of directions q whose source x - c_q is solid
+    int n_solid = 0;
+    std::vector<int32_t> bounce_node, bounce_mask;
     // mesh in plan order [wall | interior | interpolation]
     int nn = 0, n_wall = 0, n_core = 0, n_int = 0, nt = 0;
     std::vector<int32_t> perm;           // perm[new] = caller index
@@ -111,7 +116,7 @@ struct Plan {
     struct {
         size_t lev[4][2];
         size_t side[4][2];
-        size_t spans, sint_node, sint_don, sint_w;
+        size_t spans, sint_node, sint_don, sint_w, bounce_node, bounce_mask;
         size_t mesh[2], rowptr, edges, wedge, wnorm, prep[2], uint_don, uint_w, hist, stage;
         size_t wall_nrm, wall_slot, wsum, wout;
         size_t ft_meta, ft_node, ft_edges, ft_star;
@@ -144,8 +149,11 @@ struct KLevel {
     int perim_inactive;
     int ci0, cj0, ci1, cj1;          // strictly inside -> not a collide-stream node
     int farfield, periodic;
-    const int32_t* spans;            // inner-ellipse spans (finest level), or null
+    const int32_t* spans;            // inner-ellipse or solid-body spans (finest level), or null
     int sj0, sj1;
+    int n_bounce;                    // body resolved by bounce-back: nodes with a solid neighbour
+    const int32_t* bounce_node;      // i + nx * j
+    const int32_t* bounce_mask;      // bit q: the source x - c_q is solid
     double u_in_x, u_in_y, rho0;     // far-field data
 };
 
@@ -201,6 +209,10 @@ void launch_fv_fused(int prec, const KMesh& M, const void* fin, void* fout, cons
 void launch_wall_stats(int prec, const void* f, int n_wall, const double* nrm, double rho0, double inv_q, double* sum,
                        hipStream_t s);
 void launch_wall_stats_final(int n_wall, const double* sum, const int32_t* slot, double n, double* out, hipStream_t s);
+// momentum exchanged with a body resolved by bounce-back (finest level L, its
+// post-collision buffer A), as C_D, C_L into out[0..1]
+void launch_body_force(int prec, const KLevel& L, const void* A, double* out, double ca, double sa, double qn,
+                       hipStream_t s);
 void launch_wall_force(int prec, const void* f, int n_edges, const int32_t* wedge,
                        const double* wnorm, double* hist_slot, double cos_a, double sin_a, double qnorm,
                        hipStream_t s);

@@ -976,6 +976,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
 #pragma unroll
         for (int m = 0; m < kMacro; ++m) sp0[m] = prep0[sl + m], sp1[m] = prep1[sl + m];
     }
+    // two sub-steps in FP64: the edge records of this thread's first sub-step-1 node
+    // (tx + B if it has two, else tx) are loaded first, so that their latency
+    // overlaps the record loads (measured on the 264k-node mesh: -2% per launch in
+    // FP64, +3% in FP32, whose three waves per SIMD hide it already)
+    constexpr bool early = sizeof(T) == 8;
+    const int B = int(blockDim.x), tx = int(threadIdx.x);
+    const int n1 = meta[4];
+    const bool has1 = tx + B < n1, has0 = tx < n1;
+    EdgeRec<T> e[W], e0[W];
+    if (early && ksteps == 2 && has0) {
+        const int i = has1 ? tx + B : tx;
+#pragma unroll
+        for (int z = 0; z < W; ++z) e[z] = E[size_t(z) * width + i];
+    }
     // records of the tile and its rings: all loads of a batch in flight together
     constexpr int kBatch = 3;
     for (int i0 = 0; i0 < nload; i0 += kBatch * int(blockDim.x)) {
@@ -1010,28 +1024,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
         }
     }
     __syncthreads();
-    const int B = int(blockDim.x), tx = int(threadIdx.x);
     if (ksteps == 2) {
         // Sub-step 1 takes node tx + B first and node tx last, so that the edge
         // records of node tx (the same local node in both sub-steps) stay in
         // registers for sub-step 2, which takes node tx first.
-        const int n1 = meta[4];
         const T* const st1 = stg;
         const T* const st2 = stg + stj;
-        EdgeRec<T> e[W], e0[W];
         T r1[9], m1[3], r0[9], m0v[3];
-        const bool has1 = tx + B < n1, has0 = tx < n1;
         if (has1) {
+            if (!early) {
 #pragma unroll
-            for (int z = 0; z < W; ++z) e[z] = E[size_t(z) * width + tx + B];
+                for (int z = 0; z < W; ++z) e[z] = E[size_t(z) * width + tx + B];
+            }
             const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, st1, tx + B, e, r1, m1,
                                                     tx + B < ntile ? M.wmom : nullptr);
             if (mid && tx + B < ntile) store_rec(mid + size_t(P) * kRec, r1, m1[0], m1[1], m1[2]);
         }
         __builtin_amdgcn_sched_barrier(0);
         if (has0) {
+            if (has1 || !early) {
 #pragma unroll
-            for (int z = 0; z < W; ++z) e0[z] = E[size_t(z) * width + tx];
+                for (int z = 0; z < W; ++z) e0[z] = E[size_t(z) * width + tx];
+            } else {
+#pragma unroll
+                for (int z = 0; z < W; ++z) e0[z] = e[z];
+            }
             const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, st1, tx, e0, r0, m0v, tx < ntile ? M.wmom : nullptr);
             if (mid && tx < ntile) store_rec(mid + size_t(P) * kRec, r0, m0v[0], m0v[1], m0v[2]);
         }
@@ -1129,6 +1146,131 @@ __global__ __launch_bounds__(kWallForceThreads) void k_wall_force(const T* __res
     }
 }
 
+// ---- Body resolved by bounce-back (the standard LBM of eq. (14)) ----
+// The collide-stream kernels pull every direction from x - c_q; at the nodes
+// next to a solid body (a short list on the finest level) the directions whose
+// source is solid are redone here: f_q(x, t+1) = f~_{-q}(x, t), the node's own
+// post-collision population of the opposite direction (halfway bounce-back).
+
+constexpr int kOpposite[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+// Streamed populations of bounce-back node b (interior of the level: the plan
+// keeps the body 6 nodes from its edges, so no far-field or periodic source).
+template <typename T>
+__device__ __forceinline__ void bounce_pull(const KLevel& L, const T* __restrict__ A, int b, int& i, int& j,
+                                            T (&f)[9]) {
+    const int id = L.bounce_node[b], mask = L.bounce_mask[b];
+    i = id % L.nx;
+    j = id / L.nx;
+    const size_t base = size_t(j) * size_t(L.rs) + i;
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        f[q] = (mask >> q) & 1 ? A[size_t(kOpposite[q]) * L.pitch + base]
+                               : A[size_t(q) * L.pitch + base - ptrdiff_t(CY[q]) * L.rs - CX[q]];
+}
+
+// Collide-stream of the bounce-back nodes, after the level's kernel: B = collide(stream(A)).
+template <typename T, bool SHIFT>
+__global__ __launch_bounds__(256) void k_bounce(const KLevel L, const T* __restrict__ A, T* __restrict__ B) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= L.n_bounce) return;
+    int i, j;
+    T f[9], feq[9], rho, dr, ux, uy, o[9];
+    bounce_pull(L, A, b, i, j, f);
+    const T omega = T(L.omega), rho0 = T(L.rho0);
+    macro<T, SHIFT>(f, rho0, rho, dr, ux, uy);
+    equilibrium<T, SHIFT>(rho, dr, ux, uy, feq);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) o[q] = f[q] - (f[q] - feq[q]) * omega;
+    if constexpr (SHIFT && sizeof(T) == 4) conserve_f32(f, o);
+    const size_t base = size_t(j) * size_t(L.rs) + i;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) B[size_t(q) * L.pitch + base] = o[q];
+}
+
+// Canonical export of the bounce-back nodes in rows [j0, j1) (after k_export_level).
+template <typename T, bool SHIFT>
+__global__ void k_bounce_export(const KLevel L, const T* __restrict__ A, double* __restrict__ out, int j0, int j1) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= L.n_bounce) return;
+    const int jb = L.bounce_node[b] / L.nx;
+    if (jb < j0 || jb >= j1) return;
+    int i, j;
+    T f[9];
+    bounce_pull(L, A, b, i, j, f);
+    const size_t rows = size_t(j1 - j0), o = size_t(j - j0) * L.nx + i;
+    for (int q = 0; q < 9; ++q) out[q * rows * L.nx + o] = to_phys<T, SHIFT>(f[q], q, L.rho0);
+}
+
+// Canonical import of the bounce-back nodes in rows [j0, j1) (after
+// k_import_level): a bounced f_q(x) goes to the opposite direction at x itself,
+// which no other node pulls (its source would be the solid node x - c_q).
+template <typename T, bool SHIFT>
+__global__ void k_bounce_import(const KLevel L, T* __restrict__ A, const double* __restrict__ in, int j0, int j1) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= L.n_bounce) return;
+    const int id = L.bounce_node[b], mask = L.bounce_mask[b];
+    const int i = id % L.nx, j = id / L.nx;
+    if (j < j0 || j >= j1) return;
+    const size_t rows = size_t(j1 - j0), o = size_t(j - j0) * L.nx + i;
+    for (int q = 1; q < 9; ++q)
+        if ((mask >> q) & 1)   // w_q = w_{-q}: the stored form is the same
+            A[lidx(L, kOpposite[q], i, j)] = to_store<T, SHIFT>(in[q * rows * L.nx + o], q, L.rho0);
+}
+
+// The uniform start f^eq(rho, u) as the bounce-back nodes pull it (after k_fill_uniform).
+template <typename T, bool SHIFT>
+__global__ void k_bounce_uniform(const KLevel L, T* __restrict__ A, double rho, double ux, double uy) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= L.n_bounce) return;
+    const int id = L.bounce_node[b], mask = L.bounce_mask[b];
+    const int i = id % L.nx, j = id / L.nx;
+    for (int q = 1; q < 9; ++q) {
+        if (!((mask >> q) & 1)) continue;
+        const double cu = CX[q] * ux + CY[q] * uy, uu = ux * ux + uy * uy;
+        const double fe = wgt<double>(q) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        A[lidx(L, kOpposite[q], i, j)] = to_store<T, SHIFT>(fe, q, L.rho0);
+    }
+}
+
+// Force on the body by momentum exchange, in FP64, one block in a fixed order:
+// each f~_p that left a bounce-back node towards the body (x + c_p solid)
+// returns reversed and gives it 2 c_p f~_p.  Shifted storage drops the rest
+// part 2 c_p w_p rho0, whose sum over the links of a closed body is zero (as
+// many links leave the body in each direction as enter it).
+template <typename T, bool SHIFT>
+__global__ __launch_bounds__(kWallForceThreads) void k_body_force(const KLevel L, const T* __restrict__ A,
+                                                                  double* __restrict__ out, double ca, double sa,
+                                                                  double qn) {
+    __shared__ double sx[kWallForceThreads], sy[kWallForceThreads];
+    double ax = 0, ay = 0;
+    for (int b = threadIdx.x; b < L.n_bounce; b += kWallForceThreads) {
+        const int id = L.bounce_node[b], mask = L.bounce_mask[b];
+        const size_t base = size_t(id / L.nx) * size_t(L.rs) + id % L.nx;
+        for (int q = 1; q < 9; ++q) {
+            if (!((mask >> q) & 1)) continue;
+            const int p = kOpposite[q];
+            const double v = double(A[size_t(p) * L.pitch + base]);
+            ax += 2.0 * CX[p] * v;
+            ay += 2.0 * CY[p] * v;
+        }
+    }
+    sx[threadIdx.x] = ax;
+    sy[threadIdx.x] = ay;
+    __syncthreads();
+    for (int h = kWallForceThreads / 2; h > 0; h >>= 1) {
+        if (int(threadIdx.x) < h) {
+            sx[threadIdx.x] += sx[threadIdx.x + h];
+            sy[threadIdx.x] += sy[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = (sx[0] * ca + sy[0] * sa) / qn;
+        out[1] = (-sx[0] * sa + sy[0] * ca) / qn;
+    }
+}
+
 // [9][nn] FP64 populations -> mesh records (stored form plus moments)
 template <typename T, bool SHIFT>
 __global__ void k_mesh_convert(int nn, const double* __restrict__ in, T* __restrict__ out, double rho0) {
@@ -1179,6 +1321,8 @@ constexpr unsigned kSmallBlock = 64;
 
 void launch_fill_uniform(int prec, void* buf, const KLevel& L, double rho, double ux, double uy, hipStream_t s) {
     HLBM_DISPATCH(prec, (k_fill_uniform<T, S><<<blocks(size_t(L.ny) * size_t(L.rs)), 256, 0, s>>>(L, (T*)buf, rho, ux, uy)));
+    if (L.n_bounce > 0)
+        HLBM_DISPATCH(prec, (k_bounce_uniform<T, S><<<blocks(L.n_bounce), 256, 0, s>>>(L, (T*)buf, rho, ux, uy)));
 }
 
 void launch_stream_collide(int prec, const KLevel& L, const void* A, void* B, hipStream_t s) {
@@ -1191,16 +1335,27 @@ void launch_stream_collide(int prec, const KLevel& L, const void* A, void* B, hi
     }
     if (L.farfield)
         HLBM_DISPATCH(prec, (k_edges<T, S><<<blocks(2 * size_t(L.nx) + 2 * size_t(L.ny - 2), kSmallBlock), kSmallBlock, 0, s>>>(L, (const T*)A, (T*)B)));
+    if (L.n_bounce > 0)
+        HLBM_DISPATCH(prec, (k_bounce<T, S><<<blocks(L.n_bounce), 256, 0, s>>>(L, (const T*)A, (T*)B)));
+}
+
+void launch_body_force(int prec, const KLevel& L, const void* A, double* out, double ca, double sa, double qn,
+                       hipStream_t s) {
+    HLBM_DISPATCH(prec, (k_body_force<T, S><<<1, kWallForceThreads, 0, s>>>(L, (const T*)A, out, ca, sa, qn)));
 }
 
 void launch_export_level(int prec, const KLevel& L, const void* A, double* out, int j0, int j1, hipStream_t s) {
     dim3 grid(blocks(L.nx), j1 - j0);
     HLBM_DISPATCH(prec, (k_export_level<T, S><<<grid, 256, 0, s>>>(L, (const T*)A, out, j0, j1)));
+    if (L.n_bounce > 0)
+        HLBM_DISPATCH(prec, (k_bounce_export<T, S><<<blocks(L.n_bounce), 256, 0, s>>>(L, (const T*)A, out, j0, j1)));
 }
 
 void launch_import_level(int prec, const KLevel& L, void* A, const double* in, int j0, int j1, hipStream_t s) {
     dim3 grid(blocks(L.nx), j1 - j0);
     HLBM_DISPATCH(prec, (k_import_level<T, S><<<grid, 256, 0, s>>>(L, (T*)A, in, j0, j1)));
+    if (L.n_bounce > 0)
+        HLBM_DISPATCH(prec, (k_bounce_import<T, S><<<blocks(L.n_bounce), 256, 0, s>>>(L, (T*)A, in, j0, j1)));
 }
 
 void launch_side_init(int prec, const KLevel& P, int ci0, int cj0, int nxc, int nyc, const void* A, void* side, hipStream_t s) {

@@ -32,6 +32,22 @@ namespace {
 constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
+// Is (x, y) inside the polygon: crossing number of the ray towards +x, an edge
+// counted when exactly one of its end points has y' <= y, odd = inside.  No
+// floating-point contraction, so the crossing abscissae round as written.
+bool polygon_contains(int n, const double* xy, double x, double y) {
+#pragma clang fp contract(off)
+    bool in = false;
+    for (int e = 0; e < n; ++e) {
+        const double* a = xy + 2 * e;
+        const double* b = xy + 2 * ((e + 1) % n);
+        if ((a[1] <= y) == (b[1] <= y)) continue;
+        const double xc = a[0] + (y - a[1]) * (b[0] - a[0]) / (b[1] - a[1]);
+        if (x < xc) in = !in;
+    }
+    return in;
+}
+
 // Forward-mode dual number: value and derivative along one seeded input.  The
 // geometry and stencil code below is written once for a scalar type S and
 // evaluated with S = double (the plan) and S = Dual (derivatives of the
@@ -629,6 +645,7 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
     p = Plan();
     p.has_grid = g->nx_cells > 0 && g->ny_cells > 0;
     p.has_mesh = m && m->n_nodes > 0;
+    p.has_body = m && m->body_n > 0;
     if (!p.has_grid) return fail(err, HLBM_E_ARG, "a structured grid is required");
     if (g->n_refine < 0 || g->n_refine > 3) return fail(err, HLBM_E_ARG, "n_refine must be 0..3");
     if (g->precision != HLBM_FP64 && g->precision != HLBM_FP32_SHIFTED) return fail(err, HLBM_E_ARG, "bad precision");
@@ -645,7 +662,7 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
     p.u_inf = g->u_inf;
     p.aoa = g->aoa_rad;
     p.rho0 = g->rho0;
-    p.chord = p.has_mesh ? m->chord : 1.0;
+    p.chord = p.has_mesh || p.has_body ? m->chord : 1.0;
     p.check_every = std::max(0, g->check_every);
     if (g->f2c_filter != 0 && g->f2c_filter != 1) return fail(err, HLBM_E_ARG, "f2c_filter must be 0 or 1");
     p.f2c_filter = g->f2c_filter;
@@ -712,23 +729,39 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
         v.pitch = (v.nx + al - 1) / al * al;
     }
     LevelPlan& fl = p.lev[p.L];
-    // ---- inner ellipse: inactive nodes of the finest level (one span per row)
+    // ---- inner ellipse, or a body resolved by bounce-back: inactive nodes of the
+    // finest level (one span per row)
     const bool has_ein = p.has_mesh && m->inner_ellipse[2] > 0 && m->inner_ellipse[3] > 0;
-    std::vector<uint8_t> inside;   // finest level, 1 = strictly inside the inner ellipse
-    if (has_ein) {
-        const double xc = m->inner_ellipse[0], yc = m->inner_ellipse[1];
-        const double ea = m->inner_ellipse[2], eb = m->inner_ellipse[3];
+    std::vector<uint8_t> inside;   // finest level, 1 = strictly inside the inner ellipse or the body
+    if (p.has_body) {
+        if (p.has_mesh || (m->inner_ellipse[2] > 0 && m->inner_ellipse[3] > 0))
+            return fail(err, HLBM_E_ARG, "a body resolved by bounce-back excludes a mesh and an inner ellipse");
+        if (m->body_n < 3 || !m->body_xy) return fail(err, HLBM_E_ARG, "the body needs at least 3 vertices");
+    }
+    if (has_ein || p.has_body) {
         inside.assign(size_t(fl.nx) * fl.ny, 0);
         int jmin = fl.ny, jmax = -1;
         for (int j = 0; j < fl.ny; ++j)
             for (int i = 0; i < fl.nx; ++i) {
-                const double dx = (fl.ox + i * fl.sp - xc) / ea, dy = (fl.oy + j * fl.sp - yc) / eb;
-                if (dx * dx + dy * dy < 1.0) {
+                const double x = fl.ox + i * fl.sp, y = fl.oy + j * fl.sp;
+                bool in;
+                if (has_ein) {
+                    const double dx = (x - m->inner_ellipse[0]) / m->inner_ellipse[2];
+                    const double dy = (y - m->inner_ellipse[1]) / m->inner_ellipse[3];
+                    in = dx * dx + dy * dy < 1.0;
+                } else {
+                    in = polygon_contains(m->body_n, m->body_xy, x, y);
+                }
+                if (in) {
                     inside[size_t(j) * fl.nx + i] = 1;
                     jmin = std::min(jmin, j);
                     jmax = std::max(jmax, j);
                 }
             }
+        if (p.has_body && jmax < 0) return fail(err, HLBM_E_GEOMETRY, "the body covers no node of the finest level");
+        // the body keeps clear of the finest level's edge by 6 nodes: the refinement
+        // transfers and the far-field conditions read there without bounce-back
+        const int margin = p.has_body ? 6 : 2;
         if (jmax >= 0) {
             fl.sj0 = jmin;
             fl.sj1 = jmax + 1;
@@ -741,8 +774,9 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
                         hi = i + 1;
                     }
                 if (lo < 0) lo = hi = 0;
-                if (lo < 2 || hi > fl.nx - 2 || j < 2 || j > fl.ny - 3)
-                    return fail(err, HLBM_E_GEOMETRY, "inner ellipse too close to the edge of the finest level");
+                if (lo < margin || hi > fl.nx - margin || j < margin || j > fl.ny - 1 - margin)
+                    return fail(err, HLBM_E_GEOMETRY, p.has_body ? "the body is too close to the edge of the finest level"
+                                                                 : "inner ellipse too close to the edge of the finest level");
                 p.spans.push_back(lo);
                 p.spans.push_back(hi);
             }
@@ -756,6 +790,19 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
         if (l == p.L && !inside.empty() && inside[size_t(j) * v.nx + i]) return false;
         return true;
     };
+    if (p.has_body) {   // bounce-back links of the collide-stream nodes next to the body
+        for (int j = std::max(1, fl.sj0 - 1); j <= std::min(fl.ny - 2, fl.sj1); ++j)
+            for (int i = 1; i < fl.nx - 1; ++i) {
+                if (!collide_node(p.L, i, j)) continue;
+                int mask = 0;
+                for (int q = 1; q < 9; ++q)
+                    if (inside[size_t(j - kCy[q]) * fl.nx + (i - kCx[q])]) mask |= 1 << q;
+                if (!mask) continue;
+                p.bounce_node.push_back(i + fl.nx * j);
+                p.bounce_mask.push_back(mask);
+            }
+        for (uint8_t v : inside) p.n_solid += v;
+    }
     for (int l = 0; l <= p.L; ++l) {
         const LevelPlan& v = p.lev[l];
         int64_t n = int64_t(v.nx) * v.ny;
@@ -955,6 +1002,8 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
         p.off.side[l][1] = take(nb * kMacro * E);
     }
     p.off.spans = take(p.spans.size() * 4);
+    p.off.bounce_node = take(p.bounce_node.size() * 4);
+    p.off.bounce_mask = take(p.bounce_mask.size() * 4);
     const size_t ns = p.sint_node.size();
     p.off.sint_node = take(ns * 4);
     p.off.sint_don = take(ns * kSDon * 4);

@@ -58,6 +58,7 @@ class Mesh(C.Structure):
         ("xy", C.POINTER(C.c_double)), ("tri", C.POINTER(C.c_int32)), ("kind", C.POINTER(C.c_uint8)),
         ("chord", C.c_double), ("inner_ellipse", C.c_double * 4),
         ("n_shape", C.c_int32), ("dxy_dshape", C.POINTER(C.c_double)),
+        ("body_n", C.c_int32), ("body_xy", C.POINTER(C.c_double)),
     ]
 
 
@@ -78,6 +79,7 @@ class Info(C.Structure):
         ("fv_bytes", C.c_int64), ("t", C.c_int64), ("workspace_bytes", C.c_size_t),
         ("fv_fuse", C.c_int32), ("fv_tiles", C.c_int32), ("fv_tile_nodes", C.c_int32),
         ("fv_threads", C.c_int32), ("fv_layout_bytes", C.c_int64),
+        ("n_solid", C.c_int32), ("n_bounce", C.c_int32),
     ]
 
 
@@ -128,12 +130,13 @@ def _np_ptr(a):
 def make_structs(nx_cells, ny_cells, patches=(), *, u_inf=0.05, aoa_rad=0.0, rho0=1.0,
                  precision=FP64, interp=INTERP_QUADRATIC, n_sub=0, periodic=False, wall_bc=True,
                  check_every=0, history_len=0, fv_fuse=0, mesh_xy=None, mesh_tri=None, mesh_kind=None,
-                 chord=1.0, inner_ellipse=None, dxy_dshape=None, f2c_filter=False):
+                 chord=1.0, inner_ellipse=None, dxy_dshape=None, f2c_filter=False, body_xy=None):
     """ctypes Grid and Mesh (plus the arrays they point into, kept alive).
 
     dxy_dshape: optional [n_shape, n_nodes, 2] derivatives of the node
     coordinates with respect to shape parameters; the adjoint then returns
-    dJ/d(parameter) for each of them."""
+    dJ/d(parameter) for each of them.  body_xy: optional [n, 2] polygon of a
+    solid body resolved on the finest level by bounce-back (no mesh)."""
     g = Grid()
     g.nx_cells, g.ny_cells, g.n_refine = nx_cells, ny_cells, len(patches)
     for k, (i0, j0, px, py) in enumerate(patches):
@@ -160,6 +163,11 @@ def make_structs(nx_cells, ny_cells, patches=(), *, u_inf=0.05, aoa_rad=0.0, rho
             keep.append(d)
             m.n_shape = d.shape[0]
             m.dxy_dshape = d.ctypes.data_as(C.POINTER(C.c_double))
+    if body_xy is not None:
+        bxy = np.ascontiguousarray(body_xy, dtype=np.float64).reshape(-1, 2)
+        keep.append(bxy)
+        m.body_n = bxy.shape[0]
+        m.body_xy = bxy.ctypes.data_as(C.POINTER(C.c_double))
     m.chord = chord
     ein = inner_ellipse if inner_ellipse is not None else (0.0, 0.0, 0.0, 0.0)
     for k in range(4):
@@ -170,7 +178,7 @@ def make_structs(nx_cells, ny_cells, patches=(), *, u_inf=0.05, aoa_rad=0.0, rho
 def structs_from_workload(w, **over):
     kw = dict(u_inf=w.u_inf, aoa_rad=w.aoa_rad, rho0=w.rho0, periodic=w.periodic, n_sub=w.n_sub,
               mesh_xy=w.mesh_xy, mesh_tri=w.mesh_tri, mesh_kind=w.mesh_kind, chord=w.chord,
-              inner_ellipse=w.inner_ellipse, f2c_filter=w.f2c_filter)
+              inner_ellipse=w.inner_ellipse, f2c_filter=w.f2c_filter, body_xy=w.body_xy)
     kw.update(over)
     return make_structs(w.nx_cells, w.ny_cells, w.patches, **kw)
 

@@ -6,12 +6,13 @@ as the unstructured mesh does.  Here both times are measured on the GPU:
 
 * T_h: one base-level step of the workload (every level, the coupling and the
   n FV sub-steps of each finest step), from a timed run of hlbm_step;
-* T_eq: one base-level step (the same physical time) of the equivalent LBM:
-  the same structured levels plus one more nested box of half the finest
-  spacing over the finest box (inset by a margin), no mesh.  Its finest
-  spacing is half a lattice unit, the wall spacing of the workloads' meshes.
-  The body itself is not represented: in a pull-streaming kernel a
-  bounce-back mask adds no traffic, so this is a lower bound of T_eq.
+* T_eq: one base-level step (the same physical time) of the equivalent LBM
+  (workloads.equivalent_lbm): the same structured levels plus one more nested
+  box of half the finest spacing over the finest box (inset by a margin), no
+  mesh, the profile resolved on that box by halfway bounce-back with the
+  force by momentum exchange every finest step.  Its finest spacing is half a
+  lattice unit, the wall spacing of the workloads' meshes.  The same grid
+  without the body is timed too (t_eq_nobody): the cost of the body itself.
 
 The model's inputs are measured on the same runs: chi = FV node updates over
 structured node updates per base step (without n), g = structured node
@@ -26,26 +27,11 @@ prints one JSON object.
 from __future__ import annotations
 
 import argparse
-import dataclasses
 import json
 import sys
 import time
 
 from . import hlbm, workloads
-
-
-def equivalent_lbm(w: workloads.Workload, margin: int = 8) -> workloads.Workload:
-    """w's structured grid with one more box of half the finest spacing over w's finest
-    box (inset by `margin` cells of that box on every side) and no mesh.  Lengths are
-    in the new finest units, so the chord doubles and Re, U (hence tau from Re) hold."""
-    if w.patches:
-        px, py = w.patches[-1][2], w.patches[-1][3]
-    else:
-        px, py = w.nx_cells, w.ny_cells
-    box = (margin, margin, 2 * (px - 2 * margin), 2 * (py - 2 * margin))
-    return dataclasses.replace(
-        w, name=w.name + "_equivalent_lbm", patches=list(w.patches) + [box], chord=2.0 * w.chord,
-        mesh_xy=None, mesh_tri=None, mesh_kind=None, inner_ellipse=(0.0, 0.0, 0.0, 0.0), omesh=None, n_sub=0)
 
 
 def updates_per_base_step(info) -> int:
@@ -84,11 +70,16 @@ def main(argv=None):
     ups_h = updates_per_base_step(info)
     sim.close()
 
-    e = equivalent_lbm(w)
+    e = workloads.equivalent_lbm(w)
     sim = hlbm.HLBM.from_workload(e, precision=prec)
     einfo = sim.info
     t_eq = time_base_steps(sim, 2 ** (einfo.n_levels - 1), a.steps, a.warmup)
     ups_eq = updates_per_base_step(einfo)
+    n_solid, n_bounce = int(einfo.n_solid), int(einfo.n_bounce)
+    cd_eq = float(sim.history()[0][-1])
+    sim.close()
+    sim = hlbm.HLBM.from_workload(workloads.equivalent_lbm(w, body=False), precision=prec)
+    t_eq_nobody = time_base_steps(sim, 2 ** (sim.info.n_levels - 1), a.steps, a.warmup)
     sim.close()
 
     fv_ups = n_mesh * (2 ** L)                       # FV node updates per base step, without n
@@ -98,7 +89,9 @@ def main(argv=None):
     out = {
         "workload": w.name, "equivalent": e.name, "precision": "fp64" if a.fp64 else "fp32_shifted",
         "t_h_ms_per_base_step": round(1e3 * t_h, 4), "t_eq_ms_per_base_step": round(1e3 * t_eq, 4),
+        "t_eq_nobody_ms_per_base_step": round(1e3 * t_eq_nobody, 4),
         "G_measured": round(t_h / t_eq, 4),
+        "equivalent_body": {"solid_nodes": n_solid, "bounce_back_nodes": n_bounce, "cd_last": cd_eq},
         "model": {"chi": chi, "n": n_sub, "s_prime": round(s_prime, 3), "g": round(g, 4),
                   "G": round((1.0 + chi * s_prime * n_sub) / g, 4)},
         "structured_updates_per_base_step": {"hybrid": ups_h, "equivalent": ups_eq},

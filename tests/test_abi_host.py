@@ -33,8 +33,9 @@ def test_header_symbols_exported(lib):
 def test_struct_sizes_match_header(lib):
     # hlbm_grid: 15 int32 (60 B, padded to 64), 3 doubles, 9 int32 (36 B, padded to 40)
     assert C.sizeof(hlbm.Grid) == 64 + 3 * 8 + 40
-    # hlbm_mesh: 2 int32, 3 pointers, 5 doubles, int32 n_shape (padded to 8), 1 pointer
-    assert C.sizeof(hlbm.Mesh) == 4 + 4 + 3 * 8 + 8 + 32 + 8 + 8
+    # hlbm_mesh: 2 int32, 3 pointers, 5 doubles, int32 n_shape (padded to 8), 1 pointer,
+    # int32 body_n (padded to 8), 1 pointer
+    assert C.sizeof(hlbm.Mesh) == 4 + 4 + 3 * 8 + 8 + 32 + 8 + 8 + 8 + 8
 
 
 def test_struct_layouts_match_compiled_header(tmp_path):
@@ -145,12 +146,14 @@ def test_workloads_validate(lib):
 
 def test_equivalent_lbm_workload(lib):
     """The eq. (14) comparison grid: one more box of half spacing over the finest box, no mesh,
-    the same Reynolds number (chord doubled in the new finest units)."""
-    from paper_2006_10487_amd.speedup import equivalent_lbm
+    the same Reynolds number (chord doubled in the new finest units), the profile's wall
+    points doubled as the body polygon."""
     for name in ("naca_re1000_c128", "naca_re5000_c512"):
         w = W.PRESETS[name]()
-        e = equivalent_lbm(w)
+        e = W.equivalent_lbm(w)
         assert e.n_refine == w.n_refine + 1 and e.mesh_xy is None and e.chord == 2 * w.chord
+        assert np.array_equal(e.body_xy, 2.0 * w.omesh.xy[w.omesh.surface_index])
+        assert W.equivalent_lbm(w, body=False).body_xy is None
         px, py = w.patches[-1][2], w.patches[-1][3]
         assert e.patches[-1] == (8, 8, 2 * (px - 16), 2 * (py - 16))
         assert abs((e.tau_s - 0.5) - 2 * (w.tau_s - 0.5)) < 1e-12
@@ -174,3 +177,22 @@ def test_strouhal_of_sinusoid():
     st = hlbm.strouhal(cl, chord=128.0, u_inf=0.05)
     assert abs(st - 128.0 / (0.05 * period)) < 1e-6 * st
     assert math.isnan(hlbm.strouhal(np.full(100, 0.1), 128.0, 0.05))
+
+
+def test_body_option_validation(lib):
+    """A body resolved by bounce-back: accepted without a mesh, rejected with one,
+    near the edge of the finest level, or covering no node (host checks only)."""
+    import dataclasses
+    e = W.equivalent_lbm(W.naca_re100_c40_refined(0.0))
+    g, m, keep = hlbm.structs_from_workload(e)
+    assert hlbm.validate(g, m, 0.0, e.tau_s) == 0
+    w = W.naca_re100_c40_refined(0.0)
+    g, m, keep = hlbm.structs_from_workload(w, body_xy=2.0 * w.omesh.xy[w.omesh.surface_index])
+    assert hlbm.validate(g, m, 0.0, w.tau_s) == -1
+    ox = e.patches[0][0] * 4 + e.patches[1][0] * 2   # finest-level origin (finest lu)
+    shifted = dataclasses.replace(e, body_xy=e.body_xy + np.array([ox + 3.0 - e.body_xy[:, 0].min(), 0.0]))
+    g, m, keep = hlbm.structs_from_workload(shifted)
+    assert hlbm.validate(g, m, 0.0, e.tau_s) == -2
+    tiny = dataclasses.replace(e, body_xy=np.array([[300.2, 100.2], [300.6, 100.2], [300.4, 100.6]]))
+    g, m, keep = hlbm.structs_from_workload(tiny)
+    assert hlbm.validate(g, m, 0.0, e.tau_s) == -2

@@ -1,0 +1,131 @@
+"""GPU parity of the standard LBM with the body resolved by halfway bounce-back
+(the comparison scheme of eq. (14)) against the FP64 CPU oracle.
+
+The case is the refined Re 100 profile with one more box at half its finest
+spacing over the finest box and no mesh (workloads.equivalent_lbm): three
+levels, the profile a polygon on the finest.  FP64 bar as for the hybrid
+scheme: every level's state within 1e-11 (infinity norm, relative) and C_D,
+C_L within 1e-10; FP32-shifted storage within the bars written in the test.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from flowfields import feq_field
+from oracle import oracle as O
+from paper_2006_10487_amd import hlbm, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hlbm.lib()
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def compare(sim, ref):
+    out = {f"level{l}": rel(sim.get_state(l), ref.get_level(l)) for l in range(ref.n_levels)}
+    cd, cl = sim.history()
+    cdr, clr = ref.history()
+    assert len(cd) == len(cdr)
+    out["cd"] = float(np.abs(cd - cdr).max()) if len(cd) else 0.0
+    out["cl"] = float(np.abs(cl - clr).max()) if len(cl) else 0.0
+    print("bounce-back parity:", out, flush=True)
+    return out
+
+
+@pytest.mark.parametrize("aoa_deg", [4.0, -9.0])
+def test_bounce_back_fp64_matches_oracle(aoa_deg):
+    e = W.equivalent_lbm(W.naca_re100_c40_refined(aoa_deg))
+    sim = hlbm.HLBM.from_workload(e)
+    ref = O.Oracle.from_workload(e)
+    L = ref.n_levels - 1
+    assert sim.info.n_solid == int((ref.level_class(L) == 6).sum()) > 400
+    assert sim.info.n_bounce > 0 and sim.info.n_mesh_nodes == 0
+    assert [sim.info.active_nodes[l] for l in range(L + 1)] == \
+        [int((ref.level_class(l) == 0).sum()) for l in range(L + 1)]
+    for n in (4, 156):
+        sim.step(n)
+        ref.step(n)
+        err = compare(sim, ref)
+        assert max(err[f"level{l}"] for l in range(L + 1)) < TOL
+        assert err["cd"] < 1e-10 and err["cl"] < 1e-10
+    cd, _ = sim.history()
+    assert cd[-1] > 0.3
+
+
+def test_bounce_back_state_import():
+    """A state imported at t = 0 (every level, the bounced directions of the nodes
+    next to the body included) runs as in the oracle.  The perturbation of the
+    free stream vanishes within four base nodes of the far field, whose edge
+    nodes the import derives from the boundary conditions."""
+    e = W.equivalent_lbm(W.naca_re100_c40_refined(0.0))
+    sim = hlbm.HLBM.from_workload(e)
+    ref = O.Oracle.from_workload(e)
+    sp = 4
+    ox = oy = 0.0
+    width, height = 4 * e.nx_cells, 4 * e.ny_cells
+
+    def window(v, length):
+        s = np.clip((v - 16.0) / (length - 32.0), 0.0, 1.0)
+        return np.sin(math.pi * s) ** 2
+
+    for l in range(ref.n_levels):
+        if l > 0:
+            ox, oy = ox + e.patches[l - 1][0] * sp, oy + e.patches[l - 1][1] * sp
+            sp //= 2
+        ny, nx = ref.level_shape[l]
+        X, Y = np.meshgrid(ox + np.arange(nx) * sp, oy + np.arange(ny) * sp)
+        bump = window(X, width) * window(Y, height)
+        ux = e.u_inf * (1.0 + 0.2 * bump * np.sin(2 * math.pi * X / 173.0) * np.cos(2 * math.pi * Y / 91.0))
+        uy = 0.01 * bump * np.cos(2 * math.pi * X / 67.0)
+        rho = 1.0 + 0.001 * bump * np.sin(2 * math.pi * Y / 53.0)
+        f = feq_field(O.equilibrium, rho, ux, uy)
+        ref.set_level(l, f)
+        sim.set_state(l, f)
+    err = compare(sim, ref)   # export of the imported state, bounced directions included
+    assert max(err[f"level{l}"] for l in range(ref.n_levels)) < TOL
+    sim.step(60)
+    ref.step(60)
+    err = compare(sim, ref)
+    assert max(err[f"level{l}"] for l in range(ref.n_levels)) < TOL
+    assert err["cd"] < 1e-10 and err["cl"] < 1e-10
+
+
+def test_bounce_back_symmetry_fp64():
+    """alpha = 0: the solid nodes and the grid are mirror symmetric, so C_L vanishes."""
+    e = W.equivalent_lbm(W.naca_re100_c40_refined(0.0))
+    sim = hlbm.HLBM.from_workload(e)
+    sim.step(200)
+    cd, cl = sim.history()
+    assert np.abs(cl).max() < 1e-12 and cd[-1] > 0.3
+
+
+def test_bounce_back_fp32_shifted_against_oracle():
+    """FP32-shifted storage against the FP64 oracle over 400 steps (C_D, C_L and
+    the finest level's velocity field)."""
+    e = W.equivalent_lbm(W.naca_re100_c40_refined(4.0))
+    sim = hlbm.HLBM.from_workload(e, precision=hlbm.FP32_SHIFTED)
+    ref = O.Oracle.from_workload(e)
+    sim.step(400)
+    ref.step(400)
+    cd, cl = sim.history()
+    cdr, clr = ref.history()
+    dcd = float(np.abs(cd - cdr).max() / np.abs(cdr).max())
+    dcl = float(np.abs(cl - clr).max() / np.abs(cdr).max())
+    L = ref.n_levels - 1
+    g, r = sim.get_state(L), ref.get_level(L)
+    du = float(np.abs((g - r)[1:]).max() / np.abs(r[1:]).max())
+    print(f"FP32 bounce-back: C_D {dcd:.2e}, C_L {dcl:.2e} (over max C_D), finest populations {du:.2e}")
+    assert dcd < 1e-5 and dcl < 1e-5 and du < 1e-5
