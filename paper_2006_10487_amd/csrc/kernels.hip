@@ -976,20 +976,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
 #pragma unroll
         for (int m = 0; m < kMacro; ++m) sp0[m] = prep0[sl + m], sp1[m] = prep1[sl + m];
     }
-    // two sub-steps in FP64: the edge records of this thread's first sub-step-1 node
-    // (tx + B if it has two, else tx) are loaded first, so that their latency
-    // overlaps the record loads (measured on the 264k-node mesh: -2% per launch in
-    // FP64, +3% in FP32, whose three waves per SIMD hide it already)
-    constexpr bool early = sizeof(T) == 8;
-    const int B = int(blockDim.x), tx = int(threadIdx.x);
-    const int n1 = meta[4];
-    const bool has1 = tx + B < n1, has0 = tx < n1;
-    EdgeRec<T> e[W], e0[W];
-    if (early && ksteps == 2 && has0) {
-        const int i = has1 ? tx + B : tx;
-#pragma unroll
-        for (int z = 0; z < W; ++z) e[z] = E[size_t(z) * width + i];
-    }
     // records of the tile and its rings: all loads of a batch in flight together
     constexpr int kBatch = 3;
     for (int i0 = 0; i0 < nload; i0 += kBatch * int(blockDim.x)) {
@@ -1024,31 +1010,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWave
         }
     }
     __syncthreads();
+    const int B = int(blockDim.x), tx = int(threadIdx.x);
     if (ksteps == 2) {
         // Sub-step 1 takes node tx + B first and node tx last, so that the edge
         // records of node tx (the same local node in both sub-steps) stay in
         // registers for sub-step 2, which takes node tx first.
+        const int n1 = meta[4];
         const T* const st1 = stg;
         const T* const st2 = stg + stj;
+        EdgeRec<T> e[W], e0[W];
         T r1[9], m1[3], r0[9], m0v[3];
+        const bool has1 = tx + B < n1, has0 = tx < n1;
         if (has1) {
-            if (!early) {
 #pragma unroll
-                for (int z = 0; z < W; ++z) e[z] = E[size_t(z) * width + tx + B];
-            }
+            for (int z = 0; z < W; ++z) e[z] = E[size_t(z) * width + tx + B];
             const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, st1, tx + B, e, r1, m1,
                                                     tx + B < ntile ? M.wmom : nullptr);
             if (mid && tx + B < ntile) store_rec(mid + size_t(P) * kRec, r1, m1[0], m1[1], m1[2]);
         }
         __builtin_amdgcn_sched_barrier(0);
         if (has0) {
-            if (has1 || !early) {
 #pragma unroll
-                for (int z = 0; z < W; ++z) e0[z] = E[size_t(z) * width + tx];
-            } else {
-#pragma unroll
-                for (int z = 0; z < W; ++z) e0[z] = e[z];
-            }
+            for (int z = 0; z < W; ++z) e0[z] = E[size_t(z) * width + tx];
             const int P = fv_tile_node<T, SHIFT, W>(M, buf, gid, st1, tx, e0, r0, m0v, tx < ntile ? M.wmom : nullptr);
             if (mid && tx < ntile) store_rec(mid + size_t(P) * kRec, r0, m0v[0], m0v[1], m0v[2]);
         }
