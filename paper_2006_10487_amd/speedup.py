@@ -22,11 +22,15 @@ timings of the finest collide-stream and the FV sub-step).
 
     python -m paper_2006_10487_amd.speedup --workload naca_re5000_c512 --steps 20
 
-prints one JSON object.
+prints one JSON object.  With --accuracy-steps N (and optionally --aoa) both
+schemes also run N finest steps of the hybrid scheme (2N of the equivalent
+LBM, the same physical time) from the initial state, and the object gains the
+mean C_D and C_L of each over the second half.
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import sys
 import time
@@ -49,15 +53,47 @@ def time_base_steps(sim, per: int, steps: int, warmup: int) -> float:
     return (time.perf_counter() - t0) / steps
 
 
+def mean_forces(w, prec, finest_steps):
+    """Mean C_D, C_L over the second half of finest_steps steps from the initial state."""
+    import torch
+    sim = hlbm.HLBM.from_workload(w, precision=prec, history_len=finest_steps + 8)
+    per = 2 ** (sim.info.n_levels - 1)
+    n = finest_steps // per * per
+    done, t0 = 0, time.perf_counter()
+    while done < n:
+        k = min(4000 // per * per, n - done)
+        sim.step(k)
+        done += k
+        print(f"[speedup] {w.name}: {done}/{n} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    cd, cl = sim.history(n // 2, n)
+    sim.close()
+    return {"finest_steps": n, "cd_mean": float(cd.mean()), "cl_mean": float(cl.mean()),
+            "cl_amplitude": float(0.5 * (cl.max() - cl.min())), "seconds": round(time.perf_counter() - t0, 2)}
+
+
+def compare_forces(w, prec, steps):
+    """The hybrid scheme and the body-resolved equivalent LBM over the same physical time."""
+    h = mean_forces(w, prec, steps)
+    e = mean_forces(workloads.equivalent_lbm(w), prec, 2 * steps)
+    return {"aoa_deg": w.aoa_deg, "window": "second half", "hybrid": h, "equivalent_lbm": e,
+            "cd_rel_diff": (h["cd_mean"] - e["cd_mean"]) / e["cd_mean"]}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--workload", default="naca_re5000_c512")
     ap.add_argument("--steps", type=int, default=20, help="timed base steps")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--fp64", action="store_true", help="FP64 populations (default FP32-shifted)")
+    ap.add_argument("--accuracy-steps", type=int, default=0,
+                    help="also compare mean C_D, C_L over the second half of this many hybrid finest steps")
+    ap.add_argument("--aoa", type=float, default=None, help="angle of attack in degrees (default: the workload's)")
     a = ap.parse_args(argv)
     prec = hlbm.FP64 if a.fp64 else hlbm.FP32_SHIFTED
     w = workloads.PRESETS[a.workload]()
+    if a.aoa is not None:
+        w = dataclasses.replace(w, aoa_deg=a.aoa)
     sim = hlbm.HLBM.from_workload(w, precision=prec)
     info = sim.info
     L = info.n_levels - 1
@@ -98,6 +134,8 @@ def main(argv=None):
         "mesh_nodes": n_mesh, "finest_collide_us": round(1e6 * t_collide, 3), "fv_substep_us": round(1e6 * t_fv, 3),
         "paper": {"chi": 1.5e-4, "g": 1.6, "n": 10, "s_prime": "3-5", "G": 0.63},
     }
+    if a.accuracy_steps > 0:
+        out["accuracy"] = compare_forces(w, prec, a.accuracy_steps)
     print(json.dumps(out), flush=True)
     return 0
 
