@@ -59,6 +59,21 @@ def test_speedup_tool(capsys):
     assert m["n"] == 53 and m["g"] > 1 and 0 < m["chi"] < 1
     ratio = x["t_h_ms_per_base_step"] / x["t_eq_ms_per_base_step"]   # both rounded to 1e-4 ms
     assert abs(x["G_measured"] - ratio) < 2e-3 * ratio
+    assert x["equivalent_body"]["solid_nodes"] > 5000 and x["equivalent_body"]["bounce_back_nodes"] > 500
+    assert x["t_eq_nobody_ms_per_base_step"] > 0
+
+
+def test_speedup_accuracy_comparison(capsys):
+    """Both schemes over the same physical time: the equivalent LBM takes twice the
+    finest steps, and the impulsive start gives finite, positive mean drag for both."""
+    from paper_2006_10487_amd import speedup
+    assert speedup.main(["--workload", "naca_re100_c40", "--steps", "2", "--warmup", "1",
+                         "--fp64", "--accuracy-steps", "400", "--aoa", "0"]) == 0
+    (x,) = records(capsys)
+    acc = x["accuracy"]
+    assert acc["hybrid"]["finest_steps"] == 400 and acc["equivalent_lbm"]["finest_steps"] == 800
+    for k in ("hybrid", "equivalent_lbm"):
+        assert acc[k]["cd_mean"] > 0 and abs(acc[k]["cl_mean"]) < 1e-10
 
 
 def test_wallprofile_tool(capsys):
