@@ -251,85 +251,100 @@ __global__ __launch_bounds__(256) void k_stream_collide(const KLevel L, const T*
         __builtin_nontemporal_store(o[q], B + size_t(q) * L.pitch + base);
 }
 
-typedef float f32x2 __attribute__((ext_vector_type(2)));
+// Non-periodic levels: V consecutive nodes per thread (V * sizeof(T) = 16 bytes),
+// one 16-byte non-temporal load per population plane and row (every stored
+// value is read once per step) and one non-temporal store per plane.  The
+// populations that stream along x are taken from the neighbouring lane (one
+// lane shift); only the first and last lane of a wavefront load the element
+// beyond the wavefront.  Measured on MI355X, base level of the bench workload:
+// FP32 with four nodes per thread 413 us against 420 us with two (8-byte
+// accesses; those took 5.98 against 5.38 TB/s for one node per thread); FP64
+// with two nodes per thread was 1% slower than one, so FP64 keeps
+// k_stream_collide.
+template <typename T, int V> struct Vec16;
+template <> struct Vec16<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
 
-// FP32 shifted storage, non-periodic levels: two consecutive nodes per thread,
-// 8-byte aligned loads and stores.  The populations that stream along x are
-// taken from the neighbouring lane (one lane shift); only the first and last
-// lane of a wavefront load the element beyond the wavefront.  Measured on
-// MI355X: 5.98 TB/s against 5.38 TB/s for one node per thread.
-__global__ __launch_bounds__(256) void k_stream_collide_f32x2(const KLevel L, const float* __restrict__ A,
-                                                              float* __restrict__ B) {
+template <typename T, bool SHIFT, int V>
+__global__ __launch_bounds__(256) void k_stream_collide_vec(const KLevel L, const T* __restrict__ A,
+                                                            T* __restrict__ B) {
+    typedef typename Vec16<T, V>::type VT;
     const int lane = threadIdx.x & 63;
-    const int i0 = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+    const int i0 = V * (blockIdx.x * blockDim.x + threadIdx.x);
     const int j = blockIdx.y;
     if (j == 0 || j == L.ny - 1) return;   // far-field edge rows or box perimeter rows: no pulling node
-    bool act[2];
+    bool act[V], any = false;
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
+    for (int v = 0; v < V; ++v) {
         const int i = i0 + v;
         act[v] = i < L.nx && !(L.farfield && (i == 0 || i == L.nx - 1)) && is_active(L, i, j);
+        any = any || act[v];
     }
     // a wave with no active node (inside a child box or the inner ellipse)
     // loads nothing; the others keep every lane for the neighbour shuffles
-    if (__ballot(act[0] || act[1]) == 0) return;
+    if (__ballot(any) == 0) return;
     const bool in_row = i0 < L.pitch;
-    float f[2][9];
+    T f[V][9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const size_t rowb = size_t(j - CY[q]) * size_t(L.rs) + size_t(q) * L.pitch;
-        float a0 = 0.0f, a1 = 0.0f;
+        T a[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) a[v] = T(0);
         if (in_row) {
-            const f32x2 v = *reinterpret_cast<const f32x2*>(A + rowb + i0);
-            a0 = v.x;
-            a1 = v.y;
+            const VT x = __builtin_nontemporal_load(reinterpret_cast<const VT*>(A + rowb + i0));
+#pragma unroll
+            for (int v = 0; v < V; ++v) a[v] = x[v];
         }
         if (CX[q] == 0) {
-            f[0][q] = a0;
-            f[1][q] = a1;
+#pragma unroll
+            for (int v = 0; v < V; ++v) f[v][q] = a[v];
         } else if (CX[q] == 1) {        // node i pulls from i - 1
-            float left = __shfl_up(a1, 1, 64);
-            if (lane == 0) left = (in_row && i0 > 0) ? A[rowb + i0 - 1] : 0.0f;
+            T left = __shfl_up(a[V - 1], 1, 64);
+            if (lane == 0) left = (in_row && i0 > 0) ? A[rowb + i0 - 1] : T(0);
             f[0][q] = left;
-            f[1][q] = a0;
+#pragma unroll
+            for (int v = 1; v < V; ++v) f[v][q] = a[v - 1];
         } else {                        // node i pulls from i + 1
-            float right = __shfl_down(a0, 1, 64);
-            if (lane == 63) right = (i0 + 2 < L.pitch) ? A[rowb + i0 + 2] : 0.0f;
-            f[0][q] = a1;
-            f[1][q] = right;
+            T right = __shfl_down(a[0], 1, 64);
+            if (lane == 63) right = (i0 + V < L.pitch) ? A[rowb + i0 + V] : T(0);
+#pragma unroll
+            for (int v = 0; v < V - 1; ++v) f[v][q] = a[v + 1];
+            f[V - 1][q] = right;
         }
     }
-    if (!act[0] && !act[1]) return;
-    const float omega = float(L.omega), rho0 = float(L.rho0);
-    float out[9][2];
+    if (!any) return;
+    const T omega = T(L.omega), rho0 = T(L.rho0);
+    T out[9][V];
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
-        float g[9], feq[9], rho, dr, ux, uy;
+    for (int v = 0; v < V; ++v) {
+        T g[9], feq[9], rho, dr, ux, uy, o[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) g[q] = f[v][q];
-        macro<float, true>(g, rho0, rho, dr, ux, uy);
-        equilibrium<float, true>(rho, dr, ux, uy, feq);
-        float o[9];
+        macro<T, SHIFT>(g, rho0, rho, dr, ux, uy);
+        equilibrium<T, SHIFT>(rho, dr, ux, uy, feq);
 #pragma unroll
         for (int q = 0; q < 9; ++q) o[q] = g[q] - (g[q] - feq[q]) * omega;
-        conserve_f32(g, o);
+        if constexpr (SHIFT && sizeof(T) == 4) conserve_f32(g, o);
 #pragma unroll
         for (int q = 0; q < 9; ++q) out[q][v] = o[q];
     }
     const size_t base = size_t(j) * size_t(L.rs) + i0;
-    if (act[0] && act[1]) {
+    bool all = true;
+#pragma unroll
+    for (int v = 0; v < V; ++v) all = all && act[v];
+    if (all) {
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            f32x2 o;
-            o.x = out[q][0];
-            o.y = out[q][1];
-            __builtin_nontemporal_store(o, reinterpret_cast<f32x2*>(B + size_t(q) * L.pitch + base));
+            VT o;
+#pragma unroll
+            for (int v = 0; v < V; ++v) o[v] = out[q][v];
+            __builtin_nontemporal_store(o, reinterpret_cast<VT*>(B + size_t(q) * L.pitch + base));
         }
     } else {
 #pragma unroll
         for (int q = 0; q < 9; ++q)
 #pragma unroll
-            for (int v = 0; v < 2; ++v)
+            for (int v = 0; v < V; ++v)
                 if (act[v]) __builtin_nontemporal_store(out[q][v], B + size_t(q) * L.pitch + base + v);
     }
 }
@@ -1310,8 +1325,8 @@ void launch_fill_uniform(int prec, void* buf, const KLevel& L, double rho, doubl
 
 void launch_stream_collide(int prec, const KLevel& L, const void* A, void* B, hipStream_t s) {
     if (prec == HLBM_FP32_SHIFTED && !L.periodic) {
-        dim3 grid(blocks(size_t(L.pitch / 2)), L.ny);
-        k_stream_collide_f32x2<<<grid, 256, 0, s>>>(L, (const float*)A, (float*)B);
+        dim3 grid(blocks(size_t(L.pitch / 4)), L.ny);
+        k_stream_collide_vec<float, true, 4><<<grid, 256, 0, s>>>(L, (const float*)A, (float*)B);
     } else {
         dim3 grid(blocks(L.nx), L.ny);
         HLBM_DISPATCH(prec, (k_stream_collide<T, S><<<grid, 256, 0, s>>>(L, (const T*)A, (T*)B)));
