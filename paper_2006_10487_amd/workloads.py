@@ -431,7 +431,8 @@ def _inner_ellipse(om: OMesh) -> Tuple[float, float, float, float]:
 
 
 def _naca_workload(name, nx, ny, patch_sizes, chord, re, u, aoa, ns, nl, d_out,
-                   growth=None, h1=None, steps=1000, bumps=None, notes="", split="halves", outer="theta"):
+                   growth=None, h1=None, steps=1000, bumps=None, notes="", split="halves", outer="theta",
+                   spacing="arclength"):
     n_ref = len(patch_sizes)
     sp = 2 ** n_ref
     W, H = nx * sp, ny * sp
@@ -439,7 +440,7 @@ def _naca_workload(name, nx, ny, patch_sizes, chord, re, u, aoa, ns, nl, d_out,
     peaks = [0.1 * (m + 1) for m in range(8)]
     om = naca0012_omesh(chord, le, ns, nl, d_out, growth=growth, h1=h1,
                         bump_amps=bumps, bump_peaks=peaks if bumps is not None else None, split=split,
-                        outer=outer)
+                        outer=outer, spacing=spacing)
     patches = _place_patches(le[0] + 0.5 * chord, le[1], patch_sizes, n_ref, sp)
     return Workload(name=name, nx_cells=nx, ny_cells=ny, patches=patches, u_inf=u,
                     aoa_deg=aoa, re=re, chord=chord, mesh_xy=om.xy, mesh_tri=om.tri,
@@ -455,12 +456,17 @@ def hh_amplitudes(seed: int = 0) -> np.ndarray:
     return np.random.default_rng(seed).uniform(-0.002, 0.002, 8)
 
 
-def naca_re100_c40(aoa_deg: float = 0.0, bumps=None) -> Workload:
+def naca_re100_c40(aoa_deg: float = 0.0, bumps=None, spacing: str = "arclength") -> Workload:
     """Small FP64 case: 240x120 grid, c = 40, Re = 100, 128x16 O-mesh
-    (optionally with Hicks-Henne bumps of the given amplitudes at HH_PEAKS)."""
-    return _naca_workload("naca0012_re100_c40_240x120" + ("_bumps" if bumps is not None else ""), 240, 120,
-                          [], 40.0, 100.0, 0.05, aoa_deg, 128, 16, 52.0, growth=1.15, steps=2000,
-                          bumps=None if bumps is None else np.asarray(bumps, dtype=np.float64))
+    (optionally with Hicks-Henne bumps of the given amplitudes at HH_PEAKS).
+    spacing="cosine" places the surface points as the configuration text
+    states (the smallest wall element then shrinks to ~c pi^2 / ns^2 at the
+    trailing edge; the default is equal arc length)."""
+    name = "naca0012_re100_c40_240x120" + ("_bumps" if bumps is not None else "") + \
+        ("_cosine" if spacing == "cosine" else "")
+    return _naca_workload(name, 240, 120, [], 40.0, 100.0, 0.05, aoa_deg, 128, 16, 52.0, growth=1.15,
+                          steps=2000, bumps=None if bumps is None else np.asarray(bumps, dtype=np.float64),
+                          spacing=spacing)
 
 
 def naca_re100_c40_refined(aoa_deg: float = 0.0, bumps=None) -> Workload:

@@ -330,3 +330,24 @@ def test_nonfinite_detection():
     with pytest.raises(hlbm.HLBMError) as ei:
         sim.step(2)
     assert ei.value.code == -6
+
+
+def test_c0_cosine_spacing_as_stated():
+    """The Re 100 case with the surface points cosine-spaced, as its configuration text
+    states: with the default n = 17 FV sub-steps its trailing-edge element (~0.024 lu)
+    makes the explicit sub-step blow up within a few steps (both implementations); with
+    n = 68 it runs, and the GPU matches the oracle in FP64."""
+    w = W.naca_re100_c40(0.0, spacing="cosine")
+    sim = hlbm.HLBM.from_workload(w, check_every=1)
+    with pytest.raises(hlbm.HLBMError) as ei:
+        sim.step(10)
+    assert ei.value.code == -5   # HLBM_E_NONFINITE
+    sim = hlbm.HLBM.from_workload(w, n_sub=68)
+    ref = O.Oracle.from_workload(w, n_sub=68)
+    sim.step(200)
+    ref.step(200)
+    e = compare(sim, ref, 1)
+    assert max(e["level0"], e["mesh"]) < TOL and max(e["cd"], e["cl"]) < 1e-10
+    sim.step(1800)
+    cd, cl = sim.history()
+    assert np.all(np.isfinite(cd)) and np.abs(cl).max() < 1e-10
