@@ -251,18 +251,24 @@ __global__ __launch_bounds__(256) void k_stream_collide(const KLevel L, const T*
         __builtin_nontemporal_store(o[q], B + size_t(q) * L.pitch + base);
 }
 
-// Non-periodic levels: V consecutive nodes per thread (V * sizeof(T) = 16 bytes),
-// one 16-byte non-temporal load per population plane and row (every stored
-// value is read once per step) and one non-temporal store per plane.  The
+// Non-periodic FP32 levels: V consecutive nodes per thread, one V-wide load per
+// population plane and row and one non-temporal store per plane.  The
 // populations that stream along x are taken from the neighbouring lane (one
 // lane shift); only the first and last lane of a wavefront load the element
-// beyond the wavefront.  Measured on MI355X, base level of the bench workload:
-// FP32 with four nodes per thread 413 us against 420 us with two (8-byte
-// accesses; those took 5.98 against 5.38 TB/s for one node per thread); FP64
-// with two nodes per thread was 1% slower than one, so FP64 keeps
-// k_stream_collide.
+// beyond the wavefront.  Measured on MI355X: two nodes per thread took 5.98
+// against 5.38 TB/s for one.  Large levels (far beyond the 256 MB cache) take
+// four nodes per thread with 16-byte non-temporal loads, as every stored value
+// is read once per step: 413 against 420 us on the 33.6M-node base level of
+// the bench workload.  Small levels stay at two with cached loads: their grids
+// stay in the cache from step to step, and four nodes per thread with
+// non-temporal loads made the Re 1000 grids 11% slower.  FP64 with two nodes
+// per thread was 1% slower than one and keeps k_stream_collide.
 template <typename T, int V> struct Vec16;
+template <> struct Vec16<float, 2> { typedef float type __attribute__((ext_vector_type(2))); };
 template <> struct Vec16<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
+
+// levels of at least this many nodes take four nodes per thread
+constexpr size_t kWideLevelNodes = size_t(8) << 20;
 
 template <typename T, bool SHIFT, int V>
 __global__ __launch_bounds__(256) void k_stream_collide_vec(const KLevel L, const T* __restrict__ A,
@@ -291,7 +297,8 @@ __global__ __launch_bounds__(256) void k_stream_collide_vec(const KLevel L, cons
 #pragma unroll
         for (int v = 0; v < V; ++v) a[v] = T(0);
         if (in_row) {
-            const VT x = __builtin_nontemporal_load(reinterpret_cast<const VT*>(A + rowb + i0));
+            const VT* src = reinterpret_cast<const VT*>(A + rowb + i0);
+            const VT x = V == 4 ? __builtin_nontemporal_load(src) : *src;
 #pragma unroll
             for (int v = 0; v < V; ++v) a[v] = x[v];
         }
@@ -1325,8 +1332,13 @@ void launch_fill_uniform(int prec, void* buf, const KLevel& L, double rho, doubl
 
 void launch_stream_collide(int prec, const KLevel& L, const void* A, void* B, hipStream_t s) {
     if (prec == HLBM_FP32_SHIFTED && !L.periodic) {
-        dim3 grid(blocks(size_t(L.pitch / 4)), L.ny);
-        k_stream_collide_vec<float, true, 4><<<grid, 256, 0, s>>>(L, (const float*)A, (float*)B);
+        if (size_t(L.nx) * size_t(L.ny) >= kWideLevelNodes) {
+            dim3 grid(blocks(size_t(L.pitch / 4)), L.ny);
+            k_stream_collide_vec<float, true, 4><<<grid, 256, 0, s>>>(L, (const float*)A, (float*)B);
+        } else {
+            dim3 grid(blocks(size_t(L.pitch / 2)), L.ny);
+            k_stream_collide_vec<float, true, 2><<<grid, 256, 0, s>>>(L, (const float*)A, (float*)B);
+        }
     } else {
         dim3 grid(blocks(L.nx), L.ny);
         HLBM_DISPATCH(prec, (k_stream_collide<T, S><<<grid, 256, 0, s>>>(L, (const T*)A, (T*)B)));
