@@ -519,13 +519,15 @@ def naca_re1000_c128_bumps(bumps=None) -> Workload:
                           bumps=amps)
 
 
-def naca_re5000_c512() -> Workload:
+def naca_re5000_c512(aoa_deg: float = 8.0, band: float = 51.2, nl: int = 128) -> Workload:
     """Throughput case: 8192x4096 base cells (spacing 2), 2048x1024 box, 2048x128 mesh in
-    a band 0.1c = 51.2 lu thick with a 0.25 lu first layer (outer cells ~0.6 lu).  A band
-    reaching 508 lu out (outer cells 13 lu across) carried a spurious lift oscillation
-    with a period of ~100 steps."""
-    return _naca_workload("naca0012_re5000_c512_8192x4096_r1", 8192, 4096, [(2048, 1024)],
-                          512.0, 5000.0, 0.05, 8.0, 2048, 128, 51.2, h1=0.25, steps=10000)
+    a band 0.1c = 51.2 lu thick with a 0.25 lu first layer (outer cells ~0.6 lu), at 8 deg
+    unless aoa_deg says otherwise.  A band reaching 508 lu out (outer cells 13 lu across)
+    carried a spurious lift oscillation with a period of ~100 steps."""
+    name = "naca0012_re5000_c512_8192x4096_r1" + ("" if aoa_deg == 8.0 else f"_aoa{aoa_deg:g}") + \
+        ("" if (band, nl) == (51.2, 128) else f"_band{band:g}_nl{nl}")
+    return _naca_workload(name, 8192, 4096, [(2048, 1024)],
+                          512.0, 5000.0, 0.05, aoa_deg, 2048, nl, band, h1=0.25, steps=10000)
 
 
 CONV_CHORDS = (48, 64, 96, 128, 144)
