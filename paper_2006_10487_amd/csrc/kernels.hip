@@ -972,9 +972,12 @@ __device__ __forceinline__ int fv_tile_node(const KMesh& M, const T* __restrict_
 // Waves per SIMD the fused kernel is compiled for: three in FP32 with 8 slots
 // (at most 168 VGPRs), so that three workgroups of 256 threads share a CU.
 template <typename T, int W> struct FvFusedWaves { static constexpr int value = sizeof(T) == 4 && W <= 8 ? 3 : 1; };
+// Largest workgroup of the fused kernel: 512 threads in FP32 (one node per thread
+// on meshes with fewer tiles than compute units), 256 in FP64.
+template <typename T> struct FvFusedBlock { static constexpr int value = sizeof(T) == 4 ? 512 : 256; };
 
 template <typename T, bool SHIFT, int W>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FvFusedWaves<T, W>::value))) void k_fv_fused(const KMesh M, const T* __restrict__ fin, T* __restrict__ fout,
+__global__ __launch_bounds__(FvFusedBlock<T>::value) __attribute__((amdgpu_waves_per_eu(FvFusedWaves<T, W>::value))) void k_fv_fused(const KMesh M, const T* __restrict__ fin, T* __restrict__ fout,
                                                   const T* __restrict__ prep0, const T* __restrict__ prep1,
                                                   FvTheta th, int ksteps, T* __restrict__ mid, size_t mid_stride) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1422,7 +1425,7 @@ void launch_fv_fused(int prec, const KMesh& M, const void* fin, void* fout, cons
     const size_t elem = prec == HLBM_FP64 ? 8 : 4;
     const size_t lds = fv_lds_bytes(M.maxl, M.maxs, k, elem);
     const unsigned threads = unsigned(M.threads);
-    if (size_t(M.maxw) > size_t(kFvStage) * threads || threads > 256) return;   // rejected by the plan
+    if (size_t(M.maxw) > size_t(kFvStage) * threads || threads > (prec == HLBM_FP64 ? 256u : 512u)) return;   // rejected by the plan
     FvTheta th;   // theta = m / n of sub-steps m0 .. m0 + k - 1, as the one-sub-step launches take it
     for (int j = 0; j < kMaxFuse; ++j) th.v[j] = double(m0 + j) / double(M.n_sub);
     if (M.ft_width == 7) {

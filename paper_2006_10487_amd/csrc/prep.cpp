@@ -500,6 +500,7 @@ constexpr int kFvFuse = 2;
 // so that the tiles fill a whole number of such waves.
 constexpr int kFvCUs = 256;                          // compute units of an MI355X
 constexpr int kFvThreadsF32 = 256, kFvTileMinF32 = 192, kFvTileMaxF32 = 368;
+constexpr int kFvThreadsMax = 512;   // largest fused-FV workgroup (the kernel's launch bound)
 // FP64 (240 VGPRs, 2 waves per SIMD): tiles of 128 nodes on large meshes, down
 // to 64 so that a small mesh still gives about two tiles per CU (measured at
 // 33k nodes: 6.2 us per sub-step with 64, 7.6 with 128).
@@ -899,9 +900,18 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
             choose_fv_tiles(p, k);
             const int need = (p.fv_maxw + kFvStage - 1) / kFvStage;
             p.fv_threads = std::max(p.elem == 8 ? kFvThreadsF64 : kFvThreadsF32, (need + 63) / 64 * 64);
+            int cap = kFvThreadsF32;
+            // fewer FP32 tiles than compute units: the launch lasts one tile's chain of
+            // dependent gathers, so every node of sub-step 1 gets a thread of its own
+            // (measured on the 33k-node mesh: 7.3 against 8.1 us per launch of two)
+            const int one = (p.fv_maxw + 63) / 64 * 64;
+            if (p.elem == 4 && p.n_tiles < kFvCUs && one <= kFvThreadsMax) {
+                p.fv_threads = std::max(p.fv_threads, one);
+                cap = kFvThreadsMax;
+            }
             const size_t lds = fv_lds_bytes(p.fv_maxl, p.fv_maxs, k, p.elem);
             // each thread stages at most one f* node
-            if (lds <= 65536 && p.fv_threads <= 256 && p.fv_maxs <= p.fv_threads) break;
+            if (lds <= 65536 && p.fv_threads <= cap && p.fv_maxs <= p.fv_threads) break;
             p.fv_fuse = 1;
             p.n_tiles = 0;
             p.ft_meta.clear();
