@@ -893,10 +893,16 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
         // nodes of sub-step 1 with kFvStage nodes per thread, else fewer (one
         // kernel per sub-step when not even two fit)
         if (g->fv_fuse < 0 || g->fv_fuse > kMaxFuse) return fail(err, HLBM_E_ARG, "fv_fuse must be 0..%d", kMaxFuse);
-        const int fuse = g->fv_fuse > 0 ? g->fv_fuse : (p.ell_width <= 8 ? kFvFuse : 1);
+        // default: kFvFuse; FP32 meshes with fewer tiles than compute units try kMaxFuse
+        // first (below: only while the launch stays one tile's latency)
+        const bool dflt = g->fv_fuse == 0;
+        const int fuse = !dflt ? g->fv_fuse : (p.ell_width <= 8 ? (p.elem == 4 ? kMaxFuse : kFvFuse) : 1);
         // the largest count from the requested one down to two whose tiles fit
         p.fv_fuse = 1;
         for (int k = fuse; k > 1; --k) {
+            // meshes of more nodes than 256 minimal FP32 tiles hold every CU: skip building
+            // tiles that the default would reject below
+            if (dflt && k > kFvFuse && int64_t(p.nn) > int64_t(kFvCUs) * kFvTileMinF32) continue;
             choose_fv_tiles(p, k);
             const int need = (p.fv_maxw + kFvStage - 1) / kFvStage;
             p.fv_threads = std::max(p.elem == 8 ? kFvThreadsF64 : kFvThreadsF32, (need + 63) / 64 * 64);
@@ -905,13 +911,19 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
             // dependent gathers, so every node of sub-step 1 gets a thread of its own
             // (measured on the 33k-node mesh: 7.3 against 8.1 us per launch of two)
             const int one = (p.fv_maxw + 63) / 64 * 64;
-            if (p.elem == 4 && p.n_tiles < kFvCUs && one <= kFvThreadsMax) {
+            const bool small = p.elem == 4 && p.n_tiles < kFvCUs && one <= kFvThreadsMax;
+            if (small) {
                 p.fv_threads = std::max(p.fv_threads, one);
                 cap = kFvThreadsMax;
             }
+            // by default more than kFvFuse sub-steps per launch only in that regime
+            // (measured on the 33k-node mesh, FP32, per sub-step: 3.63 us with two,
+            // 3.41 with three, 3.17 with four; on the 264k-node mesh, where the
+            // launch holds every CU, the rings cost more than the launches saved)
+            const bool k_ok = !dflt || k <= kFvFuse || small;
             const size_t lds = fv_lds_bytes(p.fv_maxl, p.fv_maxs, k, p.elem);
             // each thread stages at most one f* node
-            if (lds <= 65536 && p.fv_threads <= cap && p.fv_maxs <= p.fv_threads) break;
+            if (k_ok && lds <= 65536 && p.fv_threads <= cap && p.fv_maxs <= p.fv_threads) break;
             p.fv_fuse = 1;
             p.n_tiles = 0;
             p.ft_meta.clear();

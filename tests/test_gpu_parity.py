@@ -203,10 +203,14 @@ def test_fused_fv_substeps_match_single(case):
         w, steps = W.naca_re1000_c128(10.0), 20
         prec = hlbm.FP32_SHIFTED if case.endswith("fp32") else hlbm.FP64
     states = {}
-    for fuse in (1, 2, 3):
+    for fuse in (1, 2, 3, 4, 0):
         sim = hlbm.HLBM.from_workload(w, precision=prec, fv_fuse=fuse)
-        if sim.info.fv_fuse != fuse:          # tile + rings over the budget: fewer per launch
-            assert fuse == 3 and sim.info.fv_fuse == 2
+        if fuse == 0:                         # the default: 4 on the 33k-node mesh in FP32, else 2
+            small_fp32 = prec == hlbm.FP32_SHIFTED and sim.info.fv_tiles < 256
+            assert sim.info.fv_fuse == (4 if small_fp32 else 2)
+            fuse = 10 + sim.info.fv_fuse
+        elif sim.info.fv_fuse != fuse:        # tile + rings over the budget: fewer per launch
+            assert fuse >= 3 and 2 <= sim.info.fv_fuse < fuse
             continue
         sim.step(steps)
         states[fuse] = [sim.get_state(l) for l in range(sim.info.n_levels)] + [sim.get_state(hlbm.PART_MESH)]
