@@ -484,11 +484,13 @@ template <class S> int lagrange9(S x, S y, bool linear, int* di, int* dj, S* w) 
     return 4;
 }
 
-// Default FV sub-steps per launch: two on meshes with at most 8 neighbour
-// slots per node, else one.  Measured on MI355X, per sub-step, fused against
-// one launch per sub-step: FP32 11.2 against 13.9-14.8 us (264k nodes) and
-// 4.8 against 5.7 us (33k nodes); FP64 22.5 against 29.8 us and 6.2 against
-// 8.1 us.
+// Default FV sub-steps per launch on meshes with at most 8 neighbour slots per
+// node: in FP32 the most (up to kMaxFuse) whose tiles fit, in FP64 two; else
+// one.  Measured on MI355X, per sub-step: FP32 264k nodes 8.0 us with three
+// (512-thread tiles), 8.35 with two (256-thread tiles), 13.9-14.8 unfused; FP32
+// 33k nodes 3.17 us with four, 3.41 with three, 3.63 with two, 4.94 unfused;
+// FP64 22.5 against 29.8 us (264k) and 4.6 against 7.1 us (33k) with two, three
+// and four being slower there.
 constexpr int kFvFuse = 2;
 
 // Fused-kernel tiles (plan nodes) and workgroup sizes.  A launch is fastest
@@ -497,10 +499,13 @@ constexpr int kFvFuse = 2;
 // (measured on MI355X, 264k-node mesh, two FP32 sub-steps per launch: 787
 // tiles of 336 nodes 30.8 us, 768 tiles of 344-368 nodes 22.8 us; 3 blocks of
 // 256 threads per CU x 256 CUs = 768 resident).  FP32 tiles are therefore sized
-// so that the tiles fill a whole number of such waves.
+// so that the tiles fill a whole number of such waves.  On meshes with at most
+// 8 slots the FP32 workgroups have 512 threads, two per CU (126 VGPRs: four
+// waves per SIMD), so that a tile with its rings for three or four sub-steps
+// still gives each thread at most two nodes; 16-slot meshes keep 256 threads.
 constexpr int kFvCUs = 256;                          // compute units of an MI355X
 constexpr int kFvThreadsF32 = 256, kFvTileMinF32 = 192, kFvTileMaxF32 = 368;
-constexpr int kFvThreadsMax = 512;   // largest fused-FV workgroup (the kernel's launch bound)
+constexpr int kFvThreadsWide = 512, kFvTileMaxWide = 1024;   // FP32, at most 8 slots (the kernel's launch bound)
 // FP64 (240 VGPRs, 2 waves per SIMD): tiles of 128 nodes on large meshes, down
 // to 64 so that a small mesh still gives about two tiles per CU (measured at
 // 33k nodes: 6.2 us per sub-step with 64, 7.6 with 128).
@@ -617,9 +622,9 @@ void build_fv_tiles(Plan& p, int tile, int fuse) {
     }
 }
 
-// Resident fused-FV workgroups per CU in FP32: three at 8 slots (168 VGPRs),
-// two at 16.
-int fv_blocks_per_cu_f32(int ell_width) { return ell_width <= 8 ? 3 : 2; }
+// Resident fused-FV workgroups per CU in FP32: two (of 512 threads at 8 slots,
+// of 256 at 16).
+constexpr int kFvBlocksPerCuF32 = 2;
 
 void choose_fv_tiles(Plan& p, int fuse) {
     if (p.elem == 8) {
@@ -627,13 +632,14 @@ void choose_fv_tiles(Plan& p, int fuse) {
         build_fv_tiles(p, tile, fuse);
         return;
     }
-    const int64_t slots = int64_t(kFvCUs) * fv_blocks_per_cu_f32(p.ell_width);
-    const int64_t waves = std::max<int64_t>(1, (p.nn + kFvTileMaxF32 * slots - 1) / (kFvTileMaxF32 * slots));
+    const int tmax = p.ell_width <= 8 ? kFvTileMaxWide : kFvTileMaxF32;
+    const int64_t slots = int64_t(kFvCUs) * kFvBlocksPerCuF32;
+    const int64_t waves = std::max<int64_t>(1, (p.nn + tmax * slots - 1) / (tmax * slots));
     int tile = int((p.nn + waves * slots - 1) / (waves * slots));
-    tile = std::min(kFvTileMaxF32, std::max(kFvTileMinF32, (tile + 7) / 8 * 8));
+    tile = std::min(tmax, std::max(kFvTileMinF32, (tile + 7) / 8 * 8));
     build_fv_tiles(p, tile, fuse);
     // breadth-first tiles come out partly smaller than `tile`: grow until they fit
-    while (p.n_tiles > waves * slots && tile + 8 <= kFvTileMaxF32) {
+    while (p.n_tiles > waves * slots && tile + 8 <= tmax) {
         tile += 8;
         build_fv_tiles(p, tile, fuse);
     }
@@ -893,37 +899,19 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
         // nodes of sub-step 1 with kFvStage nodes per thread, else fewer (one
         // kernel per sub-step when not even two fit)
         if (g->fv_fuse < 0 || g->fv_fuse > kMaxFuse) return fail(err, HLBM_E_ARG, "fv_fuse must be 0..%d", kMaxFuse);
-        // default: kFvFuse; FP32 meshes with fewer tiles than compute units try kMaxFuse
-        // first (below: only while the launch stays one tile's latency)
-        const bool dflt = g->fv_fuse == 0;
-        const int fuse = !dflt ? g->fv_fuse : (p.ell_width <= 8 ? (p.elem == 4 ? kMaxFuse : kFvFuse) : 1);
+        const bool wide = p.elem == 4 && p.ell_width <= 8;   // 512-thread FP32 workgroups
+        const int fuse = g->fv_fuse > 0 ? g->fv_fuse : (p.ell_width <= 8 ? (wide ? kMaxFuse : kFvFuse) : 1);
         // the largest count from the requested one down to two whose tiles fit
         p.fv_fuse = 1;
         for (int k = fuse; k > 1; --k) {
-            // meshes of more nodes than 256 minimal FP32 tiles hold every CU: skip building
-            // tiles that the default would reject below
-            if (dflt && k > kFvFuse && int64_t(p.nn) > int64_t(kFvCUs) * kFvTileMinF32) continue;
             choose_fv_tiles(p, k);
             const int need = (p.fv_maxw + kFvStage - 1) / kFvStage;
-            p.fv_threads = std::max(p.elem == 8 ? kFvThreadsF64 : kFvThreadsF32, (need + 63) / 64 * 64);
-            int cap = kFvThreadsF32;
-            // fewer FP32 tiles than compute units: the launch lasts one tile's chain of
-            // dependent gathers, so every node of sub-step 1 gets a thread of its own
-            // (measured on the 33k-node mesh: 7.3 against 8.1 us per launch of two)
-            const int one = (p.fv_maxw + 63) / 64 * 64;
-            const bool small = p.elem == 4 && p.n_tiles < kFvCUs && one <= kFvThreadsMax;
-            if (small) {
-                p.fv_threads = std::max(p.fv_threads, one);
-                cap = kFvThreadsMax;
-            }
-            // by default more than kFvFuse sub-steps per launch only in that regime
-            // (measured on the 33k-node mesh, FP32, per sub-step: 3.63 us with two,
-            // 3.41 with three, 3.17 with four; on the 264k-node mesh, where the
-            // launch holds every CU, the rings cost more than the launches saved)
-            const bool k_ok = !dflt || k <= kFvFuse || small;
+            p.fv_threads = wide ? kFvThreadsWide
+                                : std::max(p.elem == 8 ? kFvThreadsF64 : kFvThreadsF32, (need + 63) / 64 * 64);
+            const int cap = wide ? kFvThreadsWide : kFvThreadsF32;
             const size_t lds = fv_lds_bytes(p.fv_maxl, p.fv_maxs, k, p.elem);
-            // each thread stages at most one f* node
-            if (k_ok && lds <= 65536 && p.fv_threads <= cap && p.fv_maxs <= p.fv_threads) break;
+            // at most kFvStage updated nodes and one staged f* node per thread
+            if (lds <= 65536 && need <= p.fv_threads && p.fv_threads <= cap && p.fv_maxs <= p.fv_threads) break;
             p.fv_fuse = 1;
             p.n_tiles = 0;
             p.ft_meta.clear();

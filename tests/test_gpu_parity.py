@@ -205,9 +205,8 @@ def test_fused_fv_substeps_match_single(case):
     states = {}
     for fuse in (1, 2, 3, 4, 0):
         sim = hlbm.HLBM.from_workload(w, precision=prec, fv_fuse=fuse)
-        if fuse == 0:                         # the default: 4 on the 33k-node mesh in FP32, else 2
-            small_fp32 = prec == hlbm.FP32_SHIFTED and sim.info.fv_tiles < 256
-            assert sim.info.fv_fuse == (4 if small_fp32 else 2)
+        if fuse == 0:                         # the default: the most that fit in FP32 (4 here), 2 in FP64
+            assert sim.info.fv_fuse == (4 if prec == hlbm.FP32_SHIFTED else 2)
             fuse = 10 + sim.info.fv_fuse
         elif sim.info.fv_fuse != fuse:        # tile + rings over the budget: fewer per launch
             assert fuse >= 3 and 2 <= sim.info.fv_fuse < fuse
@@ -238,9 +237,9 @@ def test_bench_workload_full_size():
     assert max(e["level0"], e["level1"], e["mesh"]) < TOL and max(e["cd"], e["cl"]) < 1e-10
     sim.close()
     sim = hlbm.HLBM.from_workload(w, precision=hlbm.FP32_SHIFTED)
-    assert sim.info.fv_fuse == 2
-    # every tile of a fused launch resident at once: 3 workgroups of 256 threads on each of 256 CUs
-    assert sim.info.fv_threads == 256 and 0 < sim.info.fv_tiles <= 3 * 256
+    assert sim.info.fv_fuse == 3
+    # every tile of a fused launch resident at once: 2 workgroups of 512 threads on each of 256 CUs
+    assert sim.info.fv_threads == 512 and 0 < sim.info.fv_tiles <= 2 * 256
     sim.step(2)
     e = compare(sim, ref, 2)
     assert max(e["level0"], e["level1"], e["mesh"]) < 1e-6 and max(e["cd"], e["cl"]) < 1e-5
@@ -253,13 +252,13 @@ def test_bench_workload_full_size():
 
 
 def test_fused_fallback_when_tiles_too_large():
-    """Four or three sub-steps per launch on the 264k-node mesh would need more than
-    512 updated nodes per tile: the plan falls back to two, with the bits of one
-    launch per sub-step."""
+    """Four sub-steps per launch on the 264k-node mesh would need more than 1024
+    updated nodes per tile: the plan falls back to three (its default), with the
+    bits of one launch per sub-step."""
     w = W.naca_re5000_c512()
     for k in (4, 3):
         sim = hlbm.HLBM.from_workload(w, precision=hlbm.FP32_SHIFTED, fv_fuse=k)
-        assert sim.info.fv_fuse == 2 and sim.info.fv_threads == 256 and 0 < sim.info.fv_tiles <= 768
+        assert sim.info.fv_fuse == 3 and sim.info.fv_threads == 512 and 0 < sim.info.fv_tiles <= 512
         sim.step(2)
         fused = sim.get_state(hlbm.PART_MESH)
         sim.close()
