@@ -98,9 +98,10 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hlbm_step_naca_re5000_c512_fp3
 ADJOINT_MARKER = "// ---- Discrete adjoint kernels (reverse mode, FP64) ----"
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, fv_fuse=None):
     """Calibrated HBM bytes per launch from the committed counter summary, or
-    None when the forward kernels changed since the counters were taken."""
+    None when the forward kernels (or, for the FV launch, its number of
+    sub-steps) changed since the counters were taken."""
     import hashlib
     import re
     try:
@@ -109,6 +110,8 @@ def measured_traffic(kernel):
         src = open(os.path.join(ROOT, "paper_2006_10487_amd", "csrc", "kernels.hip")).read()
         fwd = src[:src.index(ADJOINT_MARKER)]
         if hashlib.sha256(fwd.encode()).hexdigest() != rec["forward_kernels_sha256"]:
+            return None
+        if kernel == "fv_substep" and rec[kernel].get("fv_fuse") != fv_fuse:
             return None
         return round(rec[kernel]["traffic_bytes"])
     except (OSError, ValueError, KeyError, AttributeError):
@@ -365,7 +368,8 @@ def main():
                                          "sub-steps per launch) over the mean of back-to-back launches timed "
                                          "with HIP events; traffic = calibrated FETCH_SIZE + WRITE_SIZE bytes "
                                          "per launch",
-                               measured_traffic(dom) if w.name == "naca0012_re5000_c512_8192x4096_r1" else None,
+                               measured_traffic(dom, int(r32["info"].fv_fuse))
+                               if w.name == "naca0012_re5000_c512_8192x4096_r1" else None,
                                info=r32["info"])
     res["roofline_base_grid"] = roofline(k32, "collide_l0", "base-level fused stream-collide (72 B per node)",
                                          measured_traffic("collide_l0") if w.name == "naca0012_re5000_c512_8192x4096_r1" else None)
