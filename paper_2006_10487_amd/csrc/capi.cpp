@@ -436,6 +436,21 @@ int hlbm_create(const hlbm_grid* grid, const hlbm_mesh* mesh, double Re, double 
         return set_err(nullptr, HLBM_E_WORKSPACE,
                        "workspace must be 256-byte aligned and hold " + std::to_string(need) + " bytes");
     }
+    if (c->p.fv_fuse > 1) {   // the fused FV tiles against this device's LDS per workgroup
+        int dev = 0, lds_max = 0;
+        const size_t lds = fv_lds_bytes(c->p.fv_maxl, c->p.fv_maxs, c->p.fv_fuse, c->p.elem);
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+            delete c;
+            return set_err(nullptr, HLBM_E_DEVICE, "cannot read the device's LDS per workgroup");
+        }
+        if (lds > size_t(lds_max)) {
+            delete c;
+            return set_err(nullptr, HLBM_E_DEVICE,
+                           "fused FV tiles need " + std::to_string(lds) + " bytes of LDS per workgroup; the device "
+                           "allows " + std::to_string(lds_max) + " (request fewer sub-steps per launch, fv_fuse)");
+        }
+    }
     c->ws = static_cast<char*>(d_workspace);
     c->ws_bytes = ws_bytes;
     c->s = static_cast<hipStream_t>(hip_stream);

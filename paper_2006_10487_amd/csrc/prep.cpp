@@ -506,6 +506,11 @@ constexpr int kFvFuse = 2;
 constexpr int kFvCUs = 256;                          // compute units of an MI355X
 constexpr int kFvThreadsF32 = 256, kFvTileMinF32 = 192, kFvTileMaxF32 = 368;
 constexpr int kFvThreadsWide = 512, kFvTileMaxWide = 1024;   // FP32, at most 8 slots (the kernel's launch bound)
+// LDS per fused-FV workgroup: 64 KB, and 80 KB for the 512-thread FP32 tiles, of
+// which two share a CU's 160 KB on gfx950 (hlbm_create checks the plan against the
+// device's per-workgroup limit).  With 80 KB the bench mesh takes four sub-steps per
+// launch: 7.66 against 8.0 us per sub-step with three.
+constexpr size_t kFvLds = 65536, kFvLdsWide = 81920;
 // FP64 (240 VGPRs, 2 waves per SIMD): tiles of 128 nodes on large meshes, down
 // to 64 so that a small mesh still gives about two tiles per CU (measured at
 // 33k nodes: 6.2 us per sub-step with 64, 7.6 with 128).
@@ -911,7 +916,9 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
             const int cap = wide ? kFvThreadsWide : kFvThreadsF32;
             const size_t lds = fv_lds_bytes(p.fv_maxl, p.fv_maxs, k, p.elem);
             // at most kFvStage updated nodes and one staged f* node per thread
-            if (lds <= 65536 && need <= p.fv_threads && p.fv_threads <= cap && p.fv_maxs <= p.fv_threads) break;
+            if (lds <= (wide ? kFvLdsWide : kFvLds) && need <= p.fv_threads && p.fv_threads <= cap &&
+                p.fv_maxs <= p.fv_threads)
+                break;
             p.fv_fuse = 1;
             p.n_tiles = 0;
             p.ft_meta.clear();

@@ -237,7 +237,7 @@ def test_bench_workload_full_size():
     assert max(e["level0"], e["level1"], e["mesh"]) < TOL and max(e["cd"], e["cl"]) < 1e-10
     sim.close()
     sim = hlbm.HLBM.from_workload(w, precision=hlbm.FP32_SHIFTED)
-    assert sim.info.fv_fuse == 3
+    assert sim.info.fv_fuse == 4
     # every tile of a fused launch resident at once: 2 workgroups of 512 threads on each of 256 CUs
     assert sim.info.fv_threads == 512 and 0 < sim.info.fv_tiles <= 2 * 256
     sim.step(2)
@@ -251,20 +251,21 @@ def test_bench_workload_full_size():
     assert np.array_equal(fused, one.get_state(hlbm.PART_MESH))
 
 
-def test_fused_fallback_when_tiles_too_large():
-    """Four sub-steps per launch on the 264k-node mesh would need more than 1024
-    updated nodes per tile: the plan falls back to three (its default), with the
-    bits of one launch per sub-step."""
+def test_fused_launch_shapes_on_bench_mesh():
+    """Four, three and two sub-steps per launch on the 264k-node mesh (512-thread tiles,
+    two per CU, up to 80 KB of LDS each; 66 sub-steps per finest step, so four per launch
+    ends with a launch of two) give the bits of one launch per sub-step."""
     w = W.naca_re5000_c512()
-    for k in (4, 3):
-        sim = hlbm.HLBM.from_workload(w, precision=hlbm.FP32_SHIFTED, fv_fuse=k)
-        assert sim.info.fv_fuse == 3 and sim.info.fv_threads == 512 and 0 < sim.info.fv_tiles <= 512
-        sim.step(2)
-        fused = sim.get_state(hlbm.PART_MESH)
-        sim.close()
     one = hlbm.HLBM.from_workload(w, precision=hlbm.FP32_SHIFTED, fv_fuse=1)
     one.step(2)
-    assert np.array_equal(fused, one.get_state(hlbm.PART_MESH))
+    ref = one.get_state(hlbm.PART_MESH)
+    one.close()
+    for k in (4, 3, 2):
+        sim = hlbm.HLBM.from_workload(w, precision=hlbm.FP32_SHIFTED, fv_fuse=k)
+        assert sim.info.fv_fuse == k and sim.info.fv_threads == 512 and 0 < sim.info.fv_tiles <= 512
+        sim.step(2)
+        assert np.array_equal(sim.get_state(hlbm.PART_MESH), ref), k
+        sim.close()
 
 
 def test_determinism_and_resume():
