@@ -486,8 +486,9 @@ template <class S> int lagrange9(S x, S y, bool linear, int* di, int* dj, S* w) 
 
 // Default FV sub-steps per launch on meshes with at most 8 neighbour slots per
 // node: in FP32 the most (up to kMaxFuse) whose tiles fit, in FP64 two; else
-// one.  Measured on MI355X, per sub-step: FP32 264k nodes 8.0 us with three
-// (512-thread tiles), 8.35 with two (256-thread tiles), 13.9-14.8 unfused; FP32
+// one.  Measured on MI355X, per sub-step: FP32 264k nodes 7.66 us with four and
+// 8.0 with three (512-thread tiles), 8.35 with two (256-thread tiles), 13.9-14.8
+// unfused; FP32
 // 33k nodes 3.17 us with four, 3.41 with three, 3.63 with two, 4.94 unfused;
 // FP64 22.5 against 29.8 us (264k) and 4.6 against 7.1 us (33k) with two, three
 // and four being slower there.
@@ -900,9 +901,10 @@ int build_plan(const hlbm_grid* g, const hlbm_mesh* m, double Re, double tau, Pl
                 p.wnorm.push_back(-dx);
             }
         // fused FV sub-steps: fv_fuse per launch when a tile with its rings fits
-        // in 64 KB of LDS and a workgroup of at most 256 threads covers the
-        // nodes of sub-step 1 with kFvStage nodes per thread, else fewer (one
-        // kernel per sub-step when not even two fit)
+        // in the LDS of a workgroup (kFvLds, kFvLdsWide) and a workgroup of at
+        // most 256 threads (512 for the FP32 8-slot tiles) covers the nodes of
+        // sub-step 1 with kFvStage nodes per thread, else fewer (one kernel per
+        // sub-step when not even two fit)
         if (g->fv_fuse < 0 || g->fv_fuse > kMaxFuse) return fail(err, HLBM_E_ARG, "fv_fuse must be 0..%d", kMaxFuse);
         const bool wide = p.elem == 4 && p.ell_width <= 8;   // 512-thread FP32 workgroups
         const int fuse = g->fv_fuse > 0 ? g->fv_fuse : (p.ell_width <= 8 ? (wide ? kMaxFuse : kFvFuse) : 1);
