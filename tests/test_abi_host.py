@@ -196,3 +196,44 @@ def test_body_option_validation(lib):
     tiny = dataclasses.replace(e, body_xy=np.array([[300.2, 100.2], [300.6, 100.2], [300.4, 100.6]]))
     g, m, keep = hlbm.structs_from_workload(tiny)
     assert hlbm.validate(g, m, 0.0, e.tau_s) == -2
+
+
+def _bench_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "bench_mod", os.path.join(os.path.dirname(__file__), os.pardir, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_traffic_record_applies_only_to_its_kernels_and_launch_shape(tmp_path):
+    """The counter traffic is reported only while the forward kernels hash to the
+    recorded value and, for the FV launch, the sub-steps per launch match."""
+    import hashlib
+    import json
+    B = _bench_module()
+    src = open(os.path.join(os.path.dirname(B.__file__), "paper_2006_10487_amd", "csrc", "kernels.hip")).read()
+    sha = hashlib.sha256(src[:src.index(B.ADJOINT_MARKER)].encode()).hexdigest()
+    rec = {"forward_kernels_sha256": sha, "fv_substep": {"traffic_bytes": 1234.4, "fv_fuse": 4},
+           "collide_l0": {"traffic_bytes": 99.6}}
+    f = tmp_path / "traffic.md"
+    f.write_text("# summary\n\n```json\n" + json.dumps(rec) + "\n```\n")
+    B.TRAFFIC_SUMMARY = str(f)
+    assert B.measured_traffic("fv_substep", 4) == 1234
+    assert B.measured_traffic("fv_substep", 3) is None
+    assert B.measured_traffic("collide_l0") == 100
+    rec["forward_kernels_sha256"] = "0" * 64
+    f.write_text("```json\n" + json.dumps(rec) + "\n```\n")
+    assert B.measured_traffic("fv_substep", 4) is None and B.measured_traffic("collide_l0") is None
+    B.TRAFFIC_SUMMARY = str(tmp_path / "missing.md")
+    assert B.measured_traffic("collide_l0") is None
+
+
+def test_committed_traffic_record_matches_the_committed_kernels():
+    """profiles/ holds the counter summary of the kernels in this tree (four FV
+    sub-steps per launch on the bench mesh): after a forward-kernel change the
+    counters must be taken again, or bench.py reports null traffic."""
+    B = _bench_module()
+    assert isinstance(B.measured_traffic("fv_substep", 4), int)
+    assert isinstance(B.measured_traffic("collide_l0"), int)
