@@ -514,7 +514,9 @@ constexpr int kFvThreadsWide = 512, kFvTileMaxWide = 1024;   // FP32, at most 8 
 constexpr size_t kFvLds = 65536, kFvLdsWide = 81920;
 // FP64 (240 VGPRs, 2 waves per SIMD): tiles of 128 nodes on large meshes, down
 // to 64 so that a small mesh still gives about two tiles per CU (measured at
-// 33k nodes: 6.2 us per sub-step with 64, 7.6 with 128).
+// 33k nodes: 6.2 us per sub-step with 64, 7.6 with 128; at 264k nodes, two
+// sub-steps per launch: 36.1 us with 128, 37.3 with 144, 37.7 with 160, 38.6
+// with 192).
 constexpr int kFvThreadsF64 = 128, kFvTileMinF64 = 64, kFvTileMaxF64 = 128;
 
 // Tiles for the fused finite-volume kernel, which takes several Jacobi
